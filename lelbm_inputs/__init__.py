@@ -1,0 +1,178 @@
+"""Seeded synthetic inputs shared by the GPU library's tests/benchmark and the
+CPU oracle.
+
+This module holds data generation only: primitive fields (density, velocity,
+temperature RT in lattice units) and run parameters.  It contains none of the
+method's arithmetic -- each side converts primitives to raw moments with its
+own code.  Boundary kinds are returned as strings so neither side depends on
+the other's enum values.
+
+Random numbers come from ``numpy.random.Generator(PCG64(seed))`` with a fixed
+draw order per workload.
+
+Workloads (lattice units, dx = dt = 1):
+  * ``riemann1d``  -- 1D two-state problem split at the midpoint, zero-gradient
+    outflow pads at both ends (the paper's shock tubes, Sec. V.A-B).
+  * ``quadrants``  -- 2D periodic four-quadrant piecewise-constant states with a
+    1% smooth Fourier density perturbation (structure of the paper's 2D Riemann
+    problem, Sec. V.D; the published reference solutions are not used).
+  * ``hotbox``     -- uniform periodic advection (Sec. IV.E).
+  * ``shear_wave`` / ``acoustic_pulse`` -- the paper's verification problems
+    (Sec. IV.A, IV.D).
+
+Physical states are mapped to lattice units by acoustic scaling (Sec. V.B):
+RT_lat = s^2 RT_phys and u_lat = s u_phys with s^2 = RT_floor / min RT_phys.
+"""
+import numpy as np
+
+GAMMA = 1.4
+# internal degrees of freedom for gamma = 1.4: gamma = (D + K + 2)/(D + K)
+K_1D = 4.0
+K_2D = 3.0
+
+RT_FLOOR = 0.5
+
+
+def _base_cfg(dim, nx, ny, K):
+    return {
+        "dim": dim, "nx": nx, "ny": ny, "K": K, "gamma": GAMMA,
+        # inviscid shock runs: tau = 0 for shear and heat flux, omega_b = 1
+        "omega_f": 2.0, "omega_b": 1.0, "omega_h": 2.0,
+        "n_conf": 4.0, "r_min": 2,
+        "newton_tol": 1e-12, "newton_max_it": 50,
+        "kn_limiter": 1, "kn_lo": -2.0, "kn_hi": -1.0, "omega_H": 1.0,
+        "bc": ["periodic"] * 4, "pad": 0,
+        "in_rho": 1.0, "in_u": (0.0, 0.0), "in_RT": 1.0,
+    }
+
+
+def riemann1d(seed=None, n=2000, states=None, pad=48, rt_floor=RT_FLOOR, scale=None):
+    """1D two-state problem.  With ``states=None`` draws rho_L, p_L, rho_R, p_R
+    ~ U[0.1, 1.0] in that order (zero velocity); otherwise ``states`` is
+    ((rho_L, u_L, p_L), (rho_R, u_R, p_R)) in physical units.  Returns
+    (cfg, prim) with prim fields of shape (1, n)."""
+    if states is None:
+        g = np.random.Generator(np.random.PCG64(seed))
+        rl, pl, rr, pr = g.uniform(0.1, 1.0, size=4)
+        states = ((rl, 0.0, pl), (rr, 0.0, pr))
+    (rl, ul, pl), (rr, ur, pr) = states
+    rtl, rtr = pl / rl, pr / rr
+    s = np.sqrt(rt_floor / min(rtl, rtr)) if scale is None else scale
+    cfg = _base_cfg(1, n, 1, K_1D)
+    cfg["bc"] = ["outflow", "outflow", "periodic", "periodic"]
+    cfg["pad"] = pad
+    cfg["scale"] = float(s)
+    cfg["states_phys"] = states
+    i = np.arange(n)
+    left = i < n // 2
+    rho = np.where(left, rl, rr).astype(np.float64)
+    ux = np.where(left, ul, ur) * s
+    RT = np.where(left, rtl, rtr) * s * s
+    prim = {"rho": rho[None, :], "ux": ux[None, :].astype(np.float64),
+            "uy": np.zeros((1, n)), "RT": RT[None, :].astype(np.float64)}
+    return cfg, prim
+
+
+def quadrants(seed, n=1024, ny=None, rt_floor=RT_FLOOR, perturb=0.01):
+    """2D periodic four-quadrant states (SW, SE, NW, NE; split at the middle).
+    Per quadrant, in that order: rho ~ U[0.1, 1.5], p ~ U[0.03, 1.5], then
+    u_x, u_y ~ U[-1.2, 1.2] times the local sound speed sqrt(gamma p / rho).
+    Density is perturbed by ``perturb`` times a smooth Fourier field
+    phi = sum_{kx,ky=1..4} a sin(2 pi (kx x + ky y)/L + theta), a ~ N(0,1),
+    theta ~ U[0, 2 pi), normalised to max |phi| = 1, at fixed pressure."""
+    ny = n if ny is None else ny
+    g = np.random.Generator(np.random.PCG64(seed))
+    quads = []
+    for _ in range(4):
+        rho = g.uniform(0.1, 1.5)
+        p = g.uniform(0.03, 1.5)
+        cs = np.sqrt(GAMMA * p / rho)
+        ux = g.uniform(-1.2, 1.2) * cs
+        uy = g.uniform(-1.2, 1.2) * cs
+        quads.append((rho, ux, uy, p))
+    amps = g.standard_normal((4, 4))
+    phases = g.uniform(0.0, 2.0 * np.pi, size=(4, 4))
+    x = (np.arange(n) + 0.5)[None, :]
+    y = (np.arange(ny) + 0.5)[:, None]
+    phi = np.zeros((ny, n))
+    for a in range(4):
+        for b in range(4):
+            phi += amps[a, b] * np.sin(2 * np.pi * ((a + 1) * x / n + (b + 1) * y / ny) + phases[a, b])
+    phi /= np.abs(phi).max()
+    east = np.broadcast_to(x >= n / 2, (ny, n))
+    north = np.broadcast_to(y >= ny / 2, (ny, n))
+    idx = east.astype(int) + 2 * north.astype(int)
+    table = np.array(quads)
+    rho0 = table[idx, 0]
+    ux = table[idx, 1]
+    uy = table[idx, 2]
+    p = table[idx, 3]
+    rho = rho0 * (1.0 + perturb * phi)
+    rt_phys = p / rho
+    s = np.sqrt(rt_floor / rt_phys.min())
+    cfg = _base_cfg(2, n, ny, K_2D)
+    cfg["scale"] = float(s)
+    cfg["quadrants_phys"] = quads
+    prim = {"rho": rho, "ux": ux * s, "uy": uy * s, "RT": rt_phys * s * s}
+    return cfg, prim
+
+
+def hotbox(RT, n=256, ny=None, u=(10.0, 10.0), dim=2):
+    """Uniform periodic advection: rho = 1, u = (10, 10) by default."""
+    ny = (n if ny is None else ny) if dim == 2 else 1
+    cfg = _base_cfg(dim, n, ny, K_2D if dim == 2 else K_1D)
+    shape = (ny, n)
+    prim = {"rho": np.ones(shape), "ux": np.full(shape, float(u[0])),
+            "uy": np.full(shape, float(u[1]) if dim == 2 else 0.0), "RT": np.full(shape, float(RT))}
+    return cfg, prim
+
+
+def shear_wave(L=64, ny=4, RT=0.5, u0=0.5, amp=1e-3, nu=0.05, K=K_2D):
+    """Decaying transverse shear wave u_y = amp cos(2 pi x / L) on a uniform
+    flow u_x = u0 (Sec. IV.A).  Shear frequency from nu = RT (1/omega - 1/2)."""
+    cfg = _base_cfg(2, L, ny, K)
+    omega = 1.0 / (nu / RT + 0.5)
+    cfg.update({"omega_f": omega, "omega_b": 1.0, "omega_h": omega, "kn_limiter": 0, "nu": nu})
+    x = (np.arange(L) + 0.5)[None, :]
+    shape = (ny, L)
+    prim = {"rho": np.ones(shape), "ux": np.full(shape, u0),
+            "uy": np.broadcast_to(amp * np.cos(2 * np.pi * x / L), shape).copy(),
+            "RT": np.full(shape, RT)}
+    return cfg, prim
+
+
+def acoustic_pulse(n=400, RT=1.0, drho=1e-4, width=4.0, K=K_1D, pad=32):
+    """Quiescent 1D gas with a small Gaussian density bump at the centre at
+    constant temperature (Sec. IV.D uses a point bump)."""
+    cfg = _base_cfg(1, n, 1, K)
+    cfg.update({"omega_f": 1.0, "omega_b": 1.0, "omega_h": 1.0, "kn_limiter": 0})
+    cfg["bc"] = ["outflow", "outflow", "periodic", "periodic"]
+    cfg["pad"] = pad
+    x = np.arange(n) + 0.5
+    rho = 1.0 + drho * np.exp(-0.5 * ((x - n / 2) / width) ** 2)
+    prim = {"rho": rho[None, :], "ux": np.zeros((1, n)), "uy": np.zeros((1, n)), "RT": np.full((1, n), RT)}
+    return cfg, prim
+
+
+def smooth_periodic(seed, n=16, ny=12, dim=2, amp=0.05, RT=0.8):
+    """Small smooth random periodic state (a few Fourier modes in each field)
+    for conservation and parity checks."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    ny = ny if dim == 2 else 1
+    x = (np.arange(n) + 0.5)[None, :] / n
+    y = (np.arange(ny) + 0.5)[:, None] / ny
+    fields = []
+    for _ in range(4):
+        f = np.zeros((ny, n))
+        for a in range(1, 3):
+            for b in range(0, 3 if dim == 2 else 1):
+                f += g.standard_normal() * np.sin(2 * np.pi * (a * x + b * y) + g.uniform(0, 2 * np.pi))
+        fields.append(f / max(np.abs(f).max(), 1e-30))
+    cfg = _base_cfg(dim, n, ny, K_2D if dim == 2 else K_1D)
+    prim = {"rho": 1.0 + amp * fields[0], "ux": 0.3 + 0.5 * amp * 10 * fields[1],
+            "uy": (-0.2 + 0.5 * amp * 10 * fields[2]) if dim == 2 else np.zeros((ny, n)),
+            "RT": RT * (1.0 + amp * fields[3])}
+    return cfg, prim
+
+
+BC_NAMES = ("periodic", "outflow", "inflow", "slipwall")

@@ -1,0 +1,469 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics,
+independent of the oracle's own formulas: printed worked examples, direct
+definitions of central moments, closed-form equilibria, a brute-force dual
+minimiser, conservation, symmetry, the exact Riemann solution and measured
+transport coefficients."""
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+import lelbm_inputs as li
+import oracle
+from oracle import riemann
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def prim_moments(cfg, prim):
+    return oracle.moments_from_primitives(cfg["dim"], cfg["K"], prim["rho"], prim["ux"],
+                                          prim["uy"], prim["RT"])
+
+
+# --------------------------------------------------------------------------
+# Lagrangian acoustic stencil (Sec. II.C)
+# --------------------------------------------------------------------------
+def test_las_worked_examples():
+    rows = np.loadtxt(os.path.join(GOLDEN, "las_worked_examples.txt"))
+    for RT, ux, uy, q, colat in rows:
+        c, dC, d, h = oracle.las(2, (ux, uy), RT)
+        assert len(dC) == int(q)
+        if not np.isnan(colat):
+            R = oracle.las_radius(RT)
+            assert abs(np.hypot(ux, uy) + R - colat) < 0.05     # Eq. (IIC7), printed to 3 digits
+
+
+def test_las_brute_force_disk():
+    """Base stencil = every integer point within R + 1/2 of u, by brute force."""
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        RT = rng.uniform(0.5, 12.0)
+        u = rng.uniform(-20, 20, size=2)
+        c, dC, d, h = oracle.las(2, u, RT)
+        R = max(int(np.floor(4 * np.sqrt(RT) + 0.5)), 2)
+        g = np.arange(-60, 61)
+        X, Y = np.meshgrid(g, g)
+        inside = (X - u[0]) ** 2 + (Y - u[1]) ** 2 <= (R + 0.5) ** 2
+        assert len(dC) == inside.sum()
+        assert np.all(dC == 1.0) and np.all(d == c)
+
+
+def test_las_1d_count_and_refinement_volume():
+    # 1D: the interval |c - u| <= R + 1/2 holds 2R + 1 integers (u not half-integer)
+    for RT in (0.5, 1.0, 3.7, 20.0):
+        R = oracle.las_radius(RT)
+        c, dC, d, h = oracle.las(1, (0.3, 0.0), RT)
+        assert oracle.las_levels(RT) == 0
+        assert len(dC) == 2 * R + 1
+    # refinement splits velocity volume without changing it (Eq. IIC11) and
+    # children of an integer parent land in the parent's cell
+    for dim, u, RT in ((2, (3.7, 4.1), 0.2), (2, (-1.2, 0.4), 0.3), (1, (0.45, 0.0), 0.05), (2, (0.1, 0.2), 0.04)):
+        c, dC, d, h = oracle.las(dim, u, RT)
+        assert oracle.las_levels(RT) >= 1
+        assert abs(dC.sum() - len(np.unique(d, axis=0))) < 1e-12
+        assert np.all(np.floor(c[:, 0] + 0.5) == d[:, 0])
+        if dim == 2:
+            assert np.all(np.floor(c[:, 1] + 0.5) == d[:, 1])
+        # each refined point sits at the centre of its own velocity cell of side h
+        assert np.allclose(dC, h ** dim)
+
+
+def test_las_levels_threshold():
+    # N_r = [1/(3 sqrt(RT))]: refinement switches on below RT = 4/9 (Eq. IIC9)
+    assert oracle.las_levels(0.45) == 0
+    assert oracle.las_levels(0.44) == 1
+    assert oracle.las_levels(0.05) == 1
+    assert oracle.las_levels(0.049) == 2
+
+
+# --------------------------------------------------------------------------
+# Collision (Sec. II.B, App. D)
+# --------------------------------------------------------------------------
+def _random_populations(dim, rng, q=60):
+    c = rng.uniform(-4, 4, size=(q, 2)) + np.array([1.3, -0.7])
+    if dim == 1:
+        c[:, 1] = 0.0
+    f = rng.uniform(0.1, 1.0, size=q)
+    g = rng.uniform(0.1, 1.0, size=q)
+    return c, f, g
+
+
+def _raw_moments(dim, c, f, g):
+    x, y = c[:, 0], c[:, 1]
+    cc = x * x + y * y
+    if dim == 1:
+        return np.array([f.sum(), (x * f).sum(), (x * x * f).sum(), (x ** 3 * f).sum(), g.sum(), (x * g).sum()])
+    return np.array([f.sum(), (x * f).sum(), (y * f).sum(), (x * x * f).sum(), (x * y * f).sum(),
+                     (y * y * f).sum(), (cc * x * f).sum(), (cc * y * f).sum(), g.sum(), (x * g).sum(),
+                     (y * g).sum()])
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_noneq_central_moments_match_direct_sums(dim):
+    """Eq. (IIB9) from raw moments must equal the direct central sums of
+    Eq. (IIB8) (relative velocity c - u) minus the equilibrium central moments
+    of Eq. (IIB7g-j)."""
+    rng = np.random.default_rng(7 + dim)
+    K = 3.0 if dim == 2 else 4.0
+    cfg = dict(li.hotbox(1.0, n=4, dim=dim)[0])
+    cfg["K"] = K
+    for _ in range(5):
+        c, f, g = _random_populations(dim, rng)
+        mom = _raw_moments(dim, c, f, g)
+        out = oracle.collide(cfg, mom)
+        rho = f.sum()
+        u = np.array([(c[:, 0] * f).sum(), (c[:, 1] * f).sum()]) / rho
+        ct = c - u
+        RT = ((ct[:, 0] ** 2 * f).sum() + (ct[:, 1] ** 2 * f).sum() + g.sum()) / rho / (dim + K)
+        assert np.isclose(out["rho"], rho, rtol=1e-13)
+        assert np.isclose(out["RT"], RT, rtol=1e-12)
+        x, y = ct[:, 0], ct[:, 1]
+        Pxx = (x * x * f).sum() - rho * RT
+        assert np.isclose(out["Pxx"], Pxx, rtol=1e-10, atol=1e-12)
+        Qx = ((x * x + y * y) * x * f).sum()
+        assert np.isclose(out["Qx"], Qx, rtol=1e-10, atol=1e-11)
+        assert np.isclose(out["g0"], g.sum() - rho * K * RT, rtol=1e-10, atol=1e-12)
+        assert np.isclose(out["hx"], (x * g).sum(), rtol=1e-10, atol=1e-12)
+        if dim == 2:
+            assert np.isclose(out["Pxy"], (x * y * f).sum(), rtol=1e-10, atol=1e-12)
+            assert np.isclose(out["Pyy"], (y * y * f).sum() - rho * RT, rtol=1e-10, atol=1e-12)
+            assert np.isclose(out["Qy"], ((x * x + y * y) * y * f).sum(), rtol=1e-10, atol=1e-11)
+            assert np.isclose(out["hy"], (y * g).sum(), rtol=1e-10, atol=1e-12)
+        # energy identity: trace of P equals -g0 (RT is defined with G0)
+        assert np.isclose(out["Pxx"] + out["Pyy"], -out["g0"], rtol=1e-9, atol=1e-11)
+
+
+def test_targets_relaxation_and_splits():
+    """Post-collision targets of Eq. (IIB16): omega = 1 gives the equilibrium
+    central moments; omega = 0 keeps the input central moments; the third-order
+    per-axis pieces sum to the contracted moment (Eq. IIB14)."""
+    rng = np.random.default_rng(11)
+    cfg = dict(li.hotbox(1.0, n=4)[0])
+    cfg["kn_limiter"] = 0
+    c, f, g = _random_populations(2, rng)
+    mom = _raw_moments(2, c, f, g)
+    for om in (1.0, 0.0):
+        cfg.update(omega_f=om, omega_b=om, omega_h=om)
+        out = oracle.collide(cfg, mom)
+        rho, RT, K = out["rho"], out["RT"], cfg["K"]
+        u = np.array([out["ux"], out["uy"]])
+        ct = c - u
+        x, y = ct[:, 0], ct[:, 1]
+        if om == 1.0:
+            assert np.allclose(out["m"], [1, 0, 0, RT, 0, RT, 0, 0, 0, 0], atol=1e-13)
+            assert np.allclose(out["n"], [1, 0, 0, RT, 0, RT], atol=1e-13)
+        else:
+            assert np.allclose(out["m"][3:6], [(x * x * f).sum() / rho, (x * y * f).sum() / rho,
+                                               (y * y * f).sum() / rho], rtol=1e-10)
+            Q = np.array([((x * x + y * y) * x * f).sum(), ((x * x + y * y) * y * f).sum()])
+            assert np.isclose(out["m"][6] + out["m"][8], Q[0] / rho, rtol=1e-10)
+            assert np.isclose(out["m"][7] + out["m"][9], Q[1] / rho, rtol=1e-10)
+            assert np.isclose(out["m"][6], 3 * out["m"][8], rtol=1e-12)
+            assert np.isclose(out["n"][0], g.sum() / (rho * K * RT), rtol=1e-10)
+            assert np.isclose(out["n"][1], (x * g).sum() / (rho * K * RT), rtol=1e-10, atol=1e-13)
+
+
+@pytest.mark.parametrize("kn,expect", [(0.005, "w"), (10 ** -1.5, "mid"), (0.2, "one")])
+def test_knudsen_limiter_branches(kn, expect):
+    """App. D: unchanged below Kn = 0.01, halfway (in log10) at Kn = 10^-1.5,
+    omega_H = 1 above Kn = 0.1."""
+    cfg = dict(li.hotbox(1.0, n=4)[0])
+    cfg.update(omega_f=1.8, omega_b=1.0, omega_h=1.6, kn_limiter=1)
+    rho, RT, K = 1.3, 0.9, cfg["K"]
+    mom = oracle.moments_from_primitives(2, K, [rho], [0.2], [-0.1], [RT])[:, 0]
+    # pure shear non-equilibrium P_xy = eps: Kn = 2|eps| / (rho (D+K) RT)
+    eps = kn * rho * (2 + K) * RT / 2
+    mom = mom.copy()
+    mom[4] += eps
+    out = oracle.collide(cfg, mom)
+    assert np.isclose(out["kn"], kn, rtol=1e-10)
+    w = {"w": (1.8, 1.6), "mid": (1.4, 1.3), "one": (1.0, 1.0)}[expect]
+    assert np.isclose(out["om_f"], w[0], rtol=1e-12)
+    assert np.isclose(out["om_h"], w[1], rtol=1e-12)
+    assert out["om_b"] == 1.0
+
+
+# --------------------------------------------------------------------------
+# Entropic population reconstruction (Sec. II.D)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("RT", [0.2, 0.5, 1.0, 4.0, 32.0])
+def test_epr_equilibrium_converges_fast(RT):
+    """Equilibrium targets from the guess of Eq. (IID13) converge in fewer than
+    five Newton updates (Sec. II.D), to populations that reproduce them."""
+    u = (0.37, -0.21)
+    c, dC, d, h = oracle.las(2, u, RT)
+    for nb, target in ((10, [1, 0, 0, RT, 0, RT, 0, 0, 0, 0]), (6, [1, 0, 0, RT, 0, RT])):
+        st, lam, pop, it = oracle.epr(2, c, dC, u, RT, np.array(target, dtype=float))
+        assert st == 0
+        assert it - 1 < 5          # iterations counted here include the polishing update
+        assert np.all(pop > 0)
+        ct = c - np.array(u)
+        T = _basis(ct, nb)
+        assert np.allclose(T.T @ pop, target, atol=1e-13 * max(1, RT ** 1.5))
+
+
+def _basis(ct, nb):
+    x, y = ct[:, 0], ct[:, 1]
+    cols = [np.ones_like(x), x, y, x * x, x * y, y * y, x ** 3, x * x * y, x * y * y, y ** 3]
+    return np.stack(cols[:nb], axis=1)
+
+
+def test_epr_matches_brute_force_dual_minimiser():
+    """The reconstruction is the unique minimiser of the convex dual
+    Phi(l) = sum_i dC_i exp(-1 - l.T_i) + l.m; an independent quasi-Newton
+    minimiser of Phi must find the same multipliers."""
+    rng = np.random.default_rng(5)
+    for trial in range(4):
+        RT = rng.uniform(0.6, 2.0)
+        u = rng.uniform(-1, 1, size=2)
+        c, dC, d, h = oracle.las(2, u, RT)
+        ct = c - u
+        T = _basis(ct, 10)
+        # realizable target: moments of a perturbed Gaussian on the same stencil
+        w = dC * np.exp(-(ct ** 2).sum(1) / (2 * RT)) * (1 + 0.2 * np.tanh(rng.standard_normal(len(dC))))
+        w /= w.sum()
+        target = T.T @ w
+        st, lam, pop, it = oracle.epr(2, c, dC, u, RT, target)
+        assert st == 0
+
+        def phi(l):
+            return (dC * np.exp(-1 - T @ l)).sum() + l @ target
+
+        def grad(l):
+            return -(T.T @ (dC * np.exp(-1 - T @ l))) + target
+
+        l0 = oracle.epr_initial(2, 10, RT)
+        res = minimize(phi, l0, jac=grad, method="BFGS", options={"gtol": 1e-13, "maxiter": 5000})
+        assert np.allclose(res.x, lam, rtol=1e-5, atol=1e-6)
+        assert np.allclose(T.T @ pop, target, atol=1e-12)
+        assert np.all(pop > 0)
+
+
+def test_epr_reports_unrealizable_moments():
+    """A target outside the moment cone of the stencil has no positive
+    reconstruction: the solve must fail loudly (status EEPR)."""
+    RT = 1.0
+    u = (0.0, 0.0)
+    c, dC, d, h = oracle.las(2, u, RT)
+    target = np.array([1, 0, 0, -0.5, 0, RT, 0, 0, 0, 0], dtype=float)   # negative variance
+    st, lam, pop, it = oracle.epr(2, c, dC, u, RT, target)
+    assert st == oracle.EEPR
+
+
+# --------------------------------------------------------------------------
+# Whole step (Sec. II.E, III.A)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("u,RT,tol", [((0.37, -0.21), 1.0, 1e-13), ((2.5, -0.5), 0.3, 1e-13),
+                                      ((10.0, 10.0), 0.5, 2e-11)])
+def test_uniform_state_is_invariant(u, RT, tol):
+    """A uniform equilibrium is a fixed point.  At |u| = 14 the raw-to-central
+    transform of Eq. (IIB9b) cancels terms of size rho |u|^3, so rounding of
+    the raw moments reappears as a ~1e-12 heat flux that omega_h = 2 does not
+    damp; the bound is looser there."""
+    cfg, prim = li.hotbox(RT, n=6, ny=5, u=u)
+    m = prim_moments(cfg, prim)
+    st, out, stats, done = oracle.step(cfg, m, 3)
+    assert st == 0
+    assert np.max(np.abs(out - m) / np.abs(m).max(axis=1, keepdims=True)) < tol
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_conservation_periodic(dim):
+    cfg, prim = li.smooth_periodic(1, n=16 if dim == 2 else 48, ny=10, dim=dim)
+    m = prim_moments(cfg, prim)
+    cur = m
+    for _ in range(4):
+        st, nxt, stats, done = oracle.step(cfg, cur, 1)
+        assert st == 0
+        mass = [cur[0].sum(), nxt[0].sum()]
+        assert abs(mass[1] - mass[0]) / mass[0] < 1e-13
+        for k in range(1, dim + 1):
+            assert abs(nxt[k].sum() - cur[k].sum()) / mass[0] < 1e-13
+        if dim == 2:
+            e0, e1 = (cur[3] + cur[5] + cur[8]).sum(), (nxt[3] + nxt[5] + nxt[8]).sum()
+        else:
+            e0, e1 = (cur[2] + cur[4]).sum(), (nxt[2] + nxt[4]).sum()
+        assert abs(e1 - e0) / e0 < 1e-13
+        cur = nxt
+
+
+def test_positivity_and_limiter_on_quadrants():
+    cfg, prim = li.quadrants(4, n=24)
+    m = prim_moments(cfg, prim)
+    st, out, stats, done = oracle.step(cfg, m, 4)
+    assert st == 0 and done == 4
+    assert stats["limited"] > 0            # shocks switch the limiter on
+    rho = out[0]
+    assert np.all(rho > 0)
+
+
+def test_integer_galilean_boost_is_exact():
+    """Shifting u by an integer shifts every stencil by that integer, so the
+    boosted run equals the unboosted run advected by one cell per step."""
+    cfg, prim = li.smooth_periodic(2, n=12, ny=10)
+    m = prim_moments(cfg, prim)
+    st0, out0, *_ = oracle.step(cfg, m, 2)
+    prim_b = dict(prim)
+    prim_b["ux"] = prim["ux"] + 1.0
+    mb = prim_moments(cfg, prim_b)
+    st1, out1, *_ = oracle.step(cfg, mb, 2)
+    assert st0 == 0 and st1 == 0
+
+    def primitives(o):
+        rho = o[0]
+        ux, uy = o[1] / rho, o[2] / rho
+        RT = ((o[3] + o[5] + o[8]) / rho - ux * ux - uy * uy) / (2 + cfg["K"])
+        return np.stack([rho, ux, uy, RT])
+
+    a = primitives(out0.reshape(11, 10, 12))
+    b = primitives(out1.reshape(11, 10, 12))
+    b_shift = np.roll(b, -2, axis=2)
+    b_shift[1] -= 1.0
+    assert np.max(np.abs(a - b_shift)) < 1e-11
+
+
+def test_mirror_symmetry():
+    cfg, prim = li.smooth_periodic(3, n=12, ny=8)
+    m = prim_moments(cfg, prim).reshape(11, 8, 12)
+    st0, out0, *_ = oracle.step(cfg, m.reshape(11, -1), 2)
+    # mirror x -> -x: odd-in-x moments flip sign
+    sign = np.array([1, -1, 1, 1, -1, 1, -1, 1, 1, -1, 1])[:, None, None]
+    mm = (m[:, :, ::-1] * sign).reshape(11, -1)
+    st1, out1, *_ = oracle.step(cfg, mm, 2)
+    back = (out1.reshape(11, 8, 12)[:, :, ::-1] * sign).reshape(11, -1)
+    scale = np.abs(out0).max(axis=1, keepdims=True)
+    assert np.max(np.abs(back - out0) / scale) < 1e-12
+
+
+def _run_riemann(cfg, prim, frac=0.4):
+    m = prim_moments(cfg, prim)
+    N = cfg["nx"]
+    L = (prim["rho"][0, 0], prim["ux"][0, 0], prim["rho"][0, 0] * prim["RT"][0, 0])
+    R = (prim["rho"][0, -1], prim["ux"][0, -1], prim["rho"][0, -1] * prim["RT"][0, -1])
+    smin, smax = riemann.wave_speeds(L, R)
+    steps = int(frac * (N / 2) / max(abs(smin), abs(smax)))
+    st, out, stats, done = oracle.step(cfg, m, steps)
+    x = np.arange(N) + 0.5
+    ex = riemann.sample(L, R, (x - N / 2) / steps)
+    return st, np.abs(out[0] - ex[0]).mean() / (ex[0].max() - ex[0].min()), stats
+
+
+def test_riemann_solver_textbook_values():
+    # Sod star state, a standard value of the exact solver: p* = 0.30313, u* = 0.92745
+    ps, us = riemann.star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    assert abs(ps - 0.30313) < 1e-5 and abs(us - 0.92745) < 1e-5
+
+
+def test_sod_converges_to_exact_solution():
+    """Sod's shock tube (Sec. V.A, Eq. VIA1) against the exact Riemann solution;
+    L1 density error (normalised by the density range) falls with resolution."""
+    errs = []
+    for N in (200, 400):
+        cfg, prim = li.riemann1d(n=N, states=((1.0, 0.0, 1.0), (0.125, 0.0, 0.8 * 0.125)), pad=32)
+        st, e, stats = _run_riemann(cfg, prim)
+        assert st == 0
+        errs.append(e)
+    assert errs[1] < errs[0] < 0.015
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_two_state_inputs_match_exact_riemann(seed):
+    """The seeded two-state inputs (density and pressure U[0.1, 1]) against the
+    exact solution, before any wave reaches the outflow pads."""
+    errs = []
+    for N in (250, 500):
+        cfg, prim = li.riemann1d(seed, n=N)
+        st, e, stats = _run_riemann(cfg, prim)
+        assert st == 0
+        errs.append(e)
+    assert errs[1] < errs[0]
+    assert errs[1] < 0.02
+
+
+def test_lax_courant_numbers_and_accuracy():
+    """Lax problem (Sec. V.B): lattice Courant numbers quoted by the paper and
+    agreement with the exact solution with and without acoustic scaling."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "lax_courant.txt"))
+    errs = []
+    for scale, rtmax, colat in rows:
+        cfg, prim = li.riemann1d(n=1000, states=((0.445, 0.698, 3.528), (0.5, 0.0, 0.517)),
+                                 scale=scale, pad=48)
+        assert abs(prim["RT"].max() - rtmax) < 0.01
+        m = prim_moments(cfg, prim)
+        steps = int(round(0.14 / (scale / 1000)))
+        st, out, stats, done = oracle.step(cfg, m, steps)
+        assert st == 0
+        assert abs(stats["colat_max"] - colat) < 0.6
+        L = (0.445, 0.698 * scale, 3.528 * scale ** 2)
+        R = (0.5, 0.0, 0.517 * scale ** 2)
+        x = np.arange(1000) + 0.5
+        ex = riemann.sample(L, R, (x - 500) / steps)
+        errs.append(np.abs(out[0] - ex[0]).mean() / (ex[0].max() - ex[0].min()))
+    assert max(errs) < 0.02
+    assert errs[1] < errs[0]          # lower lattice temperature is less diffusive
+
+
+@pytest.mark.parametrize("RT", [0.5, 1.0])
+def test_shear_wave_viscosity(RT):
+    """Sec. IV.A: decay of a shear wave gives nu_s = RT (1/omega_f - 1/2)
+    (App. C, Eq. C8a); the paper reports +-10%."""
+    L, nu = 64, 0.1
+    cfg, prim = li.shear_wave(L=L, ny=2, RT=RT, nu=nu)
+    m = prim_moments(cfg, prim)
+    k = 2 * np.pi / L
+    t = int(0.5 / (nu * k * k))
+    st, out, stats, done = oracle.step(cfg, m, t)
+    assert st == 0
+    uy = out[2] / out[0]
+    nu_m = -np.log(np.abs(uy).max() / 1e-3) / (k * k * t)
+    assert abs(nu_m / nu - 1) < 0.03
+
+
+@pytest.mark.parametrize("RT", [0.5, 1.0])
+def test_thermal_wave_diffusivity(RT):
+    """Sec. IV.B: decay of an isobaric density wave gives the diffusivity
+    alpha = kappa / (rho C_p) = RT (1/omega_h - 1/2) (Eq. C8c, B22b)."""
+    L, a = 64, 0.1
+    cfg, prim = li.shear_wave(L=L, ny=2, RT=RT, nu=a, amp=0.0)
+    x = (np.arange(L) + 0.5)[None, :]
+    rho = (1.0 + 0.01 * np.cos(2 * np.pi * x / L)) * np.ones((2, 1))
+    prim["rho"] = rho
+    prim["RT"] = RT / rho
+    m = prim_moments(cfg, prim)
+    k = 2 * np.pi / L
+    t = int(0.5 / (a * k * k))
+    st, out, stats, done = oracle.step(cfg, m, t)
+    assert st == 0
+    am = -np.log(np.abs(out[0] - 1.0).max() / 0.01) / (k * k * t)
+    assert abs(am / a - 1) < 0.10
+
+
+@pytest.mark.parametrize("RT", [0.5, 8.0])
+def test_acoustic_pulse_sound_speed(RT):
+    """Sec. IV.D: a small pressure pulse travels at c_s = sqrt(gamma RT)."""
+    cfg, prim = li.acoustic_pulse(n=600, RT=RT, pad=40)
+    m = prim_moments(cfg, prim)
+    cs = np.sqrt(1.4 * RT)
+    t = int(200 / cs)
+    st, out, stats, done = oracle.step(cfg, m, t)
+    assert st == 0
+    rho = out[0]
+    ux = out[1] / rho
+    RTm = ((out[2] + out[4]) / rho - ux ** 2) / (1 + cfg["K"])
+    p = rho * RTm
+    x = np.arange(600) + 0.5
+    i = np.argmax(np.where(x > 300, p, -1))
+    y0, y1, y2 = p[i - 1], p[i], p[i + 1]
+    xp = x[i] + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)
+    assert abs((xp - 300) / t / cs - 1) < 0.01
+
+
+def test_failure_is_reported_not_clamped():
+    cfg, prim = li.hotbox(1.0, n=4, ny=4)
+    m = prim_moments(cfg, prim)
+    m[3, 5] = -10.0                     # negative energy in one cell -> RT < 0
+    st, out, stats, done = oracle.step(cfg, m, 1)
+    assert st == oracle.EEPR
+    assert done == 0
+    assert stats["fail_cell"] == 5
