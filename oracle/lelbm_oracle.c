@@ -719,11 +719,13 @@ int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
                 if (D == 2 && p->bc[2] == ORC_BC_SLIPWALL && ly < 0) { ly = -1 - ly; cy = -cy; }
                 if (D == 2 && p->bc[3] == ORC_BC_SLIPWALL && ly >= ny) { ly = 2 * ny - 1 - ly; cy = -cy; }
                 if (lx < 0 || lx >= nx || ly < 0 || ly >= ny) {
-                    /* arrivals in pads are discarded (Sec. III.A); a wall
-                     * path that still leaves the domain is a reach error */
-                    int wallx = p->bc[0] == ORC_BC_SLIPWALL || p->bc[1] == ORC_BC_SLIPWALL;
-                    int wally = D == 2 && (p->bc[2] == ORC_BC_SLIPWALL || p->bc[3] == ORC_BC_SLIPWALL);
-                    if ((wallx && (lx < 0 || lx >= nx)) || (wally && (ly < 0 || ly >= ny))) {
+                    /* arrivals in pads are discarded (Sec. III.A); a path
+                     * still beyond a wall after its reflection is a reach
+                     * error */
+                    int beyond = (lx < 0 && p->bc[0] == ORC_BC_SLIPWALL) || (lx >= nx && p->bc[1] == ORC_BC_SLIPWALL) ||
+                                 (D == 2 && ly < 0 && p->bc[2] == ORC_BC_SLIPWALL) ||
+                                 (D == 2 && ly >= ny && p->bc[3] == ORC_BC_SLIPWALL);
+                    if (beyond) {
                         if (status == ORC_OK) { status = ORC_EREACH; s.fail_cell = k; s.fail_code = ORC_EREACH; }
                     }
                     continue;
