@@ -1,0 +1,162 @@
+/*
+ * lelbm.h -- C ABI of the MI355X (gfx950) LELBM time step.
+ *
+ * The library advances the per-cell raw moments {M, G} of the Lagrangian
+ * entropic lattice Boltzmann method (arXiv 2508.06911) by whole time steps on
+ * one GPU.  One step is the paper's single-cell operation (Sec. II.F, Fig. of
+ * the modular flowchart) applied to every cell, followed by moment streaming:
+ *
+ *   collision      Sec. II.B, Eqs. (IIB6-IIB18), Knudsen limiter of App. D
+ *   stencil (LAS)  Sec. II.C, Eqs. (IIC6, IIC9-IIC11)
+ *   EPR            Sec. II.D, Eqs. (IID7-IID13)
+ *   streaming (MS) Sec. II.E, Eqs. (IIE3a-b); only moments are stored
+ *   fluid BCs      Sec. III.A; slip walls by specular path reflection, Sec. III.B
+ *
+ * Units are lattice units (dV = dx = dt = 1).  Moment order per cell:
+ *   2D (11): M0 Mx My Mxx Mxy Myy MDx MDy G0 Gx Gy
+ *   1D  (6): M0 Mx Mxx Mxxx G0 Gx
+ * Host and device moment arrays are SoA [moment][y][x] over the nx*ny interior
+ * cells, FP64 unless stated otherwise.
+ *
+ * Conventions
+ *   - Every call returns an int status (LELBM_OK = 0 or a negative code);
+ *     lelbm_strerror() names it.
+ *   - The library copies every input; a context owns all device memory it
+ *     allocates; the caller owns every output buffer.
+ *   - All GPU work of a context is issued on the HIP stream given at creation
+ *     (NULL = the default stream).  Calls that return host data synchronise
+ *     that stream.
+ *   - Contexts share no global state; one context must not be used from two
+ *     threads at once.
+ *   - lelbm_step is transactional: if a step fails, the context keeps the state
+ *     of the last completed step and lelbm_last_failure() names the cell and
+ *     the step.
+ */
+#ifndef LELBM_H
+#define LELBM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lelbm_ctx lelbm_ctx;
+
+enum {
+    LELBM_OK = 0,
+    LELBM_EINVAL = -1,      /* invalid argument or parameter combination */
+    LELBM_ENOMEM = -2,      /* device or host allocation failed */
+    LELBM_EDEVICE = -3,     /* HIP runtime error */
+    LELBM_EEPR = -4,        /* non-realizable cell state (rho <= 0, RT <= 0),
+                               Newton iteration cap, Cholesky breakdown or line
+                               search exhausted in the entropic reconstruction */
+    LELBM_ENONFINITE = -5,  /* non-finite moments */
+    LELBM_EREACH = -6       /* a population path leaves the padded domain
+                               through a wall, or a cell is outside the
+                               supported stencil range: more than 3
+                               refinement levels (RT < 0.0123), acoustic
+                               radius above 128 (RT > ~1030) or |u| above
+                               2048 cells per step */
+};
+
+enum { LELBM_BC_PERIODIC = 0, LELBM_BC_OUTFLOW = 1, LELBM_BC_INFLOW = 2, LELBM_BC_SLIPWALL = 3 };
+
+/* LELBM_FP64: every stage in FP64.
+ * LELBM_MIXED: stored moments, collision, reconstruction passes and streaming
+ * in FP32; the Newton Hessian solve, the log-sum normalisation and the final
+ * conserved-moment correction in FP64. */
+enum { LELBM_FP64 = 0, LELBM_MIXED = 1 };
+
+/* Initial guess of the Newton solve: Eq. (IID13), or the learned network set
+ * with lelbm_set_mlp (with Eq. (IID13) as fallback). */
+enum { LELBM_GUESS_EQ = 0, LELBM_GUESS_MLP = 1 };
+
+typedef struct {
+    int dim, nx, ny;                  /* dim = 1 requires ny = 1 */
+    double K;                         /* internal DoF: gamma = (D+K+2)/(D+K), App. B Eqs. (B22a-b); K > 0 */
+    double omega_f, omega_b, omega_h; /* shear, bulk, heat-flux collision frequencies, Eq. (IIB16);
+                                         omega = 1/(tau/dt + 1/2), App. C Eq. (C7) */
+    double n_conf;                    /* conformation number n of Eq. (IIC6) (paper: 4) */
+    int r_min;                        /* minimum acoustic radius of Eq. (IIC6) (paper: 2) */
+    double newton_tol;                /* scaled moment residual ending Newton (paper: 1e-12) */
+    int newton_max_it;                /* iteration cap, e.g. 50 */
+    int kn_limiter;                   /* 1: Knudsen limiter of App. D, Eqs. (D2-D3) */
+    double kn_lo, kn_hi, omega_H;     /* log10 Kn thresholds and target frequency (paper: -2, -1, 1) */
+    int precision;                    /* LELBM_FP64 | LELBM_MIXED */
+    int guess;                        /* LELBM_GUESS_EQ | LELBM_GUESS_MLP */
+    int bc[4];                        /* faces xlo, xhi, ylo, yhi: LELBM_BC_*; periodic faces pair up */
+    int pad;                          /* pad width W of outflow/inflow faces (Sec. III, Fig. 5) */
+    double in_rho, in_u[2], in_RT;    /* inflow (Dirichlet) state of LELBM_BC_INFLOW faces */
+    const unsigned char *solid;       /* must be NULL (solid obstacles are not supported) */
+} lelbm_params;
+
+/* Statistics accumulated over the steps of one lelbm_step call.  Newton
+ * iterations count every multiplier update, including the final polishing
+ * update.  q is the number of stencil points of a cell (refined points
+ * counted individually).  sum[] = interior totals of mass, x/y momentum and
+ * energy (M0, Mx, My, Mxx+Myy+G0) after the last step. */
+typedef struct {
+    double it_mean_f, it_mean_g;
+    int it_max_f, it_max_g;
+    long fallbacks;                   /* cells whose learned guess was rejected */
+    long limited;                     /* cells whose frequencies the limiter changed */
+    long q_min, q_max;
+    double q_mean;
+    double rt_min, kn_max, colat_max; /* colat: Eq. (IIC7), |u| + R */
+    double sum[4];
+    long cells;                       /* cells processed (interior + pads) */
+} lelbm_stats;
+
+/* Number of stored moments per cell: 6 (1D) or 11 (2D); -1 for other dim. */
+int lelbm_num_moments(int dim);
+
+/* Equilibrium raw moments of primitive fields (Eqs. IIB7a-d, App. A Eqs. A3,
+ * A7): out[k*n + i] for k < lelbm_num_moments(dim).  uy is ignored in 1D and
+ * may be NULL there.  Host pointers; EINVAL on bad dim or n < 0. */
+int lelbm_moments_from_primitives(int dim, double K, long n, const double *rho, const double *ux,
+                                  const double *uy, const double *RT, double *out);
+
+/* Create a context from host moments (SoA, nmom*nx*ny doubles).  hip_stream
+ * is a hipStream_t (NULL = default stream).  On success *out owns all device
+ * memory of the run.  EINVAL on inconsistent parameters, ENOMEM on allocation
+ * failure, EDEVICE on a HIP error. */
+int lelbm_create(const lelbm_params *p, const double *moments, void *hip_stream, lelbm_ctx **out);
+
+/* As lelbm_create, from device moments (FP64, or FP32 if dev_is_fp32 != 0);
+ * the data is copied on hip_stream. */
+int lelbm_create_device(const lelbm_params *p, const void *dev_moments, int dev_is_fp32, void *hip_stream,
+                        lelbm_ctx **out);
+
+/* Advance nsteps >= 0 time steps.  st may be NULL.  Synchronises the stream
+ * once at the end.  On failure the state of the last completed step is kept. */
+int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st);
+
+/* Copy the current moments to caller-owned host memory (nmom*nx*ny FP64). */
+int lelbm_read_moments(const lelbm_ctx *c, double *host_out);
+
+/* Copy the current moments to caller-owned device memory (nmom*nx*ny FP64),
+ * ordered on the context's stream (no host synchronisation). */
+int lelbm_read_moments_device(const lelbm_ctx *c, void *dev_out);
+
+/* Cell index (row-major over the padded source domain, pads included) and
+ * step (0-based within the failing lelbm_step call) of the first failure. */
+int lelbm_last_failure(const lelbm_ctx *c, long *node, int *step);
+
+/* Per-kernel timing: when enabled, lelbm_step records HIP events around each
+ * kernel and lelbm_kernel_times returns accumulated milliseconds and launch
+ * counts for: [0] pad fill, [1] stencil pre-pass, [2] tile scan,
+ * [3] collision + reconstruction, [4] moment-streaming gather, [5] stats.
+ * n is the capacity of ms and launches. */
+int lelbm_set_timing(lelbm_ctx *c, int enable);
+int lelbm_kernel_times(const lelbm_ctx *c, double *ms, long *launches, int n);
+
+/* Device bytes held by the context: persistent state (moments, descriptors)
+ * and transient population scratch. */
+int lelbm_memory(const lelbm_ctx *c, long *persistent_bytes, long *scratch_bytes);
+
+const char *lelbm_strerror(int code);
+void lelbm_destroy(lelbm_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

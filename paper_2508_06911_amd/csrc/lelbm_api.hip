@@ -1,0 +1,470 @@
+// Host runtime of the LELBM library: the C ABI declared in include/lelbm.h.
+//
+// A context owns the padded state (two ping-pong buffers), the per-cell
+// stencil descriptors, the per-tile scratch layout, the population scratch,
+// error flags and statistics, all in device memory.  lelbm_step enqueues the
+// kernels of each step on the context's stream and synchronises once at the
+// end to read the error flags; a failed step leaves the previous state in
+// place because every kernel returns early once a flag is set.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <climits>
+#include <vector>
+
+#include "lelbm_internal.h"
+
+using namespace lelbm;
+
+struct lelbm_ctx {
+    lelbm_params p;
+    Geom g;
+    Phys ph;
+    int mixed;
+    int nmom;
+    hipStream_t stream;
+    int device;
+    Buffers b;
+    int cur;                 // state buffer holding the current moments
+    long last_fail_node;
+    int last_fail_step;
+    int timing;
+    hipEvent_t ev[2];
+    double kms[6];
+    long klaunch[6];
+    long long persistent_bytes;
+};
+
+// HIP errors are reported as LELBM_EDEVICE; with LELBM_DEBUG set in the
+// environment the failing call is also printed to stderr.
+static void report_hip(hipError_t e, const char *what, int line) {
+    if (getenv("LELBM_DEBUG")) fprintf(stderr, "lelbm: %s failed at line %d: %s\n", what, line, hipGetErrorString(e));
+}
+
+#define HIPCHECK(x)                                  \
+    do {                                             \
+        hipError_t e_ = (x);                         \
+        if (e_ != hipSuccess) {                      \
+            report_hip(e_, #x, __LINE__);            \
+            return LELBM_EDEVICE;                    \
+        }                                            \
+    } while (0)
+
+extern "C" int lelbm_num_moments(int dim) { return dim == 1 ? 6 : (dim == 2 ? 11 : -1); }
+
+extern "C" int lelbm_moments_from_primitives(int dim, double K, long n, const double *rho, const double *ux,
+                                             const double *uy, const double *RT, double *out) {
+    int nm = lelbm_num_moments(dim);
+    if (nm < 0 || n < 0 || !rho || !ux || !RT || !out || (dim == 2 && !uy)) return LELBM_EINVAL;
+    for (long i = 0; i < n; i++) {
+        double r = rho[i], x = ux[i], y = dim == 2 ? uy[i] : 0.0, T = RT[i];
+        double m[11];
+        if (dim == 1) {
+            m[0] = r; m[1] = r * x; m[2] = r * (x * x + T); m[3] = r * (x * x + 3.0 * T) * x;
+            m[4] = r * K * T; m[5] = r * K * T * x;
+        } else {
+            double uu = x * x + y * y;
+            m[0] = r; m[1] = r * x; m[2] = r * y;
+            m[3] = r * (x * x + T); m[4] = r * (x * y); m[5] = r * (y * y + T);
+            m[6] = r * (uu + 4.0 * T) * x; m[7] = r * (uu + 4.0 * T) * y;
+            m[8] = r * K * T; m[9] = r * K * T * x; m[10] = r * K * T * y;
+        }
+        for (int k = 0; k < nm; k++) out[(long)k * n + i] = m[k];
+    }
+    return LELBM_OK;
+}
+
+extern "C" const char *lelbm_strerror(int code) {
+    switch (code) {
+    case LELBM_OK: return "ok";
+    case LELBM_EINVAL: return "invalid argument";
+    case LELBM_ENOMEM: return "out of memory";
+    case LELBM_EDEVICE: return "HIP device error";
+    case LELBM_EEPR: return "entropic reconstruction failed (non-realizable state or Newton failure)";
+    case LELBM_ENONFINITE: return "non-finite moments";
+    case LELBM_EREACH: return "population path or stencil refinement out of range";
+    default: return "unknown error";
+    }
+}
+
+static int validate(const lelbm_params *p) {
+    if (!p) return LELBM_EINVAL;
+    if (p->dim != 1 && p->dim != 2) return LELBM_EINVAL;
+    if (p->nx <= 0 || p->ny <= 0 || (p->dim == 1 && p->ny != 1)) return LELBM_EINVAL;
+    if (!(p->K > 0.0) || !(p->n_conf > 0.0) || p->r_min < 1) return LELBM_EINVAL;
+    if (!(p->newton_tol > 0.0) || p->newton_max_it < 1) return LELBM_EINVAL;
+    if (p->precision != LELBM_FP64 && p->precision != LELBM_MIXED) return LELBM_EINVAL;
+    if (p->guess != LELBM_GUESS_EQ && p->guess != LELBM_GUESS_MLP) return LELBM_EINVAL;
+    if (p->precision == LELBM_MIXED || p->guess == LELBM_GUESS_MLP) return LELBM_EINVAL;
+    if (p->solid) return LELBM_EINVAL;
+    for (int f = 0; f < 4; f++)
+        if (p->bc[f] < LELBM_BC_PERIODIC || p->bc[f] > LELBM_BC_SLIPWALL) return LELBM_EINVAL;
+    for (int ax = 0; ax < p->dim; ax++) {
+        int a = p->bc[2 * ax], b = p->bc[2 * ax + 1];
+        if ((a == LELBM_BC_PERIODIC) != (b == LELBM_BC_PERIODIC)) return LELBM_EINVAL;
+    }
+    bool needpad = false;
+    for (int f = 0; f < 2 * p->dim; f++)
+        if (p->bc[f] == LELBM_BC_OUTFLOW || p->bc[f] == LELBM_BC_INFLOW) needpad = true;
+    if (needpad && p->pad < 1) return LELBM_EINVAL;
+    if (p->kn_limiter && !(p->kn_hi > p->kn_lo)) return LELBM_EINVAL;
+    return LELBM_OK;
+}
+
+static void free_ctx(lelbm_ctx *c) {
+    if (!c) return;
+    Buffers &b = c->b;
+    void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.tiles,
+                    b.dwin, b.scratch, b.flags, b.stats, b.partial};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    if (c->ev[0]) (void)hipEventDestroy(c->ev[0]);
+    if (c->ev[1]) (void)hipEventDestroy(c->ev[1]);
+    delete c;
+}
+
+static int reset_flags(lelbm_ctx *c) {
+    Flags f;
+    f.err = 0; f.step = -1; f.node = LLONG_MAX; f.need = 0;
+    HIPCHECK(hipMemcpyAsync(c->b.flags, &f, sizeof(Flags), hipMemcpyHostToDevice, c->stream));
+    return LELBM_OK;
+}
+
+static int grow_scratch(lelbm_ctx *c, long long need) {
+    if (need <= c->b.scratch_cap) return LELBM_OK;
+    long long cap = need + need / 4 + 1024;
+    size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    if (c->b.scratch) HIPCHECK(hipFree(c->b.scratch));
+    c->b.scratch = nullptr;
+    c->b.scratch_cap = 0;
+    if (hipMalloc(&c->b.scratch, (size_t)cap * esz) != hipSuccess) { c->b.scratch = nullptr; return LELBM_ENOMEM; }
+    c->b.scratch_cap = cap;
+    return LELBM_OK;
+}
+
+static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, lelbm_ctx **cc) {
+    int v = validate(p);
+    if (v != LELBM_OK) return v;
+    if (!out) return LELBM_EINVAL;
+    lelbm_ctx *c = new (std::nothrow) lelbm_ctx();
+    if (!c) return LELBM_ENOMEM;
+    memset(&c->b, 0, sizeof(c->b));
+    c->ev[0] = c->ev[1] = nullptr;
+    c->p = *p;
+    c->p.solid = nullptr;
+    c->mixed = p->precision == LELBM_MIXED;
+    c->nmom = lelbm_num_moments(p->dim);
+    c->stream = (hipStream_t)stream;
+    c->cur = 0;
+    c->last_fail_node = -1;
+    c->last_fail_step = -1;
+    c->timing = 0;
+    for (int k = 0; k < 6; k++) { c->kms[k] = 0; c->klaunch[k] = 0; }
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return LELBM_EDEVICE; }
+    Geom &g = c->g;
+    memset(&g, 0, sizeof(g));
+    g.dim = p->dim; g.nx = p->nx; g.ny = p->ny;
+    for (int f = 0; f < 4; f++) g.bc[f] = f < 2 * p->dim ? p->bc[f] : LELBM_BC_PERIODIC;
+    auto padw = [&](int f) { return (g.bc[f] == LELBM_BC_OUTFLOW || g.bc[f] == LELBM_BC_INFLOW) ? p->pad : 0; };
+    g.wl = padw(0); g.wr = padw(1);
+    g.wb = p->dim == 2 ? padw(2) : 0; g.wt = p->dim == 2 ? padw(3) : 0;
+    g.sxn = g.nx + g.wl + g.wr;
+    g.syn = g.ny + g.wb + g.wt;
+    g.ns = (long long)g.sxn * g.syn;
+    if (p->dim == 2) { g.tx = 16; g.ty = 16; }
+    else { g.tx = 256; g.ty = 1; }
+    g.ntx = (g.sxn + g.tx - 1) / g.tx; g.nty = (g.syn + g.ty - 1) / g.ty;
+    g.dtx = (g.nx + g.tx - 1) / g.tx; g.dty = (g.ny + g.ty - 1) / g.ty;
+    Phys &ph = c->ph;
+    ph.K = p->K; ph.omega_f = p->omega_f; ph.omega_b = p->omega_b; ph.omega_h = p->omega_h;
+    ph.n_conf = p->n_conf; ph.r_min = p->r_min; ph.tol = p->newton_tol; ph.maxit = p->newton_max_it;
+    ph.kn_limiter = p->kn_limiter; ph.kn_lo = p->kn_lo; ph.kn_hi = p->kn_hi; ph.omega_H = p->omega_H;
+    ph.kn_lo_lin = pow(10.0, p->kn_lo); ph.kn_hi_lin = pow(10.0, p->kn_hi);
+    ph.in_rho = p->in_rho; ph.in_u[0] = p->in_u[0]; ph.in_u[1] = p->dim == 2 ? p->in_u[1] : 0.0;
+    ph.in_RT = p->in_RT;
+
+    size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+    Buffers &b = c->b;
+    long long ns = g.ns;
+    int nt = g.ntx * g.nty, nd = g.dtx * g.dty;
+    bool ok = true;
+    ok = ok && hipMalloc(&b.mom[0], (size_t)c->nmom * ns * esz) == hipSuccess;
+    ok = ok && hipMalloc(&b.mom[1], (size_t)c->nmom * ns * esz) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.desc_u, (size_t)2 * ns * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.desc_rho, (size_t)ns * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.desc_rt, (size_t)ns * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.desc_rn, (size_t)ns * sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.tiles, (size_t)nt * sizeof(TileInfo)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.dwin, (size_t)nd * sizeof(DWin)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.flags, sizeof(Flags)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.stats, sizeof(DevStats)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.partial, (size_t)(num_sum_blocks(g) + 1) * 4 * sizeof(double)) == hipSuccess;
+    if (!ok) { free_ctx(c); return LELBM_ENOMEM; }
+    c->persistent_bytes = (long long)2 * c->nmom * ns * esz + ns * (4 * sizeof(double) + sizeof(int)) +
+                          nt * sizeof(TileInfo) + nd * sizeof(DWin);
+    if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+        free_ctx(c);
+        return LELBM_EDEVICE;
+    }
+    if (reset_flags(c) != LELBM_OK) { free_ctx(c); return LELBM_EDEVICE; }
+    *cc = c;
+    return LELBM_OK;
+}
+
+// Copies interior moments (SoA over nx*ny, FP64 or FP32 source on host or
+// device) into the padded state buffer.
+static int upload_interior(lelbm_ctx *c, const void *src, int src_fp32, hipMemcpyKind kind) {
+    const Geom &g = c->g;
+    size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+    size_t ssz = src_fp32 ? sizeof(float) : sizeof(double);
+    long long n = (long long)g.nx * g.ny;
+    if (ssz != esz) {
+        // convert on the host
+        std::vector<char> host((size_t)c->nmom * n * ssz);
+        if (kind == hipMemcpyDeviceToDevice) {
+            HIPCHECK(hipMemcpyAsync(host.data(), src, host.size(), hipMemcpyDeviceToHost, c->stream));
+            HIPCHECK(hipStreamSynchronize(c->stream));
+        } else {
+            memcpy(host.data(), src, host.size());
+        }
+        std::vector<char> conv((size_t)c->nmom * n * esz);
+        for (long long i = 0; i < (long long)c->nmom * n; i++) {
+            double v = src_fp32 ? ((const float *)host.data())[i] : ((const double *)host.data())[i];
+            if (esz == sizeof(float)) ((float *)conv.data())[i] = (float)v;
+            else ((double *)conv.data())[i] = v;
+        }
+        return upload_interior(c, conv.data(), esz == sizeof(float), hipMemcpyHostToDevice);
+    }
+    for (int k = 0; k < c->nmom; k++) {
+        char *dst = (char *)c->b.mom[c->cur] + ((size_t)k * g.ns + (size_t)g.wb * g.sxn + g.wl) * esz;
+        const char *s = (const char *)src + (size_t)k * n * esz;
+        HIPCHECK(hipMemcpy2DAsync(dst, (size_t)g.sxn * esz, s, (size_t)g.nx * esz, (size_t)g.nx * esz, g.ny, kind,
+                                  c->stream));
+    }
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    return LELBM_OK;
+}
+
+static int finish_create(lelbm_ctx *c) {
+    // initial scratch: run the pre-pass once to size it
+    hipStream_t s = c->stream;
+    HIPCHECK(launch_fill_pads(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b.flags, s));
+    HIPCHECK(launch_reset_step(c->g, c->b, s));
+    HIPCHECK(launch_prepare(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, 0, s));
+    HIPCHECK(launch_scan(c->g, c->b, 0, s));
+    Flags f;
+    HIPCHECK(hipMemcpyAsync(&f, c->b.flags, sizeof(Flags), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (f.err == ERR_OVERFLOW) {
+        int r = grow_scratch(c, f.need);
+        if (r != LELBM_OK) return r;
+    } else if (f.err != 0) {
+        c->last_fail_node = (long)f.node;
+        c->last_fail_step = -1;
+        return f.err;
+    }
+    return reset_flags(c);
+}
+
+extern "C" int lelbm_create(const lelbm_params *p, const double *moments, void *hip_stream, lelbm_ctx **out) {
+    if (!moments) return LELBM_EINVAL;
+    lelbm_ctx *c = nullptr;
+    int r = create_common(p, hip_stream, out, &c);
+    if (r != LELBM_OK) return r;
+    r = upload_interior(c, moments, 0, hipMemcpyHostToDevice);
+    if (r == LELBM_OK) r = finish_create(c);
+    if (r != LELBM_OK) { free_ctx(c); return r; }
+    *out = c;
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_create_device(const lelbm_params *p, const void *dev_moments, int dev_is_fp32,
+                                   void *hip_stream, lelbm_ctx **out) {
+    if (!dev_moments) return LELBM_EINVAL;
+    lelbm_ctx *c = nullptr;
+    int r = create_common(p, hip_stream, out, &c);
+    if (r != LELBM_OK) return r;
+    r = upload_interior(c, dev_moments, dev_is_fp32, hipMemcpyDeviceToDevice);
+    if (r == LELBM_OK) r = finish_create(c);
+    if (r != LELBM_OK) { free_ctx(c); return r; }
+    *out = c;
+    return LELBM_OK;
+}
+
+static int timed(lelbm_ctx *c, int k, hipError_t (*fn)(lelbm_ctx *, void *), void *arg) {
+    if (c->timing) HIPCHECK(hipEventRecord(c->ev[0], c->stream));
+    HIPCHECK(fn(c, arg));
+    if (c->timing) {
+        HIPCHECK(hipEventRecord(c->ev[1], c->stream));
+        HIPCHECK(hipEventSynchronize(c->ev[1]));
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        c->kms[k] += ms;
+        c->klaunch[k]++;
+    }
+    return LELBM_OK;
+}
+
+struct StepArg { int step; };
+
+static hipError_t do_fill(lelbm_ctx *c, void *) {
+    return launch_fill_pads(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b.flags, c->stream);
+}
+static hipError_t do_prepare(lelbm_ctx *c, void *a) {
+    hipError_t e = launch_reset_step(c->g, c->b, c->stream);
+    if (e != hipSuccess) return e;
+    return launch_prepare(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
+}
+static hipError_t do_scan(lelbm_ctx *c, void *a) { return launch_scan(c->g, c->b, ((StepArg *)a)->step, c->stream); }
+static hipError_t do_epr(lelbm_ctx *c, void *a) {
+    return launch_epr(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
+}
+static hipError_t do_gather(lelbm_ctx *c, void *) {
+    return launch_gather(c->g, c->mixed, c->b.mom[c->cur ^ 1], c->b, c->stream);
+}
+
+extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
+    if (!c || nsteps < 0) return LELBM_EINVAL;
+    int dev;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev != c->device) HIPCHECK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    int r = reset_flags(c);
+    if (r != LELBM_OK) return r;
+    HIPCHECK(launch_reset_stats(c->b, s));
+    int base = 0;   // first step not known to be complete
+    while (base < nsteps) {
+        int cur0 = c->cur;
+        for (int k = base; k < nsteps; k++) {
+            StepArg a{k};
+            if ((r = timed(c, 0, do_fill, &a)) != LELBM_OK) return r;
+            if ((r = timed(c, 1, do_prepare, &a)) != LELBM_OK) return r;
+            if ((r = timed(c, 2, do_scan, &a)) != LELBM_OK) return r;
+            if ((r = timed(c, 3, do_epr, &a)) != LELBM_OK) return r;
+            if ((r = timed(c, 4, do_gather, &a)) != LELBM_OK) return r;
+            c->cur ^= 1;
+        }
+        Flags f;
+        HIPCHECK(hipMemcpyAsync(&f, c->b.flags, sizeof(Flags), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        if (f.err == 0) break;
+        // every kernel after the failing one returned early, so the state at
+        // the start of step f.step is intact
+        c->cur = (cur0 + (f.step - base)) & 1;
+        if (f.err != ERR_OVERFLOW) {
+            c->last_fail_node = (long)f.node;
+            c->last_fail_step = f.step;
+            return f.err;
+        }
+        if ((r = grow_scratch(c, f.need)) != LELBM_OK) return r;
+        if ((r = reset_flags(c)) != LELBM_OK) return r;
+        base = f.step;
+    }
+    if (st) {
+        HIPCHECK(launch_sums(c->g, c->mixed, c->b.mom[c->cur], c->b, s));
+        DevStats ds;
+        double sums[4];
+        HIPCHECK(hipMemcpyAsync(&ds, c->b.stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(sums, c->b.partial + (size_t)num_sum_blocks(c->g) * 4, sizeof(sums),
+                                hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        memset(st, 0, sizeof(*st));
+        double cells = ds.cells ? (double)ds.cells : 1.0;
+        st->it_mean_f = ds.it_sum_f / cells;
+        st->it_mean_g = ds.it_sum_g / cells;
+        st->it_max_f = ds.it_max_f;
+        st->it_max_g = ds.it_max_g;
+        st->fallbacks = (long)ds.fallbacks;
+        st->limited = (long)ds.limited;
+        st->q_min = ds.cells ? ds.q_min : 0;
+        st->q_max = ds.q_max;
+        st->q_mean = ds.q_sum / cells;
+        double v;
+        memcpy(&v, &ds.rt_min_bits, 8); st->rt_min = v;
+        memcpy(&v, &ds.kn_max_bits, 8); st->kn_max = v;
+        memcpy(&v, &ds.colat_max_bits, 8); st->colat_max = v;
+        for (int k = 0; k < 4; k++) st->sum[k] = sums[k];
+        st->cells = (long)ds.cells;
+    }
+    return LELBM_OK;
+}
+
+static int read_common(const lelbm_ctx *c, void *out, hipMemcpyKind kind, bool sync) {
+    const Geom &g = c->g;
+    size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+    long long n = (long long)g.nx * g.ny;
+    if (c->mixed) {
+        std::vector<float> tmp((size_t)c->nmom * n);
+        for (int k = 0; k < c->nmom; k++) {
+            const char *src = (const char *)c->b.mom[c->cur] + ((size_t)k * g.ns + (size_t)g.wb * g.sxn + g.wl) * esz;
+            HIPCHECK(hipMemcpy2DAsync(tmp.data() + (size_t)k * n, (size_t)g.nx * esz, src, (size_t)g.sxn * esz,
+                                      (size_t)g.nx * esz, g.ny, hipMemcpyDeviceToHost, c->stream));
+        }
+        HIPCHECK(hipStreamSynchronize(c->stream));
+        std::vector<double> d(tmp.begin(), tmp.end());
+        if (kind == hipMemcpyDeviceToHost) memcpy(out, d.data(), d.size() * sizeof(double));
+        else {
+            HIPCHECK(hipMemcpyAsync(out, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            HIPCHECK(hipStreamSynchronize(c->stream));
+        }
+        return LELBM_OK;
+    }
+    for (int k = 0; k < c->nmom; k++) {
+        const char *src = (const char *)c->b.mom[c->cur] + ((size_t)k * g.ns + (size_t)g.wb * g.sxn + g.wl) * esz;
+        HIPCHECK(hipMemcpy2DAsync((char *)out + (size_t)k * n * esz, (size_t)g.nx * esz, src, (size_t)g.sxn * esz,
+                                  (size_t)g.nx * esz, g.ny, kind, c->stream));
+    }
+    if (sync) HIPCHECK(hipStreamSynchronize(c->stream));
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_read_moments(const lelbm_ctx *c, double *host_out) {
+    if (!c || !host_out) return LELBM_EINVAL;
+    return read_common(c, host_out, hipMemcpyDeviceToHost, true);
+}
+
+extern "C" int lelbm_read_moments_device(const lelbm_ctx *c, void *dev_out) {
+    if (!c || !dev_out) return LELBM_EINVAL;
+    return read_common(c, dev_out, hipMemcpyDeviceToDevice, false);
+}
+
+extern "C" int lelbm_last_failure(const lelbm_ctx *c, long *node, int *step) {
+    if (!c) return LELBM_EINVAL;
+    if (node) *node = c->last_fail_node;
+    if (step) *step = c->last_fail_step;
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_set_timing(lelbm_ctx *c, int enable) {
+    if (!c) return LELBM_EINVAL;
+    c->timing = enable != 0;
+    for (int k = 0; k < 6; k++) { c->kms[k] = 0; c->klaunch[k] = 0; }
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_kernel_times(const lelbm_ctx *c, double *ms, long *launches, int n) {
+    if (!c || n < 0) return LELBM_EINVAL;
+    for (int k = 0; k < n && k < 6; k++) {
+        if (ms) ms[k] = c->kms[k];
+        if (launches) launches[k] = c->klaunch[k];
+    }
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_memory(const lelbm_ctx *c, long *persistent_bytes, long *scratch_bytes) {
+    if (!c) return LELBM_EINVAL;
+    if (persistent_bytes) *persistent_bytes = (long)c->persistent_bytes;
+    if (scratch_bytes) *scratch_bytes = (long)(c->b.scratch_cap * (c->mixed ? 4 : 8));
+    return LELBM_OK;
+}
+
+extern "C" void lelbm_destroy(lelbm_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    free_ctx(c);
+}

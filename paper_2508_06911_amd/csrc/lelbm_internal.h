@@ -1,0 +1,101 @@
+// Internal declarations shared by the host runtime and the kernels of the
+// LELBM library.  Not part of the public ABI (see include/lelbm.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lelbm.h"
+
+namespace lelbm {
+
+// Source cells are processed in tiles of TILE_N cells: 16 x 16 in 2D and
+// 256 x 1 in 1D.  One workgroup handles one tile in every per-cell kernel.
+constexpr int TILE_N = 256;
+constexpr int MAX_REFINE = 3;       // supported stencil refinement levels
+constexpr int MAX_RADIUS = 128;     // largest acoustic radius (RT up to ~1000)
+constexpr double MAX_SPEED = 2048.0;  // largest |u| component in cells per step
+
+// Internal error code: population scratch too small (the host grows it and
+// repeats the step).
+constexpr int ERR_OVERFLOW = -100;
+
+struct Geom {
+    int dim, nx, ny;
+    int wl, wr, wb, wt;       // pad widths on xlo, xhi, ylo, yhi
+    int sxn, syn;             // padded (source) domain extent
+    long long ns;             // sxn * syn
+    int bc[4];
+    int tx, ty;               // tile extent (16,16) or (256,1)
+    int ntx, nty;             // source tiles over the padded domain
+    int dtx, dty;             // destination tiles over the interior
+};
+
+struct Phys {
+    double K, omega_f, omega_b, omega_h;
+    double n_conf;
+    int r_min;
+    double tol;
+    int maxit;
+    int kn_limiter;
+    double kn_lo, kn_hi, omega_H;
+    double kn_lo_lin, kn_hi_lin;  // 10^kn_lo, 10^kn_hi
+    double in_rho, in_u[2], in_RT;
+};
+
+struct Flags {
+    int err;                 // 0 or first error code
+    int step;                // step index of the failure
+    long long node;          // smallest failing cell index of that kernel
+    long long need;          // scratch elements needed (ERR_OVERFLOW)
+};
+
+struct DevStats {
+    unsigned long long it_sum_f, it_sum_g, q_sum, limited, cells, fallbacks;
+    int it_max_f, it_max_g, q_max, q_min;
+    unsigned long long rt_min_bits, kn_max_bits, colat_max_bits;
+};
+
+// Per-source-tile layout of the population scratch.
+struct TileInfo {
+    int ox, oy;              // displacement of slot (0, 0)
+    int wx, wy;              // slot box extent
+    int fmt;                 // 0: (w_f, w_g) per slot; 1: all moments per slot
+    int pad_;
+    long long size;          // elements used by the tile
+    long long base;          // first element of the tile
+};
+
+// Per-destination-tile window of displacements to scan in the gather.
+struct DWin {
+    int lox, loy, hix, hiy;
+};
+
+struct Buffers {
+    void *mom[2];            // state (padded domain), FP64 or FP32, SoA [nmom][ns]
+    double *desc_u;          // [2][ns]  cell velocity
+    double *desc_rho;        // [ns]
+    double *desc_rt;         // [ns]
+    int *desc_rn;            // [ns]  R | (N_r << 16), -1 = no emission
+    TileInfo *tiles;         // [ntx*nty]
+    DWin *dwin;              // [dtx*dty]
+    void *scratch;           // population scratch
+    long long scratch_cap;   // elements
+    Flags *flags;
+    DevStats *stats;
+    double *partial;         // block partial sums for conserved totals
+};
+
+// Kernel launchers (defined in lelbm_kernels.hip).  All enqueue on `s`.
+hipError_t launch_fill_pads(const Geom &g, const Phys &ph, int mixed, void *mom, Flags *fl, hipStream_t s);
+hipError_t launch_prepare(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
+                          hipStream_t s);
+hipError_t launch_scan(const Geom &g, Buffers &b, int step, hipStream_t s);
+hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
+                      hipStream_t s);
+hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, hipStream_t s);
+hipError_t launch_sums(const Geom &g, int mixed, const void *mom, Buffers &b, hipStream_t s);
+hipError_t launch_reset_step(const Geom &g, Buffers &b, hipStream_t s);
+hipError_t launch_reset_stats(Buffers &b, hipStream_t s);
+int num_sum_blocks(const Geom &g);
+
+}  // namespace lelbm

@@ -1,0 +1,1002 @@
+// HIP kernels of the LELBM time step for gfx950 (MI355X).
+//
+// One step = pad fill -> stencil pre-pass -> tile scan -> per-cell collision
+// and entropic reconstruction -> moment-streaming gather.
+//
+//  * k_fill_pads   fluid boundary cells, Sec. III.A (inflow: equilibrium of the
+//                  prescribed state; outflow: zero-gradient copy, non-equilibrium kept)
+//  * k_prepare     macroscopic variables (Eq. IIB6), acoustic radius and
+//                  refinement level (Eqs. IIC6, IIC9), per-tile slot boxes of
+//                  the population scratch and per-destination-tile gather windows
+//  * k_scan        exclusive scan of tile sizes -> scratch offsets
+//  * k_epr         collision (Eqs. IIB9-IIB18, App. D), stencil enumeration
+//                  (Sec. II.C), Newton-Cholesky reconstruction (Eqs. IID7-IID13),
+//                  writes the moment fractions of Eq. (IIE3a) into the scratch
+//  * k_gather      moment streaming, Eq. (IIE3b), as a deterministic gather:
+//                  every destination cell sums the fractions that land on it
+//                  (the paper scatters with atomics); slip walls by mirror
+//                  sources (specular path reflection, Sec. III.B)
+//
+// Layout: the state is SoA [moment][cell] over the padded source domain.  The
+// population scratch is tile-major; inside a tile it is plane-major, then
+// slot-major, then cell-in-tile, so the 64 lanes of a wavefront that read the
+// same displacement from neighbouring sources read consecutive addresses.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "lelbm_internal.h"
+
+namespace lelbm {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <int D> struct Basis;
+template <> struct Basis<2> { static constexpr int NF = 10, NG = 6, NMF = 28, NMG = 15, NMOM = 11; };
+template <> struct Basis<1> { static constexpr int NF = 4, NG = 3, NMF = 7, NMG = 5, NMOM = 6; };
+
+// 2D monomials x^a y^b (a + b <= 6) are numbered degree-major, then by b.
+// The first 10 are the fluon basis 1,x,y,xx,xy,yy,xxx,xxy,xyy,yyy and the
+// first 6 the phonon basis.  1D monomials are x^k.
+__host__ __device__ constexpr int deg_of(int k) {
+    int d = 0;
+    while ((d + 1) * (d + 2) / 2 <= k) d++;
+    return d;
+}
+__host__ __device__ constexpr int mono_b(int k) { return k - deg_of(k) * (deg_of(k) + 1) / 2; }
+__host__ __device__ constexpr int mono_a(int k) { return deg_of(k) - mono_b(k); }
+__host__ __device__ constexpr int mono_idx(int a, int b) { return (a + b) * (a + b + 1) / 2 + b; }
+
+template <int D> __host__ __device__ constexpr int hess_idx(int i, int j) {
+    return D == 1 ? i + j : mono_idx(mono_a(i) + mono_a(j), mono_b(i) + mono_b(j));
+}
+template <int D> __host__ __device__ constexpr int order_of(int j) { return D == 1 ? j : deg_of(j); }
+
+// Decisions that define the stencil are evaluated without FMA contraction so
+// that every kernel (and the CPU) takes them identically.
+__device__ inline int las_radius(double RT, double n_conf, int r_min) {
+#pragma clang fp contract(off)
+    int R = (int)floor(n_conf * sqrt(RT) + 0.5);
+    return R > r_min ? R : r_min;
+}
+__device__ inline int las_levels(double RT) {
+#pragma clang fp contract(off)
+    return (int)floor(1.0 / (3.0 * sqrt(RT)) + 0.5);
+}
+__device__ inline bool in_disk2(double cx, double cy, double ux, double uy, double rr) {
+#pragma clang fp contract(off)
+    double a = cx - ux, b = cy - uy;
+    return a * a + b * b <= rr * rr;
+}
+__device__ inline bool in_disk1(double cx, double ux, double rr) {
+#pragma clang fp contract(off)
+    double a = cx - ux;
+    return a * a <= rr * rr;
+}
+__device__ inline double dist2(double cx, double cy, double ux, double uy) {
+#pragma clang fp contract(off)
+    double a = cx - ux, b = cy - uy;
+    return sqrt(a * a + b * b);
+}
+
+__device__ inline void flag_fail(Flags *fl, int code, int step, long long node) {
+    if (atomicCAS(&fl->err, 0, code) == 0) {
+        fl->step = step;
+    }
+    if (fl->err == code) atomicMin((unsigned long long *)&fl->node, (unsigned long long)node);
+}
+
+__device__ inline void atomic_max_pos(unsigned long long *a, double v) {
+    atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+__device__ inline void atomic_min_pos(unsigned long long *a, double v) {
+    atomicMin(a, (unsigned long long)__double_as_longlong(v));
+}
+
+// equilibrium raw moments (Eqs. IIB7a-d; App. A)
+template <int D>
+__device__ inline void eq_moments(double K, double rho, double ux, double uy, double RT, double *m) {
+    if (D == 1) {
+        m[0] = rho;
+        m[1] = rho * ux;
+        m[2] = rho * (ux * ux + RT);
+        m[3] = rho * (ux * ux + 3.0 * RT) * ux;
+        m[4] = rho * K * RT;
+        m[5] = rho * K * RT * ux;
+    } else {
+        double uu = ux * ux + uy * uy;
+        m[0] = rho;
+        m[1] = rho * ux;
+        m[2] = rho * uy;
+        m[3] = rho * (ux * ux + RT);
+        m[4] = rho * (ux * uy);
+        m[5] = rho * (uy * uy + RT);
+        m[6] = rho * (uu + 4.0 * RT) * ux;
+        m[7] = rho * (uu + 4.0 * RT) * uy;
+        m[8] = rho * K * RT;
+        m[9] = rho * K * RT * ux;
+        m[10] = rho * K * RT * uy;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pad fill (Sec. III.A)
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_fill_pads(Geom g, Phys ph, T *mom, Flags *fl) {
+    if (fl->err) return;
+    long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.ns) return;
+    int px = (int)(s % g.sxn), py = (int)(s / g.sxn);
+    int x = px - g.wl, y = py - g.wb;
+    bool pad = x < 0 || x >= g.nx || y < 0 || y >= g.ny;
+    if (!pad) return;
+    bool inflow = (x < 0 && g.bc[0] == LELBM_BC_INFLOW) || (x >= g.nx && g.bc[1] == LELBM_BC_INFLOW) ||
+                  (y < 0 && g.bc[2] == LELBM_BC_INFLOW) || (y >= g.ny && g.bc[3] == LELBM_BC_INFLOW);
+    constexpr int NM = Basis<D>::NMOM;
+    if (inflow) {
+        double m[11];
+        eq_moments<D>(ph.K, ph.in_rho, ph.in_u[0], ph.in_u[1], ph.in_RT, m);
+#pragma unroll
+        for (int k = 0; k < NM; k++) mom[k * g.ns + s] = (T)m[k];
+    } else {
+        int ix = x < 0 ? 0 : (x >= g.nx ? g.nx - 1 : x);
+        int iy = y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y);
+        long long src = (long long)(iy + g.wb) * g.sxn + (ix + g.wl);
+#pragma unroll
+        for (int k = 0; k < NM; k++) mom[k * g.ns + s] = mom[k * g.ns + src];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pre-pass: macroscopic variables, stencil radius/levels, tile slot boxes,
+// destination gather windows
+// ---------------------------------------------------------------------------
+__device__ inline void periodic_or_clip(int r0, int r1, int n, bool periodic, int *a, int *b, int *cnt) {
+    // splits [r0, r1] into at most two intervals inside [0, n)
+    if (periodic) {
+        if (r1 - r0 + 1 >= n) { a[0] = 0; b[0] = n - 1; *cnt = 1; return; }
+        int p = ((r0 % n) + n) % n, q = ((r1 % n) + n) % n;
+        if (p <= q) { a[0] = p; b[0] = q; *cnt = 1; }
+        else { a[0] = p; b[0] = n - 1; a[1] = 0; b[1] = q; *cnt = 2; }
+    } else {
+        int p = r0 < 0 ? 0 : r0, q = r1 > n - 1 ? n - 1 : r1;
+        if (p > q) { *cnt = 0; return; }
+        a[0] = p; b[0] = q; *cnt = 1;
+    }
+}
+
+__device__ inline void update_windows(const Geom &g, DWin *dwin, int rx0, int rx1, int ry0, int ry1, int lox,
+                                      int loy, int hix, int hiy) {
+    int ax[2], bx[2], ay[2], by[2], cx, cy;
+    periodic_or_clip(rx0, rx1, g.nx, g.bc[0] == LELBM_BC_PERIODIC, ax, bx, &cx);
+    periodic_or_clip(ry0, ry1, g.ny, g.dim == 2 && g.bc[2] == LELBM_BC_PERIODIC, ay, by, &cy);
+    for (int i = 0; i < cx; i++)
+        for (int j = 0; j < cy; j++)
+            for (int ty = ay[j] / g.ty; ty <= by[j] / g.ty; ty++)
+                for (int tx = ax[i] / g.tx; tx <= bx[i] / g.tx; tx++) {
+                    DWin *w = &dwin[ty * g.dtx + tx];
+                    atomicMin(&w->lox, lox);
+                    atomicMin(&w->loy, loy);
+                    atomicMax(&w->hix, hix);
+                    atomicMax(&w->hiy, hiy);
+                }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, Buffers b, int step) {
+    __shared__ int red[4][256];
+    __shared__ int redf[256];
+    __shared__ int s_err;
+    if (threadIdx.x == 0) s_err = b.flags->err;
+    __syncthreads();
+    if (s_err) return;
+    int t = blockIdx.x;
+    int tx0 = (t % g.ntx) * g.tx, ty0 = (t / g.ntx) * g.ty;
+    int l = threadIdx.x;
+    int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
+    bool valid = px < g.sxn && py < g.syn;
+    int lox = 1 << 29, loy = 1 << 29, hix = -(1 << 29), hiy = -(1 << 29), refined = 0;
+    if (valid) {
+        long long s = (long long)py * g.sxn + px;
+        double M0 = (double)mom[s], Mx = (double)mom[g.ns + s];
+        double My = 0.0, Mxx, Myy = 0.0, G0;
+        if (D == 1) {
+            Mxx = (double)mom[2 * g.ns + s];
+            G0 = (double)mom[4 * g.ns + s];
+        } else {
+            My = (double)mom[2 * g.ns + s];
+            Mxx = (double)mom[3 * g.ns + s];
+            Myy = (double)mom[5 * g.ns + s];
+            G0 = (double)mom[8 * g.ns + s];
+        }
+        double rho = M0, ux, uy = 0.0, RT;
+        {
+#pragma clang fp contract(off)
+            ux = Mx / rho;
+            if (D == 2) uy = My / rho;
+            double uu = ux * ux + uy * uy;
+            RT = ((Mxx + Myy + G0) / rho - uu) / (D + ph.K);
+        }
+        bool ok = rho > 0.0 && isfinite(rho) && RT > 0.0 && isfinite(RT) && isfinite(ux) && isfinite(uy);
+        int rn = -1;
+        if (!ok) {
+            flag_fail(b.flags, LELBM_EEPR, step, s);
+        } else {
+            int R = las_radius(RT, ph.n_conf, ph.r_min);
+            int Nr = las_levels(RT);
+            double umax = fmax(fabs(ux), fabs(uy));
+            if (Nr > MAX_REFINE || R > MAX_RADIUS || !(umax <= MAX_SPEED)) {
+                flag_fail(b.flags, LELBM_EREACH, step, s);
+            } else {
+                rn = R | (Nr << 16);
+                int ubx = (int)floor(ux + 0.5), uby = D == 2 ? (int)floor(uy + 0.5) : 0;
+                lox = ubx - R - 1; hix = ubx + R + 1;
+                loy = D == 2 ? uby - R - 1 : 0; hiy = D == 2 ? uby + R + 1 : 0;
+                refined = Nr > 0;
+            }
+        }
+        b.desc_u[s] = ux;
+        b.desc_u[g.ns + s] = uy;
+        b.desc_rho[s] = rho;
+        b.desc_rt[s] = RT;
+        b.desc_rn[s] = rn;
+    }
+    red[0][l] = lox; red[1][l] = loy; red[2][l] = hix; red[3][l] = hiy; redf[l] = refined;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (l < off) {
+            red[0][l] = min(red[0][l], red[0][l + off]);
+            red[1][l] = min(red[1][l], red[1][l + off]);
+            red[2][l] = max(red[2][l], red[2][l + off]);
+            red[3][l] = max(red[3][l], red[3][l + off]);
+            redf[l] |= redf[l + off];
+        }
+        __syncthreads();
+    }
+    if (l == 0) {
+        TileInfo ti;
+        ti.pad_ = 0;
+        if (red[0][0] > red[2][0]) {   // no emitting cell in the tile
+            ti.ox = ti.oy = 0; ti.wx = ti.wy = 0; ti.fmt = 0; ti.size = 0; ti.base = 0;
+        } else {
+            ti.ox = red[0][0]; ti.oy = red[1][0];
+            ti.wx = red[2][0] - red[0][0] + 1; ti.wy = red[3][0] - red[1][0] + 1;
+            ti.fmt = redf[0];
+            ti.size = (long long)ti.wx * ti.wy * TILE_N * (ti.fmt ? Basis<D>::NMOM : 2);
+            ti.base = 0;
+            // gather windows of the destination tiles this tile can reach
+            int x0 = tx0 - g.wl, x1 = min(tx0 + g.tx, g.sxn) - 1 - g.wl;
+            int y0 = ty0 - g.wb, y1 = min(ty0 + g.ty, g.syn) - 1 - g.wb;
+            int lx = ti.ox, ly = ti.oy, hx = red[2][0], hy = red[3][0];
+            // mirror images across slip walls: m = 0 none, 1 low face, 2 high face
+            bool slipx = g.bc[0] == LELBM_BC_SLIPWALL || g.bc[1] == LELBM_BC_SLIPWALL;
+            bool slipy = D == 2 && (g.bc[2] == LELBM_BC_SLIPWALL || g.bc[3] == LELBM_BC_SLIPWALL);
+            for (int mx = 0; mx < (slipx ? 3 : 1); mx++) {
+                if (mx == 1 && g.bc[0] != LELBM_BC_SLIPWALL) continue;
+                if (mx == 2 && g.bc[1] != LELBM_BC_SLIPWALL) continue;
+                for (int my = 0; my < (slipy ? 3 : 1); my++) {
+                    if (my == 1 && g.bc[2] != LELBM_BC_SLIPWALL) continue;
+                    if (my == 2 && g.bc[3] != LELBM_BC_SLIPWALL) continue;
+                    int gx0 = x0, gx1 = x1, glx = lx, ghx = hx;
+                    if (mx == 1) { gx0 = -1 - x1; gx1 = -1 - x0; glx = -hx; ghx = -lx; }
+                    if (mx == 2) { gx0 = 2 * g.nx - 1 - x1; gx1 = 2 * g.nx - 1 - x0; glx = -hx; ghx = -lx; }
+                    int gy0 = y0, gy1 = y1, gly = ly, ghy = hy;
+                    if (my == 1) { gy0 = -1 - y1; gy1 = -1 - y0; gly = -hy; ghy = -ly; }
+                    if (my == 2) { gy0 = 2 * g.ny - 1 - y1; gy1 = 2 * g.ny - 1 - y0; gly = -hy; ghy = -ly; }
+                    update_windows(g, b.dwin, gx0 + glx, gx1 + ghx, gy0 + gly, gy1 + ghy, glx, gly, ghx, ghy);
+                }
+            }
+        }
+        b.tiles[t] = ti;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of tile sizes (one workgroup)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_scan(int ntiles, TileInfo *tiles, Flags *fl, long long cap, int step) {
+    __shared__ long long sh[1024];
+    __shared__ long long carry;
+    if (fl->err) return;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < ntiles; c0 += 1024) {
+        int i = c0 + threadIdx.x;
+        long long v = i < ntiles ? tiles[i].size : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            long long a = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (i < ntiles) tiles[i].base = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += sh[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && carry > cap) {
+        if (atomicCAS(&fl->err, 0, ERR_OVERFLOW) == 0) {
+            fl->need = carry;
+            fl->step = step;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stencil enumeration (Sec. II.C): base points row by row; refined children
+// replace their parent, level by level (Eqs. IIC10-11).  leaf(cx, cy, dC, dx,
+// dy) gets the exact velocity, velocity volume and landing displacement;
+// parent_end(dx, dy) is called after the last leaf of each base point.
+// ---------------------------------------------------------------------------
+template <int D, typename Leaf, typename End>
+__device__ inline void for_each_point(double ux, double uy, int R, int Nr, Leaf &&leaf, End &&parent_end) {
+    const double rr = R + 0.5;
+    int ubx = (int)floor(ux + 0.5), uby = D == 2 ? (int)floor(uy + 0.5) : 0;
+    int ylo = D == 2 ? uby - R - 1 : 0, yhi = D == 2 ? uby + R + 1 : 0;
+    for (int cy = ylo; cy <= yhi; cy++) {
+        for (int cx = ubx - R - 1; cx <= ubx + R + 1; cx++) {
+            double fx = (double)cx, fy = (double)cy;
+            bool in = D == 2 ? in_disk2(fx, fy, ux, uy, rr) : in_disk1(fx, ux, rr);
+            if (!in) continue;
+            double d0 = D == 2 ? dist2(fx, fy, ux, uy) : fabs(fx - ux);
+            if (Nr == 0 || d0 > 1.5) {
+                leaf(fx, fy, 1.0, cx, cy);
+            } else {
+                constexpr int NC = D == 2 ? 4 : 2;
+                const double v1 = D == 2 ? 0.25 : 0.5;
+                for (int k1 = 0; k1 < NC; k1++) {
+                    double c1x = fx + ((k1 & 1) ? 0.25 : -0.25);
+                    double c1y = D == 2 ? fy + ((k1 & 2) ? 0.25 : -0.25) : 0.0;
+                    double d1 = D == 2 ? dist2(c1x, c1y, ux, uy) : fabs(c1x - ux);
+                    if (Nr < 2 || d1 > 0.75) {
+                        leaf(c1x, c1y, v1, cx, cy);
+                        continue;
+                    }
+                    for (int k2 = 0; k2 < NC; k2++) {
+                        double c2x = c1x + ((k2 & 1) ? 0.125 : -0.125);
+                        double c2y = D == 2 ? c1y + ((k2 & 2) ? 0.125 : -0.125) : 0.0;
+                        double d2 = D == 2 ? dist2(c2x, c2y, ux, uy) : fabs(c2x - ux);
+                        if (Nr < 3 || d2 > 0.375) {
+                            leaf(c2x, c2y, v1 * v1, cx, cy);
+                            continue;
+                        }
+                        for (int k3 = 0; k3 < NC; k3++) {
+                            double c3x = c2x + ((k3 & 1) ? 0.0625 : -0.0625);
+                            double c3y = D == 2 ? c2y + ((k3 & 2) ? 0.0625 : -0.0625) : 0.0;
+                            leaf(c3x, c3y, v1 * v1 * v1, cx, cy);
+                        }
+                    }
+                }
+            }
+            parent_end(cx, cy);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dense Cholesky solve of an SPD system assembled from monomial sums
+// ---------------------------------------------------------------------------
+template <int D, int N>
+__device__ inline bool hess_solve(const double *S, const double *r, double *x) {
+    double L[N * (N + 1) / 2];
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+#pragma unroll
+        for (int j = 0; j <= i; j++) {
+            double s = S[hess_idx<D>(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; k++) s -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+            if (i == j) {
+                if (!(s > 0.0) || !isfinite(s)) return false;
+                L[i * (i + 1) / 2 + i] = sqrt(s);
+            } else {
+                L[i * (i + 1) / 2 + j] = s / L[j * (j + 1) / 2 + j];
+            }
+        }
+    }
+    double y[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        double s = r[i];
+#pragma unroll
+        for (int k = 0; k < i; k++) s -= L[i * (i + 1) / 2 + k] * y[k];
+        y[i] = s / L[i * (i + 1) / 2 + i];
+    }
+#pragma unroll
+    for (int i = N - 1; i >= 0; i--) {
+        double s = y[i];
+#pragma unroll
+        for (int k = i + 1; k < N; k++) s -= L[k * (k + 1) / 2 + i] * x[k];
+        x[i] = s / L[i * (i + 1) / 2 + i];
+    }
+    return true;
+}
+
+// Newton state of one species (fluon or phonon), Sec. II.D.  The step is
+// a damped Newton method on the convex dual Phi(l) = sum f + l.m' (Armijo
+// backtracking while the Newton decrement exceeds 1e-8).
+template <int NB> struct Species {
+    double lam[NB];   // accepted multipliers
+    double del[NB];   // current Newton direction
+    double t, dec, phi;
+    int phase;        // 0: first evaluation, 1: iterating, 2: polished
+    int nit, ls;
+};
+
+// After a pass evaluated at lam + t*del: accept / backtrack / step / polish.
+// Returns 0 to continue, 1 when polished, negative LELBM code on failure.
+template <int D, int NB, int NM>
+__device__ inline int species_update(Species<NB> &sp, const double *S, const double *tg, double RT, double tol,
+                                     int maxit) {
+    double lt[NB], r[NB];
+    double phit = S[0];
+    bool fin = isfinite(S[0]);
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        lt[j] = sp.lam[j] + sp.t * sp.del[j];
+        r[j] = S[j] - tg[j];
+        phit += lt[j] * tg[j];
+        fin = fin && isfinite(r[j]);
+    }
+    fin = fin && isfinite(phit);
+    if (sp.phase == 0) {
+        if (!fin) return LELBM_EEPR;
+        sp.phase = 1;
+    } else {
+        if (!(fin && (sp.dec <= 1e-8 || phit <= sp.phi - 1e-4 * sp.t * sp.dec))) {
+            sp.t *= 0.5;
+            if (++sp.ls > 30) return LELBM_EEPR;
+            return 0;
+        }
+        sp.nit++;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; j++) sp.lam[j] = lt[j];
+    sp.phi = phit;
+    double res = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        double v = fabs(r[j]) / pow(RT, 0.5 * order_of<D>(j));
+        res = v > res ? v : res;
+    }
+    double dl[NB];
+    if (res <= tol) {
+        if (!hess_solve<D, NB>(S, r, dl)) return LELBM_EEPR;
+#pragma unroll
+        for (int j = 0; j < NB; j++) { sp.lam[j] += dl[j]; sp.del[j] = 0.0; }
+        sp.t = 0.0;
+        sp.nit++;
+        sp.phase = 2;
+        return 1;
+    }
+    if (sp.nit >= maxit) return LELBM_EEPR;
+    if (!hess_solve<D, NB>(S, r, dl)) return LELBM_EEPR;
+    double dec = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; j++) { sp.del[j] = dl[j]; dec += r[j] * dl[j]; }
+    sp.dec = dec;
+    sp.t = 1.0;
+    sp.ls = 0;
+    return 0;
+}
+
+// monomials of (x, y) up to total degree NMT (numbering of mono_idx)
+template <int D, int NMT>
+__device__ inline void monomials(double x, double y, double *m) {
+    if (D == 1) {
+        m[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k < NMT; k++) m[k] = m[k - 1] * x;
+    } else {
+        double px[7], py[7];
+        px[0] = 1.0; py[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k < 7; k++) { px[k] = px[k - 1] * x; py[k] = py[k - 1] * y; }
+#pragma unroll
+        for (int k = 0; k < NMT; k++) m[k] = px[mono_a(k)] * py[mono_b(k)];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-cell collision + reconstruction (FP64 path)
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buffers b, int step) {
+    using BS = Basis<D>;
+    constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
+    __shared__ int s_err;
+    if (threadIdx.x == 0) s_err = b.flags->err;
+    __syncthreads();
+    if (s_err) return;
+    int t = blockIdx.x;
+    int tx0 = (t % g.ntx) * g.tx, ty0 = (t / g.ntx) * g.ty;
+    int l = threadIdx.x;
+    int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
+    bool valid = px < g.sxn && py < g.syn;
+    long long s = (long long)py * g.sxn + px;
+    int rn = valid ? b.desc_rn[s] : -1;
+    int my_it_f = 0, my_it_g = 0, my_q = 0, my_lim = 0;
+    double my_kn = 0.0, my_colat = 0.0, my_rt = 1e300;
+    bool active = rn >= 0;
+    if (active) {
+        const TileInfo ti = b.tiles[t];
+        double rho = b.desc_rho[s], ux = b.desc_u[s], uy = b.desc_u[g.ns + s], RT = b.desc_rt[s];
+        int R = rn & 0xffff, Nr = rn >> 16;
+        double K = ph.K;
+        // ---- collision: Eqs. (IIB9-IIB18) with the limiter of App. D
+        double mf[NF], mg[NG];
+        {
+            double P[2][2] = {{0, 0}, {0, 0}}, Q[2] = {0, 0}, h[2] = {0, 0}, g0;
+            double u[2] = {ux, uy};
+            if (D == 1) {
+                double Mxx = (double)mom[2 * g.ns + s], MD = (double)mom[3 * g.ns + s];
+                double G0 = (double)mom[4 * g.ns + s], Gx = (double)mom[5 * g.ns + s];
+                P[0][0] = Mxx - rho * (ux * ux + RT);
+                Q[0] = MD - 2.0 * (ux * P[0][0]) - ux * P[0][0] - rho * (ux * ux + 3.0 * RT) * ux;
+                g0 = G0 - rho * K * RT;
+                h[0] = Gx - ux * G0;
+            } else {
+                double Mxx = (double)mom[3 * g.ns + s], Mxy = (double)mom[4 * g.ns + s];
+                double Myy = (double)mom[5 * g.ns + s];
+                double MD[2] = {(double)mom[6 * g.ns + s], (double)mom[7 * g.ns + s]};
+                double G0 = (double)mom[8 * g.ns + s];
+                double Gv[2] = {(double)mom[9 * g.ns + s], (double)mom[10 * g.ns + s]};
+                double uu = ux * ux + uy * uy;
+                P[0][0] = Mxx - rho * (ux * ux + RT);
+                P[0][1] = P[1][0] = Mxy - rho * (ux * uy);
+                P[1][1] = Myy - rho * (uy * uy + RT);
+                double trP = P[0][0] + P[1][1];
+#pragma unroll
+                for (int gg = 0; gg < 2; gg++) {
+                    double sm = u[0] * P[0][gg] + u[1] * P[1][gg];
+                    Q[gg] = MD[gg] - 2.0 * sm - u[gg] * trP - rho * (uu + 4.0 * RT) * u[gg];
+                }
+                g0 = G0 - rho * K * RT;
+#pragma unroll
+                for (int gg = 0; gg < 2; gg++) h[gg] = Gv[gg] - u[gg] * G0;
+            }
+            double sP = 0.0, sQ = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; a++) {
+#pragma unroll
+                for (int bb = 0; bb < D; bb++) sP += fabs(P[a][bb]);
+                sQ += fabs(Q[a]) + fabs(h[a]);
+            }
+            double knA = (sP + fabs(g0)) / (rho * (D + K) * RT);
+            double knB = sQ / (rho * (D + K + 2.0) * pow(RT, 1.5));
+            double kn = knA > knB ? knA : knB;
+            double of = ph.omega_f, ob = ph.omega_b, oh = ph.omega_h;
+            if (ph.kn_limiter && kn >= ph.kn_lo_lin) {
+                if (kn > ph.kn_hi_lin) {
+                    of = ob = oh = ph.omega_H;
+                } else {
+                    double k = log10(kn), span = ph.kn_hi - ph.kn_lo;
+                    of = (ph.omega_H - ph.omega_f) / span * (k - ph.kn_lo) + ph.omega_f;
+                    ob = (ph.omega_H - ph.omega_b) / span * (k - ph.kn_lo) + ph.omega_b;
+                    oh = (ph.omega_H - ph.omega_h) / span * (k - ph.kn_lo) + ph.omega_h;
+                }
+                my_lim = (of != ph.omega_f) || (ob != ph.omega_b) || (oh != ph.omega_h);
+            }
+            my_kn = kn;
+            double bulk = -g0 / D;
+            double rKT = rho * K * RT;
+            if (D == 1) {
+                double shear = P[0][0] - bulk;
+                mf[0] = 1.0; mf[1] = 0.0;
+                mf[2] = RT + ((1.0 - of) * shear + (1.0 - ob) * bulk) / rho;
+                mf[3] = (1.0 - oh) * Q[0] / rho;
+                mg[0] = 1.0 + (1.0 - ob) * g0 / rKT;
+                mg[1] = (1.0 - oh) * h[0] / rKT;
+                mg[2] = RT;
+            } else {
+                double shxx = P[0][0] - bulk, shxy = P[0][1], shyy = P[1][1] - bulk;
+                mf[0] = 1.0; mf[1] = 0.0; mf[2] = 0.0;
+                mf[3] = RT + ((1.0 - of) * shxx + (1.0 - ob) * bulk) / rho;
+                mf[4] = ((1.0 - of) * shxy) / rho;
+                mf[5] = RT + ((1.0 - of) * shyy + (1.0 - ob) * bulk) / rho;
+                mf[6] = (1.0 - oh) * (0.75 * Q[0]) / rho;
+                mf[7] = (1.0 - oh) * (0.25 * Q[1]) / rho;
+                mf[8] = (1.0 - oh) * (0.25 * Q[0]) / rho;
+                mf[9] = (1.0 - oh) * (0.75 * Q[1]) / rho;
+                mg[0] = 1.0 + (1.0 - ob) * g0 / rKT;
+                mg[1] = (1.0 - oh) * h[0] / rKT;
+                mg[2] = (1.0 - oh) * h[1] / rKT;
+                mg[3] = RT; mg[4] = 0.0; mg[5] = RT;
+            }
+        }
+        // ---- initial guess, Eq. (IID13)
+        Species<NF> sf;
+        Species<NG> sg;
+#pragma unroll
+        for (int j = 0; j < NF; j++) { sf.lam[j] = 0.0; sf.del[j] = 0.0; }
+#pragma unroll
+        for (int j = 0; j < NG; j++) { sg.lam[j] = 0.0; sg.del[j] = 0.0; }
+        {
+            double l0 = -1.0 + 0.5 * D * log(2.0 * M_PI * RT), l2 = 1.0 / (2.0 * RT);
+            sf.lam[0] = l0; sg.lam[0] = l0;
+            if (D == 1) { sf.lam[2] = l2; sg.lam[2] = l2; }
+            else { sf.lam[3] = l2; sf.lam[5] = l2; sg.lam[3] = l2; sg.lam[5] = l2; }
+        }
+        sf.t = sg.t = 0.0; sf.dec = sg.dec = 0.0; sf.phi = sg.phi = 0.0;
+        sf.phase = sg.phase = 0; sf.nit = sg.nit = 0; sf.ls = sg.ls = 0;
+        int fail = 0;
+        // ---- Newton passes
+        while (!fail && (sf.phase < 2 || sg.phase < 2)) {
+            double Sf[NMF], Sg[NMG], lf[NF], lg[NG];
+#pragma unroll
+            for (int k = 0; k < NMF; k++) Sf[k] = 0.0;
+#pragma unroll
+            for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NF; j++) lf[j] = sf.lam[j] + sf.t * sf.del[j];
+#pragma unroll
+            for (int j = 0; j < NG; j++) lg[j] = sg.lam[j] + sg.t * sg.del[j];
+            const bool df = sf.phase < 2, dg = sg.phase < 2;
+            for_each_point<D>(
+                ux, uy, R, Nr,
+                [&](double cx, double cy, double dC, int, int) {
+                    double m[NMF];
+                    monomials<D, NMF>(cx - ux, D == 2 ? cy - uy : 0.0, m);
+                    if (df) {
+                        double e = 0.0;
+#pragma unroll
+                        for (int j = 0; j < NF; j++) e += lf[j] * m[j];
+                        double f = dC * exp(-(1.0 + e));
+#pragma unroll
+                        for (int k = 0; k < NMF; k++) Sf[k] += f * m[k];
+                    }
+                    if (dg) {
+                        double e = 0.0;
+#pragma unroll
+                        for (int j = 0; j < NG; j++) e += lg[j] * m[j];
+                        double gv = dC * exp(-(1.0 + e));
+#pragma unroll
+                        for (int k = 0; k < NMG; k++) Sg[k] += gv * m[k];
+                    }
+                },
+                [&](int, int) {});
+            if (df) {
+                int r = species_update<D, NF, NMF>(sf, Sf, mf, RT, ph.tol, ph.maxit);
+                if (r < 0) fail = r;
+            }
+            if (dg && !fail) {
+                int r = species_update<D, NG, NMG>(sg, Sg, mg, RT, ph.tol, ph.maxit);
+                if (r < 0) fail = r;
+            }
+        }
+        if (fail) {
+            flag_fail(b.flags, fail, step, s);
+        } else {
+            // ---- final pass: moment fractions rho f', rho K RT g' (Eq. IIE3a)
+            const double wsf = rho, wsg = rho * K * RT;
+            const long long plane = (long long)ti.wx * ti.wy * TILE_N;
+            double *P = (double *)b.scratch + ti.base;
+            double acc[NM];
+#pragma unroll
+            for (int k = 0; k < NM; k++) acc[k] = 0.0;
+            int q = 0;
+            for_each_point<D>(
+                ux, uy, R, Nr,
+                [&](double cx, double cy, double dC, int dx, int dy) {
+                    double m[NF];
+                    monomials<D, NF>(cx - ux, D == 2 ? cy - uy : 0.0, m);
+                    double ef = 0.0, eg = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NF; j++) ef += sf.lam[j] * m[j];
+#pragma unroll
+                    for (int j = 0; j < NG; j++) eg += sg.lam[j] * m[j];
+                    double wf = wsf * (dC * exp(-(1.0 + ef)));
+                    double wg = wsg * (dC * exp(-(1.0 + eg)));
+                    q++;
+                    if (ti.fmt == 0) {
+                        long long slot = (long long)(dy - ti.oy) * ti.wx + (dx - ti.ox);
+                        P[slot * TILE_N + l] = wf;
+                        P[plane + slot * TILE_N + l] = wg;
+                    } else {
+                        if (D == 1) {
+                            acc[0] += wf; acc[1] += cx * wf; acc[2] += cx * cx * wf; acc[3] += cx * cx * cx * wf;
+                            acc[4] += wg; acc[5] += cx * wg;
+                        } else {
+                            double cc = cx * cx + cy * cy;
+                            acc[0] += wf; acc[1] += cx * wf; acc[2] += cy * wf;
+                            acc[3] += cx * cx * wf; acc[4] += cx * cy * wf; acc[5] += cy * cy * wf;
+                            acc[6] += cc * cx * wf; acc[7] += cc * cy * wf;
+                            acc[8] += wg; acc[9] += cx * wg; acc[10] += cy * wg;
+                        }
+                    }
+                },
+                [&](int dx, int dy) {
+                    if (ti.fmt == 1) {
+                        long long slot = (long long)(dy - ti.oy) * ti.wx + (dx - ti.ox);
+#pragma unroll
+                        for (int k = 0; k < NM; k++) {
+                            P[k * plane + slot * TILE_N + l] = acc[k];
+                            acc[k] = 0.0;
+                        }
+                    }
+                });
+            my_it_f = sf.nit;
+            my_it_g = sg.nit;
+            my_q = q;
+            my_rt = RT;
+            my_colat = (D == 2 ? sqrt(ux * ux + uy * uy) : fabs(ux)) + R;
+        }
+    }
+    // ---- statistics (one atomic per wavefront)
+    unsigned long long a_itf = my_it_f, a_itg = my_it_g, a_q = my_q, a_lim = my_lim, a_cells = active ? 1 : 0;
+    int m_itf = my_it_f, m_itg = my_it_g, m_q = my_q, n_q = active ? my_q : 1 << 30;
+    double m_kn = my_kn, m_colat = my_colat, n_rt = my_rt;
+    for (int off = 32; off > 0; off >>= 1) {
+        a_itf += __shfl_xor(a_itf, off);
+        a_itg += __shfl_xor(a_itg, off);
+        a_q += __shfl_xor(a_q, off);
+        a_lim += __shfl_xor(a_lim, off);
+        a_cells += __shfl_xor(a_cells, off);
+        m_itf = max(m_itf, __shfl_xor(m_itf, off));
+        m_itg = max(m_itg, __shfl_xor(m_itg, off));
+        m_q = max(m_q, __shfl_xor(m_q, off));
+        n_q = min(n_q, __shfl_xor(n_q, off));
+        m_kn = fmax(m_kn, __shfl_xor(m_kn, off));
+        m_colat = fmax(m_colat, __shfl_xor(m_colat, off));
+        n_rt = fmin(n_rt, __shfl_xor(n_rt, off));
+    }
+    if ((threadIdx.x & 63) == 0 && a_cells > 0) {
+        DevStats *st = b.stats;
+        atomicAdd(&st->it_sum_f, a_itf);
+        atomicAdd(&st->it_sum_g, a_itg);
+        atomicAdd(&st->q_sum, a_q);
+        atomicAdd(&st->limited, a_lim);
+        atomicAdd(&st->cells, a_cells);
+        atomicMax(&st->it_max_f, m_itf);
+        atomicMax(&st->it_max_g, m_itg);
+        atomicMax(&st->q_max, m_q);
+        atomicMin(&st->q_min, n_q);
+        atomic_max_pos(&st->kn_max_bits, m_kn);
+        atomic_max_pos(&st->colat_max_bits, m_colat);
+        atomic_min_pos(&st->rt_min_bits, n_rt);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// moment-streaming gather, Eq. (IIE3b)
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
+    constexpr int NM = Basis<D>::NMOM;
+    __shared__ int s_err;
+    if (threadIdx.x == 0) s_err = b.flags->err;
+    __syncthreads();
+    if (s_err) return;
+    int t = blockIdx.x;
+    int x = (t % g.dtx) * g.tx + threadIdx.x % g.tx;
+    int y = (t / g.dtx) * g.ty + threadIdx.x / g.tx;
+    if (x >= g.nx || y >= g.ny) return;
+    const DWin w = b.dwin[t];
+    double acc[NM];
+#pragma unroll
+    for (int k = 0; k < NM; k++) acc[k] = 0.0;
+    const bool perx = g.bc[0] == LELBM_BC_PERIODIC, pery = D == 2 && g.bc[2] == LELBM_BC_PERIODIC;
+    for (int dy = w.hiy; dy >= w.loy; dy--) {
+        int sy = y - dy;
+        int fy = 1;   // sign of the y velocity after reflection
+        if (D == 2) {
+            if (pery) { sy %= g.ny; if (sy < 0) sy += g.ny; }
+            if (sy < 0 && g.bc[2] == LELBM_BC_SLIPWALL) { sy = -1 - sy; fy = -1; }
+            else if (sy >= g.ny && g.bc[3] == LELBM_BC_SLIPWALL) { sy = 2 * g.ny - 1 - sy; fy = -1; }
+            if (sy < -g.wb || sy >= g.ny + g.wt) continue;
+        }
+        for (int dx = w.hix; dx >= w.lox; dx--) {
+            int sx = x - dx;
+            int fx = 1;
+            if (perx) { sx %= g.nx; if (sx < 0) sx += g.nx; }
+            if (sx < 0 && g.bc[0] == LELBM_BC_SLIPWALL) { sx = -1 - sx; fx = -1; }
+            else if (sx >= g.nx && g.bc[1] == LELBM_BC_SLIPWALL) { sx = 2 * g.nx - 1 - sx; fx = -1; }
+            if (sx < -g.wl || sx >= g.nx + g.wr) continue;
+            int px = sx + g.wl, py = D == 2 ? sy + g.wb : 0;
+            long long s = (long long)py * g.sxn + px;
+            int rn = b.desc_rn[s];
+            if (rn < 0) continue;
+            // displacement in the source's own frame (undo the mirror)
+            int rdx = fx * dx, rdy = D == 2 ? fy * dy : 0;
+            double ux = b.desc_u[s];
+            double rr = (rn & 0xffff) + 0.5;
+            bool in;
+            if (D == 2) in = in_disk2((double)rdx, (double)rdy, ux, b.desc_u[g.ns + s], rr);
+            else in = in_disk1((double)rdx, ux, rr);
+            if (!in) continue;
+            int st = (px / g.tx) + (py / g.ty) * g.ntx;
+            int loc = (px % g.tx) + (py % g.ty) * g.tx;
+            const TileInfo ti = b.tiles[st];
+            long long slot = (long long)(rdy - ti.oy) * ti.wx + (rdx - ti.ox);
+            const long long plane = (long long)ti.wx * ti.wy * TILE_N;
+            const double *P = (const double *)b.scratch + ti.base + slot * TILE_N + loc;
+            if (ti.fmt == 0) {
+                double wf = P[0], wg = P[plane];
+                double cx = (double)dx, cy = (double)dy;   // velocity after reflection
+                if (D == 1) {
+                    acc[0] += wf; acc[1] += cx * wf; acc[2] += cx * cx * wf; acc[3] += cx * cx * cx * wf;
+                    acc[4] += wg; acc[5] += cx * wg;
+                } else {
+                    double cc = cx * cx + cy * cy;
+                    acc[0] += wf; acc[1] += cx * wf; acc[2] += cy * wf;
+                    acc[3] += cx * cx * wf; acc[4] += cx * cy * wf; acc[5] += cy * cy * wf;
+                    acc[6] += cc * cx * wf; acc[7] += cc * cy * wf;
+                    acc[8] += wg; acc[9] += cx * wg; acc[10] += cy * wg;
+                }
+            } else {
+                // pre-summed moments of refined children; reflect odd components
+                if (D == 1) {
+                    double sx1 = fx;
+                    acc[0] += P[0]; acc[1] += sx1 * P[plane]; acc[2] += P[2 * plane];
+                    acc[3] += sx1 * P[3 * plane]; acc[4] += P[4 * plane]; acc[5] += sx1 * P[5 * plane];
+                } else {
+                    double sx1 = fx, sy1 = fy;
+                    acc[0] += P[0]; acc[1] += sx1 * P[plane]; acc[2] += sy1 * P[2 * plane];
+                    acc[3] += P[3 * plane]; acc[4] += sx1 * sy1 * P[4 * plane]; acc[5] += P[5 * plane];
+                    acc[6] += sx1 * P[6 * plane]; acc[7] += sy1 * P[7 * plane];
+                    acc[8] += P[8 * plane]; acc[9] += sx1 * P[9 * plane]; acc[10] += sy1 * P[10 * plane];
+                }
+            }
+        }
+    }
+    long long o = (long long)(y + g.wb) * g.sxn + (x + g.wl);
+#pragma unroll
+    for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = (T)acc[k];
+}
+
+// ---------------------------------------------------------------------------
+// resets and conserved totals
+// ---------------------------------------------------------------------------
+__global__ void k_reset_windows(int n, DWin *w) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        w[i].lox = 1 << 29; w[i].loy = 1 << 29; w[i].hix = -(1 << 29); w[i].hiy = -(1 << 29);
+    }
+}
+
+__global__ void k_reset_stats(DevStats *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->it_sum_f = st->it_sum_g = st->q_sum = st->limited = st->cells = st->fallbacks = 0;
+        st->it_max_f = st->it_max_g = st->q_max = 0;
+        st->q_min = 1 << 30;
+        st->rt_min_bits = (unsigned long long)__double_as_longlong(1e300);
+        st->kn_max_bits = 0;
+        st->colat_max_bits = 0;
+    }
+}
+
+// Totals of mass, momentum and energy over the interior, in a fixed order:
+// block partial sums, then a one-block final sum.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_sums(Geom g, const T *mom, double *partial) {
+    __shared__ double sh[4][256];
+    long long n = (long long)g.nx * g.ny;
+    double a[4] = {0, 0, 0, 0};
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        int x = (int)(i % g.nx), y = (int)(i / g.nx);
+        long long s = (long long)(y + g.wb) * g.sxn + (x + g.wl);
+        a[0] += (double)mom[s];
+        a[1] += (double)mom[g.ns + s];
+        if (D == 2) {
+            a[2] += (double)mom[2 * g.ns + s];
+            a[3] += (double)mom[3 * g.ns + s] + (double)mom[5 * g.ns + s] + (double)mom[8 * g.ns + s];
+        } else {
+            a[3] += (double)mom[2 * g.ns + s] + (double)mom[4 * g.ns + s];
+        }
+    }
+    for (int k = 0; k < 4; k++) sh[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int k = 0; k < 4; k++) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; k++) partial[blockIdx.x * 4 + k] = sh[k][0];
+}
+
+__global__ void k_sums_final(int nb, double *partial) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double a[4] = {0, 0, 0, 0};
+        for (int i = 0; i < nb; i++)
+            for (int k = 0; k < 4; k++) a[k] += partial[i * 4 + k];
+        for (int k = 0; k < 4; k++) partial[nb * 4 + k] = a[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int num_sum_blocks(const Geom &g) {
+    long long n = (long long)g.nx * g.ny;
+    long long nb = (n + 255) / 256;
+    return (int)(nb < 1024 ? nb : 1024);
+}
+
+#define DISPATCH(mixed, dim, KERNEL, ...)                                        \
+    do {                                                                         \
+        if (mixed) {                                                             \
+            if (dim == 1) hipLaunchKernelGGL((KERNEL<float, 1>), __VA_ARGS__);  \
+            else hipLaunchKernelGGL((KERNEL<float, 2>), __VA_ARGS__);           \
+        } else {                                                                 \
+            if (dim == 1) hipLaunchKernelGGL((KERNEL<double, 1>), __VA_ARGS__); \
+            else hipLaunchKernelGGL((KERNEL<double, 2>), __VA_ARGS__);          \
+        }                                                                        \
+    } while (0)
+
+hipError_t launch_fill_pads(const Geom &g, const Phys &ph, int mixed, void *mom, Flags *fl, hipStream_t s) {
+    if (g.wl + g.wr + g.wb + g.wt == 0) return hipSuccess;
+    unsigned nb = (unsigned)((g.ns + 255) / 256);
+    if (mixed) {
+        if (g.dim == 1) hipLaunchKernelGGL((k_fill_pads<float, 1>), dim3(nb), dim3(256), 0, s, g, ph, (float *)mom, fl);
+        else hipLaunchKernelGGL((k_fill_pads<float, 2>), dim3(nb), dim3(256), 0, s, g, ph, (float *)mom, fl);
+    } else {
+        if (g.dim == 1) hipLaunchKernelGGL((k_fill_pads<double, 1>), dim3(nb), dim3(256), 0, s, g, ph, (double *)mom, fl);
+        else hipLaunchKernelGGL((k_fill_pads<double, 2>), dim3(nb), dim3(256), 0, s, g, ph, (double *)mom, fl);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_step(const Geom &g, Buffers &b, hipStream_t s) {
+    int n = g.dtx * g.dty;
+    hipLaunchKernelGGL(k_reset_windows, dim3((n + 255) / 256), dim3(256), 0, s, n, b.dwin);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_stats(Buffers &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, s, b.stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
+                          hipStream_t s) {
+    unsigned nt = (unsigned)(g.ntx * g.nty);
+    if (mixed) {
+        if (g.dim == 1) hipLaunchKernelGGL((k_prepare<float, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const float *)mom, b, step);
+        else hipLaunchKernelGGL((k_prepare<float, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const float *)mom, b, step);
+    } else {
+        if (g.dim == 1) hipLaunchKernelGGL((k_prepare<double, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
+        else hipLaunchKernelGGL((k_prepare<double, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const Geom &g, Buffers &b, int step, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, g.ntx * g.nty, b.tiles, b.flags, b.scratch_cap, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
+                      hipStream_t s) {
+    unsigned nt = (unsigned)(g.ntx * g.nty);
+    if (mixed) return hipErrorInvalidValue;
+    if (g.dim == 1) hipLaunchKernelGGL((k_epr<double, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
+    else hipLaunchKernelGGL((k_epr<double, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, hipStream_t s) {
+    unsigned nt = (unsigned)(g.dtx * g.dty);
+    if (mixed) return hipErrorInvalidValue;
+    if (g.dim == 1) hipLaunchKernelGGL((k_gather<double, 1>), dim3(nt), dim3(256), 0, s, g, (double *)mom_out, b);
+    else hipLaunchKernelGGL((k_gather<double, 2>), dim3(nt), dim3(256), 0, s, g, (double *)mom_out, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_sums(const Geom &g, int mixed, const void *mom, Buffers &b, hipStream_t s) {
+    int nb = num_sum_blocks(g);
+    if (mixed) {
+        if (g.dim == 1) hipLaunchKernelGGL((k_sums<float, 1>), dim3(nb), dim3(256), 0, s, g, (const float *)mom, b.partial);
+        else hipLaunchKernelGGL((k_sums<float, 2>), dim3(nb), dim3(256), 0, s, g, (const float *)mom, b.partial);
+    } else {
+        if (g.dim == 1) hipLaunchKernelGGL((k_sums<double, 1>), dim3(nb), dim3(256), 0, s, g, (const double *)mom, b.partial);
+        else hipLaunchKernelGGL((k_sums<double, 2>), dim3(nb), dim3(256), 0, s, g, (const double *)mom, b.partial);
+    }
+    hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(64), 0, s, nb, b.partial);
+    return hipGetLastError();
+}
+
+}  // namespace lelbm
