@@ -104,6 +104,9 @@ typedef struct {
     double rt_min, kn_max, colat_max; /* colat: Eq. (IIC7), |u| + R */
     double sum[4];
     long cells;                       /* cells processed (interior + pads) */
+    long point_passes;                /* sum over cells of q x reconstruction passes
+                                         (Newton evaluations + the final population pass) */
+    long arrivals;                    /* stencil points deposited into interior cells */
 } lelbm_stats;
 
 /* Number of stored moments per cell: 6 (1D) or 11 (2D); -1 for other dim. */

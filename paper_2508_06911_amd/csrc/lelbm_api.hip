@@ -35,6 +35,11 @@ struct lelbm_ctx {
     hipEvent_t ev[2];
     double kms[6];
     long klaunch[6];
+    // timing mode: event pairs recorded around each kernel, read after the
+    // stream synchronisation at the end of lelbm_step
+    std::vector<hipEvent_t> evpool;
+    std::vector<int> evkind;
+    size_t evused;
     long long persistent_bytes;
 };
 
@@ -123,6 +128,7 @@ static void free_ctx(lelbm_ctx *c) {
         if (q) (void)hipFree(q);
     if (c->ev[0]) (void)hipEventDestroy(c->ev[0]);
     if (c->ev[1]) (void)hipEventDestroy(c->ev[1]);
+    for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -163,6 +169,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     c->last_fail_node = -1;
     c->last_fail_step = -1;
     c->timing = 0;
+    c->evused = 0;
     for (int k = 0; k < 6; k++) { c->kms[k] = 0; c->klaunch[k] = 0; }
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return LELBM_EDEVICE; }
     Geom &g = c->g;
@@ -296,16 +303,34 @@ extern "C" int lelbm_create_device(const lelbm_params *p, const void *dev_moment
 }
 
 static int timed(lelbm_ctx *c, int k, hipError_t (*fn)(lelbm_ctx *, void *), void *arg) {
-    if (c->timing) HIPCHECK(hipEventRecord(c->ev[0], c->stream));
-    HIPCHECK(fn(c, arg));
-    if (c->timing) {
-        HIPCHECK(hipEventRecord(c->ev[1], c->stream));
-        HIPCHECK(hipEventSynchronize(c->ev[1]));
-        float ms = 0;
-        HIPCHECK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-        c->kms[k] += ms;
-        c->klaunch[k]++;
+    if (!c->timing) {
+        HIPCHECK(fn(c, arg));
+        return LELBM_OK;
     }
+    size_t i = c->evused;
+    while (c->evpool.size() < 2 * (i + 1)) {
+        hipEvent_t e;
+        HIPCHECK(hipEventCreate(&e));
+        c->evpool.push_back(e);
+    }
+    if (c->evkind.size() < i + 1) c->evkind.resize(i + 1);
+    HIPCHECK(hipEventRecord(c->evpool[2 * i], c->stream));
+    HIPCHECK(fn(c, arg));
+    HIPCHECK(hipEventRecord(c->evpool[2 * i + 1], c->stream));
+    c->evkind[i] = k;
+    c->evused = i + 1;
+    return LELBM_OK;
+}
+
+// Accumulates the recorded kernel durations (after a stream synchronisation).
+static int collect_times(lelbm_ctx *c) {
+    for (size_t i = 0; i < c->evused; i++) {
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, c->evpool[2 * i], c->evpool[2 * i + 1]));
+        c->kms[c->evkind[i]] += ms;
+        c->klaunch[c->evkind[i]]++;
+    }
+    c->evused = 0;
     return LELBM_OK;
 }
 
@@ -351,6 +376,7 @@ extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
         Flags f;
         HIPCHECK(hipMemcpyAsync(&f, c->b.flags, sizeof(Flags), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
+        if (c->timing && (r = collect_times(c)) != LELBM_OK) return r;
         if (f.err == 0) break;
         // every kernel after the failing one returned early, so the state at
         // the start of step f.step is intact
@@ -389,6 +415,8 @@ extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
         memcpy(&v, &ds.colat_max_bits, 8); st->colat_max = v;
         for (int k = 0; k < 4; k++) st->sum[k] = sums[k];
         st->cells = (long)ds.cells;
+        st->point_passes = (long)ds.qpass_sum;
+        st->arrivals = (long)ds.arrivals;
     }
     return LELBM_OK;
 }

@@ -50,7 +50,7 @@ struct Flags {
 };
 
 struct DevStats {
-    unsigned long long it_sum_f, it_sum_g, q_sum, limited, cells, fallbacks;
+    unsigned long long it_sum_f, it_sum_g, q_sum, limited, cells, fallbacks, qpass_sum, arrivals;
     int it_max_f, it_max_g, q_max, q_min;
     unsigned long long rt_min_bits, kn_max_bits, colat_max_bits;
 };

@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buff
     bool valid = px < g.sxn && py < g.syn;
     long long s = (long long)py * g.sxn + px;
     int rn = valid ? b.desc_rn[s] : -1;
-    int my_it_f = 0, my_it_g = 0, my_q = 0, my_lim = 0;
+    int my_it_f = 0, my_it_g = 0, my_q = 0, my_lim = 0, my_pass = 0;
     double my_kn = 0.0, my_colat = 0.0, my_rt = 1e300;
     bool active = rn >= 0;
     if (active) {
@@ -625,6 +625,7 @@ __global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buff
         int fail = 0;
         // ---- Newton passes
         while (!fail && (sf.phase < 2 || sg.phase < 2)) {
+            my_pass++;
             double Sf[NMF], Sg[NMG], lf[NF], lg[NG];
 #pragma unroll
             for (int k = 0; k < NMF; k++) Sf[k] = 0.0;
@@ -718,6 +719,7 @@ __global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buff
                         }
                     }
                 });
+            my_pass++;
             my_it_f = sf.nit;
             my_it_g = sg.nit;
             my_q = q;
@@ -727,6 +729,7 @@ __global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buff
     }
     // ---- statistics (one atomic per wavefront)
     unsigned long long a_itf = my_it_f, a_itg = my_it_g, a_q = my_q, a_lim = my_lim, a_cells = active ? 1 : 0;
+    unsigned long long a_qp = (unsigned long long)my_q * my_pass;
     int m_itf = my_it_f, m_itg = my_it_g, m_q = my_q, n_q = active ? my_q : 1 << 30;
     double m_kn = my_kn, m_colat = my_colat, n_rt = my_rt;
     for (int off = 32; off > 0; off >>= 1) {
@@ -735,6 +738,7 @@ __global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buff
         a_q += __shfl_xor(a_q, off);
         a_lim += __shfl_xor(a_lim, off);
         a_cells += __shfl_xor(a_cells, off);
+        a_qp += __shfl_xor(a_qp, off);
         m_itf = max(m_itf, __shfl_xor(m_itf, off));
         m_itg = max(m_itg, __shfl_xor(m_itg, off));
         m_q = max(m_q, __shfl_xor(m_q, off));
@@ -750,6 +754,7 @@ __global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buff
         atomicAdd(&st->q_sum, a_q);
         atomicAdd(&st->limited, a_lim);
         atomicAdd(&st->cells, a_cells);
+        atomicAdd(&st->qpass_sum, a_qp);
         atomicMax(&st->it_max_f, m_itf);
         atomicMax(&st->it_max_g, m_itg);
         atomicMax(&st->q_max, m_q);
@@ -773,7 +778,8 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
     int t = blockIdx.x;
     int x = (t % g.dtx) * g.tx + threadIdx.x % g.tx;
     int y = (t / g.dtx) * g.ty + threadIdx.x / g.tx;
-    if (x >= g.nx || y >= g.ny) return;
+    unsigned long long hits = 0;
+    if (x < g.nx && y < g.ny) {
     const DWin w = b.dwin[t];
     double acc[NM];
 #pragma unroll
@@ -813,6 +819,7 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
             long long slot = (long long)(rdy - ti.oy) * ti.wx + (rdx - ti.ox);
             const long long plane = (long long)ti.wx * ti.wy * TILE_N;
             const double *P = (const double *)b.scratch + ti.base + slot * TILE_N + loc;
+            hits++;
             if (ti.fmt == 0) {
                 double wf = P[0], wg = P[plane];
                 double cx = (double)dx, cy = (double)dy;   // velocity after reflection
@@ -845,6 +852,9 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
     long long o = (long long)(y + g.wb) * g.sxn + (x + g.wl);
 #pragma unroll
     for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = (T)acc[k];
+    }
+    for (int off = 32; off > 0; off >>= 1) hits += __shfl_xor(hits, off);
+    if ((threadIdx.x & 63) == 0 && hits) atomicAdd(&b.stats->arrivals, hits);
 }
 
 // ---------------------------------------------------------------------------
@@ -860,6 +870,7 @@ __global__ void k_reset_windows(int n, DWin *w) {
 __global__ void k_reset_stats(DevStats *st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->it_sum_f = st->it_sum_g = st->q_sum = st->limited = st->cells = st->fallbacks = 0;
+        st->qpass_sum = st->arrivals = 0;
         st->it_max_f = st->it_max_g = st->q_max = 0;
         st->q_min = 1 << 30;
         st->rt_min_bits = (unsigned long long)__double_as_longlong(1e300);

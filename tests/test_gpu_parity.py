@@ -62,7 +62,7 @@ def test_refined_stencils_parity():
     b, sb = run_oracle(cfg, prim, 20)
     assert rel_linf(a, b) < TOL
     assert sa["q_max"] == sb["q_max"] and sa["q_min"] == sb["q_min"]
-    assert sa["q_max"] > 60    # refined points present
+    assert sa["q_max"] > 25    # R = 2 base disks hold at most 21 points; refined ones more
 
 
 def test_pads_and_slip_walls_parity():
