@@ -501,237 +501,123 @@ __device__ inline void monomials(double x, double y, double *m) {
 }
 
 // ---------------------------------------------------------------------------
-// per-cell collision + reconstruction (FP64 path)
+// per-cell collision: normalised post-collision central-moment targets of the
+// fluon (mf) and phonon (mg) reconstructions, Eqs. (IIB9-IIB18), with the
+// Knudsen limiter of App. D, Eqs. (D2-D3)
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buffers b, int step) {
-    using BS = Basis<D>;
-    constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
-    __shared__ int s_err;
-    if (threadIdx.x == 0) s_err = b.flags->err;
-    __syncthreads();
-    if (s_err) return;
-    int t = blockIdx.x;
-    int tx0 = (t % g.ntx) * g.tx, ty0 = (t / g.ntx) * g.ty;
-    int l = threadIdx.x;
-    int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
-    bool valid = px < g.sxn && py < g.syn;
-    long long s = (long long)py * g.sxn + px;
-    int rn = valid ? b.desc_rn[s] : -1;
-    int my_it_f = 0, my_it_g = 0, my_q = 0, my_lim = 0, my_pass = 0;
-    double my_kn = 0.0, my_colat = 0.0, my_rt = 1e300;
-    bool active = rn >= 0;
-    if (active) {
-        const TileInfo ti = b.tiles[t];
-        double rho = b.desc_rho[s], ux = b.desc_u[s], uy = b.desc_u[g.ns + s], RT = b.desc_rt[s];
-        int R = rn & 0xffff, Nr = rn >> 16;
-        double K = ph.K;
-        // ---- collision: Eqs. (IIB9-IIB18) with the limiter of App. D
-        double mf[NF], mg[NG];
-        {
-            double P[2][2] = {{0, 0}, {0, 0}}, Q[2] = {0, 0}, h[2] = {0, 0}, g0;
-            double u[2] = {ux, uy};
-            if (D == 1) {
-                double Mxx = (double)mom[2 * g.ns + s], MD = (double)mom[3 * g.ns + s];
-                double G0 = (double)mom[4 * g.ns + s], Gx = (double)mom[5 * g.ns + s];
-                P[0][0] = Mxx - rho * (ux * ux + RT);
-                Q[0] = MD - 2.0 * (ux * P[0][0]) - ux * P[0][0] - rho * (ux * ux + 3.0 * RT) * ux;
-                g0 = G0 - rho * K * RT;
-                h[0] = Gx - ux * G0;
-            } else {
-                double Mxx = (double)mom[3 * g.ns + s], Mxy = (double)mom[4 * g.ns + s];
-                double Myy = (double)mom[5 * g.ns + s];
-                double MD[2] = {(double)mom[6 * g.ns + s], (double)mom[7 * g.ns + s]};
-                double G0 = (double)mom[8 * g.ns + s];
-                double Gv[2] = {(double)mom[9 * g.ns + s], (double)mom[10 * g.ns + s]};
-                double uu = ux * ux + uy * uy;
-                P[0][0] = Mxx - rho * (ux * ux + RT);
-                P[0][1] = P[1][0] = Mxy - rho * (ux * uy);
-                P[1][1] = Myy - rho * (uy * uy + RT);
-                double trP = P[0][0] + P[1][1];
+__device__ inline void collide_targets(const Geom &g, const Phys &ph, const T *mom, long long s, double rho,
+                                       double ux, double uy, double RT, double *mf, double *mg, double &kn_out,
+                                       int &lim_out) {
+    const double K = ph.K;
+    double P[2][2] = {{0, 0}, {0, 0}}, Q[2] = {0, 0}, h[2] = {0, 0}, g0;
+    double u[2] = {ux, uy};
+    if (D == 1) {
+        double Mxx = (double)mom[2 * g.ns + s], MD = (double)mom[3 * g.ns + s];
+        double G0 = (double)mom[4 * g.ns + s], Gx = (double)mom[5 * g.ns + s];
+        P[0][0] = Mxx - rho * (ux * ux + RT);
+        Q[0] = MD - 2.0 * (ux * P[0][0]) - ux * P[0][0] - rho * (ux * ux + 3.0 * RT) * ux;
+        g0 = G0 - rho * K * RT;
+        h[0] = Gx - ux * G0;
+    } else {
+        double Mxx = (double)mom[3 * g.ns + s], Mxy = (double)mom[4 * g.ns + s];
+        double Myy = (double)mom[5 * g.ns + s];
+        double MD[2] = {(double)mom[6 * g.ns + s], (double)mom[7 * g.ns + s]};
+        double G0 = (double)mom[8 * g.ns + s];
+        double Gv[2] = {(double)mom[9 * g.ns + s], (double)mom[10 * g.ns + s]};
+        double uu = ux * ux + uy * uy;
+        P[0][0] = Mxx - rho * (ux * ux + RT);
+        P[0][1] = P[1][0] = Mxy - rho * (ux * uy);
+        P[1][1] = Myy - rho * (uy * uy + RT);
+        double trP = P[0][0] + P[1][1];
 #pragma unroll
-                for (int gg = 0; gg < 2; gg++) {
-                    double sm = u[0] * P[0][gg] + u[1] * P[1][gg];
-                    Q[gg] = MD[gg] - 2.0 * sm - u[gg] * trP - rho * (uu + 4.0 * RT) * u[gg];
-                }
-                g0 = G0 - rho * K * RT;
-#pragma unroll
-                for (int gg = 0; gg < 2; gg++) h[gg] = Gv[gg] - u[gg] * G0;
-            }
-            double sP = 0.0, sQ = 0.0;
-#pragma unroll
-            for (int a = 0; a < D; a++) {
-#pragma unroll
-                for (int bb = 0; bb < D; bb++) sP += fabs(P[a][bb]);
-                sQ += fabs(Q[a]) + fabs(h[a]);
-            }
-            double knA = (sP + fabs(g0)) / (rho * (D + K) * RT);
-            double knB = sQ / (rho * (D + K + 2.0) * pow(RT, 1.5));
-            double kn = knA > knB ? knA : knB;
-            double of = ph.omega_f, ob = ph.omega_b, oh = ph.omega_h;
-            if (ph.kn_limiter && kn >= ph.kn_lo_lin) {
-                if (kn > ph.kn_hi_lin) {
-                    of = ob = oh = ph.omega_H;
-                } else {
-                    double k = log10(kn), span = ph.kn_hi - ph.kn_lo;
-                    of = (ph.omega_H - ph.omega_f) / span * (k - ph.kn_lo) + ph.omega_f;
-                    ob = (ph.omega_H - ph.omega_b) / span * (k - ph.kn_lo) + ph.omega_b;
-                    oh = (ph.omega_H - ph.omega_h) / span * (k - ph.kn_lo) + ph.omega_h;
-                }
-                my_lim = (of != ph.omega_f) || (ob != ph.omega_b) || (oh != ph.omega_h);
-            }
-            my_kn = kn;
-            double bulk = -g0 / D;
-            double rKT = rho * K * RT;
-            if (D == 1) {
-                double shear = P[0][0] - bulk;
-                mf[0] = 1.0; mf[1] = 0.0;
-                mf[2] = RT + ((1.0 - of) * shear + (1.0 - ob) * bulk) / rho;
-                mf[3] = (1.0 - oh) * Q[0] / rho;
-                mg[0] = 1.0 + (1.0 - ob) * g0 / rKT;
-                mg[1] = (1.0 - oh) * h[0] / rKT;
-                mg[2] = RT;
-            } else {
-                double shxx = P[0][0] - bulk, shxy = P[0][1], shyy = P[1][1] - bulk;
-                mf[0] = 1.0; mf[1] = 0.0; mf[2] = 0.0;
-                mf[3] = RT + ((1.0 - of) * shxx + (1.0 - ob) * bulk) / rho;
-                mf[4] = ((1.0 - of) * shxy) / rho;
-                mf[5] = RT + ((1.0 - of) * shyy + (1.0 - ob) * bulk) / rho;
-                mf[6] = (1.0 - oh) * (0.75 * Q[0]) / rho;
-                mf[7] = (1.0 - oh) * (0.25 * Q[1]) / rho;
-                mf[8] = (1.0 - oh) * (0.25 * Q[0]) / rho;
-                mf[9] = (1.0 - oh) * (0.75 * Q[1]) / rho;
-                mg[0] = 1.0 + (1.0 - ob) * g0 / rKT;
-                mg[1] = (1.0 - oh) * h[0] / rKT;
-                mg[2] = (1.0 - oh) * h[1] / rKT;
-                mg[3] = RT; mg[4] = 0.0; mg[5] = RT;
-            }
+        for (int gg = 0; gg < 2; gg++) {
+            double sm = u[0] * P[0][gg] + u[1] * P[1][gg];
+            Q[gg] = MD[gg] - 2.0 * sm - u[gg] * trP - rho * (uu + 4.0 * RT) * u[gg];
         }
-        // ---- initial guess, Eq. (IID13)
-        Species<NF> sf;
-        Species<NG> sg;
+        g0 = G0 - rho * K * RT;
 #pragma unroll
-        for (int j = 0; j < NF; j++) { sf.lam[j] = 0.0; sf.del[j] = 0.0; }
-#pragma unroll
-        for (int j = 0; j < NG; j++) { sg.lam[j] = 0.0; sg.del[j] = 0.0; }
-        {
-            double l0 = -1.0 + 0.5 * D * log(2.0 * M_PI * RT), l2 = 1.0 / (2.0 * RT);
-            sf.lam[0] = l0; sg.lam[0] = l0;
-            if (D == 1) { sf.lam[2] = l2; sg.lam[2] = l2; }
-            else { sf.lam[3] = l2; sf.lam[5] = l2; sg.lam[3] = l2; sg.lam[5] = l2; }
-        }
-        sf.t = sg.t = 0.0; sf.dec = sg.dec = 0.0; sf.phi = sg.phi = 0.0;
-        sf.phase = sg.phase = 0; sf.nit = sg.nit = 0; sf.ls = sg.ls = 0;
-        int fail = 0;
-        // ---- Newton passes
-        while (!fail && (sf.phase < 2 || sg.phase < 2)) {
-            my_pass++;
-            double Sf[NMF], Sg[NMG], lf[NF], lg[NG];
-#pragma unroll
-            for (int k = 0; k < NMF; k++) Sf[k] = 0.0;
-#pragma unroll
-            for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
-#pragma unroll
-            for (int j = 0; j < NF; j++) lf[j] = sf.lam[j] + sf.t * sf.del[j];
-#pragma unroll
-            for (int j = 0; j < NG; j++) lg[j] = sg.lam[j] + sg.t * sg.del[j];
-            const bool df = sf.phase < 2, dg = sg.phase < 2;
-            for_each_point<D>(
-                ux, uy, R, Nr,
-                [&](double cx, double cy, double dC, int, int) {
-                    double m[NMF];
-                    monomials<D, NMF>(cx - ux, D == 2 ? cy - uy : 0.0, m);
-                    if (df) {
-                        double e = 0.0;
-#pragma unroll
-                        for (int j = 0; j < NF; j++) e += lf[j] * m[j];
-                        double f = dC * exp(-(1.0 + e));
-#pragma unroll
-                        for (int k = 0; k < NMF; k++) Sf[k] += f * m[k];
-                    }
-                    if (dg) {
-                        double e = 0.0;
-#pragma unroll
-                        for (int j = 0; j < NG; j++) e += lg[j] * m[j];
-                        double gv = dC * exp(-(1.0 + e));
-#pragma unroll
-                        for (int k = 0; k < NMG; k++) Sg[k] += gv * m[k];
-                    }
-                },
-                [&](int, int) {});
-            if (df) {
-                int r = species_update<D, NF, NMF>(sf, Sf, mf, RT, ph.tol, ph.maxit);
-                if (r < 0) fail = r;
-            }
-            if (dg && !fail) {
-                int r = species_update<D, NG, NMG>(sg, Sg, mg, RT, ph.tol, ph.maxit);
-                if (r < 0) fail = r;
-            }
-        }
-        if (fail) {
-            flag_fail(b.flags, fail, step, s);
-        } else {
-            // ---- final pass: moment fractions rho f', rho K RT g' (Eq. IIE3a)
-            const double wsf = rho, wsg = rho * K * RT;
-            const long long plane = (long long)ti.wx * ti.wy * TILE_N;
-            double *P = (double *)b.scratch + ti.base;
-            double acc[NM];
-#pragma unroll
-            for (int k = 0; k < NM; k++) acc[k] = 0.0;
-            int q = 0;
-            for_each_point<D>(
-                ux, uy, R, Nr,
-                [&](double cx, double cy, double dC, int dx, int dy) {
-                    double m[NF];
-                    monomials<D, NF>(cx - ux, D == 2 ? cy - uy : 0.0, m);
-                    double ef = 0.0, eg = 0.0;
-#pragma unroll
-                    for (int j = 0; j < NF; j++) ef += sf.lam[j] * m[j];
-#pragma unroll
-                    for (int j = 0; j < NG; j++) eg += sg.lam[j] * m[j];
-                    double wf = wsf * (dC * exp(-(1.0 + ef)));
-                    double wg = wsg * (dC * exp(-(1.0 + eg)));
-                    q++;
-                    if (ti.fmt == 0) {
-                        long long slot = (long long)(dy - ti.oy) * ti.wx + (dx - ti.ox);
-                        P[slot * TILE_N + l] = wf;
-                        P[plane + slot * TILE_N + l] = wg;
-                    } else {
-                        if (D == 1) {
-                            acc[0] += wf; acc[1] += cx * wf; acc[2] += cx * cx * wf; acc[3] += cx * cx * cx * wf;
-                            acc[4] += wg; acc[5] += cx * wg;
-                        } else {
-                            double cc = cx * cx + cy * cy;
-                            acc[0] += wf; acc[1] += cx * wf; acc[2] += cy * wf;
-                            acc[3] += cx * cx * wf; acc[4] += cx * cy * wf; acc[5] += cy * cy * wf;
-                            acc[6] += cc * cx * wf; acc[7] += cc * cy * wf;
-                            acc[8] += wg; acc[9] += cx * wg; acc[10] += cy * wg;
-                        }
-                    }
-                },
-                [&](int dx, int dy) {
-                    if (ti.fmt == 1) {
-                        long long slot = (long long)(dy - ti.oy) * ti.wx + (dx - ti.ox);
-#pragma unroll
-                        for (int k = 0; k < NM; k++) {
-                            P[k * plane + slot * TILE_N + l] = acc[k];
-                            acc[k] = 0.0;
-                        }
-                    }
-                });
-            my_pass++;
-            my_it_f = sf.nit;
-            my_it_g = sg.nit;
-            my_q = q;
-            my_rt = RT;
-            my_colat = (D == 2 ? sqrt(ux * ux + uy * uy) : fabs(ux)) + R;
-        }
+        for (int gg = 0; gg < 2; gg++) h[gg] = Gv[gg] - u[gg] * G0;
     }
-    // ---- statistics (one atomic per wavefront)
-    unsigned long long a_itf = my_it_f, a_itg = my_it_g, a_q = my_q, a_lim = my_lim, a_cells = active ? 1 : 0;
-    unsigned long long a_qp = (unsigned long long)my_q * my_pass;
-    int m_itf = my_it_f, m_itg = my_it_g, m_q = my_q, n_q = active ? my_q : 1 << 30;
-    double m_kn = my_kn, m_colat = my_colat, n_rt = my_rt;
+    double sP = 0.0, sQ = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+#pragma unroll
+        for (int bb = 0; bb < D; bb++) sP += fabs(P[a][bb]);
+        sQ += fabs(Q[a]) + fabs(h[a]);
+    }
+    double knA = (sP + fabs(g0)) / (rho * (D + K) * RT);
+    double knB = sQ / (rho * (D + K + 2.0) * pow(RT, 1.5));
+    double kn = knA > knB ? knA : knB;
+    double of = ph.omega_f, ob = ph.omega_b, oh = ph.omega_h;
+    int lim = 0;
+    if (ph.kn_limiter && kn >= ph.kn_lo_lin) {
+        if (kn > ph.kn_hi_lin) {
+            of = ob = oh = ph.omega_H;
+        } else {
+            double k = log10(kn), span = ph.kn_hi - ph.kn_lo;
+            of = (ph.omega_H - ph.omega_f) / span * (k - ph.kn_lo) + ph.omega_f;
+            ob = (ph.omega_H - ph.omega_b) / span * (k - ph.kn_lo) + ph.omega_b;
+            oh = (ph.omega_H - ph.omega_h) / span * (k - ph.kn_lo) + ph.omega_h;
+        }
+        lim = (of != ph.omega_f) || (ob != ph.omega_b) || (oh != ph.omega_h);
+    }
+    kn_out = kn;
+    lim_out = lim;
+    double bulk = -g0 / D;
+    double rKT = rho * K * RT;
+    if (D == 1) {
+        double shear = P[0][0] - bulk;
+        mf[0] = 1.0; mf[1] = 0.0;
+        mf[2] = RT + ((1.0 - of) * shear + (1.0 - ob) * bulk) / rho;
+        mf[3] = (1.0 - oh) * Q[0] / rho;
+        mg[0] = 1.0 + (1.0 - ob) * g0 / rKT;
+        mg[1] = (1.0 - oh) * h[0] / rKT;
+        mg[2] = RT;
+    } else {
+        double shxx = P[0][0] - bulk, shxy = P[0][1], shyy = P[1][1] - bulk;
+        mf[0] = 1.0; mf[1] = 0.0; mf[2] = 0.0;
+        mf[3] = RT + ((1.0 - of) * shxx + (1.0 - ob) * bulk) / rho;
+        mf[4] = ((1.0 - of) * shxy) / rho;
+        mf[5] = RT + ((1.0 - of) * shyy + (1.0 - ob) * bulk) / rho;
+        mf[6] = (1.0 - oh) * (0.75 * Q[0]) / rho;
+        mf[7] = (1.0 - oh) * (0.25 * Q[1]) / rho;
+        mf[8] = (1.0 - oh) * (0.25 * Q[0]) / rho;
+        mf[9] = (1.0 - oh) * (0.75 * Q[1]) / rho;
+        mg[0] = 1.0 + (1.0 - ob) * g0 / rKT;
+        mg[1] = (1.0 - oh) * h[0] / rKT;
+        mg[2] = (1.0 - oh) * h[1] / rKT;
+        mg[3] = RT; mg[4] = 0.0; mg[5] = RT;
+    }
+}
+
+// Initial multipliers of Eq. (IID13) for both species.
+template <int D, int NF, int NG>
+__device__ inline void species_init(Species<NF> &sf, Species<NG> &sg, double RT) {
+#pragma unroll
+    for (int j = 0; j < NF; j++) { sf.lam[j] = 0.0; sf.del[j] = 0.0; }
+#pragma unroll
+    for (int j = 0; j < NG; j++) { sg.lam[j] = 0.0; sg.del[j] = 0.0; }
+    double l0 = -1.0 + 0.5 * D * log(2.0 * M_PI * RT), l2 = 1.0 / (2.0 * RT);
+    sf.lam[0] = l0; sg.lam[0] = l0;
+    if (D == 1) { sf.lam[2] = l2; sg.lam[2] = l2; }
+    else { sf.lam[3] = l2; sf.lam[5] = l2; sg.lam[3] = l2; sg.lam[5] = l2; }
+    sf.t = sg.t = 0.0; sf.dec = sg.dec = 0.0; sf.phi = sg.phi = 0.0;
+    sf.phase = sg.phase = 0; sf.nit = sg.nit = 0; sf.ls = sg.ls = 0;
+}
+
+// Per-cell statistics, reduced over the wavefront, one atomic per wave.
+struct CellStats {
+    int it_f = 0, it_g = 0, q = 0, lim = 0, pass = 0;
+    double kn = 0.0, colat = 0.0, rt = 1e300;
+    bool active = false;
+};
+
+__device__ inline void push_stats(DevStats *st, const CellStats &c) {
+    unsigned long long a_itf = c.it_f, a_itg = c.it_g, a_q = c.q, a_lim = c.lim, a_cells = c.active ? 1 : 0;
+    unsigned long long a_qp = (unsigned long long)c.q * c.pass;
+    int m_itf = c.it_f, m_itg = c.it_g, m_q = c.q, n_q = c.active ? c.q : 1 << 30;
+    double m_kn = c.kn, m_colat = c.colat, n_rt = c.rt;
     for (int off = 32; off > 0; off >>= 1) {
         a_itf += __shfl_xor(a_itf, off);
         a_itg += __shfl_xor(a_itg, off);
@@ -748,7 +634,6 @@ __global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buff
         n_rt = fmin(n_rt, __shfl_xor(n_rt, off));
     }
     if ((threadIdx.x & 63) == 0 && a_cells > 0) {
-        DevStats *st = b.stats;
         atomicAdd(&st->it_sum_f, a_itf);
         atomicAdd(&st->it_sum_g, a_itg);
         atomicAdd(&st->q_sum, a_q);
@@ -763,6 +648,346 @@ __global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buff
         atomic_max_pos(&st->colat_max_bits, m_colat);
         atomic_min_pos(&st->rt_min_bits, n_rt);
     }
+}
+
+// Exact interval [xa, xb] of integer cx in row cy with |c - u| <= rr (the
+// same predicate as the gather's), searched from the analytic estimate.
+template <int D>
+__device__ inline bool row_span(int cy, double ux, double uy, double rr, int lo, int hi, int &xa, int &xb) {
+    double yy = D == 2 ? (double)cy - uy : 0.0;
+    double rem = rr * rr - yy * yy;
+    double w = rem > 0.0 ? sqrt(rem) : 0.0;
+    int a = (int)ceil(ux - w), b = (int)floor(ux + w);
+    a = a < lo ? lo : (a > hi ? hi : a);
+    b = b > hi ? hi : (b < lo ? lo : b);
+    auto in = [&](int cx) {
+        return D == 2 ? in_disk2((double)cx, (double)cy, ux, uy, rr) : in_disk1((double)cx, ux, rr);
+    };
+    while (a > lo && in(a - 1)) a--;
+    while (a <= b && !in(a)) a++;
+    while (b < hi && in(b + 1)) b++;
+    while (b >= a && !in(b)) b--;
+    xa = a;
+    xb = b;
+    return a <= b;
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction of cells without stencil refinement (N_r = 0).
+//
+// Along a stencil row (fixed c_y) the exponent of Eq. (IID7) is a cubic (fluon)
+// or quadratic (phonon) polynomial of c_x, so consecutive populations follow
+// from a product recurrence of exponentials of its finite differences: four
+// (three) exponentials per row instead of two per point.  Row sums of f x^a
+// are folded into the monomial sums S[a,b] = sum f x^a y^b (a + b <= 6 for the
+// fluon, <= 4 for the phonon), from which the Newton residual and the Hessian
+// A_ij = S[T_i T_j] (Eq. IID11a) are assembled.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ inline void row_poly(const double *lf, const double *lg, double y, double *e, double *h) {
+    if (D == 2) {
+        double y2 = y * y, y3 = y2 * y;
+        e[0] = -1.0 - (lf[0] + lf[2] * y + lf[5] * y2 + lf[9] * y3);
+        e[1] = -(lf[1] + lf[4] * y + lf[8] * y2);
+        e[2] = -(lf[3] + lf[7] * y);
+        e[3] = -lf[6];
+        h[0] = -1.0 - (lg[0] + lg[2] * y + lg[5] * y2);
+        h[1] = -(lg[1] + lg[4] * y);
+        h[2] = -lg[3];
+    } else {
+        e[0] = -1.0 - lf[0]; e[1] = -lf[1]; e[2] = -lf[2]; e[3] = -lf[3];
+        h[0] = -1.0 - lg[0]; h[1] = -lg[1]; h[2] = -lg[2];
+    }
+}
+
+// Starting value and ratios of the product recurrence at x0 = xa - ux.
+__device__ inline void row_start(const double *e, const double *h, double x0, double &f, double &r, double &s2,
+                                 double &t3, double &gv, double &rg, double &sg2) {
+    double E0 = e[0] + x0 * (e[1] + x0 * (e[2] + x0 * e[3]));
+    double a2 = e[2] + 3.0 * e[3] * x0;
+    double a1 = e[1] + x0 * (2.0 * e[2] + 3.0 * e[3] * x0);
+    f = exp(E0);
+    r = exp(a1 + a2 + e[3]);
+    s2 = exp(2.0 * a2 + 6.0 * e[3]);
+    t3 = exp(6.0 * e[3]);
+    double H0 = h[0] + x0 * (h[1] + x0 * h[2]);
+    double b1 = h[1] + 2.0 * h[2] * x0;
+    gv = exp(H0);
+    rg = exp(b1 + h[2]);
+    sg2 = exp(2.0 * h[2]);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buffers b, int step) {
+    using BS = Basis<D>;
+    constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
+    __shared__ int s_err;
+    if (threadIdx.x == 0) s_err = b.flags->err;
+    __syncthreads();
+    if (s_err) return;
+    int t = blockIdx.x;
+    int tx0 = (t % g.ntx) * g.tx, ty0 = (t / g.ntx) * g.ty;
+    int l = threadIdx.x;
+    int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
+    bool valid = px < g.sxn && py < g.syn;
+    long long s = (long long)py * g.sxn + px;
+    int rn = valid ? b.desc_rn[s] : -1;
+    CellStats cs;
+    cs.active = rn >= 0 && (rn >> 16) == 0;
+    if (cs.active) {
+        const TileInfo ti = b.tiles[t];
+        double rho = b.desc_rho[s], ux = b.desc_u[s], uy = b.desc_u[g.ns + s], RT = b.desc_rt[s];
+        const int R = rn & 0xffff;
+        const double rr = R + 0.5;
+        const int ubx = (int)floor(ux + 0.5), uby = D == 2 ? (int)floor(uy + 0.5) : 0;
+        const int ylo = D == 2 ? uby - R - 1 : 0, yhi = D == 2 ? uby + R + 1 : 0;
+        const int xlo = ubx - R - 1, xhi = ubx + R + 1;
+        double mf[NF], mg[NG];
+        collide_targets<T, D>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, cs.kn, cs.lim);
+        Species<NF> sf;
+        Species<NG> sg;
+        species_init<D, NF, NG>(sf, sg, RT);
+        int fail = 0;
+        while (!fail && (sf.phase < 2 || sg.phase < 2)) {
+            cs.pass++;
+            double Sf[NMF], Sg[NMG];
+#pragma unroll
+            for (int k = 0; k < NMF; k++) Sf[k] = 0.0;
+#pragma unroll
+            for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
+            for (int cy = ylo; cy <= yhi; cy++) {
+                int xa, xb;
+                if (!row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb)) continue;
+                double y = D == 2 ? (double)cy - uy : 0.0;
+                double e[4], h[3];
+                {
+                    double lf[NF], lg[NG];
+#pragma unroll
+                    for (int j = 0; j < NF; j++) lf[j] = sf.lam[j] + sf.t * sf.del[j];
+#pragma unroll
+                    for (int j = 0; j < NG; j++) lg[j] = sg.lam[j] + sg.t * sg.del[j];
+                    row_poly<D>(lf, lg, y, e, h);
+                }
+                double f, r, s2, t3, gv, rg, sg2;
+                row_start(e, h, (double)xa - ux, f, r, s2, t3, gv, rg, sg2);
+                double Rf[7], Rg[5];
+#pragma unroll
+                for (int k = 0; k < 7; k++) Rf[k] = 0.0;
+#pragma unroll
+                for (int k = 0; k < 5; k++) Rg[k] = 0.0;
+                for (int cx = xa; cx <= xb; cx++) {
+                    double x = (double)cx - ux;
+                    double x2 = x * x, x3 = x2 * x, x4 = x2 * x2, x5 = x4 * x, x6 = x3 * x3;
+                    Rf[0] += f; Rf[1] += f * x; Rf[2] += f * x2; Rf[3] += f * x3;
+                    Rf[4] += f * x4; Rf[5] += f * x5; Rf[6] += f * x6;
+                    Rg[0] += gv; Rg[1] += gv * x; Rg[2] += gv * x2; Rg[3] += gv * x3; Rg[4] += gv * x4;
+                    f *= r; r *= s2; s2 *= t3;
+                    gv *= rg; rg *= sg2;
+                }
+                if (D == 2) {
+                    double py_[7];
+                    py_[0] = 1.0;
+#pragma unroll
+                    for (int k = 1; k < 7; k++) py_[k] = py_[k - 1] * y;
+#pragma unroll
+                    for (int k = 0; k < NMF; k++) Sf[k] += py_[mono_b(k)] * Rf[mono_a(k)];
+#pragma unroll
+                    for (int k = 0; k < NMG; k++) Sg[k] += py_[mono_b(k)] * Rg[mono_a(k)];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NMF; k++) Sf[k] += Rf[k];
+#pragma unroll
+                    for (int k = 0; k < NMG; k++) Sg[k] += Rg[k];
+                }
+            }
+            if (sf.phase < 2) {
+                int r = species_update<D, NF, NMF>(sf, Sf, mf, RT, ph.tol, ph.maxit);
+                if (r < 0) fail = r;
+            }
+            if (sg.phase < 2 && !fail) {
+                int r = species_update<D, NG, NMG>(sg, Sg, mg, RT, ph.tol, ph.maxit);
+                if (r < 0) fail = r;
+            }
+        }
+        if (fail) {
+            flag_fail(b.flags, fail, step, s);
+        } else {
+            // final pass: moment fractions rho f', rho K RT g' (Eq. IIE3a)
+            const double wsf = rho, wsg = rho * ph.K * RT;
+            const long long plane = (long long)ti.wx * ti.wy * TILE_N;
+            double *P = (double *)b.scratch + ti.base;
+            int q = 0;
+            for (int cy = ylo; cy <= yhi; cy++) {
+                int xa, xb;
+                if (!row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb)) continue;
+                double y = D == 2 ? (double)cy - uy : 0.0;
+                double e[4], h[3];
+                row_poly<D>(sf.lam, sg.lam, y, e, h);
+                double f, r, s2, t3, gv, rg, sg2;
+                row_start(e, h, (double)xa - ux, f, r, s2, t3, gv, rg, sg2);
+                long long rowslot = (long long)(cy - ti.oy) * ti.wx - ti.ox;
+                for (int cx = xa; cx <= xb; cx++) {
+                    double wf = wsf * f, wg = wsg * gv;
+                    long long slot = rowslot + cx;
+                    if (ti.fmt == 0) {
+                        P[slot * TILE_N + l] = wf;
+                        P[plane + slot * TILE_N + l] = wg;
+                    } else {
+                        double c1 = (double)cx, c2 = (double)cy;
+                        double mo[NM];
+                        if (D == 1) {
+                            mo[0] = wf; mo[1] = c1 * wf; mo[2] = c1 * c1 * wf; mo[3] = c1 * c1 * c1 * wf;
+                            mo[4] = wg; mo[5] = c1 * wg;
+                        } else {
+                            double cc = c1 * c1 + c2 * c2;
+                            mo[0] = wf; mo[1] = c1 * wf; mo[2] = c2 * wf;
+                            mo[3] = c1 * c1 * wf; mo[4] = c1 * c2 * wf; mo[5] = c2 * c2 * wf;
+                            mo[6] = cc * c1 * wf; mo[7] = cc * c2 * wf;
+                            mo[8] = wg; mo[9] = c1 * wg; mo[10] = c2 * wg;
+                        }
+#pragma unroll
+                        for (int k = 0; k < NM; k++) P[k * plane + slot * TILE_N + l] = mo[k];
+                    }
+                    f *= r; r *= s2; s2 *= t3;
+                    gv *= rg; rg *= sg2;
+                    q++;
+                }
+            }
+            cs.pass++;
+            cs.it_f = sf.nit;
+            cs.it_g = sg.nit;
+            cs.q = q;
+            cs.rt = RT;
+            cs.colat = (D == 2 ? sqrt(ux * ux + uy * uy) : fabs(ux)) + R;
+        }
+    }
+    push_stats(b.stats, cs);
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction of cells with refined stencils (N_r > 0, RT < 4/9): points
+// are visited one by one (Eqs. IIC10-11) with direct exponentials, and the
+// moment fractions of each base point's descendants are pre-summed, since
+// they all land in the base point's cell.  Runs only on tiles that hold
+// refined cells.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, Buffers b, int step) {
+    using BS = Basis<D>;
+    constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
+    __shared__ int s_skip;
+    int t = blockIdx.x;
+    if (threadIdx.x == 0) s_skip = b.flags->err || b.tiles[t].fmt == 0;
+    __syncthreads();
+    if (s_skip) return;
+    int tx0 = (t % g.ntx) * g.tx, ty0 = (t / g.ntx) * g.ty;
+    int l = threadIdx.x;
+    int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
+    bool valid = px < g.sxn && py < g.syn;
+    long long s = (long long)py * g.sxn + px;
+    int rn = valid ? b.desc_rn[s] : -1;
+    CellStats cs;
+    cs.active = rn >= 0 && (rn >> 16) > 0;
+    if (cs.active) {
+        const TileInfo ti = b.tiles[t];
+        double rho = b.desc_rho[s], ux = b.desc_u[s], uy = b.desc_u[g.ns + s], RT = b.desc_rt[s];
+        int R = rn & 0xffff, Nr = rn >> 16;
+        double mf[NF], mg[NG];
+        collide_targets<T, D>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, cs.kn, cs.lim);
+        Species<NF> sf;
+        Species<NG> sg;
+        species_init<D, NF, NG>(sf, sg, RT);
+        int fail = 0;
+        while (!fail && (sf.phase < 2 || sg.phase < 2)) {
+            cs.pass++;
+            double Sf[NMF], Sg[NMG], lf[NF], lg[NG];
+#pragma unroll
+            for (int k = 0; k < NMF; k++) Sf[k] = 0.0;
+#pragma unroll
+            for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NF; j++) lf[j] = sf.lam[j] + sf.t * sf.del[j];
+#pragma unroll
+            for (int j = 0; j < NG; j++) lg[j] = sg.lam[j] + sg.t * sg.del[j];
+            for_each_point<D>(
+                ux, uy, R, Nr,
+                [&](double cx, double cy, double dC, int, int) {
+                    double m[NMF];
+                    monomials<D, NMF>(cx - ux, D == 2 ? cy - uy : 0.0, m);
+                    double e = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NF; j++) e += lf[j] * m[j];
+                    double f = dC * exp(-(1.0 + e));
+#pragma unroll
+                    for (int k = 0; k < NMF; k++) Sf[k] += f * m[k];
+                    double e2 = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NG; j++) e2 += lg[j] * m[j];
+                    double gv = dC * exp(-(1.0 + e2));
+#pragma unroll
+                    for (int k = 0; k < NMG; k++) Sg[k] += gv * m[k];
+                },
+                [&](int, int) {});
+            if (sf.phase < 2) {
+                int r = species_update<D, NF, NMF>(sf, Sf, mf, RT, ph.tol, ph.maxit);
+                if (r < 0) fail = r;
+            }
+            if (sg.phase < 2 && !fail) {
+                int r = species_update<D, NG, NMG>(sg, Sg, mg, RT, ph.tol, ph.maxit);
+                if (r < 0) fail = r;
+            }
+        }
+        if (fail) {
+            flag_fail(b.flags, fail, step, s);
+        } else {
+            const double wsf = rho, wsg = rho * ph.K * RT;
+            const long long plane = (long long)ti.wx * ti.wy * TILE_N;
+            double *P = (double *)b.scratch + ti.base;
+            double acc[NM];
+#pragma unroll
+            for (int k = 0; k < NM; k++) acc[k] = 0.0;
+            int q = 0;
+            for_each_point<D>(
+                ux, uy, R, Nr,
+                [&](double cx, double cy, double dC, int, int) {
+                    double m[NF];
+                    monomials<D, NF>(cx - ux, D == 2 ? cy - uy : 0.0, m);
+                    double ef = 0.0, eg = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NF; j++) ef += sf.lam[j] * m[j];
+#pragma unroll
+                    for (int j = 0; j < NG; j++) eg += sg.lam[j] * m[j];
+                    double wf = wsf * (dC * exp(-(1.0 + ef)));
+                    double wg = wsg * (dC * exp(-(1.0 + eg)));
+                    q++;
+                    if (D == 1) {
+                        acc[0] += wf; acc[1] += cx * wf; acc[2] += cx * cx * wf; acc[3] += cx * cx * cx * wf;
+                        acc[4] += wg; acc[5] += cx * wg;
+                    } else {
+                        double cc = cx * cx + cy * cy;
+                        acc[0] += wf; acc[1] += cx * wf; acc[2] += cy * wf;
+                        acc[3] += cx * cx * wf; acc[4] += cx * cy * wf; acc[5] += cy * cy * wf;
+                        acc[6] += cc * cx * wf; acc[7] += cc * cy * wf;
+                        acc[8] += wg; acc[9] += cx * wg; acc[10] += cy * wg;
+                    }
+                },
+                [&](int dx, int dy) {
+                    long long slot = (long long)(dy - ti.oy) * ti.wx + (dx - ti.ox);
+#pragma unroll
+                    for (int k = 0; k < NM; k++) {
+                        P[k * plane + slot * TILE_N + l] = acc[k];
+                        acc[k] = 0.0;
+                    }
+                });
+            cs.pass++;
+            cs.it_f = sf.nit;
+            cs.it_g = sg.nit;
+            cs.q = q;
+            cs.rt = RT;
+            cs.colat = (D == 2 ? sqrt(ux * ux + uy * uy) : fabs(ux)) + R;
+        }
+    }
+    push_stats(b.stats, cs);
 }
 
 // ---------------------------------------------------------------------------
@@ -984,8 +1209,13 @@ hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom,
                       hipStream_t s) {
     unsigned nt = (unsigned)(g.ntx * g.nty);
     if (mixed) return hipErrorInvalidValue;
-    if (g.dim == 1) hipLaunchKernelGGL((k_epr<double, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
-    else hipLaunchKernelGGL((k_epr<double, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
+    if (g.dim == 1) {
+        hipLaunchKernelGGL((k_epr<double, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
+        hipLaunchKernelGGL((k_epr_ref<double, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
+    } else {
+        hipLaunchKernelGGL((k_epr<double, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
+        hipLaunchKernelGGL((k_epr_ref<double, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
+    }
     return hipGetLastError();
 }
 
