@@ -381,19 +381,26 @@ __device__ inline void for_each_point(double ux, double uy, int R, int Nr, Leaf 
 // ---------------------------------------------------------------------------
 template <int D, int N>
 __device__ inline bool hess_solve(const double *S, const double *r, double *x) {
-    double L[N * (N + 1) / 2];
+    // A_ij = S[T_i T_j] (Eq. IID11a), lower triangle, factored in place
+    double L[N * (N + 1) / 2], inv[N];
+#pragma unroll
+    for (int i = 0; i < N; i++)
+#pragma unroll
+        for (int j = 0; j <= i; j++) L[i * (i + 1) / 2 + j] = S[hess_idx<D>(i, j)];
 #pragma unroll
     for (int i = 0; i < N; i++) {
 #pragma unroll
         for (int j = 0; j <= i; j++) {
-            double s = S[hess_idx<D>(i, j)];
+            double s = L[i * (i + 1) / 2 + j];
 #pragma unroll
             for (int k = 0; k < j; k++) s -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
             if (i == j) {
                 if (!(s > 0.0) || !isfinite(s)) return false;
-                L[i * (i + 1) / 2 + i] = sqrt(s);
+                double d = sqrt(s);
+                L[i * (i + 1) / 2 + i] = d;
+                inv[i] = 1.0 / d;
             } else {
-                L[i * (i + 1) / 2 + j] = s / L[j * (j + 1) / 2 + j];
+                L[i * (i + 1) / 2 + j] = s * inv[j];
             }
         }
     }
@@ -403,42 +410,55 @@ __device__ inline bool hess_solve(const double *S, const double *r, double *x) {
         double s = r[i];
 #pragma unroll
         for (int k = 0; k < i; k++) s -= L[i * (i + 1) / 2 + k] * y[k];
-        y[i] = s / L[i * (i + 1) / 2 + i];
+        y[i] = s * inv[i];
     }
 #pragma unroll
     for (int i = N - 1; i >= 0; i--) {
         double s = y[i];
 #pragma unroll
         for (int k = i + 1; k < N; k++) s -= L[k * (k + 1) / 2 + i] * x[k];
-        x[i] = s / L[i * (i + 1) / 2 + i];
+        x[i] = s * inv[i];
     }
     return true;
 }
 
 // Newton state of one species (fluon or phonon), Sec. II.D.  The step is
 // a damped Newton method on the convex dual Phi(l) = sum f + l.m' (Armijo
-// backtracking while the Newton decrement exceeds 1e-8).
-template <int NB> struct Species {
-    double lam[NB];   // accepted multipliers
-    double del[NB];   // current Newton direction
+// backtracking while the Newton decrement exceeds 1e-8).  The multipliers and
+// the current direction live either in registers or in LDS (one column per
+// cell of the tile), which keeps the register file of the hot kernel small
+// enough for two waves per SIMD.
+template <int NB> struct RegStore {
+    double lam_[NB], del_[NB];
+    __device__ double &lam(int j) { return lam_[j]; }
+    __device__ double &del(int j) { return del_[j]; }
+};
+template <int NB> struct LdsStore {
+    double *lam_, *del_;   // column of the cell in [NB][TILE_N] arrays
+    __device__ double &lam(int j) { return lam_[j * TILE_N]; }
+    __device__ double &del(int j) { return del_[j * TILE_N]; }
+};
+
+template <int NB, class Store> struct Species {
+    Store v;
     double t, dec, phi;
     int phase;        // 0: first evaluation, 1: iterating, 2: polished
     int nit, ls;
+    __device__ double at(int j) { return v.lam(j) + t * v.del(j); }   // multipliers of the current pass
 };
 
 // After a pass evaluated at lam + t*del: accept / backtrack / step / polish.
 // Returns 0 to continue, 1 when polished, negative LELBM code on failure.
-template <int D, int NB, int NM>
-__device__ inline int species_update(Species<NB> &sp, const double *S, const double *tg, double RT, double tol,
-                                     int maxit) {
-    double lt[NB], r[NB];
+template <int D, int NB, int NM, class Store>
+__device__ inline int species_update(Species<NB, Store> &sp, const double *S, const double *tg, const double *isc,
+                                     double tol, int maxit) {
+    double r[NB];
     double phit = S[0];
     bool fin = isfinite(S[0]);
 #pragma unroll
     for (int j = 0; j < NB; j++) {
-        lt[j] = sp.lam[j] + sp.t * sp.del[j];
         r[j] = S[j] - tg[j];
-        phit += lt[j] * tg[j];
+        phit += sp.at(j) * tg[j];
         fin = fin && isfinite(r[j]);
     }
     fin = fin && isfinite(phit);
@@ -454,20 +474,20 @@ __device__ inline int species_update(Species<NB> &sp, const double *S, const dou
         sp.nit++;
     }
 #pragma unroll
-    for (int j = 0; j < NB; j++) sp.lam[j] = lt[j];
+    for (int j = 0; j < NB; j++) sp.v.lam(j) = sp.at(j);
+    sp.t = 0.0;
     sp.phi = phit;
     double res = 0.0;
 #pragma unroll
     for (int j = 0; j < NB; j++) {
-        double v = fabs(r[j]) / pow(RT, 0.5 * order_of<D>(j));
+        double v = fabs(r[j]) * isc[order_of<D>(j)];
         res = v > res ? v : res;
     }
     double dl[NB];
     if (res <= tol) {
         if (!hess_solve<D, NB>(S, r, dl)) return LELBM_EEPR;
 #pragma unroll
-        for (int j = 0; j < NB; j++) { sp.lam[j] += dl[j]; sp.del[j] = 0.0; }
-        sp.t = 0.0;
+        for (int j = 0; j < NB; j++) { sp.v.lam(j) += dl[j]; sp.v.del(j) = 0.0; }
         sp.nit++;
         sp.phase = 2;
         return 1;
@@ -476,7 +496,7 @@ __device__ inline int species_update(Species<NB> &sp, const double *S, const dou
     if (!hess_solve<D, NB>(S, r, dl)) return LELBM_EEPR;
     double dec = 0.0;
 #pragma unroll
-    for (int j = 0; j < NB; j++) { sp.del[j] = dl[j]; dec += r[j] * dl[j]; }
+    for (int j = 0; j < NB; j++) { sp.v.del(j) = dl[j]; dec += r[j] * dl[j]; }
     sp.dec = dec;
     sp.t = 1.0;
     sp.ls = 0;
@@ -592,16 +612,16 @@ __device__ inline void collide_targets(const Geom &g, const Phys &ph, const T *m
 }
 
 // Initial multipliers of Eq. (IID13) for both species.
-template <int D, int NF, int NG>
-__device__ inline void species_init(Species<NF> &sf, Species<NG> &sg, double RT) {
+template <int D, int NF, int NG, class SF, class SG>
+__device__ inline void species_init(Species<NF, SF> &sf, Species<NG, SG> &sg, double RT) {
 #pragma unroll
-    for (int j = 0; j < NF; j++) { sf.lam[j] = 0.0; sf.del[j] = 0.0; }
+    for (int j = 0; j < NF; j++) { sf.v.lam(j) = 0.0; sf.v.del(j) = 0.0; }
 #pragma unroll
-    for (int j = 0; j < NG; j++) { sg.lam[j] = 0.0; sg.del[j] = 0.0; }
+    for (int j = 0; j < NG; j++) { sg.v.lam(j) = 0.0; sg.v.del(j) = 0.0; }
     double l0 = -1.0 + 0.5 * D * log(2.0 * M_PI * RT), l2 = 1.0 / (2.0 * RT);
-    sf.lam[0] = l0; sg.lam[0] = l0;
-    if (D == 1) { sf.lam[2] = l2; sg.lam[2] = l2; }
-    else { sf.lam[3] = l2; sf.lam[5] = l2; sg.lam[3] = l2; sg.lam[5] = l2; }
+    sf.v.lam(0) = l0; sg.v.lam(0) = l0;
+    if (D == 1) { sf.v.lam(2) = l2; sg.v.lam(2) = l2; }
+    else { sf.v.lam(3) = l2; sf.v.lam(5) = l2; sg.v.lam(3) = l2; sg.v.lam(5) = l2; }
     sf.t = sg.t = 0.0; sf.dec = sg.dec = 0.0; sf.phi = sg.phi = 0.0;
     sf.phase = sg.phase = 0; sf.nit = sg.nit = 0; sf.ls = sg.ls = 0;
 }
@@ -700,27 +720,29 @@ __device__ inline void row_poly(const double *lf, const double *lg, double y, do
     }
 }
 
-// Starting value and ratios of the product recurrence at x0 = xa - ux.
+// Starting value and ratios of the product recurrence at x0 = xa - ux.  The
+// third difference of the fluon exponent (6 e3) and the second difference of
+// the phonon exponent (2 h2) do not depend on the row; their exponentials
+// t3 and sg2 are computed once per pass.
 __device__ inline void row_start(const double *e, const double *h, double x0, double &f, double &r, double &s2,
-                                 double &t3, double &gv, double &rg, double &sg2) {
+                                 double &gv, double &rg) {
     double E0 = e[0] + x0 * (e[1] + x0 * (e[2] + x0 * e[3]));
     double a2 = e[2] + 3.0 * e[3] * x0;
     double a1 = e[1] + x0 * (2.0 * e[2] + 3.0 * e[3] * x0);
     f = exp(E0);
     r = exp(a1 + a2 + e[3]);
     s2 = exp(2.0 * a2 + 6.0 * e[3]);
-    t3 = exp(6.0 * e[3]);
     double H0 = h[0] + x0 * (h[1] + x0 * h[2]);
     double b1 = h[1] + 2.0 * h[2] * x0;
     gv = exp(H0);
     rg = exp(b1 + h[2]);
-    sg2 = exp(2.0 * h[2]);
 }
 
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buffers b, int step) {
+__global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, Buffers b, int step) {
     using BS = Basis<D>;
     constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
+    __shared__ double s_lamf[NF * TILE_N], s_delf[NF * TILE_N], s_lamg[NG * TILE_N], s_delg[NG * TILE_N];
     __shared__ int s_err;
     if (threadIdx.x == 0) s_err = b.flags->err;
     __syncthreads();
@@ -744,32 +766,35 @@ __global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buff
         const int xlo = ubx - R - 1, xhi = ubx + R + 1;
         double mf[NF], mg[NG];
         collide_targets<T, D>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, cs.kn, cs.lim);
-        Species<NF> sf;
-        Species<NG> sg;
+        Species<NF, LdsStore<NF>> sf;
+        Species<NG, LdsStore<NG>> sg;
+        sf.v.lam_ = s_lamf + l; sf.v.del_ = s_delf + l;
+        sg.v.lam_ = s_lamg + l; sg.v.del_ = s_delg + l;
         species_init<D, NF, NG>(sf, sg, RT);
+        // residual scales RT^(-k/2) of basis order k (scale-free stopping test)
+        const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
         int fail = 0;
         while (!fail && (sf.phase < 2 || sg.phase < 2)) {
             cs.pass++;
-            double Sf[NMF], Sg[NMG];
+            double Sf[NMF], Sg[NMG], lf[NF], lg[NG];
+#pragma unroll
+            for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
+#pragma unroll
+            for (int j = 0; j < NG; j++) lg[j] = sg.at(j);
 #pragma unroll
             for (int k = 0; k < NMF; k++) Sf[k] = 0.0;
 #pragma unroll
             for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
+            const double t3 = exp(-6.0 * lf[D == 2 ? 6 : 3]);
+            const double sg2 = exp(-2.0 * lg[D == 2 ? 3 : 2]);
             for (int cy = ylo; cy <= yhi; cy++) {
                 int xa, xb;
                 if (!row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
                 double e[4], h[3];
-                {
-                    double lf[NF], lg[NG];
-#pragma unroll
-                    for (int j = 0; j < NF; j++) lf[j] = sf.lam[j] + sf.t * sf.del[j];
-#pragma unroll
-                    for (int j = 0; j < NG; j++) lg[j] = sg.lam[j] + sg.t * sg.del[j];
-                    row_poly<D>(lf, lg, y, e, h);
-                }
-                double f, r, s2, t3, gv, rg, sg2;
-                row_start(e, h, (double)xa - ux, f, r, s2, t3, gv, rg, sg2);
+                row_poly<D>(lf, lg, y, e, h);
+                double f, r, s2, gv, rg;
+                row_start(e, h, (double)xa - ux, f, r, s2, gv, rg);
                 double Rf[7], Rg[5];
 #pragma unroll
                 for (int k = 0; k < 7; k++) Rf[k] = 0.0;
@@ -800,12 +825,12 @@ __global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buff
                     for (int k = 0; k < NMG; k++) Sg[k] += Rg[k];
                 }
             }
-            if (sf.phase < 2) {
-                int r = species_update<D, NF, NMF>(sf, Sf, mf, RT, ph.tol, ph.maxit);
+            if (sg.phase < 2) {
+                int r = species_update<D, NG, NMG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
                 if (r < 0) fail = r;
             }
-            if (sg.phase < 2 && !fail) {
-                int r = species_update<D, NG, NMG>(sg, Sg, mg, RT, ph.tol, ph.maxit);
+            if (sf.phase < 2 && !fail) {
+                int r = species_update<D, NF, NMF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
                 if (r < 0) fail = r;
             }
         }
@@ -817,14 +842,21 @@ __global__ void __launch_bounds__(256) k_epr(Geom g, Phys ph, const T *mom, Buff
             const long long plane = (long long)ti.wx * ti.wy * TILE_N;
             double *P = (double *)b.scratch + ti.base;
             int q = 0;
+            double lf[NF], lg[NG];
+#pragma unroll
+            for (int j = 0; j < NF; j++) lf[j] = sf.v.lam(j);
+#pragma unroll
+            for (int j = 0; j < NG; j++) lg[j] = sg.v.lam(j);
+            const double t3 = exp(-6.0 * lf[D == 2 ? 6 : 3]);
+            const double sg2 = exp(-2.0 * lg[D == 2 ? 3 : 2]);
             for (int cy = ylo; cy <= yhi; cy++) {
                 int xa, xb;
                 if (!row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
                 double e[4], h[3];
-                row_poly<D>(sf.lam, sg.lam, y, e, h);
-                double f, r, s2, t3, gv, rg, sg2;
-                row_start(e, h, (double)xa - ux, f, r, s2, t3, gv, rg, sg2);
+                row_poly<D>(lf, lg, y, e, h);
+                double f, r, s2, gv, rg;
+                row_start(e, h, (double)xa - ux, f, r, s2, gv, rg);
                 long long rowslot = (long long)(cy - ti.oy) * ti.wx - ti.ox;
                 for (int cx = xa; cx <= xb; cx++) {
                     double wf = wsf * f, wg = wsg * gv;
@@ -894,9 +926,11 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
         int R = rn & 0xffff, Nr = rn >> 16;
         double mf[NF], mg[NG];
         collide_targets<T, D>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, cs.kn, cs.lim);
-        Species<NF> sf;
-        Species<NG> sg;
+        Species<NF, RegStore<NF>> sf;
+        Species<NG, RegStore<NG>> sg;
         species_init<D, NF, NG>(sf, sg, RT);
+        // residual scales RT^(-k/2) of basis order k (scale-free stopping test)
+        const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
         int fail = 0;
         while (!fail && (sf.phase < 2 || sg.phase < 2)) {
             cs.pass++;
@@ -906,9 +940,9 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
 #pragma unroll
             for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
 #pragma unroll
-            for (int j = 0; j < NF; j++) lf[j] = sf.lam[j] + sf.t * sf.del[j];
+            for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
 #pragma unroll
-            for (int j = 0; j < NG; j++) lg[j] = sg.lam[j] + sg.t * sg.del[j];
+            for (int j = 0; j < NG; j++) lg[j] = sg.at(j);
             for_each_point<D>(
                 ux, uy, R, Nr,
                 [&](double cx, double cy, double dC, int, int) {
@@ -928,12 +962,12 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
                     for (int k = 0; k < NMG; k++) Sg[k] += gv * m[k];
                 },
                 [&](int, int) {});
-            if (sf.phase < 2) {
-                int r = species_update<D, NF, NMF>(sf, Sf, mf, RT, ph.tol, ph.maxit);
+            if (sg.phase < 2) {
+                int r = species_update<D, NG, NMG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
                 if (r < 0) fail = r;
             }
-            if (sg.phase < 2 && !fail) {
-                int r = species_update<D, NG, NMG>(sg, Sg, mg, RT, ph.tol, ph.maxit);
+            if (sf.phase < 2 && !fail) {
+                int r = species_update<D, NF, NMF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
                 if (r < 0) fail = r;
             }
         }
@@ -954,9 +988,9 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
                     monomials<D, NF>(cx - ux, D == 2 ? cy - uy : 0.0, m);
                     double ef = 0.0, eg = 0.0;
 #pragma unroll
-                    for (int j = 0; j < NF; j++) ef += sf.lam[j] * m[j];
+                    for (int j = 0; j < NF; j++) ef += sf.v.lam(j) * m[j];
 #pragma unroll
-                    for (int j = 0; j < NG; j++) eg += sg.lam[j] * m[j];
+                    for (int j = 0; j < NG; j++) eg += sg.v.lam(j) * m[j];
                     double wf = wsf * (dC * exp(-(1.0 + ef)));
                     double wg = wsg * (dC * exp(-(1.0 + eg)));
                     q++;
