@@ -839,7 +839,6 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         } else {
             // final pass: moment fractions rho f', rho K RT g' (Eq. IIE3a)
             const double wsf = rho, wsg = rho * ph.K * RT;
-            const long long plane = (long long)ti.wx * ti.wy * TILE_N;
             double *P = (double *)b.scratch + ti.base;
             int q = 0;
             double lf[NF], lg[NG];
@@ -862,8 +861,8 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                     double wf = wsf * f, wg = wsg * gv;
                     long long slot = rowslot + cx;
                     if (ti.fmt == 0) {
-                        P[slot * TILE_N + l] = wf;
-                        P[plane + slot * TILE_N + l] = wg;
+                        P[(slot * TILE_N + l) * 2] = wf;
+                        P[(slot * TILE_N + l) * 2 + 1] = wg;
                     } else {
                         double c1 = (double)cx, c2 = (double)cy;
                         double mo[NM];
@@ -878,7 +877,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                             mo[8] = wg; mo[9] = c1 * wg; mo[10] = c2 * wg;
                         }
 #pragma unroll
-                        for (int k = 0; k < NM; k++) P[k * plane + slot * TILE_N + l] = mo[k];
+                        for (int k = 0; k < NM; k++) P[(slot * TILE_N + l) * NM + k] = mo[k];
                     }
                     f *= r; r *= s2; s2 *= t3;
                     gv *= rg; rg *= sg2;
@@ -975,7 +974,6 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
             flag_fail(b.flags, fail, step, s);
         } else {
             const double wsf = rho, wsg = rho * ph.K * RT;
-            const long long plane = (long long)ti.wx * ti.wy * TILE_N;
             double *P = (double *)b.scratch + ti.base;
             double acc[NM];
 #pragma unroll
@@ -1009,7 +1007,7 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
                     long long slot = (long long)(dy - ti.oy) * ti.wx + (dx - ti.ox);
 #pragma unroll
                     for (int k = 0; k < NM; k++) {
-                        P[k * plane + slot * TILE_N + l] = acc[k];
+                        P[(slot * TILE_N + l) * NM + k] = acc[k];
                         acc[k] = 0.0;
                     }
                 });
@@ -1026,91 +1024,181 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
 
 // ---------------------------------------------------------------------------
 // moment-streaming gather, Eq. (IIE3b)
+//
+// One workgroup per 16x16 (2D) or 256x1 (1D) destination tile; one thread per
+// destination cell.  Every destination scans the tile's window of landing
+// displacements d; the source of displacement d is x - d (wrapped on periodic
+// axes, mirrored across slip walls, which reflects the path specularly).  The
+// descriptors of the sources a chunk of window rows needs (velocity, radius,
+// scratch record address, mirror flags) are staged in LDS once per
+// workgroup, so the per-candidate work is the exact disk test of the source's
+// stencil (the same FP64 predicate its reconstruction used) and, on a hit, one
+// coalesced read of the moment fractions.
 // ---------------------------------------------------------------------------
+constexpr int G_CAP = 1792;   // staged sources per chunk (LDS: 28 B each)
+
+struct Resolved {
+    long long s;    // padded source index, -1 if none
+    int fx, fy;     // 1 if the path is mirrored in x / y
+};
+
+template <int D>
+__device__ inline Resolved resolve_source(const Geom &g, int xr, int yr) {
+    Resolved r{-1, 0, 0};
+    int sx = xr, sy = yr;
+    if (g.bc[0] == LELBM_BC_PERIODIC) { sx %= g.nx; if (sx < 0) sx += g.nx; }
+    else if (sx < 0 && g.bc[0] == LELBM_BC_SLIPWALL) { sx = -1 - sx; r.fx = 1; }
+    else if (sx >= g.nx && g.bc[1] == LELBM_BC_SLIPWALL) { sx = 2 * g.nx - 1 - sx; r.fx = 1; }
+    if (sx < -g.wl || sx >= g.nx + g.wr) return r;
+    if (D == 2) {
+        if (g.bc[2] == LELBM_BC_PERIODIC) { sy %= g.ny; if (sy < 0) sy += g.ny; }
+        else if (sy < 0 && g.bc[2] == LELBM_BC_SLIPWALL) { sy = -1 - sy; r.fy = 1; }
+        else if (sy >= g.ny && g.bc[3] == LELBM_BC_SLIPWALL) { sy = 2 * g.ny - 1 - sy; r.fy = 1; }
+        if (sy < -g.wb || sy >= g.ny + g.wt) return r;
+    } else {
+        sy = 0;
+    }
+    r.s = (long long)(sy + g.wb) * g.sxn + (sx + g.wl);
+    return r;
+}
+
+// Adds the moment fractions of one arriving record; (cx, cy) is the
+// velocity after reflection; for pre-summed refined records the odd
+// components are mirrored.
+template <int D>
+__device__ inline void deposit_record(double *acc, const double *P, int fmt, int dx, int dy, int fx, int fy) {
+    constexpr int NM = Basis<D>::NMOM;
+    if (fmt == 0) {
+        const double2 w = *(const double2 *)P;
+        double cx = (double)dx, cy = (double)dy;
+        if (D == 1) {
+            acc[0] += w.x; acc[1] += cx * w.x; acc[2] += cx * cx * w.x; acc[3] += cx * cx * cx * w.x;
+            acc[4] += w.y; acc[5] += cx * w.y;
+        } else {
+            double cc = cx * cx + cy * cy;
+            acc[0] += w.x; acc[1] += cx * w.x; acc[2] += cy * w.x;
+            acc[3] += cx * cx * w.x; acc[4] += cx * cy * w.x; acc[5] += cy * cy * w.x;
+            acc[6] += cc * cx * w.x; acc[7] += cc * cy * w.x;
+            acc[8] += w.y; acc[9] += cx * w.y; acc[10] += cy * w.y;
+        }
+    } else {
+        double sx1 = fx ? -1.0 : 1.0, sy1 = fy ? -1.0 : 1.0;
+        if (D == 1) {
+            acc[0] += P[0]; acc[1] += sx1 * P[1]; acc[2] += P[2];
+            acc[3] += sx1 * P[3]; acc[4] += P[4]; acc[5] += sx1 * P[5];
+        } else {
+            acc[0] += P[0]; acc[1] += sx1 * P[1]; acc[2] += sy1 * P[2];
+            acc[3] += P[3]; acc[4] += sx1 * sy1 * P[4]; acc[5] += P[5];
+            acc[6] += sx1 * P[6]; acc[7] += sy1 * P[7];
+            acc[8] += P[8]; acc[9] += sx1 * P[9]; acc[10] += sy1 * P[10];
+        }
+    }
+    (void)NM;
+}
+
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
     constexpr int NM = Basis<D>::NMOM;
+    __shared__ double s_ux[G_CAP], s_uy[G_CAP];
+    __shared__ long long s_a0[G_CAP];
+    __shared__ int s_meta[G_CAP];
     __shared__ int s_err;
     if (threadIdx.x == 0) s_err = b.flags->err;
     __syncthreads();
     if (s_err) return;
-    int t = blockIdx.x;
-    int x = (t % g.dtx) * g.tx + threadIdx.x % g.tx;
-    int y = (t / g.dtx) * g.ty + threadIdx.x / g.tx;
-    unsigned long long hits = 0;
-    if (x < g.nx && y < g.ny) {
+    const int t = blockIdx.x;
+    const int tx0 = (t % g.dtx) * g.tx, ty0 = (t / g.dtx) * g.ty;
+    const int lx = threadIdx.x % g.tx, ly = threadIdx.x / g.tx;
+    const int x = tx0 + lx, y = ty0 + ly;
+    const bool mine = x < g.nx && y < g.ny;
     const DWin w = b.dwin[t];
+    const double *SCR = (const double *)b.scratch;
     double acc[NM];
 #pragma unroll
     for (int k = 0; k < NM; k++) acc[k] = 0.0;
-    const bool perx = g.bc[0] == LELBM_BC_PERIODIC, pery = D == 2 && g.bc[2] == LELBM_BC_PERIODIC;
-    for (int dy = w.hiy; dy >= w.loy; dy--) {
-        int sy = y - dy;
-        int fy = 1;   // sign of the y velocity after reflection
-        if (D == 2) {
-            if (pery) { sy %= g.ny; if (sy < 0) sy += g.ny; }
-            if (sy < 0 && g.bc[2] == LELBM_BC_SLIPWALL) { sy = -1 - sy; fy = -1; }
-            else if (sy >= g.ny && g.bc[3] == LELBM_BC_SLIPWALL) { sy = 2 * g.ny - 1 - sy; fy = -1; }
-            if (sy < -g.wb || sy >= g.ny + g.wt) continue;
-        }
-        for (int dx = w.hix; dx >= w.lox; dx--) {
-            int sx = x - dx;
-            int fx = 1;
-            if (perx) { sx %= g.nx; if (sx < 0) sx += g.nx; }
-            if (sx < 0 && g.bc[0] == LELBM_BC_SLIPWALL) { sx = -1 - sx; fx = -1; }
-            else if (sx >= g.nx && g.bc[1] == LELBM_BC_SLIPWALL) { sx = 2 * g.nx - 1 - sx; fx = -1; }
-            if (sx < -g.wl || sx >= g.nx + g.wr) continue;
-            int px = sx + g.wl, py = D == 2 ? sy + g.wb : 0;
-            long long s = (long long)py * g.sxn + px;
-            int rn = b.desc_rn[s];
-            if (rn < 0) continue;
-            // displacement in the source's own frame (undo the mirror)
-            int rdx = fx * dx, rdy = D == 2 ? fy * dy : 0;
-            double ux = b.desc_u[s];
-            double rr = (rn & 0xffff) + 0.5;
-            bool in;
-            if (D == 2) in = in_disk2((double)rdx, (double)rdy, ux, b.desc_u[g.ns + s], rr);
-            else in = in_disk1((double)rdx, ux, rr);
-            if (!in) continue;
-            int st = (px / g.tx) + (py / g.ty) * g.ntx;
-            int loc = (px % g.tx) + (py % g.ty) * g.tx;
-            const TileInfo ti = b.tiles[st];
-            long long slot = (long long)(rdy - ti.oy) * ti.wx + (rdx - ti.ox);
-            const long long plane = (long long)ti.wx * ti.wy * TILE_N;
-            const double *P = (const double *)b.scratch + ti.base + slot * TILE_N + loc;
-            hits++;
-            if (ti.fmt == 0) {
-                double wf = P[0], wg = P[plane];
-                double cx = (double)dx, cy = (double)dy;   // velocity after reflection
-                if (D == 1) {
-                    acc[0] += wf; acc[1] += cx * wf; acc[2] += cx * cx * wf; acc[3] += cx * cx * cx * wf;
-                    acc[4] += wg; acc[5] += cx * wg;
-                } else {
-                    double cc = cx * cx + cy * cy;
-                    acc[0] += wf; acc[1] += cx * wf; acc[2] += cy * wf;
-                    acc[3] += cx * cx * wf; acc[4] += cx * cy * wf; acc[5] += cy * cy * wf;
-                    acc[6] += cc * cx * wf; acc[7] += cc * cy * wf;
-                    acc[8] += wg; acc[9] += cx * wg; acc[10] += cy * wg;
+    unsigned long long hits = 0;
+    const int RW = g.tx + (w.hix - w.lox);          // staged region width
+    int rows = G_CAP / RW - (g.ty - 1);             // window rows per chunk
+    if (w.lox <= w.hix && rows >= 1) {
+        for (int dy0 = w.hiy; dy0 >= w.loy; dy0 -= rows) {
+            const int dy1 = max(w.loy, dy0 - rows + 1);
+            const int RH = g.ty + (dy0 - dy1);
+            const int rx0 = tx0 - w.hix, ry0 = ty0 - dy0;
+            __syncthreads();
+            for (int i = threadIdx.x; i < RW * RH; i += 256) {
+                Resolved rs = resolve_source<D>(g, rx0 + i % RW, ry0 + i / RW);
+                int meta = -1;
+                if (rs.s >= 0) {
+                    int rn = b.desc_rn[rs.s];
+                    if (rn >= 0) {
+                        long long s = rs.s;
+                        int px = (int)(s % g.sxn), py = (int)(s / g.sxn);
+                        int st = (px / g.tx) + (py / g.ty) * g.ntx;
+                        int loc = (px % g.tx) + (py % g.ty) * g.tx;
+                        const TileInfo ti = b.tiles[st];
+                        long long recsz = ti.fmt ? NM : 2;
+                        s_a0[i] = ti.base + (long long)loc * recsz -
+                                  ((long long)ti.oy * ti.wx + ti.ox) * TILE_N * recsz;
+                        s_ux[i] = b.desc_u[s];
+                        s_uy[i] = b.desc_u[g.ns + s];
+                        meta = (rn & 0xff) | (rs.fx << 8) | (rs.fy << 9) | (ti.fmt << 10) | (ti.wx << 11);
+                    }
                 }
-            } else {
-                // pre-summed moments of refined children; reflect odd components
-                if (D == 1) {
-                    double sx1 = fx;
-                    acc[0] += P[0]; acc[1] += sx1 * P[plane]; acc[2] += P[2 * plane];
-                    acc[3] += sx1 * P[3 * plane]; acc[4] += P[4 * plane]; acc[5] += sx1 * P[5 * plane];
-                } else {
-                    double sx1 = fx, sy1 = fy;
-                    acc[0] += P[0]; acc[1] += sx1 * P[plane]; acc[2] += sy1 * P[2 * plane];
-                    acc[3] += P[3 * plane]; acc[4] += sx1 * sy1 * P[4 * plane]; acc[5] += P[5 * plane];
-                    acc[6] += sx1 * P[6 * plane]; acc[7] += sy1 * P[7 * plane];
-                    acc[8] += P[8 * plane]; acc[9] += sx1 * P[9 * plane]; acc[10] += sy1 * P[10 * plane];
+                s_meta[i] = meta;
+            }
+            __syncthreads();
+            if (mine) {
+                for (int dy = dy0; dy >= dy1; dy--) {
+                    const int rowbase = (ly + (dy0 - dy)) * RW + lx + w.hix;
+                    for (int dx = w.hix; dx >= w.lox; dx--) {
+                        const int i = rowbase - dx;
+                        const int meta = s_meta[i];
+                        if (meta < 0) continue;
+                        const int fx = (meta >> 8) & 1, fy = (meta >> 9) & 1, fmt = (meta >> 10) & 1;
+                        const int rdx = fx ? -dx : dx, rdy = fy ? -dy : dy;
+                        const double rr = (meta & 0xff) + 0.5;
+                        bool in = D == 2 ? in_disk2((double)rdx, (double)rdy, s_ux[i], s_uy[i], rr)
+                                         : in_disk1((double)rdx, s_ux[i], rr);
+                        if (!in) continue;
+                        const long long recsz = fmt ? NM : 2;
+                        const long long wx = meta >> 11;
+                        const double *P = SCR + s_a0[i] + ((long long)rdy * wx + rdx) * TILE_N * recsz;
+                        hits++;
+                        deposit_record<D>(acc, P, fmt, dx, dy, fx, fy);
+                    }
                 }
             }
         }
+    } else if (w.lox <= w.hix && mine) {
+        // window too wide to stage: descriptors straight from global memory
+        for (int dy = w.hiy; dy >= w.loy; dy--) {
+            for (int dx = w.hix; dx >= w.lox; dx--) {
+                Resolved rs = resolve_source<D>(g, x - dx, y - dy);
+                if (rs.s < 0) continue;
+                const long long s = rs.s;
+                const int rn = b.desc_rn[s];
+                if (rn < 0) continue;
+                const int rdx = rs.fx ? -dx : dx, rdy = rs.fy ? -dy : dy;
+                const double rr = (rn & 0xffff) + 0.5;
+                bool in = D == 2 ? in_disk2((double)rdx, (double)rdy, b.desc_u[s], b.desc_u[g.ns + s], rr)
+                                 : in_disk1((double)rdx, b.desc_u[s], rr);
+                if (!in) continue;
+                int px = (int)(s % g.sxn), py = (int)(s / g.sxn);
+                int st = (px / g.tx) + (py / g.ty) * g.ntx;
+                int loc = (px % g.tx) + (py % g.ty) * g.tx;
+                const TileInfo ti = b.tiles[st];
+                const long long recsz = ti.fmt ? NM : 2;
+                long long slot = (long long)(rdy - ti.oy) * ti.wx + (rdx - ti.ox);
+                const double *P = SCR + ti.base + (slot * TILE_N + loc) * recsz;
+                hits++;
+                deposit_record<D>(acc, P, ti.fmt, dx, dy, rs.fx, rs.fy);
+            }
+        }
     }
-    long long o = (long long)(y + g.wb) * g.sxn + (x + g.wl);
+    if (mine) {
+        long long o = (long long)(y + g.wb) * g.sxn + (x + g.wl);
 #pragma unroll
-    for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = (T)acc[k];
+        for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = (T)acc[k];
     }
     for (int off = 32; off > 0; off >>= 1) hits += __shfl_xor(hits, off);
     if ((threadIdx.x & 63) == 0 && hits) atomicAdd(&b.stats->arrivals, hits);
