@@ -1036,6 +1036,7 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
 // coalesced read of the moment fractions.
 // ---------------------------------------------------------------------------
 constexpr int G_CAP = 1792;   // staged sources per chunk (LDS: 28 B each)
+constexpr int GU = 8;         // candidates per batch in the gather
 
 struct Resolved {
     long long s;    // padded source index, -1 if none
@@ -1150,21 +1151,63 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
             if (mine) {
                 for (int dy = dy0; dy >= dy1; dy--) {
                     const int rowbase = (ly + (dy0 - dy)) * RW + lx + w.hix;
-                    for (int dx = w.hix; dx >= w.lox; dx--) {
-                        const int i = rowbase - dx;
-                        const int meta = s_meta[i];
-                        if (meta < 0) continue;
-                        const int fx = (meta >> 8) & 1, fy = (meta >> 9) & 1, fmt = (meta >> 10) & 1;
-                        const int rdx = fx ? -dx : dx, rdy = fy ? -dy : dy;
-                        const double rr = (meta & 0xff) + 0.5;
-                        bool in = D == 2 ? in_disk2((double)rdx, (double)rdy, s_ux[i], s_uy[i], rr)
-                                         : in_disk1((double)rdx, s_ux[i], rr);
-                        if (!in) continue;
-                        const long long recsz = fmt ? NM : 2;
-                        const long long wx = meta >> 11;
-                        const double *P = SCR + s_a0[i] + ((long long)rdy * wx + rdx) * TILE_N * recsz;
-                        hits++;
-                        deposit_record<D>(acc, P, fmt, dx, dy, fx, fy);
+                    // candidates in batches of GU so that the LDS and global
+                    // reads of a batch are in flight together
+                    for (int dxb = w.hix; dxb >= w.lox; dxb -= GU) {
+                        int meta[GU], ii[GU];
+                        double cux[GU], cuy[GU];
+                        const double *pp[GU];
+#pragma unroll
+                        for (int u = 0; u < GU; u++) {
+                            const bool ok = dxb - u >= w.lox;
+                            ii[u] = rowbase - (ok ? dxb - u : dxb);
+                            meta[u] = s_meta[ii[u]];
+                            if (!ok) meta[u] = -1;
+                            cux[u] = s_ux[ii[u]];
+                            cuy[u] = s_uy[ii[u]];
+                        }
+#pragma unroll
+                        for (int u = 0; u < GU; u++) {
+                            const int dx = dxb - u, m = meta[u];
+                            pp[u] = nullptr;
+                            if (m < 0) continue;
+                            const int fx = (m >> 8) & 1, fy = (m >> 9) & 1;
+                            const int rdx = fx ? -dx : dx, rdy = fy ? -dy : dy;
+                            const double rr = (m & 0xff) + 0.5;
+                            bool in = D == 2 ? in_disk2((double)rdx, (double)rdy, cux[u], cuy[u], rr)
+                                             : in_disk1((double)rdx, cux[u], rr);
+                            if (!in) continue;
+                            const long long recsz = ((m >> 10) & 1) ? NM : 2;
+                            pp[u] = SCR + s_a0[ii[u]] + ((long long)rdy * (m >> 11) + rdx) * TILE_N * recsz;
+                        }
+                        double2 wv[GU];
+#pragma unroll
+                        for (int u = 0; u < GU; u++) {
+                            wv[u] = make_double2(0.0, 0.0);
+                            if (pp[u] && !((meta[u] >> 10) & 1)) wv[u] = *(const double2 *)pp[u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < GU; u++) {
+                            if (!pp[u]) continue;
+                            const int dx = dxb - u, m = meta[u];
+                            hits++;
+                            if ((m >> 10) & 1) {
+                                deposit_record<D>(acc, pp[u], 1, dx, dy, (m >> 8) & 1, (m >> 9) & 1);
+                            } else {
+                                double cx = (double)dx, cy = (double)dy;
+                                if (D == 1) {
+                                    acc[0] += wv[u].x; acc[1] += cx * wv[u].x; acc[2] += cx * cx * wv[u].x;
+                                    acc[3] += cx * cx * cx * wv[u].x; acc[4] += wv[u].y; acc[5] += cx * wv[u].y;
+                                } else {
+                                    double cc = cx * cx + cy * cy;
+                                    acc[0] += wv[u].x; acc[1] += cx * wv[u].x; acc[2] += cy * wv[u].x;
+                                    acc[3] += cx * cx * wv[u].x; acc[4] += cx * cy * wv[u].x;
+                                    acc[5] += cy * cy * wv[u].x; acc[6] += cc * cx * wv[u].x;
+                                    acc[7] += cc * cy * wv[u].x; acc[8] += wv[u].y; acc[9] += cx * wv[u].y;
+                                    acc[10] += cy * wv[u].y;
+                                }
+                            }
+                        }
                     }
                 }
             }
