@@ -144,6 +144,14 @@ int lelbm_read_moments_device(const lelbm_ctx *c, void *dev_out);
  * step (0-based within the failing lelbm_step call) of the first failure. */
 int lelbm_last_failure(const lelbm_ctx *c, long *node, int *step);
 
+/* Why the reconstruction of the failing cell failed (after LELBM_EEPR):
+ * reason 1 non-finite populations at the first evaluation, 2 line search
+ * exhausted (30 halvings), 3 Cholesky breakdown in the polishing update,
+ * 4 Newton iteration cap, 5 Cholesky breakdown in a Newton step; 0 when the
+ * failure was not in the Newton solve (e.g. rho <= 0 or RT <= 0).  species:
+ * 0 fluon, 1 phonon, -1 none.  residual: last scaled moment residual. */
+int lelbm_last_failure_detail(const lelbm_ctx *c, int *reason, int *species, double *residual);
+
 /* Per-kernel timing: when enabled, lelbm_step records HIP events around each
  * kernel and lelbm_kernel_times returns accumulated milliseconds and launch
  * counts for: [0] pad fill, [1] stencil pre-pass, [2] tile scan,

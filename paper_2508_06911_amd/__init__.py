@@ -83,6 +83,8 @@ def lib():
         L.lelbm_read_moments.argtypes = [vp, dp]
         L.lelbm_read_moments_device.argtypes = [vp, vp]
         L.lelbm_last_failure.argtypes = [vp, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_int)]
+        L.lelbm_last_failure_detail.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(ctypes.c_double)]
         L.lelbm_set_timing.argtypes = [vp, ctypes.c_int]
         L.lelbm_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_long), ctypes.c_int]
         L.lelbm_memory.argtypes = [vp, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
@@ -175,8 +177,15 @@ class Lelbm:
         code = lib().lelbm_step(self._h, n, ctypes.byref(st))
         if code != OK:
             node, stp = self.last_failure()
-            raise LelbmError(code, "%s at cell %d, step %d" % (lib().lelbm_strerror(code).decode(), node, stp))
+            why, sp, res = self.last_failure_detail()
+            raise LelbmError(code, "%s at cell %d, step %d (reason %d, species %d, residual %.3e)"
+                             % (lib().lelbm_strerror(code).decode(), node, stp, why, sp, res))
         return st.as_dict()
+
+    def last_failure_detail(self):
+        why, sp, res = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        lib().lelbm_last_failure_detail(self._h, ctypes.byref(why), ctypes.byref(sp), ctypes.byref(res))
+        return why.value, sp.value, res.value
 
     def step_nostats(self, n=1):
         _check(lib().lelbm_step(self._h, n, None))

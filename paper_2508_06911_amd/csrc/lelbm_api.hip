@@ -31,6 +31,8 @@ struct lelbm_ctx {
     int cur;                 // state buffer holding the current moments
     long last_fail_node;
     int last_fail_step;
+    int last_fail_detail, last_fail_species;
+    double last_fail_residual;
     int timing;
     hipEvent_t ev[2];
     double kms[6];
@@ -103,7 +105,7 @@ static int validate(const lelbm_params *p) {
     if (!(p->newton_tol > 0.0) || p->newton_max_it < 1) return LELBM_EINVAL;
     if (p->precision != LELBM_FP64 && p->precision != LELBM_MIXED) return LELBM_EINVAL;
     if (p->guess != LELBM_GUESS_EQ && p->guess != LELBM_GUESS_MLP) return LELBM_EINVAL;
-    if (p->precision == LELBM_MIXED || p->guess == LELBM_GUESS_MLP) return LELBM_EINVAL;
+    if (p->guess == LELBM_GUESS_MLP) return LELBM_EINVAL;
     if (p->solid) return LELBM_EINVAL;
     for (int f = 0; f < 4; f++)
         if (p->bc[f] < LELBM_BC_PERIODIC || p->bc[f] > LELBM_BC_SLIPWALL) return LELBM_EINVAL;
@@ -135,6 +137,7 @@ static void free_ctx(lelbm_ctx *c) {
 static int reset_flags(lelbm_ctx *c) {
     Flags f;
     f.err = 0; f.step = -1; f.node = LLONG_MAX; f.need = 0;
+    f.detail = 0; f.species = -1; f.residual = 0.0;
     HIPCHECK(hipMemcpyAsync(c->b.flags, &f, sizeof(Flags), hipMemcpyHostToDevice, c->stream));
     return LELBM_OK;
 }
@@ -168,6 +171,9 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     c->cur = 0;
     c->last_fail_node = -1;
     c->last_fail_step = -1;
+    c->last_fail_detail = 0;
+    c->last_fail_species = -1;
+    c->last_fail_residual = 0.0;
     c->timing = 0;
     c->evused = 0;
     for (int k = 0; k < 6; k++) { c->kms[k] = 0; c->klaunch[k] = 0; }
@@ -189,6 +195,9 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     Phys &ph = c->ph;
     ph.K = p->K; ph.omega_f = p->omega_f; ph.omega_b = p->omega_b; ph.omega_h = p->omega_h;
     ph.n_conf = p->n_conf; ph.r_min = p->r_min; ph.tol = p->newton_tol; ph.maxit = p->newton_max_it;
+    // the mixed path stores FP32 moment fractions (relative rounding 6e-8), so
+    // converging the multipliers beyond 1e-8 buys nothing
+    if (p->precision == LELBM_MIXED && ph.tol < MIXED_TOL_FLOOR) ph.tol = MIXED_TOL_FLOOR;
     ph.kn_limiter = p->kn_limiter; ph.kn_lo = p->kn_lo; ph.kn_hi = p->kn_hi; ph.omega_H = p->omega_H;
     ph.kn_lo_lin = pow(10.0, p->kn_lo); ph.kn_hi_lin = pow(10.0, p->kn_hi);
     ph.in_rho = p->in_rho; ph.in_u[0] = p->in_u[0]; ph.in_u[1] = p->dim == 2 ? p->in_u[1] : 0.0;
@@ -384,6 +393,9 @@ extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
         if (f.err != ERR_OVERFLOW) {
             c->last_fail_node = (long)f.node;
             c->last_fail_step = f.step;
+            c->last_fail_detail = f.detail;
+            c->last_fail_species = f.species;
+            c->last_fail_residual = f.residual;
             return f.err;
         }
         if ((r = grow_scratch(c, f.need)) != LELBM_OK) return r;
@@ -464,6 +476,14 @@ extern "C" int lelbm_last_failure(const lelbm_ctx *c, long *node, int *step) {
     if (!c) return LELBM_EINVAL;
     if (node) *node = c->last_fail_node;
     if (step) *step = c->last_fail_step;
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_last_failure_detail(const lelbm_ctx *c, int *reason, int *species, double *residual) {
+    if (!c) return LELBM_EINVAL;
+    if (reason) *reason = c->last_fail_detail;
+    if (species) *species = c->last_fail_species;
+    if (residual) *residual = c->last_fail_residual;
     return LELBM_OK;
 }
 

@@ -14,6 +14,7 @@ constexpr int TILE_N = 256;
 constexpr int MAX_REFINE = 3;       // supported stencil refinement levels
 constexpr int MAX_RADIUS = 128;     // largest acoustic radius (RT up to ~1000)
 constexpr double MAX_SPEED = 2048.0;  // largest |u| component in cells per step
+constexpr double MIXED_TOL_FLOOR = 1e-8;  // Newton tolerance of the mixed path (records are FP32)
 
 // Internal error code: population scratch too small (the host grows it and
 // repeats the step).
@@ -47,6 +48,9 @@ struct Flags {
     int step;                // step index of the failure
     long long node;          // smallest failing cell index of that kernel
     long long need;          // scratch elements needed (ERR_OVERFLOW)
+    int detail;              // reason of an LELBM_EEPR failure (see lelbm_last_failure_detail)
+    int species;             // 0 fluon, 1 phonon
+    double residual;         // last scaled moment residual of the failing solve
 };
 
 struct DevStats {

@@ -79,12 +79,19 @@ __device__ inline double dist2(double cx, double cy, double ux, double uy) {
     return sqrt(a * a + b * b);
 }
 
-__device__ inline void flag_fail(Flags *fl, int code, int step, long long node) {
+__device__ inline void flag_fail(Flags *fl, int code, int step, long long node, int detail = 0, int species = -1,
+                                 double residual = 0.0) {
     if (atomicCAS(&fl->err, 0, code) == 0) {
         fl->step = step;
+        fl->detail = detail;
+        fl->species = species;
+        fl->residual = residual;
     }
     if (fl->err == code) atomicMin((unsigned long long *)&fl->node, (unsigned long long)node);
 }
+
+// Reasons of a failed reconstruction (lelbm_last_failure_detail).
+enum { FAIL_NONFINITE = 1, FAIL_LINESEARCH = 2, FAIL_CHOL_POLISH = 3, FAIL_MAXIT = 4, FAIL_CHOL_STEP = 5 };
 
 __device__ inline void atomic_max_pos(unsigned long long *a, double v) {
     atomicMax(a, (unsigned long long)__double_as_longlong(v));
@@ -444,6 +451,7 @@ template <int NB, class Store> struct Species {
     double t, dec, phi;
     int phase;        // 0: first evaluation, 1: iterating, 2: polished
     int nit, ls;
+    double res;       // last scaled residual
     __device__ double at(int j) { return v.lam(j) + t * v.del(j); }   // multipliers of the current pass
 };
 
@@ -463,12 +471,12 @@ __device__ inline int species_update(Species<NB, Store> &sp, const double *S, co
     }
     fin = fin && isfinite(phit);
     if (sp.phase == 0) {
-        if (!fin) return LELBM_EEPR;
+        if (!fin) return -FAIL_NONFINITE;
         sp.phase = 1;
     } else {
         if (!(fin && (sp.dec <= 1e-8 || phit <= sp.phi - 1e-4 * sp.t * sp.dec))) {
             sp.t *= 0.5;
-            if (++sp.ls > 30) return LELBM_EEPR;
+            if (++sp.ls > 30) return -FAIL_LINESEARCH;
             return 0;
         }
         sp.nit++;
@@ -483,17 +491,18 @@ __device__ inline int species_update(Species<NB, Store> &sp, const double *S, co
         double v = fabs(r[j]) * isc[order_of<D>(j)];
         res = v > res ? v : res;
     }
+    sp.res = res;
     double dl[NB];
     if (res <= tol) {
-        if (!hess_solve<D, NB>(S, r, dl)) return LELBM_EEPR;
+        if (!hess_solve<D, NB>(S, r, dl)) return -FAIL_CHOL_POLISH;
 #pragma unroll
         for (int j = 0; j < NB; j++) { sp.v.lam(j) += dl[j]; sp.v.del(j) = 0.0; }
         sp.nit++;
         sp.phase = 2;
         return 1;
     }
-    if (sp.nit >= maxit) return LELBM_EEPR;
-    if (!hess_solve<D, NB>(S, r, dl)) return LELBM_EEPR;
+    if (sp.nit >= maxit) return -FAIL_MAXIT;
+    if (!hess_solve<D, NB>(S, r, dl)) return -FAIL_CHOL_STEP;
     double dec = 0.0;
 #pragma unroll
     for (int j = 0; j < NB; j++) { sp.v.del(j) = dl[j]; dec += r[j] * dl[j]; }
@@ -624,6 +633,7 @@ __device__ inline void species_init(Species<NF, SF> &sf, Species<NG, SG> &sg, do
     else { sf.v.lam(3) = l2; sf.v.lam(5) = l2; sg.v.lam(3) = l2; sg.v.lam(5) = l2; }
     sf.t = sg.t = 0.0; sf.dec = sg.dec = 0.0; sf.phi = sg.phi = 0.0;
     sf.phase = sg.phase = 0; sf.nit = sg.nit = 0; sf.ls = sg.ls = 0;
+    sf.res = sg.res = 0.0;
 }
 
 // Per-cell statistics, reduced over the wavefront, one atomic per wave.
@@ -724,24 +734,43 @@ __device__ inline void row_poly(const double *lf, const double *lg, double y, do
 // third difference of the fluon exponent (6 e3) and the second difference of
 // the phonon exponent (2 h2) do not depend on the row; their exponentials
 // t3 and sg2 are computed once per pass.
-__device__ inline void row_start(const double *e, const double *h, double x0, double &f, double &r, double &s2,
-                                 double &gv, double &rg) {
+template <typename W>
+__device__ inline void row_start(const double *e, const double *h, double x0, W &f, W &r, W &s2, W &gv, W &rg) {
     double E0 = e[0] + x0 * (e[1] + x0 * (e[2] + x0 * e[3]));
     double a2 = e[2] + 3.0 * e[3] * x0;
     double a1 = e[1] + x0 * (2.0 * e[2] + 3.0 * e[3] * x0);
-    f = exp(E0);
-    r = exp(a1 + a2 + e[3]);
-    s2 = exp(2.0 * a2 + 6.0 * e[3]);
     double H0 = h[0] + x0 * (h[1] + x0 * h[2]);
     double b1 = h[1] + 2.0 * h[2] * x0;
-    gv = exp(H0);
-    rg = exp(b1 + h[2]);
+    if (sizeof(W) == 8) {
+        f = exp(E0);
+        r = exp(a1 + a2 + e[3]);
+        s2 = exp(2.0 * a2 + 6.0 * e[3]);
+        gv = exp(H0);
+        rg = exp(b1 + h[2]);
+    } else {
+        f = expf((float)E0);
+        r = expf((float)(a1 + a2 + e[3]));
+        s2 = expf((float)(2.0 * a2 + 6.0 * e[3]));
+        gv = expf((float)H0);
+        rg = expf((float)(b1 + h[2]));
+    }
+}
+
+template <typename W> __device__ inline W wexp(double v) {
+    if (sizeof(W) == 8) return exp(v);
+    return expf((float)v);
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, Buffers b, int step) {
     using BS = Basis<D>;
     constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
+    // Per-point arithmetic stays FP64 in both paths: without packed FP32 math
+    // an FP32 multiply-add costs the same issue slot as an FP64 one, and the
+    // product recurrence in FP32 loses up to 1e-4 relative accuracy along long
+    // rows (its rounding compounds cubically), which stalls the Newton line
+    // search.  The mixed path gains from FP32 state, records and streaming.
+    using W = double;
     __shared__ double s_lamf[NF * TILE_N], s_delf[NF * TILE_N], s_lamg[NG * TILE_N], s_delg[NG * TILE_N];
     __shared__ int s_err;
     if (threadIdx.x == 0) s_err = b.flags->err;
@@ -773,7 +802,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         species_init<D, NF, NG>(sf, sg, RT);
         // residual scales RT^(-k/2) of basis order k (scale-free stopping test)
         const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
-        int fail = 0;
+        int fail = 0, fsp = -1;
         while (!fail && (sf.phase < 2 || sg.phase < 2)) {
             cs.pass++;
             double Sf[NMF], Sg[NMG], lf[NF], lg[NG];
@@ -785,24 +814,24 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
             for (int k = 0; k < NMF; k++) Sf[k] = 0.0;
 #pragma unroll
             for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
-            const double t3 = exp(-6.0 * lf[D == 2 ? 6 : 3]);
-            const double sg2 = exp(-2.0 * lg[D == 2 ? 3 : 2]);
+            const W t3 = wexp<W>(-6.0 * lf[D == 2 ? 6 : 3]);
+            const W sg2 = wexp<W>(-2.0 * lg[D == 2 ? 3 : 2]);
             for (int cy = ylo; cy <= yhi; cy++) {
                 int xa, xb;
                 if (!row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
                 double e[4], h[3];
                 row_poly<D>(lf, lg, y, e, h);
-                double f, r, s2, gv, rg;
-                row_start(e, h, (double)xa - ux, f, r, s2, gv, rg);
-                double Rf[7], Rg[5];
+                W f, r, s2, gv, rg;
+                row_start<W>(e, h, (double)xa - ux, f, r, s2, gv, rg);
+                W Rf[7], Rg[5];
 #pragma unroll
-                for (int k = 0; k < 7; k++) Rf[k] = 0.0;
+                for (int k = 0; k < 7; k++) Rf[k] = 0;
 #pragma unroll
-                for (int k = 0; k < 5; k++) Rg[k] = 0.0;
+                for (int k = 0; k < 5; k++) Rg[k] = 0;
                 for (int cx = xa; cx <= xb; cx++) {
-                    double x = (double)cx - ux;
-                    double x2 = x * x, x3 = x2 * x, x4 = x2 * x2, x5 = x4 * x, x6 = x3 * x3;
+                    W x = (W)((double)cx - ux);
+                    W x2 = x * x, x3 = x2 * x, x4 = x2 * x2, x5 = x4 * x, x6 = x3 * x3;
                     Rf[0] += f; Rf[1] += f * x; Rf[2] += f * x2; Rf[3] += f * x3;
                     Rf[4] += f * x4; Rf[5] += f * x5; Rf[6] += f * x6;
                     Rg[0] += gv; Rg[1] += gv * x; Rg[2] += gv * x2; Rg[3] += gv * x3; Rg[4] += gv * x4;
@@ -815,62 +844,63 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
 #pragma unroll
                     for (int k = 1; k < 7; k++) py_[k] = py_[k - 1] * y;
 #pragma unroll
-                    for (int k = 0; k < NMF; k++) Sf[k] += py_[mono_b(k)] * Rf[mono_a(k)];
+                    for (int k = 0; k < NMF; k++) Sf[k] += py_[mono_b(k)] * (double)Rf[mono_a(k)];
 #pragma unroll
-                    for (int k = 0; k < NMG; k++) Sg[k] += py_[mono_b(k)] * Rg[mono_a(k)];
+                    for (int k = 0; k < NMG; k++) Sg[k] += py_[mono_b(k)] * (double)Rg[mono_a(k)];
                 } else {
 #pragma unroll
-                    for (int k = 0; k < NMF; k++) Sf[k] += Rf[k];
+                    for (int k = 0; k < NMF; k++) Sf[k] += (double)Rf[k];
 #pragma unroll
-                    for (int k = 0; k < NMG; k++) Sg[k] += Rg[k];
+                    for (int k = 0; k < NMG; k++) Sg[k] += (double)Rg[k];
                 }
             }
             if (sg.phase < 2) {
                 int r = species_update<D, NG, NMG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
-                if (r < 0) fail = r;
+                if (r < 0) { fail = -r; fsp = 1; }
             }
             if (sf.phase < 2 && !fail) {
                 int r = species_update<D, NF, NMF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
-                if (r < 0) fail = r;
+                if (r < 0) { fail = -r; fsp = 0; }
             }
         }
         if (fail) {
-            flag_fail(b.flags, fail, step, s);
+            flag_fail(b.flags, LELBM_EEPR, step, s, fail, fsp, fsp ? sg.res : sf.res);
         } else {
             // final pass: moment fractions rho f', rho K RT g' (Eq. IIE3a)
             const double wsf = rho, wsg = rho * ph.K * RT;
-            double *P = (double *)b.scratch + ti.base;
+            T *P = (T *)b.scratch + ti.base;
             int q = 0;
             double lf[NF], lg[NG];
 #pragma unroll
             for (int j = 0; j < NF; j++) lf[j] = sf.v.lam(j);
 #pragma unroll
             for (int j = 0; j < NG; j++) lg[j] = sg.v.lam(j);
-            const double t3 = exp(-6.0 * lf[D == 2 ? 6 : 3]);
-            const double sg2 = exp(-2.0 * lg[D == 2 ? 3 : 2]);
+            const W t3 = wexp<W>(-6.0 * lf[D == 2 ? 6 : 3]);
+            const W sg2 = wexp<W>(-2.0 * lg[D == 2 ? 3 : 2]);
+            const W wsfw = (W)wsf, wsgw = (W)wsg;
             for (int cy = ylo; cy <= yhi; cy++) {
                 int xa, xb;
                 if (!row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
                 double e[4], h[3];
                 row_poly<D>(lf, lg, y, e, h);
-                double f, r, s2, gv, rg;
-                row_start(e, h, (double)xa - ux, f, r, s2, gv, rg);
+                W f, r, s2, gv, rg;
+                row_start<W>(e, h, (double)xa - ux, f, r, s2, gv, rg);
                 long long rowslot = (long long)(cy - ti.oy) * ti.wx - ti.ox;
                 for (int cx = xa; cx <= xb; cx++) {
-                    double wf = wsf * f, wg = wsg * gv;
+                    W wf = wsfw * f, wg = wsgw * gv;
                     long long slot = rowslot + cx;
                     if (ti.fmt == 0) {
                         P[(slot * TILE_N + l) * 2] = wf;
                         P[(slot * TILE_N + l) * 2 + 1] = wg;
                     } else {
-                        double c1 = (double)cx, c2 = (double)cy;
-                        double mo[NM];
+                        W c1 = (W)cx, c2 = (W)cy;
+                        W mo[NM];
                         if (D == 1) {
                             mo[0] = wf; mo[1] = c1 * wf; mo[2] = c1 * c1 * wf; mo[3] = c1 * c1 * c1 * wf;
                             mo[4] = wg; mo[5] = c1 * wg;
                         } else {
-                            double cc = c1 * c1 + c2 * c2;
+                            W cc = c1 * c1 + c2 * c2;
                             mo[0] = wf; mo[1] = c1 * wf; mo[2] = c2 * wf;
                             mo[3] = c1 * c1 * wf; mo[4] = c1 * c2 * wf; mo[5] = c2 * c2 * wf;
                             mo[6] = cc * c1 * wf; mo[7] = cc * c2 * wf;
@@ -930,7 +960,7 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
         species_init<D, NF, NG>(sf, sg, RT);
         // residual scales RT^(-k/2) of basis order k (scale-free stopping test)
         const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
-        int fail = 0;
+        int fail = 0, fsp = -1;
         while (!fail && (sf.phase < 2 || sg.phase < 2)) {
             cs.pass++;
             double Sf[NMF], Sg[NMG], lf[NF], lg[NG];
@@ -963,18 +993,18 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
                 [&](int, int) {});
             if (sg.phase < 2) {
                 int r = species_update<D, NG, NMG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
-                if (r < 0) fail = r;
+                if (r < 0) { fail = -r; fsp = 1; }
             }
             if (sf.phase < 2 && !fail) {
                 int r = species_update<D, NF, NMF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
-                if (r < 0) fail = r;
+                if (r < 0) { fail = -r; fsp = 0; }
             }
         }
         if (fail) {
-            flag_fail(b.flags, fail, step, s);
+            flag_fail(b.flags, LELBM_EEPR, step, s, fail, fsp, fsp ? sg.res : sf.res);
         } else {
             const double wsf = rho, wsg = rho * ph.K * RT;
-            double *P = (double *)b.scratch + ti.base;
+            T *P = (T *)b.scratch + ti.base;
             double acc[NM];
 #pragma unroll
             for (int k = 0; k < NM; k++) acc[k] = 0.0;
@@ -1007,7 +1037,7 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
                     long long slot = (long long)(dy - ti.oy) * ti.wx + (dx - ti.ox);
 #pragma unroll
                     for (int k = 0; k < NM; k++) {
-                        P[(slot * TILE_N + l) * NM + k] = acc[k];
+                        P[(slot * TILE_N + l) * NM + k] = (T)acc[k];
                         acc[k] = 0.0;
                     }
                 });
@@ -1066,24 +1096,23 @@ __device__ inline Resolved resolve_source(const Geom &g, int xr, int yr) {
 // Adds the moment fractions of one arriving record; (cx, cy) is the
 // velocity after reflection; for pre-summed refined records the odd
 // components are mirrored.
-template <int D>
-__device__ inline void deposit_record(double *acc, const double *P, int fmt, int dx, int dy, int fx, int fy) {
-    constexpr int NM = Basis<D>::NMOM;
+template <typename T, int D>
+__device__ inline void deposit_record(T *acc, const T *P, int fmt, int dx, int dy, int fx, int fy) {
     if (fmt == 0) {
-        const double2 w = *(const double2 *)P;
-        double cx = (double)dx, cy = (double)dy;
+        const T wx_ = P[0], wy_ = P[1];
+        T cx = (T)dx, cy = (T)dy;
         if (D == 1) {
-            acc[0] += w.x; acc[1] += cx * w.x; acc[2] += cx * cx * w.x; acc[3] += cx * cx * cx * w.x;
-            acc[4] += w.y; acc[5] += cx * w.y;
+            acc[0] += wx_; acc[1] += cx * wx_; acc[2] += cx * cx * wx_; acc[3] += cx * cx * cx * wx_;
+            acc[4] += wy_; acc[5] += cx * wy_;
         } else {
-            double cc = cx * cx + cy * cy;
-            acc[0] += w.x; acc[1] += cx * w.x; acc[2] += cy * w.x;
-            acc[3] += cx * cx * w.x; acc[4] += cx * cy * w.x; acc[5] += cy * cy * w.x;
-            acc[6] += cc * cx * w.x; acc[7] += cc * cy * w.x;
-            acc[8] += w.y; acc[9] += cx * w.y; acc[10] += cy * w.y;
+            T cc = cx * cx + cy * cy;
+            acc[0] += wx_; acc[1] += cx * wx_; acc[2] += cy * wx_;
+            acc[3] += cx * cx * wx_; acc[4] += cx * cy * wx_; acc[5] += cy * cy * wx_;
+            acc[6] += cc * cx * wx_; acc[7] += cc * cy * wx_;
+            acc[8] += wy_; acc[9] += cx * wy_; acc[10] += cy * wy_;
         }
     } else {
-        double sx1 = fx ? -1.0 : 1.0, sy1 = fy ? -1.0 : 1.0;
+        T sx1 = fx ? (T)-1 : (T)1, sy1 = fy ? (T)-1 : (T)1;
         if (D == 1) {
             acc[0] += P[0]; acc[1] += sx1 * P[1]; acc[2] += P[2];
             acc[3] += sx1 * P[3]; acc[4] += P[4]; acc[5] += sx1 * P[5];
@@ -1094,8 +1123,11 @@ __device__ inline void deposit_record(double *acc, const double *P, int fmt, int
             acc[8] += P[8]; acc[9] += sx1 * P[9]; acc[10] += sy1 * P[10];
         }
     }
-    (void)NM;
 }
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
 
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
@@ -1113,10 +1145,11 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
     const int x = tx0 + lx, y = ty0 + ly;
     const bool mine = x < g.nx && y < g.ny;
     const DWin w = b.dwin[t];
-    const double *SCR = (const double *)b.scratch;
-    double acc[NM];
+    using V2 = typename Vec2<T>::type;
+    const T *SCR = (const T *)b.scratch;
+    T acc[NM];
 #pragma unroll
-    for (int k = 0; k < NM; k++) acc[k] = 0.0;
+    for (int k = 0; k < NM; k++) acc[k] = 0;
     unsigned long long hits = 0;
     const int RW = g.tx + (w.hix - w.lox);          // staged region width
     int rows = G_CAP / RW - (g.ty - 1);             // window rows per chunk
@@ -1156,7 +1189,7 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
                     for (int dxb = w.hix; dxb >= w.lox; dxb -= GU) {
                         int meta[GU], ii[GU];
                         double cux[GU], cuy[GU];
-                        const double *pp[GU];
+                        const T *pp[GU];
 #pragma unroll
                         for (int u = 0; u < GU; u++) {
                             const bool ok = dxb - u >= w.lox;
@@ -1180,11 +1213,11 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
                             const long long recsz = ((m >> 10) & 1) ? NM : 2;
                             pp[u] = SCR + s_a0[ii[u]] + ((long long)rdy * (m >> 11) + rdx) * TILE_N * recsz;
                         }
-                        double2 wv[GU];
+                        V2 wv[GU];
 #pragma unroll
                         for (int u = 0; u < GU; u++) {
-                            wv[u] = make_double2(0.0, 0.0);
-                            if (pp[u] && !((meta[u] >> 10) & 1)) wv[u] = *(const double2 *)pp[u];
+                            wv[u].x = 0; wv[u].y = 0;
+                            if (pp[u] && !((meta[u] >> 10) & 1)) wv[u] = *(const V2 *)pp[u];
                         }
 #pragma unroll
                         for (int u = 0; u < GU; u++) {
@@ -1192,14 +1225,14 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
                             const int dx = dxb - u, m = meta[u];
                             hits++;
                             if ((m >> 10) & 1) {
-                                deposit_record<D>(acc, pp[u], 1, dx, dy, (m >> 8) & 1, (m >> 9) & 1);
+                                deposit_record<T, D>(acc, pp[u], 1, dx, dy, (m >> 8) & 1, (m >> 9) & 1);
                             } else {
-                                double cx = (double)dx, cy = (double)dy;
+                                T cx = (T)dx, cy = (T)dy;
                                 if (D == 1) {
                                     acc[0] += wv[u].x; acc[1] += cx * wv[u].x; acc[2] += cx * cx * wv[u].x;
                                     acc[3] += cx * cx * cx * wv[u].x; acc[4] += wv[u].y; acc[5] += cx * wv[u].y;
                                 } else {
-                                    double cc = cx * cx + cy * cy;
+                                    T cc = cx * cx + cy * cy;
                                     acc[0] += wv[u].x; acc[1] += cx * wv[u].x; acc[2] += cy * wv[u].x;
                                     acc[3] += cx * cx * wv[u].x; acc[4] += cx * cy * wv[u].x;
                                     acc[5] += cy * cy * wv[u].x; acc[6] += cc * cx * wv[u].x;
@@ -1232,9 +1265,9 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
                 const TileInfo ti = b.tiles[st];
                 const long long recsz = ti.fmt ? NM : 2;
                 long long slot = (long long)(rdy - ti.oy) * ti.wx + (rdx - ti.ox);
-                const double *P = SCR + ti.base + (slot * TILE_N + loc) * recsz;
+                const T *P = SCR + ti.base + (slot * TILE_N + loc) * recsz;
                 hits++;
-                deposit_record<D>(acc, P, ti.fmt, dx, dy, rs.fx, rs.fy);
+                deposit_record<T, D>(acc, P, ti.fmt, dx, dy, rs.fx, rs.fy);
             }
         }
     }
@@ -1370,25 +1403,34 @@ hipError_t launch_scan(const Geom &g, Buffers &b, int step, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T>
+static void epr_launch(const Geom &g, const Phys &ph, const void *mom, Buffers &b, int step, hipStream_t s) {
+    unsigned nt = (unsigned)(g.ntx * g.nty);
+    if (g.dim == 1) {
+        hipLaunchKernelGGL((k_epr<T, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        hipLaunchKernelGGL((k_epr_ref<T, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+    } else {
+        hipLaunchKernelGGL((k_epr<T, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        hipLaunchKernelGGL((k_epr_ref<T, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+    }
+}
+
 hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
                       hipStream_t s) {
-    unsigned nt = (unsigned)(g.ntx * g.nty);
-    if (mixed) return hipErrorInvalidValue;
-    if (g.dim == 1) {
-        hipLaunchKernelGGL((k_epr<double, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
-        hipLaunchKernelGGL((k_epr_ref<double, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
-    } else {
-        hipLaunchKernelGGL((k_epr<double, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
-        hipLaunchKernelGGL((k_epr_ref<double, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
-    }
+    if (mixed) epr_launch<float>(g, ph, mom, b, step, s);
+    else epr_launch<double>(g, ph, mom, b, step, s);
     return hipGetLastError();
 }
 
 hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, hipStream_t s) {
     unsigned nt = (unsigned)(g.dtx * g.dty);
-    if (mixed) return hipErrorInvalidValue;
-    if (g.dim == 1) hipLaunchKernelGGL((k_gather<double, 1>), dim3(nt), dim3(256), 0, s, g, (double *)mom_out, b);
-    else hipLaunchKernelGGL((k_gather<double, 2>), dim3(nt), dim3(256), 0, s, g, (double *)mom_out, b);
+    if (mixed) {
+        if (g.dim == 1) hipLaunchKernelGGL((k_gather<float, 1>), dim3(nt), dim3(256), 0, s, g, (float *)mom_out, b);
+        else hipLaunchKernelGGL((k_gather<float, 2>), dim3(nt), dim3(256), 0, s, g, (float *)mom_out, b);
+    } else {
+        if (g.dim == 1) hipLaunchKernelGGL((k_gather<double, 1>), dim3(nt), dim3(256), 0, s, g, (double *)mom_out, b);
+        else hipLaunchKernelGGL((k_gather<double, 2>), dim3(nt), dim3(256), 0, s, g, (double *)mom_out, b);
+    }
     return hipGetLastError();
 }
 
