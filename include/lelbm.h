@@ -167,6 +167,63 @@ int lelbm_memory(const lelbm_ctx *c, long *persistent_bytes, long *scratch_bytes
 const char *lelbm_strerror(int code);
 void lelbm_destroy(lelbm_ctx *c);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start of the Newton solve (2D).  Not part of the paper: the
+ * paper starts every solve from Eq. (IID13) and suggests storing multipliers
+ * between steps (Sec. II.D).  Here a 16-64-64-16 ReLU network maps a cell's
+ * normalised post-collision moments and stencil geometry to its multipliers;
+ * Eq. (IID13) remains the fallback whenever the residual of a solve started
+ * from the network does not drop, so converged results equal those of the
+ * plain path (the dual problem has a unique minimiser).
+ *
+ * Parameters: 6288 FP32 values in the order W1[16][64], b1[64], W2[64][64],
+ * b2[64], W3[64][16], b3[16] (row-major [in][out]).  Inputs x[16] and
+ * targets y[16] of a training pair are described in the README of the
+ * package; pairs are harvested by the step itself (lelbm_harvest).  Training
+ * and inference run in the library's BF16-MFMA kernels with FP32
+ * accumulation and FP32 master weights (Adam).
+ * ------------------------------------------------------------------------ */
+#define LELBM_MLP_NPARAM 6288
+typedef struct lelbm_mlp lelbm_mlp;
+
+/* New network: params (host, LELBM_MLP_NPARAM floats) or NULL for a seeded
+ * He-uniform initialisation.  All work is issued on hip_stream. */
+int lelbm_mlp_create(const float *params, unsigned long long seed, void *hip_stream, lelbm_mlp **out);
+/* Current FP32 parameters to caller-owned host memory. */
+int lelbm_mlp_get_params(const lelbm_mlp *m, float *host_out);
+/* Inference: dev_x rows of 16 floats with a stride of x_stride floats,
+ * dev_y: n x 16 floats (device memory, caller-owned). */
+int lelbm_mlp_forward(lelbm_mlp *m, const float *dev_x, long long x_stride, long long n, float *dev_y);
+/* Gradient of the mean squared error over n pairs (dev_pairs: n x 32 floats,
+ * inputs then targets) with respect to the parameters; host_grad may be
+ * NULL; loss receives the mean squared error. */
+int lelbm_mlp_gradient(lelbm_mlp *m, const float *dev_pairs, long long n, float *host_grad, double *loss);
+/* steps Adam updates (learning rate lr, beta 0.9/0.999) on batches of
+ * `batch` pairs (multiple of 64) drawn with replacement by a counter-based
+ * generator seeded with seed; final_loss (nullable) receives the mean squared
+ * error of the last batch. */
+int lelbm_mlp_train(lelbm_mlp *m, const float *dev_pairs, long long n, int steps, int batch, float lr,
+                    unsigned long long seed, double *final_loss);
+/* Standardisation: the network sees (x - mean_x) / sd_x and predicts
+ * (y - mean_y) / sd_y.  The 64 constants are mean_x[16], 1/sd_x[16],
+ * mean_y[16], sd_y[16] (identity at creation).  fit computes them from n
+ * pairs on the device (columns with sd < 1e-12 get unit scale). */
+#define LELBM_MLP_NNORM 64
+int lelbm_mlp_fit_normalization(lelbm_mlp *m, const float *dev_pairs, long long n);
+int lelbm_mlp_get_norm(const lelbm_mlp *m, float *host_out);
+int lelbm_mlp_set_norm(lelbm_mlp *m, const float *host_norm);
+void lelbm_mlp_destroy(lelbm_mlp *m);
+
+/* Copies the network into a context created with guess = LELBM_GUESS_MLP
+ * (required before its first step). */
+int lelbm_set_mlp(lelbm_ctx *c, const lelbm_mlp *m);
+/* Harvest (features, converged multipliers) pairs during lelbm_step into a
+ * caller-owned device buffer of capacity x 32 floats: cell s at step k is
+ * recorded when (s + 7919 k) is divisible by stride (unrefined 2D cells).
+ * dev_buf = NULL stops harvesting.  The order of the pairs is not fixed. */
+int lelbm_harvest(lelbm_ctx *c, float *dev_buf, long long capacity, int stride);
+int lelbm_harvest_count(const lelbm_ctx *c, long long *n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,6 +92,22 @@ def lib():
         L.lelbm_strerror.restype = ctypes.c_char_p
         L.lelbm_destroy.argtypes = [vp]
         L.lelbm_destroy.restype = None
+        fp = ctypes.POINTER(ctypes.c_float)
+        ll = ctypes.c_longlong
+        L.lelbm_mlp_create.argtypes = [fp, ctypes.c_ulonglong, vp, ctypes.POINTER(vp)]
+        L.lelbm_mlp_get_params.argtypes = [vp, fp]
+        L.lelbm_mlp_forward.argtypes = [vp, vp, ll, ll, vp]
+        L.lelbm_mlp_gradient.argtypes = [vp, vp, ll, fp, ctypes.POINTER(ctypes.c_double)]
+        L.lelbm_mlp_train.argtypes = [vp, vp, ll, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_ulonglong,
+                                      ctypes.POINTER(ctypes.c_double)]
+        L.lelbm_mlp_fit_normalization.argtypes = [vp, vp, ll]
+        L.lelbm_mlp_get_norm.argtypes = [vp, fp]
+        L.lelbm_mlp_set_norm.argtypes = [vp, fp]
+        L.lelbm_mlp_destroy.argtypes = [vp]
+        L.lelbm_mlp_destroy.restype = None
+        L.lelbm_set_mlp.argtypes = [vp, vp]
+        L.lelbm_harvest.argtypes = [vp, vp, ll, ctypes.c_int]
+        L.lelbm_harvest_count.argtypes = [vp, ctypes.POINTER(ll)]
         _lib = L
     return _lib
 
@@ -218,6 +234,25 @@ class Lelbm:
         _check(lib().lelbm_memory(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
+    def set_mlp(self, mlp):
+        _check(lib().lelbm_set_mlp(self._h, mlp._h))
+
+    def harvest(self, tensor, stride):
+        """Record (features, multipliers) pairs into a torch float32 tensor of
+        shape (capacity, 32) on the device; tensor=None stops."""
+        if tensor is None:
+            _check(lib().lelbm_harvest(self._h, None, 0, 1))
+            self._harvest_ref = None
+            return
+        assert tensor.dtype == __import__("torch").float32 and tensor.shape[1] == 32 and tensor.is_contiguous()
+        self._harvest_ref = tensor
+        _check(lib().lelbm_harvest(self._h, ctypes.c_void_p(tensor.data_ptr()), tensor.shape[0], stride))
+
+    def harvest_count(self):
+        n = ctypes.c_longlong()
+        _check(lib().lelbm_harvest_count(self._h, ctypes.byref(n)))
+        return n.value
+
     def close(self):
         if self._h:
             lib().lelbm_destroy(self._h)
@@ -232,3 +267,73 @@ class Lelbm:
 
 def create(cfg, moments, precision=FP64, guess=GUESS_EQ, stream=None):
     return Lelbm(cfg, moments, precision, guess, stream)
+
+
+MLP_NPARAM = 6288
+
+
+class Mlp:
+    """Warm-start network (``lelbm_mlp``): training and inference run in the
+    library's BF16-MFMA kernels; torch tensors supply device buffers."""
+
+    def __init__(self, params=None, seed=0, stream=None):
+        self._h = ctypes.c_void_p()
+        self._stream = _stream_handle(stream)
+        fp = ctypes.POINTER(ctypes.c_float)
+        if params is not None:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            assert p.size == MLP_NPARAM
+            _check(lib().lelbm_mlp_create(p.ctypes.data_as(fp), seed, self._stream, ctypes.byref(self._h)))
+        else:
+            _check(lib().lelbm_mlp_create(None, seed, self._stream, ctypes.byref(self._h)))
+
+    def params(self):
+        out = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _check(lib().lelbm_mlp_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def fit_normalization(self, pairs):
+        _check(lib().lelbm_mlp_fit_normalization(self._h, ctypes.c_void_p(pairs.data_ptr()), pairs.shape[0]))
+
+    def norm(self):
+        out = np.zeros(64, dtype=np.float32)
+        _check(lib().lelbm_mlp_get_norm(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def set_norm(self, nm):
+        nm = np.ascontiguousarray(nm, dtype=np.float32)
+        _check(lib().lelbm_mlp_set_norm(self._h, nm.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def forward(self, x):
+        """x: torch float32 (n, >=16) on the device -> (n, 16) outputs."""
+        import torch
+        n = x.shape[0]
+        y = torch.empty((n, 16), dtype=torch.float32, device=x.device)
+        _check(lib().lelbm_mlp_forward(self._h, ctypes.c_void_p(x.data_ptr()), x.stride(0), n,
+                                       ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def gradient(self, pairs):
+        """pairs: torch float32 (n, 32) on the device -> (gradient, loss)."""
+        g = np.zeros(MLP_NPARAM, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(lib().lelbm_mlp_gradient(self._h, ctypes.c_void_p(pairs.data_ptr()), pairs.shape[0],
+                                        g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss)))
+        return g, loss.value
+
+    def train(self, pairs, steps, batch=4096, lr=1e-3, seed=0):
+        loss = ctypes.c_double()
+        _check(lib().lelbm_mlp_train(self._h, ctypes.c_void_p(pairs.data_ptr()), pairs.shape[0], steps, batch,
+                                     lr, seed, ctypes.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if self._h:
+            lib().lelbm_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <climits>
+#include <cmath>
 #include <vector>
 
 #include "lelbm_internal.h"
@@ -42,6 +43,10 @@ struct lelbm_ctx {
     std::vector<hipEvent_t> evpool;
     std::vector<int> evkind;
     size_t evused;
+    // learned guess: device copies of the network (owned by the context)
+    unsigned short *mlp_w;
+    float *mlp_p, *mlp_n;
+    int mlp_set;
     long long persistent_bytes;
 };
 
@@ -105,7 +110,7 @@ static int validate(const lelbm_params *p) {
     if (!(p->newton_tol > 0.0) || p->newton_max_it < 1) return LELBM_EINVAL;
     if (p->precision != LELBM_FP64 && p->precision != LELBM_MIXED) return LELBM_EINVAL;
     if (p->guess != LELBM_GUESS_EQ && p->guess != LELBM_GUESS_MLP) return LELBM_EINVAL;
-    if (p->guess == LELBM_GUESS_MLP) return LELBM_EINVAL;
+    if (p->guess == LELBM_GUESS_MLP && p->dim != 2) return LELBM_EINVAL;
     if (p->solid) return LELBM_EINVAL;
     for (int f = 0; f < 4; f++)
         if (p->bc[f] < LELBM_BC_PERIODIC || p->bc[f] > LELBM_BC_SLIPWALL) return LELBM_EINVAL;
@@ -125,7 +130,8 @@ static void free_ctx(lelbm_ctx *c) {
     if (!c) return;
     Buffers &b = c->b;
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.tiles,
-                    b.dwin, b.scratch, b.flags, b.stats, b.partial};
+                    b.dwin, b.scratch, b.flags, b.stats, b.partial, b.guess, b.harvest_n,
+                    c->mlp_w, c->mlp_p, c->mlp_n};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (c->ev[0]) (void)hipEventDestroy(c->ev[0]);
@@ -163,6 +169,10 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     if (!c) return LELBM_ENOMEM;
     memset(&c->b, 0, sizeof(c->b));
     c->ev[0] = c->ev[1] = nullptr;
+    c->mlp_w = nullptr;
+    c->mlp_p = nullptr;
+    c->mlp_n = nullptr;
+    c->mlp_set = 0;
     c->p = *p;
     c->p.solid = nullptr;
     c->mixed = p->precision == LELBM_MIXED;
@@ -219,6 +229,13 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ok = ok && hipMalloc((void **)&b.flags, sizeof(Flags)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.stats, sizeof(DevStats)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.partial, (size_t)(num_sum_blocks(g) + 1) * 4 * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.harvest_n, sizeof(unsigned long long)) == hipSuccess;
+    if (p->guess == LELBM_GUESS_MLP) {
+        ok = ok && hipMalloc((void **)&b.guess, (size_t)16 * ns * sizeof(double)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&c->mlp_w, MLP_NPARAM * sizeof(unsigned short)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&c->mlp_p, MLP_NPARAM * sizeof(float)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&c->mlp_n, MLP_NORM * sizeof(float)) == hipSuccess;
+    }
     if (!ok) { free_ctx(c); return LELBM_ENOMEM; }
     c->persistent_bytes = (long long)2 * c->nmom * ns * esz + ns * (4 * sizeof(double) + sizeof(int)) +
                           nt * sizeof(TileInfo) + nd * sizeof(DWin);
@@ -355,6 +372,10 @@ static hipError_t do_prepare(lelbm_ctx *c, void *a) {
 }
 static hipError_t do_scan(lelbm_ctx *c, void *a) { return launch_scan(c->g, c->b, ((StepArg *)a)->step, c->stream); }
 static hipError_t do_epr(lelbm_ctx *c, void *a) {
+    if (c->b.guess) {
+        hipError_t e = launch_mlp_guess(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, c->stream);
+        if (e != hipSuccess) return e;
+    }
     return launch_epr(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
 }
 static hipError_t do_gather(lelbm_ctx *c, void *) {
@@ -363,6 +384,7 @@ static hipError_t do_gather(lelbm_ctx *c, void *) {
 
 extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
     if (!c || nsteps < 0) return LELBM_EINVAL;
+    if (c->p.guess == LELBM_GUESS_MLP && !c->mlp_set) return LELBM_EINVAL;
     int dev;
     HIPCHECK(hipGetDevice(&dev));
     if (dev != c->device) HIPCHECK(hipSetDevice(c->device));
@@ -515,4 +537,224 @@ extern "C" void lelbm_destroy(lelbm_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     free_ctx(c);
+}
+
+// ---------------------------------------------------------------------------
+// Warm-start network: trainer object, inference, harvesting
+// ---------------------------------------------------------------------------
+struct lelbm_mlp {
+    hipStream_t stream;
+    float *params, *m1, *m2;     // FP32 master parameters and Adam moments
+    float *norm;                 // standardisation constants
+    unsigned short *wb;          // BF16 weights
+    float *partial, *lossp, *grad;
+    long long part_cap;          // waves the partial buffer holds
+    long long t;                 // Adam step counter
+};
+
+static unsigned long long splitmix(unsigned long long &st) {
+    unsigned long long z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static void mlp_free(lelbm_mlp *m) {
+    if (!m) return;
+    void *ptrs[] = {m->params, m->m1, m->m2, m->wb, m->partial, m->lossp, m->grad, m->norm};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete m;
+}
+
+static int mlp_partials(lelbm_mlp *m, long long waves) {
+    if (waves <= m->part_cap) return LELBM_OK;
+    HIPCHECK(hipStreamSynchronize(m->stream));
+    if (m->partial) HIPCHECK(hipFree(m->partial));
+    if (m->lossp) HIPCHECK(hipFree(m->lossp));
+    m->partial = nullptr;
+    m->lossp = nullptr;
+    m->part_cap = 0;
+    if (hipMalloc((void **)&m->partial, (size_t)waves * MLP_NPARAM * sizeof(float)) != hipSuccess) return LELBM_ENOMEM;
+    if (hipMalloc((void **)&m->lossp, (size_t)waves * sizeof(float)) != hipSuccess) return LELBM_ENOMEM;
+    m->part_cap = waves;
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_mlp_create(const float *params, unsigned long long seed, void *hip_stream, lelbm_mlp **out) {
+    if (!out) return LELBM_EINVAL;
+    lelbm_mlp *m = new (std::nothrow) lelbm_mlp();
+    if (!m) return LELBM_ENOMEM;
+    m->stream = (hipStream_t)hip_stream;
+    m->params = m->m1 = m->m2 = m->partial = m->lossp = m->grad = m->norm = nullptr;
+    m->wb = nullptr;
+    m->part_cap = 0;
+    m->t = 0;
+    bool ok = hipMalloc((void **)&m->params, MLP_NPARAM * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&m->m1, MLP_NPARAM * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&m->m2, MLP_NPARAM * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&m->grad, MLP_NPARAM * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&m->wb, MLP_NPARAM * sizeof(unsigned short)) == hipSuccess &&
+              hipMalloc((void **)&m->norm, MLP_NORM * sizeof(float)) == hipSuccess;
+    if (!ok) { mlp_free(m); return LELBM_ENOMEM; }
+    std::vector<float> h(MLP_NPARAM, 0.f);
+    if (params) {
+        memcpy(h.data(), params, MLP_NPARAM * sizeof(float));
+    } else {
+        // He-uniform initialisation of the ReLU layers from a SplitMix64
+        // stream; output layer scaled by 0.1; zero biases
+        unsigned long long st = seed;
+        struct L { int off, nin, nout; float gain; } layers[3] = {
+            {MLP_OFF_W1, MLP_IN, MLP_H, 1.f}, {MLP_OFF_W2, MLP_H, MLP_H, 1.f}, {MLP_OFF_W3, MLP_H, MLP_OUT, 0.1f}};
+        for (const L &ly : layers) {
+            float a = ly.gain * sqrtf(6.f / ly.nin);
+            for (int i = 0; i < ly.nin * ly.nout; i++) {
+                double u = (splitmix(st) >> 11) * (1.0 / 9007199254740992.0);
+                h[ly.off + i] = (float)((2.0 * u - 1.0) * a);
+            }
+        }
+    }
+    std::vector<float> z(MLP_NPARAM, 0.f), nm(MLP_NORM, 0.f);
+    for (int k = 0; k < 16; k++) { nm[16 + k] = 1.f; nm[48 + k] = 1.f; }   // identity standardisation
+    if (hipMemcpy(m->params, h.data(), MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->norm, nm.data(), MLP_NORM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->m1, z.data(), MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->m2, z.data(), MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        launch_mlp_to_bf16(m->params, m->wb, m->stream) != hipSuccess ||
+        hipStreamSynchronize(m->stream) != hipSuccess) {
+        mlp_free(m);
+        return LELBM_EDEVICE;
+    }
+    *out = m;
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_mlp_get_params(const lelbm_mlp *m, float *host_out) {
+    if (!m || !host_out) return LELBM_EINVAL;
+    HIPCHECK(hipMemcpyAsync(host_out, m->params, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    HIPCHECK(hipStreamSynchronize(m->stream));
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_mlp_forward(lelbm_mlp *m, const float *dev_x, long long x_stride, long long n, float *dev_y) {
+    if (!m || n < 0 || (n > 0 && (!dev_x || !dev_y)) || x_stride < MLP_IN) return LELBM_EINVAL;
+    HIPCHECK(launch_mlp_forward(m->wb, m->params, m->norm, dev_x, x_stride, n, dev_y, m->stream));
+    HIPCHECK(hipStreamSynchronize(m->stream));
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_mlp_gradient(lelbm_mlp *m, const float *dev_pairs, long long n, float *host_grad,
+                                  double *loss) {
+    if (!m || !dev_pairs || n <= 0) return LELBM_EINVAL;
+    long long waves = (n + 63) / 64;
+    int r = mlp_partials(m, waves);
+    if (r != LELBM_OK) return r;
+    HIPCHECK(launch_mlp_fwdbwd(m->wb, m->params, m->norm, dev_pairs, n, n, 0, 0, 0, m->partial, m->lossp, m->stream));
+    HIPCHECK(launch_mlp_adam(m->partial, (int)waves, m->params, m->m1, m->m2, m->wb, 0.f, 1, 0, m->grad, m->stream));
+    std::vector<float> lp(waves);
+    HIPCHECK(hipMemcpyAsync(lp.data(), m->lossp, waves * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    if (host_grad)
+        HIPCHECK(hipMemcpyAsync(host_grad, m->grad, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    HIPCHECK(hipStreamSynchronize(m->stream));
+    if (loss) {
+        double a = 0;
+        for (float v : lp) a += v;
+        *loss = a / ((double)n * MLP_OUT);
+    }
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_mlp_train(lelbm_mlp *m, const float *dev_pairs, long long n, int steps, int batch, float lr,
+                               unsigned long long seed, double *final_loss) {
+    if (!m || !dev_pairs || n <= 0 || steps < 0 || batch < 64 || batch % 64 != 0 || !(lr > 0.f)) return LELBM_EINVAL;
+    long long waves = batch / 64;
+    int r = mlp_partials(m, waves);
+    if (r != LELBM_OK) return r;
+    for (int k = 0; k < steps; k++) {
+        m->t++;
+        HIPCHECK(launch_mlp_fwdbwd(m->wb, m->params, m->norm, dev_pairs, n, batch, 1, seed, (unsigned long long)m->t,
+                                   m->partial, m->lossp, m->stream));
+        HIPCHECK(launch_mlp_adam(m->partial, (int)waves, m->params, m->m1, m->m2, m->wb, lr, (int)m->t, 1, nullptr,
+                                 m->stream));
+    }
+    if (final_loss) {
+        std::vector<float> lp(waves);
+        HIPCHECK(hipMemcpyAsync(lp.data(), m->lossp, waves * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        HIPCHECK(hipStreamSynchronize(m->stream));
+        double a = 0;
+        for (float v : lp) a += v;
+        *final_loss = a / ((double)batch * MLP_OUT);
+    } else {
+        HIPCHECK(hipStreamSynchronize(m->stream));
+    }
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_mlp_fit_normalization(lelbm_mlp *m, const float *dev_pairs, long long n) {
+    if (!m || !dev_pairs || n <= 0) return LELBM_EINVAL;
+    HIPCHECK(launch_mlp_norm_fit(dev_pairs, n, m->norm, m->stream));
+    HIPCHECK(hipStreamSynchronize(m->stream));
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_mlp_get_norm(const lelbm_mlp *m, float *host_out) {
+    if (!m || !host_out) return LELBM_EINVAL;
+    HIPCHECK(hipMemcpyAsync(host_out, m->norm, MLP_NORM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    HIPCHECK(hipStreamSynchronize(m->stream));
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_mlp_set_norm(lelbm_mlp *m, const float *host_norm) {
+    if (!m || !host_norm) return LELBM_EINVAL;
+    for (int k = 0; k < 16; k++)
+        if (!(host_norm[48 + k] > 0.f) || !std::isfinite(host_norm[16 + k])) return LELBM_EINVAL;
+    HIPCHECK(hipMemcpyAsync(m->norm, host_norm, MLP_NORM * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    HIPCHECK(hipStreamSynchronize(m->stream));
+    return LELBM_OK;
+}
+
+extern "C" void lelbm_mlp_destroy(lelbm_mlp *m) {
+    if (!m) return;
+    (void)hipStreamSynchronize(m->stream);
+    mlp_free(m);
+}
+
+extern "C" int lelbm_set_mlp(lelbm_ctx *c, const lelbm_mlp *m) {
+    if (!c || !m || c->p.guess != LELBM_GUESS_MLP) return LELBM_EINVAL;
+    HIPCHECK(hipStreamSynchronize(m->stream));
+    HIPCHECK(hipMemcpyAsync(c->mlp_p, m->params, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHECK(hipMemcpyAsync(c->mlp_n, m->norm, MLP_NORM * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHECK(launch_mlp_to_bf16(c->mlp_p, c->mlp_w, c->stream));
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    c->b.mlp_w = c->mlp_w;
+    c->b.mlp_p = c->mlp_p;
+    c->b.mlp_n = c->mlp_n;
+    c->mlp_set = 1;
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_harvest(lelbm_ctx *c, float *dev_buf, long long capacity, int stride) {
+    if (!c) return LELBM_EINVAL;
+    if (!dev_buf) {
+        c->b.harvest = nullptr;
+        c->b.harvest_cap = 0;
+        return LELBM_OK;
+    }
+    if (capacity <= 0 || stride < 1 || c->p.dim != 2) return LELBM_EINVAL;
+    c->b.harvest = dev_buf;
+    c->b.harvest_cap = capacity;
+    c->b.harvest_stride = stride;
+    unsigned long long zero = 0;
+    HIPCHECK(hipMemcpyAsync(c->b.harvest_n, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_harvest_count(const lelbm_ctx *c, long long *n) {
+    if (!c || !n) return LELBM_EINVAL;
+    unsigned long long v = 0;
+    HIPCHECK(hipMemcpyAsync(&v, c->b.harvest_n, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    *n = (long long)(v < (unsigned long long)c->b.harvest_cap ? v : (unsigned long long)c->b.harvest_cap);
+    return LELBM_OK;
 }

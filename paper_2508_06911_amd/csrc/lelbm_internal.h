@@ -16,6 +16,14 @@ constexpr int MAX_RADIUS = 128;     // largest acoustic radius (RT up to ~1000)
 constexpr double MAX_SPEED = 2048.0;  // largest |u| component in cells per step
 constexpr double MIXED_TOL_FLOOR = 1e-8;  // Newton tolerance of the mixed path (records are FP32)
 
+// Warm-start network: 16 inputs, two hidden layers of 64, 16 outputs.
+// Canonical FP32 parameter vector: W1[16][64], b1[64], W2[64][64], b2[64],
+// W3[64][16], b3[16] (row-major [in][out]).
+constexpr int MLP_IN = 16, MLP_H = 64, MLP_OUT = 16;
+constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 1024, MLP_OFF_W2 = 1088, MLP_OFF_B2 = 5184, MLP_OFF_W3 = 5248,
+              MLP_OFF_B3 = 6272, MLP_NPARAM = 6288;
+constexpr int MLP_NORM = 64;   // standardisation constants (input/output mean and scale)
+
 // Internal error code: population scratch too small (the host grows it and
 // repeats the step).
 constexpr int ERR_OVERFLOW = -100;
@@ -87,6 +95,16 @@ struct Buffers {
     Flags *flags;
     DevStats *stats;
     double *partial;         // block partial sums for conserved totals
+    // learned Newton guess
+    const unsigned short *mlp_w;   // BF16 weights (canonical order), NULL = none
+    const float *mlp_p;            // FP32 parameters (biases read from here)
+    const float *mlp_n;            // standardisation constants (64)
+    double *guess;                 // [16][ns] initial multipliers, NULL = Eq. (IID13)
+    // harvesting of (features, converged multipliers) pairs
+    float *harvest;                // [cap][32], NULL = off
+    long long harvest_cap;
+    int harvest_stride;
+    unsigned long long *harvest_n; // pairs written (device counter)
 };
 
 // Kernel launchers (defined in lelbm_kernels.hip).  All enqueue on `s`.
@@ -101,5 +119,15 @@ hipError_t launch_sums(const Geom &g, int mixed, const void *mom, Buffers &b, hi
 hipError_t launch_reset_step(const Geom &g, Buffers &b, hipStream_t s);
 hipError_t launch_reset_stats(Buffers &b, hipStream_t s);
 int num_sum_blocks(const Geom &g);
+hipError_t launch_mlp_guess(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, hipStream_t s);
+hipError_t launch_mlp_fwdbwd(const unsigned short *Wb, const float *bias, const float *nm, const float *pairs,
+                             long long n, long long nsamp, int draw, unsigned long long seed, unsigned long long step,
+                             float *partial, float *lossp, hipStream_t s);
+hipError_t launch_mlp_norm_fit(const float *pairs, long long n, float *nm, hipStream_t s);
+hipError_t launch_mlp_adam(const float *partial, int nparts, float *params, float *m1, float *m2, unsigned short *Wb,
+                           float lr, int t, int apply, float *grad_out, hipStream_t s);
+hipError_t launch_mlp_to_bf16(const float *params, unsigned short *Wb, hipStream_t s);
+hipError_t launch_mlp_forward(const unsigned short *Wb, const float *bias, const float *nm, const float *x,
+                              long long xstride, long long n, float *y, hipStream_t s);
 
 }  // namespace lelbm

@@ -25,6 +25,7 @@
 #include <math.h>
 
 #include "lelbm_internal.h"
+#include "lelbm_mlp_dev.h"
 
 namespace lelbm {
 
@@ -92,6 +93,9 @@ __device__ inline void flag_fail(Flags *fl, int code, int step, long long node, 
 
 // Reasons of a failed reconstruction (lelbm_last_failure_detail).
 enum { FAIL_NONFINITE = 1, FAIL_LINESEARCH = 2, FAIL_CHOL_POLISH = 3, FAIL_MAXIT = 4, FAIL_CHOL_STEP = 5 };
+// species_update asks for a restart from Eq. (IID13) when a solve started
+// from the learned guess does not lower its residual
+constexpr int RESTART_EQ = 2;
 
 __device__ inline void atomic_max_pos(unsigned long long *a, double v) {
     atomicMax(a, (unsigned long long)__double_as_longlong(v));
@@ -452,6 +456,8 @@ template <int NB, class Store> struct Species {
     int phase;        // 0: first evaluation, 1: iterating, 2: polished
     int nit, ls;
     double res;       // last scaled residual
+    int mlp;          // 1 while iterating from the learned guess
+    double res_prev;  // residual after the previous accepted step
     __device__ double at(int j) { return v.lam(j) + t * v.del(j); }   // multipliers of the current pass
 };
 
@@ -471,7 +477,7 @@ __device__ inline int species_update(Species<NB, Store> &sp, const double *S, co
     }
     fin = fin && isfinite(phit);
     if (sp.phase == 0) {
-        if (!fin) return -FAIL_NONFINITE;
+        if (!fin) return sp.mlp ? RESTART_EQ : -FAIL_NONFINITE;
         sp.phase = 1;
     } else {
         if (!(fin && (sp.dec <= 1e-8 || phit <= sp.phi - 1e-4 * sp.t * sp.dec))) {
@@ -492,6 +498,8 @@ __device__ inline int species_update(Species<NB, Store> &sp, const double *S, co
         res = v > res ? v : res;
     }
     sp.res = res;
+    if (sp.mlp && sp.nit > 0 && res > tol && !(res < sp.res_prev)) return RESTART_EQ;
+    sp.res_prev = res;
     double dl[NB];
     if (res <= tol) {
         if (!hess_solve<D, NB>(S, r, dl)) return -FAIL_CHOL_POLISH;
@@ -620,6 +628,19 @@ __device__ inline void collide_targets(const Geom &g, const Phys &ph, const T *m
     }
 }
 
+// Restarts one species from Eq. (IID13).
+template <int D, int NB, class S>
+__device__ inline void species_restart_eq(Species<NB, S> &sp, double RT) {
+#pragma unroll
+    for (int j = 0; j < NB; j++) { sp.v.lam(j) = 0.0; sp.v.del(j) = 0.0; }
+    sp.v.lam(0) = -1.0 + 0.5 * D * log(2.0 * M_PI * RT);
+    if (D == 1) sp.v.lam(2) = 1.0 / (2.0 * RT);
+    else { sp.v.lam(3) = 1.0 / (2.0 * RT); sp.v.lam(5) = 1.0 / (2.0 * RT); }
+    sp.t = 0.0; sp.dec = 0.0; sp.phi = 0.0;
+    sp.phase = 0; sp.nit = 0; sp.ls = 0;
+    sp.res = 0.0; sp.mlp = 0; sp.res_prev = 0.0;
+}
+
 // Initial multipliers of Eq. (IID13) for both species.
 template <int D, int NF, int NG, class SF, class SG>
 __device__ inline void species_init(Species<NF, SF> &sf, Species<NG, SG> &sg, double RT) {
@@ -634,18 +655,19 @@ __device__ inline void species_init(Species<NF, SF> &sf, Species<NG, SG> &sg, do
     sf.t = sg.t = 0.0; sf.dec = sg.dec = 0.0; sf.phi = sg.phi = 0.0;
     sf.phase = sg.phase = 0; sf.nit = sg.nit = 0; sf.ls = sg.ls = 0;
     sf.res = sg.res = 0.0;
+    sf.mlp = sg.mlp = 0; sf.res_prev = sg.res_prev = 0.0;
 }
 
 // Per-cell statistics, reduced over the wavefront, one atomic per wave.
 struct CellStats {
-    int it_f = 0, it_g = 0, q = 0, lim = 0, pass = 0;
+    int it_f = 0, it_g = 0, q = 0, lim = 0, pass = 0, fb = 0;
     double kn = 0.0, colat = 0.0, rt = 1e300;
     bool active = false;
 };
 
 __device__ inline void push_stats(DevStats *st, const CellStats &c) {
     unsigned long long a_itf = c.it_f, a_itg = c.it_g, a_q = c.q, a_lim = c.lim, a_cells = c.active ? 1 : 0;
-    unsigned long long a_qp = (unsigned long long)c.q * c.pass;
+    unsigned long long a_qp = (unsigned long long)c.q * c.pass, a_fb = c.fb;
     int m_itf = c.it_f, m_itg = c.it_g, m_q = c.q, n_q = c.active ? c.q : 1 << 30;
     double m_kn = c.kn, m_colat = c.colat, n_rt = c.rt;
     for (int off = 32; off > 0; off >>= 1) {
@@ -655,6 +677,7 @@ __device__ inline void push_stats(DevStats *st, const CellStats &c) {
         a_lim += __shfl_xor(a_lim, off);
         a_cells += __shfl_xor(a_cells, off);
         a_qp += __shfl_xor(a_qp, off);
+        a_fb += __shfl_xor(a_fb, off);
         m_itf = max(m_itf, __shfl_xor(m_itf, off));
         m_itg = max(m_itg, __shfl_xor(m_itg, off));
         m_q = max(m_q, __shfl_xor(m_q, off));
@@ -670,6 +693,7 @@ __device__ inline void push_stats(DevStats *st, const CellStats &c) {
         atomicAdd(&st->limited, a_lim);
         atomicAdd(&st->cells, a_cells);
         atomicAdd(&st->qpass_sum, a_qp);
+        if (a_fb) atomicAdd(&st->fallbacks, a_fb);
         atomicMax(&st->it_max_f, m_itf);
         atomicMax(&st->it_max_g, m_itg);
         atomicMax(&st->q_max, m_q);
@@ -800,6 +824,14 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         sf.v.lam_ = s_lamf + l; sf.v.del_ = s_delf + l;
         sg.v.lam_ = s_lamg + l; sg.v.del_ = s_delg + l;
         species_init<D, NF, NG>(sf, sg, RT);
+        if (D == 2 && b.guess) {
+            // learned guess (scaled multipliers, see k_mlp_guess)
+#pragma unroll
+            for (int j = 0; j < NF; j++) sf.v.lam(j) = b.guess[(long long)j * g.ns + s];
+#pragma unroll
+            for (int j = 0; j < NG; j++) sg.v.lam(j) = b.guess[(long long)(NF + j) * g.ns + s];
+            sf.mlp = sg.mlp = 1;
+        }
         // residual scales RT^(-k/2) of basis order k (scale-free stopping test)
         const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
         int fail = 0, fsp = -1;
@@ -857,15 +889,36 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
             if (sg.phase < 2) {
                 int r = species_update<D, NG, NMG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
                 if (r < 0) { fail = -r; fsp = 1; }
+                else if (r == RESTART_EQ) { species_restart_eq<D>(sg, RT); cs.fb = 1; }
             }
             if (sf.phase < 2 && !fail) {
                 int r = species_update<D, NF, NMF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
                 if (r < 0) { fail = -r; fsp = 0; }
+                else if (r == RESTART_EQ) { species_restart_eq<D>(sf, RT); cs.fb = 1; }
             }
         }
         if (fail) {
             flag_fail(b.flags, LELBM_EEPR, step, s, fail, fsp, fsp ? sg.res : sf.res);
         } else {
+            if (D == 2 && b.harvest && ((s + (long long)step * 7919) % b.harvest_stride) == 0) {
+                unsigned long long slot = atomicAdd(b.harvest_n, 1ull);
+                if (slot < (unsigned long long)b.harvest_cap) {
+                    float x[16];
+                    mlp_features(mf, mg, ux, uy, RT, R, x);
+                    float *hp = b.harvest + slot * 32;
+#pragma unroll
+                    for (int k = 0; k < 16; k++) hp[k] = x[k];
+                    const double sq = sqrt(RT);
+#pragma unroll
+                    for (int j = 0; j < NF + NG; j++) {
+                        const int jj = j < NF ? j : j - NF;
+                        const double lam = j < NF ? sf.v.lam(jj) : sg.v.lam(jj);
+                        const int k = basis_order2(jj);
+                        const double scl = k == 0 ? 1.0 : (k == 1 ? sq : (k == 2 ? RT : RT * sq));
+                        hp[16 + j] = (float)(lam * scl - iid13_scaled(jj, RT));
+                    }
+                }
+            }
             // final pass: moment fractions rho f', rho K RT g' (Eq. IIE3a)
             const double wsf = rho, wsg = rho * ph.K * RT;
             T *P = (T *)b.scratch + ti.base;
@@ -1050,6 +1103,72 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
         }
     }
     push_stats(b.stats, cs);
+}
+
+// ---------------------------------------------------------------------------
+// Learned initial multipliers for the unrefined cells of a tile (2D): the
+// collision targets and stencil geometry of each cell are fed through the
+// warm-start network (one wavefront = 64 cells, BF16 MFMA); the outputs are
+// turned back into multipliers and stored for k_epr.  Refined cells keep
+// Eq. (IID13) in k_epr_ref.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_mlp_guess(Geom g, Phys ph, const T *mom, Buffers b) {
+    __shared__ unsigned short xs[4][64 * MLP_IN];
+    __shared__ float ys[4][64 * MLP_OUT];
+    __shared__ int s_err;
+    if (threadIdx.x == 0) s_err = b.flags->err;
+    __syncthreads();
+    if (s_err) return;
+    const int t = blockIdx.x;
+    const int tx0 = (t % g.ntx) * g.tx, ty0 = (t / g.ntx) * g.ty;
+    const int l = threadIdx.x, wv = l >> 6, lane = l & 63;
+    const int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
+    const bool valid = px < g.sxn && py < g.syn;
+    const long long s = (long long)py * g.sxn + px;
+    const int rn = valid ? b.desc_rn[s] : -1;
+    const bool active = rn >= 0 && (rn >> 16) == 0;
+    double RT = 1.0;
+    float x[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) x[k] = 0.f;
+    if (active) {
+        double rho = b.desc_rho[s], ux = b.desc_u[s], uy = b.desc_u[g.ns + s];
+        RT = b.desc_rt[s];
+        double mf[10], mg[6], kn;
+        int lim;
+        collide_targets<T, 2>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, kn, lim);
+        mlp_features(mf, mg, ux, uy, RT, rn & 0xffff, x);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; k++) xs[wv][lane * MLP_IN + k] = f2bf(norm_in(b.mlp_n, k, x[k]));
+    __syncthreads();
+    bf16x4 h1[4][4], h2[4][4];
+    f32x4 y[4];
+    mlp_forward_wave(b.mlp_w, b.mlp_p, xs[wv], h1, h2, y, lane);
+    const int r4 = 4 * (lane >> 4), c = lane & 15;
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) ys[wv][(16 * nt + c) * MLP_OUT + r4 + i] = y[nt][i];
+    __syncthreads();
+    if (!active) return;
+    const double sq = sqrt(RT);
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        const int jj = j < 10 ? j : j - 10;
+        const int k = basis_order2(jj);
+        const double scl = k == 0 ? 1.0 : (k == 1 ? sq : (k == 2 ? RT : RT * sq));
+        const double yj = (double)denorm_out(b.mlp_n, j, ys[wv][lane * MLP_OUT + j]);
+        b.guess[(long long)j * g.ns + s] = (yj + iid13_scaled(jj, RT)) / scl;
+    }
+}
+
+hipError_t launch_mlp_guess(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, hipStream_t s) {
+    unsigned nt = (unsigned)(g.ntx * g.nty);
+    if (mixed) hipLaunchKernelGGL((k_mlp_guess<float>), dim3(nt), dim3(256), 0, s, g, ph, (const float *)mom, b);
+    else hipLaunchKernelGGL((k_mlp_guess<double>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,139 @@
+"""GPU checks of the warm-start network kernels (BF16 MFMA, FP32 accumulate)
+against the FP64 reference with the same BF16 rounding points, and of the
+learned guess inside the step: identical converged fields, fewer iterations."""
+import numpy as np
+import pytest
+
+import lelbm_inputs as li
+from helpers import gpu_moments, rel_linf, run_gpu
+from oracle import mlp_ref
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    print("\n[gpu case] %s" % name, flush=True)
+
+
+def _seeded(seed, n):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(mlp_ref.NPARAM)
+    for off, nin, nout in ((0, 16, 64), (1088, 64, 64), (5248, 64, 16)):
+        p[off:off + nin * nout] = rng.uniform(-1, 1, nin * nout) * np.sqrt(6.0 / nin)
+    p[1024:1088] = rng.normal(0, 0.1, 64)
+    p[5184:5248] = rng.normal(0, 0.1, 64)
+    p[6272:] = rng.normal(0, 0.1, 16)
+    x = rng.normal(0, 1, (n, 16))
+    t = rng.normal(0, 1, (n, 16))
+    return p.astype(np.float32), x.astype(np.float32), t.astype(np.float32)
+
+
+def _norm(seed):
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.normal(0, 0.5, 16), rng.uniform(0.5, 3, 16), rng.normal(0, 0.5, 16),
+                           rng.uniform(0.2, 2, 16)]).astype(np.float32)
+
+
+def test_forward_matches_bf16_reference():
+    _case("mlp forward n=200")
+    import torch
+    import paper_2508_06911_amd as lb
+    p, x, t = _seeded(0, 200)
+    nm = _norm(0)
+    m = lb.Mlp(params=p)
+    m.set_norm(nm)
+    y = m.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    ys, _ = mlp_ref.forward(p.astype(np.float64), x.astype(np.float64), bf=True, norm=nm)
+    ref = nm[32:48].astype(np.float64) + nm[48:64].astype(np.float64) * ys
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    print("forward rel err", err)
+    assert err < 1e-3
+    m.close()
+
+
+def test_gradient_matches_bf16_reference():
+    _case("mlp gradient n=200")
+    import torch
+    import paper_2508_06911_amd as lb
+    p, x, t = _seeded(1, 200)
+    nm = _norm(1)
+    m = lb.Mlp(params=p)
+    m.set_norm(nm)
+    pairs = torch.from_numpy(np.concatenate([x, t], axis=1)).cuda()
+    g, loss = m.gradient(pairs)
+    lref, gref = mlp_ref.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64), bf=True,
+                                       norm=nm)
+    assert abs(loss - lref) / lref < 1e-3
+    for name, a, b in (("W1", 0, 1024), ("b1", 1024, 1088), ("W2", 1088, 5184), ("b2", 5184, 5248),
+                       ("W3", 5248, 6272), ("b3", 6272, 6288)):
+        err = np.linalg.norm(g[a:b] - gref[a:b]) / np.linalg.norm(gref[a:b])
+        print(name, "grad rel err", err)
+        assert err < 1e-2, name
+    m.close()
+
+
+def test_training_reduces_loss():
+    _case("mlp training on a smooth map")
+    import torch
+    import paper_2508_06911_amd as lb
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, (20000, 16)).astype(np.float32)
+    A = rng.normal(0, 0.5, (16, 16))
+    t = np.tanh(x @ A).astype(np.float32)
+    pairs = torch.from_numpy(np.concatenate([x, t], axis=1)).cuda()
+    m = lb.Mlp(seed=7)
+    m.fit_normalization(pairs)
+    nm = m.norm()
+    assert np.allclose(nm[:16], x.mean(0), atol=1e-5) and np.allclose(nm[48:], t.std(0), rtol=1e-4)
+    _, l0 = m.gradient(pairs)
+    l1 = m.train(pairs, steps=400, batch=1024, lr=3e-3, seed=11)
+    _, l2 = m.gradient(pairs)
+    print("loss", l0, l1, l2)
+    assert l2 < 0.1 * l0
+    m.close()
+
+
+def test_learned_guess_matches_plain_path_and_saves_iterations():
+    """Harvest pairs from four-quadrant runs, train the network with the
+    library's kernels, then run an unseen seed with the learned guess: fields
+    equal to the plain path to 1e-10, fewer Newton iterations."""
+    _case("harvest/train/guess quadrants 96x96")
+    import torch
+    import paper_2508_06911_amd as lb
+    cap = 400000
+    buf = torch.zeros((cap, 32), dtype=torch.float32, device="cuda")
+    n = 0
+    for seed in (0, 1, 2, 3, 4, 5):
+        cfg, prim = li.quadrants(seed, n=96)
+        c = lb.Lelbm(cfg, gpu_moments(cfg, prim))
+        c.harvest(buf, stride=3)
+        c.step(40)
+        n = c.harvest_count()
+        c.close()
+    print("harvested", n)
+    assert n > 50000
+    pairs = buf[:n].contiguous()
+    m = lb.Mlp(seed=1)
+    m.fit_normalization(pairs)
+    loss = m.train(pairs, steps=3000, batch=2048, lr=2e-3, seed=5)
+    _, mse = m.gradient(pairs)
+    print("train loss", loss, "standardised mse on all pairs", mse)
+    assert mse < 0.05                      # > 95% of the target variance explained
+    cfg, prim = li.quadrants(9, n=96)
+    for prec in (lb.FP64, lb.MIXED):
+        a, sa = run_gpu(cfg, prim, 30, precision=prec)
+        mom = gpu_moments(cfg, prim)
+        c = lb.Lelbm(cfg, mom, precision=prec, guess=lb.GUESS_MLP)
+        c.set_mlp(m)
+        sb = c.step(30)
+        b = c.read_moments()
+        c.close()
+        err = rel_linf(b, a)
+        print("precision", prec, "rel_linf", err, "it plain", sa["it_mean_f"], sa["it_mean_g"], "passes",
+              sa["point_passes"] / sa["q_mean"] / sa["cells"], "it mlp", sb["it_mean_f"], sb["it_mean_g"], "passes",
+              sb["point_passes"] / sb["q_mean"] / sb["cells"], "fallbacks", sb["fallbacks"], "cells", sb["cells"])
+        assert err < (1e-10 if prec == lb.FP64 else 1e-5)
+        # the trained guess saves reconstruction passes over Eq. (IID13)
+        assert sb["point_passes"] < sa["point_passes"]
+        assert sb["it_mean_f"] < sa["it_mean_f"] and sb["it_mean_g"] < sa["it_mean_g"]
+    m.close()
