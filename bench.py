@@ -1,22 +1,38 @@
 """Benchmark of the LELBM time step on one MI355X.
 
-Workload: the 2D four-quadrant Riemann input (1024 x 1024 periodic, seeded
+Workload: the 2D four-quadrant Riemann input, 2048 x 2048 periodic (seeded
 states with density U[0.1,1.5], pressure U[0.03,1.5], velocity U[-1.2,1.2]
 times the local sound speed, 1% smooth Fourier density perturbation).  One
 step = one pass of the whole per-cell path (collision, stencil, entropic
 reconstruction) and the moment-streaming gather over all cells.
 
-Prints ONE JSON line (rank 0): MLUPS of the timed steps with inputs resident
-in HBM, per-kernel durations measured with HIP events on the library's stream,
-the roofline of the dominant kernel, and the CPU oracle's MLUPS on a bounded
+Protocol:
+  1. harvest (features -> converged multipliers) pairs from plain FP64 runs of
+     the 1024 x 1024 input on other seeds;
+  2. train the warm-start network on them with the library's own kernels;
+  3. run the 2048 x 2048 input from the same initial state with
+       fp64-eq   plain FP64 path, equilibrium (IID13) Newton guess,
+       mixed-mlp FP32 state/records/streaming + learned Newton guess,
+     (and the two other combinations, for attribution), W untimed warmup
+     steps then K timed steps each, inputs resident in HBM;
+  4. L1 errors of density, velocity and temperature of every run against the
+     fp64-eq run after the same steps.
+
+Prints ONE JSON line: ``value`` = MLUPS of the mixed-mlp run; the FP64 MLUPS,
+the errors, Newton iterations, per-kernel times (HIP events on the library's
+stream), the roofline of the dominant kernel (the per-cell reconstruction
+kernel), the gather's HBM fraction and the CPU oracle's MLUPS on a bounded
 sample of the same workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S]
-                       [--n 1024] [--precision fp64|mixed] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S] [--n 2048]
+                       [--runs fp64-eq,mixed-mlp,...] [--no-cpu] [--no-context]
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,7 +43,10 @@ import numpy as np  # noqa: E402
 
 METRIC = "MLUPS per LELBM step: FP32+learned-EPR vs plain FP64, at matched L1 error"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+# MI355X vector peak: 256 CUs x 64 lanes x 2.4 GHz x 2 (FMA).  FP64 and
+# non-packed FP32 run at the same rate; packed FP32 math is disabled in this
+# build, so the same figure bounds both paths.
+VALU_PEAK_TFLOPS = 78.6
 # Algorithmic FP64 work of one stencil point in one reconstruction pass (2D):
 # 27 monomial products (degree <= 6), 16 multiply-adds for the two exponents,
 # 43 multiply-adds into the fluon (28) and phonon (15) moment sums, and two
@@ -35,8 +54,12 @@ FP64_PEAK_TFLOPS = 78.6
 FLOPS_PER_POINT_PASS_2D = 27 + 2 * 16 + 2 * 43 + 2 * 20
 # Algorithmic bytes of the gather: per arriving stencil point the (w_f, w_g)
 # pair, per destination the written moments, per source its descriptor
-# (velocity and radius).
-GATHER_BYTES_PER_ARRIVAL = {"fp64": 16, "mixed": 8}
+# (velocity, density, temperature, radius: 20 bytes).
+GATHER_PAIR_BYTES = {"fp64": 16, "mixed": 8}
+GATHER_DESC_BYTES = 20
+RUNS = ("fp64-eq", "mixed-mlp", "mixed-eq", "fp64-mlp")
+# The paper's own timings (hot-box advection, 4096^2, RTX 4070), as context.
+PAPER_HOTBOX_S_PER_STEP = {0.5: 10.9, 2.0: 33.8}
 
 
 def parse():
@@ -44,15 +67,65 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--seed", type=int, default=10)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--runs", default=",".join(RUNS))
+    ap.add_argument("--harvest-n", type=int, default=1024)
+    ap.add_argument("--harvest-seeds", default="0,1,2,3")
+    ap.add_argument("--harvest-steps", type=int, default=100)
+    ap.add_argument("--harvest-pairs", type=int, default=10_000_000)
+    ap.add_argument("--train-steps", type=int, default=12000)
+    ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-window", type=int, default=256)
+    ap.add_argument("--cpu-window", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-context", action="store_true", help="skip the hot-box context runs")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def primitives(mom, dim=2, K=3.0):
+    """Density, velocity and RT from raw 2D moments [11][cells] (measurement
+    only)."""
+    rho = mom[0]
+    ux, uy = mom[1] / rho, mom[2] / rho
+    rt = ((mom[3] + mom[5] + mom[8]) / rho - ux * ux - uy * uy) / (dim + K)
+    return rho, ux, uy, rt
+
+
+def l1_errors(a, b):
+    """Relative L1 errors of (rho, u, T) of moments a against reference b."""
+    ra, uxa, uya, ta = primitives(a)
+    rb, uxb, uyb, tb = primitives(b)
+    return {
+        "rho": float(np.abs(ra - rb).sum() / np.abs(rb).sum()),
+        "u": float((np.abs(uxa - uxb) + np.abs(uya - uyb)).sum() / (np.abs(uxb) + np.abs(uyb)).sum()),
+        "T": float(np.abs(ta - tb).sum() / np.abs(tb).sum()),
+    }
+
+
+def stored_traffic():
+    """HBM traffic per launch from committed counter summaries: a line
+    ``TRAFFIC {json}`` in profiles/*.md whose ``source_sha256`` equals the
+    current kernel source (any change to the kernels voids the figure)."""
+    src = os.path.join(ROOT, "paper_2508_06911_amd", "csrc", "lelbm_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    out = {}
+    for p in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(p) as f:
+            for line in f:
+                m = re.match(r"^TRAFFIC (\{.*\})\s*$", line.strip())
+                if m:
+                    d = json.loads(m.group(1))
+                    if d.get("source_sha256") == sha:
+                        out[(d["kernel"], d["workload"])] = d["bytes_per_launch"]
+    return out
 
 
 def cpu_baseline(cfg, prim, window, steps):
@@ -71,10 +144,131 @@ def cpu_baseline(cfg, prim, window, steps):
     el = time.perf_counter() - t0
     if st != 0:
         raise RuntimeError("oracle failed on the CPU sample (%d)" % st)
-    return {"value": window * window * steps / el / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
+    return {"value": round(window * window * steps / el / 1e6, 5), "unit": "MLUPS", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": "%dx%d centre window of the same input, %d steps, no sources outside the window (%.1f s)"
                       % (window, window, steps, el)}
+
+
+def harvest_and_train(a, lb, li, torch):
+    seeds = [int(s) for s in a.harvest_seeds.split(",") if s]
+    cells = a.harvest_n * a.harvest_n
+    stride = max(1, (cells * a.harvest_steps * len(seeds)) // a.harvest_pairs)
+    cap = a.harvest_pairs + cells // stride + 1
+    buf = torch.zeros((cap, 32), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    n = 0
+    for s in seeds:
+        if n >= cap:
+            break
+        cfg, prim = li.quadrants(s, n=a.harvest_n)
+        m = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
+        c = lb.Lelbm(cfg, m)
+        c.harvest(buf[n:], stride=stride)        # each context counts from 0
+        c.step_nostats(a.harvest_steps)
+        n = min(cap, n + c.harvest_count())
+        c.close()
+    torch.cuda.synchronize()
+    t_h = time.perf_counter() - t0
+    log("harvested %d pairs (stride %d) in %.1f s" % (n, stride, t_h))
+    g = torch.Generator(device="cpu").manual_seed(1234)
+    perm = torch.randperm(n, generator=g).to("cuda")
+    nval = min(200_000, n // 20)
+    val = buf[perm[:nval]].contiguous()
+    train = buf[perm[nval:]].contiguous()
+    del buf, perm
+    mlp = lb.Mlp(seed=1)
+    mlp.fit_normalization(train)
+    t0 = time.perf_counter()
+    # three phases of constant-rate Adam with decreasing step size
+    phases = ((0.5, 2e-3), (0.3, 7e-4), (0.2, 2e-4))
+    loss = None
+    for i, (frac, lr) in enumerate(phases):
+        loss = mlp.train(train, steps=max(1, int(a.train_steps * frac)), batch=a.batch, lr=lr, seed=7 + i)
+    torch.cuda.synchronize()
+    t_t = time.perf_counter() - t0
+    _, vmse = mlp.gradient(val)
+    log("trained %d steps in %.1f s: train loss %.4f, held-out mse %.4f" % (a.train_steps, t_t, loss, vmse))
+    info = {"pairs": n, "harvest_grid": "%dx%d" % (a.harvest_n, a.harvest_n), "harvest_seeds": seeds,
+            "harvest_steps": a.harvest_steps, "stride": stride, "harvest_s": round(t_h, 2),
+            "train_steps": a.train_steps, "batch": a.batch, "train_s": round(t_t, 2),
+            "train_mse": round(loss, 5), "heldout_mse": round(vmse, 5),
+            "mse_unit": "per-output standardised (1.0 = predicting the mean)"}
+    del train, val
+    return mlp, info
+
+
+def timed_run(name, a, lb, torch, cfg, mom0, mlp):
+    prec = lb.FP64 if name.startswith("fp64") else lb.MIXED
+    guess = lb.GUESS_MLP if name.endswith("mlp") else lb.GUESS_EQ
+    stream = torch.cuda.current_stream()
+    ctx = lb.Lelbm(cfg, mom0, precision=prec, guess=guess, stream=stream)
+    if guess == lb.GUESS_MLP:
+        ctx.set_mlp(mlp)
+    if a.warmup:
+        ctx.step(a.warmup)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    st = ctx.step(a.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    kt = ctx.kernel_times()
+    persistent, scratch = ctx.memory()
+    mom = ctx.read_moments()
+    ctx.close()
+    ncell = cfg["nx"] * cfg["ny"]
+    prec_name = "fp64" if prec == lb.FP64 else "mixed"
+    epr_ms = kt["epr"][0] / max(kt["epr"][1], 1)
+    gat_ms = kt["gather"][0] / max(kt["gather"][1], 1)
+    # k_epr handles the cells with unrefined stencils; refined cells go to
+    # k_epr_ref (timed apart)
+    flops = (st["point_passes"] - st["point_passes_refined"]) / a.steps * FLOPS_PER_POINT_PASS_2D
+    esz = 8 if prec == lb.FP64 else 4
+    gbytes = (st["arrivals"] / a.steps * GATHER_PAIR_BYTES[prec_name]
+              + ncell * (11 * esz + GATHER_DESC_BYTES))
+    r = {
+        "mlups": ncell * a.steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / a.steps,
+        "epr_ms": epr_ms, "gather_ms": gat_ms, "epr_flops": flops, "gather_bytes": gbytes,
+        "epr_tflops": flops / (epr_ms * 1e-3) / 1e12, "gather_gbs": gbytes / (gat_ms * 1e-3) / 1e9,
+        "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]},
+        "newton_it": {"mean_f": round(st["it_mean_f"], 3), "max_f": st["it_max_f"],
+                      "mean_g": round(st["it_mean_g"], 3), "max_g": st["it_max_g"]},
+        "passes_per_cell": round(st["point_passes"] / max(st["q_mean"], 1e-30) / st["cells"], 3),
+        "refined_share": round(st["point_passes_refined"] / max(st["point_passes"], 1), 5),
+        "fallbacks": st["fallbacks"], "stencil_q": {"min": st["q_min"], "mean": round(st["q_mean"], 1),
+                                                    "max": st["q_max"]},
+        "hbm_bytes": {"persistent": persistent, "scratch": scratch},
+    }
+    log("%-9s %.2f ms/step  %.1f MLUPS  epr %.3f ms  gather %.3f ms  it %.3f/%.3f  passes %.3f"
+        % (name, r["ms_per_step"], r["mlups"], epr_ms, gat_ms, st["it_mean_f"], st["it_mean_g"],
+           r["passes_per_cell"]))
+    return r, mom
+
+
+def hotbox_context(lb, li, torch):
+    """The paper's only timed workload (uniform advection u = (10, 10),
+    4096^2 periodic) on the FP64 path, beside the paper's RTX 4070 times."""
+    out = []
+    for rt, paper_s in PAPER_HOTBOX_S_PER_STEP.items():
+        cfg, prim = li.hotbox(rt, n=4096)
+        m = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
+        c = lb.Lelbm(cfg, m)
+        c.step_nostats(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step_nostats(3)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / 3
+        c.close()
+        out.append({"RT": rt, "cells": 4096 * 4096, "s_per_step": round(el, 5),
+                    "mlups": round(4096 * 4096 / el / 1e6, 2), "paper_s_per_step": paper_s,
+                    "paper_hardware": "RTX 4070 (precision not stated)"})
+        log("hot box RT=%.1f: %.4f s/step (paper %.1f s)" % (rt, el, paper_s))
+    return out
 
 
 def main():
@@ -99,70 +293,74 @@ def main():
     import paper_2508_06911_amd as lb
 
     torch.cuda.set_device(0)
+    runs = [r for r in a.runs.split(",") if r]
+    for r in runs:
+        if r not in RUNS:
+            raise SystemExit("unknown run %r (choose from %s)" % (r, ", ".join(RUNS)))
+    mlp, train_info = (None, None)
+    if any(r.endswith("mlp") for r in runs):
+        mlp, train_info = harvest_and_train(a, lb, li, torch)
+
     cfg, prim = li.quadrants(a.seed, n=a.n)
-    prec = lb.FP64 if a.precision == "fp64" else lb.MIXED
-    m = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
-    stream = torch.cuda.current_stream()
-    ctx = lb.Lelbm(cfg, m, precision=prec, stream=stream)
-    if a.warmup:
-        ctx.step(a.warmup)
-    torch.cuda.synchronize()
-    ctx.set_timing(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    st = ctx.step(a.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    kt = ctx.kernel_times()
-    persistent, scratch = ctx.memory()
-    ctx.close()
+    mom0 = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
+    res_runs, moms = {}, {}
+    for r in runs:
+        res_runs[r], moms[r] = timed_run(r, a, lb, torch, cfg, mom0, mlp)
+    ref = "fp64-eq" if "fp64-eq" in moms else None
+    for r in runs:
+        if ref is not None and r != ref:
+            res_runs[r]["l1_vs_fp64"] = l1_errors(moms[r], moms[ref])
+    del moms
+    head = "mixed-mlp" if "mixed-mlp" in res_runs else runs[0]
+    h = res_runs[head]
+    traffic = stored_traffic()
+    wl = "quadrants%d" % a.n
     ncell = cfg["nx"] * cfg["ny"]
-    mlups = ncell * a.steps / (ms * 1e-3) / 1e6
-
-    epr_ms = kt["epr"][0] / max(kt["epr"][1], 1)
-    gat_ms = kt["gather"][0] / max(kt["gather"][1], 1)
-    flops = st["point_passes"] / a.steps * FLOPS_PER_POINT_PASS_2D
-    epr_tflops = flops / (epr_ms * 1e-3) / 1e12
-    esz = 8 if a.precision == "fp64" else 4
-    gbytes = (st["arrivals"] / a.steps * GATHER_BYTES_PER_ARRIVAL[a.precision]
-              + ncell * (11 * esz + 20))
-    gat_gbs = gbytes / (gat_ms * 1e-3) / 1e9
-
+    prec = "fp64" if head.startswith("fp64") else "mixed"
     res = {
         "metric": METRIC,
-        "value": round(mlups, 3),
+        "value": round(h["mlups"], 3),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms / a.steps, 4),
+        "ms_per_step": round(h["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if a.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "2D four-quadrant Riemann input, %dx%d periodic, seed %d, %s path, "
-                               "equilibrium Newton guess" % (a.n, a.n, a.seed, a.precision),
-                   "cells": ncell, "steps_after_warmup": a.steps},
-        "roofline": {"bound": "alu", "kernel": "k_epr (collision + stencil + Newton reconstruction)",
-                     "achieved": round(epr_tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(epr_tflops / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                     "avg_ms": round(epr_ms, 4),
-                     "flops_per_launch": flops},
-        "ms_gather": {"bound": "hbm", "kernel": "k_gather", "achieved": round(gat_gbs, 1), "peak": HBM_PEAK_GBS,
-                      "unit": "GB/s", "frac": round(gat_gbs / HBM_PEAK_GBS, 4), "avg_ms": round(gat_ms, 4),
-                      "bytes_per_launch": gbytes},
-        "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]},
-        "newton_it": {"mean_f": round(st["it_mean_f"], 3), "max_f": st["it_max_f"],
-                      "mean_g": round(st["it_mean_g"], 3), "max_g": st["it_max_g"]},
-        "stencil_q": {"min": st["q_min"], "mean": round(st["q_mean"], 1), "max": st["q_max"]},
-        "hbm_bytes": {"persistent": persistent, "scratch": scratch},
+        "config": {"workload": "2D four-quadrant Riemann input %dx%d periodic, seed %d; run %s "
+                               "(%s)" % (a.n, a.n, a.seed, head,
+                                         "FP32 state, records and streaming, FP64 reconstruction, "
+                                         "learned Newton guess" if head == "mixed-mlp" else head),
+                   "cells": ncell, "warmup_steps": a.warmup},
+        "fp64_mlups": round(res_runs["fp64-eq"]["mlups"], 3) if "fp64-eq" in res_runs else None,
+        "speedup_vs_fp64": (round(h["mlups"] / res_runs["fp64-eq"]["mlups"], 4)
+                            if "fp64-eq" in res_runs else None),
+        "l1_vs_fp64": h.get("l1_vs_fp64"),
+        "l1_budget": 1e-4,
+        "roofline": {"bound": "alu", "kernel": "k_epr (collision, stencil, Newton reconstruction, records)",
+                     "achieved": round(h["epr_tflops"], 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(h["epr_tflops"] / VALU_PEAK_TFLOPS, 4),
+                     "traffic": traffic.get(("k_epr", wl + "-" + head)),
+                     "avg_ms": round(h["epr_ms"], 4), "flops_per_launch": h["epr_flops"]},
+        "gather_roofline": {"bound": "hbm", "kernel": "k_gather", "achieved": round(h["gather_gbs"], 1),
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(h["gather_gbs"] / HBM_PEAK_GBS, 4),
+                            "traffic": traffic.get(("k_gather", wl + "-" + head)),
+                            "avg_ms": round(h["gather_ms"], 4), "bytes_per_launch": h["gather_bytes"]},
+        "runs": {r: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()
+                     if k not in ("epr_flops", "gather_bytes")} for r, d in res_runs.items()},
     }
+    if train_info is not None:
+        res["mlp"] = train_info
+    if not a.no_context:
+        res["paper_context"] = hotbox_context(lb, li, torch)
+    if mlp is not None:
+        mlp.close()
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline(cfg, prim, a.cpu_window, a.cpu_steps)
-    print(json.dumps(res))
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

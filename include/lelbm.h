@@ -107,6 +107,8 @@ typedef struct {
     long point_passes;                /* sum over cells of q x reconstruction passes
                                          (Newton evaluations + the final population pass) */
     long arrivals;                    /* stencil points deposited into interior cells */
+    long point_passes_refined;        /* the part of point_passes spent on cells with
+                                         refined stencils (Eqs. IIC10-11) */
 } lelbm_stats;
 
 /* Number of stored moments per cell: 6 (1D) or 11 (2D); -1 for other dim. */
@@ -155,8 +157,11 @@ int lelbm_last_failure_detail(const lelbm_ctx *c, int *reason, int *species, dou
 /* Per-kernel timing: when enabled, lelbm_step records HIP events around each
  * kernel and lelbm_kernel_times returns accumulated milliseconds and launch
  * counts for: [0] pad fill, [1] stencil pre-pass, [2] tile scan,
- * [3] collision + reconstruction, [4] moment-streaming gather, [5] stats.
- * n is the capacity of ms and launches. */
+ * [3] collision + reconstruction of cells with unrefined stencils,
+ * [4] moment-streaming gather, [5] unused, [6] learned Newton guess,
+ * [7] collision + reconstruction of cells with refined stencils.
+ * n is the capacity of ms and launches (at most LELBM_NTIMERS are filled). */
+#define LELBM_NTIMERS 8
 int lelbm_set_timing(lelbm_ctx *c, int enable);
 int lelbm_kernel_times(const lelbm_ctx *c, double *ms, long *launches, int n);
 

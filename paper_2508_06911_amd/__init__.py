@@ -51,6 +51,7 @@ class Stats(ctypes.Structure):
         ("rt_min", ctypes.c_double), ("kn_max", ctypes.c_double), ("colat_max", ctypes.c_double),
         ("sum", ctypes.c_double * 4), ("cells", ctypes.c_long),
         ("point_passes", ctypes.c_long), ("arrivals", ctypes.c_long),
+        ("point_passes_refined", ctypes.c_long),
     ]
 
     def as_dict(self):
@@ -223,10 +224,10 @@ class Lelbm:
         _check(lib().lelbm_set_timing(self._h, 1 if on else 0))
 
     def kernel_times(self):
-        ms = (ctypes.c_double * 6)()
-        ln = (ctypes.c_long * 6)()
-        _check(lib().lelbm_kernel_times(self._h, ms, ln, 6))
-        names = ["fill_pads", "prepare", "scan", "epr", "gather", "stats"]
+        ms = (ctypes.c_double * 8)()
+        ln = (ctypes.c_long * 8)()
+        _check(lib().lelbm_kernel_times(self._h, ms, ln, 8))
+        names = ["fill_pads", "prepare", "scan", "epr", "gather", "unused", "guess", "epr_ref"]
         return {n: (ms[i], ln[i]) for i, n in enumerate(names)}
 
     def memory(self):

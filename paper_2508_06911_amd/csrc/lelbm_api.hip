@@ -20,6 +20,13 @@
 
 using namespace lelbm;
 
+// pinned host staging memory (see stage_h2d / stage_d2h)
+struct Stage {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+
 struct lelbm_ctx {
     lelbm_params p;
     Geom g;
@@ -36,8 +43,8 @@ struct lelbm_ctx {
     double last_fail_residual;
     int timing;
     hipEvent_t ev[2];
-    double kms[6];
-    long klaunch[6];
+    double kms[LELBM_NTIMERS];
+    long klaunch[LELBM_NTIMERS];
     // timing mode: event pairs recorded around each kernel, read after the
     // stream synchronisation at the end of lelbm_step
     std::vector<hipEvent_t> evpool;
@@ -48,6 +55,8 @@ struct lelbm_ctx {
     float *mlp_p, *mlp_n;
     int mlp_set;
     long long persistent_bytes;
+    Stage stage;             // pinned host staging memory
+    int gcap;                // staged sources per gather chunk
 };
 
 // HIP errors are reported as LELBM_EDEVICE; with LELBM_DEBUG set in the
@@ -64,6 +73,52 @@ static void report_hip(hipError_t e, const char *what, int line) {
             return LELBM_EDEVICE;                    \
         }                                            \
     } while (0)
+
+// Host <-> device transfers go through pinned staging memory (hipHostMalloc)
+// owned by the context or network; user memory is only touched by host
+// memcpy, so nothing depends on how the runtime treats pageable memory.
+static const size_t STAGE_MAX = (size_t)32 << 20;
+
+static int stage_reserve(Stage &st, size_t bytes) {
+    if (bytes <= st.cap) return LELBM_OK;
+    if (st.p) HIPCHECK(hipHostFree(st.p));
+    st.p = nullptr;
+    st.cap = 0;
+    if (hipHostMalloc(&st.p, bytes, hipHostMallocDefault) != hipSuccess) { st.p = nullptr; return LELBM_ENOMEM; }
+    st.cap = bytes;
+    return LELBM_OK;
+}
+
+static void stage_free(Stage &st) {
+    if (st.p) (void)hipHostFree(st.p);
+    st.p = nullptr;
+    st.cap = 0;
+}
+
+// Contiguous copies in chunks of at most STAGE_MAX bytes.
+static int stage_h2d(Stage &st, hipStream_t s, void *dev, const void *host, size_t bytes) {
+    int r = stage_reserve(st, bytes < STAGE_MAX ? bytes : STAGE_MAX);
+    if (r != LELBM_OK) return r;
+    for (size_t o = 0; o < bytes; o += st.cap) {
+        size_t n = bytes - o < st.cap ? bytes - o : st.cap;
+        memcpy(st.p, (const char *)host + o, n);
+        HIPCHECK(hipMemcpyAsync((char *)dev + o, st.p, n, hipMemcpyHostToDevice, s));
+        HIPCHECK(hipStreamSynchronize(s));
+    }
+    return LELBM_OK;
+}
+
+static int stage_d2h(Stage &st, hipStream_t s, void *host, const void *dev, size_t bytes) {
+    int r = stage_reserve(st, bytes < STAGE_MAX ? bytes : STAGE_MAX);
+    if (r != LELBM_OK) return r;
+    for (size_t o = 0; o < bytes; o += st.cap) {
+        size_t n = bytes - o < st.cap ? bytes - o : st.cap;
+        HIPCHECK(hipMemcpyAsync(st.p, (const char *)dev + o, n, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        memcpy((char *)host + o, st.p, n);
+    }
+    return LELBM_OK;
+}
 
 extern "C" int lelbm_num_moments(int dim) { return dim == 1 ? 6 : (dim == 2 ? 11 : -1); }
 
@@ -137,14 +192,12 @@ static void free_ctx(lelbm_ctx *c) {
     if (c->ev[0]) (void)hipEventDestroy(c->ev[0]);
     if (c->ev[1]) (void)hipEventDestroy(c->ev[1]);
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+    stage_free(c->stage);
     delete c;
 }
 
 static int reset_flags(lelbm_ctx *c) {
-    Flags f;
-    f.err = 0; f.step = -1; f.node = LLONG_MAX; f.need = 0;
-    f.detail = 0; f.species = -1; f.residual = 0.0;
-    HIPCHECK(hipMemcpyAsync(c->b.flags, &f, sizeof(Flags), hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(launch_reset_flags(c->b.flags, c->stream));
     return LELBM_OK;
 }
 
@@ -186,7 +239,14 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     c->last_fail_residual = 0.0;
     c->timing = 0;
     c->evused = 0;
-    for (int k = 0; k < 6; k++) { c->kms[k] = 0; c->klaunch[k] = 0; }
+    // gather staging capacity (LDS per workgroup = 28 B x gcap); the
+    // LELBM_GATHER_CAP environment variable overrides it for tuning
+    c->gcap = GATHER_CAP;
+    if (const char *e = getenv("LELBM_GATHER_CAP")) {
+        int v = atoi(e);
+        if (v >= 256 && v <= GATHER_CAP_MAX) c->gcap = v;
+    }
+    for (int k = 0; k < LELBM_NTIMERS; k++) { c->kms[k] = 0; c->klaunch[k] = 0; }
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return LELBM_EDEVICE; }
     Geom &g = c->g;
     memset(&g, 0, sizeof(g));
@@ -248,37 +308,38 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     return LELBM_OK;
 }
 
-// Copies interior moments (SoA over nx*ny, FP64 or FP32 source on host or
-// device) into the padded state buffer.
+// Copies interior moments (SoA [nmom][ny][nx], FP64 or FP32, on the host or
+// the device) into the padded state buffer.  Host data is converted to the
+// state precision row by row into the pinned stage; device data is copied
+// (and converted) by a kernel.
 static int upload_interior(lelbm_ctx *c, const void *src, int src_fp32, hipMemcpyKind kind) {
     const Geom &g = c->g;
-    size_t esz = c->mixed ? sizeof(float) : sizeof(double);
-    size_t ssz = src_fp32 ? sizeof(float) : sizeof(double);
-    long long n = (long long)g.nx * g.ny;
-    if (ssz != esz) {
-        // convert on the host
-        std::vector<char> host((size_t)c->nmom * n * ssz);
-        if (kind == hipMemcpyDeviceToDevice) {
-            HIPCHECK(hipMemcpyAsync(host.data(), src, host.size(), hipMemcpyDeviceToHost, c->stream));
-            HIPCHECK(hipStreamSynchronize(c->stream));
-        } else {
-            memcpy(host.data(), src, host.size());
-        }
-        std::vector<char> conv((size_t)c->nmom * n * esz);
-        for (long long i = 0; i < (long long)c->nmom * n; i++) {
-            double v = src_fp32 ? ((const float *)host.data())[i] : ((const double *)host.data())[i];
-            if (esz == sizeof(float)) ((float *)conv.data())[i] = (float)v;
-            else ((double *)conv.data())[i] = v;
-        }
-        return upload_interior(c, conv.data(), esz == sizeof(float), hipMemcpyHostToDevice);
+    const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+    const long long n = (long long)g.nx * g.ny;
+    if (kind == hipMemcpyDeviceToDevice) {
+        HIPCHECK(launch_load_interior(g, c->nmom, src, src_fp32, c->b.mom[c->cur], c->mixed, c->stream));
+        HIPCHECK(hipStreamSynchronize(c->stream));
+        return LELBM_OK;
     }
+    const size_t rowb = (size_t)g.nx * esz;
+    const long long rows_per = (long long)(STAGE_MAX / rowb) > 0 ? (long long)(STAGE_MAX / rowb) : 1;
+    int r = stage_reserve(c->stage, (size_t)(rows_per < g.ny ? rows_per : g.ny) * rowb);
+    if (r != LELBM_OK) return r;
     for (int k = 0; k < c->nmom; k++) {
-        char *dst = (char *)c->b.mom[c->cur] + ((size_t)k * g.ns + (size_t)g.wb * g.sxn + g.wl) * esz;
-        const char *s = (const char *)src + (size_t)k * n * esz;
-        HIPCHECK(hipMemcpy2DAsync(dst, (size_t)g.sxn * esz, s, (size_t)g.nx * esz, (size_t)g.nx * esz, g.ny, kind,
-                                  c->stream));
+        for (long long y0 = 0; y0 < g.ny; y0 += rows_per) {
+            const long long ny = g.ny - y0 < rows_per ? g.ny - y0 : rows_per;
+            const long long e0 = (long long)k * n + y0 * g.nx, ne = ny * g.nx;
+            for (long long i = 0; i < ne; i++) {
+                double v = src_fp32 ? (double)((const float *)src)[e0 + i] : ((const double *)src)[e0 + i];
+                if (c->mixed) ((float *)c->stage.p)[i] = (float)v;
+                else ((double *)c->stage.p)[i] = v;
+            }
+            char *dst = (char *)c->b.mom[c->cur] + ((size_t)k * g.ns + (size_t)(y0 + g.wb) * g.sxn + g.wl) * esz;
+            HIPCHECK(hipMemcpy2DAsync(dst, (size_t)g.sxn * esz, c->stage.p, rowb, rowb, (size_t)ny,
+                                      hipMemcpyHostToDevice, c->stream));
+            HIPCHECK(hipStreamSynchronize(c->stream));
+        }
     }
-    HIPCHECK(hipStreamSynchronize(c->stream));
     return LELBM_OK;
 }
 
@@ -290,14 +351,27 @@ static int finish_create(lelbm_ctx *c) {
     HIPCHECK(launch_prepare(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, 0, s));
     HIPCHECK(launch_scan(c->g, c->b, 0, s));
     Flags f;
-    HIPCHECK(hipMemcpyAsync(&f, c->b.flags, sizeof(Flags), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
+    int rr = stage_d2h(c->stage, s, &f, c->b.flags, sizeof(Flags));
+    if (rr != LELBM_OK) return rr;
     if (f.err == ERR_OVERFLOW) {
         int r = grow_scratch(c, f.need);
         if (r != LELBM_OK) return r;
     } else if (f.err != 0) {
         c->last_fail_node = (long)f.node;
         c->last_fail_step = -1;
+        if (getenv("LELBM_DEBUG")) {
+            fprintf(stderr, "lelbm: create pre-pass failed: err %d node %lld step %d\n", f.err, f.node, f.step);
+            if (f.node >= 0 && f.node < c->g.ns) {
+                size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+                for (int k = 0; k < c->nmom; k++) {
+                    double v = 0.0;
+                    float vf = 0.f;
+                    const char *src = (const char *)c->b.mom[c->cur] + ((size_t)k * c->g.ns + (size_t)f.node) * esz;
+                    if (stage_d2h(c->stage, s, c->mixed ? (void *)&vf : (void *)&v, src, esz) == LELBM_OK)
+                        fprintf(stderr, "  moment %d = %.17g\n", k, c->mixed ? (double)vf : v);
+                }
+            }
+        }
         return f.err;
     }
     return reset_flags(c);
@@ -371,15 +445,17 @@ static hipError_t do_prepare(lelbm_ctx *c, void *a) {
     return launch_prepare(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
 }
 static hipError_t do_scan(lelbm_ctx *c, void *a) { return launch_scan(c->g, c->b, ((StepArg *)a)->step, c->stream); }
+static hipError_t do_guess(lelbm_ctx *c, void *) {
+    return launch_mlp_guess(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, c->stream);
+}
 static hipError_t do_epr(lelbm_ctx *c, void *a) {
-    if (c->b.guess) {
-        hipError_t e = launch_mlp_guess(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, c->stream);
-        if (e != hipSuccess) return e;
-    }
     return launch_epr(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
 }
+static hipError_t do_epr_ref(lelbm_ctx *c, void *a) {
+    return launch_epr_ref(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
+}
 static hipError_t do_gather(lelbm_ctx *c, void *) {
-    return launch_gather(c->g, c->mixed, c->b.mom[c->cur ^ 1], c->b, c->stream);
+    return launch_gather(c->g, c->mixed, c->b.mom[c->cur ^ 1], c->b, c->gcap, c->stream);
 }
 
 extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
@@ -400,13 +476,14 @@ extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
             if ((r = timed(c, 0, do_fill, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 1, do_prepare, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 2, do_scan, &a)) != LELBM_OK) return r;
+            if (c->b.guess && (r = timed(c, 6, do_guess, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 3, do_epr, &a)) != LELBM_OK) return r;
+            if ((r = timed(c, 7, do_epr_ref, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 4, do_gather, &a)) != LELBM_OK) return r;
             c->cur ^= 1;
         }
         Flags f;
-        HIPCHECK(hipMemcpyAsync(&f, c->b.flags, sizeof(Flags), hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipStreamSynchronize(s));
+        if ((r = stage_d2h(c->stage, s, &f, c->b.flags, sizeof(Flags))) != LELBM_OK) return r;
         if (c->timing && (r = collect_times(c)) != LELBM_OK) return r;
         if (f.err == 0) break;
         // every kernel after the failing one returned early, so the state at
@@ -428,10 +505,10 @@ extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
         HIPCHECK(launch_sums(c->g, c->mixed, c->b.mom[c->cur], c->b, s));
         DevStats ds;
         double sums[4];
-        HIPCHECK(hipMemcpyAsync(&ds, c->b.stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipMemcpyAsync(sums, c->b.partial + (size_t)num_sum_blocks(c->g) * 4, sizeof(sums),
-                                hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipStreamSynchronize(s));
+        if ((r = stage_d2h(c->stage, s, &ds, c->b.stats, sizeof(DevStats))) != LELBM_OK) return r;
+        if ((r = stage_d2h(c->stage, s, sums, c->b.partial + (size_t)num_sum_blocks(c->g) * 4, sizeof(sums))) !=
+            LELBM_OK)
+            return r;
         memset(st, 0, sizeof(*st));
         double cells = ds.cells ? (double)ds.cells : 1.0;
         st->it_mean_f = ds.it_sum_f / cells;
@@ -451,36 +528,41 @@ extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
         st->cells = (long)ds.cells;
         st->point_passes = (long)ds.qpass_sum;
         st->arrivals = (long)ds.arrivals;
+        st->point_passes_refined = (long)ds.qpass_ref_sum;
     }
     return LELBM_OK;
 }
 
-static int read_common(const lelbm_ctx *c, void *out, hipMemcpyKind kind, bool sync) {
+// Interior moments as FP64 SoA [nmom][ny][nx]: to the host through the
+// pinned stage (row chunks, widened on the host), or to the device by a
+// kernel.
+static int read_common(const lelbm_ctx *cc, void *out, hipMemcpyKind kind, bool sync) {
+    lelbm_ctx *c = const_cast<lelbm_ctx *>(cc);     // the stage is scratch state
     const Geom &g = c->g;
-    size_t esz = c->mixed ? sizeof(float) : sizeof(double);
-    long long n = (long long)g.nx * g.ny;
-    if (c->mixed) {
-        std::vector<float> tmp((size_t)c->nmom * n);
-        for (int k = 0; k < c->nmom; k++) {
-            const char *src = (const char *)c->b.mom[c->cur] + ((size_t)k * g.ns + (size_t)g.wb * g.sxn + g.wl) * esz;
-            HIPCHECK(hipMemcpy2DAsync(tmp.data() + (size_t)k * n, (size_t)g.nx * esz, src, (size_t)g.sxn * esz,
-                                      (size_t)g.nx * esz, g.ny, hipMemcpyDeviceToHost, c->stream));
-        }
-        HIPCHECK(hipStreamSynchronize(c->stream));
-        std::vector<double> d(tmp.begin(), tmp.end());
-        if (kind == hipMemcpyDeviceToHost) memcpy(out, d.data(), d.size() * sizeof(double));
-        else {
-            HIPCHECK(hipMemcpyAsync(out, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-            HIPCHECK(hipStreamSynchronize(c->stream));
-        }
+    const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+    const long long n = (long long)g.nx * g.ny;
+    if (kind == hipMemcpyDeviceToDevice) {
+        HIPCHECK(launch_store_interior(g, c->nmom, c->b.mom[c->cur], c->mixed, (double *)out, c->stream));
+        if (sync) HIPCHECK(hipStreamSynchronize(c->stream));
         return LELBM_OK;
     }
+    const size_t rowb = (size_t)g.nx * esz;
+    const long long rows_per = (long long)(STAGE_MAX / rowb) > 0 ? (long long)(STAGE_MAX / rowb) : 1;
+    int r = stage_reserve(c->stage, (size_t)(rows_per < g.ny ? rows_per : g.ny) * rowb);
+    if (r != LELBM_OK) return r;
     for (int k = 0; k < c->nmom; k++) {
-        const char *src = (const char *)c->b.mom[c->cur] + ((size_t)k * g.ns + (size_t)g.wb * g.sxn + g.wl) * esz;
-        HIPCHECK(hipMemcpy2DAsync((char *)out + (size_t)k * n * esz, (size_t)g.nx * esz, src, (size_t)g.sxn * esz,
-                                  (size_t)g.nx * esz, g.ny, kind, c->stream));
+        for (long long y0 = 0; y0 < g.ny; y0 += rows_per) {
+            const long long ny = g.ny - y0 < rows_per ? g.ny - y0 : rows_per;
+            const char *src = (const char *)c->b.mom[c->cur] + ((size_t)k * g.ns + (size_t)(y0 + g.wb) * g.sxn + g.wl) * esz;
+            HIPCHECK(hipMemcpy2DAsync(c->stage.p, rowb, src, (size_t)g.sxn * esz, rowb, (size_t)ny,
+                                      hipMemcpyDeviceToHost, c->stream));
+            HIPCHECK(hipStreamSynchronize(c->stream));
+            double *o = (double *)out + (long long)k * n + y0 * g.nx;
+            const long long ne = ny * g.nx;
+            for (long long i = 0; i < ne; i++)
+                o[i] = c->mixed ? (double)((const float *)c->stage.p)[i] : ((const double *)c->stage.p)[i];
+        }
     }
-    if (sync) HIPCHECK(hipStreamSynchronize(c->stream));
     return LELBM_OK;
 }
 
@@ -518,7 +600,7 @@ extern "C" int lelbm_set_timing(lelbm_ctx *c, int enable) {
 
 extern "C" int lelbm_kernel_times(const lelbm_ctx *c, double *ms, long *launches, int n) {
     if (!c || n < 0) return LELBM_EINVAL;
-    for (int k = 0; k < n && k < 6; k++) {
+    for (int k = 0; k < n && k < LELBM_NTIMERS; k++) {
         if (ms) ms[k] = c->kms[k];
         if (launches) launches[k] = c->klaunch[k];
     }
@@ -550,6 +632,7 @@ struct lelbm_mlp {
     float *partial, *lossp, *grad;
     long long part_cap;          // waves the partial buffer holds
     long long t;                 // Adam step counter
+    Stage stage;                 // pinned host staging memory
 };
 
 static unsigned long long splitmix(unsigned long long &st) {
@@ -564,6 +647,7 @@ static void mlp_free(lelbm_mlp *m) {
     void *ptrs[] = {m->params, m->m1, m->m2, m->wb, m->partial, m->lossp, m->grad, m->norm};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    stage_free(m->stage);
     delete m;
 }
 
@@ -616,10 +700,10 @@ extern "C" int lelbm_mlp_create(const float *params, unsigned long long seed, vo
     }
     std::vector<float> z(MLP_NPARAM, 0.f), nm(MLP_NORM, 0.f);
     for (int k = 0; k < 16; k++) { nm[16 + k] = 1.f; nm[48 + k] = 1.f; }   // identity standardisation
-    if (hipMemcpy(m->params, h.data(), MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(m->norm, nm.data(), MLP_NORM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(m->m1, z.data(), MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(m->m2, z.data(), MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+    if (stage_h2d(m->stage, m->stream, m->params, h.data(), MLP_NPARAM * sizeof(float)) != LELBM_OK ||
+        stage_h2d(m->stage, m->stream, m->norm, nm.data(), MLP_NORM * sizeof(float)) != LELBM_OK ||
+        stage_h2d(m->stage, m->stream, m->m1, z.data(), MLP_NPARAM * sizeof(float)) != LELBM_OK ||
+        stage_h2d(m->stage, m->stream, m->m2, z.data(), MLP_NPARAM * sizeof(float)) != LELBM_OK ||
         launch_mlp_to_bf16(m->params, m->wb, m->stream) != hipSuccess ||
         hipStreamSynchronize(m->stream) != hipSuccess) {
         mlp_free(m);
@@ -631,9 +715,7 @@ extern "C" int lelbm_mlp_create(const float *params, unsigned long long seed, vo
 
 extern "C" int lelbm_mlp_get_params(const lelbm_mlp *m, float *host_out) {
     if (!m || !host_out) return LELBM_EINVAL;
-    HIPCHECK(hipMemcpyAsync(host_out, m->params, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
-    HIPCHECK(hipStreamSynchronize(m->stream));
-    return LELBM_OK;
+    return stage_d2h(const_cast<lelbm_mlp *>(m)->stage, m->stream, host_out, m->params, MLP_NPARAM * sizeof(float));
 }
 
 extern "C" int lelbm_mlp_forward(lelbm_mlp *m, const float *dev_x, long long x_stride, long long n, float *dev_y) {
@@ -652,10 +734,9 @@ extern "C" int lelbm_mlp_gradient(lelbm_mlp *m, const float *dev_pairs, long lon
     HIPCHECK(launch_mlp_fwdbwd(m->wb, m->params, m->norm, dev_pairs, n, n, 0, 0, 0, m->partial, m->lossp, m->stream));
     HIPCHECK(launch_mlp_adam(m->partial, (int)waves, m->params, m->m1, m->m2, m->wb, 0.f, 1, 0, m->grad, m->stream));
     std::vector<float> lp(waves);
-    HIPCHECK(hipMemcpyAsync(lp.data(), m->lossp, waves * sizeof(float), hipMemcpyDeviceToHost, m->stream));
-    if (host_grad)
-        HIPCHECK(hipMemcpyAsync(host_grad, m->grad, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
-    HIPCHECK(hipStreamSynchronize(m->stream));
+    if ((r = stage_d2h(m->stage, m->stream, lp.data(), m->lossp, waves * sizeof(float))) != LELBM_OK) return r;
+    if (host_grad && (r = stage_d2h(m->stage, m->stream, host_grad, m->grad, MLP_NPARAM * sizeof(float))) != LELBM_OK)
+        return r;
     if (loss) {
         double a = 0;
         for (float v : lp) a += v;
@@ -679,8 +760,7 @@ extern "C" int lelbm_mlp_train(lelbm_mlp *m, const float *dev_pairs, long long n
     }
     if (final_loss) {
         std::vector<float> lp(waves);
-        HIPCHECK(hipMemcpyAsync(lp.data(), m->lossp, waves * sizeof(float), hipMemcpyDeviceToHost, m->stream));
-        HIPCHECK(hipStreamSynchronize(m->stream));
+        if ((r = stage_d2h(m->stage, m->stream, lp.data(), m->lossp, waves * sizeof(float))) != LELBM_OK) return r;
         double a = 0;
         for (float v : lp) a += v;
         *final_loss = a / ((double)batch * MLP_OUT);
@@ -699,18 +779,14 @@ extern "C" int lelbm_mlp_fit_normalization(lelbm_mlp *m, const float *dev_pairs,
 
 extern "C" int lelbm_mlp_get_norm(const lelbm_mlp *m, float *host_out) {
     if (!m || !host_out) return LELBM_EINVAL;
-    HIPCHECK(hipMemcpyAsync(host_out, m->norm, MLP_NORM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
-    HIPCHECK(hipStreamSynchronize(m->stream));
-    return LELBM_OK;
+    return stage_d2h(const_cast<lelbm_mlp *>(m)->stage, m->stream, host_out, m->norm, MLP_NORM * sizeof(float));
 }
 
 extern "C" int lelbm_mlp_set_norm(lelbm_mlp *m, const float *host_norm) {
     if (!m || !host_norm) return LELBM_EINVAL;
     for (int k = 0; k < 16; k++)
         if (!(host_norm[48 + k] > 0.f) || !std::isfinite(host_norm[16 + k])) return LELBM_EINVAL;
-    HIPCHECK(hipMemcpyAsync(m->norm, host_norm, MLP_NORM * sizeof(float), hipMemcpyHostToDevice, m->stream));
-    HIPCHECK(hipStreamSynchronize(m->stream));
-    return LELBM_OK;
+    return stage_h2d(m->stage, m->stream, m->norm, host_norm, MLP_NORM * sizeof(float));
 }
 
 extern "C" void lelbm_mlp_destroy(lelbm_mlp *m) {
@@ -745,16 +821,14 @@ extern "C" int lelbm_harvest(lelbm_ctx *c, float *dev_buf, long long capacity, i
     c->b.harvest_cap = capacity;
     c->b.harvest_stride = stride;
     unsigned long long zero = 0;
-    HIPCHECK(hipMemcpyAsync(c->b.harvest_n, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
-    HIPCHECK(hipStreamSynchronize(c->stream));
-    return LELBM_OK;
+    return stage_h2d(c->stage, c->stream, c->b.harvest_n, &zero, sizeof(zero));
 }
 
 extern "C" int lelbm_harvest_count(const lelbm_ctx *c, long long *n) {
     if (!c || !n) return LELBM_EINVAL;
     unsigned long long v = 0;
-    HIPCHECK(hipMemcpyAsync(&v, c->b.harvest_n, sizeof(v), hipMemcpyDeviceToHost, c->stream));
-    HIPCHECK(hipStreamSynchronize(c->stream));
+    int r = stage_d2h(const_cast<lelbm_ctx *>(c)->stage, c->stream, &v, c->b.harvest_n, sizeof(v));
+    if (r != LELBM_OK) return r;
     *n = (long long)(v < (unsigned long long)c->b.harvest_cap ? v : (unsigned long long)c->b.harvest_cap);
     return LELBM_OK;
 }

@@ -14,6 +14,9 @@ constexpr int TILE_N = 256;
 constexpr int MAX_REFINE = 3;       // supported stencil refinement levels
 constexpr int MAX_RADIUS = 128;     // largest acoustic radius (RT up to ~1000)
 constexpr double MAX_SPEED = 2048.0;  // largest |u| component in cells per step
+// staged sources per gather chunk (28 B of LDS each)
+constexpr int GATHER_CAP = 1024;
+constexpr int GATHER_CAP_MAX = 2340;      // 64 KiB of LDS
 constexpr double MIXED_TOL_FLOOR = 1e-8;  // Newton tolerance of the mixed path (records are FP32)
 
 // Warm-start network: 16 inputs, two hidden layers of 64, 16 outputs.
@@ -62,7 +65,7 @@ struct Flags {
 };
 
 struct DevStats {
-    unsigned long long it_sum_f, it_sum_g, q_sum, limited, cells, fallbacks, qpass_sum, arrivals;
+    unsigned long long it_sum_f, it_sum_g, q_sum, limited, cells, fallbacks, qpass_sum, arrivals, qpass_ref_sum;
     int it_max_f, it_max_g, q_max, q_min;
     unsigned long long rt_min_bits, kn_max_bits, colat_max_bits;
 };
@@ -114,10 +117,16 @@ hipError_t launch_prepare(const Geom &g, const Phys &ph, int mixed, const void *
 hipError_t launch_scan(const Geom &g, Buffers &b, int step, hipStream_t s);
 hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
                       hipStream_t s);
-hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, hipStream_t s);
+hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
+                          hipStream_t s);
+hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, int gcap, hipStream_t s);
 hipError_t launch_sums(const Geom &g, int mixed, const void *mom, Buffers &b, hipStream_t s);
 hipError_t launch_reset_step(const Geom &g, Buffers &b, hipStream_t s);
 hipError_t launch_reset_stats(Buffers &b, hipStream_t s);
+hipError_t launch_reset_flags(Flags *f, hipStream_t s);
+hipError_t launch_load_interior(const Geom &g, int nmom, const void *src, int src_fp32, void *dst, int dst_fp32,
+                                hipStream_t s);
+hipError_t launch_store_interior(const Geom &g, int nmom, const void *src, int src_fp32, double *dst, hipStream_t s);
 int num_sum_blocks(const Geom &g);
 hipError_t launch_mlp_guess(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, hipStream_t s);
 hipError_t launch_mlp_fwdbwd(const unsigned short *Wb, const float *bias, const float *nm, const float *pairs,

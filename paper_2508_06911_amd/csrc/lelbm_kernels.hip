@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <climits>
+
 #include "lelbm_internal.h"
 #include "lelbm_mlp_dev.h"
 
@@ -663,11 +665,13 @@ struct CellStats {
     int it_f = 0, it_g = 0, q = 0, lim = 0, pass = 0, fb = 0;
     double kn = 0.0, colat = 0.0, rt = 1e300;
     bool active = false;
+    bool refined = false;    // handled by the refined-stencil kernel
 };
 
 __device__ inline void push_stats(DevStats *st, const CellStats &c) {
     unsigned long long a_itf = c.it_f, a_itg = c.it_g, a_q = c.q, a_lim = c.lim, a_cells = c.active ? 1 : 0;
     unsigned long long a_qp = (unsigned long long)c.q * c.pass, a_fb = c.fb;
+    unsigned long long a_qpr = c.refined ? a_qp : 0ull;
     int m_itf = c.it_f, m_itg = c.it_g, m_q = c.q, n_q = c.active ? c.q : 1 << 30;
     double m_kn = c.kn, m_colat = c.colat, n_rt = c.rt;
     for (int off = 32; off > 0; off >>= 1) {
@@ -677,6 +681,7 @@ __device__ inline void push_stats(DevStats *st, const CellStats &c) {
         a_lim += __shfl_xor(a_lim, off);
         a_cells += __shfl_xor(a_cells, off);
         a_qp += __shfl_xor(a_qp, off);
+        a_qpr += __shfl_xor(a_qpr, off);
         a_fb += __shfl_xor(a_fb, off);
         m_itf = max(m_itf, __shfl_xor(m_itf, off));
         m_itg = max(m_itg, __shfl_xor(m_itg, off));
@@ -693,6 +698,7 @@ __device__ inline void push_stats(DevStats *st, const CellStats &c) {
         atomicAdd(&st->limited, a_lim);
         atomicAdd(&st->cells, a_cells);
         atomicAdd(&st->qpass_sum, a_qp);
+        if (a_qpr) atomicAdd(&st->qpass_ref_sum, a_qpr);
         if (a_fb) atomicAdd(&st->fallbacks, a_fb);
         atomicMax(&st->it_max_f, m_itf);
         atomicMax(&st->it_max_g, m_itg);
@@ -1002,6 +1008,7 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
     int rn = valid ? b.desc_rn[s] : -1;
     CellStats cs;
     cs.active = rn >= 0 && (rn >> 16) > 0;
+    cs.refined = true;
     if (cs.active) {
         const TileInfo ti = b.tiles[t];
         double rho = b.desc_rho[s], ux = b.desc_u[s], uy = b.desc_u[g.ns + s], RT = b.desc_rt[s];
@@ -1182,9 +1189,10 @@ hipError_t launch_mlp_guess(const Geom &g, const Phys &ph, int mixed, const void
 // scratch record address, mirror flags) are staged in LDS once per
 // workgroup, so the per-candidate work is the exact disk test of the source's
 // stencil (the same FP64 predicate its reconstruction used) and, on a hit, one
-// coalesced read of the moment fractions.
+// coalesced read of the moment fractions.  Along a window row c_y is fixed,
+// so the row accumulates sum w_f c_x^k (k <= 3) and sum w_g c_x^k (k <= 1)
+// and the eleven moments are formed once per row.
 // ---------------------------------------------------------------------------
-constexpr int G_CAP = 1792;   // staged sources per chunk (LDS: 28 B each)
 constexpr int GU = 8;         // candidates per batch in the gather
 
 struct Resolved {
@@ -1248,13 +1256,23 @@ template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
-template <typename T, int D>
-__global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
+// Gather LDS per staged source: velocity (16 B), record base (8 B), meta (4 B).
+constexpr int G_ENTRY_BYTES = 28;
+// meta bits: [0,8) radius R, 8 / 9 mirrored in x / y, 10 refined (all-moment
+// records), [11,32) slot box width of the source tile; -1 = no source
+constexpr int META_FX = 1 << 8, META_FY = 1 << 9, META_REF = 1 << 10;
+
+// WALLS: some face is a slip wall (sources may be mirror images).  Sources
+// with refined stencils are skipped by the main scan and handled by a second
+// scan that runs only in workgroups whose staged region holds one.
+template <typename T, int D, bool WALLS>
+__global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b, int gcap) {
     constexpr int NM = Basis<D>::NMOM;
-    __shared__ double s_ux[G_CAP], s_uy[G_CAP];
-    __shared__ long long s_a0[G_CAP];
-    __shared__ int s_meta[G_CAP];
-    __shared__ int s_err;
+    extern __shared__ double2 g_lds[];
+    double2 *s_u = g_lds;
+    long long *s_a0 = (long long *)(s_u + gcap);
+    int *s_meta = (int *)(s_a0 + gcap);
+    __shared__ int s_err, s_ref;
     if (threadIdx.x == 0) s_err = b.flags->err;
     __syncthreads();
     if (s_err) return;
@@ -1269,15 +1287,21 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
     T acc[NM];
 #pragma unroll
     for (int k = 0; k < NM; k++) acc[k] = 0;
-    unsigned long long hits = 0;
-    const int RW = g.tx + (w.hix - w.lox);          // staged region width
-    int rows = G_CAP / RW - (g.ty - 1);             // window rows per chunk
+    int hits = 0;
+    // staged region: window columns plus GU - 1 more, so that a batch that
+    // runs past the window's low edge reads real entries (whose disk test
+    // fails: those displacements lie outside every reaching source's box)
+    const int RW = g.tx + (w.hix - w.lox) + GU - 1;
+    int rows = gcap / RW - (g.ty - 1);              // window rows per chunk
     if (w.lox <= w.hix && rows >= 1) {
         for (int dy0 = w.hiy; dy0 >= w.loy; dy0 -= rows) {
             const int dy1 = max(w.loy, dy0 - rows + 1);
             const int RH = g.ty + (dy0 - dy1);
             const int rx0 = tx0 - w.hix, ry0 = ty0 - dy0;
             __syncthreads();
+            if (threadIdx.x == 0) s_ref = 0;
+            __syncthreads();
+            int anyref = 0;
             for (int i = threadIdx.x; i < RW * RH; i += 256) {
                 Resolved rs = resolve_source<D>(g, rx0 + i % RW, ry0 + i / RW);
                 int meta = -1;
@@ -1292,74 +1316,97 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
                         long long recsz = ti.fmt ? NM : 2;
                         s_a0[i] = ti.base + (long long)loc * recsz -
                                   ((long long)ti.oy * ti.wx + ti.ox) * TILE_N * recsz;
-                        s_ux[i] = b.desc_u[s];
-                        s_uy[i] = b.desc_u[g.ns + s];
-                        meta = (rn & 0xff) | (rs.fx << 8) | (rs.fy << 9) | (ti.fmt << 10) | (ti.wx << 11);
+                        s_u[i] = make_double2(b.desc_u[s], b.desc_u[g.ns + s]);
+                        meta = (rn & 0xff) | (rs.fx ? META_FX : 0) | (rs.fy ? META_FY : 0) |
+                               (ti.fmt ? META_REF : 0) | (ti.wx << 11);
+                        anyref |= ti.fmt;
                     }
                 }
+                if (meta < 0) s_u[i] = make_double2(0.0, 0.0);
                 s_meta[i] = meta;
             }
+            if (anyref) s_ref = 1;
             __syncthreads();
-            if (mine) {
-                for (int dy = dy0; dy >= dy1; dy--) {
-                    const int rowbase = (ly + (dy0 - dy)) * RW + lx + w.hix;
-                    // candidates in batches of GU so that the LDS and global
-                    // reads of a batch are in flight together
-                    for (int dxb = w.hix; dxb >= w.lox; dxb -= GU) {
-                        int meta[GU], ii[GU];
-                        double cux[GU], cuy[GU];
-                        const T *pp[GU];
+            const bool ref = s_ref != 0;
+            if (!mine) continue;
+            for (int dy = dy0; dy >= dy1; dy--) {
+                const int rowbase = (ly + (dy0 - dy)) * RW + lx + w.hix;
+                // sums over the row of w_f c_x^k (k <= 3) and w_g c_x^k
+                // (k <= 1); c_y enters once per row
+                T a0 = 0, a1 = 0, a2 = 0, a3 = 0, h0 = 0, h1 = 0;
+                const double cyd = (double)dy;
+                // candidates in batches of GU so that the LDS and global
+                // reads of a batch are in flight together
+                for (int dxb = w.hix; dxb >= w.lox; dxb -= GU) {
+                    const int ib = rowbase - dxb;
+                    const double cxb = (double)dxb;
+                    const T *pp[GU];
 #pragma unroll
-                        for (int u = 0; u < GU; u++) {
-                            const bool ok = dxb - u >= w.lox;
-                            ii[u] = rowbase - (ok ? dxb - u : dxb);
-                            meta[u] = s_meta[ii[u]];
-                            if (!ok) meta[u] = -1;
-                            cux[u] = s_ux[ii[u]];
-                            cuy[u] = s_uy[ii[u]];
+                    for (int u = 0; u < GU; u++) {
+                        const int m = s_meta[ib + u];
+                        const double2 cu = s_u[ib + u];
+                        // exact FP64 disk test of the source's stencil
+                        double a, bb;
+                        int rdx = dxb - u, rdy = dy;
+                        if (WALLS) {
+                            if (m & META_FX) rdx = -rdx;
+                            if (m & META_FY) rdy = -rdy;
+                            a = (double)rdx - cu.x;
+                            bb = (double)rdy - cu.y;
+                        } else {
+                            a = (cxb - (double)u) - cu.x;
+                            bb = cyd - cu.y;
                         }
+                        const double rr = (double)(m & 0xff) + 0.5;
+                        bool in;
+                        {
+#pragma clang fp contract(off)
+                            in = a * a + bb * bb <= rr * rr;
+                        }
+                        in = in && m >= 0 && !(m & META_REF);
+                        const T *P = SCR + s_a0[ib + u] + (long long)(rdy * (m >> 11) + rdx) * (TILE_N * 2);
+                        pp[u] = in ? P : nullptr;
+                        hits += in ? 1 : 0;
+                    }
+                    V2 wv[GU];
 #pragma unroll
-                        for (int u = 0; u < GU; u++) {
-                            const int dx = dxb - u, m = meta[u];
-                            pp[u] = nullptr;
-                            if (m < 0) continue;
-                            const int fx = (m >> 8) & 1, fy = (m >> 9) & 1;
-                            const int rdx = fx ? -dx : dx, rdy = fy ? -dy : dy;
-                            const double rr = (m & 0xff) + 0.5;
-                            bool in = D == 2 ? in_disk2((double)rdx, (double)rdy, cux[u], cuy[u], rr)
-                                             : in_disk1((double)rdx, cux[u], rr);
-                            if (!in) continue;
-                            const long long recsz = ((m >> 10) & 1) ? NM : 2;
-                            pp[u] = SCR + s_a0[ii[u]] + ((long long)rdy * (m >> 11) + rdx) * TILE_N * recsz;
-                        }
-                        V2 wv[GU];
+                    for (int u = 0; u < GU; u++) {
+                        wv[u].x = 0; wv[u].y = 0;
+                        if (pp[u]) wv[u] = *(const V2 *)pp[u];
+                    }
+                    const T cxt = (T)dxb;
 #pragma unroll
-                        for (int u = 0; u < GU; u++) {
-                            wv[u].x = 0; wv[u].y = 0;
-                            if (pp[u] && !((meta[u] >> 10) & 1)) wv[u] = *(const V2 *)pp[u];
-                        }
-#pragma unroll
-                        for (int u = 0; u < GU; u++) {
-                            if (!pp[u]) continue;
-                            const int dx = dxb - u, m = meta[u];
-                            hits++;
-                            if ((m >> 10) & 1) {
-                                deposit_record<T, D>(acc, pp[u], 1, dx, dy, (m >> 8) & 1, (m >> 9) & 1);
-                            } else {
-                                T cx = (T)dx, cy = (T)dy;
-                                if (D == 1) {
-                                    acc[0] += wv[u].x; acc[1] += cx * wv[u].x; acc[2] += cx * cx * wv[u].x;
-                                    acc[3] += cx * cx * cx * wv[u].x; acc[4] += wv[u].y; acc[5] += cx * wv[u].y;
-                                } else {
-                                    T cc = cx * cx + cy * cy;
-                                    acc[0] += wv[u].x; acc[1] += cx * wv[u].x; acc[2] += cy * wv[u].x;
-                                    acc[3] += cx * cx * wv[u].x; acc[4] += cx * cy * wv[u].x;
-                                    acc[5] += cy * cy * wv[u].x; acc[6] += cc * cx * wv[u].x;
-                                    acc[7] += cc * cy * wv[u].x; acc[8] += wv[u].y; acc[9] += cx * wv[u].y;
-                                    acc[10] += cy * wv[u].y;
-                                }
-                            }
-                        }
+                    for (int u = 0; u < GU; u++) {
+                        const T cx = cxt - (T)u, wf = wv[u].x, wg = wv[u].y;
+                        const T cw = cx * wf, c2w = cx * cw;
+                        a0 += wf; a1 += cw; a2 += c2w; a3 += cx * c2w;
+                        h0 += wg; h1 += cx * wg;
+                    }
+                }
+                if (D == 1) {
+                    acc[0] += a0; acc[1] += a1; acc[2] += a2; acc[3] += a3; acc[4] += h0; acc[5] += h1;
+                } else {
+                    const T cy = (T)dy, cy2 = cy * cy;
+                    acc[0] += a0; acc[1] += a1; acc[2] += cy * a0;
+                    acc[3] += a2; acc[4] += cy * a1; acc[5] += cy2 * a0;
+                    acc[6] += a3 + cy2 * a1; acc[7] += cy * a2 + cy2 * cy * a0;
+                    acc[8] += h0; acc[9] += h1; acc[10] += cy * h0;
+                }
+                if (ref) {
+                    // sources with refined stencils: pre-summed moment records
+                    for (int dx = w.hix; dx >= w.lox; dx--) {
+                        const int m = s_meta[rowbase - dx];
+                        if (m < 0 || !(m & META_REF)) continue;
+                        const double2 cu = s_u[rowbase - dx];
+                        const int fx = (m & META_FX) ? 1 : 0, fy = (m & META_FY) ? 1 : 0;
+                        const int rdx = fx ? -dx : dx, rdy = fy ? -dy : dy;
+                        const double rr = (m & 0xff) + 0.5;
+                        bool in = D == 2 ? in_disk2((double)rdx, (double)rdy, cu.x, cu.y, rr)
+                                         : in_disk1((double)rdx, cu.x, rr);
+                        if (!in) continue;
+                        hits++;
+                        const T *P = SCR + s_a0[rowbase - dx] + (long long)(rdy * (m >> 11) + rdx) * (TILE_N * NM);
+                        deposit_record<T, D>(acc, P, 1, dx, dy, fx, fy);
                     }
                 }
             }
@@ -1395,8 +1442,9 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b) {
 #pragma unroll
         for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = (T)acc[k];
     }
-    for (int off = 32; off > 0; off >>= 1) hits += __shfl_xor(hits, off);
-    if ((threadIdx.x & 63) == 0 && hits) atomicAdd(&b.stats->arrivals, hits);
+    unsigned long long hl = (unsigned long long)hits;
+    for (int off = 32; off > 0; off >>= 1) hl += __shfl_xor(hl, off);
+    if ((threadIdx.x & 63) == 0 && hl) atomicAdd(&b.stats->arrivals, hl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1409,10 +1457,41 @@ __global__ void k_reset_windows(int n, DWin *w) {
     }
 }
 
+// Interior copies between a contiguous SoA array [nmom][ny][nx] and the
+// padded state, with precision conversion (device to device).
+template <typename S, typename T>
+__global__ void __launch_bounds__(256) k_load_interior(Geom g, int nmom, const S *src, T *dst) {
+    const long long n = (long long)g.nx * g.ny;
+    const long long i = blockIdx.x * 256ll + threadIdx.x;
+    if (i >= n * nmom) return;
+    const long long k = i / n, r = i - k * n;
+    const int y = (int)(r / g.nx), x = (int)(r - (long long)y * g.nx);
+    dst[k * g.ns + (long long)(y + g.wb) * g.sxn + x + g.wl] = (T)src[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_store_interior(Geom g, int nmom, const T *src, double *dst) {
+    const long long n = (long long)g.nx * g.ny;
+    const long long i = blockIdx.x * 256ll + threadIdx.x;
+    if (i >= n * nmom) return;
+    const long long k = i / n, r = i - k * n;
+    const int y = (int)(r / g.nx), x = (int)(r - (long long)y * g.nx);
+    dst[i] = (double)src[k * g.ns + (long long)(y + g.wb) * g.sxn + x + g.wl];
+}
+
+// Flags are cleared on the device, in stream order: no host staging memory
+// has to outlive the call that enqueues the reset.
+__global__ void k_reset_flags(Flags *f) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        f->err = 0; f->step = -1; f->node = LLONG_MAX; f->need = 0;
+        f->detail = 0; f->species = -1; f->residual = 0.0;
+    }
+}
+
 __global__ void k_reset_stats(DevStats *st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->it_sum_f = st->it_sum_g = st->q_sum = st->limited = st->cells = st->fallbacks = 0;
-        st->qpass_sum = st->arrivals = 0;
+        st->qpass_sum = st->qpass_ref_sum = st->arrivals = 0;
         st->it_max_f = st->it_max_g = st->q_max = 0;
         st->q_min = 1 << 30;
         st->rt_min_bits = (unsigned long long)__double_as_longlong(1e300);
@@ -1499,6 +1578,41 @@ hipError_t launch_reset_step(const Geom &g, Buffers &b, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_load_interior(const Geom &g, int nmom, const void *src, int src_fp32, void *dst, int dst_fp32,
+                                hipStream_t s) {
+    const long long tot = (long long)g.nx * g.ny * nmom;
+    if (tot == 0) return hipSuccess;
+    dim3 grid((unsigned)((tot + 255) / 256));
+    if (src_fp32 && dst_fp32)
+        hipLaunchKernelGGL((k_load_interior<float, float>), grid, dim3(256), 0, s, g, nmom, (const float *)src, (float *)dst);
+    else if (src_fp32)
+        hipLaunchKernelGGL((k_load_interior<float, double>), grid, dim3(256), 0, s, g, nmom, (const float *)src,
+                           (double *)dst);
+    else if (dst_fp32)
+        hipLaunchKernelGGL((k_load_interior<double, float>), grid, dim3(256), 0, s, g, nmom, (const double *)src,
+                           (float *)dst);
+    else
+        hipLaunchKernelGGL((k_load_interior<double, double>), grid, dim3(256), 0, s, g, nmom, (const double *)src,
+                           (double *)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_interior(const Geom &g, int nmom, const void *src, int src_fp32, double *dst, hipStream_t s) {
+    const long long tot = (long long)g.nx * g.ny * nmom;
+    if (tot == 0) return hipSuccess;
+    dim3 grid((unsigned)((tot + 255) / 256));
+    if (src_fp32)
+        hipLaunchKernelGGL((k_store_interior<float>), grid, dim3(256), 0, s, g, nmom, (const float *)src, dst);
+    else
+        hipLaunchKernelGGL((k_store_interior<double>), grid, dim3(256), 0, s, g, nmom, (const double *)src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_flags(Flags *f, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_flags, dim3(1), dim3(64), 0, s, f);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset_stats(Buffers &b, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, s, b.stats);
     return hipGetLastError();
@@ -1523,32 +1637,49 @@ hipError_t launch_scan(const Geom &g, Buffers &b, int step, hipStream_t s) {
 }
 
 template <typename T>
-static void epr_launch(const Geom &g, const Phys &ph, const void *mom, Buffers &b, int step, hipStream_t s) {
+static void epr_launch(const Geom &g, const Phys &ph, const void *mom, Buffers &b, int step, int refined,
+                       hipStream_t s) {
     unsigned nt = (unsigned)(g.ntx * g.nty);
     if (g.dim == 1) {
-        hipLaunchKernelGGL((k_epr<T, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
-        hipLaunchKernelGGL((k_epr_ref<T, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        if (refined) hipLaunchKernelGGL((k_epr_ref<T, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        else hipLaunchKernelGGL((k_epr<T, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
     } else {
-        hipLaunchKernelGGL((k_epr<T, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
-        hipLaunchKernelGGL((k_epr_ref<T, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        if (refined) hipLaunchKernelGGL((k_epr_ref<T, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        else hipLaunchKernelGGL((k_epr<T, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
     }
 }
 
 hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
                       hipStream_t s) {
-    if (mixed) epr_launch<float>(g, ph, mom, b, step, s);
-    else epr_launch<double>(g, ph, mom, b, step, s);
+    if (mixed) epr_launch<float>(g, ph, mom, b, step, 0, s);
+    else epr_launch<double>(g, ph, mom, b, step, 0, s);
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, hipStream_t s) {
-    unsigned nt = (unsigned)(g.dtx * g.dty);
+hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
+                          hipStream_t s) {
+    if (mixed) epr_launch<float>(g, ph, mom, b, step, 1, s);
+    else epr_launch<double>(g, ph, mom, b, step, 1, s);
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static void gather_launch(const Geom &g, void *mom_out, Buffers &b, int gcap, hipStream_t s) {
+    const unsigned nt = (unsigned)(g.dtx * g.dty);
+    const size_t lds = (size_t)gcap * G_ENTRY_BYTES;
+    bool walls = false;
+    for (int f = 0; f < 2 * D; f++) walls = walls || g.bc[f] == LELBM_BC_SLIPWALL;
+    if (walls) hipLaunchKernelGGL((k_gather<T, D, true>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap);
+    else hipLaunchKernelGGL((k_gather<T, D, false>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap);
+}
+
+hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, int gcap, hipStream_t s) {
     if (mixed) {
-        if (g.dim == 1) hipLaunchKernelGGL((k_gather<float, 1>), dim3(nt), dim3(256), 0, s, g, (float *)mom_out, b);
-        else hipLaunchKernelGGL((k_gather<float, 2>), dim3(nt), dim3(256), 0, s, g, (float *)mom_out, b);
+        if (g.dim == 1) gather_launch<float, 1>(g, mom_out, b, gcap, s);
+        else gather_launch<float, 2>(g, mom_out, b, gcap, s);
     } else {
-        if (g.dim == 1) hipLaunchKernelGGL((k_gather<double, 1>), dim3(nt), dim3(256), 0, s, g, (double *)mom_out, b);
-        else hipLaunchKernelGGL((k_gather<double, 2>), dim3(nt), dim3(256), 0, s, g, (double *)mom_out, b);
+        if (g.dim == 1) gather_launch<double, 1>(g, mom_out, b, gcap, s);
+        else gather_launch<double, 2>(g, mom_out, b, gcap, s);
     }
     return hipGetLastError();
 }

@@ -100,18 +100,18 @@ def test_learned_guess_matches_plain_path_and_saves_iterations():
     _case("harvest/train/guess quadrants 96x96")
     import torch
     import paper_2508_06911_amd as lb
-    cap = 400000
+    cap = 800000
     buf = torch.zeros((cap, 32), dtype=torch.float32, device="cuda")
     n = 0
     for seed in (0, 1, 2, 3, 4, 5):
         cfg, prim = li.quadrants(seed, n=96)
         c = lb.Lelbm(cfg, gpu_moments(cfg, prim))
-        c.harvest(buf, stride=3)
+        c.harvest(buf[n:], stride=3)           # each context counts from 0
         c.step(40)
-        n = c.harvest_count()
+        n = min(cap, n + c.harvest_count())
         c.close()
     print("harvested", n)
-    assert n > 50000
+    assert n > 400000
     pairs = buf[:n].contiguous()
     m = lb.Mlp(seed=1)
     m.fit_normalization(pairs)
