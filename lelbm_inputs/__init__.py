@@ -17,6 +17,9 @@ Workloads (lattice units, dx = dt = 1):
     1% smooth Fourier density perturbation (structure of the paper's 2D Riemann
     problem, Sec. V.D; the published reference solutions are not used).
   * ``hotbox``     -- uniform periodic advection (Sec. IV.E).
+  * ``channel``    -- supersonic inflow past seeded elliptical obstacles in a
+    channel with slip walls (structure of the paper's blunt-body cases,
+    Sec. V.E; no external reference data is used).
   * ``shear_wave`` / ``acoustic_pulse`` -- the paper's verification problems
     (Sec. IV.A, IV.D).
 
@@ -114,6 +117,59 @@ def quadrants(seed, n=1024, ny=None, rt_floor=RT_FLOOR, perturb=0.01):
     cfg["scale"] = float(s)
     cfg["quadrants_phys"] = quads
     prim = {"rho": rho, "ux": ux * s, "uy": uy * s, "RT": rt_phys * s * s}
+    return cfg, prim
+
+
+def channel(seed, nx=4096, ny=2048, n_obstacles=None, mach=None, size_scale=1.0, pad=24):
+    """Channel with uniform supersonic inflow past 1-4 elliptical obstacles.
+
+    Draw order: Mach ~ U[2, 6] (unless given), obstacle count ~ U{1..4}
+    (unless given), then per obstacle semi-axes a, b ~ U[20, 120] * size_scale,
+    rotation ~ U[0, pi), centre x ~ U[0.15, 0.7] nx, y ~ U[0.2, 0.8] ny,
+    rejected (and redrawn) while it overlaps an earlier obstacle's bounding
+    circle or comes closer than 10 cells to a wall.  Lattice inflow state
+    rho = 1, RT = 1, u = (Ma sqrt(gamma), 0); the initial field is the inflow
+    state everywhere.  A cell is solid iff its centre lies inside an ellipse.
+    Faces: inflow left, zero-gradient outflow right, slip walls top and
+    bottom.  Returns (cfg, prim) with cfg["solid"] a uint8 [ny][nx] mask."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    ma = g.uniform(2.0, 6.0) if mach is None else float(mach)
+    nob = int(g.integers(1, 5)) if n_obstacles is None else int(n_obstacles)
+    obs = []
+    tries = 0
+    while len(obs) < nob:
+        tries += 1
+        if tries > 10000:
+            raise RuntimeError("could not place the obstacles")
+        a = g.uniform(20.0, 120.0) * size_scale
+        b = g.uniform(20.0, 120.0) * size_scale
+        th = g.uniform(0.0, np.pi)
+        cx = g.uniform(0.15, 0.7) * nx
+        cy = g.uniform(0.2, 0.8) * ny
+        r = max(a, b)
+        if cy - r < 10 or cy + r > ny - 10 or cx - r < 10 or cx + r > nx - 10:
+            continue
+        if any(np.hypot(cx - o[3], cy - o[4]) < r + max(o[0], o[1]) for o in obs):
+            continue
+        obs.append((a, b, th, cx, cy))
+    x = (np.arange(nx) + 0.5)[None, :]
+    y = (np.arange(ny) + 0.5)[:, None]
+    solid = np.zeros((ny, nx), dtype=bool)
+    for a, b, th, cx, cy in obs:
+        c, sn = np.cos(th), np.sin(th)
+        xr = (x - cx) * c + (y - cy) * sn
+        yr = -(x - cx) * sn + (y - cy) * c
+        solid |= (xr / a) ** 2 + (yr / b) ** 2 <= 1.0
+    u_in = ma * np.sqrt(GAMMA)
+    cfg = _base_cfg(2, nx, ny, K_2D)
+    cfg["bc"] = ["inflow", "outflow", "slipwall", "slipwall"]
+    cfg["pad"] = pad
+    cfg["in_rho"], cfg["in_u"], cfg["in_RT"] = 1.0, (float(u_in), 0.0), 1.0
+    cfg["solid"] = solid.astype(np.uint8)
+    cfg["mach"] = float(ma)
+    cfg["obstacles"] = obs
+    shape = (ny, nx)
+    prim = {"rho": np.ones(shape), "ux": np.full(shape, u_in), "uy": np.zeros(shape), "RT": np.ones(shape)}
     return cfg, prim
 
 

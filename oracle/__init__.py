@@ -93,6 +93,8 @@ def lib():
         L.orc_epr_initial.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
         L.orc_step.argtypes = [ctypes.POINTER(Params), dp, dp, ctypes.POINTER(Stats)]
         L.orc_run.argtypes = [ctypes.POINTER(Params), dp, dp, ctypes.c_int, ctypes.POINTER(Stats), ip]
+        L.orc_walk.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip]
+        L.orc_walk.restype = None
         _lib = L
     return _lib
 
@@ -131,7 +133,13 @@ def make_params(cfg):
     iu = cfg.get("in_u", (0.0, 0.0))
     p.in_u[0], p.in_u[1] = iu[0], iu[1]
     p.in_RT = cfg.get("in_RT", 1.0)
-    p.solid = None
+    solid = cfg.get("solid")
+    if solid is None:
+        p.solid = None
+    else:
+        m = np.ascontiguousarray(solid, dtype=np.uint8).reshape(p.ny, p.nx)
+        p._solid_ref = m                     # keep the mask alive with the struct
+        p.solid = m.ctypes.data_as(ctypes.c_void_p)
     return p
 
 
@@ -219,6 +227,14 @@ def step(cfg, mom, nsteps=1):
     done = np.zeros(1, dtype=np.int32)
     status = lib().orc_run(ctypes.byref(p), _dp(mom), _dp(out), nsteps, ctypes.byref(st), _ip(done))
     return status, out, st.as_dict(), int(done[0])
+
+
+def walk(cfg, x, y, dx, dy):
+    """Path of one population (Sec. III.B): (final x, final y, sign x, sign y)."""
+    p = make_params(cfg)
+    out = np.zeros(4, dtype=np.int32)
+    lib().orc_walk(ctypes.byref(p), x, y, dx, dy, _ip(out))
+    return tuple(int(v) for v in out)
 
 
 def num_threads():

@@ -22,8 +22,9 @@
  *   - entropic reconstruction .......... Sec. II.D, Eqs. (IID7-11, IID13)
  *   - moment streaming ................. Sec. II.E, Eqs. (IIE3a-b)
  *   - fluid boundaries ................. Sec. III.A
- *   - slip walls ....................... Sec. III.B (specular reflection of
- *                                        the population path)
+ *   - slip walls and solid cells ....... Sec. III.B (specular reflection of
+ *                                        the population path at every face
+ *                                        it would cross into a blocker)
  *
  * Readings taken where the paper is ambiguous are listed in the header
  * comment of each function.
@@ -58,7 +59,7 @@ typedef struct {
     int bc[4];                       /* xlo, xhi, ylo, yhi */
     int pad;                         /* pad width for outflow/inflow faces */
     double in_rho, in_u[2], in_RT;   /* inflow state */
-    const unsigned char *solid;      /* must be NULL in this oracle */
+    const unsigned char *solid;      /* nx*ny legoland mask (1 = solid cell) or NULL */
 } orc_params;
 
 typedef struct {
@@ -653,14 +654,92 @@ static void deposit(int dim, double *acc, double cx, double cy, double wf, doubl
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Path of one population, Sec. III.B.                                        */
+/*                                                                            */
+/* The population leaves the centre of cell (x, y) of the padded domain with  */
+/* integer displacement (dx, dy).  Its straight path crosses the grid lines   */
+/* x = const |dx| times and y = const |dy| times; the k-th crossing of the x  */
+/* lines happens at path parameter (2k - 1) / (2|dx|), likewise for y.  The   */
+/* crossings are taken in order of that parameter (compared exactly in        */
+/* integers), an x crossing before a y crossing at the same parameter (the    */
+/* path through a cell corner).  A crossing into a blocker -- a solid cell or */
+/* the far side of a slip wall -- reverses that velocity component (specular  */
+/* reflection) and the path stays in its cell; otherwise the path enters the  */
+/* neighbouring cell.  Periodic axes wrap.  Reflection keeps |c| per          */
+/* component, so mass and energy are exact.                                   */
+/* Reading: the paper reflects paths at slip boundaries without fixing the     */
+/* order of the two crossings at a corner; x first is our choice.  The walk   */
+/* is reversible (undone by the same walk from the end with the velocity      */
+/* reversed and y first at corners), so every (cell, velocity) pair is        */
+/* reached by exactly one path.                                                */
+/* ------------------------------------------------------------------------ */
+static int blocked(const orc_params *p, int x, int y)
+{
+    if (x < 0 && p->bc[0] == ORC_BC_SLIPWALL) return 1;
+    if (x >= p->nx && p->bc[1] == ORC_BC_SLIPWALL) return 1;
+    if (p->dim == 2 && y < 0 && p->bc[2] == ORC_BC_SLIPWALL) return 1;
+    if (p->dim == 2 && y >= p->ny && p->bc[3] == ORC_BC_SLIPWALL) return 1;
+    if (p->solid && x >= 0 && x < p->nx && y >= 0 && y < p->ny && p->solid[(long)y * p->nx + x]) return 1;
+    return 0;
+}
+
+static int wrap(int v, int n) { v %= n; return v < 0 ? v + n : v; }
+
+static void walk_path(const orc_params *p, int x, int y, int dx, int dy, int *ex, int *ey, int *sgx, int *sgy)
+{
+    int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
+    int sx = dx < 0 ? -1 : 1, sy = dy < 0 ? -1 : 1;
+    int kx = 0, ky = 0;
+    int perx = p->bc[0] == ORC_BC_PERIODIC, pery = p->dim == 2 && p->bc[2] == ORC_BC_PERIODIC;
+    while (kx < ax || ky < ay) {
+        /* next crossing: x if its parameter (2kx+1)/(2ax) is not larger */
+        int takex;
+        if (kx >= ax) takex = 0;
+        else if (ky >= ay) takex = 1;
+        else takex = (long)(2 * kx + 1) * ay <= (long)(2 * ky + 1) * ax;
+        if (takex) {
+            int nx_ = x + sx;
+            if (perx) nx_ = wrap(nx_, p->nx);
+            if (blocked(p, nx_, y)) sx = -sx; else x = nx_;
+            kx++;
+        } else {
+            int ny_ = y + sy;
+            if (pery) ny_ = wrap(ny_, p->ny);
+            if (blocked(p, x, ny_)) sy = -sy; else y = ny_;
+            ky++;
+        }
+    }
+    *ex = x; *ey = y;
+    *sgx = (dx == 0 || (sx < 0) == (dx < 0)) ? 1 : -1;
+    *sgy = (dy == 0 || (sy < 0) == (dy < 0)) ? 1 : -1;
+}
+
+/* Exported for the tests: final cell and component signs of one path. */
+void orc_walk(const orc_params *p, int x, int y, int dx, int dy, int *out)
+{
+    walk_path(p, x, y, dx, dy, &out[0], &out[1], &out[2], &out[3]);
+}
+
 int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
 {
     int D = p->dim, nx = p->nx, ny = p->ny;
     if ((D != 1 && D != 2) || nx <= 0 || ny <= 0 || (D == 1 && ny != 1) || !(p->K > 0.0)) return ORC_EINVAL;
-    if (p->solid) return ORC_EINVAL;
     for (int ax = 0; ax < D; ax++) {
         int a = p->bc[2 * ax], b = p->bc[2 * ax + 1];
         if ((a == ORC_BC_PERIODIC) != (b == ORC_BC_PERIODIC)) return ORC_EINVAL;
+    }
+    if (p->solid) {
+        /* solids are 2D, and may not touch a pad face (its cells copy the
+         * nearest interior cell) */
+        if (D != 2) return ORC_EINVAL;
+        for (int y = 0; y < ny; y++)
+            for (int x = 0; x < nx; x++) {
+                if (!p->solid[(long)y * nx + x]) continue;
+                if ((x == 0 && pad_w(p, 0)) || (x == nx - 1 && pad_w(p, 1)) || (y == 0 && pad_w(p, 2)) ||
+                    (y == ny - 1 && pad_w(p, 3)))
+                    return ORC_EINVAL;
+            }
     }
     int nm = orc_num_moments(D);
     long n = (long)nx * ny;
@@ -682,6 +761,11 @@ int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
         #pragma omp parallel for schedule(dynamic, 16)
         for (long k = c0; k < c1; k++) {
             int sx = (int)(k % sxn) - wl, sy = (int)(k / sxn) - wb;
+            if (p->solid && sx >= 0 && sx < nx && sy >= 0 && sy < ny && p->solid[(long)sy * nx + sx]) {
+                memset(&co[k - c0], 0, sizeof(cell_out));
+                co[k - c0].status = 1;   /* no population */
+                continue;
+            }
             double m[11];
             source_moments(p, in, sx, sy, m);
             process_cell(p, m, &co[k - c0]);
@@ -689,6 +773,7 @@ int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
         /* serial, source-major deposit */
         for (long k = c0; k < c1; k++) {
             cell_out *o = &co[k - c0];
+            if (o->status == 1) continue;   /* solid cell */
             if (o->status != ORC_OK) {
                 if (status == ORC_OK) { status = o->status; s.fail_cell = k; s.fail_code = o->status; }
                 continue;
@@ -708,28 +793,13 @@ int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
             double colat = umag + orc_las_radius(o->RT, p->n_conf, p->r_min);   /* Eq. (IIC7) */
             if (colat > s.colat_max) s.colat_max = colat;
             for (int i = 0; i < o->q; i++) {
-                int lx = sx + o->d[2 * i], ly = sy + o->d[2 * i + 1];
-                double cx = o->c[2 * i], cy = o->c[2 * i + 1];
-                /* periodic wrap */
-                if (p->bc[0] == ORC_BC_PERIODIC) { lx %= nx; if (lx < 0) lx += nx; }
-                if (D == 2 && p->bc[2] == ORC_BC_PERIODIC) { ly %= ny; if (ly < 0) ly += ny; }
-                /* specular reflection at slip walls (one bounce per face) */
-                if (p->bc[0] == ORC_BC_SLIPWALL && lx < 0) { lx = -1 - lx; cx = -cx; }
-                if (p->bc[1] == ORC_BC_SLIPWALL && lx >= nx) { lx = 2 * nx - 1 - lx; cx = -cx; }
-                if (D == 2 && p->bc[2] == ORC_BC_SLIPWALL && ly < 0) { ly = -1 - ly; cy = -cy; }
-                if (D == 2 && p->bc[3] == ORC_BC_SLIPWALL && ly >= ny) { ly = 2 * ny - 1 - ly; cy = -cy; }
-                if (lx < 0 || lx >= nx || ly < 0 || ly >= ny) {
-                    /* arrivals in pads are discarded (Sec. III.A); a path
-                     * still beyond a wall after its reflection is a reach
-                     * error */
-                    int beyond = (lx < 0 && p->bc[0] == ORC_BC_SLIPWALL) || (lx >= nx && p->bc[1] == ORC_BC_SLIPWALL) ||
-                                 (D == 2 && ly < 0 && p->bc[2] == ORC_BC_SLIPWALL) ||
-                                 (D == 2 && ly >= ny && p->bc[3] == ORC_BC_SLIPWALL);
-                    if (beyond) {
-                        if (status == ORC_OK) { status = ORC_EREACH; s.fail_cell = k; s.fail_code = ORC_EREACH; }
-                    }
-                    continue;
-                }
+                /* the path of the (base) point, Sec. III.B; refined children
+                 * follow their parent's path and flips */
+                int lx, ly, fx, fy;
+                walk_path(p, sx, sy, o->d[2 * i], D == 2 ? o->d[2 * i + 1] : 0, &lx, &ly, &fx, &fy);
+                double cx = fx * o->c[2 * i], cy = fy * o->c[2 * i + 1];
+                /* arrivals in pads are discarded (Sec. III.A) */
+                if (lx < 0 || lx >= nx || ly < 0 || ly >= ny) continue;
                 double a[11] = {0};
                 deposit(D, a, cx, cy, o->wf[i], o->wg[i]);
                 long dst = (long)ly * nx + lx;

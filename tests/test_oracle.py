@@ -467,3 +467,117 @@ def test_failure_is_reported_not_clamped():
     assert st == oracle.EEPR
     assert done == 0
     assert stats["fail_cell"] == 5
+
+
+# --------------------------------------------------------------------------
+# Paths through slip walls and solid cells (Sec. III.B)
+# --------------------------------------------------------------------------
+def _obstacle_cfg(nx=14, ny=12, seed=0, density=0.15, bc=("periodic", "periodic", "slipwall", "slipwall")):
+    cfg, _ = li.hotbox(1.0, n=nx, ny=ny)
+    cfg["bc"] = list(bc)
+    rng = np.random.default_rng(seed)
+    cfg["solid"] = (rng.random((ny, nx)) < density).astype(np.uint8)
+    return cfg
+
+
+def test_walk_without_blockers_is_a_straight_path():
+    cfg, _ = li.hotbox(1.0, n=9, ny=7)
+    for (x, y, dx, dy) in [(0, 0, 3, -2), (8, 6, 4, 5), (4, 3, -9, 0), (2, 5, 0, -13)]:
+        assert oracle.walk(cfg, x, y, dx, dy) == ((x + dx) % 9, (y + dy) % 7, 1, 1)
+
+
+def test_walk_reflects_once_at_a_slip_wall_like_a_mirror():
+    cfg, _ = li.hotbox(1.0, n=9, ny=7)
+    cfg["bc"] = ["periodic", "periodic", "slipwall", "slipwall"]
+    for y in range(7):
+        for dy in range(-6, 7):
+            t = y + dy
+            ey, sg = (t, 1) if 0 <= t < 7 else ((-1 - t, -1) if t < 0 else (13 - t, -1))
+            if 0 <= ey < 7:
+                assert oracle.walk(cfg, 4, y, 2, dy) == (6, ey, 1, sg if dy else 1)
+
+
+def test_walk_is_a_speed_preserving_bijection():
+    """Every (cell, velocity) pair is reached by exactly one path, paths end
+    in fluid cells, and reflections keep |c_x| and |c_y|: mass and energy
+    are deposited exactly."""
+    for seed in (0, 1, 2):
+        cfg = _obstacle_cfg(seed=seed)
+        sol = cfg["solid"]
+        seen = set()
+        n = 0
+        for y in range(12):
+            for x in range(14):
+                if sol[y, x]:
+                    continue
+                for dy in range(-4, 5):
+                    for dx in range(-4, 5):
+                        ex, ey, sx, sy = oracle.walk(cfg, x, y, dx, dy)
+                        assert 0 <= ex < 14 and 0 <= ey < 12 and not sol[ey, ex]
+                        key = (ex, ey, sx * dx, sy * dy)
+                        assert key not in seen
+                        seen.add(key)
+                        n += 1
+        assert len(seen) == n
+
+
+def test_gas_at_rest_around_obstacles_stays_at_rest():
+    cfg = _obstacle_cfg(nx=16, ny=12, seed=3, density=0.1)
+    cfg["RT"] = 0.8
+    shape = (12, 16)
+    prim = {"rho": np.ones(shape), "ux": np.zeros(shape), "uy": np.zeros(shape), "RT": np.full(shape, 0.8)}
+    m = prim_moments(cfg, prim)
+    st, out, stats, done = oracle.step(cfg, m, 3)
+    assert st == 0
+    fluid = cfg["solid"].ravel() == 0
+    assert np.abs(out[:, ~fluid]).max() == 0.0
+    err = np.abs(out[:, fluid] - m[:, fluid]).max(axis=1) / np.maximum(np.abs(m[:, fluid]).max(axis=1), 1.0)
+    assert err.max() < 1e-13
+
+
+def test_obstacles_conserve_mass_and_energy():
+    cfg, prim = li.smooth_periodic(5, n=16, ny=12)
+    rng = np.random.default_rng(7)
+    cfg["solid"] = (rng.random((12, 16)) < 0.12).astype(np.uint8)
+    fluid = cfg["solid"].ravel() == 0
+    m = prim_moments(cfg, prim)
+    m[:, ~fluid] = 0.0
+    st, out, stats, done = oracle.step(cfg, m, 2)
+    assert st == 0
+    mass0, mass1 = m[0, fluid].sum(), out[0, fluid].sum()
+    e0 = (m[3] + m[5] + m[8])[fluid].sum()
+    e1 = (out[3] + out[5] + out[8])[fluid].sum()
+    assert abs(mass1 - mass0) / mass0 < 1e-13
+    assert abs(e1 - e0) / e0 < 1e-13
+    # the obstacles exert a force: momentum changes
+    assert abs(out[1, fluid].sum() - m[1, fluid].sum()) > 1e-6 * mass0
+
+
+def test_flow_past_a_symmetric_obstacle_stays_symmetric():
+    """A y-mirror-symmetric channel, obstacle and state stay y-symmetric
+    (corner crossings are taken x first in both mirror images)."""
+    nx, ny = 20, 12
+    cfg, _ = li.hotbox(1.0, n=nx, ny=ny)
+    cfg["bc"] = ["periodic", "periodic", "slipwall", "slipwall"]
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny) + 0.5
+    X, Y = np.meshgrid(x, y)
+    cfg["solid"] = (((X - 8.0) / 3.2) ** 2 + ((Y - 6.0) / 2.3) ** 2 <= 1.0).astype(np.uint8)
+    assert (cfg["solid"] == cfg["solid"][::-1]).all()
+    shape = (ny, nx)
+    prim = {"rho": 1.0 + 0.05 * np.cos(2 * np.pi * X / nx) * np.cos(np.pi * (Y - 6.0) / 6.0),
+            "ux": np.full(shape, 1.1), "uy": np.zeros(shape), "RT": np.full(shape, 0.9)}
+    m = prim_moments(cfg, prim)
+    st, out, *_ = oracle.step(cfg, m, 3)
+    assert st == 0
+    o = out.reshape(11, ny, nx)
+    sign = np.array([1, 1, -1, 1, -1, 1, 1, -1, 1, 1, -1])[:, None, None]
+    scale = np.abs(o).reshape(11, -1).max(axis=1)[:, None, None] + 1e-300
+    assert np.max(np.abs(o[:, ::-1] * sign - o) / scale) < 1e-12
+
+
+def test_solid_touching_a_pad_face_is_rejected():
+    cfg, prim = li.channel(0, nx=64, ny=32, n_obstacles=1, size_scale=0.05, pad=8)
+    cfg["solid"][:, 0] = 1
+    st, *_ = oracle.step(cfg, prim_moments(cfg, prim), 1)
+    assert st == -1
