@@ -86,7 +86,10 @@ typedef struct {
     int bc[4];                        /* faces xlo, xhi, ylo, yhi: LELBM_BC_*; periodic faces pair up */
     int pad;                          /* pad width W of outflow/inflow faces (Sec. III, Fig. 5) */
     double in_rho, in_u[2], in_RT;    /* inflow (Dirichlet) state of LELBM_BC_INFLOW faces */
-    const unsigned char *solid;       /* must be NULL (solid obstacles are not supported) */
+    const unsigned char *solid;       /* 2D only: nx*ny legoland mask [ny][nx], nonzero = solid cell, or
+                                         NULL; copied at create.  Solid cells hold no gas (their moments
+                                         read as 0) and reflect population paths like slip walls
+                                         (Sec. III.B); they may not touch an outflow or inflow face. */
 } lelbm_params;
 
 /* Statistics accumulated over the steps of one lelbm_step call.  Newton

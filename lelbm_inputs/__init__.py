@@ -120,7 +120,7 @@ def quadrants(seed, n=1024, ny=None, rt_floor=RT_FLOOR, perturb=0.01):
     return cfg, prim
 
 
-def channel(seed, nx=4096, ny=2048, n_obstacles=None, mach=None, size_scale=1.0, pad=24):
+def channel(seed, nx=4096, ny=2048, n_obstacles=None, mach=None, size_scale=1.0, pad=24, start="rest"):
     """Channel with uniform supersonic inflow past 1-4 elliptical obstacles.
 
     Draw order: Mach ~ U[2, 6] (unless given), obstacle count ~ U{1..4}
@@ -129,7 +129,12 @@ def channel(seed, nx=4096, ny=2048, n_obstacles=None, mach=None, size_scale=1.0,
     rejected (and redrawn) while it overlaps an earlier obstacle's bounding
     circle or comes closer than 10 cells to a wall.  Lattice inflow state
     rho = 1, RT = 1, u = (Ma sqrt(gamma), 0); the initial field is the inflow
-    state everywhere.  A cell is solid iff its centre lies inside an ellipse.
+    state with zero velocity (start="rest": the inflow enters through the left
+    face; at these Mach numbers every population of the inflow stencil moves
+    downstream, so an initial field moving at the inflow velocity would leave
+    vacuum cells in the lee of each obstacle after one step), or the inflow
+    state itself (start="inflow").  A cell is solid iff its centre lies inside
+    an ellipse.
     Faces: inflow left, zero-gradient outflow right, slip walls top and
     bottom.  Returns (cfg, prim) with cfg["solid"] a uint8 [ny][nx] mask."""
     g = np.random.Generator(np.random.PCG64(seed))
@@ -169,7 +174,8 @@ def channel(seed, nx=4096, ny=2048, n_obstacles=None, mach=None, size_scale=1.0,
     cfg["mach"] = float(ma)
     cfg["obstacles"] = obs
     shape = (ny, nx)
-    prim = {"rho": np.ones(shape), "ux": np.full(shape, u_in), "uy": np.zeros(shape), "RT": np.ones(shape)}
+    ux0 = np.full(shape, u_in) if start == "inflow" else np.zeros(shape)
+    prim = {"rho": np.ones(shape), "ux": ux0, "uy": np.zeros(shape), "RT": np.ones(shape)}
     return cfg, prim
 
 

@@ -158,7 +158,13 @@ def make_params(cfg, precision=FP64, guess=GUESS_EQ):
     iu = cfg.get("in_u", (0.0, 0.0))
     p.in_u[0], p.in_u[1] = iu[0], iu[1]
     p.in_RT = cfg.get("in_RT", 1.0)
-    p.solid = None
+    solid = cfg.get("solid")
+    if solid is None:
+        p.solid = None
+    else:
+        m = np.ascontiguousarray(solid, dtype=np.uint8).reshape(p.ny, p.nx)
+        p._solid_ref = m                     # kept alive with the struct; the library copies it
+        p.solid = m.ctypes.data_as(ctypes.c_void_p)
     return p
 
 

@@ -12,6 +12,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <vector>
@@ -166,7 +167,7 @@ static int validate(const lelbm_params *p) {
     if (p->precision != LELBM_FP64 && p->precision != LELBM_MIXED) return LELBM_EINVAL;
     if (p->guess != LELBM_GUESS_EQ && p->guess != LELBM_GUESS_MLP) return LELBM_EINVAL;
     if (p->guess == LELBM_GUESS_MLP && p->dim != 2) return LELBM_EINVAL;
-    if (p->solid) return LELBM_EINVAL;
+    if (p->solid && p->dim != 2) return LELBM_EINVAL;
     for (int f = 0; f < 4; f++)
         if (p->bc[f] < LELBM_BC_PERIODIC || p->bc[f] > LELBM_BC_SLIPWALL) return LELBM_EINVAL;
     for (int ax = 0; ax < p->dim; ax++) {
@@ -186,7 +187,7 @@ static void free_ctx(lelbm_ctx *c) {
     Buffers &b = c->b;
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.tiles,
                     b.dwin, b.scratch, b.flags, b.stats, b.partial, b.guess, b.harvest_n,
-                    c->mlp_w, c->mlp_p, c->mlp_n};
+                    c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (c->ev[0]) (void)hipEventDestroy(c->ev[0]);
@@ -214,6 +215,85 @@ static int grow_scratch(lelbm_ctx *c, long long need) {
     return LELBM_OK;
 }
 
+// Solid cells and slip walls block population paths.  The device gets the
+// mask and, per destination tile, the Chebyshev distance from the tile to the
+// nearest blocker (a solid cell, or the cell just beyond a slip wall), so the
+// gather can tell the tiles that need path tracing.  Solids may not touch a
+// pad face: pad cells copy the nearest interior cell.
+static int setup_blockers(lelbm_ctx *c, const unsigned char *mask) {
+    const Geom &g = c->g;
+    const int nx = g.nx, ny = g.ny;
+    bool walls = false;
+    for (int f = 0; f < 2 * g.dim; f++) walls = walls || g.bc[f] == LELBM_BC_SLIPWALL;
+    if (!mask && !walls) return LELBM_OK;
+    const long long n = (long long)nx * ny;
+    const int INF = 1 << 28;
+    std::vector<int> d((size_t)n, INF);
+    if (mask) {
+        for (int y = 0; y < ny; y++)
+            for (int x = 0; x < nx; x++) {
+                if (!mask[(long long)y * nx + x]) continue;
+                if ((x == 0 && g.wl) || (x == nx - 1 && g.wr) || (y == 0 && g.wb) || (y == ny - 1 && g.wt))
+                    return LELBM_EINVAL;
+                d[(long long)y * nx + x] = 0;
+            }
+        // Chebyshev distance transform: forward and backward sweeps over the
+        // 8-neighbourhood (periodic axes wrap), repeated until stable
+        const bool px = g.bc[0] == LELBM_BC_PERIODIC, py = g.bc[2] == LELBM_BC_PERIODIC;
+        auto relax = [&](int x, int y, int ddx, int ddy, bool &chg) {
+            int xx = x + ddx, yy = y + ddy;
+            if (px) xx = (xx + nx) % nx;
+            if (py) yy = (yy + ny) % ny;
+            if (xx < 0 || xx >= nx || yy < 0 || yy >= ny) return;
+            int v = d[(long long)yy * nx + xx] + 1;
+            int &me = d[(long long)y * nx + x];
+            if (v < me) { me = v; chg = true; }
+        };
+        for (int round = 0; round < 64; round++) {
+            bool chg = false;
+            for (int y = 0; y < ny; y++)
+                for (int x = 0; x < nx; x++) {
+                    relax(x, y, -1, 0, chg); relax(x, y, -1, -1, chg); relax(x, y, 0, -1, chg); relax(x, y, 1, -1, chg);
+                }
+            for (int y = ny - 1; y >= 0; y--)
+                for (int x = nx - 1; x >= 0; x--) {
+                    relax(x, y, 1, 0, chg); relax(x, y, 1, 1, chg); relax(x, y, 0, 1, chg); relax(x, y, -1, 1, chg);
+                }
+            if (!chg) break;
+        }
+    }
+    const int nd = g.dtx * g.dty;
+    std::vector<int> td((size_t)nd, INF);
+    for (int y = 0; y < ny; y++)
+        for (int x = 0; x < nx; x++) {
+            int v = d[(long long)y * nx + x];
+            if (g.bc[0] == LELBM_BC_SLIPWALL) v = std::min(v, x + 1);
+            if (g.bc[1] == LELBM_BC_SLIPWALL) v = std::min(v, nx - x);
+            if (g.dim == 2 && g.bc[2] == LELBM_BC_SLIPWALL) v = std::min(v, y + 1);
+            if (g.dim == 2 && g.bc[3] == LELBM_BC_SLIPWALL) v = std::min(v, ny - y);
+            int &t = td[(size_t)(y / g.ty) * g.dtx + x / g.tx];
+            t = std::min(t, v);
+        }
+    Buffers &b = c->b;
+    int *dt = nullptr, *mr = nullptr;
+    unsigned char *sm = nullptr;
+    if (hipMalloc((void **)&dt, (size_t)nd * sizeof(int)) != hipSuccess) return LELBM_ENOMEM;
+    b.tdist = dt;
+    if (hipMalloc((void **)&mr, sizeof(int)) != hipSuccess) return LELBM_ENOMEM;
+    b.maxreach = mr;
+    int r = stage_h2d(c->stage, c->stream, dt, td.data(), (size_t)nd * sizeof(int));
+    if (r != LELBM_OK) return r;
+    if (mask) {
+        if (hipMalloc((void **)&sm, (size_t)n) != hipSuccess) return LELBM_ENOMEM;
+        b.solid = sm;
+        r = stage_h2d(c->stage, c->stream, sm, mask, (size_t)n);
+        if (r != LELBM_OK) return r;
+        c->persistent_bytes += n;
+    }
+    c->persistent_bytes += (long long)nd * sizeof(int);
+    return LELBM_OK;
+}
+
 static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, lelbm_ctx **cc) {
     int v = validate(p);
     if (v != LELBM_OK) return v;
@@ -227,7 +307,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     c->mlp_n = nullptr;
     c->mlp_set = 0;
     c->p = *p;
-    c->p.solid = nullptr;
+    c->p.solid = nullptr;      // the mask is copied to the device below
     c->mixed = p->precision == LELBM_MIXED;
     c->nmom = lelbm_num_moments(p->dim);
     c->stream = (hipStream_t)stream;
@@ -299,6 +379,8 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     if (!ok) { free_ctx(c); return LELBM_ENOMEM; }
     c->persistent_bytes = (long long)2 * c->nmom * ns * esz + ns * (4 * sizeof(double) + sizeof(int)) +
                           nt * sizeof(TileInfo) + nd * sizeof(DWin);
+    int r = setup_blockers(c, p->solid);
+    if (r != LELBM_OK) { free_ctx(c); return r; }
     if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
         free_ctx(c);
         return LELBM_EDEVICE;
@@ -346,6 +428,7 @@ static int upload_interior(lelbm_ctx *c, const void *src, int src_fp32, hipMemcp
 static int finish_create(lelbm_ctx *c) {
     // initial scratch: run the pre-pass once to size it
     hipStream_t s = c->stream;
+    HIPCHECK(launch_zero_solid(c->g, c->nmom, c->mixed, c->b.mom[c->cur], c->b.solid, s));
     HIPCHECK(launch_fill_pads(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b.flags, s));
     HIPCHECK(launch_reset_step(c->g, c->b, s));
     HIPCHECK(launch_prepare(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, 0, s));

@@ -108,6 +108,11 @@ struct Buffers {
     long long harvest_cap;
     int harvest_stride;
     unsigned long long *harvest_n; // pairs written (device counter)
+    // blockers: solid cells and slip walls
+    const unsigned char *solid;    // [ny][nx] 1 = solid cell, NULL = none
+    const int *tdist;              // [dtx*dty] Chebyshev distance from the tile to the nearest
+                                   // blocker (solid cell or the cell beyond a slip wall); NULL = none
+    int *maxreach;                 // max over sources of max(|round(u)|) + R + 1 (this step)
 };
 
 // Kernel launchers (defined in lelbm_kernels.hip).  All enqueue on `s`.
@@ -124,6 +129,8 @@ hipError_t launch_sums(const Geom &g, int mixed, const void *mom, Buffers &b, hi
 hipError_t launch_reset_step(const Geom &g, Buffers &b, hipStream_t s);
 hipError_t launch_reset_stats(Buffers &b, hipStream_t s);
 hipError_t launch_reset_flags(Flags *f, hipStream_t s);
+hipError_t launch_zero_solid(const Geom &g, int nmom, int mixed, void *mom, const unsigned char *solid,
+                             hipStream_t s);
 hipError_t launch_load_interior(const Geom &g, int nmom, const void *src, int src_fp32, void *dst, int dst_fp32,
                                 hipStream_t s);
 hipError_t launch_store_interior(const Geom &g, int nmom, const void *src, int src_fp32, double *dst, hipStream_t s);

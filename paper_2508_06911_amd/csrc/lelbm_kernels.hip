@@ -210,6 +210,14 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
     int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
     bool valid = px < g.sxn && py < g.syn;
     int lox = 1 << 29, loy = 1 << 29, hix = -(1 << 29), hiy = -(1 << 29), refined = 0;
+    int reach = 0;
+    if (valid && b.solid) {
+        const int ix = px - g.wl, iy = py - g.wb;
+        if (ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny && b.solid[(long long)iy * g.nx + ix]) {
+            b.desc_rn[(long long)py * g.sxn + px] = -1;     // solid cell: no population
+            valid = false;
+        }
+    }
     if (valid) {
         long long s = (long long)py * g.sxn + px;
         double M0 = (double)mom[s], Mx = (double)mom[g.ns + s];
@@ -247,6 +255,7 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
                 lox = ubx - R - 1; hix = ubx + R + 1;
                 loy = D == 2 ? uby - R - 1 : 0; hiy = D == 2 ? uby + R + 1 : 0;
                 refined = Nr > 0;
+                reach = max(abs(ubx), abs(uby)) + R + 1;
             }
         }
         b.desc_u[s] = ux;
@@ -256,6 +265,10 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
         b.desc_rn[s] = rn;
     }
     red[0][l] = lox; red[1][l] = loy; red[2][l] = hix; red[3][l] = hiy; redf[l] = refined;
+    if (b.maxreach) {
+        for (int off = 32; off > 0; off >>= 1) reach = max(reach, __shfl_xor(reach, off));
+        if ((l & 63) == 0 && reach > 0) atomicMax(b.maxreach, reach);
+    }
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (l < off) {
@@ -1252,6 +1265,58 @@ __device__ inline void deposit_record(T *acc, const T *P, int fmt, int dx, int d
     }
 }
 
+// Blockers of a population path (Sec. III.B): solid cells and the cells
+// beyond a slip wall.
+__device__ inline bool is_blocked(const Geom &g, const unsigned char *solid, int x, int y) {
+    if (x < 0 && g.bc[0] == LELBM_BC_SLIPWALL) return true;
+    if (x >= g.nx && g.bc[1] == LELBM_BC_SLIPWALL) return true;
+    if (g.dim == 2 && y < 0 && g.bc[2] == LELBM_BC_SLIPWALL) return true;
+    if (g.dim == 2 && y >= g.ny && g.bc[3] == LELBM_BC_SLIPWALL) return true;
+    return solid && x >= 0 && x < g.nx && y >= 0 && y < g.ny && solid[(long long)y * g.nx + x];
+}
+
+// A population's path crosses the grid lines x = const and y = const in the
+// order of its path parameter ((2k+1)/(2|v|) for the k-th crossing of each
+// kind), an x crossing first where both coincide; a crossing into a blocker
+// reverses that velocity component, otherwise the path enters the next cell.
+// walk_back undoes such a path: from the landing cell with the landing
+// velocity reversed it takes the same crossings in reverse order (so y
+// first where they coincide), each of which exactly undoes its forward
+// counterpart.  It returns the cell of origin and the signs the forward path
+// applied to each component, or false if it leaves the padded domain (no
+// source there).
+template <int D>
+__device__ inline bool walk_back(const Geom &g, const unsigned char *solid, int x, int y, int vx, int vy, int &ox,
+                                 int &oy, int &sgx, int &sgy) {
+    const int ax = abs(vx), ay = abs(vy);
+    int sx = vx < 0 ? -1 : 1, sy = vy < 0 ? -1 : 1, kx = 0, ky = 0;
+    const bool perx = g.bc[0] == LELBM_BC_PERIODIC, pery = D == 2 && g.bc[2] == LELBM_BC_PERIODIC;
+    while (kx < ax || ky < ay) {
+        bool takey;
+        if (ky >= ay) takey = false;
+        else if (kx >= ax) takey = true;
+        else takey = (long long)(2 * ky + 1) * ax <= (long long)(2 * kx + 1) * ay;
+        if (takey) {
+            int t = y + sy;
+            if (pery) { t %= g.ny; if (t < 0) t += g.ny; }
+            if (is_blocked(g, solid, x, t)) sy = -sy; else y = t;
+            ky++;
+        } else {
+            int t = x + sx;
+            if (perx) { t %= g.nx; if (t < 0) t += g.nx; }
+            if (is_blocked(g, solid, t, y)) sx = -sx; else x = t;
+            kx++;
+        }
+        if (x < -g.wl || x >= g.nx + g.wr || y < -g.wb || y >= g.ny + g.wt) return false;
+    }
+    ox = x;
+    oy = y;
+    // the forward path ends with velocity -(sx, sy) and started with -(vx, vy) times its flips
+    sgx = (vx == 0 || (sx < 0) == (vx < 0)) ? 1 : -1;
+    sgy = (vy == 0 || (sy < 0) == (vy < 0)) ? 1 : -1;
+    return true;
+}
+
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
@@ -1293,7 +1358,42 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b, i
     // fails: those displacements lie outside every reaching source's box)
     const int RW = g.tx + (w.hix - w.lox) + GU - 1;
     int rows = gcap / RW - (g.ty - 1);              // window rows per chunk
-    if (w.lox <= w.hix && rows >= 1) {
+    // Tiles within reach of a blocker: every landing displacement d with
+    // |d_x|, |d_y| <= the step's maximum reach M is traced back to the source
+    // it comes from (walk_back), which finds the straight and the reflected
+    // arrivals alike.  Elsewhere no path that ends in the tile can touch a
+    // blocker (it would have to pass within M cells of the tile), so every
+    // arrival comes straight from x - d.
+    const int M = b.maxreach ? *b.maxreach : 0;
+    const bool near = b.tdist && b.tdist[t] <= M + 1;
+    if (near) {
+        const bool fluid = mine && !(b.solid && b.solid[(long long)y * g.nx + x]);
+        if (fluid) {
+            for (int dy = D == 2 ? M : 0; dy >= (D == 2 ? -M : 0); dy--) {
+                for (int dx = M; dx >= -M; dx--) {
+                    int ox, oy, sgx, sgy;
+                    if (!walk_back<D>(g, b.solid, x, y, -dx, -dy, ox, oy, sgx, sgy)) continue;
+                    const long long s = (long long)(oy + g.wb) * g.sxn + (ox + g.wl);
+                    const int rn = b.desc_rn[s];
+                    if (rn < 0) continue;
+                    const int cx = sgx * dx, cy = sgy * dy;        // the source's own displacement
+                    const double rr = (rn & 0xffff) + 0.5;
+                    const bool in = D == 2 ? in_disk2((double)cx, (double)cy, b.desc_u[s], b.desc_u[g.ns + s], rr)
+                                           : in_disk1((double)cx, b.desc_u[s], rr);
+                    if (!in) continue;
+                    const int px = (int)(s % g.sxn), py = (int)(s / g.sxn);
+                    const int st = (px / g.tx) + (py / g.ty) * g.ntx;
+                    const int loc = (px % g.tx) + (py % g.ty) * g.tx;
+                    const TileInfo ti = b.tiles[st];
+                    const long long recsz = ti.fmt ? NM : 2;
+                    const long long slot = (long long)(cy - ti.oy) * ti.wx + (cx - ti.ox);
+                    const T *P = SCR + ti.base + (slot * TILE_N + loc) * recsz;
+                    hits++;
+                    deposit_record<T, D>(acc, P, ti.fmt, dx, dy, sgx < 0, sgy < 0);
+                }
+            }
+        }
+    } else if (w.lox <= w.hix && rows >= 1) {
         for (int dy0 = w.hiy; dy0 >= w.loy; dy0 -= rows) {
             const int dy1 = max(w.loy, dy0 - rows + 1);
             const int RH = g.ty + (dy0 - dy1);
@@ -1450,11 +1550,22 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b, i
 // ---------------------------------------------------------------------------
 // resets and conserved totals
 // ---------------------------------------------------------------------------
-__global__ void k_reset_windows(int n, DWin *w) {
+__global__ void k_reset_windows(int n, DWin *w, int *maxreach) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         w[i].lox = 1 << 29; w[i].loy = 1 << 29; w[i].hix = -(1 << 29); w[i].hiy = -(1 << 29);
     }
+    if (i == 0 && maxreach) *maxreach = 0;
+}
+
+// Zeroes the state of solid cells (they hold no gas).
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero_solid(Geom g, int nmom, T *mom, const unsigned char *solid) {
+    const long long n = (long long)g.nx * g.ny;
+    const long long i = blockIdx.x * 256ll + threadIdx.x;
+    if (i >= n || !solid[i]) return;
+    const int y = (int)(i / g.nx), x = (int)(i - (long long)y * g.nx);
+    for (int k = 0; k < nmom; k++) mom[k * g.ns + (long long)(y + g.wb) * g.sxn + x + g.wl] = (T)0;
 }
 
 // Interior copies between a contiguous SoA array [nmom][ny][nx] and the
@@ -1574,7 +1685,7 @@ hipError_t launch_fill_pads(const Geom &g, const Phys &ph, int mixed, void *mom,
 
 hipError_t launch_reset_step(const Geom &g, Buffers &b, hipStream_t s) {
     int n = g.dtx * g.dty;
-    hipLaunchKernelGGL(k_reset_windows, dim3((n + 255) / 256), dim3(256), 0, s, n, b.dwin);
+    hipLaunchKernelGGL(k_reset_windows, dim3((n + 255) / 256), dim3(256), 0, s, n, b.dwin, b.maxreach);
     return hipGetLastError();
 }
 
@@ -1605,6 +1716,16 @@ hipError_t launch_store_interior(const Geom &g, int nmom, const void *src, int s
         hipLaunchKernelGGL((k_store_interior<float>), grid, dim3(256), 0, s, g, nmom, (const float *)src, dst);
     else
         hipLaunchKernelGGL((k_store_interior<double>), grid, dim3(256), 0, s, g, nmom, (const double *)src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_solid(const Geom &g, int nmom, int mixed, void *mom, const unsigned char *solid,
+                             hipStream_t s) {
+    const long long n = (long long)g.nx * g.ny;
+    if (!solid || n == 0) return hipSuccess;
+    dim3 grid((unsigned)((n + 255) / 256));
+    if (mixed) hipLaunchKernelGGL((k_zero_solid<float>), grid, dim3(256), 0, s, g, nmom, (float *)mom, solid);
+    else hipLaunchKernelGGL((k_zero_solid<double>), grid, dim3(256), 0, s, g, nmom, (double *)mom, solid);
     return hipGetLastError();
 }
 
