@@ -79,7 +79,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-window", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--no-context", action="store_true", help="skip the hot-box context runs")
+    ap.add_argument("--no-context", action="store_true", help="skip the hot-box and channel context runs")
+    ap.add_argument("--channel-seed", type=int, default=0)
+    ap.add_argument("--channel-warmup", type=int, default=300)
+    ap.add_argument("--channel-steps", type=int, default=10)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -271,6 +274,47 @@ def hotbox_context(lb, li, torch):
     return out
 
 
+def channel_context(lb, li, torch, a):
+    """The channel configuration (4096x2048, inflow at the seed's Mach number,
+    1-4 seeded elliptical obstacles, slip walls, outflow), started from rest:
+    after a warm-up that lets the bow shocks form, the FP64 path and the FP32
+    path from the same state, with the relative L1 error of each field of
+    the FP32 path against the FP64 path on fluid cells."""
+    cfg, prim = li.channel(a.channel_seed, nx=4096, ny=2048, pad=32)
+    m = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
+    ctx = lb.Lelbm(cfg, m)
+    ctx.step_nostats(a.channel_warmup)
+    torch.cuda.synchronize()
+    m0 = ctx.read_moments()
+    ctx.close()
+    fluid = cfg["solid"].ravel() == 0
+    out, moms = {}, {}
+    for name, prec in (("fp64", lb.FP64), ("mixed", lb.MIXED)):
+        c = lb.Lelbm(cfg, m0, precision=prec)
+        c.step_nostats(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = c.step(a.channel_steps)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / a.channel_steps
+        persistent, scratch = c.memory()
+        moms[name] = c.read_moments()[:, fluid]
+        c.close()
+        out[name] = {"ms_per_step": round(el * 1e3, 3), "mlups": round(fluid.sum() / el / 1e6, 2),
+                     "newton_it": {"mean_f": round(st["it_mean_f"], 3), "max_f": st["it_max_f"],
+                                   "mean_g": round(st["it_mean_g"], 3), "max_g": st["it_max_g"]},
+                     "stencil_q": {"mean": round(st["q_mean"], 1), "max": st["q_max"]},
+                     "colat_max": round(float(st["colat_max"]), 2),
+                     "hbm_bytes": {"persistent": persistent, "scratch": scratch}}
+        log("channel %s: %.2f ms/step %.1f MLUPS q_max %d" % (name, el * 1e3, out[name]["mlups"], st["q_max"]))
+    out["l1_mixed_vs_fp64"] = l1_errors(moms["mixed"], moms["fp64"])
+    out["config"] = ("channel 4096x2048, Mach %.2f inflow (rho 1, RT 1), %d obstacles, seed %d, started from rest, "
+                     "%d warm-up steps, %d timed steps" % (cfg["mach"], len(cfg["obstacles"]), a.channel_seed,
+                                                          a.channel_warmup, a.channel_steps))
+    out["fluid_cells"] = int(fluid.sum())
+    return out
+
+
 def main():
     a = parse()
     if a.copy_probe:
@@ -356,6 +400,7 @@ def main():
         res["mlp"] = train_info
     if not a.no_context:
         res["paper_context"] = hotbox_context(lb, li, torch)
+        res["channel_context"] = channel_context(lb, li, torch, a)
     if mlp is not None:
         mlp.close()
     if not a.no_cpu:
