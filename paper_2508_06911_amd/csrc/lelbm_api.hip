@@ -185,7 +185,7 @@ static int validate(const lelbm_params *p) {
 static void free_ctx(lelbm_ctx *c) {
     if (!c) return;
     Buffers &b = c->b;
-    void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.tiles,
+    void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.spans, b.tiles,
                     b.dwin, b.scratch, b.flags, b.stats, b.partial, b.guess, b.harvest_n,
                     c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach};
     for (void *q : ptrs)
@@ -364,6 +364,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ok = ok && hipMalloc((void **)&b.desc_rho, (size_t)ns * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.desc_rt, (size_t)ns * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.desc_rn, (size_t)ns * sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.spans, (size_t)ns * SPAN_ROWS * sizeof(unsigned short)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.tiles, (size_t)nt * sizeof(TileInfo)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.dwin, (size_t)nd * sizeof(DWin)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.flags, sizeof(Flags)) == hipSuccess;

@@ -14,6 +14,11 @@ constexpr int TILE_N = 256;
 constexpr int MAX_REFINE = 3;       // supported stencil refinement levels
 constexpr int MAX_RADIUS = 128;     // largest acoustic radius (RT up to ~1000)
 constexpr double MAX_SPEED = 2048.0;  // largest |u| component in cells per step
+// Stencil row spans cached per cell for the reconstruction passes: row k
+// (c_y = round(u_y) - R - 1 + k) holds (xa - x0) | (xb - x0) << 8 with
+// x0 = round(u_x) - R - 1; 0x00ff = empty.  Cells with more rows (R > 30)
+// recompute their spans in every pass.
+constexpr int SPAN_ROWS = 64;
 // staged sources per gather chunk (28 B of LDS each)
 constexpr int GATHER_CAP = 1024;
 constexpr int GATHER_CAP_MAX = 2340;      // 64 KiB of LDS
@@ -91,6 +96,7 @@ struct Buffers {
     double *desc_rho;        // [ns]
     double *desc_rt;         // [ns]
     int *desc_rn;            // [ns]  R | (N_r << 16), -1 = no emission
+    unsigned short *spans;   // [ns][SPAN_ROWS] stencil row spans (see k_epr)
     TileInfo *tiles;         // [ntx*nty]
     DWin *dwin;              // [dtx*dty]
     void *scratch;           // population scratch

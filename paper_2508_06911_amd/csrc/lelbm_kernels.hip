@@ -804,6 +804,64 @@ template <typename W> __device__ inline W wexp(double v) {
     return expf((float)v);
 }
 
+// Row starts along a column (2D).  The five exponents a stencil row needs at
+// its first point -- E, its first and second x differences, H and its first x
+// difference (see row_start) -- are polynomials in the row coordinate y at a
+// fixed column x = X (cubic, quadratic, linear, quadratic, linear), so down
+// the column they follow product recurrences of the exponentials of their
+// forward differences in y: 14 exponentials per pass instead of 5 per row.
+// Multipliers are in the basis order 1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2,
+// y^3 (fluon) and 1, x, y, x^2, xy, y^2 (phonon).
+struct ColumnStarts {
+    double F, F1, F2, F3;   // exp(E(X, y)) and the exponentials of its y differences
+    double R, R1, R2;       // exp(D_x E(X, y)) ...
+    double S, S1;           // exp(D_x^2 E(X, y)) ...
+    double G, G1, G2;       // exp(H(X, y)) ...
+    double Q, Q1;           // exp(D_x H(X, y)) ...
+    __device__ void init(const double *l, const double *g, double X, double y) {
+        const double X2 = X * X;
+        // E(X, y) = c0 + c1 y + c2 y^2 + c3 y^3
+        const double c0 = -1.0 - (l[0] + l[1] * X + l[3] * X2 + l[6] * X2 * X);
+        const double c1 = -(l[2] + l[4] * X + l[7] * X2), c2 = -(l[5] + l[8] * X), c3 = -l[9];
+        F = exp(c0 + y * (c1 + y * (c2 + y * c3)));
+        F1 = exp(c1 + c2 * (2.0 * y + 1.0) + c3 * (3.0 * y * y + 3.0 * y + 1.0));
+        F2 = exp(2.0 * c2 + c3 * (6.0 * y + 6.0));
+        F3 = exp(6.0 * c3);
+        // D_x E(X, y) = d0 + d1 y + d2 y^2
+        const double d0 = -l[1] - l[3] * (2.0 * X + 1.0) - l[6] * (3.0 * X2 + 3.0 * X + 1.0);
+        const double d1 = -l[4] - l[7] * (2.0 * X + 1.0), d2 = -l[8];
+        R = exp(d0 + y * (d1 + y * d2));
+        R1 = exp(d1 + d2 * (2.0 * y + 1.0));
+        R2 = exp(2.0 * d2);
+        // D_x^2 E(X, y) = s0 + s1 y
+        const double s0 = -2.0 * l[3] - l[6] * (6.0 * X + 6.0), s1 = -2.0 * l[7];
+        S = exp(s0 + s1 * y);
+        S1 = exp(s1);
+        // H(X, y) = h0 + h1 y + h2 y^2
+        const double h0 = -1.0 - (g[0] + g[1] * X + g[3] * X2), h1 = -(g[2] + g[4] * X), h2 = -g[5];
+        G = exp(h0 + y * (h1 + y * h2));
+        G1 = exp(h1 + h2 * (2.0 * y + 1.0));
+        G2 = exp(2.0 * h2);
+        // D_x H(X, y) = q0 + q1 y
+        const double q0 = -g[1] - g[3] * (2.0 * X + 1.0), q1 = -g[4];
+        Q = exp(q0 + q1 * y);
+        Q1 = exp(q1);
+    }
+    __device__ void next() {
+        F *= F1; F1 *= F2; F2 *= F3;
+        R *= R1; R1 *= R2;
+        S *= S1;
+        G *= G1; G1 *= G2;
+        Q *= Q1;
+    }
+};
+
+// True when recurrence values can start a row (normal range, finite).
+__device__ inline bool row_start_ok(double f, double r, double s2, double gv, double rg) {
+    return f > 1e-280 && f < 1e280 && gv > 1e-280 && gv < 1e280 && r > 1e-280 && r < 1e280 && s2 > 1e-280 &&
+           s2 < 1e280 && rg > 1e-280 && rg < 1e280;
+}
+
 template <typename T, int D>
 __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, Buffers b, int step) {
     using BS = Basis<D>;
@@ -836,6 +894,26 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         const int ubx = (int)floor(ux + 0.5), uby = D == 2 ? (int)floor(uy + 0.5) : 0;
         const int ylo = D == 2 ? uby - R - 1 : 0, yhi = D == 2 ? uby + R + 1 : 0;
         const int xlo = ubx - R - 1, xhi = ubx + R + 1;
+        // stencil row spans, computed once and reused by every pass
+        const bool tab = D == 1 ? 2 * R + 2 <= 255 : 2 * R + 3 <= SPAN_ROWS;
+        unsigned short *spt = b.spans + s * SPAN_ROWS;
+        if (tab) {
+            for (int cy = ylo; cy <= yhi; cy++) {
+                int xa, xb;
+                unsigned short v = 0x00ff;
+                if (row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb)) v = (unsigned short)((xa - xlo) | ((xb - xlo) << 8));
+                spt[cy - ylo] = v;
+            }
+        }
+        auto span = [&](int cy, int &xa, int &xb) -> bool {
+            if (tab) {
+                const unsigned v = spt[cy - ylo];
+                xa = xlo + (int)(v & 0xffu);
+                xb = xlo + (int)(v >> 8);
+                return xa <= xb;
+            }
+            return row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb);
+        };
         double mf[NF], mg[NG];
         collide_targets<T, D>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, cs.kn, cs.lim);
         Species<NF, LdsStore<NF>> sf;
@@ -856,25 +934,43 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         int fail = 0, fsp = -1;
         while (!fail && (sf.phase < 2 || sg.phase < 2)) {
             cs.pass++;
-            double Sf[NMF], Sg[NMG], lf[NF], lg[NG];
-#pragma unroll
-            for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
-#pragma unroll
-            for (int j = 0; j < NG; j++) lg[j] = sg.at(j);
+            double Sf[NMF], Sg[NMG];
 #pragma unroll
             for (int k = 0; k < NMF; k++) Sf[k] = 0.0;
 #pragma unroll
             for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
-            const W t3 = wexp<W>(-6.0 * lf[D == 2 ? 6 : 3]);
-            const W sg2 = wexp<W>(-2.0 * lg[D == 2 ? 3 : 2]);
+            // multipliers of this pass live in LDS; registers hold them only
+            // while the column and the rare direct row starts are set up
+            const W t3 = wexp<W>(-6.0 * sf.at(D == 2 ? 6 : 3));
+            const W sg2 = wexp<W>(-2.0 * sg.at(D == 2 ? 3 : 2));
+            ColumnStarts col;
+            if (D == 2) {
+                double lf[NF], lg[NG];
+#pragma unroll
+                for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
+#pragma unroll
+                for (int j = 0; j < NG; j++) lg[j] = sg.at(j);
+                col.init(lf, lg, (double)xlo - ux, (double)ylo - uy);
+            }
             for (int cy = ylo; cy <= yhi; cy++) {
+                W f = 0, r = 0, s2 = 0, gv = 0, rg = 0;
+                if (D == 2) { f = col.F; r = col.R; s2 = col.S; gv = col.G; rg = col.Q; col.next(); }
                 int xa, xb;
-                if (!row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb)) continue;
+                if (!span(cy, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
-                double e[4], h[3];
-                row_poly<D>(lf, lg, y, e, h);
-                W f, r, s2, gv, rg;
-                row_start<W>(e, h, (double)xa - ux, f, r, s2, gv, rg);
+                if (D == 2) {
+                    // walk from the column to the row's first point
+                    for (int k = xlo; k < xa; k++) { f *= r; r *= s2; s2 *= t3; gv *= rg; rg *= sg2; }
+                }
+                if (D == 1 || !row_start_ok(f, r, s2, gv, rg)) {
+                    double lf[NF], lg[NG], e[4], h[3];
+#pragma unroll
+                    for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
+#pragma unroll
+                    for (int j = 0; j < NG; j++) lg[j] = sg.at(j);
+                    row_poly<D>(lf, lg, y, e, h);
+                    row_start<W>(e, h, (double)xa - ux, f, r, s2, gv, rg);
+                }
                 W Rf[7], Rg[5];
 #pragma unroll
                 for (int k = 0; k < 7; k++) Rf[k] = 0;
@@ -942,22 +1038,36 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
             const double wsf = rho, wsg = rho * ph.K * RT;
             T *P = (T *)b.scratch + ti.base;
             int q = 0;
-            double lf[NF], lg[NG];
-#pragma unroll
-            for (int j = 0; j < NF; j++) lf[j] = sf.v.lam(j);
-#pragma unroll
-            for (int j = 0; j < NG; j++) lg[j] = sg.v.lam(j);
-            const W t3 = wexp<W>(-6.0 * lf[D == 2 ? 6 : 3]);
-            const W sg2 = wexp<W>(-2.0 * lg[D == 2 ? 3 : 2]);
+            const W t3 = wexp<W>(-6.0 * sf.v.lam(D == 2 ? 6 : 3));
+            const W sg2 = wexp<W>(-2.0 * sg.v.lam(D == 2 ? 3 : 2));
             const W wsfw = (W)wsf, wsgw = (W)wsg;
+            ColumnStarts col;
+            if (D == 2) {
+                double lf[NF], lg[NG];
+#pragma unroll
+                for (int j = 0; j < NF; j++) lf[j] = sf.v.lam(j);
+#pragma unroll
+                for (int j = 0; j < NG; j++) lg[j] = sg.v.lam(j);
+                col.init(lf, lg, (double)xlo - ux, (double)ylo - uy);
+            }
             for (int cy = ylo; cy <= yhi; cy++) {
+                W f = 0, r = 0, s2 = 0, gv = 0, rg = 0;
+                if (D == 2) { f = col.F; r = col.R; s2 = col.S; gv = col.G; rg = col.Q; col.next(); }
                 int xa, xb;
-                if (!row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb)) continue;
+                if (!span(cy, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
-                double e[4], h[3];
-                row_poly<D>(lf, lg, y, e, h);
-                W f, r, s2, gv, rg;
-                row_start<W>(e, h, (double)xa - ux, f, r, s2, gv, rg);
+                if (D == 2) {
+                    for (int k = xlo; k < xa; k++) { f *= r; r *= s2; s2 *= t3; gv *= rg; rg *= sg2; }
+                }
+                if (D == 1 || !row_start_ok(f, r, s2, gv, rg)) {
+                    double lf[NF], lg[NG], e[4], h[3];
+#pragma unroll
+                    for (int j = 0; j < NF; j++) lf[j] = sf.v.lam(j);
+#pragma unroll
+                    for (int j = 0; j < NG; j++) lg[j] = sg.v.lam(j);
+                    row_poly<D>(lf, lg, y, e, h);
+                    row_start<W>(e, h, (double)xa - ux, f, r, s2, gv, rg);
+                }
                 long long rowslot = (long long)(cy - ti.oy) * ti.wx - ti.ox;
                 for (int cx = xa; cx <= xb; cx++) {
                     W wf = wsfw * f, wg = wsgw * gv;
