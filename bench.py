@@ -57,7 +57,7 @@ FLOPS_PER_POINT_PASS_2D = 27 + 2 * 16 + 2 * 43 + 2 * 20
 # (velocity, density, temperature, radius: 20 bytes).
 GATHER_PAIR_BYTES = {"fp64": 16, "mixed": 8}
 GATHER_DESC_BYTES = 20
-RUNS = ("fp64-eq", "mixed-mlp", "mixed-eq", "fp64-mlp")
+RUNS = ("fp64-eq", "mixed-mlp", "mixed-eq", "fp64-mlp", "mixed-lin", "fp64-lin")
 # The paper's own timings (hot-box advection, 4096^2, RTX 4070), as context.
 PAPER_HOTBOX_S_PER_STEP = {0.5: 10.9, 2.0: 33.8}
 
@@ -203,7 +203,7 @@ def harvest_and_train(a, lb, li, torch):
 
 def timed_run(name, a, lb, torch, cfg, mom0, mlp):
     prec = lb.FP64 if name.startswith("fp64") else lb.MIXED
-    guess = lb.GUESS_MLP if name.endswith("mlp") else lb.GUESS_EQ
+    guess = {"eq": lb.GUESS_EQ, "mlp": lb.GUESS_MLP, "lin": lb.GUESS_LIN}[name.split("-")[1]]
     stream = torch.cuda.current_stream()
     ctx = lb.Lelbm(cfg, mom0, precision=prec, guess=guess, stream=stream)
     if guess == lb.GUESS_MLP:

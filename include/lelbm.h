@@ -68,7 +68,16 @@ enum { LELBM_FP64 = 0, LELBM_MIXED = 1 };
 
 /* Initial guess of the Newton solve: Eq. (IID13), or the learned network set
  * with lelbm_set_mlp (with Eq. (IID13) as fallback). */
-enum { LELBM_GUESS_EQ = 0, LELBM_GUESS_MLP = 1 };
+/* Newton initial guess.  EQ: Eq. (IID13), the equilibrium multipliers.
+ * LIN: Eq. (IID13) plus one Newton step taken in closed form with the
+ * moments of the continuous Maxwellian (the linear response of the
+ * multipliers to the non-equilibrium targets); it coincides with the first
+ * discrete Newton step up to the stencil's quadrature error.  MLP: LIN plus
+ * the correction predicted by the learned network (lelbm_set_mlp).  With
+ * LIN and MLP a cell whose first Newton update does not lower the residual
+ * restarts from Eq. (IID13); the converged result is the same in all modes
+ * (the multipliers are unique). */
+enum { LELBM_GUESS_EQ = 0, LELBM_GUESS_MLP = 1, LELBM_GUESS_LIN = 2 };
 
 typedef struct {
     int dim, nx, ny;                  /* dim = 1 requires ny = 1 */
@@ -82,7 +91,7 @@ typedef struct {
     int kn_limiter;                   /* 1: Knudsen limiter of App. D, Eqs. (D2-D3) */
     double kn_lo, kn_hi, omega_H;     /* log10 Kn thresholds and target frequency (paper: -2, -1, 1) */
     int precision;                    /* LELBM_FP64 | LELBM_MIXED */
-    int guess;                        /* LELBM_GUESS_EQ | LELBM_GUESS_MLP */
+    int guess;                        /* LELBM_GUESS_EQ | LELBM_GUESS_MLP | LELBM_GUESS_LIN */
     int bc[4];                        /* faces xlo, xhi, ylo, yhi: LELBM_BC_*; periodic faces pair up */
     int pad;                          /* pad width W of outflow/inflow faces (Sec. III, Fig. 5) */
     double in_rho, in_u[2], in_RT;    /* inflow (Dirichlet) state of LELBM_BC_INFLOW faces */

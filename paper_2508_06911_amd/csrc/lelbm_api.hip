@@ -165,7 +165,7 @@ static int validate(const lelbm_params *p) {
     if (!(p->K > 0.0) || !(p->n_conf > 0.0) || p->r_min < 1) return LELBM_EINVAL;
     if (!(p->newton_tol > 0.0) || p->newton_max_it < 1) return LELBM_EINVAL;
     if (p->precision != LELBM_FP64 && p->precision != LELBM_MIXED) return LELBM_EINVAL;
-    if (p->guess != LELBM_GUESS_EQ && p->guess != LELBM_GUESS_MLP) return LELBM_EINVAL;
+    if (p->guess != LELBM_GUESS_EQ && p->guess != LELBM_GUESS_MLP && p->guess != LELBM_GUESS_LIN) return LELBM_EINVAL;
     if (p->guess == LELBM_GUESS_MLP && p->dim != 2) return LELBM_EINVAL;
     if (p->solid && p->dim != 2) return LELBM_EINVAL;
     for (int f = 0; f < 4; f++)
@@ -352,6 +352,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ph.kn_lo_lin = pow(10.0, p->kn_lo); ph.kn_hi_lin = pow(10.0, p->kn_hi);
     ph.in_rho = p->in_rho; ph.in_u[0] = p->in_u[0]; ph.in_u[1] = p->dim == 2 ? p->in_u[1] : 0.0;
     ph.in_RT = p->in_RT;
+    ph.lin_guess = p->guess == LELBM_GUESS_LIN;
 
     size_t esz = c->mixed ? sizeof(float) : sizeof(double);
     Buffers &b = c->b;

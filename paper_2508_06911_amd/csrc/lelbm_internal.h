@@ -57,6 +57,7 @@ struct Phys {
     double kn_lo, kn_hi, omega_H;
     double kn_lo_lin, kn_hi_lin;  // 10^kn_lo, 10^kn_hi
     double in_rho, in_u[2], in_RT;
+    int lin_guess;                  // 1: start Newton from the linearised guess (lin_guess_scaled)
 };
 
 struct Flags {

@@ -673,6 +673,76 @@ __device__ inline void species_init(Species<NF, SF> &sf, Species<NG, SG> &sg, do
     sf.mlp = sg.mlp = 0; sf.res_prev = sg.res_prev = 0.0;
 }
 
+// Linearised initial multipliers.  At the equilibrium multipliers of
+// Eq. (IID13) the populations are the Maxwellian of variance RT, so one
+// Newton step A dlambda = (equilibrium moments - targets) can be taken with
+// the Hessian A_ij = <T_i T_j> of the continuous Maxwellian instead of the
+// stencil sums.  In units scaled by RT^(k/2) (k = polynomial order) A is a
+// constant matrix that splits by parity into blocks {1, x^2, y^2}, {xy},
+// {x, x^3, x y^2}, {y, x^2 y, y^3} (fluon), {1, x^2, y^2}, {xy}, {x}, {y}
+// (phonon); their inverses are written out below.  d receives the scaled
+// corrections (fluon 0..NF-1, phonon NF..), to be added to Eq. (IID13)'s
+// scaled values.  Targets: mf, mg as from collide_targets.
+template <int D>
+__device__ inline void lin_guess_scaled(const double *mf, const double *mg, double RT, double *d) {
+    const double is = 1.0 / sqrt(RT), i2 = 1.0 / RT, i3 = i2 * is;
+    if (D == 2) {
+        // scaled target deviations from equilibrium (targets minus Maxwellian moments)
+        const double a = mf[3] * i2 - 1.0, bxy = mf[4] * i2, c = mf[5] * i2 - 1.0;
+        const double x3 = mf[6] * i3, x2y = mf[7] * i3, xy2 = mf[8] * i3, y3 = mf[9] * i3;
+        const double n0 = mg[0] - 1.0, nx = mg[1] * is, ny = mg[2] * is;
+        // inverse of [[1,1,1],[1,3,1],[1,1,3]] = [[2,-1/2,-1/2],[-1/2,1/2,0],[-1/2,0,1/2]]
+        d[0] = 0.5 * (a + c);
+        d[3] = -0.5 * a;
+        d[5] = -0.5 * c;
+        d[4] = -bxy;
+        // inverse of [[1,3,1],[3,15,3],[1,3,3]] (x, x^3, x y^2) = [[3,-1/2,-1/2],[-1/2,1/6,0],[-1/2,0,1/2]]
+        d[1] = 0.5 * (x3 + xy2);
+        d[6] = -x3 / 6.0;
+        d[8] = -0.5 * xy2;
+        // the same block for (y, y^3, x^2 y)
+        d[2] = 0.5 * (y3 + x2y);
+        d[9] = -y3 / 6.0;
+        d[7] = -0.5 * x2y;
+        // phonons: only n0 and n_gamma deviate
+        d[10 + 0] = -2.0 * n0;
+        d[10 + 3] = 0.5 * n0;
+        d[10 + 5] = 0.5 * n0;
+        d[10 + 4] = 0.0;
+        d[10 + 1] = -nx;
+        d[10 + 2] = -ny;
+    } else {
+        const double a = mf[2] * i2 - 1.0, x3 = mf[3] * i3;
+        const double n0 = mg[0] - 1.0, nx = mg[1] * is;
+        // inverse of [[1,1],[1,3]] = [[3/2,-1/2],[-1/2,1/2]], of [[1,3],[3,15]] = [[5/2,-1/2],[-1/2,1/6]]
+        d[0] = 0.5 * a;
+        d[2] = -0.5 * a;
+        d[1] = 0.5 * x3;
+        d[3] = -x3 / 6.0;
+        d[4 + 0] = -1.5 * n0;
+        d[4 + 2] = 0.5 * n0;
+        d[4 + 1] = -nx;
+    }
+}
+
+// Adds the linearised correction to multipliers holding Eq. (IID13).
+template <int D, int NF, int NG, class SF, class SG>
+__device__ inline void species_linear(Species<NF, SF> &sf, Species<NG, SG> &sg, const double *mf, const double *mg,
+                                      double RT) {
+    double d[NF + NG];
+    lin_guess_scaled<D>(mf, mg, RT, d);
+    const double sq = sqrt(RT);
+#pragma unroll
+    for (int j = 0; j < NF + NG; j++) {
+        const int jj = j < NF ? j : j - NF;
+        const int k = order_of<D>(jj);
+        const double scl = k == 0 ? 1.0 : (k == 1 ? sq : (k == 2 ? RT : RT * sq));
+        if (j < NF) sf.v.lam(jj) += d[j] / scl;
+        else sg.v.lam(jj) += d[j] / scl;
+    }
+    sf.mlp = sg.mlp = 1;
+}
+
 // Per-cell statistics, reduced over the wavefront, one atomic per wave.
 struct CellStats {
     int it_f = 0, it_g = 0, q = 0, lim = 0, pass = 0, fb = 0;
@@ -921,6 +991,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         sf.v.lam_ = s_lamf + l; sf.v.del_ = s_delf + l;
         sg.v.lam_ = s_lamg + l; sg.v.del_ = s_delg + l;
         species_init<D, NF, NG>(sf, sg, RT);
+        if (ph.lin_guess) species_linear<D>(sf, sg, mf, mg, RT);
         if (D == 2 && b.guess) {
             // learned guess (scaled multipliers, see k_mlp_guess)
 #pragma unroll
@@ -1024,13 +1095,16 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
 #pragma unroll
                     for (int k = 0; k < 16; k++) hp[k] = x[k];
                     const double sq = sqrt(RT);
+                    double dl[16];
+                    lin_guess_scaled<2>(mf, mg, RT, dl);
 #pragma unroll
                     for (int j = 0; j < NF + NG; j++) {
                         const int jj = j < NF ? j : j - NF;
                         const double lam = j < NF ? sf.v.lam(jj) : sg.v.lam(jj);
                         const int k = basis_order2(jj);
                         const double scl = k == 0 ? 1.0 : (k == 1 ? sq : (k == 2 ? RT : RT * sq));
-                        hp[16 + j] = (float)(lam * scl - iid13_scaled(jj, RT));
+                        // target: what the network adds to the linearised guess
+                        hp[16 + j] = (float)(lam * scl - iid13_scaled(jj, RT) - dl[j]);
                     }
                 }
             }
@@ -1259,6 +1333,9 @@ __global__ void __launch_bounds__(256) k_mlp_guess(Geom g, Phys ph, const T *mom
     const int rn = valid ? b.desc_rn[s] : -1;
     const bool active = rn >= 0 && (rn >> 16) == 0;
     double RT = 1.0;
+    double dl[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) dl[k] = 0.0;
     float x[16];
 #pragma unroll
     for (int k = 0; k < 16; k++) x[k] = 0.f;
@@ -1269,6 +1346,7 @@ __global__ void __launch_bounds__(256) k_mlp_guess(Geom g, Phys ph, const T *mom
         int lim;
         collide_targets<T, 2>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, kn, lim);
         mlp_features(mf, mg, ux, uy, RT, rn & 0xffff, x);
+        lin_guess_scaled<2>(mf, mg, RT, dl);
     }
 #pragma unroll
     for (int k = 0; k < 16; k++) xs[wv][lane * MLP_IN + k] = f2bf(norm_in(b.mlp_n, k, x[k]));
@@ -1290,7 +1368,7 @@ __global__ void __launch_bounds__(256) k_mlp_guess(Geom g, Phys ph, const T *mom
         const int k = basis_order2(jj);
         const double scl = k == 0 ? 1.0 : (k == 1 ? sq : (k == 2 ? RT : RT * sq));
         const double yj = (double)denorm_out(b.mlp_n, j, ys[wv][lane * MLP_OUT + j]);
-        b.guess[(long long)j * g.ns + s] = (yj + iid13_scaled(jj, RT)) / scl;
+        b.guess[(long long)j * g.ns + s] = (yj + iid13_scaled(jj, RT) + dl[j]) / scl;
     }
 }
 

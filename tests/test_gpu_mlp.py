@@ -118,7 +118,9 @@ def test_learned_guess_matches_plain_path_and_saves_iterations():
     loss = m.train(pairs, steps=3000, batch=2048, lr=2e-3, seed=5)
     _, mse = m.gradient(pairs)
     print("train loss", loss, "standardised mse on all pairs", mse)
-    assert mse < 0.05                      # > 95% of the target variance explained
+    # the target is what remains after the linearised guess: > 80 % of its
+    # variance explained
+    assert mse < 0.2
     cfg, prim = li.quadrants(9, n=96)
     for prec in (lb.FP64, lb.MIXED):
         a, sa = run_gpu(cfg, prim, 30, precision=prec)
@@ -137,3 +139,20 @@ def test_learned_guess_matches_plain_path_and_saves_iterations():
         assert sb["point_passes"] < sa["point_passes"]
         assert sb["it_mean_f"] < sa["it_mean_f"] and sb["it_mean_g"] < sa["it_mean_g"]
     m.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_linearised_guess_matches_plain_path(prec):
+    """Newton started from the closed-form linearised multipliers converges
+    to the same fields (the multipliers are unique) in no more passes."""
+    _case("linearised guess quadrants 96x96 precision %d" % prec)
+    import paper_2508_06911_amd as lb
+    cfg, prim = li.quadrants(7, n=96)
+    a, sa = run_gpu(cfg, prim, 30, precision=prec)
+    b, sb = run_gpu(cfg, prim, 30, precision=prec, guess=lb.GUESS_LIN)
+    err = rel_linf(b, a)
+    pa = sa["point_passes"] / sa["q_mean"] / sa["cells"]
+    pb = sb["point_passes"] / sb["q_mean"] / sb["cells"]
+    print("rel_linf", err, "passes plain", pa, "linearised", pb, "fallbacks", sb["fallbacks"])
+    assert err < (1e-10 if prec == 0 else 1e-5)
+    assert pb <= pa
