@@ -975,9 +975,11 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                 spt[cy - ylo] = v;
             }
         }
-        auto span = [&](int cy, int &xa, int &xb) -> bool {
+        // Row cy's span from the table entry v (loaded one row ahead, so the
+        // load latency hides behind the previous row's points) or, without a
+        // table, computed directly.
+        auto span = [&](unsigned v, int cy, int &xa, int &xb) -> bool {
             if (tab) {
-                const unsigned v = spt[cy - ylo];
                 xa = xlo + (int)(v & 0xffu);
                 xb = xlo + (int)(v >> 8);
                 return xa <= xb;
@@ -1012,6 +1014,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
             for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
             // multipliers of this pass live in LDS; registers hold them only
             // while the column and the rare direct row starts are set up
+            unsigned nxt = tab ? spt[0] : 0u;
             const W t3 = wexp<W>(-6.0 * sf.at(D == 2 ? 6 : 3));
             const W sg2 = wexp<W>(-2.0 * sg.at(D == 2 ? 3 : 2));
             ColumnStarts col;
@@ -1026,8 +1029,10 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
             for (int cy = ylo; cy <= yhi; cy++) {
                 W f = 0, r = 0, s2 = 0, gv = 0, rg = 0;
                 if (D == 2) { f = col.F; r = col.R; s2 = col.S; gv = col.G; rg = col.Q; col.next(); }
+                const unsigned cur = nxt;
+                if (tab && cy < yhi) nxt = spt[cy + 1 - ylo];
                 int xa, xb;
-                if (!span(cy, xa, xb)) continue;
+                if (!span(cur, cy, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
                 if (D == 2) {
                     // walk from the column to the row's first point
@@ -1112,6 +1117,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
             const double wsf = rho, wsg = rho * ph.K * RT;
             T *P = (T *)b.scratch + ti.base;
             int q = 0;
+            unsigned nxt = tab ? spt[0] : 0u;
             const W t3 = wexp<W>(-6.0 * sf.v.lam(D == 2 ? 6 : 3));
             const W sg2 = wexp<W>(-2.0 * sg.v.lam(D == 2 ? 3 : 2));
             const W wsfw = (W)wsf, wsgw = (W)wsg;
@@ -1127,8 +1133,10 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
             for (int cy = ylo; cy <= yhi; cy++) {
                 W f = 0, r = 0, s2 = 0, gv = 0, rg = 0;
                 if (D == 2) { f = col.F; r = col.R; s2 = col.S; gv = col.G; rg = col.Q; col.next(); }
+                const unsigned cur = nxt;
+                if (tab && cy < yhi) nxt = spt[cy + 1 - ylo];
                 int xa, xb;
-                if (!span(cy, xa, xb)) continue;
+                if (!span(cur, cy, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
                 if (D == 2) {
                     for (int k = xlo; k < xa; k++) { f *= r; r *= s2; s2 *= t3; gv *= rg; rg *= sg2; }
@@ -1152,7 +1160,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                     } else {
                         W c1 = (W)cx, c2 = (W)cy;
                         W mo[NM];
-                        if (D == 1) {
+                        if constexpr (D == 1) {
                             mo[0] = wf; mo[1] = c1 * wf; mo[2] = c1 * c1 * wf; mo[3] = c1 * c1 * c1 * wf;
                             mo[4] = wg; mo[5] = c1 * wg;
                         } else {
