@@ -1,0 +1,78 @@
+"""Physics of the HIP path against closed forms (Sec. IV): the decay rate of a
+shear wave gives the shear viscosity nu_s = RT (1/omega_f - 1/2) (Eq. C8a),
+the decay of an isobaric density wave the thermal diffusivity
+alpha = RT (1/omega_h - 1/2) (Eq. C8c), and a weak pulse travels at
+c_s = sqrt(gamma RT).  The paper measures the first two at Fourier number
+Fo = 1 and draws +-10 % margins; the same bar is used here, on both precision
+paths, at sizes and step counts the CPU oracle would take minutes for."""
+import numpy as np
+import pytest
+
+import lelbm_inputs as li
+from helpers import gpu_moments, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _print_case(name):
+    print("\n[gpu case] %s" % name, flush=True)
+
+
+@pytest.mark.parametrize("RT,nu,prec", [(0.5, 0.1, 0), (1.0, 0.1, 0), (2.0, 0.1, 0), (0.5, 0.01, 0),
+                                        (1.0, 0.01, 0), (0.5, 0.01, 1)])
+def test_shear_wave_viscosity(RT, nu, prec):
+    """Eqs. (VA1)-(VA5): u_y = u' cos(k (x - u0 t)) exp(-nu k^2 t) on a
+    uniform flow u0 = 0.5 (the paper's worst case: the distribution centre
+    lands between cells every step); nu measured from max_x |u_y| at Fo = 1."""
+    L = 64
+    _print_case("shear wave L=%d RT=%g nu=%g precision=%d" % (L, RT, nu, prec))
+    cfg, prim = li.shear_wave(L=L, ny=2, RT=RT, nu=nu)
+    k = 2 * np.pi / L
+    t = int(round(1.0 / (nu * k * k)))
+    out, st = run_gpu(cfg, prim, t, precision=prec)
+    uy = out[2] / out[0]
+    nu_m = -np.log(np.abs(uy).max() / 1e-3) / (k * k * t)
+    print("measured nu %.5g (target %.5g, %d steps)" % (nu_m, nu, t), flush=True)
+    assert abs(nu_m / nu - 1) < 0.10
+
+
+@pytest.mark.parametrize("RT,alpha", [(0.5, 0.1), (1.0, 0.1), (0.5, 0.01)])
+def test_thermal_wave_diffusivity(RT, alpha):
+    """Sec. IV.B: an isobaric density wave rho = 1 + 0.01 cos(k x) on u0 = 0.5
+    decays at alpha k^2 with alpha = kappa / (rho C_p) = RT (1/omega_h - 1/2)."""
+    L = 64
+    _print_case("thermal wave L=%d RT=%g alpha=%g" % (L, RT, alpha))
+    cfg, prim = li.shear_wave(L=L, ny=2, RT=RT, nu=alpha, amp=0.0)
+    x = (np.arange(L) + 0.5)[None, :]
+    rho = (1.0 + 0.01 * np.cos(2 * np.pi * x / L)) * np.ones((2, 1))
+    prim["rho"] = rho
+    prim["RT"] = RT / rho
+    k = 2 * np.pi / L
+    t = int(round(1.0 / (alpha * k * k)))
+    out, st = run_gpu(cfg, prim, t, mom=gpu_moments(cfg, prim))
+    am = -np.log(np.abs(out[0] - 1.0).max() / 0.01) / (k * k * t)
+    print("measured alpha %.5g (target %.5g, %d steps)" % (am, alpha, t), flush=True)
+    assert abs(am / alpha - 1) < 0.10
+
+
+@pytest.mark.parametrize("RT", [0.5, 2.0, 8.0])
+def test_acoustic_pulse_sound_speed(RT):
+    """Sec. IV.D: a weak pressure pulse in 1D travels at c_s = sqrt(gamma RT);
+    the pressure peak is located to sub-cell accuracy by a parabola."""
+    n = 1200
+    _print_case("acoustic pulse n=%d RT=%g" % (n, RT))
+    cfg, prim = li.acoustic_pulse(n=n, RT=RT, pad=64)
+    cs = np.sqrt(1.4 * RT)
+    t = int(400 / cs)
+    out, st = run_gpu(cfg, prim, t)
+    rho = out[0]
+    ux = out[1] / rho
+    RTm = ((out[2] + out[4]) / rho - ux ** 2) / (1 + cfg["K"])
+    p = rho * RTm
+    x = np.arange(n) + 0.5
+    i = int(np.argmax(np.where(x > n / 2, p, -1)))
+    y0, y1, y2 = p[i - 1], p[i], p[i + 1]
+    xp = x[i] + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)
+    c_m = (xp - n / 2) / t
+    print("measured c_s %.5g (sqrt(gamma RT) = %.5g, %d steps)" % (c_m, cs, t), flush=True)
+    assert abs(c_m / cs - 1) < 0.01
