@@ -57,7 +57,7 @@ FLOPS_PER_POINT_PASS_2D = 27 + 2 * 16 + 2 * 43 + 2 * 20
 # (velocity, density, temperature, radius: 20 bytes).
 GATHER_PAIR_BYTES = {"fp64": 16, "mixed": 8}
 GATHER_DESC_BYTES = 20
-RUNS = ("fp64-eq", "mixed-mlp", "mixed-eq", "fp64-mlp", "mixed-lin", "fp64-lin")
+RUNS = ("fp64-eq", "mixed-mlp", "mixed-eq", "fp64-mlp", "mixed-lin", "fp64-lin", "mixed-prev", "fp64-prev")
 # The paper's own timings (hot-box advection, 4096^2, RTX 4070), as context.
 PAPER_HOTBOX_S_PER_STEP = {0.5: 10.9, 2.0: 33.8}
 
@@ -206,7 +206,7 @@ def harvest_and_train(a, lb, li, torch):
 
 def timed_run(name, a, lb, torch, cfg, mom0, mlp):
     prec = lb.FP64 if name.startswith("fp64") else lb.MIXED
-    guess = {"eq": lb.GUESS_EQ, "mlp": lb.GUESS_MLP, "lin": lb.GUESS_LIN}[name.split("-")[1]]
+    guess = {"eq": lb.GUESS_EQ, "mlp": lb.GUESS_MLP, "lin": lb.GUESS_LIN, "prev": lb.GUESS_PREV}[name.split("-")[1]]
     stream = torch.cuda.current_stream()
     ctx = lb.Lelbm(cfg, mom0, precision=prec, guess=guess, stream=stream)
     if guess == lb.GUESS_MLP:
@@ -243,7 +243,7 @@ def timed_run(name, a, lb, torch, cfg, mom0, mlp):
         "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]},
         "newton_it": {"mean_f": round(st["it_mean_f"], 3), "max_f": st["it_max_f"],
                       "mean_g": round(st["it_mean_g"], 3), "max_g": st["it_max_g"]},
-        "passes_per_cell": round(st["point_passes"] / max(st["q_mean"], 1e-30) / st["cells"], 3),
+        "passes_per_cell": round(st["point_passes"] / max(st["q_mean"], 1e-30) / max(st["cells"], 1), 3),
         "refined_share": round(st["point_passes_refined"] / max(st["point_passes"], 1), 5),
         "fallbacks": st["fallbacks"], "stencil_q": {"min": st["q_min"], "mean": round(st["q_mean"], 1),
                                                     "max": st["q_max"]},

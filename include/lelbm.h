@@ -74,10 +74,17 @@ enum { LELBM_FP64 = 0, LELBM_MIXED = 1 };
  * multipliers to the non-equilibrium targets); it coincides with the first
  * discrete Newton step up to the stencil's quadrature error.  MLP: LIN plus
  * the correction predicted by the learned network (lelbm_set_mlp).  With
- * LIN and MLP a cell whose first Newton update does not lower the residual
- * restarts from Eq. (IID13); the converged result is the same in all modes
- * (the multipliers are unique). */
-enum { LELBM_GUESS_EQ = 0, LELBM_GUESS_MLP = 1, LELBM_GUESS_LIN = 2 };
+ * PREV: LIN plus the cell's own correction beyond LIN from the previous
+ * step (the warm start from stored multipliers the paper suggests in
+ * Sec. II.D).  The correction is kept in scaled units, so it carries over
+ * when the temperature changes; at omega = 2 the non-equilibrium part of the
+ * targets flips sign every step, and LIN, not the stored correction, follows
+ * that flip.  The context keeps 16 doubles per cell for it; the first step,
+ * and cells whose previous step used refined stencils, start from LIN.
+ * With LIN, MLP and PREV a cell whose first Newton update does not lower
+ * the residual restarts from Eq. (IID13); the converged result is the same
+ * in all modes (the multipliers are unique). */
+enum { LELBM_GUESS_EQ = 0, LELBM_GUESS_MLP = 1, LELBM_GUESS_LIN = 2, LELBM_GUESS_PREV = 3 };
 
 typedef struct {
     int dim, nx, ny;                  /* dim = 1 requires ny = 1 */
@@ -91,7 +98,7 @@ typedef struct {
     int kn_limiter;                   /* 1: Knudsen limiter of App. D, Eqs. (D2-D3) */
     double kn_lo, kn_hi, omega_H;     /* log10 Kn thresholds and target frequency (paper: -2, -1, 1) */
     int precision;                    /* LELBM_FP64 | LELBM_MIXED */
-    int guess;                        /* LELBM_GUESS_EQ | LELBM_GUESS_MLP | LELBM_GUESS_LIN */
+    int guess;                        /* LELBM_GUESS_EQ | _MLP | _LIN | _PREV */
     int bc[4];                        /* faces xlo, xhi, ylo, yhi: LELBM_BC_*; periodic faces pair up */
     int pad;                          /* pad width W of outflow/inflow faces (Sec. III, Fig. 5) */
     double in_rho, in_u[2], in_RT;    /* inflow (Dirichlet) state of LELBM_BC_INFLOW faces */

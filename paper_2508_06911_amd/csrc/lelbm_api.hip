@@ -165,7 +165,9 @@ static int validate(const lelbm_params *p) {
     if (!(p->K > 0.0) || !(p->n_conf > 0.0) || p->r_min < 1) return LELBM_EINVAL;
     if (!(p->newton_tol > 0.0) || p->newton_max_it < 1) return LELBM_EINVAL;
     if (p->precision != LELBM_FP64 && p->precision != LELBM_MIXED) return LELBM_EINVAL;
-    if (p->guess != LELBM_GUESS_EQ && p->guess != LELBM_GUESS_MLP && p->guess != LELBM_GUESS_LIN) return LELBM_EINVAL;
+    if (p->guess != LELBM_GUESS_EQ && p->guess != LELBM_GUESS_MLP && p->guess != LELBM_GUESS_LIN &&
+        p->guess != LELBM_GUESS_PREV)
+        return LELBM_EINVAL;
     if (p->guess == LELBM_GUESS_MLP && p->dim != 2) return LELBM_EINVAL;
     if (p->solid && p->dim != 2) return LELBM_EINVAL;
     for (int f = 0; f < 4; f++)
@@ -187,7 +189,8 @@ static void free_ctx(lelbm_ctx *c) {
     Buffers &b = c->b;
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.spans, b.tiles,
                     b.dwin, b.scratch, b.flags, b.stats, b.partial, b.guess, b.harvest_n,
-                    c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach};
+                    c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, b.lamprev,
+                    b.bpart, b.gpart};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (c->ev[0]) (void)hipEventDestroy(c->ev[0]);
@@ -353,6 +356,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ph.in_rho = p->in_rho; ph.in_u[0] = p->in_u[0]; ph.in_u[1] = p->dim == 2 ? p->in_u[1] : 0.0;
     ph.in_RT = p->in_RT;
     ph.lin_guess = p->guess == LELBM_GUESS_LIN;
+    ph.prev_guess = p->guess == LELBM_GUESS_PREV;
 
     size_t esz = c->mixed ? sizeof(float) : sizeof(double);
     Buffers &b = c->b;
@@ -372,6 +376,13 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ok = ok && hipMalloc((void **)&b.stats, sizeof(DevStats)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.partial, (size_t)(num_sum_blocks(g) + 1) * 4 * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.harvest_n, sizeof(unsigned long long)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.bpart, (size_t)nt * sizeof(DevStats)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.gpart, (size_t)nd * sizeof(unsigned long long)) == hipSuccess;
+    if (p->guess == LELBM_GUESS_PREV) {
+        ok = ok && hipMalloc((void **)&b.lamprev, (size_t)16 * ns * sizeof(double)) == hipSuccess;
+        // all-ones bytes are a NaN: no stored correction yet
+        ok = ok && hipMemset(b.lamprev, 0xff, (size_t)16 * ns * sizeof(double)) == hipSuccess;
+    }
     if (p->guess == LELBM_GUESS_MLP) {
         ok = ok && hipMalloc((void **)&b.guess, (size_t)16 * ns * sizeof(double)) == hipSuccess;
         ok = ok && hipMalloc((void **)&c->mlp_w, MLP_NPARAM * sizeof(unsigned short)) == hipSuccess;
@@ -380,7 +391,8 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     }
     if (!ok) { free_ctx(c); return LELBM_ENOMEM; }
     c->persistent_bytes = (long long)2 * c->nmom * ns * esz + ns * (4 * sizeof(double) + sizeof(int)) +
-                          nt * sizeof(TileInfo) + nd * sizeof(DWin);
+                          nt * sizeof(TileInfo) + nd * sizeof(DWin) +
+                          (b.lamprev ? (long long)16 * ns * sizeof(double) : 0);
     int r = setup_blockers(c, p->solid);
     if (r != LELBM_OK) { free_ctx(c); return r; }
     if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {

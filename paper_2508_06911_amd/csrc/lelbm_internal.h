@@ -58,6 +58,7 @@ struct Phys {
     double kn_lo_lin, kn_hi_lin;  // 10^kn_lo, 10^kn_hi
     double in_rho, in_u[2], in_RT;
     int lin_guess;                  // 1: start Newton from the linearised guess (lin_guess_scaled)
+    int prev_guess;                 // 1: linearised guess plus the cell's previous-step correction
 };
 
 struct Flags {
@@ -110,6 +111,10 @@ struct Buffers {
     const float *mlp_p;            // FP32 parameters (biases read from here)
     const float *mlp_n;            // standardisation constants (64)
     double *guess;                 // [16][ns] initial multipliers, NULL = Eq. (IID13)
+    DevStats *bpart;               // [ntx*nty] per-workgroup statistics of k_epr
+    unsigned long long *gpart;     // [dtx*dty] per-workgroup arrival counts of k_gather
+    double *lamprev;               // [16][ns] scaled correction beyond the linearised guess, last step
+                                   // (NaN in row 0: none); allocated for LELBM_GUESS_PREV only
     // harvesting of (features, converged multipliers) pairs
     float *harvest;                // [cap][32], NULL = off
     long long harvest_cap;

@@ -743,7 +743,56 @@ __device__ inline void species_linear(Species<NF, SF> &sf, Species<NG, SG> &sg, 
     sf.mlp = sg.mlp = 1;
 }
 
-// Per-cell statistics, reduced over the wavefront, one atomic per wave.
+// Multiplier j of Eq. (IID13), unscaled: the Maxwellian of variance RT.
+template <int D>
+__device__ inline double iid13_value(int j, double RT) {
+    if (j == 0) return -1.0 + 0.5 * D * log(2.0 * M_PI * RT);
+    if (D == 2 ? (j == 3 || j == 5) : j == 2) return 0.5 / RT;
+    return 0.0;
+}
+
+// Warm start from the previous step (Sec. II.D suggests reusing stored
+// multipliers).  The stored quantity is the cell's correction beyond the
+// linearised guess in scaled units, e_j = lambda_j RT^(k/2) - (IID13 + LIN)_j
+// (k = basis order), which carries over smoothly across steps; the
+// linearised part follows this step's targets, including the sign flip of
+// their non-equilibrium part at omega = 2.  prev = NaN in row 0: none.
+template <int D, int NF, int NG, class SF, class SG>
+__device__ inline void species_prev(Species<NF, SF> &sf, Species<NG, SG> &sg, const double *mf, const double *mg,
+                                    double RT, const double *prev, long long ns, long long s) {
+    species_linear<D>(sf, sg, mf, mg, RT);
+    if (!(prev[s] == prev[s])) return;
+    const double sq = sqrt(RT);
+#pragma unroll
+    for (int j = 0; j < NF + NG; j++) {
+        const int jj = j < NF ? j : j - NF;
+        const int k = order_of<D>(jj);
+        const double scl = k == 0 ? 1.0 : (k == 1 ? sq : (k == 2 ? RT : RT * sq));
+        const double e = prev[(long long)j * ns + s];
+        if (j < NF) sf.v.lam(jj) += e / scl;
+        else sg.v.lam(jj) += e / scl;
+    }
+}
+
+// Stores the converged multipliers' correction beyond IID13 + LIN (see
+// species_prev) for the next step's guess.
+template <int D, int NF, int NG, class SF, class SG>
+__device__ inline void store_prev(Species<NF, SF> &sf, Species<NG, SG> &sg, const double *mf, const double *mg,
+                                  double RT, double *prev, long long ns, long long s) {
+    double d[NF + NG];
+    lin_guess_scaled<D>(mf, mg, RT, d);
+    const double sq = sqrt(RT);
+#pragma unroll
+    for (int j = 0; j < NF + NG; j++) {
+        const int jj = j < NF ? j : j - NF;
+        const int k = order_of<D>(jj);
+        const double scl = k == 0 ? 1.0 : (k == 1 ? sq : (k == 2 ? RT : RT * sq));
+        const double lam = j < NF ? sf.v.lam(jj) : sg.v.lam(jj);
+        prev[(long long)j * ns + s] = (lam - iid13_value<D>(jj, RT)) * scl - d[j];
+    }
+}
+
+// Per-cell statistics.
 struct CellStats {
     int it_f = 0, it_g = 0, q = 0, lim = 0, pass = 0, fb = 0;
     double kn = 0.0, colat = 0.0, rt = 1e300;
@@ -751,45 +800,101 @@ struct CellStats {
     bool refined = false;    // handled by the refined-stencil kernel
 };
 
-__device__ inline void push_stats(DevStats *st, const CellStats &c) {
-    unsigned long long a_itf = c.it_f, a_itg = c.it_g, a_q = c.q, a_lim = c.lim, a_cells = c.active ? 1 : 0;
-    unsigned long long a_qp = (unsigned long long)c.q * c.pass, a_fb = c.fb;
-    unsigned long long a_qpr = c.refined ? a_qp : 0ull;
-    int m_itf = c.it_f, m_itg = c.it_g, m_q = c.q, n_q = c.active ? c.q : 1 << 30;
-    double m_kn = c.kn, m_colat = c.colat, n_rt = c.rt;
-    for (int off = 32; off > 0; off >>= 1) {
-        a_itf += __shfl_xor(a_itf, off);
-        a_itg += __shfl_xor(a_itg, off);
-        a_q += __shfl_xor(a_q, off);
-        a_lim += __shfl_xor(a_lim, off);
-        a_cells += __shfl_xor(a_cells, off);
-        a_qp += __shfl_xor(a_qp, off);
-        a_qpr += __shfl_xor(a_qpr, off);
-        a_fb += __shfl_xor(a_fb, off);
-        m_itf = max(m_itf, __shfl_xor(m_itf, off));
-        m_itg = max(m_itg, __shfl_xor(m_itg, off));
-        m_q = max(m_q, __shfl_xor(m_q, off));
-        n_q = min(n_q, __shfl_xor(n_q, off));
-        m_kn = fmax(m_kn, __shfl_xor(m_kn, off));
-        m_colat = fmax(m_colat, __shfl_xor(m_colat, off));
-        n_rt = fmin(n_rt, __shfl_xor(n_rt, off));
+// Sums, maxima and minima of CellStats over a set of cells (the fields of
+// DevStats; an empty set is the neutral element).
+struct StatSum {
+    unsigned long long itf = 0, itg = 0, q = 0, lim = 0, cells = 0, qp = 0, qpr = 0, fb = 0;
+    int mitf = 0, mitg = 0, mq = 0, nq = 1 << 30;
+    double mkn = 0.0, mcolat = 0.0, nrt = 1e300;
+    __device__ void add_cell(const CellStats &c) {
+        if (!c.active) return;
+        itf = c.it_f; itg = c.it_g; q = c.q; lim = c.lim; cells = 1;
+        qp = (unsigned long long)c.q * c.pass; qpr = c.refined ? qp : 0ull; fb = c.fb;
+        mitf = c.it_f; mitg = c.it_g; mq = c.q; nq = c.q;
+        mkn = c.kn; mcolat = c.colat; nrt = c.rt;
     }
-    if ((threadIdx.x & 63) == 0 && a_cells > 0) {
-        atomicAdd(&st->it_sum_f, a_itf);
-        atomicAdd(&st->it_sum_g, a_itg);
-        atomicAdd(&st->q_sum, a_q);
-        atomicAdd(&st->limited, a_lim);
-        atomicAdd(&st->cells, a_cells);
-        atomicAdd(&st->qpass_sum, a_qp);
-        if (a_qpr) atomicAdd(&st->qpass_ref_sum, a_qpr);
-        if (a_fb) atomicAdd(&st->fallbacks, a_fb);
-        atomicMax(&st->it_max_f, m_itf);
-        atomicMax(&st->it_max_g, m_itg);
-        atomicMax(&st->q_max, m_q);
-        atomicMin(&st->q_min, n_q);
-        atomic_max_pos(&st->kn_max_bits, m_kn);
-        atomic_max_pos(&st->colat_max_bits, m_colat);
-        atomic_min_pos(&st->rt_min_bits, n_rt);
+    __device__ void add(const StatSum &o) {
+        itf += o.itf; itg += o.itg; q += o.q; lim += o.lim; cells += o.cells; qp += o.qp; qpr += o.qpr;
+        fb += o.fb;
+        mitf = max(mitf, o.mitf); mitg = max(mitg, o.mitg); mq = max(mq, o.mq); nq = min(nq, o.nq);
+        mkn = fmax(mkn, o.mkn); mcolat = fmax(mcolat, o.mcolat); nrt = fmin(nrt, o.nrt);
+    }
+    __device__ void wave_reduce() {
+        for (int off = 32; off > 0; off >>= 1) {
+            StatSum o;
+            o.itf = __shfl_xor(itf, off); o.itg = __shfl_xor(itg, off); o.q = __shfl_xor(q, off);
+            o.lim = __shfl_xor(lim, off); o.cells = __shfl_xor(cells, off); o.qp = __shfl_xor(qp, off);
+            o.qpr = __shfl_xor(qpr, off); o.fb = __shfl_xor(fb, off);
+            o.mitf = __shfl_xor(mitf, off); o.mitg = __shfl_xor(mitg, off); o.mq = __shfl_xor(mq, off);
+            o.nq = __shfl_xor(nq, off);
+            o.mkn = __shfl_xor(mkn, off); o.mcolat = __shfl_xor(mcolat, off); o.nrt = __shfl_xor(nrt, off);
+            add(o);
+        }
+    }
+    __device__ void load(const DevStats &d) {
+        itf = d.it_sum_f; itg = d.it_sum_g; q = d.q_sum; lim = d.limited; cells = d.cells; qp = d.qpass_sum;
+        qpr = d.qpass_ref_sum; fb = d.fallbacks;
+        mitf = d.it_max_f; mitg = d.it_max_g; mq = d.q_max; nq = d.q_min;
+        mkn = __longlong_as_double((long long)d.kn_max_bits);
+        mcolat = __longlong_as_double((long long)d.colat_max_bits);
+        nrt = __longlong_as_double((long long)d.rt_min_bits);
+    }
+    __device__ void store(DevStats &d) const {
+        d.it_sum_f = itf; d.it_sum_g = itg; d.q_sum = q; d.limited = lim; d.cells = cells; d.qpass_sum = qp;
+        d.qpass_ref_sum = qpr; d.fallbacks = fb; d.arrivals = 0;
+        d.it_max_f = mitf; d.it_max_g = mitg; d.q_max = mq; d.q_min = nq;
+        d.kn_max_bits = (unsigned long long)__double_as_longlong(mkn);
+        d.colat_max_bits = (unsigned long long)__double_as_longlong(mcolat);
+        d.rt_min_bits = (unsigned long long)__double_as_longlong(nrt);
+    }
+    // One atomic per field: for the few partials of a reduction (never per
+    // wavefront of a large grid: same-address atomics serialise device-wide).
+    __device__ void atomics_into(DevStats *st) const {
+        if (cells == 0) return;
+        atomicAdd(&st->it_sum_f, itf);
+        atomicAdd(&st->it_sum_g, itg);
+        atomicAdd(&st->q_sum, q);
+        atomicAdd(&st->limited, lim);
+        atomicAdd(&st->cells, cells);
+        atomicAdd(&st->qpass_sum, qp);
+        if (qpr) atomicAdd(&st->qpass_ref_sum, qpr);
+        if (fb) atomicAdd(&st->fallbacks, fb);
+        atomicMax(&st->it_max_f, mitf);
+        atomicMax(&st->it_max_g, mitg);
+        atomicMax(&st->q_max, mq);
+        atomicMin(&st->q_min, nq);
+        atomic_max_pos(&st->kn_max_bits, mkn);
+        atomic_max_pos(&st->colat_max_bits, mcolat);
+        atomic_min_pos(&st->rt_min_bits, nrt);
+    }
+};
+
+// Statistics of a workgroup's cells, one wave-reduced atomic set per wave
+// (used by kernels that run on few workgroups).
+__device__ inline void push_stats(DevStats *st, const CellStats &c) {
+    StatSum a;
+    a.add_cell(c);
+    a.wave_reduce();
+    if ((threadIdx.x & 63) == 0) a.atomics_into(st);
+}
+
+// Statistics of a 256-lane workgroup written as one partial (no atomics);
+// k_stats_reduce sums the partials.  Every thread of the workgroup calls it.
+__device__ inline void block_stats(DevStats *part, const CellStats &c) {
+    __shared__ DevStats s_w[4];
+    StatSum a;
+    a.add_cell(c);
+    a.wave_reduce();
+    if ((threadIdx.x & 63) == 0) a.store(s_w[threadIdx.x >> 6]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        StatSum t;
+        for (int w = 0; w < 4; w++) {
+            StatSum o;
+            o.load(s_w[w]);
+            t.add(o);
+        }
+        t.store(part[blockIdx.x]);
     }
 }
 
@@ -946,7 +1051,10 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
     __shared__ int s_err;
     if (threadIdx.x == 0) s_err = b.flags->err;
     __syncthreads();
-    if (s_err) return;
+    if (s_err) {
+        if (threadIdx.x == 0) StatSum().store(b.bpart[blockIdx.x]);
+        return;
+    }
     int t = blockIdx.x;
     int tx0 = (t % g.ntx) * g.tx, ty0 = (t / g.ntx) * g.ty;
     int l = threadIdx.x;
@@ -994,6 +1102,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         sg.v.lam_ = s_lamg + l; sg.v.del_ = s_delg + l;
         species_init<D, NF, NG>(sf, sg, RT);
         if (ph.lin_guess) species_linear<D>(sf, sg, mf, mg, RT);
+        if (ph.prev_guess) species_prev<D>(sf, sg, mf, mg, RT, b.lamprev, g.ns, s);
         if (D == 2 && b.guess) {
             // learned guess (scaled multipliers, see k_mlp_guess)
 #pragma unroll
@@ -1091,6 +1200,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         if (fail) {
             flag_fail(b.flags, LELBM_EEPR, step, s, fail, fsp, fsp ? sg.res : sf.res);
         } else {
+            if (ph.prev_guess) store_prev<D>(sf, sg, mf, mg, RT, b.lamprev, g.ns, s);
             if (D == 2 && b.harvest && ((s + (long long)step * 7919) % b.harvest_stride) == 0) {
                 unsigned long long slot = atomicAdd(b.harvest_n, 1ull);
                 if (slot < (unsigned long long)b.harvest_cap) {
@@ -1186,7 +1296,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
             cs.colat = (D == 2 ? sqrt(ux * ux + uy * uy) : fabs(ux)) + R;
         }
     }
-    push_stats(b.stats, cs);
+    block_stats(b.bpart, cs);
 }
 
 // ---------------------------------------------------------------------------
@@ -1215,6 +1325,8 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
     cs.active = rn >= 0 && (rn >> 16) > 0;
     cs.refined = true;
     if (cs.active) {
+        // refined cells leave no correction for the next step's warm start
+        if (ph.prev_guess) b.lamprev[s] = __builtin_nan("");
         const TileInfo ti = b.tiles[t];
         double rho = b.desc_rho[s], ux = b.desc_u[s], uy = b.desc_u[g.ns + s], RT = b.desc_rt[s];
         int R = rn & 0xffff, Nr = rn >> 16;
@@ -1536,7 +1648,10 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b, i
     __shared__ int s_err, s_ref;
     if (threadIdx.x == 0) s_err = b.flags->err;
     __syncthreads();
-    if (s_err) return;
+    if (s_err) {
+        if (threadIdx.x == 0) b.gpart[blockIdx.x] = 0ull;
+        return;
+    }
     const int t = blockIdx.x;
     const int tx0 = (t % g.dtx) * g.tx, ty0 = (t / g.dtx) * g.ty;
     const int lx = threadIdx.x % g.tx, ly = threadIdx.x / g.tx;
@@ -1738,9 +1853,13 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b, i
 #pragma unroll
         for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = (T)acc[k];
     }
+    // arrivals of the workgroup as one partial (summed by k_sum_partials)
+    __shared__ unsigned long long s_hits[4];
     unsigned long long hl = (unsigned long long)hits;
     for (int off = 32; off > 0; off >>= 1) hl += __shfl_xor(hl, off);
-    if ((threadIdx.x & 63) == 0 && hl) atomicAdd(&b.stats->arrivals, hl);
+    if ((threadIdx.x & 63) == 0) s_hits[threadIdx.x >> 6] = hl;
+    __syncthreads();
+    if (threadIdx.x == 0) b.gpart[blockIdx.x] = s_hits[0] + s_hits[1] + s_hits[2] + s_hits[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -1804,6 +1923,46 @@ __global__ void k_reset_stats(DevStats *st) {
         st->rt_min_bits = (unsigned long long)__double_as_longlong(1e300);
         st->kn_max_bits = 0;
         st->colat_max_bits = 0;
+    }
+}
+
+// Sums the per-workgroup partials of k_epr into the step statistics: each
+// workgroup folds a strided share, then adds it with one atomic per field.
+__global__ void __launch_bounds__(256) k_stats_reduce(const DevStats *part, int n, DevStats *st) {
+    __shared__ DevStats s_w[4];
+    StatSum a;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        StatSum p;
+        p.load(part[i]);
+        a.add(p);
+    }
+    a.wave_reduce();
+    if ((threadIdx.x & 63) == 0) a.store(s_w[threadIdx.x >> 6]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        StatSum t;
+        for (int w = 0; w < 4; w++) {
+            StatSum o;
+            o.load(s_w[w]);
+            t.add(o);
+        }
+        t.atomics_into(st);
+    }
+}
+
+// Adds n per-workgroup counts to *out: a strided share per workgroup, one
+// atomic per workgroup.
+__global__ void __launch_bounds__(256) k_sum_partials(const unsigned long long *part, int n,
+                                                      unsigned long long *out) {
+    __shared__ unsigned long long s_w[4];
+    unsigned long long a = 0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) a += part[i];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        if (t) atomicAdd(out, t);
     }
 }
 
@@ -1970,6 +2129,9 @@ hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom,
                       hipStream_t s) {
     if (mixed) epr_launch<float>(g, ph, mom, b, step, 0, s);
     else epr_launch<double>(g, ph, mom, b, step, 0, s);
+    const int nt = g.ntx * g.nty;
+    const int nb = (nt + 255) / 256 < 256 ? (nt + 255) / 256 : 256;
+    hipLaunchKernelGGL(k_stats_reduce, dim3(nb), dim3(256), 0, s, (const DevStats *)b.bpart, nt, b.stats);
     return hipGetLastError();
 }
 
@@ -1998,6 +2160,10 @@ hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, in
         if (g.dim == 1) gather_launch<double, 1>(g, mom_out, b, gcap, s);
         else gather_launch<double, 2>(g, mom_out, b, gcap, s);
     }
+    const int nd = g.dtx * g.dty;
+    const int nb = (nd + 255) / 256 < 256 ? (nd + 255) / 256 : 256;
+    hipLaunchKernelGGL(k_sum_partials, dim3(nb), dim3(256), 0, s, (const unsigned long long *)b.gpart, nd,
+                       &b.stats->arrivals);
     return hipGetLastError();
 }
 

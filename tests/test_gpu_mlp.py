@@ -156,3 +156,24 @@ def test_linearised_guess_matches_plain_path(prec):
     print("rel_linf", err, "passes plain", pa, "linearised", pb, "fallbacks", sb["fallbacks"])
     assert err < (1e-10 if prec == 0 else 1e-5)
     assert pb <= pa
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_previous_step_guess_matches_plain_path(prec):
+    """Newton started from the linearised guess plus each cell's correction
+    from the previous step converges to the same fields in fewer passes; the
+    first step (no stored correction) is the linearised path itself."""
+    _case("previous-step guess quadrants 96x96 precision %d" % prec)
+    import paper_2508_06911_amd as lb
+    cfg, prim = li.quadrants(7, n=96)
+    a, sa = run_gpu(cfg, prim, 30, precision=prec)
+    b, sb = run_gpu(cfg, prim, 30, precision=prec, guess=lb.GUESS_PREV)
+    err = rel_linf(b, a)
+    pa = sa["point_passes"] / sa["q_mean"] / sa["cells"]
+    pb = sb["point_passes"] / sb["q_mean"] / sb["cells"]
+    print("rel_linf", err, "passes plain", pa, "previous-step", pb, "fallbacks", sb["fallbacks"])
+    assert err < (1e-10 if prec == 0 else 1e-5)
+    assert pb < pa
+    c1, _ = run_gpu(cfg, prim, 1, precision=prec, guess=lb.GUESS_PREV)
+    l1, _ = run_gpu(cfg, prim, 1, precision=prec, guess=lb.GUESS_LIN)
+    assert np.array_equal(c1, l1)
