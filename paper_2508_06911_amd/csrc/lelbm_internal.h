@@ -98,7 +98,8 @@ struct Buffers {
     double *desc_rho;        // [ns]
     double *desc_rt;         // [ns]
     int *desc_rn;            // [ns]  R | (N_r << 16), -1 = no emission
-    unsigned short *spans;   // [ns][SPAN_ROWS] stencil row spans (see k_epr)
+    unsigned short *spans;   // [SPAN_ROWS][ns] stencil row spans, row-major so a wavefront reads one row
+                             // of 64 cells in one line (see k_epr)
     TileInfo *tiles;         // [ntx*nty]
     DWin *dwin;              // [dtx*dty]
     void *scratch;           // population scratch

@@ -1074,13 +1074,13 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         const int xlo = ubx - R - 1, xhi = ubx + R + 1;
         // stencil row spans, computed once and reused by every pass
         const bool tab = D == 1 ? 2 * R + 2 <= 255 : 2 * R + 3 <= SPAN_ROWS;
-        unsigned short *spt = b.spans + s * SPAN_ROWS;
+        unsigned short *spt = b.spans + s;   // row k of the cell at spt[k * ns]
         if (tab) {
             for (int cy = ylo; cy <= yhi; cy++) {
                 int xa, xb;
                 unsigned short v = 0x00ff;
                 if (row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb)) v = (unsigned short)((xa - xlo) | ((xb - xlo) << 8));
-                spt[cy - ylo] = v;
+                spt[(long long)(cy - ylo) * g.ns] = v;
             }
         }
         // Row cy's span from the table entry v (loaded one row ahead, so the
@@ -1139,7 +1139,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                 W f = 0, r = 0, s2 = 0, gv = 0, rg = 0;
                 if (D == 2) { f = col.F; r = col.R; s2 = col.S; gv = col.G; rg = col.Q; col.next(); }
                 const unsigned cur = nxt;
-                if (tab && cy < yhi) nxt = spt[cy + 1 - ylo];
+                if (tab && cy < yhi) nxt = spt[(long long)(cy + 1 - ylo) * g.ns];
                 int xa, xb;
                 if (!span(cur, cy, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
@@ -1244,7 +1244,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                 W f = 0, r = 0, s2 = 0, gv = 0, rg = 0;
                 if (D == 2) { f = col.F; r = col.R; s2 = col.S; gv = col.G; rg = col.Q; col.next(); }
                 const unsigned cur = nxt;
-                if (tab && cy < yhi) nxt = spt[cy + 1 - ylo];
+                if (tab && cy < yhi) nxt = spt[(long long)(cy + 1 - ylo) * g.ns];
                 int xa, xb;
                 if (!span(cur, cy, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
