@@ -13,8 +13,10 @@ Protocol:
   3. run the 2048 x 2048 input from the same initial state with
        fp64-eq   plain FP64 path, equilibrium (IID13) Newton guess,
        mixed-mlp FP32 state/records/streaming + learned Newton guess,
-     (and the two other combinations, for attribution), W untimed warmup
-     steps then K timed steps each, inputs resident in HBM;
+     and, for attribution, the other combinations of {fp64, mixed} with
+     {eq, mlp, lin (closed-form linearised guess), prev (linearised guess
+     plus the previous step's correction)}, W untimed warmup steps then K
+     timed steps each, inputs resident in HBM;
   4. L1 errors of density, velocity and temperature of every run against the
      fp64-eq run after the same steps.
 
@@ -22,7 +24,10 @@ Prints ONE JSON line: ``value`` = MLUPS of the mixed-mlp run; the FP64 MLUPS,
 the errors, Newton iterations, per-kernel times (HIP events on the library's
 stream), the roofline of the dominant kernel (the per-cell reconstruction
 kernel), the gather's HBM fraction and the CPU oracle's MLUPS on a bounded
-sample of the same workload.
+sample of the same workload.  Context runs (unless --no-context): the
+paper's hot box at RT 0.5 and 2 (4096 x 4096), the 4096 x 2048 channel and
+the 8192 x 4096 Mach-10 channel (unless --no-c4), FP64 and FP32 from one
+developed state with per-field L1 errors.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S] [--n 2048]
                        [--runs fp64-eq,mixed-mlp,...] [--no-cpu] [--no-context]
@@ -47,11 +52,27 @@ HBM_PEAK_GBS = 8000.0
 # non-packed FP32 run at the same rate; packed FP32 math is disabled in this
 # build, so the same figure bounds both paths.
 VALU_PEAK_TFLOPS = 78.6
-# Algorithmic FP64 work of one stencil point in one reconstruction pass (2D):
-# 27 monomial products (degree <= 6), 16 multiply-adds for the two exponents,
-# 43 multiply-adds into the fluon (28) and phonon (15) moment sums, and two
-# exponentials counted as 20 flops each (a degree-10 polynomial).
-FLOPS_PER_POINT_PASS_2D = 27 + 2 * 16 + 2 * 43 + 2 * 20
+# Algorithmic FP64 work of the reconstruction of one cell (2D), the method's
+# cost model: q [I (2E + 80) + (2E + 20)] + 400 I, with q the stencil size,
+# I the Newton evaluations (passes minus the final record pass), E = 20 flops
+# for one exponential evaluated in software, 80 flops of monomial products and
+# moment-sum updates per point and evaluation, 20 for the point's final moment
+# fractions, 400 for the two Hessian factorisations and solves per evaluation.
+EXP_FLOPS = 20
+
+
+def epr_flops_per_step(st, steps):
+    """Algorithmic flops of k_epr per step from the step statistics (sums
+    over cells and steps): point_passes = sum q * passes, q_mean * cells =
+    sum q; cells with refined stencils (k_epr_ref) are left out of the point
+    terms."""
+    pp = st["point_passes"] - st["point_passes_refined"]
+    q = st["q_mean"] * st["cells"]
+    evals_pts = max(pp - q, 0.0)                         # sum over cells of q * I
+    evals = max(pp / max(st["q_mean"], 1e-30) - st["cells"], 0.0)   # ~ sum of I
+    return ((2 * EXP_FLOPS + 80) * evals_pts + (2 * EXP_FLOPS + 20) * q + 400 * evals) / steps
+
+
 # Algorithmic bytes of the gather: per arriving stencil point the (w_f, w_g)
 # pair, per destination the written moments, per source its descriptor
 # (velocity, density, temperature, radius: 20 bytes).
@@ -232,7 +253,7 @@ def timed_run(name, a, lb, torch, cfg, mom0, mlp):
     gat_ms = kt["gather"][0] / max(kt["gather"][1], 1)
     # k_epr handles the cells with unrefined stencils; refined cells go to
     # k_epr_ref (timed apart)
-    flops = (st["point_passes"] - st["point_passes_refined"]) / a.steps * FLOPS_PER_POINT_PASS_2D
+    flops = epr_flops_per_step(st, a.steps)
     esz = 8 if prec == lb.FP64 else 4
     gbytes = (st["arrivals"] / a.steps * GATHER_PAIR_BYTES[prec_name]
               + ncell * (11 * esz + GATHER_DESC_BYTES))
