@@ -177,7 +177,8 @@ int lelbm_last_failure_detail(const lelbm_ctx *c, int *reason, int *species, dou
  * kernel and lelbm_kernel_times returns accumulated milliseconds and launch
  * counts for: [0] pad fill, [1] stencil pre-pass, [2] tile scan,
  * [3] collision + reconstruction of cells with unrefined stencils,
- * [4] moment-streaming gather, [5] unused, [6] learned Newton guess,
+ * [4] moment-streaming gather, [5] unused, [6] unused (the learned guess runs inside the
+ * reconstruction kernel [3]),
  * [7] collision + reconstruction of cells with refined stencils.
  * n is the capacity of ms and launches (at most LELBM_NTIMERS are filled). */
 #define LELBM_NTIMERS 8

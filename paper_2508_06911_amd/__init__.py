@@ -233,7 +233,7 @@ class Lelbm:
         ms = (ctypes.c_double * 8)()
         ln = (ctypes.c_long * 8)()
         _check(lib().lelbm_kernel_times(self._h, ms, ln, 8))
-        names = ["fill_pads", "prepare", "scan", "epr", "gather", "unused", "guess", "epr_ref"]
+        names = ["fill_pads", "prepare", "scan", "epr", "gather", "unused5", "unused6", "epr_ref"]
         return {n: (ms[i], ln[i]) for i, n in enumerate(names)}
 
     def memory(self):

@@ -188,7 +188,7 @@ static void free_ctx(lelbm_ctx *c) {
     if (!c) return;
     Buffers &b = c->b;
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.spans, b.tiles,
-                    b.dwin, b.scratch, b.flags, b.stats, b.partial, b.guess, b.harvest_n,
+                    b.dwin, b.scratch, b.flags, b.stats, b.partial, b.harvest_n,
                     c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, b.lamprev,
                     b.bpart, b.gpart};
     for (void *q : ptrs)
@@ -369,7 +369,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ok = ok && hipMalloc((void **)&b.desc_rho, (size_t)ns * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.desc_rt, (size_t)ns * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.desc_rn, (size_t)ns * sizeof(int)) == hipSuccess;
-    ok = ok && hipMalloc((void **)&b.spans, (size_t)ns * SPAN_ROWS * sizeof(unsigned short)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.spans, (size_t)nt * TILE_N * SPAN_ROWS * sizeof(unsigned short)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.tiles, (size_t)nt * sizeof(TileInfo)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.dwin, (size_t)nd * sizeof(DWin)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.flags, sizeof(Flags)) == hipSuccess;
@@ -384,7 +384,6 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
         ok = ok && hipMemset(b.lamprev, 0xff, (size_t)16 * ns * sizeof(double)) == hipSuccess;
     }
     if (p->guess == LELBM_GUESS_MLP) {
-        ok = ok && hipMalloc((void **)&b.guess, (size_t)16 * ns * sizeof(double)) == hipSuccess;
         ok = ok && hipMalloc((void **)&c->mlp_w, MLP_NPARAM * sizeof(unsigned short)) == hipSuccess;
         ok = ok && hipMalloc((void **)&c->mlp_p, MLP_NPARAM * sizeof(float)) == hipSuccess;
         ok = ok && hipMalloc((void **)&c->mlp_n, MLP_NORM * sizeof(float)) == hipSuccess;
@@ -542,9 +541,6 @@ static hipError_t do_prepare(lelbm_ctx *c, void *a) {
     return launch_prepare(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
 }
 static hipError_t do_scan(lelbm_ctx *c, void *a) { return launch_scan(c->g, c->b, ((StepArg *)a)->step, c->stream); }
-static hipError_t do_guess(lelbm_ctx *c, void *) {
-    return launch_mlp_guess(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, c->stream);
-}
 static hipError_t do_epr(lelbm_ctx *c, void *a) {
     return launch_epr(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
 }
@@ -573,7 +569,6 @@ extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
             if ((r = timed(c, 0, do_fill, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 1, do_prepare, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 2, do_scan, &a)) != LELBM_OK) return r;
-            if (c->b.guess && (r = timed(c, 6, do_guess, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 3, do_epr, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 7, do_epr_ref, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 4, do_gather, &a)) != LELBM_OK) return r;

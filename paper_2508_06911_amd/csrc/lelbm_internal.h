@@ -98,8 +98,8 @@ struct Buffers {
     double *desc_rho;        // [ns]
     double *desc_rt;         // [ns]
     int *desc_rn;            // [ns]  R | (N_r << 16), -1 = no emission
-    unsigned short *spans;   // [SPAN_ROWS][ns] stencil row spans, row-major so a wavefront reads one row
-                             // of 64 cells in one line (see k_epr)
+    unsigned short *spans;   // [SPAN_ROWS][tiles * 256] stencil row spans by source tile and cell of the
+                             // tile, so a wavefront reads one row of its 64 cells in one line (k_epr)
     TileInfo *tiles;         // [ntx*nty]
     DWin *dwin;              // [dtx*dty]
     void *scratch;           // population scratch
@@ -111,7 +111,6 @@ struct Buffers {
     const unsigned short *mlp_w;   // BF16 weights (canonical order), NULL = none
     const float *mlp_p;            // FP32 parameters (biases read from here)
     const float *mlp_n;            // standardisation constants (64)
-    double *guess;                 // [16][ns] initial multipliers, NULL = Eq. (IID13)
     DevStats *bpart;               // [ntx*nty] per-workgroup statistics of k_epr
     unsigned long long *gpart;     // [dtx*dty] per-workgroup arrival counts of k_gather
     double *lamprev;               // [16][ns] scaled correction beyond the linearised guess, last step
@@ -148,7 +147,6 @@ hipError_t launch_load_interior(const Geom &g, int nmom, const void *src, int sr
                                 hipStream_t s);
 hipError_t launch_store_interior(const Geom &g, int nmom, const void *src, int src_fp32, double *dst, hipStream_t s);
 int num_sum_blocks(const Geom &g);
-hipError_t launch_mlp_guess(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, hipStream_t s);
 hipError_t launch_mlp_fwdbwd(const unsigned short *Wb, const float *bias, const float *nm, const float *pairs,
                              long long n, long long nsamp, int draw, unsigned long long seed, unsigned long long step,
                              float *partial, float *lossp, hipStream_t s);

@@ -920,6 +920,40 @@ __device__ inline bool row_span(int cy, double ux, double uy, double rr, int lo,
     return a <= b;
 }
 
+// Learned guess inside the reconstruction kernel: every cell of a wavefront
+// computes its 16 features, the 16 -> 64 -> 64 -> 16 network runs once per
+// wavefront on MFMA (BF16 operands, FP32 accumulation), and each cell gets its
+// destandardised output: the scaled correction beyond the linearised guess
+// (the harvest target), from the cell's collision targets mf, mg.  xs_all and
+// ys_all are LDS scratch of 2 KB and 4 KB per wavefront; every thread of the
+// workgroup calls this (barriers).
+__device__ inline void mlp_guess_cells(const Buffers &b, const double *mf, const double *mg, double ux, double uy,
+                                       double RT, int R, bool active, unsigned short *xs_all, float *ys_all,
+                                       float *out) {
+    const int l = threadIdx.x, wv = l >> 6, lane = l & 63;
+    unsigned short *xs = xs_all + wv * 64 * MLP_IN;
+    float *ys = ys_all + wv * 64 * MLP_OUT;
+    float x[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) x[k] = 0.f;
+    if (active) mlp_features(mf, mg, ux, uy, RT, R, x);
+#pragma unroll
+    for (int k = 0; k < 16; k++) xs[lane * MLP_IN + k] = f2bf(norm_in(b.mlp_n, k, x[k]));
+    __syncthreads();
+    bf16x4 h1[4][4], h2[4][4];
+    f32x4 y[4];
+    mlp_forward_wave(b.mlp_w, b.mlp_p, xs, h1, h2, y, lane);
+    const int r4 = 4 * (lane >> 4), c = lane & 15;
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) ys[(16 * nt + c) * MLP_OUT + r4 + i] = y[nt][i];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) out[k] = denorm_out(b.mlp_n, k, ys[lane * MLP_OUT + k]);
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Reconstruction of cells without stencil refinement (N_r = 0).
 //
@@ -1064,9 +1098,22 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
     int rn = valid ? b.desc_rn[s] : -1;
     CellStats cs;
     cs.active = rn >= 0 && (rn >> 16) == 0;
+    double rho = 0.0, ux = 0.0, uy = 0.0, RT = 1.0;
+    double mf[NF], mg[NG];
+    if (cs.active) {
+        rho = b.desc_rho[s]; ux = b.desc_u[s]; uy = b.desc_u[g.ns + s]; RT = b.desc_rt[s];
+        collide_targets<T, D>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, cs.kn, cs.lim);
+    }
+    // learned guess: the network's correction, computed before the Newton
+    // state takes over the LDS arrays it borrows
+    float ynet[16];
+    if constexpr (D == 2) {
+        if (b.mlp_w)
+            mlp_guess_cells(b, mf, mg, ux, uy, RT, rn & 0xffff, cs.active, (unsigned short *)s_delg, (float *)s_delf,
+                            ynet);
+    }
     if (cs.active) {
         const TileInfo ti = b.tiles[t];
-        double rho = b.desc_rho[s], ux = b.desc_u[s], uy = b.desc_u[g.ns + s], RT = b.desc_rt[s];
         const int R = rn & 0xffff;
         const double rr = R + 0.5;
         const int ubx = (int)floor(ux + 0.5), uby = D == 2 ? (int)floor(uy + 0.5) : 0;
@@ -1074,13 +1121,16 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         const int xlo = ubx - R - 1, xhi = ubx + R + 1;
         // stencil row spans, computed once and reused by every pass
         const bool tab = D == 1 ? 2 * R + 2 <= 255 : 2 * R + 3 <= SPAN_ROWS;
-        unsigned short *spt = b.spans + s;   // row k of the cell at spt[k * ns]
+        // row k of the cell at spt[k * SW]: a row of a tile's 256 cells is
+        // contiguous, so a wavefront reads one 128-byte line per row
+        const long long SW = (long long)g.ntx * g.nty * TILE_N;
+        unsigned short *spt = b.spans + (long long)t * TILE_N + l;
         if (tab) {
             for (int cy = ylo; cy <= yhi; cy++) {
                 int xa, xb;
                 unsigned short v = 0x00ff;
                 if (row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb)) v = (unsigned short)((xa - xlo) | ((xb - xlo) << 8));
-                spt[(long long)(cy - ylo) * g.ns] = v;
+                spt[(long long)(cy - ylo) * SW] = v;
             }
         }
         // Row cy's span from the table entry v (loaded one row ahead, so the
@@ -1094,8 +1144,6 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
             }
             return row_span<D>(cy, ux, uy, rr, xlo, xhi, xa, xb);
         };
-        double mf[NF], mg[NG];
-        collide_targets<T, D>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, cs.kn, cs.lim);
         Species<NF, LdsStore<NF>> sf;
         Species<NG, LdsStore<NG>> sg;
         sf.v.lam_ = s_lamf + l; sf.v.del_ = s_delf + l;
@@ -1103,13 +1151,19 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         species_init<D, NF, NG>(sf, sg, RT);
         if (ph.lin_guess) species_linear<D>(sf, sg, mf, mg, RT);
         if (ph.prev_guess) species_prev<D>(sf, sg, mf, mg, RT, b.lamprev, g.ns, s);
-        if (D == 2 && b.guess) {
-            // learned guess (scaled multipliers, see k_mlp_guess)
+        if (D == 2 && b.mlp_w) {
+            // learned guess: the linearised guess plus the network's scaled correction
+            // (mlp_guess_cells)
+            species_linear<D>(sf, sg, mf, mg, RT);
+            const double sq = sqrt(RT);
 #pragma unroll
-            for (int j = 0; j < NF; j++) sf.v.lam(j) = b.guess[(long long)j * g.ns + s];
-#pragma unroll
-            for (int j = 0; j < NG; j++) sg.v.lam(j) = b.guess[(long long)(NF + j) * g.ns + s];
-            sf.mlp = sg.mlp = 1;
+            for (int j = 0; j < NF + NG; j++) {
+                const int jj = j < NF ? j : j - NF;
+                const int k = order_of<D>(jj);
+                const double scl = k == 0 ? 1.0 : (k == 1 ? sq : (k == 2 ? RT : RT * sq));
+                if (j < NF) sf.v.lam(jj) += (double)ynet[j] / scl;
+                else sg.v.lam(jj) += (double)ynet[j] / scl;
+            }
         }
         // residual scales RT^(-k/2) of basis order k (scale-free stopping test)
         const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
@@ -1139,7 +1193,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                 W f = 0, r = 0, s2 = 0, gv = 0, rg = 0;
                 if (D == 2) { f = col.F; r = col.R; s2 = col.S; gv = col.G; rg = col.Q; col.next(); }
                 const unsigned cur = nxt;
-                if (tab && cy < yhi) nxt = spt[(long long)(cy + 1 - ylo) * g.ns];
+                if (tab && cy < yhi) nxt = spt[(long long)(cy + 1 - ylo) * SW];
                 int xa, xb;
                 if (!span(cur, cy, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
@@ -1244,7 +1298,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                 W f = 0, r = 0, s2 = 0, gv = 0, rg = 0;
                 if (D == 2) { f = col.F; r = col.R; s2 = col.S; gv = col.G; rg = col.Q; col.next(); }
                 const unsigned cur = nxt;
-                if (tab && cy < yhi) nxt = spt[(long long)(cy + 1 - ylo) * g.ns];
+                if (tab && cy < yhi) nxt = spt[(long long)(cy + 1 - ylo) * SW];
                 int xa, xb;
                 if (!span(cur, cy, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
@@ -1436,69 +1490,6 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
 // turned back into multipliers and stored for k_epr.  Refined cells keep
 // Eq. (IID13) in k_epr_ref.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) k_mlp_guess(Geom g, Phys ph, const T *mom, Buffers b) {
-    __shared__ unsigned short xs[4][64 * MLP_IN];
-    __shared__ float ys[4][64 * MLP_OUT];
-    __shared__ int s_err;
-    if (threadIdx.x == 0) s_err = b.flags->err;
-    __syncthreads();
-    if (s_err) return;
-    const int t = blockIdx.x;
-    const int tx0 = (t % g.ntx) * g.tx, ty0 = (t / g.ntx) * g.ty;
-    const int l = threadIdx.x, wv = l >> 6, lane = l & 63;
-    const int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
-    const bool valid = px < g.sxn && py < g.syn;
-    const long long s = (long long)py * g.sxn + px;
-    const int rn = valid ? b.desc_rn[s] : -1;
-    const bool active = rn >= 0 && (rn >> 16) == 0;
-    double RT = 1.0;
-    double dl[16];
-#pragma unroll
-    for (int k = 0; k < 16; k++) dl[k] = 0.0;
-    float x[16];
-#pragma unroll
-    for (int k = 0; k < 16; k++) x[k] = 0.f;
-    if (active) {
-        double rho = b.desc_rho[s], ux = b.desc_u[s], uy = b.desc_u[g.ns + s];
-        RT = b.desc_rt[s];
-        double mf[10], mg[6], kn;
-        int lim;
-        collide_targets<T, 2>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, kn, lim);
-        mlp_features(mf, mg, ux, uy, RT, rn & 0xffff, x);
-        lin_guess_scaled<2>(mf, mg, RT, dl);
-    }
-#pragma unroll
-    for (int k = 0; k < 16; k++) xs[wv][lane * MLP_IN + k] = f2bf(norm_in(b.mlp_n, k, x[k]));
-    __syncthreads();
-    bf16x4 h1[4][4], h2[4][4];
-    f32x4 y[4];
-    mlp_forward_wave(b.mlp_w, b.mlp_p, xs[wv], h1, h2, y, lane);
-    const int r4 = 4 * (lane >> 4), c = lane & 15;
-#pragma unroll
-    for (int nt = 0; nt < 4; nt++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) ys[wv][(16 * nt + c) * MLP_OUT + r4 + i] = y[nt][i];
-    __syncthreads();
-    if (!active) return;
-    const double sq = sqrt(RT);
-#pragma unroll
-    for (int j = 0; j < 16; j++) {
-        const int jj = j < 10 ? j : j - 10;
-        const int k = basis_order2(jj);
-        const double scl = k == 0 ? 1.0 : (k == 1 ? sq : (k == 2 ? RT : RT * sq));
-        const double yj = (double)denorm_out(b.mlp_n, j, ys[wv][lane * MLP_OUT + j]);
-        b.guess[(long long)j * g.ns + s] = (yj + iid13_scaled(jj, RT) + dl[j]) / scl;
-    }
-}
-
-hipError_t launch_mlp_guess(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, hipStream_t s) {
-    unsigned nt = (unsigned)(g.ntx * g.nty);
-    if (mixed) hipLaunchKernelGGL((k_mlp_guess<float>), dim3(nt), dim3(256), 0, s, g, ph, (const float *)mom, b);
-    else hipLaunchKernelGGL((k_mlp_guess<double>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b);
-    return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // moment-streaming gather, Eq. (IIE3b)
 //
@@ -1514,7 +1505,7 @@ hipError_t launch_mlp_guess(const Geom &g, const Phys &ph, int mixed, const void
 // so the row accumulates sum w_f c_x^k (k <= 3) and sum w_g c_x^k (k <= 1)
 // and the eleven moments are formed once per row.
 // ---------------------------------------------------------------------------
-constexpr int GU = 8;         // candidates per batch in the gather
+constexpr int GU = 4;         // candidates per batch in the gather
 
 struct Resolved {
     long long s;    // padded source index, -1 if none
