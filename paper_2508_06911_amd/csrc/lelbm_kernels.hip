@@ -924,34 +924,44 @@ __device__ inline bool row_span(int cy, double ux, double uy, double rr, int lo,
 // computes its 16 features, the 16 -> 64 -> 64 -> 16 network runs once per
 // wavefront on MFMA (BF16 operands, FP32 accumulation), and each cell gets its
 // destandardised output: the scaled correction beyond the linearised guess
-// (the harvest target), from the cell's collision targets mf, mg.  xs_all and
-// ys_all are LDS scratch of 2 KB and 4 KB per wavefront; every thread of the
-// workgroup calls this (barriers).
+// (the harvest target), from the cell's collision targets mf, mg.  The inputs
+// (2 KB) and outputs (4 KB) of a wavefront are staged in the wavefront's own
+// columns of the LDS direction arrays (dg: 6 x 64 doubles, df: 10 x 64, for
+// NG = 6, NF = 10), which its cells' Newton state uses only afterwards, so a
+// wavefront never waits for the others.
 __device__ inline void mlp_guess_cells(const Buffers &b, const double *mf, const double *mg, double ux, double uy,
-                                       double RT, int R, bool active, unsigned short *xs_all, float *ys_all,
-                                       float *out) {
-    const int l = threadIdx.x, wv = l >> 6, lane = l & 63;
-    unsigned short *xs = xs_all + wv * 64 * MLP_IN;
-    float *ys = ys_all + wv * 64 * MLP_OUT;
+                                       double RT, int R, bool active, double *dg, double *df, float *out) {
+    const int l = threadIdx.x, w64 = l & ~63, lane = l & 63;
+    // sample r's inputs: chunk r / 16 of the wavefront's phonon-direction
+    // columns (16 samples of 16 BF16 per 64-double chunk); outputs: chunk r / 8
+    // of its fluon-direction columns (8 samples of 16 floats per chunk)
+    auto xrow = [&](int r) { return (unsigned short *)(dg + (r >> 4) * TILE_N + w64) + (r & 15) * MLP_IN; };
+    auto yrow = [&](int r) { return (float *)(df + (r >> 3) * TILE_N + w64) + (r & 7) * MLP_OUT; };
     float x[16];
 #pragma unroll
     for (int k = 0; k < 16; k++) x[k] = 0.f;
     if (active) mlp_features(mf, mg, ux, uy, RT, R, x);
+    unsigned short *xr = xrow(lane);
 #pragma unroll
-    for (int k = 0; k < 16; k++) xs[lane * MLP_IN + k] = f2bf(norm_in(b.mlp_n, k, x[k]));
-    __syncthreads();
+    for (int k = 0; k < 16; k++) xr[k] = f2bf(norm_in(b.mlp_n, k, x[k]));
+    // LDS operations of one wavefront complete in order: the reads of other
+    // lanes' rows below see these writes; the barrier keeps the compiler from
+    // reordering them
+    __builtin_amdgcn_wave_barrier();
     bf16x4 h1[4][4], h2[4][4];
     f32x4 y[4];
-    mlp_forward_wave(b.mlp_w, b.mlp_p, xs, h1, h2, y, lane);
+    mlp_forward_wave_rows(b.mlp_w, b.mlp_p, [&](int r) { return (const unsigned short *)xrow(r); }, h1, h2, y,
+                          lane);
     const int r4 = 4 * (lane >> 4), c = lane & 15;
 #pragma unroll
     for (int nt = 0; nt < 4; nt++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) ys[(16 * nt + c) * MLP_OUT + r4 + i] = y[nt][i];
-    __syncthreads();
+        for (int i = 0; i < 4; i++) yrow(16 * nt + c)[r4 + i] = y[nt][i];
+    __builtin_amdgcn_wave_barrier();
+    const float *yr = yrow(lane);
 #pragma unroll
-    for (int k = 0; k < 16; k++) out[k] = denorm_out(b.mlp_n, k, ys[lane * MLP_OUT + k]);
-    __syncthreads();
+    for (int k = 0; k < 16; k++) out[k] = denorm_out(b.mlp_n, k, yr[k]);
+    __builtin_amdgcn_wave_barrier();
 }
 
 // ---------------------------------------------------------------------------
@@ -1109,8 +1119,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
     float ynet[16];
     if constexpr (D == 2) {
         if (b.mlp_w)
-            mlp_guess_cells(b, mf, mg, ux, uy, RT, rn & 0xffff, cs.active, (unsigned short *)s_delg, (float *)s_delf,
-                            ynet);
+            mlp_guess_cells(b, mf, mg, ux, uy, RT, rn & 0xffff, cs.active, s_delg, s_delf, ynet);
     }
     if (cs.active) {
         const TileInfo ti = b.tiles[t];

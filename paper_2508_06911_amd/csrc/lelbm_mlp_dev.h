@@ -55,15 +55,17 @@ __device__ inline bf16x4 frag_w(const unsigned short *W, int nout, int mt, int k
 // Outputs the BF16 hidden activations (B-operand layout, kept for the
 // backward pass) and the FP32 outputs y[nt] (lane: outputs 4(l/16)..+3 of
 // sample 16nt+l%16).
-__device__ inline void mlp_forward_wave(const unsigned short *Wb, const float *bias, const unsigned short *xs,
-                                        bf16x4 (&h1)[4][4], bf16x4 (&h2)[4][4], f32x4 (&y)[4], int lane) {
+// xrow(r) points to the MLP_IN BF16 inputs of sample r.
+template <class XRow>
+__device__ inline void mlp_forward_wave_rows(const unsigned short *Wb, const float *bias, XRow xrow,
+                                             bf16x4 (&h1)[4][4], bf16x4 (&h2)[4][4], f32x4 (&y)[4], int lane) {
     const unsigned short *W1 = Wb + MLP_OFF_W1, *W2 = Wb + MLP_OFF_W2, *W3 = Wb + MLP_OFF_W3;
     const float *b1 = bias + MLP_OFF_B1, *b2 = bias + MLP_OFF_B2, *b3 = bias + MLP_OFF_B3;
     const int r4 = 4 * (lane >> 4);
     bf16x4 xb[4];
 #pragma unroll
     for (int nt = 0; nt < 4; nt++) {
-        const unsigned short *p = xs + (16 * nt + (lane & 15)) * MLP_IN + r4;
+        const unsigned short *p = xrow(16 * nt + (lane & 15)) + r4;
 #pragma unroll
         for (int i = 0; i < 4; i++) xb[nt][i] = (short)p[i];
     }
@@ -111,6 +113,12 @@ __device__ inline void mlp_forward_wave(const unsigned short *Wb, const float *b
     for (int nt = 0; nt < 4; nt++)
 #pragma unroll
         for (int i = 0; i < 4; i++) y[nt][i] += b3[r4 + i];
+}
+
+// Inputs of the 64 samples contiguous in xs ([64][MLP_IN]).
+__device__ inline void mlp_forward_wave(const unsigned short *Wb, const float *bias, const unsigned short *xs,
+                                        bf16x4 (&h1)[4][4], bf16x4 (&h2)[4][4], f32x4 (&y)[4], int lane) {
+    mlp_forward_wave_rows(Wb, bias, [&](int r) { return xs + r * MLP_IN; }, h1, h2, y, lane);
 }
 
 // Standardisation constants of the network (64 floats): input means and
