@@ -61,9 +61,12 @@ enum {
 enum { LELBM_BC_PERIODIC = 0, LELBM_BC_OUTFLOW = 1, LELBM_BC_INFLOW = 2, LELBM_BC_SLIPWALL = 3 };
 
 /* LELBM_FP64: every stage in FP64.
- * LELBM_MIXED: stored moments, collision, reconstruction passes and streaming
- * in FP32; the Newton Hessian solve, the log-sum normalisation and the final
- * conserved-moment correction in FP64. */
+ * LELBM_MIXED: stored moments, reconstruction records and the streaming
+ * gather in FP32; collision, per-point reconstruction arithmetic, Hessian
+ * solves and the final conserved-moment correction in FP64.  Newton stops at
+ * a scaled residual of max(newton_tol, 1e-4); the polishing update that
+ * follows squares it (quadratic convergence) to about 1e-8, the rounding level
+ * of the FP32 state. */
 enum { LELBM_FP64 = 0, LELBM_MIXED = 1 };
 
 /* Initial guess of the Newton solve: Eq. (IID13), or the learned network set

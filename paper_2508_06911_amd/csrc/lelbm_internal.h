@@ -22,7 +22,10 @@ constexpr int SPAN_ROWS = 64;
 // staged sources per gather chunk (28 B of LDS each)
 constexpr int GATHER_CAP = 1024;
 constexpr int GATHER_CAP_MAX = 2340;      // 64 KiB of LDS
-constexpr double MIXED_TOL_FLOOR = 1e-8;  // Newton tolerance of the mixed path (records are FP32)
+// Newton stopping tolerance of the mixed path: the polishing update after the
+// stop squares the residual (quadratic convergence), landing near 1e-8, the
+// rounding level of the path's FP32 records and state
+constexpr double MIXED_TOL_FLOOR = 1e-4;
 
 // Warm-start network: 16 inputs, two hidden layers of 64, 16 outputs.
 // Canonical FP32 parameter vector: W1[16][64], b1[64], W2[64][64], b2[64],
