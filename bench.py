@@ -99,7 +99,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-window", type=int, default=512)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-context", action="store_true", help="skip the hot-box and channel context runs")
     ap.add_argument("--channel-seed", type=int, default=0)
     ap.add_argument("--channel-warmup", type=int, default=300)
