@@ -177,3 +177,23 @@ def test_previous_step_guess_matches_plain_path(prec):
     c1, _ = run_gpu(cfg, prim, 1, precision=prec, guess=lb.GUESS_PREV)
     l1, _ = run_gpu(cfg, prim, 1, precision=prec, guess=lb.GUESS_LIN)
     assert np.array_equal(c1, l1)
+
+
+@pytest.mark.parametrize("case", ["refined", "channel"])
+def test_previous_step_guess_with_refinement_pads_and_obstacles(case):
+    """The stored correction survives refined stencils (their cells keep none),
+    pads, slip walls and solid cells: FP64 fields equal to the plain path's."""
+    import paper_2508_06911_amd as lb
+    if case == "refined":
+        _case("previous-step guess, smooth periodic RT~0.3 refined 40x24")
+        cfg, prim = li.smooth_periodic(5, n=40, ny=24, RT=0.3)
+        steps = 20
+    else:
+        _case("previous-step guess, channel Mach 2.5 128x48 with obstacles")
+        cfg, prim = li.channel(0, nx=128, ny=48, size_scale=0.08, pad=24, mach=2.5)
+        steps = 40
+    a, sa = run_gpu(cfg, prim, steps)
+    b, sb = run_gpu(cfg, prim, steps, guess=lb.GUESS_PREV)
+    err = rel_linf(b, a)
+    print("rel_linf", err, "fallbacks", sb["fallbacks"])
+    assert err < 1e-10
