@@ -1328,8 +1328,9 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                     W wf = wsfw * f, wg = wsgw * gv;
                     long long slot = rowslot + cx;
                     if (ti.fmt == 0) {
-                        P[(slot * TILE_N + l) * 2] = wf;
-                        P[(slot * TILE_N + l) * 2 + 1] = wg;
+                        // streaming stores: the records are read once, by the gather
+                        __builtin_nontemporal_store((T)wf, &P[(slot * TILE_N + l) * 2]);
+                        __builtin_nontemporal_store((T)wg, &P[(slot * TILE_N + l) * 2 + 1]);
                     } else {
                         W c1 = (W)cx, c2 = (W)cy;
                         W mo[NM];
