@@ -119,7 +119,8 @@ typedef struct {
 typedef struct {
     double it_mean_f, it_mean_g;
     int it_max_f, it_max_g;
-    long fallbacks;                   /* cells whose learned guess was rejected */
+    long fallbacks;                   /* cells restarted from Eq. (IID13) because their LIN, MLP or PREV
+                                         guess did not lower the residual at the first update */
     long limited;                     /* cells whose frequencies the limiter changed */
     long q_min, q_max;
     double q_mean;
