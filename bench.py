@@ -298,11 +298,12 @@ def hotbox_context(lb, li, torch):
     return out
 
 
-def channel_run(lb, li, torch, cfg, prim, warmup, steps, label):
+def channel_run(lb, li, torch, cfg, prim, warmup, steps, label, mlp=None):
     """A channel configuration started from rest: after a warm-up that lets the
-    bow shocks form, the FP64 path and the FP32 path from the same state, with
-    the relative L1 error of each field of the FP32 path against the FP64 path
-    on fluid cells."""
+    bow shocks form, the FP64 path and the FP32 path (with the learned Newton
+    guess when a network is given) from the same state, with the relative L1
+    error of each field of the FP32 path against the FP64 path on fluid
+    cells."""
     m = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
     ctx = lb.Lelbm(cfg, m, precision=lb.MIXED if label == "c4" else lb.FP64)
     ctx.step_nostats(warmup)
@@ -313,7 +314,10 @@ def channel_run(lb, li, torch, cfg, prim, warmup, steps, label):
     fluid = cfg["solid"].ravel() == 0
     out, moms = {}, {}
     for name, prec in (("fp64", lb.FP64), ("mixed", lb.MIXED)):
-        c = lb.Lelbm(cfg, m0, precision=prec)
+        learned = mlp is not None and prec == lb.MIXED
+        c = lb.Lelbm(cfg, m0, precision=prec, guess=lb.GUESS_MLP if learned else lb.GUESS_EQ)
+        if learned:
+            c.set_mlp(mlp)
         c.step_nostats(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -328,6 +332,7 @@ def channel_run(lb, li, torch, cfg, prim, warmup, steps, label):
                                    "mean_g": round(st["it_mean_g"], 3), "max_g": st["it_max_g"]},
                      "stencil_q": {"mean": round(st["q_mean"], 1), "max": st["q_max"]},
                      "reach_max": round(float(st["colat_max"]), 2),
+                     "guess": "learned" if learned else "equilibrium", "fallbacks": st["fallbacks"],
                      "hbm_bytes": {"persistent": persistent, "scratch": scratch}}
         log("%s %s: %.2f ms/step %.1f MLUPS q_mean %.1f q_max %d" % (label, name, el * 1e3, out[name]["mlups"],
                                                                       st["q_mean"], st["q_max"]))
@@ -348,15 +353,17 @@ def channel_context(lb, li, torch, a):
     return out
 
 
-def c4_context(lb, li, torch, a):
+def c4_context(lb, li, torch, a, mlp):
     """The large hypersonic channel: 8192x4096, Mach 10 inflow, eight seeded
     elliptical obstacles (seed 0), pads of 48 cells (the start from rest
     drives a strong shock whose hot gas needs stencils of radius up to ~20).
     The warm-up runs the FP32 path; the bow shocks of the upstream obstacles
-    form within it.  Reports the HBM footprint: persistent state vs the
-    transient record scratch."""
+    form within it.  The FP32 path then runs with the learned guess (trained
+    on four-quadrant runs; cells it does not help fall back to Eq. IID13).
+    Reports the HBM footprint: persistent state vs the transient record
+    scratch."""
     cfg, prim = li.channel(0, nx=8192, ny=4096, n_obstacles=8, mach=10.0, pad=48)
-    out = channel_run(lb, li, torch, cfg, prim, a.c4_warmup, a.c4_steps, "c4")
+    out = channel_run(lb, li, torch, cfg, prim, a.c4_warmup, a.c4_steps, "c4", mlp)
     out["seed"] = 0
     return out
 
@@ -448,7 +455,7 @@ def main():
         res["paper_context"] = hotbox_context(lb, li, torch)
         res["channel_context"] = channel_context(lb, li, torch, a)
         if not a.no_c4:
-            res["c4_context"] = c4_context(lb, li, torch, a)
+            res["c4_context"] = c4_context(lb, li, torch, a, mlp)
     if mlp is not None:
         mlp.close()
     if not a.no_cpu:
