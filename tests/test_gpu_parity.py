@@ -213,3 +213,22 @@ def test_full_size_quadrants_sampled_windows():
         err = rel_linf(ref.reshape(11, -1), out.reshape(11, -1))
         print("window", cx, cy, "rel_linf", err)
         assert err < TOL
+
+
+def test_step_statistics_match_oracle():
+    """The step statistics (reduced per workgroup on the GPU, then folded) equal
+    the oracle's on the same input: cell and stencil counts exactly, extrema to
+    rounding, Newton iteration counts to within a few cells (a residual at the
+    tolerance may fall either side of it)."""
+    _print_case("statistics quadrants seed 4 72x56 10 steps")
+    cfg, prim = li.quadrants(4, n=72, ny=56)
+    _, sa = run_gpu(cfg, prim, 10)
+    _, sb = run_oracle(cfg, prim, 10)
+    assert sa["cells"] == sb["cells"]
+    assert round(sa["q_mean"] * sa["cells"]) == sb["q_sum"]
+    assert sa["q_min"] == sb["q_min"] and sa["q_max"] == sb["q_max"]
+    assert abs(sa["limited"] - sb["limited"]) <= 2
+    for k in ("rt_min", "kn_max", "colat_max"):
+        assert abs(sa[k] - sb[k]) <= 1e-10 * abs(sb[k]), k
+    assert abs(sa["it_mean_f"] - sb["it_mean_f"]) < 1e-3 and abs(sa["it_mean_g"] - sb["it_mean_g"]) < 1e-3
+    assert abs(sa["it_max_f"] - sb["it_max_f"]) <= 1 and abs(sa["it_max_g"] - sb["it_max_g"]) <= 1
