@@ -93,6 +93,11 @@ struct TileInfo {
 // Per-destination-tile window of displacements to scan in the gather.
 struct DWin {
     int lox, loy, hix, hiy;
+    // bounds of the velocities (in 1/1024 cells, rounded outwards) and the
+    // largest radius of the sources that can reach the tile: the gather
+    // narrows each window row to the displacements such sources can hit
+    // (periodic and open faces only)
+    int uxl, uxh, uyl, uyh, rmax;
 };
 
 struct Buffers {

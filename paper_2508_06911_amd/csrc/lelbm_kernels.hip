@@ -180,7 +180,7 @@ __device__ inline void periodic_or_clip(int r0, int r1, int n, bool periodic, in
 }
 
 __device__ inline void update_windows(const Geom &g, DWin *dwin, int rx0, int rx1, int ry0, int ry1, int lox,
-                                      int loy, int hix, int hiy) {
+                                      int loy, int hix, int hiy, const int *ub) {
     int ax[2], bx[2], ay[2], by[2], cx, cy;
     periodic_or_clip(rx0, rx1, g.nx, g.bc[0] == LELBM_BC_PERIODIC, ax, bx, &cx);
     periodic_or_clip(ry0, ry1, g.ny, g.dim == 2 && g.bc[2] == LELBM_BC_PERIODIC, ay, by, &cy);
@@ -193,12 +193,17 @@ __device__ inline void update_windows(const Geom &g, DWin *dwin, int rx0, int rx
                     atomicMin(&w->loy, loy);
                     atomicMax(&w->hix, hix);
                     atomicMax(&w->hiy, hiy);
+                    atomicMin(&w->uxl, ub[0]);
+                    atomicMax(&w->uxh, ub[1]);
+                    atomicMin(&w->uyl, ub[2]);
+                    atomicMax(&w->uyh, ub[3]);
+                    atomicMax(&w->rmax, ub[4]);
                 }
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, Buffers b, int step) {
-    __shared__ int red[4][256];
+    __shared__ int red[9][256];
     __shared__ int redf[256];
     __shared__ int s_err;
     if (threadIdx.x == 0) s_err = b.flags->err;
@@ -210,6 +215,7 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
     int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
     bool valid = px < g.sxn && py < g.syn;
     int lox = 1 << 29, loy = 1 << 29, hix = -(1 << 29), hiy = -(1 << 29), refined = 0;
+    int uxl = 1 << 29, uxh = -(1 << 29), uyl = 1 << 29, uyh = -(1 << 29), rmx = -1;
     int reach = 0;
     if (valid && b.solid) {
         const int ix = px - g.wl, iy = py - g.wb;
@@ -256,6 +262,9 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
                 loy = D == 2 ? uby - R - 1 : 0; hiy = D == 2 ? uby + R + 1 : 0;
                 refined = Nr > 0;
                 reach = max(abs(ubx), abs(uby)) + R + 1;
+                uxl = (int)floor(ux * 1024.0); uxh = (int)ceil(ux * 1024.0);
+                uyl = D == 2 ? (int)floor(uy * 1024.0) : 0; uyh = D == 2 ? (int)ceil(uy * 1024.0) : 0;
+                rmx = R;
             }
         }
         b.desc_u[s] = ux;
@@ -265,6 +274,7 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
         b.desc_rn[s] = rn;
     }
     red[0][l] = lox; red[1][l] = loy; red[2][l] = hix; red[3][l] = hiy; redf[l] = refined;
+    red[4][l] = uxl; red[5][l] = uxh; red[6][l] = uyl; red[7][l] = uyh; red[8][l] = rmx;
     if (b.maxreach) {
         for (int off = 32; off > 0; off >>= 1) reach = max(reach, __shfl_xor(reach, off));
         if ((l & 63) == 0 && reach > 0) atomicMax(b.maxreach, reach);
@@ -276,6 +286,11 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
             red[1][l] = min(red[1][l], red[1][l + off]);
             red[2][l] = max(red[2][l], red[2][l + off]);
             red[3][l] = max(red[3][l], red[3][l + off]);
+            red[4][l] = min(red[4][l], red[4][l + off]);
+            red[5][l] = max(red[5][l], red[5][l + off]);
+            red[6][l] = min(red[6][l], red[6][l + off]);
+            red[7][l] = max(red[7][l], red[7][l + off]);
+            red[8][l] = max(red[8][l], red[8][l + off]);
             redf[l] |= redf[l + off];
         }
         __syncthreads();
@@ -310,7 +325,10 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
                     int gy0 = y0, gy1 = y1, gly = ly, ghy = hy;
                     if (my == 1) { gy0 = -1 - y1; gy1 = -1 - y0; gly = -hy; ghy = -ly; }
                     if (my == 2) { gy0 = 2 * g.ny - 1 - y1; gy1 = 2 * g.ny - 1 - y0; gly = -hy; ghy = -ly; }
-                    update_windows(g, b.dwin, gx0 + glx, gx1 + ghx, gy0 + gly, gy1 + ghy, glx, gly, ghx, ghy);
+                    // velocity bounds serve the straight gather only (mirror images
+                    // reverse velocities; tiles of domains with slip walls ignore them)
+                    const int ub[5] = {red[4][0], red[5][0], red[6][0], red[7][0], red[8][0]};
+                    update_windows(g, b.dwin, gx0 + glx, gx1 + ghx, gy0 + gly, gy1 + ghy, glx, gly, ghx, ghy, ub);
                 }
             }
         }
@@ -1747,9 +1765,26 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b, i
                 // (k <= 1); c_y enters once per row
                 T a0 = 0, a1 = 0, a2 = 0, a3 = 0, h0 = 0, h1 = 0;
                 const double cyd = (double)dy;
+                // the row's displacements that a reaching source can hit: with
+                // every source velocity in [ux0, ux1] x [uy0, uy1] and radius at
+                // most rmax, |dx - u_x| <= sqrt(rr^2 - dist(dy, [uy0, uy1])^2)
+                // (the slack of 1e-6 covers the rounding of the disk test)
+                int rlo = w.lox, rhi = w.hix;
+                if (!WALLS && w.rmax >= 0) {
+                    const double rrm = w.rmax + 0.5, q = 1.0 / 1024.0;
+                    const double dd = fmax(0.0, fmax(w.uyl * q - cyd, cyd - w.uyh * q));
+                    const double rem = rrm * rrm - dd * dd;
+                    if (rem < 0.0) {
+                        rlo = 1; rhi = 0;
+                    } else {
+                        const double wv = sqrt(rem);
+                        rlo = max(rlo, (int)ceil(w.uxl * q - wv - 1e-6));
+                        rhi = min(rhi, (int)floor(w.uxh * q + wv + 1e-6));
+                    }
+                }
                 // candidates in batches of GU so that the LDS and global
                 // reads of a batch are in flight together
-                for (int dxb = w.hix; dxb >= w.lox; dxb -= GU) {
+                for (int dxb = rhi; dxb >= rlo; dxb -= GU) {
                     const int ib = rowbase - dxb;
                     const double cxb = (double)dxb;
                     const T *pp[GU];
@@ -1870,6 +1905,7 @@ __global__ void k_reset_windows(int n, DWin *w, int *maxreach) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         w[i].lox = 1 << 29; w[i].loy = 1 << 29; w[i].hix = -(1 << 29); w[i].hiy = -(1 << 29);
+        w[i].uxl = 1 << 29; w[i].uyl = 1 << 29; w[i].uxh = -(1 << 29); w[i].uyh = -(1 << 29); w[i].rmax = -1;
     }
     if (i == 0 && maxreach) *maxreach = 0;
 }
