@@ -1656,9 +1656,11 @@ constexpr int META_FX = 1 << 8, META_FY = 1 << 9, META_REF = 1 << 10;
 
 // WALLS: some face is a slip wall (sources may be mirror images).  Sources
 // with refined stencils are skipped by the main scan and handled by a second
-// scan that runs only in workgroups whose staged region holds one.
+// scan that runs only in workgroups whose staged region holds one.  Five
+// wavefronts per SIMD at FP32 (the LDS of five workgroups fits a CU); the
+// FP64 variant needs more registers and keeps four.
 template <typename T, int D, bool WALLS>
-__global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b, int gcap) {
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, T *mom_out, Buffers b, int gcap) {
     constexpr int NM = Basis<D>::NMOM;
     extern __shared__ double2 g_lds[];
     double2 *s_u = g_lds;
@@ -1671,7 +1673,19 @@ __global__ void __launch_bounds__(256) k_gather(Geom g, T *mom_out, Buffers b, i
         if (threadIdx.x == 0) b.gpart[blockIdx.x] = 0ull;
         return;
     }
-    const int t = blockIdx.x;
+    // Workgroups go to the 8 XCDs in turn.  Deal whole tile rows to the XCDs
+    // instead (row r to XCD r mod 8, in order), so that the two x-neighbour
+    // tiles that read the halves of one record line run on the same XCD at
+    // about the same time and the second read hits its L2; rows that do not
+    // fill a round of 8 keep the plain order.
+    int t = blockIdx.x;
+    {
+        const int full = g.dty / 8 * 8 * g.dtx;
+        if (t < full) {
+            const int k = t & 7, i = t >> 3;
+            t = (i / g.dtx * 8 + k) * g.dtx + i % g.dtx;
+        }
+    }
     const int tx0 = (t % g.dtx) * g.tx, ty0 = (t / g.dtx) * g.ty;
     const int lx = threadIdx.x % g.tx, ly = threadIdx.x / g.tx;
     const int x = tx0 + lx, y = ty0 + ly;
