@@ -341,8 +341,8 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     g.sxn = g.nx + g.wl + g.wr;
     g.syn = g.ny + g.wb + g.wt;
     g.ns = (long long)g.sxn * g.syn;
-    if (p->dim == 2) { g.tx = 16; g.ty = 16; }
-    else { g.tx = 256; g.ty = 1; }
+    if (p->dim == 2) { g.tx = tile_x<2>(); g.ty = tile_y<2>(); }
+    else { g.tx = tile_x<1>(); g.ty = tile_y<1>(); }
     g.ntx = (g.sxn + g.tx - 1) / g.tx; g.nty = (g.syn + g.ty - 1) / g.ty;
     g.dtx = (g.nx + g.tx - 1) / g.tx; g.dty = (g.ny + g.ty - 1) / g.ty;
     Phys &ph = c->ph;
@@ -377,7 +377,8 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ok = ok && hipMalloc((void **)&b.partial, (size_t)(num_sum_blocks(g) + 1) * 4 * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.harvest_n, sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.bpart, (size_t)nt * sizeof(DevStats)) == hipSuccess;
-    ok = ok && hipMalloc((void **)&b.gpart, (size_t)nd * sizeof(unsigned long long)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.gpart, (size_t)gather_blocks_x(g) * gather_blocks_y(g) *
+                                                sizeof(unsigned long long)) == hipSuccess;
     if (p->guess == LELBM_GUESS_PREV) {
         ok = ok && hipMalloc((void **)&b.lamprev, (size_t)16 * ns * sizeof(double)) == hipSuccess;
         // all-ones bytes are a NaN: no stored correction yet

@@ -11,6 +11,8 @@ namespace lelbm {
 // Source cells are processed in tiles of TILE_N cells: 16 x 16 in 2D and
 // 256 x 1 in 1D.  One workgroup handles one tile in every per-cell kernel.
 constexpr int TILE_N = 256;
+template <int D> constexpr int tile_x() { return D == 2 ? 16 : 256; }
+template <int D> constexpr int tile_y() { return D == 2 ? 16 : 1; }
 constexpr int MAX_REFINE = 3;       // supported stencil refinement levels
 constexpr int MAX_RADIUS = 128;     // largest acoustic radius (RT up to ~1000)
 constexpr double MAX_SPEED = 2048.0;  // largest |u| component in cells per step
@@ -49,6 +51,11 @@ struct Geom {
     int ntx, nty;             // source tiles over the padded domain
     int dtx, dty;             // destination tiles over the interior
 };
+
+// Gather workgroups: in 2D one per lower or upper half of a pair of
+// x-neighbour destination tiles (32 x 8 cells), in 1D one per tile.
+__host__ __device__ inline int gather_blocks_x(const Geom &g) { return g.dim == 2 ? (g.dtx + 1) / 2 : g.dtx; }
+__host__ __device__ inline int gather_blocks_y(const Geom &g) { return g.dim == 2 ? 2 * g.dty : g.dty; }
 
 struct Phys {
     double K, omega_f, omega_b, omega_h;

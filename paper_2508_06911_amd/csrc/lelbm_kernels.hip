@@ -1537,12 +1537,23 @@ constexpr int GU = 4;         // candidates per batch in the gather
 
 struct Resolved {
     long long s;    // padded source index, -1 if none
+    int px, py;     // padded source coordinates
     int fx, fy;     // 1 if the path is mirrored in x / y
 };
 
+// Source tile and the cell's place in it from padded coordinates (tile
+// shapes are powers of two, so these are shifts and masks).
+template <int D>
+__device__ inline void tile_of(const Geom &g, int px, int py, int &st, int &loc) {
+    constexpr unsigned TX = tile_x<D>(), TY = tile_y<D>();
+    const unsigned ux = (unsigned)px, uy = (unsigned)py;
+    st = (int)(ux / TX + uy / TY * (unsigned)g.ntx);
+    loc = (int)(ux % TX + uy % TY * TX);
+}
+
 template <int D>
 __device__ inline Resolved resolve_source(const Geom &g, int xr, int yr) {
-    Resolved r{-1, 0, 0};
+    Resolved r{-1, 0, 0, 0, 0};
     int sx = xr, sy = yr;
     if (g.bc[0] == LELBM_BC_PERIODIC) { sx %= g.nx; if (sx < 0) sx += g.nx; }
     else if (sx < 0 && g.bc[0] == LELBM_BC_SLIPWALL) { sx = -1 - sx; r.fx = 1; }
@@ -1556,7 +1567,9 @@ __device__ inline Resolved resolve_source(const Geom &g, int xr, int yr) {
     } else {
         sy = 0;
     }
-    r.s = (long long)(sy + g.wb) * g.sxn + (sx + g.wl);
+    r.px = sx + g.wl;
+    r.py = sy + g.wb;
+    r.s = (long long)r.py * g.sxn + r.px;
     return r;
 }
 
@@ -1673,24 +1686,53 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
         if (threadIdx.x == 0) b.gpart[blockIdx.x] = 0ull;
         return;
     }
-    // Workgroups go to the 8 XCDs in turn.  Deal whole tile rows to the XCDs
-    // instead (row r to XCD r mod 8, in order), so that the two x-neighbour
-    // tiles that read the halves of one record line run on the same XCD at
-    // about the same time and the second read hits its L2; rows that do not
-    // fill a round of 8 keep the plain order.
+    // Destination block of a workgroup: in 2D the lower or upper half (32 x 8
+    // cells) of two x-neighbour tiles, each wavefront 16 x 4 cells of one of
+    // them; in 1D one tile.  A record line holds 16 cells of a source-tile
+    // row; the destination row segment it lands on straddles two tiles, and
+    // with both in one workgroup the second half is read from the L1 of the
+    // same CU.
+    constexpr int TX = tile_x<D>(), TY = tile_y<D>();
+    constexpr int BX = D == 2 ? 2 * TX : TX, BY = D == 2 ? TY / 2 : TY;
+    const int nbx = gather_blocks_x(g), nby = gather_blocks_y(g);
+    // Workgroups go to the 8 XCDs in turn.  Deal whole block rows to the XCDs
+    // instead (row r to XCD r mod 8, in order), so that x-neighbour blocks,
+    // which read the two halves of the record lines on their common edge, run
+    // on the same XCD at about the same time and the second read hits its L2;
+    // rows that do not fill a round of 8 keep the plain order.
     int t = blockIdx.x;
     {
-        const int full = g.dty / 8 * 8 * g.dtx;
+        const int full = nby / 8 * 8 * nbx;
         if (t < full) {
             const int k = t & 7, i = t >> 3;
-            t = (i / g.dtx * 8 + k) * g.dtx + i % g.dtx;
+            t = (i / nbx * 8 + k) * nbx + i % nbx;
         }
     }
-    const int tx0 = (t % g.dtx) * g.tx, ty0 = (t / g.dtx) * g.ty;
-    const int lx = threadIdx.x % g.tx, ly = threadIdx.x / g.tx;
-    const int x = tx0 + lx, y = ty0 + ly;
+    const int x0 = (t % nbx) * BX, y0 = (t / nbx) * BY;
+    int lx, ly;                                  // the lane's cell in the block
+    if (D == 2) {
+        const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+        lx = (wv & 1) * TX + (l & 15);
+        ly = (wv >> 1) * 4 + (l >> 4);
+    } else {
+        lx = threadIdx.x;
+        ly = 0;
+    }
+    const int x = x0 + lx, y = y0 + ly;
     const bool mine = x < g.nx && y < g.ny;
-    const DWin w = b.dwin[t];
+    // windows of the block's tiles (an absent right tile has an empty one),
+    // of the lane's own tile (uniform per wavefront) and their union
+    const int tl = (y0 / TY) * g.dtx + x0 / TX;
+    const bool has_r = D == 2 && x0 / TX + 1 < g.dtx;
+    const DWin wl = b.dwin[tl];
+    DWin wr = wl;
+    if (D == 2) {
+        if (has_r) wr = b.dwin[tl + 1];
+        else { wr.lox = wr.loy = 1 << 29; wr.hix = wr.hiy = -(1 << 29); }
+    }
+    const DWin w = lx >= TX ? wr : wl;
+    const int ulox = min(wl.lox, wr.lox), uhix = max(wl.hix, wr.hix);
+    const int uloy = min(wl.loy, wr.loy), uhiy = max(wl.hiy, wr.hiy);
     using V2 = typename Vec2<T>::type;
     const T *SCR = (const T *)b.scratch;
     T acc[NM];
@@ -1700,8 +1742,8 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     // staged region: window columns plus GU - 1 more, so that a batch that
     // runs past the window's low edge reads real entries (whose disk test
     // fails: those displacements lie outside every reaching source's box)
-    const int RW = g.tx + (w.hix - w.lox) + GU - 1;
-    int rows = gcap / RW - (g.ty - 1);              // window rows per chunk
+    const int RW = BX + (uhix - ulox) + GU - 1;
+    int rows = gcap / RW - (BY - 1);                // window rows per chunk
     // Tiles within reach of a blocker: every landing displacement d with
     // |d_x|, |d_y| <= the step's maximum reach M is traced back to the source
     // it comes from (walk_back), which finds the straight and the reflected
@@ -1709,7 +1751,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     // blocker (it would have to pass within M cells of the tile), so every
     // arrival comes straight from x - d.
     const int M = b.maxreach ? *b.maxreach : 0;
-    const bool near = b.tdist && b.tdist[t] <= M + 1;
+    const bool near = b.tdist && (b.tdist[tl] <= M + 1 || (has_r && b.tdist[tl + 1] <= M + 1));
     if (near) {
         const bool fluid = mine && !(b.solid && b.solid[(long long)y * g.nx + x]);
         if (fluid) {
@@ -1725,9 +1767,8 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
                     const bool in = D == 2 ? in_disk2((double)cx, (double)cy, b.desc_u[s], b.desc_u[g.ns + s], rr)
                                            : in_disk1((double)cx, b.desc_u[s], rr);
                     if (!in) continue;
-                    const int px = (int)(s % g.sxn), py = (int)(s / g.sxn);
-                    const int st = (px / g.tx) + (py / g.ty) * g.ntx;
-                    const int loc = (px % g.tx) + (py % g.ty) * g.tx;
+                    int st, loc;
+                    tile_of<D>(g, ox + g.wl, oy + g.wb, st, loc);
                     const TileInfo ti = b.tiles[st];
                     const long long recsz = ti.fmt ? NM : 2;
                     const long long slot = (long long)(cy - ti.oy) * ti.wx + (cx - ti.ox);
@@ -1737,11 +1778,11 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
                 }
             }
         }
-    } else if (w.lox <= w.hix && rows >= 1) {
-        for (int dy0 = w.hiy; dy0 >= w.loy; dy0 -= rows) {
-            const int dy1 = max(w.loy, dy0 - rows + 1);
-            const int RH = g.ty + (dy0 - dy1);
-            const int rx0 = tx0 - w.hix, ry0 = ty0 - dy0;
+    } else if (ulox <= uhix && rows >= 1) {
+        for (int dy0 = uhiy; dy0 >= uloy; dy0 -= rows) {
+            const int dy1 = max(uloy, dy0 - rows + 1);
+            const int RH = BY + (dy0 - dy1);
+            const int rx0 = x0 - uhix, ry0 = y0 - dy0;
             __syncthreads();
             if (threadIdx.x == 0) s_ref = 0;
             __syncthreads();
@@ -1752,10 +1793,9 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
                 if (rs.s >= 0) {
                     int rn = b.desc_rn[rs.s];
                     if (rn >= 0) {
-                        long long s = rs.s;
-                        int px = (int)(s % g.sxn), py = (int)(s / g.sxn);
-                        int st = (px / g.tx) + (py / g.ty) * g.ntx;
-                        int loc = (px % g.tx) + (py % g.ty) * g.tx;
+                        const long long s = rs.s;
+                        int st, loc;
+                        tile_of<D>(g, rs.px, rs.py, st, loc);
                         const TileInfo ti = b.tiles[st];
                         long long recsz = ti.fmt ? NM : 2;
                         s_a0[i] = ti.base + (long long)loc * recsz -
@@ -1773,8 +1813,9 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
             __syncthreads();
             const bool ref = s_ref != 0;
             if (!mine) continue;
-            for (int dy = dy0; dy >= dy1; dy--) {
-                const int rowbase = (ly + (dy0 - dy)) * RW + lx + w.hix;
+            // the rows of the chunk that the lane's own tile window holds
+            for (int dy = min(dy0, w.hiy); dy >= max(dy1, w.loy); dy--) {
+                const int rowbase = (ly + (dy0 - dy)) * RW + lx + uhix;
                 // sums over the row of w_f c_x^k (k <= 3) and w_g c_x^k
                 // (k <= 1); c_y enters once per row
                 T a0 = 0, a1 = 0, a2 = 0, a3 = 0, h0 = 0, h1 = 0;
@@ -1886,9 +1927,8 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
                 bool in = D == 2 ? in_disk2((double)rdx, (double)rdy, b.desc_u[s], b.desc_u[g.ns + s], rr)
                                  : in_disk1((double)rdx, b.desc_u[s], rr);
                 if (!in) continue;
-                int px = (int)(s % g.sxn), py = (int)(s / g.sxn);
-                int st = (px / g.tx) + (py / g.ty) * g.ntx;
-                int loc = (px % g.tx) + (py % g.ty) * g.tx;
+                int st, loc;
+                tile_of<D>(g, rs.px, rs.py, st, loc);
                 const TileInfo ti = b.tiles[st];
                 const long long recsz = ti.fmt ? NM : 2;
                 long long slot = (long long)(rdy - ti.oy) * ti.wx + (rdx - ti.ox);
@@ -2195,7 +2235,7 @@ hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const void *
 
 template <typename T, int D>
 static void gather_launch(const Geom &g, void *mom_out, Buffers &b, int gcap, hipStream_t s) {
-    const unsigned nt = (unsigned)(g.dtx * g.dty);
+    const unsigned nt = (unsigned)(gather_blocks_x(g) * gather_blocks_y(g));
     const size_t lds = (size_t)gcap * G_ENTRY_BYTES;
     bool walls = false;
     for (int f = 0; f < 2 * D; f++) walls = walls || g.bc[f] == LELBM_BC_SLIPWALL;
@@ -2211,7 +2251,7 @@ hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, in
         if (g.dim == 1) gather_launch<double, 1>(g, mom_out, b, gcap, s);
         else gather_launch<double, 2>(g, mom_out, b, gcap, s);
     }
-    const int nd = g.dtx * g.dty;
+    const int nd = gather_blocks_x(g) * gather_blocks_y(g);
     const int nb = (nd + 255) / 256 < 256 ? (nd + 255) / 256 : 256;
     hipLaunchKernelGGL(k_sum_partials, dim3(nb), dim3(256), 0, s, (const unsigned long long *)b.gpart, nd,
                        &b.stats->arrivals);
