@@ -52,10 +52,13 @@ struct Geom {
     int dtx, dty;             // destination tiles over the interior
 };
 
-// Gather workgroups: in 2D one per lower or upper half of a pair of
-// x-neighbour destination tiles (32 x 8 cells), in 1D one per tile.
-__host__ __device__ inline int gather_blocks_x(const Geom &g) { return g.dim == 2 ? (g.dtx + 1) / 2 : g.dtx; }
-__host__ __device__ inline int gather_blocks_y(const Geom &g) { return g.dim == 2 ? 2 * g.dty : g.dty; }
+// Gather workgroups: in 2D one per strip of GATHER_NTB x-neighbour
+// destination tiles, 16 / GATHER_NTB cells high; in 1D one per tile.
+constexpr int GATHER_NTB = 2;
+__host__ __device__ inline int gather_blocks_x(const Geom &g) {
+    return g.dim == 2 ? (g.dtx + GATHER_NTB - 1) / GATHER_NTB : g.dtx;
+}
+__host__ __device__ inline int gather_blocks_y(const Geom &g) { return g.dim == 2 ? GATHER_NTB * g.dty : g.dty; }
 
 struct Phys {
     double K, omega_f, omega_b, omega_h;

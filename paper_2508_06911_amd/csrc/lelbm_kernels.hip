@@ -1686,14 +1686,15 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
         if (threadIdx.x == 0) b.gpart[blockIdx.x] = 0ull;
         return;
     }
-    // Destination block of a workgroup: in 2D the lower or upper half (32 x 8
-    // cells) of two x-neighbour tiles, each wavefront 16 x 4 cells of one of
-    // them; in 1D one tile.  A record line holds 16 cells of a source-tile
-    // row; the destination row segment it lands on straddles two tiles, and
-    // with both in one workgroup the second half is read from the L1 of the
-    // same CU.
+    // Destination block of a workgroup: in 2D a GATHER_NTB x 16 wide and
+    // 16 / GATHER_NTB high strip of GATHER_NTB x-neighbour tiles, each
+    // wavefront 16 x 4 cells of one of them; in 1D one tile.  A record line
+    // holds 16 cells of a source-tile row; the destination row segment it
+    // lands on straddles two tiles, and with both in one workgroup the second
+    // half is read from the L1 of the same CU.
     constexpr int TX = tile_x<D>(), TY = tile_y<D>();
-    constexpr int BX = D == 2 ? 2 * TX : TX, BY = D == 2 ? TY / 2 : TY;
+    constexpr int NTB = D == 2 ? GATHER_NTB : 1;
+    constexpr int BX = NTB * TX, BY = TY / NTB;
     const int nbx = gather_blocks_x(g), nby = gather_blocks_y(g);
     // Workgroups go to the 8 XCDs in turn.  Deal whole block rows to the XCDs
     // instead (row r to XCD r mod 8, in order), so that x-neighbour blocks,
@@ -1712,27 +1713,29 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     int lx, ly;                                  // the lane's cell in the block
     if (D == 2) {
         const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-        lx = (wv & 1) * TX + (l & 15);
-        ly = (wv >> 1) * 4 + (l >> 4);
+        lx = (wv % NTB) * TX + (l & 15);
+        ly = (wv / NTB) * 4 + (l >> 4);
     } else {
         lx = threadIdx.x;
         ly = 0;
     }
     const int x = x0 + lx, y = y0 + ly;
     const bool mine = x < g.nx && y < g.ny;
-    // windows of the block's tiles (an absent right tile has an empty one),
-    // of the lane's own tile (uniform per wavefront) and their union
+    // windows of the block's tiles (absent tiles past the domain's edge have
+    // none), of the lane's own tile (uniform per wavefront) and their union
     const int tl = (y0 / TY) * g.dtx + x0 / TX;
-    const bool has_r = D == 2 && x0 / TX + 1 < g.dtx;
-    const DWin wl = b.dwin[tl];
-    DWin wr = wl;
-    if (D == 2) {
-        if (has_r) wr = b.dwin[tl + 1];
-        else { wr.lox = wr.loy = 1 << 29; wr.hix = wr.hiy = -(1 << 29); }
+    const int ntb = min(NTB, g.dtx - x0 / TX);  // tiles of the block in the domain
+    DWin w = b.dwin[tl + min(lx / TX, ntb - 1)];
+    if (lx / TX >= ntb) { w.lox = w.loy = 1 << 29; w.hix = w.hiy = -(1 << 29); }
+    int ulox = 1 << 29, uhix = -(1 << 29), uloy = 1 << 29, uhiy = -(1 << 29);
+    bool near_any = false;
+    const int M = b.maxreach ? *b.maxreach : 0;
+    for (int k = 0; k < ntb; k++) {
+        const DWin wk = b.dwin[tl + k];
+        ulox = min(ulox, wk.lox); uhix = max(uhix, wk.hix);
+        uloy = min(uloy, wk.loy); uhiy = max(uhiy, wk.hiy);
+        near_any = near_any || (b.tdist && b.tdist[tl + k] <= M + 1);
     }
-    const DWin w = lx >= TX ? wr : wl;
-    const int ulox = min(wl.lox, wr.lox), uhix = max(wl.hix, wr.hix);
-    const int uloy = min(wl.loy, wr.loy), uhiy = max(wl.hiy, wr.hiy);
     using V2 = typename Vec2<T>::type;
     const T *SCR = (const T *)b.scratch;
     T acc[NM];
@@ -1750,8 +1753,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     // arrivals alike.  Elsewhere no path that ends in the tile can touch a
     // blocker (it would have to pass within M cells of the tile), so every
     // arrival comes straight from x - d.
-    const int M = b.maxreach ? *b.maxreach : 0;
-    const bool near = b.tdist && (b.tdist[tl] <= M + 1 || (has_r && b.tdist[tl + 1] <= M + 1));
+    const bool near = near_any;
     if (near) {
         const bool fluid = mine && !(b.solid && b.solid[(long long)y * g.nx + x]);
         if (fluid) {
