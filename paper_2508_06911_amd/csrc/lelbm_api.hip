@@ -189,7 +189,7 @@ static void free_ctx(lelbm_ctx *c) {
     Buffers &b = c->b;
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.spans, b.tiles,
                     b.dwin, b.scratch, b.flags, b.stats, b.partial, b.harvest_n,
-                    c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, b.lamprev,
+                    c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, (void *)b.cdist, b.lamprev,
                     b.bpart, b.gpart};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -252,7 +252,8 @@ static int setup_blockers(lelbm_ctx *c, const unsigned char *mask) {
             int &me = d[(long long)y * nx + x];
             if (v < me) { me = v; chg = true; }
         };
-        for (int round = 0; round < 64; round++) {
+        bool stable = false;
+        for (int round = 0; round < 64 && !stable; round++) {
             bool chg = false;
             for (int y = 0; y < ny; y++)
                 for (int x = 0; x < nx; x++) {
@@ -262,11 +263,14 @@ static int setup_blockers(lelbm_ctx *c, const unsigned char *mask) {
                 for (int x = nx - 1; x >= 0; x--) {
                     relax(x, y, 1, 0, chg); relax(x, y, 1, 1, chg); relax(x, y, 0, 1, chg); relax(x, y, -1, 1, chg);
                 }
-            if (!chg) break;
+            stable = !chg;
         }
+        // not settled: no distance is trusted (every cell traces its paths)
+        if (!stable) std::fill(d.begin(), d.end(), 0);
     }
     const int nd = g.dtx * g.dty;
     std::vector<int> td((size_t)nd, INF);
+    std::vector<unsigned short> cd((size_t)n);
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
             int v = d[(long long)y * nx + x];
@@ -276,16 +280,23 @@ static int setup_blockers(lelbm_ctx *c, const unsigned char *mask) {
             if (g.dim == 2 && g.bc[3] == LELBM_BC_SLIPWALL) v = std::min(v, ny - y);
             int &t = td[(size_t)(y / g.ty) * g.dtx + x / g.tx];
             t = std::min(t, v);
+            cd[(size_t)y * nx + x] = (unsigned short)std::min(v, 65535);
         }
     Buffers &b = c->b;
     int *dt = nullptr, *mr = nullptr;
+    unsigned short *cdv = nullptr;
     unsigned char *sm = nullptr;
     if (hipMalloc((void **)&dt, (size_t)nd * sizeof(int)) != hipSuccess) return LELBM_ENOMEM;
     b.tdist = dt;
     if (hipMalloc((void **)&mr, sizeof(int)) != hipSuccess) return LELBM_ENOMEM;
     b.maxreach = mr;
+    if (hipMalloc((void **)&cdv, (size_t)n * sizeof(unsigned short)) != hipSuccess) return LELBM_ENOMEM;
+    b.cdist = cdv;
     int r = stage_h2d(c->stage, c->stream, dt, td.data(), (size_t)nd * sizeof(int));
     if (r != LELBM_OK) return r;
+    r = stage_h2d(c->stage, c->stream, cdv, cd.data(), (size_t)n * sizeof(unsigned short));
+    if (r != LELBM_OK) return r;
+    c->persistent_bytes += n * (long long)sizeof(unsigned short);
     if (mask) {
         if (hipMalloc((void **)&sm, (size_t)n) != hipSuccess) return LELBM_ENOMEM;
         b.solid = sm;
@@ -377,7 +388,8 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ok = ok && hipMalloc((void **)&b.partial, (size_t)(num_sum_blocks(g) + 1) * 4 * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.harvest_n, sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.bpart, (size_t)nt * sizeof(DevStats)) == hipSuccess;
-    ok = ok && hipMalloc((void **)&b.gpart, (size_t)gather_blocks_x(g) * gather_blocks_y(g) *
+    // arrival partials of the straight gather and of the backward-walk gather
+    ok = ok && hipMalloc((void **)&b.gpart, (size_t)2 * gather_blocks_x(g) * gather_blocks_y(g) *
                                                 sizeof(unsigned long long)) == hipSuccess;
     if (p->guess == LELBM_GUESS_PREV) {
         ok = ok && hipMalloc((void **)&b.lamprev, (size_t)16 * ns * sizeof(double)) == hipSuccess;

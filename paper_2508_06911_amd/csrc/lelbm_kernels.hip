@@ -1624,33 +1624,47 @@ __device__ inline bool is_blocked(const Geom &g, const unsigned char *solid, int
 // first where they coincide), each of which exactly undoes its forward
 // counterpart.  It returns the cell of origin and the signs the forward path
 // applied to each component, or false if it leaves the padded domain (no
-// source there).
+// source there).  The walk runs in unwrapped coordinates (each stays within
+// |v| of the landing cell, each probe within |v| + 1); blocked(x, y) wraps
+// periodic axes itself, and the origin is wrapped at the end.
+__device__ inline int wrap_coord(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
 template <int D>
-__device__ inline bool walk_back(const Geom &g, const unsigned char *solid, int x, int y, int vx, int vy, int &ox,
+__device__ inline bool blocked_wrapped(const Geom &g, const unsigned char *solid, int x, int y) {
+    if (g.bc[0] == LELBM_BC_PERIODIC) x = wrap_coord(x, g.nx);
+    if (D == 2 && g.bc[2] == LELBM_BC_PERIODIC) y = wrap_coord(y, g.ny);
+    return is_blocked(g, solid, x, y);
+}
+
+template <int D, typename Blocked>
+__device__ inline bool walk_back(const Geom &g, const Blocked &blocked, int x, int y, int vx, int vy, int &ox,
                                  int &oy, int &sgx, int &sgy) {
+    // Every step is written with selects rather than branches (the crossing
+    // order depends only on |v|, the same for all lanes of a call); a walk
+    // that leaves the padded domain is finished and then rejected.
     const int ax = abs(vx), ay = abs(vy);
     int sx = vx < 0 ? -1 : 1, sy = vy < 0 ? -1 : 1, kx = 0, ky = 0;
     const bool perx = g.bc[0] == LELBM_BC_PERIODIC, pery = D == 2 && g.bc[2] == LELBM_BC_PERIODIC;
-    while (kx < ax || ky < ay) {
-        bool takey;
-        if (ky >= ay) takey = false;
-        else if (kx >= ax) takey = true;
-        else takey = (long long)(2 * ky + 1) * ax <= (long long)(2 * kx + 1) * ay;
-        if (takey) {
-            int t = y + sy;
-            if (pery) { t %= g.ny; if (t < 0) t += g.ny; }
-            if (is_blocked(g, solid, x, t)) sy = -sy; else y = t;
-            ky++;
-        } else {
-            int t = x + sx;
-            if (perx) { t %= g.nx; if (t < 0) t += g.nx; }
-            if (is_blocked(g, solid, t, y)) sx = -sx; else x = t;
-            kx++;
-        }
-        if (x < -g.wl || x >= g.nx + g.wr || y < -g.wb || y >= g.ny + g.wt) return false;
+    bool out = false;
+    for (int k = 0; k < ax + ay; k++) {
+        const bool takey =
+            kx >= ax || (ky < ay && __mul24(2 * ky + 1, ax) <= __mul24(2 * kx + 1, ay));  // < 2^31 for |v| < 2^15
+        const int px = takey ? x : x + sx, py = takey ? y + sy : y;
+        const bool bl = blocked(px, py);
+        x = bl ? x : px;
+        y = bl ? y : py;
+        sx = (bl && !takey) ? -sx : sx;
+        sy = (bl && takey) ? -sy : sy;
+        kx += takey ? 0 : 1;
+        ky += takey ? 1 : 0;
+        out = out || (!perx && (x < -g.wl || x >= g.nx + g.wr)) || (!pery && (y < -g.wb || y >= g.ny + g.wt));
     }
-    ox = x;
-    oy = y;
+    if (out) return false;
+    ox = perx ? wrap_coord(x, g.nx) : x;
+    oy = pery ? wrap_coord(y, g.ny) : y;
     // the forward path ends with velocity -(sx, sy) and started with -(vx, vy) times its flips
     sgx = (vx == 0 || (sx < 0) == (vx < 0)) ? 1 : -1;
     sgy = (vy == 0 || (sy < 0) == (vy < 0)) ? 1 : -1;
@@ -1721,20 +1735,27 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     }
     const int x = x0 + lx, y = y0 + ly;
     const bool mine = x < g.nx && y < g.ny;
-    // windows of the block's tiles (absent tiles past the domain's edge have
-    // none), of the lane's own tile (uniform per wavefront) and their union
+    // Tiles within reach of a blocker: every landing displacement d with
+    // |d_x|, |d_y| <= the step's maximum reach M is traced back to the source
+    // it comes from (walk_back), which finds the straight and the reflected
+    // arrivals alike.  Elsewhere no path that ends in the tile can touch a
+    // blocker (it would have to pass within M cells of the tile), so every
+    // arrival comes straight from x - d.  The lane's own tile decides (uniform
+    // per wavefront); the straight gather stages the union of the windows of
+    // the block's other tiles (absent tiles past the domain's edge have none).
     const int tl = (y0 / TY) * g.dtx + x0 / TX;
     const int ntb = min(NTB, g.dtx - x0 / TX);  // tiles of the block in the domain
-    DWin w = b.dwin[tl + min(lx / TX, ntb - 1)];
-    if (lx / TX >= ntb) { w.lox = w.loy = 1 << 29; w.hix = w.hiy = -(1 << 29); }
-    int ulox = 1 << 29, uhix = -(1 << 29), uloy = 1 << 29, uhiy = -(1 << 29);
-    bool near_any = false;
     const int M = b.maxreach ? *b.maxreach : 0;
+    const int own = lx / TX;
+    DWin w = b.dwin[tl + min(own, ntb - 1)];
+    if (own >= ntb) { w.lox = w.loy = 1 << 29; w.hix = w.hiy = -(1 << 29); }
+    const bool near = own < ntb && b.tdist && b.tdist[tl + own] <= M + 1;
+    int ulox = 1 << 29, uhix = -(1 << 29), uloy = 1 << 29, uhiy = -(1 << 29);
     for (int k = 0; k < ntb; k++) {
+        if (b.tdist && b.tdist[tl + k] <= M + 1) continue;
         const DWin wk = b.dwin[tl + k];
         ulox = min(ulox, wk.lox); uhix = max(uhix, wk.hix);
         uloy = min(uloy, wk.loy); uhiy = max(uhiy, wk.hiy);
-        near_any = near_any || (b.tdist && b.tdist[tl + k] <= M + 1);
     }
     using V2 = typename Vec2<T>::type;
     const T *SCR = (const T *)b.scratch;
@@ -1747,40 +1768,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     // fails: those displacements lie outside every reaching source's box)
     const int RW = BX + (uhix - ulox) + GU - 1;
     int rows = gcap / RW - (BY - 1);                // window rows per chunk
-    // Tiles within reach of a blocker: every landing displacement d with
-    // |d_x|, |d_y| <= the step's maximum reach M is traced back to the source
-    // it comes from (walk_back), which finds the straight and the reflected
-    // arrivals alike.  Elsewhere no path that ends in the tile can touch a
-    // blocker (it would have to pass within M cells of the tile), so every
-    // arrival comes straight from x - d.
-    const bool near = near_any;
-    if (near) {
-        const bool fluid = mine && !(b.solid && b.solid[(long long)y * g.nx + x]);
-        if (fluid) {
-            for (int dy = D == 2 ? M : 0; dy >= (D == 2 ? -M : 0); dy--) {
-                for (int dx = M; dx >= -M; dx--) {
-                    int ox, oy, sgx, sgy;
-                    if (!walk_back<D>(g, b.solid, x, y, -dx, -dy, ox, oy, sgx, sgy)) continue;
-                    const long long s = (long long)(oy + g.wb) * g.sxn + (ox + g.wl);
-                    const int rn = b.desc_rn[s];
-                    if (rn < 0) continue;
-                    const int cx = sgx * dx, cy = sgy * dy;        // the source's own displacement
-                    const double rr = (rn & 0xffff) + 0.5;
-                    const bool in = D == 2 ? in_disk2((double)cx, (double)cy, b.desc_u[s], b.desc_u[g.ns + s], rr)
-                                           : in_disk1((double)cx, b.desc_u[s], rr);
-                    if (!in) continue;
-                    int st, loc;
-                    tile_of<D>(g, ox + g.wl, oy + g.wb, st, loc);
-                    const TileInfo ti = b.tiles[st];
-                    const long long recsz = ti.fmt ? NM : 2;
-                    const long long slot = (long long)(cy - ti.oy) * ti.wx + (cx - ti.ox);
-                    const T *P = SCR + ti.base + (slot * TILE_N + loc) * recsz;
-                    hits++;
-                    deposit_record<T, D>(acc, P, ti.fmt, dx, dy, sgx < 0, sgy < 0);
-                }
-            }
-        }
-    } else if (ulox <= uhix && rows >= 1) {
+    if (ulox <= uhix && rows >= 1) {
         for (int dy0 = uhiy; dy0 >= uloy; dy0 -= rows) {
             const int dy1 = max(uloy, dy0 - rows + 1);
             const int RH = BY + (dy0 - dy1);
@@ -1814,7 +1802,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
             if (anyref) s_ref = 1;
             __syncthreads();
             const bool ref = s_ref != 0;
-            if (!mine) continue;
+            if (!mine || near) continue;
             // the rows of the chunk that the lane's own tile window holds
             for (int dy = min(dy0, w.hiy); dy >= max(dy1, w.loy); dy--) {
                 const int rowbase = (ly + (dy0 - dy)) * RW + lx + uhix;
@@ -1915,7 +1903,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
                 }
             }
         }
-    } else if (w.lox <= w.hix && mine) {
+    } else if (!near && w.lox <= w.hix && mine) {
         // window too wide to stage: descriptors straight from global memory
         for (int dy = w.hiy; dy >= w.loy; dy--) {
             for (int dx = w.hix; dx >= w.lox; dx--) {
@@ -1940,7 +1928,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
             }
         }
     }
-    if (mine) {
+    if (mine && !near) {
         long long o = (long long)(y + g.wb) * g.sxn + (x + g.wl);
 #pragma unroll
         for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = (T)acc[k];
@@ -1952,6 +1940,148 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     if ((threadIdx.x & 63) == 0) s_hits[threadIdx.x >> 6] = hl;
     __syncthreads();
     if (threadIdx.x == 0) b.gpart[blockIdx.x] = s_hits[0] + s_hits[1] + s_hits[2] + s_hits[3];
+}
+
+// Destination tiles within reach of a blocker (the ones k_gather leaves
+// out): every landing displacement d with |d_x|, |d_y| <= the step's maximum
+// reach M is traced back to the source it comes from (walk_back), which finds
+// the straight and the reflected arrivals alike.  Same workgroup blocks as
+// k_gather; wavefronts of other tiles return at once.  The walks probe the
+// blockers of the cells within M + 1 of the wavefront's 16 x 4 cells (64 x 1
+// in 1D): staged once as one byte per cell in the wavefront's quarter of the
+// LDS (mapb bytes), else read from global memory.  Candidates go in batches
+// of GU so that the descriptor loads of a batch are in flight together.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers b, int mapb) {
+    constexpr int NM = Basis<D>::NMOM;
+    constexpr int TX = tile_x<D>(), TY = tile_y<D>();
+    constexpr int NTB = D == 2 ? GATHER_NTB : 1;
+    constexpr int BX = NTB * TX, BY = TY / NTB;
+    extern __shared__ double2 g_lds[];
+    const int nbx = gather_blocks_x(g), nd = nbx * gather_blocks_y(g);
+    const int x0 = (blockIdx.x % nbx) * BX, y0 = (blockIdx.x / nbx) * BY;
+    int lx, ly;
+    if (D == 2) {
+        const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+        lx = (wv % NTB) * TX + (l & 15);
+        ly = (wv / NTB) * 4 + (l >> 4);
+    } else {
+        lx = threadIdx.x;
+        ly = 0;
+    }
+    const int x = x0 + lx, y = y0 + ly;
+    const bool mine = x < g.nx && y < g.ny;
+    const int tl = (y0 / TY) * g.dtx + x0 / TX;
+    const int ntb = min(NTB, g.dtx - x0 / TX);
+    const int own = lx / TX;
+    const int M = *b.maxreach;
+    const bool near = !b.flags->err && own < ntb && b.tdist[tl + own] <= M + 1;
+    const T *SCR = (const T *)b.scratch;
+    int hits = 0;
+    if (near) {
+        constexpr int WX = D == 2 ? 16 : 64, WY = D == 2 ? 4 : 1;
+        const int xw = x0 + (lx & ~(WX - 1)), yw = y0 + (ly & ~(WY - 1));
+        const int bx0 = xw - M - 1, by0 = D == 2 ? yw - M - 1 : 0;
+        const int bw = WX + 2 * M + 2, bh = D == 2 ? WY + 2 * M + 2 : 1;
+        const bool staged_map = (long long)bw * bh <= mapb;
+        unsigned char *bmap = (unsigned char *)g_lds + (size_t)(threadIdx.x >> 6) * mapb;
+        if (staged_map) {
+            for (int i = threadIdx.x & 63; i < bw * bh; i += 64)
+                bmap[i] = blocked_wrapped<D>(g, b.solid, bx0 + i % bw, by0 + i / bw) ? 1 : 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        const auto blocked_lds = [&](int px, int py) { return bmap[(py - by0) * bw + (px - bx0)] != 0; };
+        const auto blocked_glb = [&](int px, int py) { return blocked_wrapped<D>(g, b.solid, px, py); };
+        T acc[NM];
+#pragma unroll
+        for (int k = 0; k < NM; k++) acc[k] = 0;
+        const bool fluid = mine && !(b.solid && b.solid[(long long)y * g.nx + x]);
+        // a path of displacement d with max(|d_x|, |d_y|) below the cell's
+        // distance to the nearest blocker stays in the box between x - d and
+        // x, which holds no blocker: it comes straight from x - d
+        const int clear = mine ? (int)b.cdist[(long long)y * g.nx + x] : 0;
+        const bool perx = g.bc[0] == LELBM_BC_PERIODIC, pery = D == 2 && g.bc[2] == LELBM_BC_PERIODIC;
+        const auto candidates = [&](const auto &blocked) {
+            if (fluid) {
+                for (int dy = D == 2 ? M : 0; dy >= (D == 2 ? -M : 0); dy--) {
+                    for (int dxb = M; dxb >= -M; dxb -= GU) {
+                        long long sv[GU];
+                        int sg[GU], spx[GU], spy[GU];
+#pragma unroll
+                        for (int u = 0; u < GU; u++) {
+                            const int dx = dxb - u;
+                            sv[u] = -1;
+                            if (dx < -M) continue;
+                            if (max(abs(dx), abs(dy)) < clear) {
+                                int ox = x - dx, oy = y - dy;
+                                if (perx) ox = wrap_coord(ox, g.nx);
+                                if (pery) oy = wrap_coord(oy, g.ny);
+                                if (ox >= -g.wl && ox < g.nx + g.wr && oy >= -g.wb && oy < g.ny + g.wt) {
+                                    spx[u] = ox + g.wl;
+                                    spy[u] = oy + g.wb;
+                                    sv[u] = (long long)spy[u] * g.sxn + spx[u];
+                                    sg[u] = 0;
+                                }
+                            } else {
+                                int ox, oy, sgx, sgy;
+                                if (walk_back<D>(g, blocked, x, y, -dx, -dy, ox, oy, sgx, sgy)) {
+                                    spx[u] = ox + g.wl;
+                                    spy[u] = oy + g.wb;
+                                    sv[u] = (long long)spy[u] * g.sxn + spx[u];
+                                    sg[u] = (sgx < 0 ? 1 : 0) | (sgy < 0 ? 2 : 0);
+                                }
+                            }
+                        }
+                        int rn[GU];
+                        double ux[GU], uy[GU];
+#pragma unroll
+                        for (int u = 0; u < GU; u++) {
+                            rn[u] = -1;
+                            if (sv[u] >= 0) {
+                                rn[u] = b.desc_rn[sv[u]];
+                                ux[u] = b.desc_u[sv[u]];
+                                uy[u] = D == 2 ? b.desc_u[g.ns + sv[u]] : 0.0;
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < GU; u++) {
+                            if (rn[u] < 0) continue;
+                            const int dx = dxb - u;
+                            const int fx = sg[u] & 1, fy = sg[u] >> 1;
+                            const int cx = fx ? -dx : dx, cy = fy ? -dy : dy;   // the source's own displacement
+                            const double rr = (rn[u] & 0xffff) + 0.5;
+                            const bool in = D == 2 ? in_disk2((double)cx, (double)cy, ux[u], uy[u], rr)
+                                                   : in_disk1((double)cx, ux[u], rr);
+                            if (!in) continue;
+                            int st, loc;
+                            tile_of<D>(g, spx[u], spy[u], st, loc);
+                            const TileInfo ti = b.tiles[st];
+                            const long long recsz = ti.fmt ? NM : 2;
+                            const long long slot = (long long)(cy - ti.oy) * ti.wx + (cx - ti.ox);
+                            const T *P = SCR + ti.base + (slot * TILE_N + loc) * recsz;
+                            hits++;
+                            deposit_record<T, D>(acc, P, ti.fmt, dx, dy, fx, fy);
+                        }
+                    }
+                }
+            }
+        };
+        if (staged_map) candidates(blocked_lds);
+        else candidates(blocked_glb);
+        if (mine) {
+            long long o = (long long)(y + g.wb) * g.sxn + (x + g.wl);
+#pragma unroll
+            for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = (T)acc[k];
+        }
+    }
+    __shared__ unsigned long long s_hits[4];
+    unsigned long long hl = (unsigned long long)hits;
+    for (int off = 32; off > 0; off >>= 1) hl += __shfl_xor(hl, off);
+    if ((threadIdx.x & 63) == 0) s_hits[threadIdx.x >> 6] = hl;
+    __syncthreads();
+    if (threadIdx.x == 0) b.gpart[nd + blockIdx.x] = s_hits[0] + s_hits[1] + s_hits[2] + s_hits[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -2243,6 +2373,11 @@ static void gather_launch(const Geom &g, void *mom_out, Buffers &b, int gcap, hi
     for (int f = 0; f < 2 * D; f++) walls = walls || g.bc[f] == LELBM_BC_SLIPWALL;
     if (walls) hipLaunchKernelGGL((k_gather<T, D, true>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap);
     else hipLaunchKernelGGL((k_gather<T, D, false>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap);
+    if (b.tdist) {
+        // the blocker map of a wavefront: the quarter of the same LDS size
+        const int mapb = (int)(lds / 4);
+        hipLaunchKernelGGL((k_gather_near<T, D>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, mapb);
+    }
 }
 
 hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, int gcap, hipStream_t s) {
@@ -2253,7 +2388,8 @@ hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, in
         if (g.dim == 1) gather_launch<double, 1>(g, mom_out, b, gcap, s);
         else gather_launch<double, 2>(g, mom_out, b, gcap, s);
     }
-    const int nd = gather_blocks_x(g) * gather_blocks_y(g);
+    // partials of k_gather, then of k_gather_near (when it runs)
+    const int nd = gather_blocks_x(g) * gather_blocks_y(g) * (b.tdist ? 2 : 1);
     const int nb = (nd + 255) / 256 < 256 ? (nd + 255) / 256 : 256;
     hipLaunchKernelGGL(k_sum_partials, dim3(nb), dim3(256), 0, s, (const unsigned long long *)b.gpart, nd,
                        &b.stats->arrivals);
