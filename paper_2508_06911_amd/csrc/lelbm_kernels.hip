@@ -275,9 +275,10 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
     }
     red[0][l] = lox; red[1][l] = loy; red[2][l] = hix; red[3][l] = hiy; redf[l] = refined;
     red[4][l] = uxl; red[5][l] = uxh; red[6][l] = uyl; red[7][l] = uyh; red[8][l] = rmx;
+    __shared__ int s_reach[4];
     if (b.maxreach) {
         for (int off = 32; off > 0; off >>= 1) reach = max(reach, __shfl_xor(reach, off));
-        if ((l & 63) == 0 && reach > 0) atomicMax(b.maxreach, reach);
+        if ((l & 63) == 0) s_reach[l >> 6] = reach;
     }
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -294,6 +295,12 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
             redf[l] |= redf[l + off];
         }
         __syncthreads();
+    }
+    if (l == 0 && b.maxreach) {
+        // one atomic per workgroup, and only while it raises the maximum
+        // (same-address atomics from every wavefront serialise)
+        const int r = max(max(s_reach[0], s_reach[1]), max(s_reach[2], s_reach[3]));
+        if (r > __hip_atomic_load(b.maxreach, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(b.maxreach, r);
     }
     if (l == 0) {
         TileInfo ti;
