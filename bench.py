@@ -107,6 +107,8 @@ def parse():
     ap.add_argument("--c4-warmup", type=int, default=200)
     ap.add_argument("--c4-steps", type=int, default=3)
     ap.add_argument("--no-c4", action="store_true", help="skip the 8192x4096 Mach-10 channel context run")
+    ap.add_argument("--channel-only", action="store_true",
+                    help="run only the 4096x2048 channel context (for kernel traces of that workload)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -390,6 +392,9 @@ def main():
     import paper_2508_06911_amd as lb
 
     torch.cuda.set_device(0)
+    if a.channel_only:
+        print(json.dumps({"channel_context": channel_context(lb, li, torch, a)}), flush=True)
+        return
     runs = [r for r in a.runs.split(",") if r]
     for r in runs:
         if r not in RUNS:
