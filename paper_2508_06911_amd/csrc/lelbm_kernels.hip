@@ -1653,7 +1653,12 @@ __device__ inline bool walk_back(const Geom &g, const Blocked &blocked, int x, i
     // order depends only on |v|, the same for all lanes of a call); a walk
     // that leaves the padded domain is finished and then rejected.
     const int ax = abs(vx), ay = abs(vy);
-    int sx = vx < 0 ? -1 : 1, sy = vy < 0 ? -1 : 1, kx = 0, ky = 0;
+    // the crossing counters live in vector registers: the walk's selects then
+    // run on the SIMDs instead of the CU's one scalar unit
+    int kx, ky;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(kx));
+    asm volatile("v_mov_b32 %0, 0" : "=v"(ky));
+    int sx = vx < 0 ? -1 : 1, sy = vy < 0 ? -1 : 1;
     const bool perx = g.bc[0] == LELBM_BC_PERIODIC, pery = D == 2 && g.bc[2] == LELBM_BC_PERIODIC;
     bool out = false;
     for (int k = 0; k < ax + ay; k++) {
