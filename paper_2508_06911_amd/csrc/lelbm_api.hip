@@ -189,7 +189,7 @@ static void free_ctx(lelbm_ctx *c) {
     Buffers &b = c->b;
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.spans, b.tiles,
                     b.dwin, b.scratch, b.flags, b.stats, b.partial, b.harvest_n,
-                    c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, (void *)b.cdist, b.lamprev,
+                    c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, (void *)b.cdist, (void *)b.tdist_s, b.lamprev,
                     b.bpart, b.gpart};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -269,11 +269,13 @@ static int setup_blockers(lelbm_ctx *c, const unsigned char *mask) {
         if (!stable) std::fill(d.begin(), d.end(), 0);
     }
     const int nd = g.dtx * g.dty;
-    std::vector<int> td((size_t)nd, INF);
+    std::vector<int> td((size_t)nd, INF), tds((size_t)nd, INF);
     std::vector<unsigned short> cd((size_t)n);
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
             int v = d[(long long)y * nx + x];
+            int &ts = tds[(size_t)(y / g.ty) * g.dtx + x / g.tx];
+            ts = std::min(ts, v);
             if (g.bc[0] == LELBM_BC_SLIPWALL) v = std::min(v, x + 1);
             if (g.bc[1] == LELBM_BC_SLIPWALL) v = std::min(v, nx - x);
             if (g.dim == 2 && g.bc[2] == LELBM_BC_SLIPWALL) v = std::min(v, y + 1);
@@ -283,7 +285,7 @@ static int setup_blockers(lelbm_ctx *c, const unsigned char *mask) {
             cd[(size_t)y * nx + x] = (unsigned short)std::min(v, 65535);
         }
     Buffers &b = c->b;
-    int *dt = nullptr, *mr = nullptr;
+    int *dt = nullptr, *mr = nullptr, *dts = nullptr;
     unsigned short *cdv = nullptr;
     unsigned char *sm = nullptr;
     if (hipMalloc((void **)&dt, (size_t)nd * sizeof(int)) != hipSuccess) return LELBM_ENOMEM;
@@ -292,9 +294,13 @@ static int setup_blockers(lelbm_ctx *c, const unsigned char *mask) {
     b.maxreach = mr;
     if (hipMalloc((void **)&cdv, (size_t)n * sizeof(unsigned short)) != hipSuccess) return LELBM_ENOMEM;
     b.cdist = cdv;
+    if (hipMalloc((void **)&dts, (size_t)nd * sizeof(int)) != hipSuccess) return LELBM_ENOMEM;
+    b.tdist_s = dts;
     int r = stage_h2d(c->stage, c->stream, dt, td.data(), (size_t)nd * sizeof(int));
     if (r != LELBM_OK) return r;
     r = stage_h2d(c->stage, c->stream, cdv, cd.data(), (size_t)n * sizeof(unsigned short));
+    if (r != LELBM_OK) return r;
+    r = stage_h2d(c->stage, c->stream, dts, tds.data(), (size_t)nd * sizeof(int));
     if (r != LELBM_OK) return r;
     c->persistent_bytes += n * (long long)sizeof(unsigned short);
     if (mask) {
@@ -304,7 +310,7 @@ static int setup_blockers(lelbm_ctx *c, const unsigned char *mask) {
         if (r != LELBM_OK) return r;
         c->persistent_bytes += n;
     }
-    c->persistent_bytes += (long long)nd * sizeof(int);
+    c->persistent_bytes += (long long)2 * nd * sizeof(int);
     return LELBM_OK;
 }
 

@@ -144,6 +144,7 @@ struct Buffers {
                                    // blocker (solid cell or the cell beyond a slip wall); NULL = none
     int *maxreach;                 // max over sources of max(|round(u)|) + R + 1 (this step)
     const unsigned short *cdist;   // [ny][nx] the same distance per cell (capped at 65535)
+    const int *tdist_s;            // [dtx*dty] Chebyshev distance from the tile to the nearest solid cell
 };
 
 // Kernel launchers (defined in lelbm_kernels.hip).  All enqueue on `s`.

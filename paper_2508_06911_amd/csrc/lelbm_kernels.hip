@@ -1683,6 +1683,19 @@ __device__ inline bool walk_back(const Geom &g, const Blocked &blocked, int x, i
     return true;
 }
 
+// Distance from destination tile t to the blockers its arrivals must be
+// traced around: solid cells always; slip walls only where one path could
+// reflect off both walls of an axis (the domain at most 2M + 2 cells across).
+// Elsewhere a path meets at most one wall per axis, and the straight gather's
+// mirror images across the walls are exact (each reflection folds one
+// coordinate, independently of the other axis).
+__device__ inline int walk_distance(const Geom &g, const Buffers &b, int t, int M) {
+    const bool wx = g.bc[0] == LELBM_BC_SLIPWALL || g.bc[1] == LELBM_BC_SLIPWALL;
+    const bool wy = g.dim == 2 && (g.bc[2] == LELBM_BC_SLIPWALL || g.bc[3] == LELBM_BC_SLIPWALL);
+    const bool narrow = (wx && g.nx <= 2 * M + 2) || (wy && g.ny <= 2 * M + 2);
+    return narrow ? b.tdist[t] : b.tdist_s[t];
+}
+
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
@@ -1761,10 +1774,10 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     const int own = lx / TX;
     DWin w = b.dwin[tl + min(own, ntb - 1)];
     if (own >= ntb) { w.lox = w.loy = 1 << 29; w.hix = w.hiy = -(1 << 29); }
-    const bool near = own < ntb && b.tdist && b.tdist[tl + own] <= M + 1;
+    const bool near = own < ntb && b.tdist && walk_distance(g, b, tl + own, M) <= M + 1;
     int ulox = 1 << 29, uhix = -(1 << 29), uloy = 1 << 29, uhiy = -(1 << 29);
     for (int k = 0; k < ntb; k++) {
-        if (b.tdist && b.tdist[tl + k] <= M + 1) continue;
+        if (b.tdist && walk_distance(g, b, tl + k, M) <= M + 1) continue;
         const DWin wk = b.dwin[tl + k];
         ulox = min(ulox, wk.lox); uhix = max(uhix, wk.hix);
         uloy = min(uloy, wk.loy); uhiy = max(uhiy, wk.hiy);
@@ -1987,7 +2000,7 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers
     const int ntb = min(NTB, g.dtx - x0 / TX);
     const int own = lx / TX;
     const int M = *b.maxreach;
-    const bool near = !b.flags->err && own < ntb && b.tdist[tl + own] <= M + 1;
+    const bool near = !b.flags->err && own < ntb && walk_distance(g, b, tl + own, M) <= M + 1;
     const T *SCR = (const T *)b.scratch;
     int hits = 0;
     if (near) {
