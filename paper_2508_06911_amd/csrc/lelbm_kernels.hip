@@ -1661,6 +1661,7 @@ __device__ inline bool walk_back(const Geom &g, const Blocked &blocked, int x, i
     int sx = vx < 0 ? -1 : 1, sy = vy < 0 ? -1 : 1;
     const bool perx = g.bc[0] == LELBM_BC_PERIODIC, pery = D == 2 && g.bc[2] == LELBM_BC_PERIODIC;
     bool out = false;
+#pragma unroll 4
     for (int k = 0; k < ax + ay; k++) {
         const bool takey =
             kx >= ax || (ky < ay && __mul24(2 * ky + 1, ax) <= __mul24(2 * kx + 1, ay));  // < 2^31 for |v| < 2^15
@@ -1974,8 +1975,9 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
 // k_gather; wavefronts of other tiles return at once.  The walks probe the
 // blockers of the cells within M + 1 of the wavefront's 16 x 4 cells (64 x 1
 // in 1D): staged once as one byte per cell in the wavefront's quarter of the
-// LDS (mapb bytes), else read from global memory.  Candidates go in batches
-// of GU so that the descriptor loads of a batch are in flight together.
+// LDS (mapb bytes) with their summed-area table, else read from global memory.
+// Candidates go in batches of GU so that the descriptor loads of a batch are
+// in flight together.
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers b, int mapb) {
     constexpr int NM = Basis<D>::NMOM;
@@ -2008,16 +2010,52 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers
         const int xw = x0 + (lx & ~(WX - 1)), yw = y0 + (ly & ~(WY - 1));
         const int bx0 = xw - M - 1, by0 = D == 2 ? yw - M - 1 : 0;
         const int bw = WX + 2 * M + 2, bh = D == 2 ? WY + 2 * M + 2 : 1;
-        const bool staged_map = (long long)bw * bh <= mapb;
-        unsigned char *bmap = (unsigned char *)g_lds + (size_t)(threadIdx.x >> 6) * mapb;
-        if (staged_map) {
-            for (int i = threadIdx.x & 63; i < bw * bh; i += 64)
-                bmap[i] = blocked_wrapped<D>(g, b.solid, bx0 + i % bw, by0 + i / bw) ? 1 : 0;
+        // blocker bits of the region (one 32-bit word per 32 cells of a row),
+        // then their summed-area table (u16, (bh + 1) x (bw + 1)): a
+        // displacement whose box between x - d and x holds no blocker has a
+        // straight path, with no walk
+        const int wpr = (bw + 31) >> 5, satw = bw + 1;
+        const bool staged_map = 4LL * wpr * bh + 2LL * satw * (bh + 1) <= mapb;
+        unsigned *bits = (unsigned *)((unsigned char *)g_lds + (size_t)(threadIdx.x >> 6) * mapb);
+        unsigned short *sat = (unsigned short *)(bits + wpr * bh);
+        const int lane = threadIdx.x & 63;
+        const auto wave_sync = [] {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        if (staged_map) {
+            for (int i = lane; i < wpr * bh; i += 64) bits[i] = 0u;
+            wave_sync();
+            for (int i = lane; i < bw * bh; i += 64) {
+                const int cx = i % bw, cy = i / bw;
+                if (blocked_wrapped<D>(g, b.solid, bx0 + cx, by0 + cy)) atomicOr(&bits[cy * wpr + (cx >> 5)], 1u << (cx & 31));
+            }
+            wave_sync();
+            for (int j = lane; j <= bh; j += 64) {
+                int run = 0;
+                sat[j * satw] = 0;
+                for (int i = 0; i < bw; i++) {
+                    run += j > 0 ? (int)((bits[(j - 1) * wpr + (i >> 5)] >> (i & 31)) & 1u) : 0;
+                    sat[j * satw + i + 1] = (unsigned short)run;
+                }
+            }
+            wave_sync();
+            for (int i = lane; i <= bw; i += 64)
+                for (int j = 1; j <= bh; j++) sat[j * satw + i] = (unsigned short)(sat[j * satw + i] + sat[(j - 1) * satw + i]);
+            wave_sync();
         }
-        const auto blocked_lds = [&](int px, int py) { return bmap[(py - by0) * bw + (px - bx0)] != 0; };
+        const int rx = x - bx0, ry = y - by0;    // the lane's cell in the region
+        const auto box_clear = [&](int dx, int dy) {
+            const int xa = rx - dx, ya = ry - dy;
+            const int xl = min(rx, xa), xh = max(rx, xa) + 1, yl = min(ry, ya), yh = max(ry, ya) + 1;
+            return (int)sat[yh * satw + xh] - (int)sat[yl * satw + xh] - (int)sat[yh * satw + xl] +
+                       (int)sat[yl * satw + xl] == 0;
+        };
+        const auto blocked_lds = [&](int px, int py) {
+            const int cx = px - bx0;
+            return ((bits[(py - by0) * wpr + (cx >> 5)] >> (cx & 31)) & 1u) != 0;
+        };
         const auto blocked_glb = [&](int px, int py) { return blocked_wrapped<D>(g, b.solid, px, py); };
         T acc[NM];
 #pragma unroll
@@ -2039,7 +2077,7 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers
                             const int dx = dxb - u;
                             sv[u] = -1;
                             if (dx < -M) continue;
-                            if (max(abs(dx), abs(dy)) < clear) {
+                            if (max(abs(dx), abs(dy)) < clear || (staged_map && box_clear(dx, dy))) {
                                 int ox = x - dx, oy = y - dy;
                                 if (perx) ox = wrap_coord(ox, g.nx);
                                 if (pery) oy = wrap_coord(oy, g.ny);
@@ -2399,9 +2437,11 @@ static void gather_launch(const Geom &g, void *mom_out, Buffers &b, int gcap, hi
     if (walls) hipLaunchKernelGGL((k_gather<T, D, true>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap);
     else hipLaunchKernelGGL((k_gather<T, D, false>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap);
     if (b.tdist) {
-        // the blocker map of a wavefront: the quarter of the same LDS size
-        const int mapb = (int)(lds / 4);
-        hipLaunchKernelGGL((k_gather_near<T, D>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, mapb);
+        // 8 KB of LDS per wavefront for its blocker bits and summed-area table
+        // (five workgroups per CU)
+        const size_t lds_near = 32768;
+        hipLaunchKernelGGL((k_gather_near<T, D>), dim3(nt), dim3(256), lds_near, s, g, (T *)mom_out, b,
+                           (int)(lds_near / 4));
     }
 }
 
