@@ -189,7 +189,7 @@ static void free_ctx(lelbm_ctx *c) {
     Buffers &b = c->b;
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.spans, b.tiles,
                     b.dwin, b.scratch, b.flags, b.stats, b.partial, b.harvest_n,
-                    c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, (void *)b.cdist, (void *)b.tdist_s, b.lamprev,
+                    c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, (void *)b.cdist, (void *)b.tdist_s, b.wcache, (void *)b.wslot, b.wbuilt, b.lamprev,
                     b.bpart, b.gpart};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -302,6 +302,39 @@ static int setup_blockers(lelbm_ctx *c, const unsigned char *mask) {
     if (r != LELBM_OK) return r;
     r = stage_h2d(c->stage, c->stream, dts, tds.data(), (size_t)nd * sizeof(int));
     if (r != LELBM_OK) return r;
+    // cache of backward-walk results for the tiles that can need walks at a
+    // reach up to WCACHE_M (fluid tiles near a solid; near a slip wall only
+    // where the domain is narrow enough for a double reflection); without
+    // the memory for it the walks run every step
+    {
+        const bool wx = g.bc[0] == LELBM_BC_SLIPWALL || g.bc[1] == LELBM_BC_SLIPWALL;
+        const bool wy = g.dim == 2 && (g.bc[2] == LELBM_BC_SLIPWALL || g.bc[3] == LELBM_BC_SLIPWALL);
+        const bool narrow = (wx && nx <= 2 * WCACHE_M + 2) || (wy && ny <= 2 * WCACHE_M + 2);
+        std::vector<char> fluid_tile((size_t)nd, 0);
+        for (int y = 0; y < ny; y++)
+            for (int x = 0; x < nx; x++)
+                if (!mask || !mask[(long long)y * nx + x]) fluid_tile[(size_t)(y / g.ty) * g.dtx + x / g.tx] = 1;
+        std::vector<int> slot((size_t)nd, -1);
+        int nslots = 0;
+        for (int t = 0; t < nd; t++)
+            if (fluid_tile[t] && (narrow ? td[t] : tds[t]) <= WCACHE_M + 1) slot[t] = nslots++;
+        const size_t cbytes = (size_t)nslots * WCACHE_W * WCACHE_W * TILE_N * sizeof(unsigned short);
+        int *ws = nullptr, *wb = nullptr;
+        unsigned short *wc = nullptr;
+        if (nslots > 0 && hipMalloc((void **)&wc, cbytes) == hipSuccess) {
+            if (hipMalloc((void **)&ws, (size_t)nd * sizeof(int)) != hipSuccess ||
+                hipMalloc((void **)&wb, sizeof(int)) != hipSuccess)
+                return LELBM_ENOMEM;
+            b.wcache = wc;
+            b.wslot = ws;
+            b.wbuilt = wb;
+            if ((r = stage_h2d(c->stage, c->stream, ws, slot.data(), (size_t)nd * sizeof(int))) != LELBM_OK) return r;
+            if (hipMemsetAsync(wb, 0xff, sizeof(int), c->stream) != hipSuccess) return LELBM_EDEVICE;
+            c->persistent_bytes += (long long)cbytes + (long long)nd * sizeof(int);
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     c->persistent_bytes += n * (long long)sizeof(unsigned short);
     if (mask) {
         if (hipMalloc((void **)&sm, (size_t)n) != hipSuccess) return LELBM_ENOMEM;

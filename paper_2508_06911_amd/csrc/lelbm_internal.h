@@ -11,6 +11,8 @@ namespace lelbm {
 // Source cells are processed in tiles of TILE_N cells: 16 x 16 in 2D and
 // 256 x 1 in 1D.  One workgroup handles one tile in every per-cell kernel.
 constexpr int TILE_N = 256;
+constexpr int WCACHE_M = 31;              // largest reach whose walks are cached
+constexpr int WCACHE_W = 2 * WCACHE_M + 1;
 template <int D> constexpr int tile_x() { return D == 2 ? 16 : 256; }
 template <int D> constexpr int tile_y() { return D == 2 ? 16 : 1; }
 constexpr int MAX_REFINE = 3;       // supported stencil refinement levels
@@ -145,6 +147,12 @@ struct Buffers {
     int *maxreach;                 // max over sources of max(|round(u)|) + R + 1 (this step)
     const unsigned short *cdist;   // [ny][nx] the same distance per cell (capped at 65535)
     const int *tdist_s;            // [dtx*dty] Chebyshev distance from the tile to the nearest solid cell
+    // backward-walk results (the geometry is fixed, so a walk's result never
+    // changes): per cached destination tile, per displacement |d| <= WCACHE_M,
+    // per cell, the origin's offset and the path's flips
+    unsigned short *wcache;        // [slots][WCACHE_W^2][TILE_N], NULL = not cached
+    const int *wslot;              // [dtx*dty] cache slot of a destination tile, -1 = none
+    int *wbuilt;                   // largest reach the cache holds every near tile's walks for, -1 = none
 };
 
 // Kernel launchers (defined in lelbm_kernels.hip).  All enqueue on `s`.

@@ -1633,7 +1633,8 @@ __device__ inline bool is_blocked(const Geom &g, const unsigned char *solid, int
 // applied to each component, or false if it leaves the padded domain (no
 // source there).  The walk runs in unwrapped coordinates (each stays within
 // |v| of the landing cell, each probe within |v| + 1); blocked(x, y) wraps
-// periodic axes itself, and the origin is wrapped at the end.
+// periodic axes itself, and the origin is returned wrapped (ox, oy) and
+// unwrapped (ux, uy).
 __device__ inline int wrap_coord(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
@@ -1648,7 +1649,7 @@ __device__ inline bool blocked_wrapped(const Geom &g, const unsigned char *solid
 
 template <int D, typename Blocked>
 __device__ inline bool walk_back(const Geom &g, const Blocked &blocked, int x, int y, int vx, int vy, int &ox,
-                                 int &oy, int &sgx, int &sgy) {
+                                 int &oy, int &ux, int &uy, int &sgx, int &sgy) {
     // Every step is written with selects rather than branches (the crossing
     // order depends only on |v|, the same for all lanes of a call); a walk
     // that leaves the padded domain is finished and then rejected.
@@ -1676,6 +1677,8 @@ __device__ inline bool walk_back(const Geom &g, const Blocked &blocked, int x, i
         out = out || (!perx && (x < -g.wl || x >= g.nx + g.wr)) || (!pery && (y < -g.wb || y >= g.ny + g.wt));
     }
     if (out) return false;
+    ux = x;
+    uy = y;
     ox = perx ? wrap_coord(x, g.nx) : x;
     oy = pery ? wrap_coord(y, g.ny) : y;
     // the forward path ends with velocity -(sx, sy) and started with -(vx, vy) times its flips
@@ -2005,6 +2008,18 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers
     const bool near = !b.flags->err && own < ntb && walk_distance(g, b, tl + own, M) <= M + 1;
     const T *SCR = (const T *)b.scratch;
     int hits = 0;
+    // walk results of the tile, cached once the reach has been seen (entry of
+    // displacement d at ((d_y + WCACHE_M) * WCACHE_W + d_x + WCACHE_M) * TILE_N:
+    // 0xffff no source, else bits [0,6) and [6,12) the origin's offset + 32,
+    // 12 / 13 the flips of x / y)
+    const int slot = near && b.wcache ? b.wslot[tl + own] : -1;
+    const bool use_cache = slot >= 0 && M <= WCACHE_M;
+    const bool cached = use_cache && M <= *b.wbuilt;
+    unsigned short *wrow =
+        use_cache ? b.wcache + (size_t)slot * WCACHE_W * WCACHE_W * TILE_N + (x % TX) + (y % TY) * TX : nullptr;
+    const auto wentry = [&](int dx, int dy) -> unsigned short & {
+        return wrow[((dy + WCACHE_M) * WCACHE_W + dx + WCACHE_M) * TILE_N];
+    };
     if (near) {
         constexpr int WX = D == 2 ? 16 : 64, WY = D == 2 ? 4 : 1;
         const int xw = x0 + (lx & ~(WX - 1)), yw = y0 + (ly & ~(WY - 1));
@@ -2015,7 +2030,7 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers
         // displacement whose box between x - d and x holds no blocker has a
         // straight path, with no walk
         const int wpr = (bw + 31) >> 5, satw = bw + 1;
-        const bool staged_map = 4LL * wpr * bh + 2LL * satw * (bh + 1) <= mapb;
+        const bool staged_map = !cached && 4LL * wpr * bh + 2LL * satw * (bh + 1) <= mapb;
         unsigned *bits = (unsigned *)((unsigned char *)g_lds + (size_t)(threadIdx.x >> 6) * mapb);
         unsigned short *sat = (unsigned short *)(bits + wpr * bh);
         const int lane = threadIdx.x & 63;
@@ -2077,24 +2092,35 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers
                             const int dx = dxb - u;
                             sv[u] = -1;
                             if (dx < -M) continue;
-                            if (max(abs(dx), abs(dy)) < clear || (staged_map && box_clear(dx, dy))) {
-                                int ox = x - dx, oy = y - dy;
-                                if (perx) ox = wrap_coord(ox, g.nx);
-                                if (pery) oy = wrap_coord(oy, g.ny);
-                                if (ox >= -g.wl && ox < g.nx + g.wr && oy >= -g.wb && oy < g.ny + g.wt) {
-                                    spx[u] = ox + g.wl;
-                                    spy[u] = oy + g.wb;
-                                    sv[u] = (long long)spy[u] * g.sxn + spx[u];
-                                    sg[u] = 0;
-                                }
+                            int ux, uy, fl;           // unwrapped origin, flips
+                            bool ok;
+                            if (cached) {
+                                const unsigned e = wentry(dx, dy);
+                                ok = e != 0xffffu;
+                                ux = x + (int)(e & 63u) - 32;
+                                uy = y + (int)((e >> 6) & 63u) - 32;
+                                fl = (int)(e >> 12) & 3;
+                            } else if (max(abs(dx), abs(dy)) < clear || (staged_map && box_clear(dx, dy))) {
+                                ux = x - dx;
+                                uy = y - dy;
+                                fl = 0;
+                                ok = (perx || (ux >= -g.wl && ux < g.nx + g.wr)) &&
+                                     (pery || (uy >= -g.wb && uy < g.ny + g.wt));
                             } else {
                                 int ox, oy, sgx, sgy;
-                                if (walk_back<D>(g, blocked, x, y, -dx, -dy, ox, oy, sgx, sgy)) {
-                                    spx[u] = ox + g.wl;
-                                    spy[u] = oy + g.wb;
-                                    sv[u] = (long long)spy[u] * g.sxn + spx[u];
-                                    sg[u] = (sgx < 0 ? 1 : 0) | (sgy < 0 ? 2 : 0);
-                                }
+                                ok = walk_back<D>(g, blocked, x, y, -dx, -dy, ox, oy, ux, uy, sgx, sgy);
+                                fl = (sgx < 0 ? 1 : 0) | (sgy < 0 ? 2 : 0);
+                            }
+                            if (use_cache && !cached)
+                                wentry(dx, dy) = ok ? (unsigned short)((ux - x + 32) | ((uy - y + 32) << 6) | (fl << 12))
+                                                    : (unsigned short)0xffff;
+                            if (ok) {
+                                const int ox = perx ? wrap_coord(ux, g.nx) : ux;
+                                const int oy = pery ? wrap_coord(uy, g.ny) : uy;
+                                spx[u] = ox + g.wl;
+                                spy[u] = oy + g.wb;
+                                sv[u] = (long long)spy[u] * g.sxn + spx[u];
+                                sg[u] = fl;
                             }
                         }
                         int rn[GU];
@@ -2428,6 +2454,13 @@ hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const void *
     return hipGetLastError();
 }
 
+// After the backward-walk gather: a step that filled the walk cache (at a
+// reach above the one it held) makes that reach available to later steps.
+__global__ void k_mark_built(const Flags *fl, const int *maxreach, int *wbuilt) {
+    const int M = *maxreach;
+    if (!fl->err && M <= WCACHE_M && M > *wbuilt) *wbuilt = M;
+}
+
 template <typename T, int D>
 static void gather_launch(const Geom &g, void *mom_out, Buffers &b, int gcap, hipStream_t s) {
     const unsigned nt = (unsigned)(gather_blocks_x(g) * gather_blocks_y(g));
@@ -2442,6 +2475,7 @@ static void gather_launch(const Geom &g, void *mom_out, Buffers &b, int gcap, hi
         const size_t lds_near = 32768;
         hipLaunchKernelGGL((k_gather_near<T, D>), dim3(nt), dim3(256), lds_near, s, g, (T *)mom_out, b,
                            (int)(lds_near / 4));
+        if (b.wcache) hipLaunchKernelGGL(k_mark_built, dim3(1), dim3(1), 0, s, b.flags, b.maxreach, b.wbuilt);
     }
 }
 
