@@ -1977,10 +1977,11 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
 // the straight and the reflected arrivals alike.  Same workgroup blocks as
 // k_gather; wavefronts of other tiles return at once.  The walks probe the
 // blockers of the cells within M + 1 of the wavefront's 16 x 4 cells (64 x 1
-// in 1D): staged once as one byte per cell in the wavefront's quarter of the
-// LDS (mapb bytes) with their summed-area table, else read from global memory.
-// Candidates go in batches of GU so that the descriptor loads of a batch are
-// in flight together.
+// in 1D): staged once as one bit per cell in the wavefront's share of the LDS
+// (mapb bytes) with their summed-area table, else read from global memory.
+// Walk results go to the walk cache; a step at a reach the cache already holds
+// reads them instead.  Candidates go in batches of GU so that the descriptor
+// loads of a batch are in flight together.
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers b, int mapb) {
     constexpr int NM = Basis<D>::NMOM;
