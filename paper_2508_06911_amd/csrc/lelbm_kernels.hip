@@ -2149,8 +2149,8 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers
                             tile_of<D>(g, spx[u], spy[u], st, loc);
                             const TileInfo ti = b.tiles[st];
                             const long long recsz = ti.fmt ? NM : 2;
-                            const long long slot = (long long)(cy - ti.oy) * ti.wx + (cx - ti.ox);
-                            const T *P = SCR + ti.base + (slot * TILE_N + loc) * recsz;
+                            const long long sl = (long long)(cy - ti.oy) * ti.wx + (cx - ti.ox);
+                            const T *P = SCR + ti.base + (sl * TILE_N + loc) * recsz;
                             hits++;
                             deposit_record<T, D>(acc, P, ti.fmt, dx, dy, fx, fy);
                         }
