@@ -321,7 +321,11 @@ static int setup_blockers(lelbm_ctx *c, const unsigned char *mask) {
         const size_t cbytes = (size_t)nslots * WCACHE_W * WCACHE_W * TILE_N * sizeof(unsigned short);
         int *ws = nullptr, *wb = nullptr;
         unsigned short *wc = nullptr;
-        if (nslots > 0 && hipMalloc((void **)&wc, cbytes) == hipSuccess) {
+        // at most an eighth of the free device memory: the record scratch
+        // grows with the temperature and takes precedence
+        size_t mfree = 0, mtotal = 0;
+        const bool room = hipMemGetInfo(&mfree, &mtotal) == hipSuccess && cbytes <= mfree / 8;
+        if (nslots > 0 && room && hipMalloc((void **)&wc, cbytes) == hipSuccess) {
             if (hipMalloc((void **)&ws, (size_t)nd * sizeof(int)) != hipSuccess ||
                 hipMalloc((void **)&wb, sizeof(int)) != hipSuccess)
                 return LELBM_ENOMEM;
