@@ -2082,17 +2082,49 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers
         // x, which holds no blocker: it comes straight from x - d
         const int clear = mine ? (int)b.cdist[(long long)y * g.nx + x] : 0;
         const bool perx = g.bc[0] == LELBM_BC_PERIODIC, pery = D == 2 && g.bc[2] == LELBM_BC_PERIODIC;
+        // With the walks cached, only displacements some source of the region
+        // can have are tried: a source's own displacement lies in its tile's
+        // slot box, and the landing displacement has the same magnitudes.
+        // (A step that fills the cache tries every |d| <= M.)
+        int mx = M, my = D == 2 ? M : 0;
+        if (cached) {
+            int ax[2], bx[2], ay[2], by[2], cnx, cny;
+            if (perx) periodic_or_clip(bx0, bx0 + bw - 1, g.nx, true, ax, bx, &cnx);
+            else { ax[0] = max(bx0, -g.wl); bx[0] = min(bx0 + bw - 1, g.nx + g.wr - 1); cnx = ax[0] <= bx[0]; }
+            if (D == 2 && pery) periodic_or_clip(by0, by0 + bh - 1, g.ny, true, ay, by, &cny);
+            else if (D == 2) { ay[0] = max(by0, -g.wb); by[0] = min(by0 + bh - 1, g.ny + g.wt - 1); cny = ay[0] <= by[0]; }
+            else { ay[0] = by[0] = 0; cny = 1; }
+            int bxm = 0, bym = 0;
+            for (int i = 0; i < cnx; i++)
+                for (int j = 0; j < cny; j++) {
+                    const int t0x = (ax[i] + g.wl) / TX, t1x = (bx[i] + g.wl) / TX;
+                    const int t0y = (ay[j] + g.wb) / TY, t1y = (by[j] + g.wb) / TY;
+                    const int ntl = (t1x - t0x + 1) * (t1y - t0y + 1);
+                    for (int k = lane; k < ntl; k += 64) {
+                        const TileInfo ti = b.tiles[(t0y + k / (t1x - t0x + 1)) * g.ntx + t0x + k % (t1x - t0x + 1)];
+                        if (ti.wx <= 0) continue;          // no emitting cell
+                        bxm = max(bxm, max(abs(ti.ox), abs(ti.ox + ti.wx - 1)));
+                        bym = max(bym, max(abs(ti.oy), abs(ti.oy + ti.wy - 1)));
+                    }
+                }
+            for (int off = 32; off > 0; off >>= 1) {
+                bxm = max(bxm, __shfl_xor(bxm, off));
+                bym = max(bym, __shfl_xor(bym, off));
+            }
+            mx = min(mx, bxm);
+            my = min(my, bym);
+        }
         const auto candidates = [&](const auto &blocked) {
             if (fluid) {
-                for (int dy = D == 2 ? M : 0; dy >= (D == 2 ? -M : 0); dy--) {
-                    for (int dxb = M; dxb >= -M; dxb -= GU) {
+                for (int dy = my; dy >= -my; dy--) {
+                    for (int dxb = mx; dxb >= -mx; dxb -= GU) {
                         long long sv[GU];
                         int sg[GU], spx[GU], spy[GU];
 #pragma unroll
                         for (int u = 0; u < GU; u++) {
                             const int dx = dxb - u;
                             sv[u] = -1;
-                            if (dx < -M) continue;
+                            if (dx < -mx) continue;
                             int ux, uy, fl;           // unwrapped origin, flips
                             bool ok;
                             if (cached) {
