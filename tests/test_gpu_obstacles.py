@@ -60,6 +60,20 @@ def test_narrow_slip_channel_reflects_twice():
     assert err < 1e-10
 
 
+def test_narrow_1d_slip_box_traces_paths():
+    """A 1D box between two slip walls, narrower than twice the stencil
+    reach: every tile traces its paths back (the 1D backward-walk gather and
+    its cache, filled at the first step and read at the later ones)."""
+    _case("1d slip box 12 cells, 40 steps")
+    cfg, prim = li.riemann1d(2, n=12)
+    cfg["bc"] = ["slipwall", "slipwall", "periodic", "periodic"]
+    a, _ = run_gpu(cfg, prim, 40)
+    b, _ = run_oracle(cfg, prim, 40)
+    err = rel_linf(a, b)
+    print("rel_linf", err)
+    assert err < 1e-10
+
+
 def test_gas_at_rest_around_obstacles_stays_at_rest():
     _case("rest state with obstacles 64x48")
     cfg, _ = li.hotbox(0.8, n=64, ny=48)
