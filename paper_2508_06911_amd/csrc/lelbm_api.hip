@@ -190,7 +190,7 @@ static void free_ctx(lelbm_ctx *c) {
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.spans, b.tiles,
                     b.dwin, b.scratch, b.flags, b.stats, b.partial, b.harvest_n,
                     c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, (void *)b.cdist, (void *)b.tdist_s, b.wcache, (void *)b.wslot, b.wbuilt, b.lamprev,
-                    b.bpart, b.gpart};
+                    b.bpart, b.gpart, b.order};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (c->ev[0]) (void)hipEventDestroy(c->ev[0]);
@@ -431,6 +431,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ok = ok && hipMalloc((void **)&b.partial, (size_t)(num_sum_blocks(g) + 1) * 4 * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.harvest_n, sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.bpart, (size_t)nt * sizeof(DevStats)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.order, (size_t)nt * sizeof(int)) == hipSuccess;
     // arrival partials of the straight gather and of the backward-walk gather
     ok = ok && hipMalloc((void **)&b.gpart, (size_t)2 * gather_blocks_x(g) * gather_blocks_y(g) *
                                                 sizeof(unsigned long long)) == hipSuccess;

@@ -132,6 +132,7 @@ struct Buffers {
     const float *mlp_p;            // FP32 parameters (biases read from here)
     const float *mlp_n;            // standardisation constants (64)
     DevStats *bpart;               // [ntx*nty] per-workgroup statistics of k_epr
+    int *order;                    // [ntx*nty] source tiles in the order k_epr takes them (k_scan)
     unsigned long long *gpart;     // [dtx*dty] per-workgroup arrival counts of k_gather
     double *lamprev;               // [16][ns] scaled correction beyond the linearised guess, last step
                                    // (NaN in row 0: none); allocated for LELBM_GUESS_PREV only

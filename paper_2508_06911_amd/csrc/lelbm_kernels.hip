@@ -346,7 +346,8 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
 // ---------------------------------------------------------------------------
 // exclusive scan of tile sizes (one workgroup)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_scan(int ntiles, TileInfo *tiles, Flags *fl, long long cap, int step) {
+__global__ void __launch_bounds__(1024) k_scan(int ntiles, TileInfo *tiles, Flags *fl, long long cap, int step,
+                                               int *order) {
     __shared__ long long sh[1024];
     __shared__ long long carry;
     if (fl->err) return;
@@ -372,6 +373,37 @@ __global__ void __launch_bounds__(1024) k_scan(int ntiles, TileInfo *tiles, Flag
         if (atomicCAS(&fl->err, 0, ERR_OVERFLOW) == 0) {
             fl->need = carry;
             fl->step = step;
+        }
+    }
+    // Order in which k_epr takes the tiles: the heaviest first (a tile's
+    // records measure its stencil work), so that the long ones do not start
+    // last and leave the CUs idle at the end.  Stable partition into tiles
+    // with at least twice the mean size, at least the mean, and the rest.
+    __shared__ int base;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    const long long total = carry;
+    for (int cls = 0; cls < 3; cls++) {
+        for (int c0 = 0; c0 < ntiles; c0 += 1024) {
+            const int i = c0 + threadIdx.x;
+            int in = 0;
+            if (i < ntiles) {
+                const long long v = tiles[i].size * (long long)ntiles;
+                const int c = v >= 2 * total ? 0 : (v >= total ? 1 : 2);
+                in = c == cls;
+            }
+            sh[threadIdx.x] = in;
+            __syncthreads();
+            for (int off = 1; off < 1024; off <<= 1) {
+                long long a = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+                __syncthreads();
+                sh[threadIdx.x] += a;
+                __syncthreads();
+            }
+            if (in) order[base + (int)sh[threadIdx.x] - 1] = i;
+            __syncthreads();
+            if (threadIdx.x == 1023) base += (int)sh[1023];
+            __syncthreads();
         }
     }
 }
@@ -1124,7 +1156,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
         if (threadIdx.x == 0) StatSum().store(b.bpart[blockIdx.x]);
         return;
     }
-    int t = blockIdx.x;
+    const int t = b.order[blockIdx.x];        // heaviest tiles first (k_scan)
     int tx0 = (t % g.ntx) * g.tx, ty0 = (t / g.ntx) * g.ty;
     int l = threadIdx.x;
     int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
@@ -2453,7 +2485,8 @@ hipError_t launch_prepare(const Geom &g, const Phys &ph, int mixed, const void *
 }
 
 hipError_t launch_scan(const Geom &g, Buffers &b, int step, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, g.ntx * g.nty, b.tiles, b.flags, b.scratch_cap, step);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, g.ntx * g.nty, b.tiles, b.flags, b.scratch_cap, step,
+                       b.order);
     return hipGetLastError();
 }
 
