@@ -12,6 +12,7 @@ namespace lelbm {
 // 256 x 1 in 1D.  One workgroup handles one tile in every per-cell kernel.
 constexpr int TILE_N = 256;
 constexpr int WCACHE_M = 31;              // largest reach whose walks are cached
+constexpr int EPR_ORDER_MAX_TILES = 32768; // above: k_epr takes the tiles in index order
 constexpr int WCACHE_W = 2 * WCACHE_M + 1;
 template <int D> constexpr int tile_x() { return D == 2 ? 16 : 256; }
 template <int D> constexpr int tile_y() { return D == 2 ? 16 : 1; }

@@ -348,63 +348,94 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_scan(int ntiles, TileInfo *tiles, Flags *fl, long long cap, int step,
                                                int *order) {
-    __shared__ long long sh[1024];
-    __shared__ long long carry;
+    // 16 wavefronts: scans within a wavefront by shuffles and ballots, across
+    // the wavefronts of a 1024-tile chunk through LDS
+    __shared__ long long s_wave[16];
+    __shared__ int s_cnt[16][3];
+    __shared__ long long s_carry;
+    __shared__ int s_class[3], s_run[3];
     if (fl->err) return;
-    if (threadIdx.x == 0) carry = 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
+    if (threadIdx.x < 3) s_class[threadIdx.x] = s_run[threadIdx.x] = 0;
     __syncthreads();
+    // record offsets: exclusive scan of the tile sizes
     for (int c0 = 0; c0 < ntiles; c0 += 1024) {
-        int i = c0 + threadIdx.x;
-        long long v = i < ntiles ? tiles[i].size : 0;
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            long long a = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += a;
-            __syncthreads();
+        const int i = c0 + threadIdx.x;
+        const long long v = i < ntiles ? tiles[i].size : 0;
+        long long incl = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const long long o = __shfl_up(incl, off);
+            if (lane >= off) incl += o;
         }
-        if (i < ntiles) tiles[i].base = carry + sh[threadIdx.x] - v;
+        if (lane == 63) s_wave[w] = incl;
         __syncthreads();
-        if (threadIdx.x == 1023) carry += sh[1023];
+        long long wbase = 0, ctot = 0;
+        for (int k = 0; k < 16; k++) {
+            const long long sk = s_wave[k];
+            wbase += k < w ? sk : 0;
+            ctot += sk;
+        }
+        if (i < ntiles) tiles[i].base = s_carry + wbase + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry += ctot;
         __syncthreads();
     }
-    if (threadIdx.x == 0 && carry > cap) {
+    const long long total = s_carry;
+    if (threadIdx.x == 0 && total > cap) {
         if (atomicCAS(&fl->err, 0, ERR_OVERFLOW) == 0) {
-            fl->need = carry;
+            fl->need = total;
             fl->step = step;
         }
     }
     // Order in which k_epr takes the tiles: the heaviest first (a tile's
     // records measure its stencil work), so that the long ones do not start
     // last and leave the CUs idle at the end.  Stable partition into tiles
-    // with at least twice the mean size, at least the mean, and the rest.
-    __shared__ int base;
-    if (threadIdx.x == 0) base = 0;
-    __syncthreads();
-    const long long total = carry;
-    for (int cls = 0; cls < 3; cls++) {
-        for (int c0 = 0; c0 < ntiles; c0 += 1024) {
-            const int i = c0 + threadIdx.x;
-            int in = 0;
-            if (i < ntiles) {
-                const long long v = tiles[i].size * (long long)ntiles;
-                const int c = v >= 2 * total ? 0 : (v >= total ? 1 : 2);
-                in = c == cls;
-            }
-            sh[threadIdx.x] = in;
-            __syncthreads();
-            for (int off = 1; off < 1024; off <<= 1) {
-                long long a = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-                __syncthreads();
-                sh[threadIdx.x] += a;
-                __syncthreads();
-            }
-            if (in) order[base + (int)sh[threadIdx.x] - 1] = i;
-            __syncthreads();
-            if (threadIdx.x == 1023) base += (int)sh[1023];
-            __syncthreads();
+    // with at least twice the mean size, at least the mean, and the rest:
+    // the class sizes first, then each tile's place.  Worth it only while a
+    // launch spans few rounds of resident workgroups: with many tiles the
+    // tail is short and the index order writes the records more locally
+    // (measured: 16K tiles -9 % k_epr time, 33K about even, 131K +4 %).
+    if (ntiles > EPR_ORDER_MAX_TILES) {
+        for (int i = threadIdx.x; i < ntiles; i += 1024) order[i] = i;
+        return;
+    }
+    const auto class_of = [&](int i) {
+        const long long v = tiles[i].size * (long long)ntiles;
+        return v >= 2 * total ? 0 : (v >= total ? 1 : 2);
+    };
+    for (int c0 = 0; c0 < ntiles; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const int c = i < ntiles ? class_of(i) : -1;
+        for (int k = 0; k < 3; k++) {
+            const unsigned long long m = __ballot(c == k);
+            if (lane == 0 && m) atomicAdd(&s_class[k], __popcll(m));
         }
+    }
+    __syncthreads();
+    const int cbase[3] = {0, s_class[0], s_class[0] + s_class[1]};
+    for (int c0 = 0; c0 < ntiles; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const int c = i < ntiles ? class_of(i) : -1;
+        int rank = 0;
+        for (int k = 0; k < 3; k++) {
+            const unsigned long long m = __ballot(c == k);
+            if (c == k) rank = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) s_cnt[w][k] = __popcll(m);
+        }
+        __syncthreads();
+        if (c >= 0) {
+            int woff = 0;
+            for (int k = 0; k < w; k++) woff += s_cnt[k][c];
+            order[cbase[c] + s_run[c] + woff + rank] = i;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            int t = 0;
+            for (int k = 0; k < 16; k++) t += s_cnt[k][threadIdx.x];
+            s_run[threadIdx.x] += t;
+        }
+        __syncthreads();
     }
 }
 
