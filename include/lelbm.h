@@ -189,8 +189,10 @@ int lelbm_last_failure_detail(const lelbm_ctx *c, int *reason, int *species, dou
 int lelbm_set_timing(lelbm_ctx *c, int enable);
 int lelbm_kernel_times(const lelbm_ctx *c, double *ms, long *launches, int n);
 
-/* Device bytes held by the context: persistent state (moments, descriptors)
- * and transient population scratch. */
+/* Device bytes held by the context: persistent state (moments, descriptors;
+ * with solid cells or slip walls also the blocker distances and, when it fits
+ * in an eighth of the free device memory, the cache of backward-walk results
+ * around the solids) and the transient population scratch. */
 int lelbm_memory(const lelbm_ctx *c, long *persistent_bytes, long *scratch_bytes);
 
 const char *lelbm_strerror(int code);
