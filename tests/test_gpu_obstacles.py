@@ -47,6 +47,25 @@ def test_random_solids_in_a_periodic_box_parity(seed):
     assert err < 1e-10
 
 
+@pytest.mark.parametrize("seed,nx,ny,frac,walls", [(4, 33, 47, 0.12, True), (6, 29, 29, 0.20, False)])
+def test_dense_random_solids_parity(seed, nx, ny, frac, walls):
+    """Dense random solids (most tiles trace their paths, many paths reflect
+    several times), with and without slip walls, on tiles that are cut by
+    the domain edge; the walk cache is filled and then read."""
+    _case("dense random solids %dx%d %.2f walls=%s, 25 steps" % (nx, ny, frac, walls))
+    cfg, prim = li.smooth_periodic(seed, n=nx, ny=ny, RT=1.2)
+    if walls:
+        cfg["bc"] = ["periodic", "periodic", "slipwall", "slipwall"]
+    rng = np.random.default_rng(seed)
+    cfg["solid"] = (rng.random((ny, nx)) < frac).astype(np.uint8)
+    m = oracle_moments(cfg, prim)
+    a, _ = run_gpu(cfg, prim, 25, mom=m)
+    b, _ = run_oracle(cfg, prim, 25, mom=m)
+    err = _fluid_rel_linf(a, b, cfg["solid"])
+    print("rel_linf", err)
+    assert err < 1e-10
+
+
 def test_narrow_slip_channel_reflects_twice():
     """A channel narrower than the stencil reach: paths reflect off both
     walls."""
