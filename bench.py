@@ -109,6 +109,9 @@ def parse():
     ap.add_argument("--no-c4", action="store_true", help="skip the 8192x4096 Mach-10 channel context run")
     ap.add_argument("--channel-only", action="store_true",
                     help="run only the 4096x2048 channel context (for kernel traces of that workload)")
+    ap.add_argument("--c4-only", action="store_true",
+                    help="run only the 8192x4096 Mach-10 channel context, FP32 path with the learned guess "
+                         "(for kernel traces of that workload)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -394,6 +397,12 @@ def main():
     torch.cuda.set_device(0)
     if a.channel_only:
         print(json.dumps({"channel_context": channel_context(lb, li, torch, a)}), flush=True)
+        return
+    if a.c4_only:
+        mlp, _ = harvest_and_train(a, lb, li, torch)
+        out = c4_context(lb, li, torch, a, mlp)
+        mlp.close()
+        print(json.dumps({"c4_context": out}), flush=True)
         return
     runs = [r for r in a.runs.split(",") if r]
     for r in runs:
