@@ -21,7 +21,9 @@
  *   - Lagrangian acoustic stencil ...... Sec. II.C, Eqs. (IIC6, IIC9-11)
  *   - entropic reconstruction .......... Sec. II.D, Eqs. (IID7-11, IID13)
  *   - moment streaming ................. Sec. II.E, Eqs. (IIE3a-b)
- *   - fluid boundaries ................. Sec. III.A
+ *   - fluid boundaries ................. Sec. III.A (pads of width W; a pad
+ *                                        narrower than a stencil's reach toward
+ *                                        the interior is an error, Sec. III)
  *   - slip walls and solid cells ....... Sec. III.B (specular reflection of
  *                                        the population path at every face
  *                                        it would cross into a blocker)
@@ -721,6 +723,32 @@ void orc_walk(const orc_params *p, int x, int y, int dx, int dy, int *out)
     walk_path(p, x, y, dx, dy, &out[0], &out[1], &out[2], &out[3]);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Pad width, Sec. III (Fig. 5): the pads of an outflow or inflow face must   */
+/* hold every source whose populations can land in the interior.  The cells   */
+/* beyond a pad would be in the pad's own state (a zero-gradient copy of the  */
+/* same interior cell, or the inflow equilibrium), so if a pad cell's stencil */
+/* can reach farther toward the interior than the pad is wide, arrivals from  */
+/* outside the padded domain are missing.  Reading: the reach toward the      */
+/* interior is bounded by the stencil's box around the rounded velocity of    */
+/* Eq. (IIC6), [u] + R (every base point has |c - u| <= R + 1/2, so          */
+/* c <= [u] + R componentwise, and refined children land with their parent); */
+/* a pad of width W must have [u_n] + R <= W, u_n the velocity component     */
+/* toward the interior.  Returns 1 if source (sx, sy) breaks this.            */
+/* ------------------------------------------------------------------------ */
+static int pad_reach_exceeded(const orc_params *p, int sx, int sy, const double *u, double RT)
+{
+    int R = orc_las_radius(RT, p->n_conf, p->r_min);
+    int bx = (int)round_half_up(u[0]), by = p->dim == 2 ? (int)round_half_up(u[1]) : 0;
+    int wl = pad_w(p, 0), wr = pad_w(p, 1);
+    int wb = p->dim == 2 ? pad_w(p, 2) : 0, wt = p->dim == 2 ? pad_w(p, 3) : 0;
+    if (sx < 0 && bx + R > wl) return 1;
+    if (sx >= p->nx && R - bx > wr) return 1;
+    if (sy < 0 && by + R > wb) return 1;
+    if (sy >= p->ny && R - by > wt) return 1;
+    return 0;
+}
+
 int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
 {
     int D = p->dim, nx = p->nx, ny = p->ny;
@@ -774,11 +802,12 @@ int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
         for (long k = c0; k < c1; k++) {
             cell_out *o = &co[k - c0];
             if (o->status == 1) continue;   /* solid cell */
+            int sx = (int)(k % sxn) - wl, sy = (int)(k / sxn) - wb;
+            if (o->status == ORC_OK && pad_reach_exceeded(p, sx, sy, o->u, o->RT)) o->status = ORC_EREACH;
             if (o->status != ORC_OK) {
                 if (status == ORC_OK) { status = o->status; s.fail_cell = k; s.fail_code = o->status; }
                 continue;
             }
-            int sx = (int)(k % sxn) - wl, sy = (int)(k / sxn) - wb;
             s.cells++;
             s.it_sum_f += o->it_f; s.it_sum_g += o->it_g;
             if (o->it_f > s.it_max_f) s.it_max_f = o->it_f;

@@ -132,6 +132,16 @@ def test_noneq_central_moments_match_direct_sums(dim):
             assert np.isclose(out["hy"], (y * g).sum(), rtol=1e-10, atol=1e-12)
         # energy identity: trace of P equals -g0 (RT is defined with G0)
         assert np.isclose(out["Pxx"] + out["Pyy"], -out["g0"], rtol=1e-9, atol=1e-11)
+        # Knudsen number of Eq. (D2) from the same direct central sums: the
+        # larger of the second-order ratio (all D^2 stress components and g0)
+        # and the third-order ratio (heat fluxes of both species, RT^(3/2))
+        P = [[Pxx, (x * y * f).sum()], [(x * y * f).sum(), (y * y * f).sum() - rho * RT]]
+        Q = [Qx, ((x * x + y * y) * y * f).sum()]
+        h = [(x * g).sum(), (y * g).sum()]
+        g0 = g.sum() - rho * K * RT
+        A = (sum(abs(P[a][b]) for a in range(dim) for b in range(dim)) + abs(g0)) / (rho * (dim + K) * RT)
+        B = sum(abs(Q[a]) + abs(h[a]) for a in range(dim)) / (rho * (dim + K + 2) * RT ** 1.5)
+        assert np.isclose(out["kn"], max(A, B), rtol=1e-9)
 
 
 def test_targets_relaxation_and_splits():
@@ -182,6 +192,35 @@ def test_knudsen_limiter_branches(kn, expect):
     assert np.isclose(out["om_f"], w[0], rtol=1e-12)
     assert np.isclose(out["om_h"], w[1], rtol=1e-12)
     assert out["om_b"] == 1.0
+
+
+@pytest.mark.parametrize("kn,expect", [(0.005, "w"), (10 ** -1.5, "mid"), (0.2, "one")])
+@pytest.mark.parametrize("which", ["Qx", "hx", "Qy+hx"])
+def test_knudsen_heat_flux_ratio_branches(kn, expect, which):
+    """App. D, Eq. (D2), third-order ratio: an equilibrium cell whose only
+    non-equilibrium is a heat flux of the fluon (M_Dx raises Q_x one for one)
+    or of the phonon (G_x raises h_x one for one), or both on different axes
+    (the ratio sums their magnitudes), normalised by rho (D+K+2) RT^(3/2).
+    The limiter then takes the branch values of the text after Eq. (D3b)."""
+    cfg = dict(li.hotbox(1.0, n=4)[0])
+    cfg.update(omega_f=1.8, omega_b=1.2, omega_h=1.6, kn_limiter=1)
+    rho, RT, K = 0.7, 2.3, cfg["K"]
+    mom = oracle.moments_from_primitives(2, K, [rho], [0.4], [-0.3], [RT])[:, 0].copy()
+    total = kn * rho * (2 + K + 2) * RT ** 1.5
+    if which == "Qx":
+        mom[6] += total                     # M_Dx
+    elif which == "hx":
+        mom[9] -= total                     # G_x (sign does not matter)
+    else:
+        mom[7] += 0.25 * total              # M_Dy -> Q_y
+        mom[9] += 0.75 * total              # G_x -> h_x
+    out = oracle.collide(cfg, mom)
+    assert np.isclose(out["kn"], kn, rtol=1e-9)
+    assert abs(out["Pxx"]) < 1e-12 and abs(out["g0"]) < 1e-12      # second-order ratio is zero
+    w = {"w": (1.8, 1.2, 1.6), "mid": (1.4, 1.1, 1.3), "one": (1.0, 1.0, 1.0)}[expect]
+    assert np.isclose(out["om_f"], w[0], rtol=1e-12)
+    assert np.isclose(out["om_b"], w[1], rtol=1e-12)
+    assert np.isclose(out["om_h"], w[2], rtol=1e-12)
 
 
 # --------------------------------------------------------------------------
@@ -467,6 +506,92 @@ def test_failure_is_reported_not_clamped():
     assert st == oracle.EEPR
     assert done == 0
     assert stats["fail_cell"] == 5
+
+
+def _inflow_riemann(N, L, R, frac=0.8):
+    """The whole tube starts in state R; the inflow face on the left holds the
+    equilibrium of state L (Sec. III.A, Dirichlet).  With every wave of the
+    Riemann problem (L, R) moving right, the exact solution for x > 0 is that
+    problem's self-similar solution from x = 0, until its fastest wave nears
+    the outflow pad.  States are physical (rho, u, p); the lattice takes
+    RT_R = 0.5 by acoustic scaling."""
+    s = np.sqrt(0.5 / (R[2] / R[0]))
+    cfg, prim = li.riemann1d(n=N, states=(R, R), scale=s, pad=24)
+    cfg["bc"] = ["inflow", "outflow", "periodic", "periodic"]
+    cfg["in_rho"], cfg["in_u"], cfg["in_RT"] = L[0], (L[1] * s, 0.0), L[2] / L[0] * s * s
+    Ll = (L[0], L[1] * s, L[2] * s * s)
+    Rl = (R[0], R[1] * s, R[2] * s * s)
+    smin, smax = riemann.wave_speeds(Ll, Rl)
+    assert smin > 0                       # no wave runs back into the inflow pad
+    steps = int(frac * N / smax)
+    st, out, stats, done = oracle.step(cfg, prim_moments(cfg, prim), steps)
+    x = np.arange(N) + 0.5
+    ex = riemann.sample(Ll, Rl, x / steps)
+    return st, np.abs(out[0] - ex[0]).mean() / (ex[0].max() - ex[0].min())
+
+
+def test_inflow_face_drives_the_exact_riemann_solution():
+    """A supersonic inflow (Mach 2.5) into gas at rest: the density behind the
+    inflow face follows the exact Riemann solution, and the error falls under
+    refinement.  A pad that copied the interior instead of holding the inflow
+    equilibrium would leave the tube at rest."""
+    L = (1.0, 2.5 * np.sqrt(1.4), 1.0)
+    R = (0.4, 0.0, 0.25)
+    errs = []
+    for N in (200, 400):
+        st, e = _inflow_riemann(N, L, R)
+        assert st == 0
+        errs.append(e)
+    # first-order convergence (measured 1.26e-2 -> 6.5e-3 -> 3.2e-3 at N = 800)
+    assert errs[1] < 1e-2 and errs[1] < 0.6 * errs[0]
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_uniform_inflow_state_is_invariant(dim):
+    """A uniform state equal to the inflow state, between an inflow face and an
+    outflow face, is a fixed point (both pads then hold that state)."""
+    if dim == 1:
+        cfg, prim = li.hotbox(0.8, n=40, u=(0.7, 0.0), dim=1)
+    else:
+        cfg, prim = li.hotbox(0.8, n=40, ny=24, u=(0.9, 0.3))
+    cfg["bc"] = ["inflow", "outflow", "periodic", "periodic"]
+    cfg["pad"] = 8
+    cfg["in_rho"], cfg["in_u"], cfg["in_RT"] = 1.0, (prim["ux"][0, 0], prim["uy"][0, 0]), 0.8
+    m = prim_moments(cfg, prim)
+    st, out, stats, done = oracle.step(cfg, m, 4)
+    assert st == 0
+    assert np.max(np.abs(out - m) / np.abs(m).max(axis=1, keepdims=True)) < 1e-13
+
+
+@pytest.mark.parametrize("xfaces,u,pad,fails", [
+    ("open", (10.0, 0.5), 13, "left"),      # inflow pad: [u_x] + R = 10 + 4 = 14 > 13
+    ("open", (10.0, 0.5), 14, None),
+    ("periodic", (10.0, 0.4), 4, None),     # y pads: [u_y] + R = 4 <= 4 and R - [u_y] = 4 <= 4
+    ("periodic", (10.0, -3.0), 6, "top"),   # top pad: R - [u_y] = 4 + 3 = 7 > 6
+])
+def test_pad_narrower_than_the_reach_is_rejected(xfaces, u, pad, fails):
+    """Sec. III (Fig. 5): pads hold every source within reach of the interior.
+    A pad narrower than the stencil's reach toward the interior is reported
+    (EREACH), with the state of the last completed step left in place; the
+    reach away from the interior does not count."""
+    cfg, prim = li.hotbox(1.0, n=36, ny=20, u=u)
+    if xfaces == "open":
+        cfg["bc"] = ["inflow", "outflow", "periodic", "periodic"]
+    else:
+        cfg["bc"] = ["periodic", "periodic", "outflow", "outflow"]
+    cfg["pad"] = pad
+    cfg["in_rho"], cfg["in_u"], cfg["in_RT"] = 1.0, u, 1.0
+    m = prim_moments(cfg, prim)
+    st, out, stats, done = oracle.step(cfg, m, 2)
+    if fails is None:
+        assert st == 0 and done == 2
+    else:
+        assert st == oracle.EREACH and done == 0
+        assert np.array_equal(out, m)
+        sxn = 36 + (2 * pad if xfaces == "open" else 0)
+        fx = stats["fail_cell"] % sxn - (pad if xfaces == "open" else 0)
+        fy = stats["fail_cell"] // sxn - (0 if xfaces == "open" else pad)
+        assert (fx < 0) if fails == "left" else (fy >= 20)
 
 
 # --------------------------------------------------------------------------
