@@ -50,12 +50,15 @@ enum {
                                Newton iteration cap, Cholesky breakdown or line
                                search exhausted in the entropic reconstruction */
     LELBM_ENONFINITE = -5,  /* non-finite moments */
-    LELBM_EREACH = -6       /* a population path leaves the padded domain
-                               through a wall, or a cell is outside the
-                               supported stencil range: more than 3
-                               refinement levels (RT < 0.0123), acoustic
-                               radius above 128 (RT > ~1030) or |u| above
-                               2048 cells per step */
+    LELBM_EREACH = -6       /* a pad is narrower than the reach of its
+                               cells' stencils toward the interior
+                               ([u_n] + R > pad width, u_n the velocity
+                               component toward the interior; Sec. III), or
+                               a cell is outside the supported stencil
+                               range: more than 3 refinement levels
+                               (RT < 0.0123), acoustic radius above 128
+                               (RT > ~1030) or |u| above 2048 cells per
+                               step */
 };
 
 enum { LELBM_BC_PERIODIC = 0, LELBM_BC_OUTFLOW = 1, LELBM_BC_INFLOW = 2, LELBM_BC_SLIPWALL = 3 };
@@ -69,8 +72,6 @@ enum { LELBM_BC_PERIODIC = 0, LELBM_BC_OUTFLOW = 1, LELBM_BC_INFLOW = 2, LELBM_B
  * of the FP32 state. */
 enum { LELBM_FP64 = 0, LELBM_MIXED = 1 };
 
-/* Initial guess of the Newton solve: Eq. (IID13), or the learned network set
- * with lelbm_set_mlp (with Eq. (IID13) as fallback). */
 /* Newton initial guess.  EQ: Eq. (IID13), the equilibrium multipliers.
  * LIN: Eq. (IID13) plus one Newton step taken in closed form with the
  * moments of the continuous Maxwellian (the linear response of the
@@ -85,8 +86,10 @@ enum { LELBM_FP64 = 0, LELBM_MIXED = 1 };
  * that flip.  The context keeps 16 doubles per cell for it; the first step,
  * and cells whose previous step used refined stencils, start from LIN.
  * With LIN, MLP and PREV a cell whose first Newton update does not lower
- * the residual restarts from Eq. (IID13); the converged result is the same
- * in all modes (the multipliers are unique). */
+ * the residual, or whose solve fails (non-finite values, Cholesky
+ * breakdown, line search exhausted, iteration cap), restarts from
+ * Eq. (IID13); the converged result is the same in all modes (the
+ * multipliers are unique). */
 enum { LELBM_GUESS_EQ = 0, LELBM_GUESS_MLP = 1, LELBM_GUESS_LIN = 2, LELBM_GUESS_PREV = 3 };
 
 typedef struct {
@@ -120,7 +123,8 @@ typedef struct {
     double it_mean_f, it_mean_g;
     int it_max_f, it_max_g;
     long fallbacks;                   /* cells restarted from Eq. (IID13) because their LIN, MLP or PREV
-                                         guess did not lower the residual at the first update */
+                                         guess did not lower the residual at the first update, or
+                                         its Newton solve failed */
     long limited;                     /* cells whose frequencies the limiter changed */
     long q_min, q_max;
     double q_mean;
@@ -132,6 +136,11 @@ typedef struct {
     long arrivals;                    /* stencil points deposited into interior cells */
     long point_passes_refined;        /* the part of point_passes spent on cells with
                                          refined stencils (Eqs. IIC10-11) */
+    long wave_point_passes;           /* sum over the reconstruction's wavefronts (64 cells each)
+                                         of 64 x the largest q x passes of their cells: the lanes
+                                         of a wavefront run in lock step, so
+                                         point_passes / wave_point_passes is the share of lane
+                                         time spent on stencil points */
 } lelbm_stats;
 
 /* Number of stored moments per cell: 6 (1D) or 11 (2D); -1 for other dim. */

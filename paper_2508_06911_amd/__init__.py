@@ -51,7 +51,7 @@ class Stats(ctypes.Structure):
         ("rt_min", ctypes.c_double), ("kn_max", ctypes.c_double), ("colat_max", ctypes.c_double),
         ("sum", ctypes.c_double * 4), ("cells", ctypes.c_long),
         ("point_passes", ctypes.c_long), ("arrivals", ctypes.c_long),
-        ("point_passes_refined", ctypes.c_long),
+        ("point_passes_refined", ctypes.c_long), ("wave_point_passes", ctypes.c_long),
     ]
 
     def as_dict(self):

@@ -153,7 +153,7 @@ extern "C" const char *lelbm_strerror(int code) {
     case LELBM_EDEVICE: return "HIP device error";
     case LELBM_EEPR: return "entropic reconstruction failed (non-realizable state or Newton failure)";
     case LELBM_ENONFINITE: return "non-finite moments";
-    case LELBM_EREACH: return "population path or stencil refinement out of range";
+    case LELBM_EREACH: return "pad narrower than a stencil's reach, or stencil out of the supported range";
     default: return "unknown error";
     }
 }
@@ -430,7 +430,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ok = ok && hipMalloc((void **)&b.stats, sizeof(DevStats)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.partial, (size_t)(num_sum_blocks(g) + 1) * 4 * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.harvest_n, sizeof(unsigned long long)) == hipSuccess;
-    ok = ok && hipMalloc((void **)&b.bpart, (size_t)nt * sizeof(DevStats)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.bpart, (size_t)2 * nt * sizeof(DevStats)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.order, (size_t)nt * sizeof(int)) == hipSuccess;
     // arrival partials of the straight gather and of the backward-walk gather
     ok = ok && hipMalloc((void **)&b.gpart, (size_t)2 * gather_blocks_x(g) * gather_blocks_y(g) *
@@ -456,6 +456,9 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
         return LELBM_EDEVICE;
     }
     if (reset_flags(c) != LELBM_OK) { free_ctx(c); return LELBM_EDEVICE; }
+    // pinned staging for flags and statistics, reserved here so that stepping
+    // never has to allocate it
+    if (stage_reserve(c->stage, 4096) != LELBM_OK) { free_ctx(c); return LELBM_ENOMEM; }
     *cc = c;
     return LELBM_OK;
 }
@@ -608,16 +611,41 @@ static hipError_t do_gather(lelbm_ctx *c, void *) {
     return launch_gather(c->g, c->mixed, c->b.mom[c->cur ^ 1], c->b, c->gcap, c->stream);
 }
 
-extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
+// The steps of lelbm_step.  With fixed_scratch the record scratch is that
+// fixed buffer (fixed_cap elements) and nothing is allocated: a step that
+// needs more scratch fails with LELBM_ENOMEM, keeping the state of the last
+// completed step, and no timing events are recorded.
+static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scratch, long long fixed_cap) {
     if (!c || nsteps < 0) return LELBM_EINVAL;
     if (c->p.guess == LELBM_GUESS_MLP && !c->mlp_set) return LELBM_EINVAL;
-    int dev;
-    HIPCHECK(hipGetDevice(&dev));
-    if (dev != c->device) HIPCHECK(hipSetDevice(c->device));
+    const bool noalloc = fixed_scratch != nullptr;
+    if (noalloc && c->stage.cap < sizeof(DevStats) + sizeof(Flags)) return LELBM_EINVAL;
     hipStream_t s = c->stream;
     int r = reset_flags(c);
     if (r != LELBM_OK) return r;
     HIPCHECK(launch_reset_stats(c->b, s));
+    // With noalloc the steps run on the static scratch, without timing; the
+    // context's own scratch and timing mode are restored on every return.
+    // (Without noalloc nothing is swapped: the context's scratch may grow
+    // during the call and must stay the one it owns.)
+    struct Swap {
+        lelbm_ctx *c;
+        bool on;
+        void *p;
+        long long cap;
+        int timing;
+        ~Swap() {
+            if (!on) return;
+            c->b.scratch = p;
+            c->b.scratch_cap = cap;
+            c->timing = timing;
+        }
+    } keep{c, noalloc, c->b.scratch, c->b.scratch_cap, c->timing};
+    if (noalloc) {
+        c->b.scratch = fixed_scratch;
+        c->b.scratch_cap = fixed_cap;
+        c->timing = 0;
+    }
     int base = 0;   // first step not known to be complete
     while (base < nsteps) {
         int cur0 = c->cur;
@@ -638,13 +666,13 @@ extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
         // every kernel after the failing one returned early, so the state at
         // the start of step f.step is intact
         c->cur = (cur0 + (f.step - base)) & 1;
-        if (f.err != ERR_OVERFLOW) {
-            c->last_fail_node = (long)f.node;
+        if (f.err != ERR_OVERFLOW || noalloc) {
+            c->last_fail_node = f.err == ERR_OVERFLOW ? -1 : (long)f.node;
             c->last_fail_step = f.step;
             c->last_fail_detail = f.detail;
             c->last_fail_species = f.species;
             c->last_fail_residual = f.residual;
-            return f.err;
+            return f.err == ERR_OVERFLOW ? LELBM_ENOMEM : f.err;
         }
         if ((r = grow_scratch(c, f.need)) != LELBM_OK) return r;
         if ((r = reset_flags(c)) != LELBM_OK) return r;
@@ -678,9 +706,19 @@ extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
         st->point_passes = (long)ds.qpass_sum;
         st->arrivals = (long)ds.arrivals;
         st->point_passes_refined = (long)ds.qpass_ref_sum;
+        st->wave_point_passes = (long)ds.wave_qpass;
     }
     return LELBM_OK;
 }
+
+extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
+    if (!c) return LELBM_EINVAL;
+    int dev;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev != c->device) HIPCHECK(hipSetDevice(c->device));
+    return step_impl(c, nsteps, st, nullptr, 0);
+}
+
 
 // Interior moments as FP64 SoA [nmom][ny][nx]: to the host through the
 // pinned stage (row chunks, widened on the host), or to the device by a
@@ -743,7 +781,7 @@ extern "C" int lelbm_last_failure_detail(const lelbm_ctx *c, int *reason, int *s
 extern "C" int lelbm_set_timing(lelbm_ctx *c, int enable) {
     if (!c) return LELBM_EINVAL;
     c->timing = enable != 0;
-    for (int k = 0; k < 6; k++) { c->kms[k] = 0; c->klaunch[k] = 0; }
+    for (int k = 0; k < LELBM_NTIMERS; k++) { c->kms[k] = 0; c->klaunch[k] = 0; }
     return LELBM_OK;
 }
 

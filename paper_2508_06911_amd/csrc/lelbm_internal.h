@@ -24,6 +24,13 @@ constexpr double MAX_SPEED = 2048.0;  // largest |u| component in cells per step
 // x0 = round(u_x) - R - 1; 0x00ff = empty.  Cells with more rows (R > 30)
 // recompute their spans in every pass.
 constexpr int SPAN_ROWS = 64;
+// The reconstruction's product recurrences (along a stencil row, and down
+// the column of row starts) accumulate rounding as the cube of their length;
+// stencils with longer rows (R >= 15) are reconstructed by a variant of the
+// kernel that restarts them from exact exponentials every REC_SEG points and
+// rows, which keeps the populations of the widest stencils within ~1e-13
+// (without restarts, a radius of 33 stalls Newton at a residual of ~2e-12).
+constexpr int REC_SEG = 32;
 // staged sources per gather chunk (28 B of LDS each)
 constexpr int GATHER_CAP = 1024;
 constexpr int GATHER_CAP_MAX = 2340;      // 64 KiB of LDS
@@ -89,6 +96,7 @@ struct Flags {
 
 struct DevStats {
     unsigned long long it_sum_f, it_sum_g, q_sum, limited, cells, fallbacks, qpass_sum, arrivals, qpass_ref_sum;
+    unsigned long long wave_qpass;   // sum over wavefronts of 64 x the wavefront's largest q x passes
     int it_max_f, it_max_g, q_max, q_min;
     unsigned long long rt_min_bits, kn_max_bits, colat_max_bits;
 };
@@ -98,7 +106,7 @@ struct TileInfo {
     int ox, oy;              // displacement of slot (0, 0)
     int wx, wy;              // slot box extent
     int fmt;                 // 0: (w_f, w_g) per slot; 1: all moments per slot
-    int pad_;
+    int wide;                // 1: holds cells with wide stencils (unrefined, 2R + 3 > REC_SEG)
     long long size;          // elements used by the tile
     long long base;          // first element of the tile
 };
@@ -132,7 +140,7 @@ struct Buffers {
     const unsigned short *mlp_w;   // BF16 weights (canonical order), NULL = none
     const float *mlp_p;            // FP32 parameters (biases read from here)
     const float *mlp_n;            // standardisation constants (64)
-    DevStats *bpart;               // [ntx*nty] per-workgroup statistics of k_epr
+    DevStats *bpart;               // [2][ntx*nty] per-workgroup statistics of k_epr (narrow, wide stencils)
     int *order;                    // [ntx*nty] source tiles in the order k_epr takes them (k_scan)
     unsigned long long *gpart;     // [dtx*dty] per-workgroup arrival counts of k_gather
     double *lamprev;               // [16][ns] scaled correction beyond the linearised guess, last step

@@ -62,6 +62,9 @@ __device__ inline int las_radius(double RT, double n_conf, int r_min) {
     int R = (int)floor(n_conf * sqrt(RT) + 0.5);
     return R > r_min ? R : r_min;
 }
+// Stencils with rows longer than REC_SEG points (R >= 15): their
+// reconstruction restarts the product recurrences (k_epr<..., true>).
+__host__ __device__ constexpr bool wide_stencil(int R) { return 2 * R + 3 > REC_SEG; }
 __device__ inline int las_levels(double RT) {
 #pragma clang fp contract(off)
     return (int)floor(1.0 / (3.0 * sqrt(RT)) + 0.5);
@@ -96,7 +99,8 @@ __device__ inline void flag_fail(Flags *fl, int code, int step, long long node, 
 // Reasons of a failed reconstruction (lelbm_last_failure_detail).
 enum { FAIL_NONFINITE = 1, FAIL_LINESEARCH = 2, FAIL_CHOL_POLISH = 3, FAIL_MAXIT = 4, FAIL_CHOL_STEP = 5 };
 // species_update asks for a restart from Eq. (IID13) when a solve started
-// from the learned guess does not lower its residual
+// from a non-equilibrium guess (linearised, previous step, learned) does not
+// lower its residual at the first update, or fails
 constexpr int RESTART_EQ = 2;
 
 __device__ inline void atomic_max_pos(unsigned long long *a, double v) {
@@ -204,7 +208,7 @@ __device__ inline void update_windows(const Geom &g, DWin *dwin, int rx0, int rx
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, Buffers b, int step) {
     __shared__ int red[9][256];
-    __shared__ int redf[256];
+    __shared__ int redf[256], redw[256];
     __shared__ int s_err;
     if (threadIdx.x == 0) s_err = b.flags->err;
     __syncthreads();
@@ -214,7 +218,7 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
     int l = threadIdx.x;
     int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
     bool valid = px < g.sxn && py < g.syn;
-    int lox = 1 << 29, loy = 1 << 29, hix = -(1 << 29), hiy = -(1 << 29), refined = 0;
+    int lox = 1 << 29, loy = 1 << 29, hix = -(1 << 29), hiy = -(1 << 29), refined = 0, wide = 0;
     int uxl = 1 << 29, uxh = -(1 << 29), uyl = 1 << 29, uyh = -(1 << 29), rmx = -1;
     int reach = 0;
     if (valid && b.solid) {
@@ -253,14 +257,27 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
             int R = las_radius(RT, ph.n_conf, ph.r_min);
             int Nr = las_levels(RT);
             double umax = fmax(fabs(ux), fabs(uy));
-            if (Nr > MAX_REFINE || R > MAX_RADIUS || !(umax <= MAX_SPEED)) {
+            int ubx = 0, uby = 0;
+            bool over = Nr > MAX_REFINE || R > MAX_RADIUS || !(umax <= MAX_SPEED);
+            if (!over) {
+                ubx = (int)floor(ux + 0.5);
+                uby = D == 2 ? (int)floor(uy + 0.5) : 0;
+                // Pads (Sec. III) must hold every source within reach of the
+                // interior: the cells beyond a pad are in the pad's state, so a
+                // pad cell whose stencil box [u] +- R reaches farther toward the
+                // interior than the pad is wide means missing arrivals.
+                const int ix = px - g.wl, iy = py - g.wb;
+                over = (ix < 0 && ubx + R > g.wl) || (ix >= g.nx && R - ubx > g.wr) ||
+                       (iy < 0 && uby + R > g.wb) || (iy >= g.ny && R - uby > g.wt);
+            }
+            if (over) {
                 flag_fail(b.flags, LELBM_EREACH, step, s);
             } else {
                 rn = R | (Nr << 16);
-                int ubx = (int)floor(ux + 0.5), uby = D == 2 ? (int)floor(uy + 0.5) : 0;
                 lox = ubx - R - 1; hix = ubx + R + 1;
                 loy = D == 2 ? uby - R - 1 : 0; hiy = D == 2 ? uby + R + 1 : 0;
                 refined = Nr > 0;
+                wide = Nr == 0 && wide_stencil(R);
                 reach = max(abs(ubx), abs(uby)) + R + 1;
                 uxl = (int)floor(ux * 1024.0); uxh = (int)ceil(ux * 1024.0);
                 uyl = D == 2 ? (int)floor(uy * 1024.0) : 0; uyh = D == 2 ? (int)ceil(uy * 1024.0) : 0;
@@ -273,7 +290,7 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
         b.desc_rt[s] = RT;
         b.desc_rn[s] = rn;
     }
-    red[0][l] = lox; red[1][l] = loy; red[2][l] = hix; red[3][l] = hiy; redf[l] = refined;
+    red[0][l] = lox; red[1][l] = loy; red[2][l] = hix; red[3][l] = hiy; redf[l] = refined; redw[l] = wide;
     red[4][l] = uxl; red[5][l] = uxh; red[6][l] = uyl; red[7][l] = uyh; red[8][l] = rmx;
     __shared__ int s_reach[4];
     if (b.maxreach) {
@@ -293,6 +310,7 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
             red[7][l] = max(red[7][l], red[7][l + off]);
             red[8][l] = max(red[8][l], red[8][l + off]);
             redf[l] |= redf[l + off];
+            redw[l] |= redw[l + off];
         }
         __syncthreads();
     }
@@ -304,7 +322,7 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
     }
     if (l == 0) {
         TileInfo ti;
-        ti.pad_ = 0;
+        ti.wide = redw[0];
         if (red[0][0] > red[2][0]) {   // no emitting cell in the tile
             ti.ox = ti.oy = 0; ti.wx = ti.wy = 0; ti.fmt = 0; ti.size = 0; ti.base = 0;
         } else {
@@ -892,6 +910,7 @@ struct CellStats {
 // DevStats; an empty set is the neutral element).
 struct StatSum {
     unsigned long long itf = 0, itg = 0, q = 0, lim = 0, cells = 0, qp = 0, qpr = 0, fb = 0;
+    unsigned long long wq = 0;   // sum over wavefronts of 64 x the wavefront's largest q x passes
     int mitf = 0, mitg = 0, mq = 0, nq = 1 << 30;
     double mkn = 0.0, mcolat = 0.0, nrt = 1e300;
     __device__ void add_cell(const CellStats &c) {
@@ -903,7 +922,7 @@ struct StatSum {
     }
     __device__ void add(const StatSum &o) {
         itf += o.itf; itg += o.itg; q += o.q; lim += o.lim; cells += o.cells; qp += o.qp; qpr += o.qpr;
-        fb += o.fb;
+        fb += o.fb; wq += o.wq;
         mitf = max(mitf, o.mitf); mitg = max(mitg, o.mitg); mq = max(mq, o.mq); nq = min(nq, o.nq);
         mkn = fmax(mkn, o.mkn); mcolat = fmax(mcolat, o.mcolat); nrt = fmin(nrt, o.nrt);
     }
@@ -921,7 +940,7 @@ struct StatSum {
     }
     __device__ void load(const DevStats &d) {
         itf = d.it_sum_f; itg = d.it_sum_g; q = d.q_sum; lim = d.limited; cells = d.cells; qp = d.qpass_sum;
-        qpr = d.qpass_ref_sum; fb = d.fallbacks;
+        qpr = d.qpass_ref_sum; fb = d.fallbacks; wq = d.wave_qpass;
         mitf = d.it_max_f; mitg = d.it_max_g; mq = d.q_max; nq = d.q_min;
         mkn = __longlong_as_double((long long)d.kn_max_bits);
         mcolat = __longlong_as_double((long long)d.colat_max_bits);
@@ -929,7 +948,7 @@ struct StatSum {
     }
     __device__ void store(DevStats &d) const {
         d.it_sum_f = itf; d.it_sum_g = itg; d.q_sum = q; d.limited = lim; d.cells = cells; d.qpass_sum = qp;
-        d.qpass_ref_sum = qpr; d.fallbacks = fb; d.arrivals = 0;
+        d.qpass_ref_sum = qpr; d.fallbacks = fb; d.arrivals = 0; d.wave_qpass = wq;
         d.it_max_f = mitf; d.it_max_g = mitg; d.q_max = mq; d.q_min = nq;
         d.kn_max_bits = (unsigned long long)__double_as_longlong(mkn);
         d.colat_max_bits = (unsigned long long)__double_as_longlong(mcolat);
@@ -947,6 +966,7 @@ struct StatSum {
         atomicAdd(&st->qpass_sum, qp);
         if (qpr) atomicAdd(&st->qpass_ref_sum, qpr);
         if (fb) atomicAdd(&st->fallbacks, fb);
+        if (wq) atomicAdd(&st->wave_qpass, wq);
         atomicMax(&st->it_max_f, mitf);
         atomicMax(&st->it_max_g, mitg);
         atomicMax(&st->q_max, mq);
@@ -957,12 +977,24 @@ struct StatSum {
     }
 };
 
+// Lane occupancy of the stencil work: the lanes of a wavefront run in lock
+// step, so a wavefront costs 64 x the largest q x passes of its cells.
+__device__ inline unsigned long long wave_lanes_max(const CellStats &c) {
+    unsigned long long m = c.active ? (unsigned long long)c.q * c.pass : 0ull;
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off);
+        m = o > m ? o : m;
+    }
+    return 64ull * m;
+}
+
 // Statistics of a workgroup's cells, one wave-reduced atomic set per wave
 // (used by kernels that run on few workgroups).
 __device__ inline void push_stats(DevStats *st, const CellStats &c) {
     StatSum a;
     a.add_cell(c);
     a.wave_reduce();
+    a.wq = wave_lanes_max(c);
     if ((threadIdx.x & 63) == 0) a.atomics_into(st);
 }
 
@@ -973,6 +1005,7 @@ __device__ inline void block_stats(DevStats *part, const CellStats &c) {
     StatSum a;
     a.add_cell(c);
     a.wave_reduce();
+    a.wq = wave_lanes_max(c);
     if ((threadIdx.x & 63) == 0) a.store(s_w[threadIdx.x >> 6]);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1169,7 +1202,11 @@ __device__ inline bool row_start_ok(double f, double r, double s2, double gv, do
            s2 < 1e280 && rg > 1e-280 && rg < 1e280;
 }
 
-template <typename T, int D>
+// WIDE: the cells with wide stencils (wide_stencil(R)), on the tiles that
+// hold any, with the recurrences restarted every REC_SEG points and rows;
+// otherwise the other unrefined cells, whose rows are short enough to run
+// each recurrence from one start.
+template <typename T, int D, bool WIDE>
 __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, Buffers b, int step) {
     using BS = Basis<D>;
     constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
@@ -1181,13 +1218,14 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
     using W = double;
     __shared__ double s_lamf[NF * TILE_N], s_delf[NF * TILE_N], s_lamg[NG * TILE_N], s_delg[NG * TILE_N];
     __shared__ int s_err;
-    if (threadIdx.x == 0) s_err = b.flags->err;
+    const int t = b.order[blockIdx.x];        // heaviest tiles first (k_scan)
+    DevStats *part = b.bpart + (WIDE ? (long long)g.ntx * g.nty : 0);
+    if (threadIdx.x == 0) s_err = b.flags->err || (WIDE && !b.tiles[t].wide);
     __syncthreads();
     if (s_err) {
-        if (threadIdx.x == 0) StatSum().store(b.bpart[blockIdx.x]);
+        if (threadIdx.x == 0) StatSum().store(part[blockIdx.x]);
         return;
     }
-    const int t = b.order[blockIdx.x];        // heaviest tiles first (k_scan)
     int tx0 = (t % g.ntx) * g.tx, ty0 = (t / g.ntx) * g.ty;
     int l = threadIdx.x;
     int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
@@ -1195,7 +1233,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
     long long s = (long long)py * g.sxn + px;
     int rn = valid ? b.desc_rn[s] : -1;
     CellStats cs;
-    cs.active = rn >= 0 && (rn >> 16) == 0;
+    cs.active = rn >= 0 && (rn >> 16) == 0 && wide_stencil(rn & 0xffff) == WIDE;
     double rho = 0.0, ux = 0.0, uy = 0.0, RT = 1.0;
     double mf[NF], mg[NG];
     if (cs.active) {
@@ -1287,6 +1325,16 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                 col.init(lf, lg, (double)xlo - ux, (double)ylo - uy);
             }
             for (int cy = ylo; cy <= yhi; cy++) {
+                if constexpr (WIDE) {
+                    if (D == 2 && cy != ylo && (cy - ylo) % REC_SEG == 0) {
+                        double lf[NF], lg[NG];
+#pragma unroll
+                        for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
+#pragma unroll
+                        for (int j = 0; j < NG; j++) lg[j] = sg.at(j);
+                        col.init(lf, lg, (double)xlo - ux, (double)cy - uy);
+                    }
+                }
                 W f = 0, r = 0, s2 = 0, gv = 0, rg = 0;
                 if (D == 2) { f = col.F; r = col.R; s2 = col.S; gv = col.G; rg = col.Q; col.next(); }
                 const unsigned cur = nxt;
@@ -1294,11 +1342,12 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                 int xa, xb;
                 if (!span(cur, cy, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
-                if (D == 2) {
+                const bool walk = D == 2 && (!WIDE || xa - xlo < REC_SEG);
+                if (walk) {
                     // walk from the column to the row's first point
                     for (int k = xlo; k < xa; k++) { f *= r; r *= s2; s2 *= t3; gv *= rg; rg *= sg2; }
                 }
-                if (D == 1 || !row_start_ok(f, r, s2, gv, rg)) {
+                if (!walk || !row_start_ok(f, r, s2, gv, rg)) {
                     double lf[NF], lg[NG], e[4], h[3];
 #pragma unroll
                     for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
@@ -1313,6 +1362,17 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
 #pragma unroll
                 for (int k = 0; k < 5; k++) Rg[k] = 0;
                 for (int cx = xa; cx <= xb; cx++) {
+                    if constexpr (WIDE) {
+                        if (cx != xa && (cx - xlo) % REC_SEG == 0) {
+                            double lf[NF], lg[NG], e[4], h[3];
+#pragma unroll
+                            for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
+#pragma unroll
+                            for (int j = 0; j < NG; j++) lg[j] = sg.at(j);
+                            row_poly<D>(lf, lg, y, e, h);
+                            row_start<W>(e, h, (double)cx - ux, f, r, s2, gv, rg);
+                        }
+                    }
                     W x = (W)((double)cx - ux);
                     W x2 = x * x, x3 = x2 * x, x4 = x2 * x2, x5 = x4 * x, x6 = x3 * x3;
                     Rf[0] += f; Rf[1] += f * x; Rf[2] += f * x2; Rf[3] += f * x3;
@@ -1339,11 +1399,13 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
             }
             if (sg.phase < 2) {
                 int r = species_update<D, NG, NMG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
+                if (r < 0 && r != -FAIL_CHOL_POLISH && sg.mlp) r = RESTART_EQ;
                 if (r < 0) { fail = -r; fsp = 1; }
                 else if (r == RESTART_EQ) { species_restart_eq<D>(sg, RT); cs.fb = 1; }
             }
             if (sf.phase < 2 && !fail) {
                 int r = species_update<D, NF, NMF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
+                if (r < 0 && r != -FAIL_CHOL_POLISH && sf.mlp) r = RESTART_EQ;
                 if (r < 0) { fail = -r; fsp = 0; }
                 else if (r == RESTART_EQ) { species_restart_eq<D>(sf, RT); cs.fb = 1; }
             }
@@ -1392,6 +1454,16 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                 col.init(lf, lg, (double)xlo - ux, (double)ylo - uy);
             }
             for (int cy = ylo; cy <= yhi; cy++) {
+                if constexpr (WIDE) {
+                    if (D == 2 && cy != ylo && (cy - ylo) % REC_SEG == 0) {
+                        double lf[NF], lg[NG];
+#pragma unroll
+                        for (int j = 0; j < NF; j++) lf[j] = sf.v.lam(j);
+#pragma unroll
+                        for (int j = 0; j < NG; j++) lg[j] = sg.v.lam(j);
+                        col.init(lf, lg, (double)xlo - ux, (double)cy - uy);
+                    }
+                }
                 W f = 0, r = 0, s2 = 0, gv = 0, rg = 0;
                 if (D == 2) { f = col.F; r = col.R; s2 = col.S; gv = col.G; rg = col.Q; col.next(); }
                 const unsigned cur = nxt;
@@ -1399,10 +1471,11 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                 int xa, xb;
                 if (!span(cur, cy, xa, xb)) continue;
                 double y = D == 2 ? (double)cy - uy : 0.0;
-                if (D == 2) {
+                const bool walk = D == 2 && (!WIDE || xa - xlo < REC_SEG);
+                if (walk) {
                     for (int k = xlo; k < xa; k++) { f *= r; r *= s2; s2 *= t3; gv *= rg; rg *= sg2; }
                 }
-                if (D == 1 || !row_start_ok(f, r, s2, gv, rg)) {
+                if (!walk || !row_start_ok(f, r, s2, gv, rg)) {
                     double lf[NF], lg[NG], e[4], h[3];
 #pragma unroll
                     for (int j = 0; j < NF; j++) lf[j] = sf.v.lam(j);
@@ -1413,6 +1486,17 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                 }
                 long long rowslot = (long long)(cy - ti.oy) * ti.wx - ti.ox;
                 for (int cx = xa; cx <= xb; cx++) {
+                    if constexpr (WIDE) {
+                        if (cx != xa && (cx - xlo) % REC_SEG == 0) {
+                            double lf[NF], lg[NG], e[4], h[3];
+#pragma unroll
+                            for (int j = 0; j < NF; j++) lf[j] = sf.v.lam(j);
+#pragma unroll
+                            for (int j = 0; j < NG; j++) lg[j] = sg.v.lam(j);
+                            row_poly<D>(lf, lg, y, e, h);
+                            row_start<W>(e, h, (double)cx - ux, f, r, s2, gv, rg);
+                        }
+                    }
                     W wf = wsfw * f, wg = wsgw * gv;
                     long long slot = rowslot + cx;
                     if (ti.fmt == 0) {
@@ -1448,7 +1532,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
             cs.colat = (D == 2 ? sqrt(ux * ux + uy * uy) : fabs(ux)) + R;
         }
     }
-    block_stats(b.bpart, cs);
+    block_stats(part, cs);
 }
 
 // ---------------------------------------------------------------------------
@@ -2325,7 +2409,7 @@ __global__ void k_reset_flags(Flags *f) {
 __global__ void k_reset_stats(DevStats *st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->it_sum_f = st->it_sum_g = st->q_sum = st->limited = st->cells = st->fallbacks = 0;
-        st->qpass_sum = st->qpass_ref_sum = st->arrivals = 0;
+        st->qpass_sum = st->qpass_ref_sum = st->arrivals = st->wave_qpass = 0;
         st->it_max_f = st->it_max_g = st->q_max = 0;
         st->q_min = 1 << 30;
         st->rt_min_bits = (unsigned long long)__double_as_longlong(1e300);
@@ -2526,11 +2610,19 @@ static void epr_launch(const Geom &g, const Phys &ph, const void *mom, Buffers &
                        hipStream_t s) {
     unsigned nt = (unsigned)(g.ntx * g.nty);
     if (g.dim == 1) {
-        if (refined) hipLaunchKernelGGL((k_epr_ref<T, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
-        else hipLaunchKernelGGL((k_epr<T, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        if (refined) {
+            hipLaunchKernelGGL((k_epr_ref<T, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        } else {
+            hipLaunchKernelGGL((k_epr<T, 1, false>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+            hipLaunchKernelGGL((k_epr<T, 1, true>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        }
     } else {
-        if (refined) hipLaunchKernelGGL((k_epr_ref<T, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
-        else hipLaunchKernelGGL((k_epr<T, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        if (refined) {
+            hipLaunchKernelGGL((k_epr_ref<T, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        } else {
+            hipLaunchKernelGGL((k_epr<T, 2, false>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+            hipLaunchKernelGGL((k_epr<T, 2, true>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
+        }
     }
 }
 
@@ -2538,7 +2630,8 @@ hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom,
                       hipStream_t s) {
     if (mixed) epr_launch<float>(g, ph, mom, b, step, 0, s);
     else epr_launch<double>(g, ph, mom, b, step, 0, s);
-    const int nt = g.ntx * g.nty;
+    // partials of both k_epr variants
+    const int nt = 2 * g.ntx * g.nty;
     const int nb = (nt + 255) / 256 < 256 ? (nt + 255) / 256 : 256;
     hipLaunchKernelGGL(k_stats_reduce, dim3(nb), dim3(256), 0, s, (const DevStats *)b.bpart, nt, b.stats);
     return hipGetLastError();

@@ -141,6 +141,35 @@ def test_learned_guess_matches_plain_path_and_saves_iterations():
     m.close()
 
 
+@pytest.mark.parametrize("scale", [3.0, 30.0, 3000.0])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_garbage_network_falls_back_to_the_equilibrium_guess(prec, scale):
+    """A network with random weights far too large gives starting points from
+    which Newton does not converge (non-finite populations, residuals that do
+    not drop, failing solves): those cells restart from Eq. (IID13), so the
+    fields equal the plain path's and the fallbacks are counted."""
+    _case("garbage network weights x%g, precision %d" % (scale, prec))
+    import paper_2508_06911_amd as lb
+    rng = np.random.default_rng(int(scale))
+    p = np.zeros(mlp_ref.NPARAM, dtype=np.float32)
+    for off, nin, nout in ((0, 16, 64), (1088, 64, 64), (5248, 64, 16)):
+        p[off:off + nin * nout] = rng.uniform(-1, 1, nin * nout) * scale * np.sqrt(6.0 / nin)
+    p[6272:] = rng.normal(0, scale, 16)
+    m = lb.Mlp(params=p)
+    cfg, prim = li.quadrants(7, n=72, ny=56)
+    a, sa = run_gpu(cfg, prim, 15, precision=prec)
+    c = lb.Lelbm(cfg, gpu_moments(cfg, prim), precision=prec, guess=lb.GUESS_MLP)
+    c.set_mlp(m)
+    sb = c.step(15)
+    b = c.read_moments()
+    c.close()
+    m.close()
+    err = rel_linf(b, a)
+    print("rel_linf", err, "fallbacks", sb["fallbacks"], "of", sb["cells"], "it", sb["it_mean_f"], sb["it_max_f"])
+    assert sb["fallbacks"] > 0
+    assert err < (1e-10 if prec == 0 else 1e-5)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_linearised_guess_matches_plain_path(prec):
     """Newton started from the closed-form linearised multipliers converges

@@ -53,6 +53,110 @@ def test_quadrants_parity_100_steps(seed):
     assert sa["limited"] == sb["limited"]
 
 
+@pytest.mark.parametrize("seed", [0, 9])
+def test_hot_quadrant_seeds_parity_100_steps(seed):
+    """The seeds with the hottest quadrants of the distribution (lattice RT up
+    to 13.6 and 17.1: stencil radii 15 and 17, q up to ~970), where the
+    limiter is active in most cells and the Newton solves take the most
+    iterations."""
+    _print_case("quadrants seed %d 72x56 100 steps (hot)" % seed)
+    cfg, prim = li.quadrants(seed, n=72, ny=56)
+    assert prim["RT"].max() > 13.0
+    a, sa = run_gpu(cfg, prim, 100)
+    b, sb = run_oracle(cfg, prim, 100)
+    err = rel_linf(a, b)
+    print("rel_linf", err, "q", sa["q_min"], sa["q_max"], "it", sa["it_mean_f"], sa["it_max_f"])
+    assert err < TOL
+    assert sa["q_min"] == sb["q_min"] and sa["q_max"] == sb["q_max"]
+    assert sa["q_max"] > 800
+    assert abs(sa["it_mean_f"] - sb["it_mean_f"]) < 0.01
+
+
+def test_wide_stencils_parity_100_steps():
+    """Stencil radii of 31 and more (RT ~ 70, q ~ 3500-4000): more rows than
+    the reconstruction kernel's table of row spans holds, so every pass
+    recomputes each row's span; the gather stages windows of ~70 x 70
+    displacements in few rows per chunk."""
+    _print_case("smooth periodic RT~72 24x18 100 steps (R >= 31)")
+    cfg, prim = li.smooth_periodic(7, n=24, ny=18, RT=72.0)
+    a, sa = run_gpu(cfg, prim, 100)
+    b, sb = run_oracle(cfg, prim, 100)
+    err = rel_linf(a, b)
+    print("rel_linf", err, "q", sa["q_min"], sa["q_max"], "it", sa["it_mean_f"], sa["it_max_f"])
+    assert err < TOL
+    assert sa["q_min"] == sb["q_min"] and sa["q_max"] == sb["q_max"]
+    assert sa["q_min"] > 3100          # R >= 31 in every cell: q > pi 31.5^2
+
+
+@pytest.mark.parametrize("case", ["quadrants", "riemann1d", "channel"])
+def test_unstaged_gather_parity(case, monkeypatch):
+    """The gather's fallback for windows too wide to stage in LDS: with the
+    staging capacity at its minimum (256 sources, set from the host), no
+    window fits, and every destination reads its sources' descriptors from
+    global memory."""
+    _print_case("unstaged gather %s" % case)
+    monkeypatch.setenv("LELBM_GATHER_CAP", "256")
+    if case == "quadrants":
+        cfg, prim = li.quadrants(4, n=72, ny=56)
+        steps = 20
+    elif case == "riemann1d":
+        cfg, prim = li.riemann1d(0, n=600)
+        steps = 30
+    else:
+        cfg, prim = li.hotbox(1.0, n=48, ny=40, u=(2.0 * np.sqrt(1.4), 0.0))
+        cfg["bc"] = ["inflow", "outflow", "slipwall", "slipwall"]
+        cfg["pad"] = 12
+        cfg["in_rho"], cfg["in_u"], cfg["in_RT"] = 1.0, (2.0 * np.sqrt(1.4), 0.0), 1.0
+        y = (np.arange(40) + 0.5)[:, None]
+        prim["uy"] = 0.4 * np.sin(np.pi * y / 40) * np.ones((1, 48))
+        steps = 20
+    a, sa = run_gpu(cfg, prim, steps)
+    b, sb = run_oracle(cfg, prim, steps)
+    err = rel_linf(a, b)
+    print("rel_linf", err)
+    assert err < TOL
+    assert sa["arrivals"] > 0
+
+
+def test_pad_reach_error_mid_run():
+    """A pad narrower than a stencil's reach toward the interior is an error
+    (Sec. III): 1D gas at RT = 1.2 (R = 4) between 4-cell outflow pads, with a
+    hot slug in the middle whose compression wave heats the gas at the ends
+    past R = 4.  The step at which that happens fails with EREACH on the GPU
+    and in the oracle alike, both keeping the state of the step before."""
+    _print_case("1d pad reach error mid run")
+    import paper_2508_06911_amd as lb
+    cfg, prim = li.hotbox(1.2, n=80, dim=1, u=(0.0, 0.0))
+    cfg["bc"] = ["outflow", "outflow", "periodic", "periodic"]
+    cfg["pad"] = 4
+    x = np.arange(80) + 0.5
+    prim["RT"] = np.where(np.abs(x - 40) < 6, 2.4, 1.2)[None, :]
+    st, ref, ostats, done = oracle.step(cfg, oracle_moments(cfg, prim), 80)
+    assert st == oracle.EREACH and done > 0
+    c = lb.Lelbm(cfg, gpu_moments(cfg, prim))
+    with pytest.raises(lb.LelbmError) as e:
+        c.step(80)
+    assert e.value.code == lb.EREACH
+    node, step = c.last_failure()
+    assert step == done and node == ostats["fail_cell"]
+    assert rel_linf(c.read_moments(), ref) < TOL
+    c.close()
+    # a pad that is too narrow from the start fails at creation (u_y = 0.37:
+    # no integer point lies exactly on the stencil's rim, where rounding of u
+    # could decide membership differently on the two sides)
+    cfg2, prim2 = li.hotbox(1.0, n=36, ny=20, u=(10.0, 0.37))
+    cfg2["bc"] = ["inflow", "outflow", "periodic", "periodic"]
+    cfg2["pad"] = 13
+    cfg2["in_rho"], cfg2["in_u"], cfg2["in_RT"] = 1.0, (10.0, 0.37), 1.0
+    with pytest.raises(lb.LelbmError) as e:
+        lb.Lelbm(cfg2, gpu_moments(cfg2, prim2))
+    assert e.value.code == lb.EREACH
+    cfg2["pad"] = 14
+    a, _ = run_gpu(cfg2, prim2, 3)
+    b, _ = run_oracle(cfg2, prim2, 3)
+    assert rel_linf(a, b) < TOL
+
+
 def test_refined_stencils_parity():
     """RT < 4/9 switches on stencil refinement (Eq. IIC9): refined tiles store
     pre-summed moment fractions."""

@@ -564,8 +564,8 @@ def test_uniform_inflow_state_is_invariant(dim):
 
 
 @pytest.mark.parametrize("xfaces,u,pad,fails", [
-    ("open", (10.0, 0.5), 13, "left"),      # inflow pad: [u_x] + R = 10 + 4 = 14 > 13
-    ("open", (10.0, 0.5), 14, None),
+    ("open", (10.0, 0.37), 13, "left"),     # inflow pad: [u_x] + R = 10 + 4 = 14 > 13
+    ("open", (10.0, 0.37), 14, None),
     ("periodic", (10.0, 0.4), 4, None),     # y pads: [u_y] + R = 4 <= 4 and R - [u_y] = 4 <= 4
     ("periodic", (10.0, -3.0), 6, "top"),   # top pad: R - [u_y] = 4 + 3 = 7 > 6
 ])
@@ -592,6 +592,26 @@ def test_pad_narrower_than_the_reach_is_rejected(xfaces, u, pad, fails):
         fx = stats["fail_cell"] % sxn - (pad if xfaces == "open" else 0)
         fy = stats["fail_cell"] // sxn - (0 if xfaces == "open" else pad)
         assert (fx < 0) if fails == "left" else (fy >= 20)
+
+
+def test_pad_reach_exceeded_mid_run_keeps_the_last_state():
+    """1D gas at RT = 1.2 (R = 4) between 4-cell outflow pads, with a hot slug
+    in the middle: the compression wave heats the end cells past R = 4, and
+    that step fails with EREACH, leaving the state after the steps before."""
+    cfg, prim = li.hotbox(1.2, n=80, dim=1, u=(0.0, 0.0))
+    cfg["bc"] = ["outflow", "outflow", "periodic", "periodic"]
+    cfg["pad"] = 4
+    x = np.arange(80) + 0.5
+    prim["RT"] = np.where(np.abs(x - 40) < 6, 2.4, 1.2)[None, :]
+    m = prim_moments(cfg, prim)
+    st, out, stats, done = oracle.step(cfg, m, 80)
+    assert st == oracle.EREACH and 0 < done < 80
+    st2, out2, _, done2 = oracle.step(cfg, m, done)
+    assert st2 == 0 and done2 == done
+    assert np.array_equal(out, out2)
+    rho, ux, _, RT = (out[0], out[1] / out[0], None, ((out[2] + out[4]) / out[0] - (out[1] / out[0]) ** 2) / 5.0)
+    R = np.floor(4 * np.sqrt(RT) + 0.5)
+    assert R[0] + np.floor(ux[0] + 0.5) > 4 or R[-1] - np.floor(ux[-1] + 0.5) > 4
 
 
 # --------------------------------------------------------------------------
