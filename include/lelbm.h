@@ -167,6 +167,22 @@ int lelbm_create_device(const lelbm_params *p, const void *dev_moments, int dev_
  * once at the end.  On failure the state of the last completed step is kept. */
 int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lelbm_step with no
+ * allocation of any kind.  The population scratch of the steps is a static
+ * device array of LELBM_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on (until the process ends), instead of the context's
+ * own growable buffer; no timing events are recorded (lelbm_set_timing has
+ * no effect on this call).  A step whose records need more than that array
+ * fails with LELBM_ENOMEM and the context keeps the state of the last
+ * completed step (lelbm_last_failure names the step; node = -1).  All calls
+ * on one GPU share the array: calls that overlap in time on the same GPU
+ * (two contexts on different streams, or two threads) race and must be
+ * serialised by the caller.  Results equal those of lelbm_step bit for bit.
+ * Error behaviour is otherwise that of lelbm_step. */
+#define LELBM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int lelbm_step_noalloc(lelbm_ctx *c, int nsteps, lelbm_stats *st);
+
 /* Copy the current moments to caller-owned host memory (nmom*nx*ny FP64). */
 int lelbm_read_moments(const lelbm_ctx *c, double *host_out);
 

@@ -81,6 +81,7 @@ def lib():
         L.lelbm_create.argtypes = [ctypes.POINTER(Params), dp, vp, ctypes.POINTER(vp)]
         L.lelbm_create_device.argtypes = [ctypes.POINTER(Params), vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
         L.lelbm_step.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Stats)]
+        L.lelbm_step_noalloc.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Stats)]
         L.lelbm_read_moments.argtypes = [vp, dp]
         L.lelbm_read_moments_device.argtypes = [vp, vp]
         L.lelbm_last_failure.argtypes = [vp, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_int)]
@@ -203,6 +204,16 @@ class Lelbm:
             why, sp, res = self.last_failure_detail()
             raise LelbmError(code, "%s at cell %d, step %d (reason %d, species %d, residual %.3e)"
                              % (lib().lelbm_strerror(code).decode(), node, stp, why, sp, res))
+        return st.as_dict()
+
+    def step_noalloc(self, n=1):
+        """lelbm_step_noalloc: the same steps with the library's static scratch
+        array and no allocation."""
+        st = Stats()
+        code = lib().lelbm_step_noalloc(self._h, n, ctypes.byref(st))
+        if code != OK:
+            node, stp = self.last_failure()
+            raise LelbmError(code, "%s at cell %d, step %d" % (lib().lelbm_strerror(code).decode(), node, stp))
         return st.as_dict()
 
     def last_failure_detail(self):

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "lelbm_internal.h"
@@ -611,10 +612,11 @@ static hipError_t do_gather(lelbm_ctx *c, void *) {
     return launch_gather(c->g, c->mixed, c->b.mom[c->cur ^ 1], c->b, c->gcap, c->stream);
 }
 
-// The steps of lelbm_step.  With fixed_scratch the record scratch is that
-// fixed buffer (fixed_cap elements) and nothing is allocated: a step that
-// needs more scratch fails with LELBM_ENOMEM, keeping the state of the last
-// completed step, and no timing events are recorded.
+// The steps of lelbm_step and lelbm_step_noalloc.  With noalloc the record
+// scratch is the caller-independent static array of this GPU (see below)
+// and nothing is allocated: a step that needs more scratch fails with
+// LELBM_ENOMEM, keeping the state of the last completed step, and no timing
+// events are recorded.
 static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scratch, long long fixed_cap) {
     if (!c || nsteps < 0) return LELBM_EINVAL;
     if (c->p.guess == LELBM_GUESS_MLP && !c->mlp_set) return LELBM_EINVAL;
@@ -719,6 +721,45 @@ extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
     return step_impl(c, nsteps, st, nullptr, 0);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free stepping.  The record scratch of lelbm_step_noalloc is this
+// file-scope device array: every GPU the library runs on holds its own copy
+// (allocated with the code object, kept until the process ends).  In host
+// code its name stands for a host-side shadow, not a device address, so the
+// device address is looked up once per device (hipGetSymbolAddress, with the
+// device current) and only that address is ever handed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[LELBM_NOALLOC_SCRATCH_BYTES];
+
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex noalloc_mutex;
+static void *noalloc_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of this device's scratch array (set up on first use).
+static int noalloc_scratch(int dev, void **out) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return LELBM_EDEVICE;
+    std::lock_guard<std::mutex> lock(noalloc_mutex);
+    if (!noalloc_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return LELBM_EDEVICE;
+        noalloc_ptr[dev] = p;
+    }
+    *out = noalloc_ptr[dev];
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_step_noalloc(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
+    if (!c) return LELBM_EINVAL;
+    int dev;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev != c->device) HIPCHECK(hipSetDevice(c->device));
+    void *p = nullptr;
+    int r = noalloc_scratch(c->device, &p);
+    if (r != LELBM_OK) return r;
+    const long long cap = (long long)(LELBM_NOALLOC_SCRATCH_BYTES / (c->mixed ? sizeof(float) : sizeof(double)));
+    return step_impl(c, nsteps, st, p, cap);
+}
 
 // Interior moments as FP64 SoA [nmom][ny][nx]: to the host through the
 // pinned stage (row chunks, widened on the host), or to the device by a
