@@ -98,6 +98,8 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=12000)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--scratch-budget", type=float, default=0,
+                    help="population scratch budget in bytes (0: the library's default)")
     ap.add_argument("--cpu-window", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-context", action="store_true", help="skip the hot-box and channel context runs")
@@ -235,6 +237,8 @@ def timed_run(name, a, lb, torch, cfg, mom0, mlp):
     guess = {"eq": lb.GUESS_EQ, "mlp": lb.GUESS_MLP, "lin": lb.GUESS_LIN, "prev": lb.GUESS_PREV}[name.split("-")[1]]
     stream = torch.cuda.current_stream()
     ctx = lb.Lelbm(cfg, mom0, precision=prec, guess=guess, stream=stream)
+    if a.scratch_budget:
+        ctx.set_scratch_budget(a.scratch_budget)
     if guess == lb.GUESS_MLP:
         ctx.set_mlp(mlp)
     if a.warmup:
@@ -254,8 +258,10 @@ def timed_run(name, a, lb, torch, cfg, mom0, mlp):
     ctx.close()
     ncell = cfg["nx"] * cfg["ny"]
     prec_name = "fp64" if prec == lb.FP64 else "mixed"
-    epr_ms = kt["epr"][0] / max(kt["epr"][1], 1)
-    gat_ms = kt["gather"][0] / max(kt["gather"][1], 1)
+    # per step: the reconstruction and the gather run once per band of the
+    # scratch plan
+    epr_ms = kt["epr"][0] / a.steps
+    gat_ms = kt["gather"][0] / a.steps
     # k_epr handles the cells with unrefined stencils; refined cells go to
     # k_epr_ref (timed apart)
     flops = epr_flops_per_step(st, a.steps)
@@ -266,7 +272,9 @@ def timed_run(name, a, lb, torch, cfg, mom0, mlp):
         "mlups": ncell * a.steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / a.steps,
         "epr_ms": epr_ms, "gather_ms": gat_ms, "epr_flops": flops, "gather_bytes": gbytes,
         "epr_tflops": flops / (epr_ms * 1e-3) / 1e12, "gather_gbs": gbytes / (gat_ms * 1e-3) / 1e9,
-        "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]},
+        "kernels_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in kt.items() if v[1]},
+        "launches_per_step": {k: round(v[1] / a.steps, 2) for k, v in kt.items() if v[1]},
+        "lane_occupancy": round(st["point_passes"] / max(st["wave_point_passes"], 1), 4),
         "newton_it": {"mean_f": round(st["it_mean_f"], 3), "max_f": st["it_max_f"],
                       "mean_g": round(st["it_mean_g"], 3), "max_g": st["it_max_g"]},
         "passes_per_cell": round(st["point_passes"] / max(st["q_mean"], 1e-30) / max(st["cells"], 1), 3),

@@ -172,14 +172,16 @@ int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st);
  * allocation of any kind.  The population scratch of the steps is a static
  * device array of LELBM_NOALLOC_SCRATCH_BYTES that the library holds on
  * every GPU it runs on (until the process ends), instead of the context's
- * own growable buffer; no timing events are recorded (lelbm_set_timing has
- * no effect on this call).  A step whose records need more than that array
- * fails with LELBM_ENOMEM and the context keeps the state of the last
- * completed step (lelbm_last_failure names the step; node = -1).  All calls
- * on one GPU share the array: calls that overlap in time on the same GPU
- * (two contexts on different streams, or two threads) race and must be
- * serialised by the caller.  Results equal those of lelbm_step bit for bit.
- * Error behaviour is otherwise that of lelbm_step. */
+ * own buffer, banded like the context's scratch (see
+ * lelbm_set_scratch_budget) but within the array; no timing events are
+ * recorded (lelbm_set_timing has no effect on this call).  A step whose
+ * bands of a single tile row do not fit the array fails with LELBM_ENOMEM
+ * and the context keeps the state of the last completed step
+ * (lelbm_last_failure names the step; node = -1).  All calls on one GPU
+ * share the array: calls that overlap in time on the same GPU (two contexts
+ * on different streams, or two threads) race and must be serialised by the
+ * caller.  Results equal those of lelbm_step bit for bit.  Error behaviour
+ * is otherwise that of lelbm_step. */
 #define LELBM_NOALLOC_SCRATCH_BYTES (64u << 20)
 int lelbm_step_noalloc(lelbm_ctx *c, int nsteps, lelbm_stats *st);
 
@@ -205,10 +207,12 @@ int lelbm_last_failure_detail(const lelbm_ctx *c, int *reason, int *species, dou
 /* Per-kernel timing: when enabled, lelbm_step records HIP events around each
  * kernel and lelbm_kernel_times returns accumulated milliseconds and launch
  * counts for: [0] pad fill, [1] stencil pre-pass, [2] tile scan,
- * [3] collision + reconstruction of cells with unrefined stencils,
- * [4] moment-streaming gather, [5] unused, [6] unused (the learned guess runs inside the
- * reconstruction kernel [3]),
- * [7] collision + reconstruction of cells with refined stencils.
+ * [3] collision + reconstruction of cells with unrefined stencils (narrow and
+ * wide stencils; one launch pair per band of the scratch plan), [4]
+ * moment-streaming gather (one launch per run of destination rows), [5] step
+ * totals (statistics and arrival counts), [6] unused (the learned guess runs
+ * inside the reconstruction kernel [3]), [7] collision + reconstruction of
+ * cells with refined stencils.
  * n is the capacity of ms and launches (at most LELBM_NTIMERS are filled). */
 #define LELBM_NTIMERS 8
 int lelbm_set_timing(lelbm_ctx *c, int enable);
@@ -219,6 +223,22 @@ int lelbm_kernel_times(const lelbm_ctx *c, double *ms, long *launches, int n);
  * in an eighth of the free device memory, the cache of backward-walk results
  * around the solids) and the transient population scratch. */
 int lelbm_memory(const lelbm_ctx *c, long *persistent_bytes, long *scratch_bytes);
+
+/* Population scratch budget.  The moment fractions of Eq. (IIE3a) exist only
+ * within a step, between the reconstruction of a source and the gather of
+ * its destinations (Sec. II.E).  The library reconstructs the source tiles
+ * in bands of whole tile rows and gathers each destination row as soon as
+ * the bands within its reach are done, reusing the scratch slots of bands
+ * no longer needed; the bands are as wide as the budget allows (one band
+ * when the whole domain's records fit) and are re-planned, before the step
+ * is repeated, when a band outgrows its slot or a stencil reaches farther
+ * than the plan allows for.  The scratch therefore stays within the budget
+ * whatever the temperature, unless a band of a single tile row (16 rows of
+ * cells) needs more, which then sets the scratch size.  Results do not
+ * depend on the banding (bit for bit).  Default LELBM_DEFAULT_SCRATCH_BUDGET
+ * bytes; a budget below the current scratch frees it.  EINVAL for bytes < 1. */
+#define LELBM_DEFAULT_SCRATCH_BUDGET (16ll << 30)
+int lelbm_set_scratch_budget(lelbm_ctx *c, long long bytes);
 
 const char *lelbm_strerror(int code);
 void lelbm_destroy(lelbm_ctx *c);

@@ -90,6 +90,7 @@ def lib():
         L.lelbm_set_timing.argtypes = [vp, ctypes.c_int]
         L.lelbm_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_long), ctypes.c_int]
         L.lelbm_memory.argtypes = [vp, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
+        L.lelbm_set_scratch_budget.argtypes = [vp, ctypes.c_longlong]
         L.lelbm_strerror.argtypes = [ctypes.c_int]
         L.lelbm_strerror.restype = ctypes.c_char_p
         L.lelbm_destroy.argtypes = [vp]
@@ -244,13 +245,16 @@ class Lelbm:
         ms = (ctypes.c_double * 8)()
         ln = (ctypes.c_long * 8)()
         _check(lib().lelbm_kernel_times(self._h, ms, ln, 8))
-        names = ["fill_pads", "prepare", "scan", "epr", "gather", "unused5", "unused6", "epr_ref"]
+        names = ["fill_pads", "prepare", "scan", "epr", "gather", "totals", "unused6", "epr_ref"]
         return {n: (ms[i], ln[i]) for i, n in enumerate(names)}
 
     def memory(self):
         a, b = ctypes.c_long(), ctypes.c_long()
         _check(lib().lelbm_memory(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def set_scratch_budget(self, nbytes):
+        _check(lib().lelbm_set_scratch_budget(self._h, int(nbytes)))
 
     def set_mlp(self, mlp):
         _check(lib().lelbm_set_mlp(self._h, mlp._h))

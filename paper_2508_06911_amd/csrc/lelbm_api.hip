@@ -28,6 +28,49 @@ struct Stage {
     size_t cap = 0;
 };
 
+// ---------------------------------------------------------------------------
+// Band plan of the population scratch.
+//
+// The source tiles are reconstructed in bands of whole tile rows; a band
+// writes its records into one of nslots slots of slot_cap elements, and the
+// gather of a destination tile row runs as soon as every band holding a
+// source within reach of it (m_plan cells, the plan's largest reach) has
+// been reconstructed.  A slot is reused once no pending destination row
+// needs its band.  With a periodic y axis the last band is reconstructed
+// first, so that the first destination rows, which reach across the wrap,
+// are gathered early; the first and the last band then stay live to the end.
+// The scratch is nslots x slot_cap elements, kept within the context's
+// budget: more bands of fewer rows when a band's records outgrow their slot.
+// ---------------------------------------------------------------------------
+enum { OP_EPR = 0, OP_GATHER = 1 };
+struct Op {
+    int kind;    // OP_EPR: reconstruct band a; OP_GATHER: gather destination block rows [a, a + n)
+    int a, n;
+    // what must finish first: a reconstruction into a reused slot waits for
+    // the last gather of the slot's former band (op dep, -1: none); a gather
+    // waits for the reconstructions of the bands it needs (ops
+    // Plan::gdeps[dep, dep + ndep))
+    int dep, ndep;
+};
+
+struct Plan {
+    int rows = 0;              // source tile rows per band (0: not built)
+    int m_plan = 0;            // largest reach (cells) the plan allows for
+    int nslots = 1;
+    long long slot_cap = 0;    // elements per slot
+    std::vector<BandInfo> bands;
+    std::vector<int> slot_of;
+    std::vector<Op> ops;
+    std::vector<int> gdeps;    // reconstruction ops the gathers wait for
+    bool uploaded = false;     // the device band table holds this plan
+    bool whole = false;        // one band of the whole domain because bands of one tile row cost more
+    bool overlap = true;       // a spare slot lets consecutive bands' reconstructions overlap
+    // working arrays of build_plan, reserved at creation so that re-planning
+    // allocates nothing
+    std::vector<int> w_order, w_int;
+    std::vector<char> w_flags;
+};
+
 
 struct lelbm_ctx {
     lelbm_params p;
@@ -59,6 +102,18 @@ struct lelbm_ctx {
     long long persistent_bytes;
     Stage stage;             // pinned host staging memory
     int gcap;                // staged sources per gather chunk
+    long long budget;        // population scratch budget (bytes)
+    Plan plan;               // band plan of lelbm_step (the context's scratch)
+    Plan fixed_plan;         // band plan of lelbm_step_noalloc (the static array)
+    // A banded step reconstructs the narrow and refined stencils of the even
+    // bands on the caller's stream and of the odd bands on side[0], the wide
+    // stencils of every band on side[2] and gathers on side[1] (all streams
+    // at the default priority), so that the long tiles at the end of one
+    // band's reconstruction overlap the next band's and the gathers; two
+    // events per operation of the plan (and one for the step's start) order
+    // the streams.
+    hipStream_t side[3];
+    std::vector<hipEvent_t> opev;
 };
 
 // HIP errors are reported as LELBM_EDEVICE; with LELBM_DEBUG set in the
@@ -191,9 +246,12 @@ static void free_ctx(lelbm_ctx *c) {
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.spans, b.tiles,
                     b.dwin, b.scratch, b.flags, b.stats, b.partial, b.harvest_n,
                     c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, (void *)b.cdist, (void *)b.tdist_s, b.wcache, (void *)b.wslot, b.wbuilt, b.lamprev,
-                    b.bpart, b.gpart, b.order};
+                    b.bpart, b.gpart, b.order, b.bands};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    for (hipEvent_t e : c->opev) (void)hipEventDestroy(e);
+    for (hipStream_t q : c->side)
+        if (q) (void)hipStreamDestroy(q);
     if (c->ev[0]) (void)hipEventDestroy(c->ev[0]);
     if (c->ev[1]) (void)hipEventDestroy(c->ev[1]);
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
@@ -206,9 +264,11 @@ static int reset_flags(lelbm_ctx *c) {
     return LELBM_OK;
 }
 
+// Makes the population scratch hold at least `need` elements (the band
+// plan sizes its slots with room to spare).
 static int grow_scratch(lelbm_ctx *c, long long need) {
     if (need <= c->b.scratch_cap) return LELBM_OK;
-    long long cap = need + need / 4 + 1024;
+    long long cap = need;
     size_t esz = c->mixed ? sizeof(float) : sizeof(double);
     HIPCHECK(hipStreamSynchronize(c->stream));
     if (c->b.scratch) HIPCHECK(hipFree(c->b.scratch));
@@ -286,13 +346,11 @@ static int setup_blockers(lelbm_ctx *c, const unsigned char *mask) {
             cd[(size_t)y * nx + x] = (unsigned short)std::min(v, 65535);
         }
     Buffers &b = c->b;
-    int *dt = nullptr, *mr = nullptr, *dts = nullptr;
+    int *dt = nullptr, *dts = nullptr;
     unsigned short *cdv = nullptr;
     unsigned char *sm = nullptr;
     if (hipMalloc((void **)&dt, (size_t)nd * sizeof(int)) != hipSuccess) return LELBM_ENOMEM;
     b.tdist = dt;
-    if (hipMalloc((void **)&mr, sizeof(int)) != hipSuccess) return LELBM_ENOMEM;
-    b.maxreach = mr;
     if (hipMalloc((void **)&cdv, (size_t)n * sizeof(unsigned short)) != hipSuccess) return LELBM_ENOMEM;
     b.cdist = cdv;
     if (hipMalloc((void **)&dts, (size_t)nd * sizeof(int)) != hipSuccess) return LELBM_ENOMEM;
@@ -360,6 +418,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     if (!c) return LELBM_ENOMEM;
     memset(&c->b, 0, sizeof(c->b));
     c->ev[0] = c->ev[1] = nullptr;
+    c->side[0] = c->side[1] = c->side[2] = nullptr;
     c->mlp_w = nullptr;
     c->mlp_p = nullptr;
     c->mlp_n = nullptr;
@@ -433,6 +492,8 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ok = ok && hipMalloc((void **)&b.harvest_n, sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.bpart, (size_t)2 * nt * sizeof(DevStats)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.order, (size_t)nt * sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.maxreach, sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.bands, (size_t)g.nty * sizeof(BandInfo)) == hipSuccess;
     // arrival partials of the straight gather and of the backward-walk gather
     ok = ok && hipMalloc((void **)&b.gpart, (size_t)2 * gather_blocks_x(g) * gather_blocks_y(g) *
                                                 sizeof(unsigned long long)) == hipSuccess;
@@ -452,14 +513,31 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
                           (b.lamprev ? (long long)16 * ns * sizeof(double) : 0);
     int r = setup_blockers(c, p->solid);
     if (r != LELBM_OK) { free_ctx(c); return r; }
-    if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+    if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side[0], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side[1], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side[2], hipStreamNonBlocking) != hipSuccess) {
         free_ctx(c);
         return LELBM_EDEVICE;
     }
     if (reset_flags(c) != LELBM_OK) { free_ctx(c); return LELBM_EDEVICE; }
-    // pinned staging for flags and statistics, reserved here so that stepping
-    // never has to allocate it
-    if (stage_reserve(c->stage, 4096) != LELBM_OK) { free_ctx(c); return LELBM_ENOMEM; }
+    // pinned staging for flags, statistics and band plans, and room for the
+    // plans' host arrays, reserved here so that stepping never has to
+    // allocate them
+    if (stage_reserve(c->stage, 4096 + (size_t)g.nty * sizeof(BandInfo)) != LELBM_OK) {
+        free_ctx(c);
+        return LELBM_ENOMEM;
+    }
+    for (Plan *P : {&c->plan, &c->fixed_plan}) {
+        P->bands.reserve((size_t)g.nty);
+        P->slot_of.reserve((size_t)g.nty);
+        P->ops.reserve((size_t)4 * g.nty + 8);
+        P->gdeps.reserve((size_t)16 * g.nty + 16);
+        P->w_order.reserve((size_t)g.nty);
+        P->w_int.reserve((size_t)4 * g.nty);
+        P->w_flags.reserve((size_t)4 * g.nty + (size_t)g.dty);
+    }
+    c->budget = LELBM_DEFAULT_SCRATCH_BUDGET;
     *cc = c;
     return LELBM_OK;
 }
@@ -499,6 +577,172 @@ static int upload_interior(lelbm_ctx *c, const void *src, int src_fp32, hipMemcp
     return LELBM_OK;
 }
 
+// Bands of `rows` source tile rows and the schedule of their reconstruction
+// and gathers for a largest reach of M cells (see Plan).
+static void build_plan(const Geom &g, Plan &P, int rows, int M) {
+    const int nty = g.nty, dty = g.dty;
+    rows = std::max(1, std::min(rows, nty));
+    const int nb = (nty + rows - 1) / rows;
+    P.rows = rows;
+    P.whole = false;
+    P.m_plan = nb == 1 ? INT_MAX / 2 : M;
+    P.bands.resize((size_t)nb);
+    P.slot_of.assign((size_t)nb, -1);
+    P.ops.clear();
+    P.gdeps.clear();
+    for (int k = 0; k < nb; k++) {
+        P.bands[k].row0 = k * rows;
+        P.bands[k].row1 = std::min(nty, (k + 1) * rows);
+        P.bands[k].base = 0;
+    }
+    // the bands that hold sources within reach of destination tile row j:
+    // padded cell rows j ty + wb - M ... (j + 1) ty - 1 + wb + M, wrapped on a
+    // periodic axis (mirror images across slip walls lie within that range)
+    const bool pery = g.dim == 2 && g.bc[2] == LELBM_BC_PERIODIC;
+    auto needs = [&](int j, int k) {
+        if (nb == 1) return true;
+        const int y0 = j * g.ty + g.wb - M, y1 = (j + 1) * g.ty - 1 + g.wb + M;
+        const int c0 = P.bands[k].row0 * g.ty, c1 = P.bands[k].row1 * g.ty - 1;   // the band's cell rows
+        if (!pery) return std::max(y0, c0) <= std::min(y1, std::min(c1, g.syn - 1));
+        if (y1 - y0 + 1 >= g.syn) return true;
+        const int a = ((y0 % g.syn) + g.syn) % g.syn, b = ((y1 % g.syn) + g.syn) % g.syn;
+        if (a <= b) return std::max(a, c0) <= std::min(b, c1);
+        return c1 >= a || c0 <= b;
+    };
+    std::vector<int> &order = P.w_order;
+    order.clear();
+    if (pery && nb > 1) order.push_back(nb - 1);
+    for (int k = 0; k < nb; k++)
+        if (!(pery && nb > 1 && k == nb - 1)) order.push_back(k);
+    P.w_flags.assign((size_t)4 * nb + (size_t)dty, 0);
+    char *done = P.w_flags.data(), *live = done + nb, *slot_busy = live + nb, *gathered = slot_busy + 2 * nb;
+    P.w_int.assign((size_t)4 * nb, -1);
+    int *last_gather = P.w_int.data(), *slot_free_op = last_gather + nb, *epr_of = slot_free_op + nb;   // op indices
+    int *freed_at = epr_of + nb;   // iteration that freed a slot
+    int nslots = 0;
+    // destination tile rows -> gather block rows
+    const int bpr = gather_blocks_y(g) / std::max(dty, 1);
+    for (int it = 0; it < nb; it++) {
+        const int k = order[it];
+        // a slot freed by the gathers that followed the previous band's
+        // reconstruction is not reused yet: reusing it would make this
+        // reconstruction wait for those gathers, which wait for the previous
+        // one, and the bands would not overlap (the oldest free slot first)
+        int slot = -1;
+        const int delay = P.overlap ? 2 : 1;
+        for (int sl = 0; sl < nslots; sl++)
+            if (!slot_busy[sl] && freed_at[sl] <= it - delay && (slot < 0 || freed_at[sl] < freed_at[slot])) slot = sl;
+        if (slot < 0) slot = nslots++;
+        slot_busy[slot] = 1;
+        P.slot_of[k] = slot;
+        done[k] = live[k] = 1;
+        epr_of[k] = (int)P.ops.size();
+        P.ops.push_back(Op{OP_EPR, k, 1, slot_free_op[slot], 0});
+        // every destination row whose bands are all reconstructed, in runs
+        int run0 = -1;
+        for (int j = 0; j <= dty; j++) {
+            bool ready = j < dty && !gathered[j];
+            for (int kk = 0; ready && kk < nb; kk++) ready = done[kk] || !needs(j, kk);
+            if (ready) {
+                gathered[j] = 1;
+                if (run0 < 0) run0 = j;
+            } else if (run0 >= 0) {
+                const int gop = (int)P.ops.size();
+                Op op{OP_GATHER, run0 * bpr, (j - run0) * bpr, (int)P.gdeps.size(), 0};
+                for (int kk = 0; kk < nb; kk++) {
+                    bool any = false;
+                    for (int jj = run0; jj < j && !any; jj++) any = needs(jj, kk);
+                    if (!any) continue;
+                    last_gather[kk] = gop;
+                    P.gdeps.push_back(epr_of[kk]);
+                    op.ndep++;
+                }
+                P.ops.push_back(op);
+                run0 = -1;
+            }
+        }
+        // slots of bands no pending destination row needs are free again
+        for (int kk = 0; kk < nb; kk++) {
+            if (!live[kk]) continue;
+            bool used = false;
+            for (int j = 0; j < dty && !used; j++) used = !gathered[j] && needs(j, kk);
+            if (!used) {
+                live[kk] = 0;
+                slot_busy[P.slot_of[kk]] = 0;
+                slot_free_op[P.slot_of[kk]] = last_gather[kk];
+                freed_at[P.slot_of[kk]] = it;
+            }
+        }
+    }
+    P.nslots = std::max(1, nslots);
+    P.uploaded = false;
+}
+
+static void set_bases(Plan &P) {
+    for (size_t k = 0; k < P.bands.size(); k++) P.bands[k].base = (long long)P.slot_of[k] * P.slot_cap;
+    P.uploaded = false;
+}
+
+static int upload_plan(lelbm_ctx *c, Plan &P) {
+    if (P.uploaded) return LELBM_OK;
+    int r = stage_h2d(c->stage, c->stream, c->b.bands, P.bands.data(), P.bands.size() * sizeof(BandInfo));
+    if (r != LELBM_OK) return r;
+    c->plan.uploaded = c->fixed_plan.uploaded = false;   // the device table holds one plan at a time
+    P.uploaded = true;
+    return LELBM_OK;
+}
+
+// After a step found a band's records larger than its slot (err =
+// ERR_OVERFLOW, need = the largest band's elements, total = all bands') or a
+// reach beyond the plan (ERR_REPLAN): the next plan within `limit` elements
+// of scratch.  When even bands of one tile row do not fit, the smaller of
+// one band of the whole domain and bands of one row (the scratch then
+// exceeds the limit); with a fixed scratch that is ENOMEM unless one band
+// fits it.
+static int plan_adapt(const Geom &g, Plan &P, long long limit, bool fixed, int err, long long need, long long total,
+                      int reach) {
+    const int margin = std::max(4, reach / 4);
+    if (P.whole && err == ERR_OVERFLOW) {
+        // stays one band (bands of one row cost more before): it grows
+        if (fixed && need > limit) return LELBM_ENOMEM;
+        P.slot_cap = fixed ? limit : need + need / 4 + 1024;
+    } else if (err == ERR_REPLAN) {
+        build_plan(g, P, P.rows, reach + margin);
+        P.slot_cap = std::min(P.slot_cap, limit / P.nslots);
+    } else if (need <= limit / P.nslots) {
+        P.slot_cap = std::min(limit / P.nslots, need + need / 4 + 1024);
+    } else if (P.rows > 1) {
+        // thinner bands, scaled by the share of a slot the largest band may
+        // take (a thinner plan may keep more bands live at once)
+        const long long per = limit / P.nslots;
+        const int old_rows = P.rows;
+        int rows = (int)std::max(1.0, 0.8 * old_rows * (double)per / (double)need);
+        rows = std::min(rows, old_rows - 1);
+        build_plan(g, P, rows, std::max(P.m_plan == INT_MAX / 2 ? 0 : P.m_plan, reach + margin));
+        const long long est = (long long)((double)need * rows / old_rows * 1.25) + 1024;
+        P.slot_cap = std::min(limit / P.nslots, est);
+    } else if (P.overlap) {
+        // bands of one row without the spare slot (no overlap of consecutive
+        // bands' reconstructions) before giving up the budget
+        P.overlap = false;
+        build_plan(g, P, 1, std::max(P.m_plan == INT_MAX / 2 ? 0 : P.m_plan, reach + margin));
+        P.slot_cap = limit / P.nslots;
+    } else {
+        const long long whole = total + total / 4 + 1024, rowwise = P.nslots * (need + need / 4 + 1024);
+        if (whole <= rowwise || (fixed && whole <= limit)) {
+            if (fixed && whole > limit) return LELBM_ENOMEM;
+            build_plan(g, P, g.nty, 0);
+            P.whole = true;
+            P.slot_cap = fixed ? limit : whole;
+        } else {
+            if (fixed) return LELBM_ENOMEM;
+            P.slot_cap = need + need / 4 + 1024;
+        }
+    }
+    set_bases(P);
+    return LELBM_OK;
+}
+
 static int finish_create(lelbm_ctx *c) {
     // initial scratch: run the pre-pass once to size it
     hipStream_t s = c->stream;
@@ -506,12 +750,34 @@ static int finish_create(lelbm_ctx *c) {
     HIPCHECK(launch_fill_pads(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b.flags, s));
     HIPCHECK(launch_reset_step(c->g, c->b, s));
     HIPCHECK(launch_prepare(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, 0, s));
-    HIPCHECK(launch_scan(c->g, c->b, 0, s));
+    // one band of all rows with an empty slot: the scan reports the records
+    // of the whole domain
+    build_plan(c->g, c->plan, c->g.nty, 0);
+    c->plan.slot_cap = 0;
+    set_bases(c->plan);
+    int rr = upload_plan(c, c->plan);
+    if (rr != LELBM_OK) return rr;
+    HIPCHECK(launch_scan(c->g, c->b, (int)c->plan.bands.size(), c->plan.slot_cap, c->plan.m_plan, 0, s));
     Flags f;
-    int rr = stage_d2h(c->stage, s, &f, c->b.flags, sizeof(Flags));
+    rr = stage_d2h(c->stage, s, &f, c->b.flags, sizeof(Flags));
     if (rr != LELBM_OK) return rr;
     if (f.err == ERR_OVERFLOW) {
-        int r = grow_scratch(c, f.need);
+        // the first plan: one band if the whole domain's records (with a
+        // quarter to spare) fit the budget, else bands sized for about five
+        // slots (the most a periodic plan keeps live with bands wider than
+        // the reach)
+        const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+        const long long limit = std::max<long long>(c->budget / (long long)esz, 1);
+        const long long want = f.need + f.need / 4 + 1024;
+        if (want <= limit) {
+            c->plan.slot_cap = want;
+        } else {
+            const int rows = (int)std::max(1.0, (double)c->g.nty * (double)limit / (5.0 * (double)want));
+            build_plan(c->g, c->plan, rows, f.reach + std::max(4, f.reach / 4));
+            c->plan.slot_cap = limit / c->plan.nslots;
+        }
+        set_bases(c->plan);
+        int r = grow_scratch(c, (long long)c->plan.nslots * c->plan.slot_cap);
         if (r != LELBM_OK) return r;
     } else if (f.err != 0) {
         c->last_fail_node = (long)f.node;
@@ -559,7 +825,9 @@ extern "C" int lelbm_create_device(const lelbm_params *p, const void *dev_moment
     return LELBM_OK;
 }
 
-static int timed(lelbm_ctx *c, int k, hipError_t (*fn)(lelbm_ctx *, void *), void *arg) {
+static int timed(lelbm_ctx *c, int k, hipError_t (*fn)(lelbm_ctx *, void *), void *arg,
+                 hipStream_t st = nullptr) {
+    if (!st) st = c->stream;
     if (!c->timing) {
         HIPCHECK(fn(c, arg));
         return LELBM_OK;
@@ -571,9 +839,9 @@ static int timed(lelbm_ctx *c, int k, hipError_t (*fn)(lelbm_ctx *, void *), voi
         c->evpool.push_back(e);
     }
     if (c->evkind.size() < i + 1) c->evkind.resize(i + 1);
-    HIPCHECK(hipEventRecord(c->evpool[2 * i], c->stream));
+    HIPCHECK(hipEventRecord(c->evpool[2 * i], st));
     HIPCHECK(fn(c, arg));
-    HIPCHECK(hipEventRecord(c->evpool[2 * i + 1], c->stream));
+    HIPCHECK(hipEventRecord(c->evpool[2 * i + 1], st));
     c->evkind[i] = k;
     c->evused = i + 1;
     return LELBM_OK;
@@ -591,7 +859,14 @@ static int collect_times(lelbm_ctx *c) {
     return LELBM_OK;
 }
 
-struct StepArg { int step; };
+struct StepArg {
+    int step;
+    const Plan *plan;
+    int a, n;        // band / block rows of the operation
+    hipStream_t gs;  // stream of the gathers
+    hipStream_t es;  // stream of the operation's reconstruction (narrow and refined stencils)
+    hipStream_t ws;  // stream of the wide stencils' reconstruction
+};
 
 static hipError_t do_fill(lelbm_ctx *c, void *) {
     return launch_fill_pads(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b.flags, c->stream);
@@ -601,22 +876,39 @@ static hipError_t do_prepare(lelbm_ctx *c, void *a) {
     if (e != hipSuccess) return e;
     return launch_prepare(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
 }
-static hipError_t do_scan(lelbm_ctx *c, void *a) { return launch_scan(c->g, c->b, ((StepArg *)a)->step, c->stream); }
+static hipError_t do_scan(lelbm_ctx *c, void *a) {
+    const StepArg &s = *(StepArg *)a;
+    return launch_scan(c->g, c->b, (int)s.plan->bands.size(), s.plan->slot_cap, s.plan->m_plan, s.step, c->stream);
+}
 static hipError_t do_epr(lelbm_ctx *c, void *a) {
-    return launch_epr(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
+    const StepArg &s = *(StepArg *)a;
+    const BandInfo &bd = s.plan->bands[s.a];
+    return launch_epr(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
+                      (bd.row1 - bd.row0) * c->g.ntx, 0, s.es);
+}
+static hipError_t do_epr_wide(lelbm_ctx *c, void *a) {
+    const StepArg &s = *(StepArg *)a;
+    const BandInfo &bd = s.plan->bands[s.a];
+    return launch_epr(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
+                      (bd.row1 - bd.row0) * c->g.ntx, 1, s.ws);
 }
 static hipError_t do_epr_ref(lelbm_ctx *c, void *a) {
-    return launch_epr_ref(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
+    const StepArg &s = *(StepArg *)a;
+    const BandInfo &bd = s.plan->bands[s.a];
+    return launch_epr_ref(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
+                          (bd.row1 - bd.row0) * c->g.ntx, s.es);
 }
-static hipError_t do_gather(lelbm_ctx *c, void *) {
-    return launch_gather(c->g, c->mixed, c->b.mom[c->cur ^ 1], c->b, c->gcap, c->stream);
+static hipError_t do_gather(lelbm_ctx *c, void *a) {
+    const StepArg &s = *(StepArg *)a;
+    return launch_gather(c->g, c->mixed, c->b.mom[c->cur ^ 1], c->b, c->gcap, s.a, s.n, s.gs);
 }
+static hipError_t do_totals(lelbm_ctx *c, void *) { return launch_step_totals(c->g, c->b, c->stream); }
 
-// The steps of lelbm_step and lelbm_step_noalloc.  With noalloc the record
-// scratch is the caller-independent static array of this GPU (see below)
-// and nothing is allocated: a step that needs more scratch fails with
-// LELBM_ENOMEM, keeping the state of the last completed step, and no timing
-// events are recorded.
+// The steps of lelbm_step and lelbm_step_noalloc.  With fixed_scratch the
+// record scratch is that fixed buffer (fixed_cap elements, with its own band
+// plan) and nothing is allocated: a step whose bands of one tile row do not
+// fit fails with LELBM_ENOMEM, keeping the state of the last completed step,
+// and no timing events are recorded.
 static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scratch, long long fixed_cap) {
     if (!c || nsteps < 0) return LELBM_EINVAL;
     if (c->p.guess == LELBM_GUESS_MLP && !c->mlp_set) return LELBM_EINVAL;
@@ -643,22 +935,87 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
             c->timing = timing;
         }
     } keep{c, noalloc, c->b.scratch, c->b.scratch_cap, c->timing};
+    Plan &P = noalloc ? c->fixed_plan : c->plan;
+    const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+    const long long limit = noalloc ? fixed_cap : std::max<long long>(c->budget / (long long)esz, 1);
     if (noalloc) {
         c->b.scratch = fixed_scratch;
         c->b.scratch_cap = fixed_cap;
         c->timing = 0;
+        if (P.rows == 0) {
+            // first call: the context's own plan, its slots shrunk to the array
+            P = c->plan;
+            P.slot_cap = std::min(P.slot_cap, limit / P.nslots);
+            set_bases(P);
+        }
     }
+    if ((r = upload_plan(c, P)) != LELBM_OK) return r;
     int base = 0;   // first step not known to be complete
     while (base < nsteps) {
         int cur0 = c->cur;
+        // banded plans run on four streams; a plan of one band, or a
+        // no-alloc call without enough events, runs on the caller's stream.
+        // Events: 2 i after the narrow and refined stencils (or the gather)
+        // of op i, 2 i + 1 after its wide stencils, 2 nops at the step's
+        // start.
+        const size_t nops = P.ops.size();
+        if (!noalloc && nops > 2) {
+            while (c->opev.size() < 2 * nops + 1) {
+                hipEvent_t e;
+                HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                c->opev.push_back(e);
+            }
+        }
+        const bool multi = nops > 2 && c->opev.size() >= 2 * nops + 1;
         for (int k = base; k < nsteps; k++) {
-            StepArg a{k};
+            StepArg a{k, &P, 0, 0, multi ? c->side[1] : s, s, multi ? c->side[2] : s};
             if ((r = timed(c, 0, do_fill, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 1, do_prepare, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 2, do_scan, &a)) != LELBM_OK) return r;
-            if ((r = timed(c, 3, do_epr, &a)) != LELBM_OK) return r;
-            if ((r = timed(c, 7, do_epr_ref, &a)) != LELBM_OK) return r;
-            if ((r = timed(c, 4, do_gather, &a)) != LELBM_OK) return r;
+            if (multi) {
+                HIPCHECK(hipEventRecord(c->opev[2 * nops], s));   // the step's descriptors and plan are ready
+                HIPCHECK(hipStreamWaitEvent(c->side[0], c->opev[2 * nops], 0));
+                HIPCHECK(hipStreamWaitEvent(c->side[2], c->opev[2 * nops], 0));
+            }
+            int last_odd = -1, last_wide = -1;
+            for (size_t i = 0; i < nops; i++) {
+                const Op &op = P.ops[i];
+                a.a = op.a;
+                a.n = op.n;
+                if (op.kind == OP_EPR) {
+                    a.es = multi && (op.a & 1) ? c->side[0] : s;
+                    if (multi && op.dep >= 0) {
+                        HIPCHECK(hipStreamWaitEvent(a.es, c->opev[2 * op.dep], 0));
+                        HIPCHECK(hipStreamWaitEvent(a.ws, c->opev[2 * op.dep], 0));
+                    }
+                    if ((r = timed(c, 3, do_epr, &a, a.es)) != LELBM_OK) return r;
+                    if ((r = timed(c, 7, do_epr_ref, &a, a.es)) != LELBM_OK) return r;
+                    if ((r = timed(c, 3, do_epr_wide, &a, a.ws)) != LELBM_OK) return r;
+                    if (multi) {
+                        HIPCHECK(hipEventRecord(c->opev[2 * i], a.es));
+                        HIPCHECK(hipEventRecord(c->opev[2 * i + 1], a.ws));
+                        if (op.a & 1) last_odd = (int)i;
+                        last_wide = (int)i;
+                    }
+                } else {
+                    if (multi)
+                        for (int d = 0; d < op.ndep; d++) {
+                            const int e = P.gdeps[op.dep + d];
+                            HIPCHECK(hipStreamWaitEvent(c->side[1], c->opev[2 * e], 0));
+                            HIPCHECK(hipStreamWaitEvent(c->side[1], c->opev[2 * e + 1], 0));
+                        }
+                    if ((r = timed(c, 4, do_gather, &a, a.gs)) != LELBM_OK) return r;
+                    if (multi) HIPCHECK(hipEventRecord(c->opev[2 * i], c->side[1]));
+                }
+            }
+            if (multi) {
+                // the step's totals (and the next step) after the last gather
+                // and the last reconstructions of the side streams
+                HIPCHECK(hipStreamWaitEvent(s, c->opev[2 * (nops - 1)], 0));
+                if (last_odd >= 0) HIPCHECK(hipStreamWaitEvent(s, c->opev[2 * last_odd], 0));
+                if (last_wide >= 0) HIPCHECK(hipStreamWaitEvent(s, c->opev[2 * last_wide + 1], 0));
+            }
+            if ((r = timed(c, 5, do_totals, &a)) != LELBM_OK) return r;
             c->cur ^= 1;
         }
         Flags f;
@@ -668,17 +1025,36 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
         // every kernel after the failing one returned early, so the state at
         // the start of step f.step is intact
         c->cur = (cur0 + (f.step - base)) & 1;
-        if (f.err != ERR_OVERFLOW || noalloc) {
-            c->last_fail_node = f.err == ERR_OVERFLOW ? -1 : (long)f.node;
+        if (f.err == ERR_OVERFLOW || f.err == ERR_REPLAN) {
+            // re-plan the bands (and grow the context's scratch within its
+            // budget), then repeat the step
+            r = plan_adapt(c->g, P, limit, noalloc, f.err, f.need, f.total, f.reach);
+            if (getenv("LELBM_DEBUG"))
+                fprintf(stderr,
+                        "lelbm: step %d %s (need %lld, total %lld, reach %d): %zu bands of %d rows, %d slots of "
+                        "%lld elements, reach %d\n",
+                        f.step, f.err == ERR_REPLAN ? "re-plan" : "overflow", f.need, f.total, f.reach,
+                        P.bands.size(), P.rows, P.nslots, P.slot_cap, P.m_plan);
+            if (r == LELBM_OK && !noalloc) r = grow_scratch(c, (long long)P.nslots * P.slot_cap);
+            if (r == LELBM_OK) r = upload_plan(c, P);
+            if (r == LELBM_OK) r = reset_flags(c);
+            if (r == LELBM_OK) {
+                base = f.step;
+                continue;
+            }
+            c->last_fail_node = -1;
             c->last_fail_step = f.step;
-            c->last_fail_detail = f.detail;
-            c->last_fail_species = f.species;
-            c->last_fail_residual = f.residual;
-            return f.err == ERR_OVERFLOW ? LELBM_ENOMEM : f.err;
+            c->last_fail_detail = 0;
+            c->last_fail_species = -1;
+            c->last_fail_residual = 0.0;
+            return r;
         }
-        if ((r = grow_scratch(c, f.need)) != LELBM_OK) return r;
-        if ((r = reset_flags(c)) != LELBM_OK) return r;
-        base = f.step;
+        c->last_fail_node = (long)f.node;
+        c->last_fail_step = f.step;
+        c->last_fail_detail = f.detail;
+        c->last_fail_species = f.species;
+        c->last_fail_residual = f.residual;
+        return f.err;
     }
     if (st) {
         HIPCHECK(launch_sums(c->g, c->mixed, c->b.mom[c->cur], c->b, s));
@@ -832,6 +1208,26 @@ extern "C" int lelbm_kernel_times(const lelbm_ctx *c, double *ms, long *launches
         if (ms) ms[k] = c->kms[k];
         if (launches) launches[k] = c->klaunch[k];
     }
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_set_scratch_budget(lelbm_ctx *c, long long bytes) {
+    if (!c || bytes < 1) return LELBM_EINVAL;
+    c->budget = bytes;
+    const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+    const long long limit = std::max<long long>(bytes / (long long)esz, 1);
+    // the plan starts again from one band of the whole domain (the next step
+    // re-plans within the budget); a scratch beyond the budget is freed
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    if (c->b.scratch_cap > limit) {
+        if (c->b.scratch) HIPCHECK(hipFree(c->b.scratch));
+        c->b.scratch = nullptr;
+        c->b.scratch_cap = 0;
+    }
+    c->plan.overlap = true;
+    build_plan(c->g, c->plan, c->g.nty, 0);
+    c->plan.slot_cap = std::min(c->b.scratch_cap, limit);
+    set_bases(c->plan);
     return LELBM_OK;
 }
 

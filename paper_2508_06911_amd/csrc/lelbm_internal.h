@@ -47,9 +47,21 @@ constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 1024, MLP_OFF_W2 = 1088, MLP_OFF_B2 =
               MLP_OFF_B3 = 6272, MLP_NPARAM = 6288;
 constexpr int MLP_NORM = 64;   // standardisation constants (input/output mean and scale)
 
-// Internal error code: population scratch too small (the host grows it and
-// repeats the step).
+// Internal error codes: a band's population records exceed their scratch
+// slot (the host grows the slots or re-plans the bands and repeats the step);
+// a stencil reaches farther than the band plan allows for (the host re-plans
+// and repeats the step).
 constexpr int ERR_OVERFLOW = -100;
+constexpr int ERR_REPLAN = -101;
+
+// The source tiles are reconstructed in bands of whole tile rows, each
+// writing its records into one slot of the population scratch (the slots
+// are reused as the gather consumes them), so the scratch is bounded by a
+// budget instead of growing with the stencils of the whole domain.
+struct BandInfo {
+    int row0, row1;          // source tile rows [row0, row1)
+    long long base;          // first scratch element of the band's slot
+};
 
 struct Geom {
     int dim, nx, ny;
@@ -92,6 +104,8 @@ struct Flags {
     int detail;              // reason of an LELBM_EEPR failure (see lelbm_last_failure_detail)
     int species;             // 0 fluon, 1 phonon
     double residual;         // last scaled moment residual of the failing solve
+    int reach;               // the step's largest reach (with ERR_OVERFLOW, ERR_REPLAN)
+    long long total;         // elements of all bands' records (with ERR_OVERFLOW)
 };
 
 struct DevStats {
@@ -131,7 +145,7 @@ struct Buffers {
                              // tile, so a wavefront reads one row of its 64 cells in one line (k_epr)
     TileInfo *tiles;         // [ntx*nty]
     DWin *dwin;              // [dtx*dty]
-    void *scratch;           // population scratch
+    void *scratch;           // population scratch (the bands' slots)
     long long scratch_cap;   // elements
     Flags *flags;
     DevStats *stats;
@@ -155,6 +169,7 @@ struct Buffers {
     const int *tdist;              // [dtx*dty] Chebyshev distance from the tile to the nearest
                                    // blocker (solid cell or the cell beyond a slip wall); NULL = none
     int *maxreach;                 // max over sources of max(|round(u)|) + R + 1 (this step)
+    BandInfo *bands;               // [nty] the band plan of the population scratch
     const unsigned short *cdist;   // [ny][nx] the same distance per cell (capped at 65535)
     const int *tdist_s;            // [dtx*dty] Chebyshev distance from the tile to the nearest solid cell
     // backward-walk results (the geometry is fixed, so a walk's result never
@@ -169,12 +184,19 @@ struct Buffers {
 hipError_t launch_fill_pads(const Geom &g, const Phys &ph, int mixed, void *mom, Flags *fl, hipStream_t s);
 hipError_t launch_prepare(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
                           hipStream_t s);
-hipError_t launch_scan(const Geom &g, Buffers &b, int step, hipStream_t s);
-hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
-                      hipStream_t s);
+hipError_t launch_scan(const Geom &g, Buffers &b, int nbands, long long slot_cap, int m_plan, int step,
+                       hipStream_t s);
+// reconstruction of the tiles [tile0, tile0 + ntiles) of the scan's order:
+// the cells with narrow stencils, or (wide != 0) those with wide ones
+hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step, int tile0,
+                      int ntiles, int wide, hipStream_t s);
 hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
-                          hipStream_t s);
-hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, int gcap, hipStream_t s);
+                          int tile0, int ntiles, hipStream_t s);
+// gather of the destination block rows [br0, br0 + nbr)
+hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, int gcap, int br0, int nbr,
+                         hipStream_t s);
+// statistics and arrival counts of a step (after its last gather)
+hipError_t launch_step_totals(const Geom &g, Buffers &b, hipStream_t s);
 hipError_t launch_sums(const Geom &g, int mixed, const void *mom, Buffers &b, hipStream_t s);
 hipError_t launch_reset_step(const Geom &g, Buffers &b, hipStream_t s);
 hipError_t launch_reset_stats(Buffers &b, hipStream_t s);

@@ -362,98 +362,125 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan of tile sizes (one workgroup)
+// record offsets and k_epr's tile order, band by band (one workgroup)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_scan(int ntiles, TileInfo *tiles, Flags *fl, long long cap, int step,
-                                               int *order) {
+__global__ void __launch_bounds__(1024) k_scan(int ntx, int nbands, const BandInfo *bands, TileInfo *tiles,
+                                               Flags *fl, long long slot_cap, int step, int *order,
+                                               const int *maxreach, int m_plan) {
     // 16 wavefronts: scans within a wavefront by shuffles and ballots, across
     // the wavefronts of a 1024-tile chunk through LDS
     __shared__ long long s_wave[16];
     __shared__ int s_cnt[16][3];
-    __shared__ long long s_carry;
+    __shared__ long long s_carry, s_need, s_total;
     __shared__ int s_class[3], s_run[3];
     if (fl->err) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (threadIdx.x == 0) s_carry = 0;
-    if (threadIdx.x < 3) s_class[threadIdx.x] = s_run[threadIdx.x] = 0;
-    __syncthreads();
-    // record offsets: exclusive scan of the tile sizes
-    for (int c0 = 0; c0 < ntiles; c0 += 1024) {
-        const int i = c0 + threadIdx.x;
-        const long long v = i < ntiles ? tiles[i].size : 0;
-        long long incl = v;
-        for (int off = 1; off < 64; off <<= 1) {
-            const long long o = __shfl_up(incl, off);
-            if (lane >= off) incl += o;
+    if (threadIdx.x == 0) s_need = s_total = 0;
+    for (int bd = 0; bd < nbands; bd++) {
+        // the band's tiles: whole source tile rows [row0, row1), records from
+        // its scratch slot's first element
+        const BandInfo band = bands[bd];
+        const int t0 = band.row0 * ntx, nt = (band.row1 - band.row0) * ntx;
+        if (threadIdx.x == 0) s_carry = 0;
+        if (threadIdx.x < 3) s_class[threadIdx.x] = s_run[threadIdx.x] = 0;
+        __syncthreads();
+        // record offsets: exclusive scan of the tile sizes
+        for (int c0 = 0; c0 < nt; c0 += 1024) {
+            const int i = c0 + threadIdx.x;
+            const long long v = i < nt ? tiles[t0 + i].size : 0;
+            long long incl = v;
+            for (int off = 1; off < 64; off <<= 1) {
+                const long long o = __shfl_up(incl, off);
+                if (lane >= off) incl += o;
+            }
+            if (lane == 63) s_wave[w] = incl;
+            __syncthreads();
+            long long wbase = 0, ctot = 0;
+            for (int k = 0; k < 16; k++) {
+                const long long sk = s_wave[k];
+                wbase += k < w ? sk : 0;
+                ctot += sk;
+            }
+            if (i < nt) tiles[t0 + i].base = band.base + s_carry + wbase + incl - v;
+            __syncthreads();
+            if (threadIdx.x == 0) s_carry += ctot;
+            __syncthreads();
         }
-        if (lane == 63) s_wave[w] = incl;
-        __syncthreads();
-        long long wbase = 0, ctot = 0;
-        for (int k = 0; k < 16; k++) {
-            const long long sk = s_wave[k];
-            wbase += k < w ? sk : 0;
-            ctot += sk;
+        const long long total = s_carry;
+        if (threadIdx.x == 0) {
+            s_need = total > s_need ? total : s_need;
+            s_total += total;
         }
-        if (i < ntiles) tiles[i].base = s_carry + wbase + incl - v;
+        // Order in which k_epr takes the band's tiles: the heaviest first (a
+        // tile's records measure its stencil work), so that the long ones do
+        // not start last and leave the CUs idle at the end.  Stable partition
+        // into tiles with at least twice the mean size, at least the mean, and
+        // the rest: the class sizes first, then each tile's place.  Worth it
+        // only while a launch spans few rounds of resident workgroups: with
+        // many tiles the tail is short and the index order writes the records
+        // more locally (measured: 16K tiles -9 % k_epr time, 33K about even,
+        // 131K +4 %).
+        if (nt > EPR_ORDER_MAX_TILES) {
+            for (int i = threadIdx.x; i < nt; i += 1024) order[t0 + i] = t0 + i;
+            __syncthreads();
+            continue;
+        }
+        const auto class_of = [&](int i) {
+            const long long v = tiles[t0 + i].size * (long long)nt;
+            return v >= 2 * total ? 0 : (v >= total ? 1 : 2);
+        };
+        for (int c0 = 0; c0 < nt; c0 += 1024) {
+            const int i = c0 + threadIdx.x;
+            const int c = i < nt ? class_of(i) : -1;
+            for (int k = 0; k < 3; k++) {
+                const unsigned long long m = __ballot(c == k);
+                if (lane == 0 && m) atomicAdd(&s_class[k], __popcll(m));
+            }
+        }
         __syncthreads();
-        if (threadIdx.x == 0) s_carry += ctot;
-        __syncthreads();
+        const int cbase[3] = {0, s_class[0], s_class[0] + s_class[1]};
+        for (int c0 = 0; c0 < nt; c0 += 1024) {
+            const int i = c0 + threadIdx.x;
+            const int c = i < nt ? class_of(i) : -1;
+            int rank = 0;
+            for (int k = 0; k < 3; k++) {
+                const unsigned long long m = __ballot(c == k);
+                if (c == k) rank = __popcll(m & ((1ull << lane) - 1ull));
+                if (lane == 0) s_cnt[w][k] = __popcll(m);
+            }
+            __syncthreads();
+            if (c >= 0) {
+                int woff = 0;
+                for (int k = 0; k < w; k++) woff += s_cnt[k][c];
+                order[t0 + cbase[c] + s_run[c] + woff + rank] = t0 + i;
+            }
+            __syncthreads();
+            if (threadIdx.x < 3) {
+                int t = 0;
+                for (int k = 0; k < 16; k++) t += s_cnt[k][threadIdx.x];
+                s_run[threadIdx.x] += t;
+            }
+            __syncthreads();
+        }
     }
-    const long long total = s_carry;
-    if (threadIdx.x == 0 && total > cap) {
-        if (atomicCAS(&fl->err, 0, ERR_OVERFLOW) == 0) {
-            fl->need = total;
-            fl->step = step;
+    // a band's records exceed its slot, or a stencil reaches farther than the
+    // band plan allows for: the host re-plans and repeats the step
+    if (threadIdx.x == 0) {
+        const int M = *maxreach;
+        if (s_need > slot_cap) {
+            if (atomicCAS(&fl->err, 0, ERR_OVERFLOW) == 0) {
+                fl->need = s_need;
+                fl->total = s_total;
+                fl->reach = M;
+                fl->step = step;
+            }
+        } else if (M > m_plan) {
+            if (atomicCAS(&fl->err, 0, ERR_REPLAN) == 0) {
+                fl->need = M;
+                fl->reach = M;
+                fl->step = step;
+            }
         }
-    }
-    // Order in which k_epr takes the tiles: the heaviest first (a tile's
-    // records measure its stencil work), so that the long ones do not start
-    // last and leave the CUs idle at the end.  Stable partition into tiles
-    // with at least twice the mean size, at least the mean, and the rest:
-    // the class sizes first, then each tile's place.  Worth it only while a
-    // launch spans few rounds of resident workgroups: with many tiles the
-    // tail is short and the index order writes the records more locally
-    // (measured: 16K tiles -9 % k_epr time, 33K about even, 131K +4 %).
-    if (ntiles > EPR_ORDER_MAX_TILES) {
-        for (int i = threadIdx.x; i < ntiles; i += 1024) order[i] = i;
-        return;
-    }
-    const auto class_of = [&](int i) {
-        const long long v = tiles[i].size * (long long)ntiles;
-        return v >= 2 * total ? 0 : (v >= total ? 1 : 2);
-    };
-    for (int c0 = 0; c0 < ntiles; c0 += 1024) {
-        const int i = c0 + threadIdx.x;
-        const int c = i < ntiles ? class_of(i) : -1;
-        for (int k = 0; k < 3; k++) {
-            const unsigned long long m = __ballot(c == k);
-            if (lane == 0 && m) atomicAdd(&s_class[k], __popcll(m));
-        }
-    }
-    __syncthreads();
-    const int cbase[3] = {0, s_class[0], s_class[0] + s_class[1]};
-    for (int c0 = 0; c0 < ntiles; c0 += 1024) {
-        const int i = c0 + threadIdx.x;
-        const int c = i < ntiles ? class_of(i) : -1;
-        int rank = 0;
-        for (int k = 0; k < 3; k++) {
-            const unsigned long long m = __ballot(c == k);
-            if (c == k) rank = __popcll(m & ((1ull << lane) - 1ull));
-            if (lane == 0) s_cnt[w][k] = __popcll(m);
-        }
-        __syncthreads();
-        if (c >= 0) {
-            int woff = 0;
-            for (int k = 0; k < w; k++) woff += s_cnt[k][c];
-            order[cbase[c] + s_run[c] + woff + rank] = i;
-        }
-        __syncthreads();
-        if (threadIdx.x < 3) {
-            int t = 0;
-            for (int k = 0; k < 16; k++) t += s_cnt[k][threadIdx.x];
-            s_run[threadIdx.x] += t;
-        }
-        __syncthreads();
     }
 }
 
@@ -931,7 +958,7 @@ struct StatSum {
             StatSum o;
             o.itf = __shfl_xor(itf, off); o.itg = __shfl_xor(itg, off); o.q = __shfl_xor(q, off);
             o.lim = __shfl_xor(lim, off); o.cells = __shfl_xor(cells, off); o.qp = __shfl_xor(qp, off);
-            o.qpr = __shfl_xor(qpr, off); o.fb = __shfl_xor(fb, off);
+            o.qpr = __shfl_xor(qpr, off); o.fb = __shfl_xor(fb, off); o.wq = __shfl_xor(wq, off);
             o.mitf = __shfl_xor(mitf, off); o.mitg = __shfl_xor(mitg, off); o.mq = __shfl_xor(mq, off);
             o.nq = __shfl_xor(nq, off);
             o.mkn = __shfl_xor(mkn, off); o.mcolat = __shfl_xor(mcolat, off); o.nrt = __shfl_xor(nrt, off);
@@ -1207,7 +1234,7 @@ __device__ inline bool row_start_ok(double f, double r, double s2, double gv, do
 // otherwise the other unrefined cells, whose rows are short enough to run
 // each recurrence from one start.
 template <typename T, int D, bool WIDE>
-__global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, Buffers b, int step) {
+__global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, Buffers b, int step, int tile0) {
     using BS = Basis<D>;
     constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
     // Per-point arithmetic stays FP64 in both paths: without packed FP32 math
@@ -1218,8 +1245,9 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
     using W = double;
     __shared__ double s_lamf[NF * TILE_N], s_delf[NF * TILE_N], s_lamg[NG * TILE_N], s_delg[NG * TILE_N];
     __shared__ int s_err;
-    const int t = b.order[blockIdx.x];        // heaviest tiles first (k_scan)
-    DevStats *part = b.bpart + (WIDE ? (long long)g.ntx * g.nty : 0);
+    // a band's tiles from tile0 on, heaviest first (k_scan)
+    const int t = b.order[tile0 + blockIdx.x];
+    DevStats *part = b.bpart + (WIDE ? (long long)g.ntx * g.nty : 0) + tile0;
     if (threadIdx.x == 0) s_err = b.flags->err || (WIDE && !b.tiles[t].wide);
     __syncthreads();
     if (s_err) {
@@ -1543,11 +1571,11 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
 // refined cells.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, Buffers b, int step) {
+__global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, Buffers b, int step, int tile0) {
     using BS = Basis<D>;
     constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
     __shared__ int s_skip;
-    int t = blockIdx.x;
+    int t = tile0 + blockIdx.x;
     if (threadIdx.x == 0) s_skip = b.flags->err || b.tiles[t].fmt == 0;
     __syncthreads();
     if (s_skip) return;
@@ -1863,7 +1891,8 @@ constexpr int META_FX = 1 << 8, META_FY = 1 << 9, META_REF = 1 << 10;
 // wavefronts per SIMD at FP32 (the LDS of five workgroups fits a CU); the
 // FP64 variant needs more registers and keeps four.
 template <typename T, int D, bool WALLS>
-__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, T *mom_out, Buffers b, int gcap) {
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, T *mom_out, Buffers b, int gcap,
+                                                                       int br0, int nbr) {
     constexpr int NM = Basis<D>::NMOM;
     extern __shared__ double2 g_lds[];
     double2 *s_u = g_lds;
@@ -1872,8 +1901,9 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     __shared__ int s_err, s_ref;
     if (threadIdx.x == 0) s_err = b.flags->err;
     __syncthreads();
+    const int nbx = gather_blocks_x(g);
     if (s_err) {
-        if (threadIdx.x == 0) b.gpart[blockIdx.x] = 0ull;
+        if (threadIdx.x == 0) b.gpart[(long long)br0 * nbx + blockIdx.x] = 0ull;
         return;
     }
     // Destination block of a workgroup: in 2D a GATHER_NTB x 16 wide and
@@ -1885,21 +1915,21 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     constexpr int TX = tile_x<D>(), TY = tile_y<D>();
     constexpr int NTB = D == 2 ? GATHER_NTB : 1;
     constexpr int BX = NTB * TX, BY = TY / NTB;
-    const int nbx = gather_blocks_x(g), nby = gather_blocks_y(g);
-    // Workgroups go to the 8 XCDs in turn.  Deal whole block rows to the XCDs
-    // instead (row r to XCD r mod 8, in order), so that x-neighbour blocks,
-    // which read the two halves of the record lines on their common edge, run
-    // on the same XCD at about the same time and the second read hits its L2;
-    // rows that do not fill a round of 8 keep the plain order.
+    // The launch covers block rows [br0, br0 + nbr).  Workgroups go to the 8
+    // XCDs in turn.  Deal whole block rows to the XCDs instead (row r to XCD
+    // r mod 8, in order), so that x-neighbour blocks, which read the two
+    // halves of the record lines on their common edge, run on the same XCD at
+    // about the same time and the second read hits its L2; rows that do not
+    // fill a round of 8 keep the plain order.
     int t = blockIdx.x;
     {
-        const int full = nby / 8 * 8 * nbx;
+        const int full = nbr / 8 * 8 * nbx;
         if (t < full) {
             const int k = t & 7, i = t >> 3;
             t = (i / nbx * 8 + k) * nbx + i % nbx;
         }
     }
-    const int x0 = (t % nbx) * BX, y0 = (t / nbx) * BY;
+    const int x0 = (t % nbx) * BX, y0 = (br0 + t / nbx) * BY;
     int lx, ly;                                  // the lane's cell in the block
     if (D == 2) {
         const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -2115,7 +2145,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     for (int off = 32; off > 0; off >>= 1) hl += __shfl_xor(hl, off);
     if ((threadIdx.x & 63) == 0) s_hits[threadIdx.x >> 6] = hl;
     __syncthreads();
-    if (threadIdx.x == 0) b.gpart[blockIdx.x] = s_hits[0] + s_hits[1] + s_hits[2] + s_hits[3];
+    if (threadIdx.x == 0) b.gpart[(long long)br0 * nbx + blockIdx.x] = s_hits[0] + s_hits[1] + s_hits[2] + s_hits[3];
 }
 
 // Destination tiles within reach of a blocker (the ones k_gather leaves
@@ -2130,14 +2160,15 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
 // reads them instead.  Candidates go in batches of GU so that the descriptor
 // loads of a batch are in flight together.
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers b, int mapb) {
+__global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers b, int mapb, int br0) {
     constexpr int NM = Basis<D>::NMOM;
     constexpr int TX = tile_x<D>(), TY = tile_y<D>();
     constexpr int NTB = D == 2 ? GATHER_NTB : 1;
     constexpr int BX = NTB * TX, BY = TY / NTB;
     extern __shared__ double2 g_lds[];
+    // the launch covers block rows from br0 on
     const int nbx = gather_blocks_x(g), nd = nbx * gather_blocks_y(g);
-    const int x0 = (blockIdx.x % nbx) * BX, y0 = (blockIdx.x / nbx) * BY;
+    const int x0 = (blockIdx.x % nbx) * BX, y0 = (br0 + blockIdx.x / nbx) * BY;
     int lx, ly;
     if (D == 2) {
         const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -2350,7 +2381,7 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers
     for (int off = 32; off > 0; off >>= 1) hl += __shfl_xor(hl, off);
     if ((threadIdx.x & 63) == 0) s_hits[threadIdx.x >> 6] = hl;
     __syncthreads();
-    if (threadIdx.x == 0) b.gpart[nd + blockIdx.x] = s_hits[0] + s_hits[1] + s_hits[2] + s_hits[3];
+    if (threadIdx.x == 0) b.gpart[nd + (long long)br0 * nbx + blockIdx.x] = s_hits[0] + s_hits[1] + s_hits[2] + s_hits[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -2402,7 +2433,7 @@ __global__ void __launch_bounds__(256) k_store_interior(Geom g, int nmom, const 
 __global__ void k_reset_flags(Flags *f) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         f->err = 0; f->step = -1; f->node = LLONG_MAX; f->need = 0;
-        f->detail = 0; f->species = -1; f->residual = 0.0;
+        f->detail = 0; f->species = -1; f->residual = 0.0; f->reach = 0; f->total = 0;
     }
 }
 
@@ -2599,48 +2630,47 @@ hipError_t launch_prepare(const Geom &g, const Phys &ph, int mixed, const void *
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const Geom &g, Buffers &b, int step, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, g.ntx * g.nty, b.tiles, b.flags, b.scratch_cap, step,
-                       b.order);
+hipError_t launch_scan(const Geom &g, Buffers &b, int nbands, long long slot_cap, int m_plan, int step,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, g.ntx, nbands, (const BandInfo *)b.bands, b.tiles, b.flags,
+                       slot_cap, step, b.order, (const int *)b.maxreach, m_plan);
     return hipGetLastError();
 }
 
-template <typename T>
-static void epr_launch(const Geom &g, const Phys &ph, const void *mom, Buffers &b, int step, int refined,
-                       hipStream_t s) {
-    unsigned nt = (unsigned)(g.ntx * g.nty);
-    if (g.dim == 1) {
-        if (refined) {
-            hipLaunchKernelGGL((k_epr_ref<T, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
-        } else {
-            hipLaunchKernelGGL((k_epr<T, 1, false>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
-            hipLaunchKernelGGL((k_epr<T, 1, true>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
-        }
+// variant 0: cells with narrow stencils, 1: refined stencils, 2: wide
+template <typename T, int D>
+static void epr_launch(const Geom &g, const Phys &ph, const void *mom, Buffers &b, int step, int variant, int tile0,
+                       int ntiles, hipStream_t s) {
+    const dim3 grid((unsigned)ntiles), blk(256);
+    if (variant == 1)
+        hipLaunchKernelGGL((k_epr_ref<T, D>), grid, blk, 0, s, g, ph, (const T *)mom, b, step, tile0);
+    else if (variant == 2)
+        hipLaunchKernelGGL((k_epr<T, D, true>), grid, blk, 0, s, g, ph, (const T *)mom, b, step, tile0);
+    else
+        hipLaunchKernelGGL((k_epr<T, D, false>), grid, blk, 0, s, g, ph, (const T *)mom, b, step, tile0);
+}
+
+static void epr_dispatch(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
+                         int variant, int tile0, int ntiles, hipStream_t s) {
+    if (ntiles <= 0) return;
+    if (mixed) {
+        if (g.dim == 1) epr_launch<float, 1>(g, ph, mom, b, step, variant, tile0, ntiles, s);
+        else epr_launch<float, 2>(g, ph, mom, b, step, variant, tile0, ntiles, s);
     } else {
-        if (refined) {
-            hipLaunchKernelGGL((k_epr_ref<T, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
-        } else {
-            hipLaunchKernelGGL((k_epr<T, 2, false>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
-            hipLaunchKernelGGL((k_epr<T, 2, true>), dim3(nt), dim3(256), 0, s, g, ph, (const T *)mom, b, step);
-        }
+        if (g.dim == 1) epr_launch<double, 1>(g, ph, mom, b, step, variant, tile0, ntiles, s);
+        else epr_launch<double, 2>(g, ph, mom, b, step, variant, tile0, ntiles, s);
     }
 }
 
-hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
-                      hipStream_t s) {
-    if (mixed) epr_launch<float>(g, ph, mom, b, step, 0, s);
-    else epr_launch<double>(g, ph, mom, b, step, 0, s);
-    // partials of both k_epr variants
-    const int nt = 2 * g.ntx * g.nty;
-    const int nb = (nt + 255) / 256 < 256 ? (nt + 255) / 256 : 256;
-    hipLaunchKernelGGL(k_stats_reduce, dim3(nb), dim3(256), 0, s, (const DevStats *)b.bpart, nt, b.stats);
+hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step, int tile0,
+                      int ntiles, int wide, hipStream_t s) {
+    epr_dispatch(g, ph, mixed, mom, b, step, wide ? 2 : 0, tile0, ntiles, s);
     return hipGetLastError();
 }
 
 hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
-                          hipStream_t s) {
-    if (mixed) epr_launch<float>(g, ph, mom, b, step, 1, s);
-    else epr_launch<double>(g, ph, mom, b, step, 1, s);
+                          int tile0, int ntiles, hipStream_t s) {
+    epr_dispatch(g, ph, mixed, mom, b, step, 1, tile0, ntiles, s);
     return hipGetLastError();
 }
 
@@ -2652,36 +2682,48 @@ __global__ void k_mark_built(const Flags *fl, const int *maxreach, int *wbuilt) 
 }
 
 template <typename T, int D>
-static void gather_launch(const Geom &g, void *mom_out, Buffers &b, int gcap, hipStream_t s) {
-    const unsigned nt = (unsigned)(gather_blocks_x(g) * gather_blocks_y(g));
+static void gather_launch(const Geom &g, void *mom_out, Buffers &b, int gcap, int br0, int nbr, hipStream_t s) {
+    const unsigned nt = (unsigned)(gather_blocks_x(g) * nbr);
     const size_t lds = (size_t)gcap * G_ENTRY_BYTES;
     bool walls = false;
     for (int f = 0; f < 2 * D; f++) walls = walls || g.bc[f] == LELBM_BC_SLIPWALL;
-    if (walls) hipLaunchKernelGGL((k_gather<T, D, true>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap);
-    else hipLaunchKernelGGL((k_gather<T, D, false>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap);
+    if (walls)
+        hipLaunchKernelGGL((k_gather<T, D, true>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap, br0, nbr);
+    else
+        hipLaunchKernelGGL((k_gather<T, D, false>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap, br0, nbr);
     if (b.tdist) {
         // 8 KB of LDS per wavefront for its blocker bits and summed-area table
         // (five workgroups per CU)
         const size_t lds_near = 32768;
         hipLaunchKernelGGL((k_gather_near<T, D>), dim3(nt), dim3(256), lds_near, s, g, (T *)mom_out, b,
-                           (int)(lds_near / 4));
-        if (b.wcache) hipLaunchKernelGGL(k_mark_built, dim3(1), dim3(1), 0, s, b.flags, b.maxreach, b.wbuilt);
+                           (int)(lds_near / 4), br0);
     }
 }
 
-hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, int gcap, hipStream_t s) {
+hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, int gcap, int br0, int nbr,
+                         hipStream_t s) {
+    if (nbr <= 0) return hipSuccess;
     if (mixed) {
-        if (g.dim == 1) gather_launch<float, 1>(g, mom_out, b, gcap, s);
-        else gather_launch<float, 2>(g, mom_out, b, gcap, s);
+        if (g.dim == 1) gather_launch<float, 1>(g, mom_out, b, gcap, br0, nbr, s);
+        else gather_launch<float, 2>(g, mom_out, b, gcap, br0, nbr, s);
     } else {
-        if (g.dim == 1) gather_launch<double, 1>(g, mom_out, b, gcap, s);
-        else gather_launch<double, 2>(g, mom_out, b, gcap, s);
+        if (g.dim == 1) gather_launch<double, 1>(g, mom_out, b, gcap, br0, nbr, s);
+        else gather_launch<double, 2>(g, mom_out, b, gcap, br0, nbr, s);
     }
-    // partials of k_gather, then of k_gather_near (when it runs)
+    return hipGetLastError();
+}
+
+hipError_t launch_step_totals(const Geom &g, Buffers &b, hipStream_t s) {
+    // partials of both k_epr variants
+    const int nt = 2 * g.ntx * g.nty;
+    const int nb = (nt + 255) / 256 < 256 ? (nt + 255) / 256 : 256;
+    hipLaunchKernelGGL(k_stats_reduce, dim3(nb), dim3(256), 0, s, (const DevStats *)b.bpart, nt, b.stats);
+    // arrival partials of k_gather, then of k_gather_near (when it runs)
     const int nd = gather_blocks_x(g) * gather_blocks_y(g) * (b.tdist ? 2 : 1);
-    const int nb = (nd + 255) / 256 < 256 ? (nd + 255) / 256 : 256;
-    hipLaunchKernelGGL(k_sum_partials, dim3(nb), dim3(256), 0, s, (const unsigned long long *)b.gpart, nd,
+    const int nb2 = (nd + 255) / 256 < 256 ? (nd + 255) / 256 : 256;
+    hipLaunchKernelGGL(k_sum_partials, dim3(nb2), dim3(256), 0, s, (const unsigned long long *)b.gpart, nd,
                        &b.stats->arrivals);
+    if (b.wcache) hipLaunchKernelGGL(k_mark_built, dim3(1), dim3(1), 0, s, b.flags, b.maxreach, b.wbuilt);
     return hipGetLastError();
 }
 

@@ -1,9 +1,10 @@
 """The allocation-free step (lelbm_step_noalloc) against lelbm_step, through
 the C ABI: the same kernels with the library's static per-GPU scratch array
 instead of the context's own buffer, so the fields must agree bit for bit.
-Two calls in a row on one GPU, the second on a smaller input (the array keeps
-the first call's contents), on both precision paths; and a step whose records
-exceed the array fails with ENOMEM, keeping the state."""
+Calls in a row on one GPU, each on a smaller input than the one before (the
+array keeps the previous call's contents), the first banded within the array,
+on both precision paths; and a step whose bands of one tile row exceed the
+array fails with ENOMEM, keeping the state."""
 import numpy as np
 import pytest
 
@@ -35,7 +36,9 @@ def _pair(cfg, prim, steps, prec):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_noalloc_step_equals_step(prec):
     _case("noalloc vs step, precision %d" % prec)
-    cases = [li.quadrants(4, n=72, ny=56), li.smooth_periodic(5, n=40, ny=24, RT=0.3)]
+    # the first case's records exceed the static array: it runs in bands
+    cases = [li.quadrants(2, n=128, ny=256), li.quadrants(4, n=72, ny=56),
+             li.smooth_periodic(5, n=40, ny=24, RT=0.3)]
     for k, (cfg, prim) in enumerate(cases):
         ra, sa, rb, sb, _ = _pair(cfg, prim, 12 - 4 * k, prec)
         print("case", k, "max diff", np.abs(ra - rb).max(), "q_max", sa["q_max"], sb["q_max"])
@@ -46,8 +49,9 @@ def test_noalloc_step_equals_step(prec):
 
 def test_noalloc_rejects_records_beyond_its_array():
     """Records of a hot 160 x 160 box (q ~ 3500 points per cell, ~7 GB in
-    FP64) do not fit the static array: the step fails with ENOMEM and the
-    state is the initial one; lelbm_step then runs the same context."""
+    FP64; ~140 MB per tile row) do not fit the static array even in bands of
+    one tile row: the step fails with ENOMEM and the state is the initial
+    one; lelbm_step then runs the same context."""
     _case("noalloc ENOMEM on a hot 160x160 box")
     import paper_2508_06911_amd as lb
     cfg, prim = li.smooth_periodic(7, n=160, ny=160, RT=72.0)
