@@ -12,7 +12,7 @@ Protocol:
   2. train the warm-start network on them with the library's own kernels;
   3. run the 2048 x 2048 input from the same initial state with
        fp64-eq   plain FP64 path, equilibrium (IID13) Newton guess,
-       mixed-mlp FP32 state/records/streaming + learned Newton guess,
+       mixed-mlp FP32 records (FP64 state and sums) + learned Newton guess,
      and, for attribution, the other combinations of {fp64, mixed} with
      {eq, mlp, lin (closed-form linearised guess), prev (linearised guess
      plus the previous step's correction)}, W untimed warmup steps then K
@@ -52,25 +52,38 @@ HBM_PEAK_GBS = 8000.0
 # non-packed FP32 run at the same rate; packed FP32 math is disabled in this
 # build, so the same figure bounds both paths.
 VALU_PEAK_TFLOPS = 78.6
-# Algorithmic FP64 work of the reconstruction of one cell (2D), the method's
-# cost model: q [I (2E + 80) + (2E + 20)] + 400 I, with q the stencil size,
-# I the Newton evaluations (passes minus the final record pass), E = 20 flops
-# for one exponential evaluated in software, 80 flops of monomial products and
-# moment-sum updates per point and evaluation, 20 for the point's final moment
-# fractions, 400 for the two Hessian factorisations and solves per evaluation.
-EXP_FLOPS = 20
+# FP64 work of the reconstruction kernel as written.  The stencil points'
+# exponentials come from product recurrences along the rows and down the
+# first column (exact exponentials only at a few starts per row and pass), so
+# the count follows the code rather than the method's one-exponential-per-
+# point cost model:
+#   33 per point and Newton evaluation: x^2..x^6 (5 multiplies + the offset),
+#      12 moment-sum updates (10 of them multiply-adds), 5 recurrence products
+#    7 per point of the final pass: two weights, five recurrence products
+#  100 per stencil row and pass: folding the row sums into the 28 + 15
+#      monomial sums (43 multiply-adds), y powers, the column recurrence
+# 1480 per evaluation: Hessian assembly, Cholesky factorisations of the
+#      10x10 and 6x6 systems and their solves (~1100), the column's and the
+#      recurrence ratios' exponentials (16 at ~20 flops each, plus setup)
+#  630 per cell: collision, linearised guess, the final pass's exponentials
+# (the learned guess's 12.3 kFLOP per cell run on MFMA in BF16 and are not
+# counted against the FP64 peak).
+FLOPS_POINT_EVAL, FLOPS_POINT_FINAL, FLOPS_ROW, FLOPS_EVAL, FLOPS_CELL = 33, 7, 100, 1480, 630
 
 
 def epr_flops_per_step(st, steps):
-    """Algorithmic flops of k_epr per step from the step statistics (sums
-    over cells and steps): point_passes = sum q * passes, q_mean * cells =
-    sum q; cells with refined stencils (k_epr_ref) are left out of the point
-    terms."""
+    """Executed FP64 flops of the reconstruction kernels per step from the
+    step statistics (sums over cells and steps): point_passes = sum of
+    q x passes, q_mean x cells = sum of q, row_passes = sum of rows x passes;
+    cells with refined stencils (a separate point-by-point kernel) are left
+    out of the point terms.  The evaluations per cell are passes - 1, their
+    sum taken as point_passes / q_mean - cells."""
     pp = st["point_passes"] - st["point_passes_refined"]
     q = st["q_mean"] * st["cells"]
-    evals_pts = max(pp - q, 0.0)                         # sum over cells of q * I
-    evals = max(pp / max(st["q_mean"], 1e-30) - st["cells"], 0.0)   # ~ sum of I
-    return ((2 * EXP_FLOPS + 80) * evals_pts + (2 * EXP_FLOPS + 20) * q + 400 * evals) / steps
+    eval_points = max(pp - q, 0.0)
+    evals = max(pp / max(st["q_mean"], 1e-30) - st["cells"], 0.0)
+    return (FLOPS_POINT_EVAL * eval_points + FLOPS_POINT_FINAL * q + FLOPS_ROW * st["row_passes"]
+            + FLOPS_EVAL * evals + FLOPS_CELL * st["cells"]) / steps
 
 
 # Algorithmic bytes of the gather: per arriving stencil point the (w_f, w_g)
@@ -109,6 +122,11 @@ def parse():
     ap.add_argument("--c4-warmup", type=int, default=200)
     ap.add_argument("--c4-steps", type=int, default=3)
     ap.add_argument("--no-c4", action="store_true", help="skip the 8192x4096 Mach-10 channel context run")
+    ap.add_argument("--horizon-steps", type=int, default=2000,
+                    help="steps of the 2048^2 four-quadrant and 4096x2048 channel horizon runs (0: skip)")
+    ap.add_argument("--c4-horizon", type=int, default=0,
+                    help="only run the 8192x4096 Mach-10 channel for this many steps on both paths "
+                         "(FP64 and FP32 + learned guess) and report the L1 error per field")
     ap.add_argument("--channel-only", action="store_true",
                     help="run only the 4096x2048 channel context (for kernel traces of that workload)")
     ap.add_argument("--c4-only", action="store_true",
@@ -265,9 +283,9 @@ def timed_run(name, a, lb, torch, cfg, mom0, mlp):
     # k_epr handles the cells with unrefined stencils; refined cells go to
     # k_epr_ref (timed apart)
     flops = epr_flops_per_step(st, a.steps)
-    esz = 8 if prec == lb.FP64 else 4
+    # the state the gather writes is FP64 in both modes
     gbytes = (st["arrivals"] / a.steps * GATHER_PAIR_BYTES[prec_name]
-              + ncell * (11 * esz + GATHER_DESC_BYTES))
+              + ncell * (11 * 8 + GATHER_DESC_BYTES))
     r = {
         "mlups": ncell * a.steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / a.steps,
         "epr_ms": epr_ms, "gather_ms": gat_ms, "epr_flops": flops, "gather_bytes": gbytes,
@@ -381,6 +399,98 @@ def c4_context(lb, li, torch, a, mlp):
     return out
 
 
+def horizon_run(lb, torch, cfg, prim, steps, runs, mlp, label, fluid=None):
+    """Two paths from the same initial state for the configuration's own
+    number of steps: ms per step of each, and the relative L1 error of each
+    field of the second run against the first (the FP64 reference) at the
+    end, on fluid cells.  Steps go in chunks of 500 with a progress line."""
+    m = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
+    out, moms = {}, {}
+    for name, prec, guess in runs:
+        c = lb.Lelbm(cfg, m, precision=prec, guess=guess)
+        if guess == lb.GUESS_MLP:
+            c.set_mlp(mlp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, qmax, it = 0, 0, 0.0
+        while done < steps:
+            k = min(500, steps - done)
+            st = c.step(k)
+            done += k
+            qmax = max(qmax, st["q_max"])
+            log("%s %s: %d / %d steps, %.1f s" % (label, name, done, steps, time.perf_counter() - t0))
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        persistent, scratch = c.memory()
+        mom = c.read_moments()
+        moms[name] = mom[:, fluid] if fluid is not None else mom
+        c.close()
+        out[name] = {"ms_per_step": round(el * 1e3, 3), "q_max": int(qmax), "fallbacks_last_chunk": st["fallbacks"],
+                     "hbm_bytes": {"persistent": persistent, "scratch": scratch}}
+    first, second = runs[0][0], runs[1][0]
+    out["l1_%s_vs_%s" % (second, first)] = l1_errors(moms[second], moms[first])
+    out["steps"] = steps
+    log("%s: L1 after %d steps %s" % (label, steps, out["l1_%s_vs_%s" % (second, first)]))
+    return out
+
+
+def c0_line(lb, li, torch):
+    """The 1D two-state configuration: 2000 cells, seed 0, 1000 steps, on both
+    paths, beside the oracle on the host cores for the same 1000 steps."""
+    import oracle
+    cfg, prim = li.riemann1d(0, n=2000)
+    m = lb.moments_from_primitives(1, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
+    out, moms = {"workload": "1D two-state, 2000 cells, seed 0, zero-gradient pads of 48, 1000 steps"}, {}
+    for name, prec in (("fp64", lb.FP64), ("mixed", lb.MIXED)):
+        c = lb.Lelbm(cfg, m, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step_nostats(1000)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        moms[name] = c.read_moments()
+        c.close()
+        out[name + "_mlups"] = round(2000 * 1000 / el / 1e6, 3)
+    r = moms["fp64"][0]
+    out["l1_rho_mixed_vs_fp64"] = float(np.abs(moms["mixed"][0] - r).sum() / np.abs(r).sum())
+    mo = oracle.moments_from_primitives(1, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
+    t0 = time.perf_counter()
+    code, ref, _, _ = oracle.step(cfg, mo, 1000)
+    el = time.perf_counter() - t0
+    out["oracle"] = {"mlups": round(2000 * 1000 / el / 1e6, 4), "cores": oracle.num_threads(), "s": round(el, 2),
+                     "status": code}
+    out["rel_linf_fp64_vs_oracle"] = float((np.abs(moms["fp64"] - ref).max(axis=1)
+                                            / np.maximum(np.abs(ref).max(axis=1), np.abs(ref[0]).max())).max())
+    log("C0: fp64 %.2f MLUPS, mixed %.2f MLUPS, oracle %.3f MLUPS (%d threads, %.1f s), GPU vs oracle %.2e"
+        % (out["fp64_mlups"], out["mixed_mlups"], out["oracle"]["mlups"], out["oracle"]["cores"], el,
+           out["rel_linf_fp64_vs_oracle"]))
+    return out
+
+
+def c1_line(lb, li, torch, mlp):
+    """The 1024x1024 four-quadrant configuration, seed 0: the plain FP64 path
+    (the configuration's own) and the FP32 path with the learned guess,
+    3 warm-up and 20 timed steps each."""
+    cfg, prim = li.quadrants(0, n=1024)
+    m = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
+    out = {"workload": "2D four-quadrant 1024x1024 periodic, seed 0, 3 warm-up + 20 timed steps"}
+    for name, prec, guess in (("fp64-eq", lb.FP64, lb.GUESS_EQ), ("mixed-mlp", lb.MIXED, lb.GUESS_MLP)):
+        c = lb.Lelbm(cfg, m, precision=prec, guess=guess)
+        if guess == lb.GUESS_MLP:
+            c.set_mlp(mlp)
+        c.step_nostats(3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = c.step(20)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / 20
+        c.close()
+        out[name] = {"mlups": round(1024 * 1024 / el / 1e6, 2), "ms_per_step": round(el * 1e3, 3),
+                     "q_max": st["q_max"], "it_mean_f": round(st["it_mean_f"], 3)}
+        log("C1 %s: %.1f MLUPS" % (name, out[name]["mlups"]))
+    return out
+
+
 def main():
     a = parse()
     if a.copy_probe:
@@ -405,6 +515,17 @@ def main():
     torch.cuda.set_device(0)
     if a.channel_only:
         print(json.dumps({"channel_context": channel_context(lb, li, torch, a)}), flush=True)
+        return
+    if a.c4_horizon:
+        mlp, _ = harvest_and_train(a, lb, li, torch)
+        cfg, prim = li.channel(0, nx=8192, ny=4096, n_obstacles=8, mach=10.0, pad=48)
+        out = horizon_run(lb, torch, cfg, prim, a.c4_horizon,
+                          (("fp64-eq", lb.FP64, lb.GUESS_EQ), ("mixed-mlp", lb.MIXED, lb.GUESS_MLP)), mlp, "C4",
+                          fluid=cfg["solid"].ravel() == 0)
+        out["workload"] = ("channel 8192x4096, Mach 10 inflow, 8 obstacles (seed 0), started from rest, "
+                           "%d steps" % a.c4_horizon)
+        mlp.close()
+        print(json.dumps({"c4_horizon": out}), flush=True)
         return
     if a.c4_only:
         mlp, _ = harvest_and_train(a, lb, li, torch)
@@ -451,7 +572,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D four-quadrant Riemann input %dx%d periodic, seed %d; run %s "
                                "(%s)" % (a.n, a.n, a.seed, head,
-                                         "FP32 state, records and streaming, FP64 reconstruction, "
+                                         "FP32 records, FP64 state, sums and reconstruction, "
                                          "learned Newton guess" if head == "mixed-mlp" else head),
                    "cells": ncell, "warmup_steps": a.warmup},
         "fp64_mlups": round(res_runs["fp64-eq"]["mlups"], 3) if "fp64-eq" in res_runs else None,
@@ -459,21 +580,42 @@ def main():
                             if "fp64-eq" in res_runs else None),
         "l1_vs_fp64": h.get("l1_vs_fp64"),
         "l1_budget": 1e-4,
-        "roofline": {"bound": "alu", "kernel": "k_epr (collision, stencil, Newton reconstruction, records)",
+        "roofline": {"bound": "alu",
+                     "kernel": "k_epr (collision, stencil, Newton reconstruction, records; narrow- and "
+                               "wide-stencil launches of one step)",
                      "achieved": round(h["epr_tflops"], 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(h["epr_tflops"] / VALU_PEAK_TFLOPS, 4),
                      "traffic": traffic.get(("k_epr", wl + "-" + head)),
-                     "avg_ms": round(h["epr_ms"], 4), "flops_per_launch": h["epr_flops"]},
+                     "ms_per_step": round(h["epr_ms"], 4), "flops_per_step": h["epr_flops"],
+                     "model": "executed FP64 work of the code (recurrence exponentials), see FLOPS_* in bench.py",
+                     "lane_occupancy": h["lane_occupancy"]},
         "gather_roofline": {"bound": "hbm", "kernel": "k_gather", "achieved": round(h["gather_gbs"], 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(h["gather_gbs"] / HBM_PEAK_GBS, 4),
                             "traffic": traffic.get(("k_gather", wl + "-" + head)),
-                            "avg_ms": round(h["gather_ms"], 4), "bytes_per_launch": h["gather_bytes"]},
+                            "ms_per_step": round(h["gather_ms"], 4), "bytes_per_step": h["gather_bytes"]},
         "runs": {r: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()
                      if k not in ("epr_flops", "gather_bytes")} for r, d in res_runs.items()},
     }
     if train_info is not None:
         res["mlp"] = train_info
     if not a.no_context:
+        res["c0"] = c0_line(lb, li, torch)
+        if mlp is not None:
+            res["c1"] = c1_line(lb, li, torch, mlp)
+        if a.horizon_steps and mlp is not None:
+            res["c2_horizon"] = horizon_run(lb, torch, cfg, prim, a.horizon_steps,
+                                            (("fp64-eq", lb.FP64, lb.GUESS_EQ),
+                                             ("mixed-mlp", lb.MIXED, lb.GUESS_MLP)), mlp, "C2")
+            res["c2_horizon"]["workload"] = ("2D four-quadrant %dx%d periodic, seed %d, %d steps"
+                                             % (a.n, a.n, a.seed, a.horizon_steps))
+            ccfg, cprim = li.channel(a.channel_seed, nx=4096, ny=2048, pad=32)
+            res["c3_horizon"] = horizon_run(lb, torch, ccfg, cprim, a.horizon_steps,
+                                            (("fp64-eq", lb.FP64, lb.GUESS_EQ),
+                                             ("mixed-eq", lb.MIXED, lb.GUESS_EQ)), None, "C3",
+                                            fluid=ccfg["solid"].ravel() == 0)
+            res["c3_horizon"]["workload"] = ("channel 4096x2048, seed %d (Mach %.2f, %d obstacles), started "
+                                             "from rest, %d steps" % (a.channel_seed, ccfg["mach"],
+                                                                      len(ccfg["obstacles"]), a.horizon_steps))
         res["paper_context"] = hotbox_context(lb, li, torch)
         res["channel_context"] = channel_context(lb, li, torch, a)
         if not a.no_c4:

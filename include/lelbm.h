@@ -64,12 +64,15 @@ enum {
 enum { LELBM_BC_PERIODIC = 0, LELBM_BC_OUTFLOW = 1, LELBM_BC_INFLOW = 2, LELBM_BC_SLIPWALL = 3 };
 
 /* LELBM_FP64: every stage in FP64.
- * LELBM_MIXED: stored moments, reconstruction records and the streaming
- * gather in FP32; collision, per-point reconstruction arithmetic, Hessian
+ * LELBM_MIXED: the reconstruction records (population multipliers and moment
+ * fractions, the bulk of the HBM traffic) in FP32; the stored moments, the
+ * gather's sums, collision, per-point reconstruction arithmetic, Hessian
  * solves and the final conserved-moment correction in FP64.  Newton stops at
  * a scaled residual of max(newton_tol, 1e-4); the polishing update that
  * follows squares it (quadratic convergence) to about 1e-8, the rounding level
- * of the FP32 state. */
+ * of the FP32 records.  Keeping the state in FP64 keeps the per-step rounding
+ * of large raw moments (the energy moment grows with |u|^2) from adding up
+ * over long runs. */
 enum { LELBM_FP64 = 0, LELBM_MIXED = 1 };
 
 /* Newton initial guess.  EQ: Eq. (IID13), the equilibrium multipliers.
@@ -141,6 +144,8 @@ typedef struct {
                                          of a wavefront run in lock step, so
                                          point_passes / wave_point_passes is the share of lane
                                          time spent on stencil points */
+    long row_passes;                  /* sum over cells with unrefined stencils of the stencil rows
+                                         holding points x reconstruction passes */
 } lelbm_stats;
 
 /* Number of stored moments per cell: 6 (1D) or 11 (2D); -1 for other dim. */

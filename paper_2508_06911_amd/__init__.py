@@ -52,6 +52,7 @@ class Stats(ctypes.Structure):
         ("sum", ctypes.c_double * 4), ("cells", ctypes.c_long),
         ("point_passes", ctypes.c_long), ("arrivals", ctypes.c_long),
         ("point_passes_refined", ctypes.c_long), ("wave_point_passes", ctypes.c_long),
+        ("row_passes", ctypes.c_long),
     ]
 
     def as_dict(self):

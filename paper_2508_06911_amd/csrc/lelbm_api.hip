@@ -472,13 +472,12 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ph.lin_guess = p->guess == LELBM_GUESS_LIN;
     ph.prev_guess = p->guess == LELBM_GUESS_PREV;
 
-    size_t esz = c->mixed ? sizeof(float) : sizeof(double);
     Buffers &b = c->b;
     long long ns = g.ns;
     int nt = g.ntx * g.nty, nd = g.dtx * g.dty;
     bool ok = true;
-    ok = ok && hipMalloc(&b.mom[0], (size_t)c->nmom * ns * esz) == hipSuccess;
-    ok = ok && hipMalloc(&b.mom[1], (size_t)c->nmom * ns * esz) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.mom[0], (size_t)c->nmom * ns * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.mom[1], (size_t)c->nmom * ns * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.desc_u, (size_t)2 * ns * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.desc_rho, (size_t)ns * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.desc_rt, (size_t)ns * sizeof(double)) == hipSuccess;
@@ -508,7 +507,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
         ok = ok && hipMalloc((void **)&c->mlp_n, MLP_NORM * sizeof(float)) == hipSuccess;
     }
     if (!ok) { free_ctx(c); return LELBM_ENOMEM; }
-    c->persistent_bytes = (long long)2 * c->nmom * ns * esz + ns * (4 * sizeof(double) + sizeof(int)) +
+    c->persistent_bytes = (long long)2 * c->nmom * ns * sizeof(double) + ns * (4 * sizeof(double) + sizeof(int)) +
                           nt * sizeof(TileInfo) + nd * sizeof(DWin) +
                           (b.lamprev ? (long long)16 * ns * sizeof(double) : 0);
     int r = setup_blockers(c, p->solid);
@@ -543,15 +542,14 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
 }
 
 // Copies interior moments (SoA [nmom][ny][nx], FP64 or FP32, on the host or
-// the device) into the padded state buffer.  Host data is converted to the
-// state precision row by row into the pinned stage; device data is copied
-// (and converted) by a kernel.
+// the device) into the padded FP64 state buffer.  Host data is widened row by
+// row into the pinned stage; device data is copied (and widened) by a kernel.
 static int upload_interior(lelbm_ctx *c, const void *src, int src_fp32, hipMemcpyKind kind) {
     const Geom &g = c->g;
-    const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+    const size_t esz = sizeof(double);
     const long long n = (long long)g.nx * g.ny;
     if (kind == hipMemcpyDeviceToDevice) {
-        HIPCHECK(launch_load_interior(g, c->nmom, src, src_fp32, c->b.mom[c->cur], c->mixed, c->stream));
+        HIPCHECK(launch_load_interior(g, c->nmom, src, src_fp32, c->b.mom[c->cur], c->stream));
         HIPCHECK(hipStreamSynchronize(c->stream));
         return LELBM_OK;
     }
@@ -563,11 +561,8 @@ static int upload_interior(lelbm_ctx *c, const void *src, int src_fp32, hipMemcp
         for (long long y0 = 0; y0 < g.ny; y0 += rows_per) {
             const long long ny = g.ny - y0 < rows_per ? g.ny - y0 : rows_per;
             const long long e0 = (long long)k * n + y0 * g.nx, ne = ny * g.nx;
-            for (long long i = 0; i < ne; i++) {
-                double v = src_fp32 ? (double)((const float *)src)[e0 + i] : ((const double *)src)[e0 + i];
-                if (c->mixed) ((float *)c->stage.p)[i] = (float)v;
-                else ((double *)c->stage.p)[i] = v;
-            }
+            for (long long i = 0; i < ne; i++)
+                ((double *)c->stage.p)[i] = src_fp32 ? (double)((const float *)src)[e0 + i] : ((const double *)src)[e0 + i];
             char *dst = (char *)c->b.mom[c->cur] + ((size_t)k * g.ns + (size_t)(y0 + g.wb) * g.sxn + g.wl) * esz;
             HIPCHECK(hipMemcpy2DAsync(dst, (size_t)g.sxn * esz, c->stage.p, rowb, rowb, (size_t)ny,
                                       hipMemcpyHostToDevice, c->stream));
@@ -746,10 +741,10 @@ static int plan_adapt(const Geom &g, Plan &P, long long limit, bool fixed, int e
 static int finish_create(lelbm_ctx *c) {
     // initial scratch: run the pre-pass once to size it
     hipStream_t s = c->stream;
-    HIPCHECK(launch_zero_solid(c->g, c->nmom, c->mixed, c->b.mom[c->cur], c->b.solid, s));
-    HIPCHECK(launch_fill_pads(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b.flags, s));
+    HIPCHECK(launch_zero_solid(c->g, c->nmom, c->b.mom[c->cur], c->b.solid, s));
+    HIPCHECK(launch_fill_pads(c->g, c->ph, c->b.mom[c->cur], c->b.flags, s));
     HIPCHECK(launch_reset_step(c->g, c->b, s));
-    HIPCHECK(launch_prepare(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, 0, s));
+    HIPCHECK(launch_prepare(c->g, c->ph, c->b.mom[c->cur], c->b, 0, s));
     // one band of all rows with an empty slot: the scan reports the records
     // of the whole domain
     build_plan(c->g, c->plan, c->g.nty, 0);
@@ -785,13 +780,11 @@ static int finish_create(lelbm_ctx *c) {
         if (getenv("LELBM_DEBUG")) {
             fprintf(stderr, "lelbm: create pre-pass failed: err %d node %lld step %d\n", f.err, f.node, f.step);
             if (f.node >= 0 && f.node < c->g.ns) {
-                size_t esz = c->mixed ? sizeof(float) : sizeof(double);
                 for (int k = 0; k < c->nmom; k++) {
                     double v = 0.0;
-                    float vf = 0.f;
-                    const char *src = (const char *)c->b.mom[c->cur] + ((size_t)k * c->g.ns + (size_t)f.node) * esz;
-                    if (stage_d2h(c->stage, s, c->mixed ? (void *)&vf : (void *)&v, src, esz) == LELBM_OK)
-                        fprintf(stderr, "  moment %d = %.17g\n", k, c->mixed ? (double)vf : v);
+                    const double *src = c->b.mom[c->cur] + (size_t)k * c->g.ns + (size_t)f.node;
+                    if (stage_d2h(c->stage, s, &v, src, sizeof(double)) == LELBM_OK)
+                        fprintf(stderr, "  moment %d = %.17g\n", k, v);
                 }
             }
         }
@@ -869,12 +862,12 @@ struct StepArg {
 };
 
 static hipError_t do_fill(lelbm_ctx *c, void *) {
-    return launch_fill_pads(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b.flags, c->stream);
+    return launch_fill_pads(c->g, c->ph, c->b.mom[c->cur], c->b.flags, c->stream);
 }
 static hipError_t do_prepare(lelbm_ctx *c, void *a) {
     hipError_t e = launch_reset_step(c->g, c->b, c->stream);
     if (e != hipSuccess) return e;
-    return launch_prepare(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
+    return launch_prepare(c->g, c->ph, c->b.mom[c->cur], c->b, ((StepArg *)a)->step, c->stream);
 }
 static hipError_t do_scan(lelbm_ctx *c, void *a) {
     const StepArg &s = *(StepArg *)a;
@@ -1057,7 +1050,7 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
         return f.err;
     }
     if (st) {
-        HIPCHECK(launch_sums(c->g, c->mixed, c->b.mom[c->cur], c->b, s));
+        HIPCHECK(launch_sums(c->g, c->b.mom[c->cur], c->b, s));
         DevStats ds;
         double sums[4];
         if ((r = stage_d2h(c->stage, s, &ds, c->b.stats, sizeof(DevStats))) != LELBM_OK) return r;
@@ -1085,6 +1078,7 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
         st->arrivals = (long)ds.arrivals;
         st->point_passes_refined = (long)ds.qpass_ref_sum;
         st->wave_point_passes = (long)ds.wave_qpass;
+        st->row_passes = (long)ds.row_passes;
     }
     return LELBM_OK;
 }
@@ -1138,15 +1132,15 @@ extern "C" int lelbm_step_noalloc(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
 }
 
 // Interior moments as FP64 SoA [nmom][ny][nx]: to the host through the
-// pinned stage (row chunks, widened on the host), or to the device by a
+// pinned stage (row chunks), or to the device by a
 // kernel.
 static int read_common(const lelbm_ctx *cc, void *out, hipMemcpyKind kind, bool sync) {
     lelbm_ctx *c = const_cast<lelbm_ctx *>(cc);     // the stage is scratch state
     const Geom &g = c->g;
-    const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+    const size_t esz = sizeof(double);
     const long long n = (long long)g.nx * g.ny;
     if (kind == hipMemcpyDeviceToDevice) {
-        HIPCHECK(launch_store_interior(g, c->nmom, c->b.mom[c->cur], c->mixed, (double *)out, c->stream));
+        HIPCHECK(launch_store_interior(g, c->nmom, c->b.mom[c->cur], (double *)out, c->stream));
         if (sync) HIPCHECK(hipStreamSynchronize(c->stream));
         return LELBM_OK;
     }
@@ -1163,8 +1157,7 @@ static int read_common(const lelbm_ctx *cc, void *out, hipMemcpyKind kind, bool 
             HIPCHECK(hipStreamSynchronize(c->stream));
             double *o = (double *)out + (long long)k * n + y0 * g.nx;
             const long long ne = ny * g.nx;
-            for (long long i = 0; i < ne; i++)
-                o[i] = c->mixed ? (double)((const float *)c->stage.p)[i] : ((const double *)c->stage.p)[i];
+            memcpy(o, c->stage.p, (size_t)ne * sizeof(double));
         }
     }
     return LELBM_OK;

@@ -111,6 +111,7 @@ struct Flags {
 struct DevStats {
     unsigned long long it_sum_f, it_sum_g, q_sum, limited, cells, fallbacks, qpass_sum, arrivals, qpass_ref_sum;
     unsigned long long wave_qpass;   // sum over wavefronts of 64 x the wavefront's largest q x passes
+    unsigned long long row_passes;   // sum over cells of stencil rows x passes (unrefined stencils)
     int it_max_f, it_max_g, q_max, q_min;
     unsigned long long rt_min_bits, kn_max_bits, colat_max_bits;
 };
@@ -136,7 +137,7 @@ struct DWin {
 };
 
 struct Buffers {
-    void *mom[2];            // state (padded domain), FP64 or FP32, SoA [nmom][ns]
+    double *mom[2];          // state (padded domain), FP64 in both modes, SoA [nmom][ns]
     double *desc_u;          // [2][ns]  cell velocity
     double *desc_rho;        // [ns]
     double *desc_rt;         // [ns]
@@ -181,31 +182,28 @@ struct Buffers {
 };
 
 // Kernel launchers (defined in lelbm_kernels.hip).  All enqueue on `s`.
-hipError_t launch_fill_pads(const Geom &g, const Phys &ph, int mixed, void *mom, Flags *fl, hipStream_t s);
-hipError_t launch_prepare(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
-                          hipStream_t s);
+hipError_t launch_fill_pads(const Geom &g, const Phys &ph, double *mom, Flags *fl, hipStream_t s);
+hipError_t launch_prepare(const Geom &g, const Phys &ph, const double *mom, Buffers &b, int step, hipStream_t s);
 hipError_t launch_scan(const Geom &g, Buffers &b, int nbands, long long slot_cap, int m_plan, int step,
                        hipStream_t s);
 // reconstruction of the tiles [tile0, tile0 + ntiles) of the scan's order:
 // the cells with narrow stencils, or (wide != 0) those with wide ones
-hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step, int tile0,
+hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step, int tile0,
                       int ntiles, int wide, hipStream_t s);
-hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
+hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step,
                           int tile0, int ntiles, hipStream_t s);
 // gather of the destination block rows [br0, br0 + nbr)
-hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, int gcap, int br0, int nbr,
+hipError_t launch_gather(const Geom &g, int mixed, double *mom_out, Buffers &b, int gcap, int br0, int nbr,
                          hipStream_t s);
 // statistics and arrival counts of a step (after its last gather)
 hipError_t launch_step_totals(const Geom &g, Buffers &b, hipStream_t s);
-hipError_t launch_sums(const Geom &g, int mixed, const void *mom, Buffers &b, hipStream_t s);
+hipError_t launch_sums(const Geom &g, const double *mom, Buffers &b, hipStream_t s);
 hipError_t launch_reset_step(const Geom &g, Buffers &b, hipStream_t s);
 hipError_t launch_reset_stats(Buffers &b, hipStream_t s);
 hipError_t launch_reset_flags(Flags *f, hipStream_t s);
-hipError_t launch_zero_solid(const Geom &g, int nmom, int mixed, void *mom, const unsigned char *solid,
-                             hipStream_t s);
-hipError_t launch_load_interior(const Geom &g, int nmom, const void *src, int src_fp32, void *dst, int dst_fp32,
-                                hipStream_t s);
-hipError_t launch_store_interior(const Geom &g, int nmom, const void *src, int src_fp32, double *dst, hipStream_t s);
+hipError_t launch_zero_solid(const Geom &g, int nmom, double *mom, const unsigned char *solid, hipStream_t s);
+hipError_t launch_load_interior(const Geom &g, int nmom, const void *src, int src_fp32, double *dst, hipStream_t s);
+hipError_t launch_store_interior(const Geom &g, int nmom, const double *src, double *dst, hipStream_t s);
 int num_sum_blocks(const Geom &g);
 hipError_t launch_mlp_fwdbwd(const unsigned short *Wb, const float *bias, const float *nm, const float *pairs,
                              long long n, long long nsamp, int draw, unsigned long long seed, unsigned long long step,

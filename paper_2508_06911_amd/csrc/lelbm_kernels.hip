@@ -928,6 +928,7 @@ __device__ inline void store_prev(Species<NF, SF> &sf, Species<NG, SG> &sg, cons
 // Per-cell statistics.
 struct CellStats {
     int it_f = 0, it_g = 0, q = 0, lim = 0, pass = 0, fb = 0;
+    int rows = 0;             // stencil rows holding points (unrefined stencils)
     double kn = 0.0, colat = 0.0, rt = 1e300;
     bool active = false;
     bool refined = false;    // handled by the refined-stencil kernel
@@ -938,18 +939,20 @@ struct CellStats {
 struct StatSum {
     unsigned long long itf = 0, itg = 0, q = 0, lim = 0, cells = 0, qp = 0, qpr = 0, fb = 0;
     unsigned long long wq = 0;   // sum over wavefronts of 64 x the wavefront's largest q x passes
+    unsigned long long rp = 0;   // rows x passes
     int mitf = 0, mitg = 0, mq = 0, nq = 1 << 30;
     double mkn = 0.0, mcolat = 0.0, nrt = 1e300;
     __device__ void add_cell(const CellStats &c) {
         if (!c.active) return;
         itf = c.it_f; itg = c.it_g; q = c.q; lim = c.lim; cells = 1;
         qp = (unsigned long long)c.q * c.pass; qpr = c.refined ? qp : 0ull; fb = c.fb;
+        rp = (unsigned long long)c.rows * c.pass;
         mitf = c.it_f; mitg = c.it_g; mq = c.q; nq = c.q;
         mkn = c.kn; mcolat = c.colat; nrt = c.rt;
     }
     __device__ void add(const StatSum &o) {
         itf += o.itf; itg += o.itg; q += o.q; lim += o.lim; cells += o.cells; qp += o.qp; qpr += o.qpr;
-        fb += o.fb; wq += o.wq;
+        fb += o.fb; wq += o.wq; rp += o.rp;
         mitf = max(mitf, o.mitf); mitg = max(mitg, o.mitg); mq = max(mq, o.mq); nq = min(nq, o.nq);
         mkn = fmax(mkn, o.mkn); mcolat = fmax(mcolat, o.mcolat); nrt = fmin(nrt, o.nrt);
     }
@@ -959,6 +962,7 @@ struct StatSum {
             o.itf = __shfl_xor(itf, off); o.itg = __shfl_xor(itg, off); o.q = __shfl_xor(q, off);
             o.lim = __shfl_xor(lim, off); o.cells = __shfl_xor(cells, off); o.qp = __shfl_xor(qp, off);
             o.qpr = __shfl_xor(qpr, off); o.fb = __shfl_xor(fb, off); o.wq = __shfl_xor(wq, off);
+            o.rp = __shfl_xor(rp, off);
             o.mitf = __shfl_xor(mitf, off); o.mitg = __shfl_xor(mitg, off); o.mq = __shfl_xor(mq, off);
             o.nq = __shfl_xor(nq, off);
             o.mkn = __shfl_xor(mkn, off); o.mcolat = __shfl_xor(mcolat, off); o.nrt = __shfl_xor(nrt, off);
@@ -967,7 +971,7 @@ struct StatSum {
     }
     __device__ void load(const DevStats &d) {
         itf = d.it_sum_f; itg = d.it_sum_g; q = d.q_sum; lim = d.limited; cells = d.cells; qp = d.qpass_sum;
-        qpr = d.qpass_ref_sum; fb = d.fallbacks; wq = d.wave_qpass;
+        qpr = d.qpass_ref_sum; fb = d.fallbacks; wq = d.wave_qpass; rp = d.row_passes;
         mitf = d.it_max_f; mitg = d.it_max_g; mq = d.q_max; nq = d.q_min;
         mkn = __longlong_as_double((long long)d.kn_max_bits);
         mcolat = __longlong_as_double((long long)d.colat_max_bits);
@@ -975,7 +979,7 @@ struct StatSum {
     }
     __device__ void store(DevStats &d) const {
         d.it_sum_f = itf; d.it_sum_g = itg; d.q_sum = q; d.limited = lim; d.cells = cells; d.qpass_sum = qp;
-        d.qpass_ref_sum = qpr; d.fallbacks = fb; d.arrivals = 0; d.wave_qpass = wq;
+        d.qpass_ref_sum = qpr; d.fallbacks = fb; d.arrivals = 0; d.wave_qpass = wq; d.row_passes = rp;
         d.it_max_f = mitf; d.it_max_g = mitg; d.q_max = mq; d.q_min = nq;
         d.kn_max_bits = (unsigned long long)__double_as_longlong(mkn);
         d.colat_max_bits = (unsigned long long)__double_as_longlong(mcolat);
@@ -994,6 +998,7 @@ struct StatSum {
         if (qpr) atomicAdd(&st->qpass_ref_sum, qpr);
         if (fb) atomicAdd(&st->fallbacks, fb);
         if (wq) atomicAdd(&st->wave_qpass, wq);
+        if (rp) atomicAdd(&st->row_passes, rp);
         atomicMax(&st->it_max_f, mitf);
         atomicMax(&st->it_max_g, mitg);
         atomicMax(&st->q_max, mq);
@@ -1234,7 +1239,7 @@ __device__ inline bool row_start_ok(double f, double r, double s2, double gv, do
 // otherwise the other unrefined cells, whose rows are short enough to run
 // each recurrence from one start.
 template <typename T, int D, bool WIDE>
-__global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, Buffers b, int step, int tile0) {
+__global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const double *mom, Buffers b, int step, int tile0) {
     using BS = Basis<D>;
     constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
     // Per-point arithmetic stays FP64 in both paths: without packed FP32 math
@@ -1266,7 +1271,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
     double mf[NF], mg[NG];
     if (cs.active) {
         rho = b.desc_rho[s]; ux = b.desc_u[s]; uy = b.desc_u[g.ns + s]; RT = b.desc_rt[s];
-        collide_targets<T, D>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, cs.kn, cs.lim);
+        collide_targets<double, D>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, cs.kn, cs.lim);
     }
     // learned guess: the network's correction, computed before the Newton
     // state takes over the LDS arrays it borrows
@@ -1498,6 +1503,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
                 if (tab && cy < yhi) nxt = spt[(long long)(cy + 1 - ylo) * SW];
                 int xa, xb;
                 if (!span(cur, cy, xa, xb)) continue;
+                cs.rows++;
                 double y = D == 2 ? (double)cy - uy : 0.0;
                 const bool walk = D == 2 && (!WIDE || xa - xlo < REC_SEG);
                 if (walk) {
@@ -1571,7 +1577,7 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const T *mom, B
 // refined cells.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, Buffers b, int step, int tile0) {
+__global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const double *mom, Buffers b, int step, int tile0) {
     using BS = Basis<D>;
     constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
     __shared__ int s_skip;
@@ -1595,7 +1601,7 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const T *mom, 
         double rho = b.desc_rho[s], ux = b.desc_u[s], uy = b.desc_u[g.ns + s], RT = b.desc_rt[s];
         int R = rn & 0xffff, Nr = rn >> 16;
         double mf[NF], mg[NG];
-        collide_targets<T, D>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, cs.kn, cs.lim);
+        collide_targets<double, D>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, cs.kn, cs.lim);
         Species<NF, RegStore<NF>> sf;
         Species<NG, RegStore<NG>> sg;
         species_init<D, NF, NG>(sf, sg, RT);
@@ -1759,30 +1765,30 @@ __device__ inline Resolved resolve_source(const Geom &g, int xr, int yr) {
 // velocity after reflection; for pre-summed refined records the odd
 // components are mirrored.
 template <typename T, int D>
-__device__ inline void deposit_record(T *acc, const T *P, int fmt, int dx, int dy, int fx, int fy) {
+__device__ inline void deposit_record(double *acc, const T *P, int fmt, int dx, int dy, int fx, int fy) {
     if (fmt == 0) {
-        const T wx_ = P[0], wy_ = P[1];
-        T cx = (T)dx, cy = (T)dy;
+        const double wx_ = (double)P[0], wy_ = (double)P[1];
+        double cx = (double)dx, cy = (double)dy;
         if (D == 1) {
             acc[0] += wx_; acc[1] += cx * wx_; acc[2] += cx * cx * wx_; acc[3] += cx * cx * cx * wx_;
             acc[4] += wy_; acc[5] += cx * wy_;
         } else {
-            T cc = cx * cx + cy * cy;
+            double cc = cx * cx + cy * cy;
             acc[0] += wx_; acc[1] += cx * wx_; acc[2] += cy * wx_;
             acc[3] += cx * cx * wx_; acc[4] += cx * cy * wx_; acc[5] += cy * cy * wx_;
             acc[6] += cc * cx * wx_; acc[7] += cc * cy * wx_;
             acc[8] += wy_; acc[9] += cx * wy_; acc[10] += cy * wy_;
         }
     } else {
-        T sx1 = fx ? (T)-1 : (T)1, sy1 = fy ? (T)-1 : (T)1;
+        double sx1 = fx ? -1.0 : 1.0, sy1 = fy ? -1.0 : 1.0;
         if (D == 1) {
-            acc[0] += P[0]; acc[1] += sx1 * P[1]; acc[2] += P[2];
-            acc[3] += sx1 * P[3]; acc[4] += P[4]; acc[5] += sx1 * P[5];
+            acc[0] += (double)P[0]; acc[1] += sx1 * (double)P[1]; acc[2] += (double)P[2];
+            acc[3] += sx1 * (double)P[3]; acc[4] += (double)P[4]; acc[5] += sx1 * (double)P[5];
         } else {
-            acc[0] += P[0]; acc[1] += sx1 * P[1]; acc[2] += sy1 * P[2];
-            acc[3] += P[3]; acc[4] += sx1 * sy1 * P[4]; acc[5] += P[5];
-            acc[6] += sx1 * P[6]; acc[7] += sy1 * P[7];
-            acc[8] += P[8]; acc[9] += sx1 * P[9]; acc[10] += sy1 * P[10];
+            acc[0] += (double)P[0]; acc[1] += sx1 * (double)P[1]; acc[2] += sy1 * (double)P[2];
+            acc[3] += (double)P[3]; acc[4] += sx1 * sy1 * (double)P[4]; acc[5] += (double)P[5];
+            acc[6] += sx1 * (double)P[6]; acc[7] += sy1 * (double)P[7];
+            acc[8] += (double)P[8]; acc[9] += sx1 * (double)P[9]; acc[10] += sy1 * (double)P[10];
         }
     }
 }
@@ -1887,12 +1893,12 @@ constexpr int META_FX = 1 << 8, META_FY = 1 << 9, META_REF = 1 << 10;
 
 // WALLS: some face is a slip wall (sources may be mirror images).  Sources
 // with refined stencils are skipped by the main scan and handled by a second
-// scan that runs only in workgroups whose staged region holds one.  Five
-// wavefronts per SIMD at FP32 (the LDS of five workgroups fits a CU); the
-// FP64 variant needs more registers and keeps four.
+// scan that runs only in workgroups whose staged region holds one.  The sums
+// are FP64 in both precision modes (the FP32 records are widened as they
+// arrive); four wavefronts per SIMD (capped at five, the FP64 accumulators
+// spill at the row level and the kernel is 19 % slower).
 template <typename T, int D, bool WALLS>
-__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, T *mom_out, Buffers b, int gcap,
-                                                                       int br0, int nbr) {
+__global__ void __launch_bounds__(256, 4) k_gather(Geom g, double *mom_out, Buffers b, int gcap, int br0, int nbr) {
     constexpr int NM = Basis<D>::NMOM;
     extern __shared__ double2 g_lds[];
     double2 *s_u = g_lds;
@@ -1965,7 +1971,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     }
     using V2 = typename Vec2<T>::type;
     const T *SCR = (const T *)b.scratch;
-    T acc[NM];
+    double acc[NM];
 #pragma unroll
     for (int k = 0; k < NM; k++) acc[k] = 0;
     int hits = 0;
@@ -2014,7 +2020,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
                 const int rowbase = (ly + (dy0 - dy)) * RW + lx + uhix;
                 // sums over the row of w_f c_x^k (k <= 3) and w_g c_x^k
                 // (k <= 1); c_y enters once per row
-                T a0 = 0, a1 = 0, a2 = 0, a3 = 0, h0 = 0, h1 = 0;
+                double a0 = 0, a1 = 0, a2 = 0, a3 = 0, h0 = 0, h1 = 0;
                 const double cyd = (double)dy;
                 // the row's displacements that a reaching source can hit: with
                 // every source velocity in [ux0, ux1] x [uy0, uy1] and radius at
@@ -2072,11 +2078,22 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
                         wv[u].x = 0; wv[u].y = 0;
                         if (pp[u]) wv[u] = *(const V2 *)pp[u];
                     }
-                    const T cxt = (T)dxb;
+                    // the batch's values are taken here, after all of its
+                    // loads: otherwise the compiler moves the FP32 -> FP64
+                    // conversions into each load's branch and waits for every
+                    // load before issuing the next
+                    if constexpr (sizeof(V2) == 8) {
+#pragma unroll
+                        for (int u = 0; u < GU; u++) {
+                            double d = __builtin_bit_cast(double, wv[u]);
+                            asm volatile("" : "+v"(d));
+                            wv[u] = __builtin_bit_cast(V2, d);
+                        }
+                    }
 #pragma unroll
                     for (int u = 0; u < GU; u++) {
-                        const T cx = cxt - (T)u, wf = wv[u].x, wg = wv[u].y;
-                        const T cw = cx * wf, c2w = cx * cw;
+                        const double cx = cxb - (double)u, wf = (double)wv[u].x, wg = (double)wv[u].y;
+                        const double cw = cx * wf, c2w = cx * cw;
                         a0 += wf; a1 += cw; a2 += c2w; a3 += cx * c2w;
                         h0 += wg; h1 += cx * wg;
                     }
@@ -2084,7 +2101,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
                 if (D == 1) {
                     acc[0] += a0; acc[1] += a1; acc[2] += a2; acc[3] += a3; acc[4] += h0; acc[5] += h1;
                 } else {
-                    const T cy = (T)dy, cy2 = cy * cy;
+                    const double cy = (double)dy, cy2 = cy * cy;
                     acc[0] += a0; acc[1] += a1; acc[2] += cy * a0;
                     acc[3] += a2; acc[4] += cy * a1; acc[5] += cy2 * a0;
                     acc[6] += a3 + cy2 * a1; acc[7] += cy * a2 + cy2 * cy * a0;
@@ -2137,7 +2154,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
     if (mine && !near) {
         long long o = (long long)(y + g.wb) * g.sxn + (x + g.wl);
 #pragma unroll
-        for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = (T)acc[k];
+        for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = acc[k];
     }
     // arrivals of the workgroup as one partial (summed by k_sum_partials)
     __shared__ unsigned long long s_hits[4];
@@ -2160,7 +2177,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 5 : 4) k_gather(Geom g, 
 // reads them instead.  Candidates go in batches of GU so that the descriptor
 // loads of a batch are in flight together.
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers b, int mapb, int br0) {
+__global__ void __launch_bounds__(256) k_gather_near(Geom g, double *mom_out, Buffers b, int mapb, int br0) {
     constexpr int NM = Basis<D>::NMOM;
     constexpr int TX = tile_x<D>(), TY = tile_y<D>();
     constexpr int NTB = D == 2 ? GATHER_NTB : 1;
@@ -2251,7 +2268,7 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers
             return ((bits[(py - by0) * wpr + (cx >> 5)] >> (cx & 31)) & 1u) != 0;
         };
         const auto blocked_glb = [&](int px, int py) { return blocked_wrapped<D>(g, b.solid, px, py); };
-        T acc[NM];
+        double acc[NM];
 #pragma unroll
         for (int k = 0; k < NM; k++) acc[k] = 0;
         const bool fluid = mine && !(b.solid && b.solid[(long long)y * g.nx + x]);
@@ -2373,7 +2390,7 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, T *mom_out, Buffers
         if (mine) {
             long long o = (long long)(y + g.wb) * g.sxn + (x + g.wl);
 #pragma unroll
-            for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = (T)acc[k];
+            for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = acc[k];
         }
     }
     __shared__ unsigned long long s_hits[4];
@@ -2440,7 +2457,7 @@ __global__ void k_reset_flags(Flags *f) {
 __global__ void k_reset_stats(DevStats *st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->it_sum_f = st->it_sum_g = st->q_sum = st->limited = st->cells = st->fallbacks = 0;
-        st->qpass_sum = st->qpass_ref_sum = st->arrivals = st->wave_qpass = 0;
+        st->qpass_sum = st->qpass_ref_sum = st->arrivals = st->wave_qpass = st->row_passes = 0;
         st->it_max_f = st->it_max_g = st->q_max = 0;
         st->q_min = 1 << 30;
         st->rt_min_bits = (unsigned long long)__double_as_longlong(1e300);
@@ -2537,27 +2554,13 @@ int num_sum_blocks(const Geom &g) {
     return (int)(nb < 1024 ? nb : 1024);
 }
 
-#define DISPATCH(mixed, dim, KERNEL, ...)                                        \
-    do {                                                                         \
-        if (mixed) {                                                             \
-            if (dim == 1) hipLaunchKernelGGL((KERNEL<float, 1>), __VA_ARGS__);  \
-            else hipLaunchKernelGGL((KERNEL<float, 2>), __VA_ARGS__);           \
-        } else {                                                                 \
-            if (dim == 1) hipLaunchKernelGGL((KERNEL<double, 1>), __VA_ARGS__); \
-            else hipLaunchKernelGGL((KERNEL<double, 2>), __VA_ARGS__);          \
-        }                                                                        \
-    } while (0)
-
-hipError_t launch_fill_pads(const Geom &g, const Phys &ph, int mixed, void *mom, Flags *fl, hipStream_t s) {
+// The state (moments, SoA over the padded domain) is FP64 in both
+// precision modes; only the population records of the mixed mode are FP32.
+hipError_t launch_fill_pads(const Geom &g, const Phys &ph, double *mom, Flags *fl, hipStream_t s) {
     if (g.wl + g.wr + g.wb + g.wt == 0) return hipSuccess;
     unsigned nb = (unsigned)((g.ns + 255) / 256);
-    if (mixed) {
-        if (g.dim == 1) hipLaunchKernelGGL((k_fill_pads<float, 1>), dim3(nb), dim3(256), 0, s, g, ph, (float *)mom, fl);
-        else hipLaunchKernelGGL((k_fill_pads<float, 2>), dim3(nb), dim3(256), 0, s, g, ph, (float *)mom, fl);
-    } else {
-        if (g.dim == 1) hipLaunchKernelGGL((k_fill_pads<double, 1>), dim3(nb), dim3(256), 0, s, g, ph, (double *)mom, fl);
-        else hipLaunchKernelGGL((k_fill_pads<double, 2>), dim3(nb), dim3(256), 0, s, g, ph, (double *)mom, fl);
-    }
+    if (g.dim == 1) hipLaunchKernelGGL((k_fill_pads<double, 1>), dim3(nb), dim3(256), 0, s, g, ph, mom, fl);
+    else hipLaunchKernelGGL((k_fill_pads<double, 2>), dim3(nb), dim3(256), 0, s, g, ph, mom, fl);
     return hipGetLastError();
 }
 
@@ -2567,43 +2570,30 @@ hipError_t launch_reset_step(const Geom &g, Buffers &b, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_load_interior(const Geom &g, int nmom, const void *src, int src_fp32, void *dst, int dst_fp32,
-                                hipStream_t s) {
-    const long long tot = (long long)g.nx * g.ny * nmom;
-    if (tot == 0) return hipSuccess;
-    dim3 grid((unsigned)((tot + 255) / 256));
-    if (src_fp32 && dst_fp32)
-        hipLaunchKernelGGL((k_load_interior<float, float>), grid, dim3(256), 0, s, g, nmom, (const float *)src, (float *)dst);
-    else if (src_fp32)
-        hipLaunchKernelGGL((k_load_interior<float, double>), grid, dim3(256), 0, s, g, nmom, (const float *)src,
-                           (double *)dst);
-    else if (dst_fp32)
-        hipLaunchKernelGGL((k_load_interior<double, float>), grid, dim3(256), 0, s, g, nmom, (const double *)src,
-                           (float *)dst);
-    else
-        hipLaunchKernelGGL((k_load_interior<double, double>), grid, dim3(256), 0, s, g, nmom, (const double *)src,
-                           (double *)dst);
-    return hipGetLastError();
-}
-
-hipError_t launch_store_interior(const Geom &g, int nmom, const void *src, int src_fp32, double *dst, hipStream_t s) {
+hipError_t launch_load_interior(const Geom &g, int nmom, const void *src, int src_fp32, double *dst, hipStream_t s) {
     const long long tot = (long long)g.nx * g.ny * nmom;
     if (tot == 0) return hipSuccess;
     dim3 grid((unsigned)((tot + 255) / 256));
     if (src_fp32)
-        hipLaunchKernelGGL((k_store_interior<float>), grid, dim3(256), 0, s, g, nmom, (const float *)src, dst);
+        hipLaunchKernelGGL((k_load_interior<float, double>), grid, dim3(256), 0, s, g, nmom, (const float *)src, dst);
     else
-        hipLaunchKernelGGL((k_store_interior<double>), grid, dim3(256), 0, s, g, nmom, (const double *)src, dst);
+        hipLaunchKernelGGL((k_load_interior<double, double>), grid, dim3(256), 0, s, g, nmom, (const double *)src, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_zero_solid(const Geom &g, int nmom, int mixed, void *mom, const unsigned char *solid,
-                             hipStream_t s) {
+hipError_t launch_store_interior(const Geom &g, int nmom, const double *src, double *dst, hipStream_t s) {
+    const long long tot = (long long)g.nx * g.ny * nmom;
+    if (tot == 0) return hipSuccess;
+    dim3 grid((unsigned)((tot + 255) / 256));
+    hipLaunchKernelGGL((k_store_interior<double>), grid, dim3(256), 0, s, g, nmom, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_solid(const Geom &g, int nmom, double *mom, const unsigned char *solid, hipStream_t s) {
     const long long n = (long long)g.nx * g.ny;
     if (!solid || n == 0) return hipSuccess;
     dim3 grid((unsigned)((n + 255) / 256));
-    if (mixed) hipLaunchKernelGGL((k_zero_solid<float>), grid, dim3(256), 0, s, g, nmom, (float *)mom, solid);
-    else hipLaunchKernelGGL((k_zero_solid<double>), grid, dim3(256), 0, s, g, nmom, (double *)mom, solid);
+    hipLaunchKernelGGL((k_zero_solid<double>), grid, dim3(256), 0, s, g, nmom, mom, solid);
     return hipGetLastError();
 }
 
@@ -2617,16 +2607,10 @@ hipError_t launch_reset_stats(Buffers &b, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_prepare(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
-                          hipStream_t s) {
+hipError_t launch_prepare(const Geom &g, const Phys &ph, const double *mom, Buffers &b, int step, hipStream_t s) {
     unsigned nt = (unsigned)(g.ntx * g.nty);
-    if (mixed) {
-        if (g.dim == 1) hipLaunchKernelGGL((k_prepare<float, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const float *)mom, b, step);
-        else hipLaunchKernelGGL((k_prepare<float, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const float *)mom, b, step);
-    } else {
-        if (g.dim == 1) hipLaunchKernelGGL((k_prepare<double, 1>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
-        else hipLaunchKernelGGL((k_prepare<double, 2>), dim3(nt), dim3(256), 0, s, g, ph, (const double *)mom, b, step);
-    }
+    if (g.dim == 1) hipLaunchKernelGGL((k_prepare<double, 1>), dim3(nt), dim3(256), 0, s, g, ph, mom, b, step);
+    else hipLaunchKernelGGL((k_prepare<double, 2>), dim3(nt), dim3(256), 0, s, g, ph, mom, b, step);
     return hipGetLastError();
 }
 
@@ -2639,18 +2623,18 @@ hipError_t launch_scan(const Geom &g, Buffers &b, int nbands, long long slot_cap
 
 // variant 0: cells with narrow stencils, 1: refined stencils, 2: wide
 template <typename T, int D>
-static void epr_launch(const Geom &g, const Phys &ph, const void *mom, Buffers &b, int step, int variant, int tile0,
-                       int ntiles, hipStream_t s) {
+static void epr_launch(const Geom &g, const Phys &ph, const double *mom, Buffers &b, int step, int variant,
+                       int tile0, int ntiles, hipStream_t s) {
     const dim3 grid((unsigned)ntiles), blk(256);
     if (variant == 1)
-        hipLaunchKernelGGL((k_epr_ref<T, D>), grid, blk, 0, s, g, ph, (const T *)mom, b, step, tile0);
+        hipLaunchKernelGGL((k_epr_ref<T, D>), grid, blk, 0, s, g, ph, mom, b, step, tile0);
     else if (variant == 2)
-        hipLaunchKernelGGL((k_epr<T, D, true>), grid, blk, 0, s, g, ph, (const T *)mom, b, step, tile0);
+        hipLaunchKernelGGL((k_epr<T, D, true>), grid, blk, 0, s, g, ph, mom, b, step, tile0);
     else
-        hipLaunchKernelGGL((k_epr<T, D, false>), grid, blk, 0, s, g, ph, (const T *)mom, b, step, tile0);
+        hipLaunchKernelGGL((k_epr<T, D, false>), grid, blk, 0, s, g, ph, mom, b, step, tile0);
 }
 
-static void epr_dispatch(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
+static void epr_dispatch(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step,
                          int variant, int tile0, int ntiles, hipStream_t s) {
     if (ntiles <= 0) return;
     if (mixed) {
@@ -2662,13 +2646,13 @@ static void epr_dispatch(const Geom &g, const Phys &ph, int mixed, const void *m
     }
 }
 
-hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step, int tile0,
+hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step, int tile0,
                       int ntiles, int wide, hipStream_t s) {
     epr_dispatch(g, ph, mixed, mom, b, step, wide ? 2 : 0, tile0, ntiles, s);
     return hipGetLastError();
 }
 
-hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const void *mom, Buffers &b, int step,
+hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step,
                           int tile0, int ntiles, hipStream_t s) {
     epr_dispatch(g, ph, mixed, mom, b, step, 1, tile0, ntiles, s);
     return hipGetLastError();
@@ -2682,25 +2666,25 @@ __global__ void k_mark_built(const Flags *fl, const int *maxreach, int *wbuilt) 
 }
 
 template <typename T, int D>
-static void gather_launch(const Geom &g, void *mom_out, Buffers &b, int gcap, int br0, int nbr, hipStream_t s) {
+static void gather_launch(const Geom &g, double *mom_out, Buffers &b, int gcap, int br0, int nbr, hipStream_t s) {
     const unsigned nt = (unsigned)(gather_blocks_x(g) * nbr);
     const size_t lds = (size_t)gcap * G_ENTRY_BYTES;
     bool walls = false;
     for (int f = 0; f < 2 * D; f++) walls = walls || g.bc[f] == LELBM_BC_SLIPWALL;
     if (walls)
-        hipLaunchKernelGGL((k_gather<T, D, true>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap, br0, nbr);
+        hipLaunchKernelGGL((k_gather<T, D, true>), dim3(nt), dim3(256), lds, s, g, mom_out, b, gcap, br0, nbr);
     else
-        hipLaunchKernelGGL((k_gather<T, D, false>), dim3(nt), dim3(256), lds, s, g, (T *)mom_out, b, gcap, br0, nbr);
+        hipLaunchKernelGGL((k_gather<T, D, false>), dim3(nt), dim3(256), lds, s, g, mom_out, b, gcap, br0, nbr);
     if (b.tdist) {
         // 8 KB of LDS per wavefront for its blocker bits and summed-area table
         // (five workgroups per CU)
         const size_t lds_near = 32768;
-        hipLaunchKernelGGL((k_gather_near<T, D>), dim3(nt), dim3(256), lds_near, s, g, (T *)mom_out, b,
+        hipLaunchKernelGGL((k_gather_near<T, D>), dim3(nt), dim3(256), lds_near, s, g, mom_out, b,
                            (int)(lds_near / 4), br0);
     }
 }
 
-hipError_t launch_gather(const Geom &g, int mixed, void *mom_out, Buffers &b, int gcap, int br0, int nbr,
+hipError_t launch_gather(const Geom &g, int mixed, double *mom_out, Buffers &b, int gcap, int br0, int nbr,
                          hipStream_t s) {
     if (nbr <= 0) return hipSuccess;
     if (mixed) {
@@ -2727,15 +2711,10 @@ hipError_t launch_step_totals(const Geom &g, Buffers &b, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_sums(const Geom &g, int mixed, const void *mom, Buffers &b, hipStream_t s) {
+hipError_t launch_sums(const Geom &g, const double *mom, Buffers &b, hipStream_t s) {
     int nb = num_sum_blocks(g);
-    if (mixed) {
-        if (g.dim == 1) hipLaunchKernelGGL((k_sums<float, 1>), dim3(nb), dim3(256), 0, s, g, (const float *)mom, b.partial);
-        else hipLaunchKernelGGL((k_sums<float, 2>), dim3(nb), dim3(256), 0, s, g, (const float *)mom, b.partial);
-    } else {
-        if (g.dim == 1) hipLaunchKernelGGL((k_sums<double, 1>), dim3(nb), dim3(256), 0, s, g, (const double *)mom, b.partial);
-        else hipLaunchKernelGGL((k_sums<double, 2>), dim3(nb), dim3(256), 0, s, g, (const double *)mom, b.partial);
-    }
+    if (g.dim == 1) hipLaunchKernelGGL((k_sums<double, 1>), dim3(nb), dim3(256), 0, s, g, mom, b.partial);
+    else hipLaunchKernelGGL((k_sums<double, 2>), dim3(nb), dim3(256), 0, s, g, mom, b.partial);
     hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(64), 0, s, nb, b.partial);
     return hipGetLastError();
 }
