@@ -329,7 +329,7 @@ def hotbox_context(lb, li, torch):
     return out
 
 
-def channel_run(lb, li, torch, cfg, prim, warmup, steps, label, mlp=None):
+def channel_run(lb, li, torch, cfg, prim, warmup, steps, label, mlp=None, budget=0):
     """A channel configuration started from rest: after a warm-up that lets the
     bow shocks form, the FP64 path and the FP32 path (with the learned Newton
     guess when a network is given) from the same state, with the relative L1
@@ -337,6 +337,8 @@ def channel_run(lb, li, torch, cfg, prim, warmup, steps, label, mlp=None):
     cells."""
     m = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
     ctx = lb.Lelbm(cfg, m, precision=lb.MIXED if label == "c4" else lb.FP64)
+    if budget:
+        ctx.set_scratch_budget(budget)
     ctx.step_nostats(warmup)
     torch.cuda.synchronize()
     m0 = ctx.read_moments()
@@ -349,6 +351,8 @@ def channel_run(lb, li, torch, cfg, prim, warmup, steps, label, mlp=None):
         c = lb.Lelbm(cfg, m0, precision=prec, guess=lb.GUESS_MLP if learned else lb.GUESS_EQ)
         if learned:
             c.set_mlp(mlp)
+        if budget:
+            c.set_scratch_budget(budget)
         c.step_nostats(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -379,7 +383,8 @@ def channel_context(lb, li, torch, a):
     """The channel configuration: 4096x2048, inflow at the seed's Mach number,
     1-4 seeded elliptical obstacles, slip walls, outflow."""
     cfg, prim = li.channel(a.channel_seed, nx=4096, ny=2048, pad=32)
-    out = channel_run(lb, li, torch, cfg, prim, a.channel_warmup, a.channel_steps, "channel")
+    out = channel_run(lb, li, torch, cfg, prim, a.channel_warmup, a.channel_steps, "channel",
+                      budget=a.scratch_budget)
     out["seed"] = a.channel_seed
     return out
 
@@ -394,7 +399,7 @@ def c4_context(lb, li, torch, a, mlp):
     Reports the HBM footprint: persistent state vs the transient record
     scratch."""
     cfg, prim = li.channel(0, nx=8192, ny=4096, n_obstacles=8, mach=10.0, pad=48)
-    out = channel_run(lb, li, torch, cfg, prim, a.c4_warmup, a.c4_steps, "c4", mlp)
+    out = channel_run(lb, li, torch, cfg, prim, a.c4_warmup, a.c4_steps, "c4", mlp, budget=a.scratch_budget)
     out["seed"] = 0
     return out
 

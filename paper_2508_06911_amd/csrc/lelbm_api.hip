@@ -246,7 +246,7 @@ static void free_ctx(lelbm_ctx *c) {
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.spans, b.tiles,
                     b.dwin, b.scratch, b.flags, b.stats, b.partial, b.harvest_n,
                     c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, (void *)b.cdist, (void *)b.tdist_s, b.wcache, (void *)b.wslot, b.wbuilt, b.lamprev,
-                    b.bpart, b.gpart, b.order, b.bands};
+                    b.bpart, b.gpart, b.order, b.rlist, b.rcount, b.bands};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t e : c->opev) (void)hipEventDestroy(e);
@@ -491,10 +491,12 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ok = ok && hipMalloc((void **)&b.harvest_n, sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.bpart, (size_t)2 * nt * sizeof(DevStats)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.order, (size_t)nt * sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.rlist, (size_t)nt * sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc((void **)&b.rcount, (size_t)g.nty * sizeof(int)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.maxreach, sizeof(int)) == hipSuccess;
     ok = ok && hipMalloc((void **)&b.bands, (size_t)g.nty * sizeof(BandInfo)) == hipSuccess;
     // arrival partials of the straight gather and of the backward-walk gather
-    ok = ok && hipMalloc((void **)&b.gpart, (size_t)2 * gather_blocks_x(g) * gather_blocks_y(g) *
+    ok = ok && hipMalloc((void **)&b.gpart, (size_t)5 * gather_blocks_x(g) * gather_blocks_y(g) *
                                                 sizeof(unsigned long long)) == hipSuccess;
     if (p->guess == LELBM_GUESS_PREV) {
         ok = ok && hipMalloc((void **)&b.lamprev, (size_t)16 * ns * sizeof(double)) == hipSuccess;
@@ -889,7 +891,7 @@ static hipError_t do_epr_ref(lelbm_ctx *c, void *a) {
     const StepArg &s = *(StepArg *)a;
     const BandInfo &bd = s.plan->bands[s.a];
     return launch_epr_ref(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
-                          (bd.row1 - bd.row0) * c->g.ntx, s.es);
+                          (bd.row1 - bd.row0) * c->g.ntx, s.a, s.es);
 }
 static hipError_t do_gather(lelbm_ctx *c, void *a) {
     const StepArg &s = *(StepArg *)a;

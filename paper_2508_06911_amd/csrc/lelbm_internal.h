@@ -13,6 +13,7 @@ namespace lelbm {
 constexpr int TILE_N = 256;
 constexpr int WCACHE_M = 31;              // largest reach whose walks are cached
 constexpr int EPR_ORDER_MAX_TILES = 32768; // above: k_epr takes the tiles in index order
+constexpr int EPR_REF_GRID = 512;          // workgroups of a k_epr_ref launch (two per CU)
 constexpr int WCACHE_W = 2 * WCACHE_M + 1;
 template <int D> constexpr int tile_x() { return D == 2 ? 16 : 256; }
 template <int D> constexpr int tile_y() { return D == 2 ? 16 : 1; }
@@ -157,7 +158,9 @@ struct Buffers {
     const float *mlp_n;            // standardisation constants (64)
     DevStats *bpart;               // [2][ntx*nty] per-workgroup statistics of k_epr (narrow, wide stencils)
     int *order;                    // [ntx*nty] source tiles in the order k_epr takes them (k_scan)
-    unsigned long long *gpart;     // [dtx*dty] per-workgroup arrival counts of k_gather
+    int *rlist;                    // [ntx*nty] per band from its first tile on: its tiles with refined cells
+    int *rcount;                   // [nty] per band: how many (k_scan)
+    unsigned long long *gpart;     // arrival counts per workgroup: [dtx*dty] of k_gather, then 4 per block of k_gather_near
     double *lamprev;               // [16][ns] scaled correction beyond the linearised guess, last step
                                    // (NaN in row 0: none); allocated for LELBM_GUESS_PREV only
     // harvesting of (features, converged multipliers) pairs
@@ -190,8 +193,10 @@ hipError_t launch_scan(const Geom &g, Buffers &b, int nbands, long long slot_cap
 // the cells with narrow stencils, or (wide != 0) those with wide ones
 hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step, int tile0,
                       int ntiles, int wide, hipStream_t s);
+// reconstruction of the refined-stencil tiles of band `band` (tiles
+// [tile0, tile0 + ntiles))
 hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step,
-                          int tile0, int ntiles, hipStream_t s);
+                          int tile0, int ntiles, int band, hipStream_t s);
 // gather of the destination block rows [br0, br0 + nbr)
 hipError_t launch_gather(const Geom &g, int mixed, double *mom_out, Buffers &b, int gcap, int br0, int nbr,
                          hipStream_t s);

@@ -365,14 +365,14 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
 // record offsets and k_epr's tile order, band by band (one workgroup)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_scan(int ntx, int nbands, const BandInfo *bands, TileInfo *tiles,
-                                               Flags *fl, long long slot_cap, int step, int *order,
-                                               const int *maxreach, int m_plan) {
+                                               Flags *fl, long long slot_cap, int step, int *order, int *rlist,
+                                               int *rcount, const int *maxreach, int m_plan) {
     // 16 wavefronts: scans within a wavefront by shuffles and ballots, across
     // the wavefronts of a 1024-tile chunk through LDS
     __shared__ long long s_wave[16];
     __shared__ int s_cnt[16][3];
     __shared__ long long s_carry, s_need, s_total;
-    __shared__ int s_class[3], s_run[3];
+    __shared__ int s_class[3], s_run[3], s_nref;
     if (fl->err) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x == 0) s_need = s_total = 0;
@@ -410,7 +410,27 @@ __global__ void __launch_bounds__(1024) k_scan(int ntx, int nbands, const BandIn
         if (threadIdx.x == 0) {
             s_need = total > s_need ? total : s_need;
             s_total += total;
+            s_nref = 0;
         }
+        // the band's tiles with refined cells, in index order, for k_epr_ref
+        for (int c0 = 0; c0 < nt; c0 += 1024) {
+            const int i = c0 + threadIdx.x;
+            const bool f = i < nt && tiles[t0 + i].fmt != 0;
+            const unsigned long long m = __ballot(f);
+            const int rank = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) s_cnt[w][0] = __popcll(m);
+            __syncthreads();
+            int woff = 0, ctot = 0;
+            for (int k = 0; k < 16; k++) {
+                woff += k < w ? s_cnt[k][0] : 0;
+                ctot += s_cnt[k][0];
+            }
+            if (f) rlist[t0 + s_nref + woff + rank] = t0 + i;
+            __syncthreads();
+            if (threadIdx.x == 0) s_nref += ctot;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) rcount[bd] = s_nref;
         // Order in which k_epr takes the band's tiles: the heaviest first (a
         // tile's records measure its stencil work), so that the long ones do
         // not start last and leave the CUs idle at the end.  Stable partition
@@ -1577,14 +1597,9 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const double *m
 // refined cells.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const double *mom, Buffers b, int step, int tile0) {
+__device__ void epr_ref_tile(const Geom &g, const Phys &ph, const double *mom, Buffers &b, int step, int t) {
     using BS = Basis<D>;
     constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
-    __shared__ int s_skip;
-    int t = tile0 + blockIdx.x;
-    if (threadIdx.x == 0) s_skip = b.flags->err || b.tiles[t].fmt == 0;
-    __syncthreads();
-    if (s_skip) return;
     int tx0 = (t % g.ntx) * g.tx, ty0 = (t / g.ntx) * g.ty;
     int l = threadIdx.x;
     int px = tx0 + l % g.tx, py = ty0 + l / g.tx;
@@ -1697,6 +1712,22 @@ __global__ void __launch_bounds__(256) k_epr_ref(Geom g, Phys ph, const double *
         }
     }
     push_stats(b.stats, cs);
+}
+
+// The band's tiles with refined cells (listed by k_scan), a fixed grid of
+// workgroups taking them in turn: with none, the launch ends at once.  Two
+// waves per SIMD (the kernel spills), so that its workgroups fit beside the
+// other reconstruction kernels of the concurrent bands instead of waiting for
+// a CU to drain.
+template <typename T, int D>
+__global__ void __launch_bounds__(256, 2) k_epr_ref(Geom g, Phys ph, const double *mom, Buffers b, int step, int tile0,
+                                                    int band) {
+    __shared__ int s_skip;
+    if (threadIdx.x == 0) s_skip = b.flags->err;
+    __syncthreads();
+    if (s_skip) return;
+    const int n = b.rcount[band];
+    for (int j = blockIdx.x; j < n; j += gridDim.x) epr_ref_tile<T, D>(g, ph, mom, b, step, b.rlist[tile0 + j]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2183,16 +2214,21 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, double *mom_out, Bu
     constexpr int NTB = D == 2 ? GATHER_NTB : 1;
     constexpr int BX = NTB * TX, BY = TY / NTB;
     extern __shared__ double2 g_lds[];
-    // the launch covers block rows from br0 on
+    // Four workgroups per gather block (the launch covers block rows from br0
+    // on), one per 16 x 4 cell group (64 x 1 in 1D).  A cell's candidates are
+    // a chain of dependent loads (walk entry, descriptor, tile, record), so
+    // the four wavefronts of the workgroup share its 64 cells and take every
+    // fourth row of displacements (every fourth batch in 1D); their sums are
+    // added in wavefront order at the end.
     const int nbx = gather_blocks_x(g), nd = nbx * gather_blocks_y(g);
-    const int x0 = (blockIdx.x % nbx) * BX, y0 = (br0 + blockIdx.x / nbx) * BY;
+    const int blk = blockIdx.x >> 2, grp = blockIdx.x & 3, part = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int x0 = (blk % nbx) * BX, y0 = (br0 + blk / nbx) * BY;
     int lx, ly;
     if (D == 2) {
-        const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-        lx = (wv % NTB) * TX + (l & 15);
-        ly = (wv / NTB) * 4 + (l >> 4);
+        lx = (grp % NTB) * TX + (l & 15);
+        ly = (grp / NTB) * 4 + (l >> 4);
     } else {
-        lx = threadIdx.x;
+        lx = grp * 64 + l;
         ly = 0;
     }
     const int x = x0 + lx, y = y0 + ly;
@@ -2201,7 +2237,13 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, double *mom_out, Bu
     const int ntb = min(NTB, g.dtx - x0 / TX);
     const int own = lx / TX;
     const int M = *b.maxreach;
+    // uniform per workgroup (one cell group of one tile)
     const bool near = !b.flags->err && own < ntb && walk_distance(g, b, tl + own, M) <= M + 1;
+    unsigned long long *gp = b.gpart + nd + 4LL * br0 * nbx + blockIdx.x;
+    if (!near) {
+        if (threadIdx.x == 0) *gp = 0;
+        return;
+    }
     const T *SCR = (const T *)b.scratch;
     int hits = 0;
     // walk results of the tile, cached once the reach has been seen (entry of
@@ -2311,8 +2353,10 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, double *mom_out, Bu
         }
         const auto candidates = [&](const auto &blocked) {
             if (fluid) {
-                for (int dy = my; dy >= -my; dy--) {
-                    for (int dxb = mx; dxb >= -mx; dxb -= GU) {
+                for (int dy = my - (D == 2 ? part : 0); dy >= -my; dy -= (D == 2 ? 4 : 1)) {
+                    int batch = 0;
+                    for (int dxb = mx; dxb >= -mx; dxb -= GU, batch++) {
+                        if (D == 1 && (batch & 3) != part) continue;
                         long long sv[GU];
                         int sg[GU], spx[GU], spy[GU];
 #pragma unroll
@@ -2387,18 +2431,31 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, double *mom_out, Bu
         };
         if (staged_map) candidates(blocked_lds);
         else candidates(blocked_glb);
-        if (mine) {
+        // the four wavefronts' sums of each cell, added in wavefront order
+        // (the LDS of the blocker maps is free again once all are done)
+        __syncthreads();
+        double *red = (double *)g_lds;
+#pragma unroll
+        for (int k = 0; k < NM; k++) red[(part * NM + k) * 64 + l] = acc[k];
+        __syncthreads();
+        if (part == 0 && mine) {
             long long o = (long long)(y + g.wb) * g.sxn + (x + g.wl);
 #pragma unroll
-            for (int k = 0; k < NM; k++) mom_out[k * g.ns + o] = acc[k];
+            for (int k = 0; k < NM; k++) {
+                double v = red[k * 64 + l];
+                v += red[(NM + k) * 64 + l];
+                v += red[(2 * NM + k) * 64 + l];
+                v += red[(3 * NM + k) * 64 + l];
+                mom_out[k * g.ns + o] = v;
+            }
         }
     }
     __shared__ unsigned long long s_hits[4];
     unsigned long long hl = (unsigned long long)hits;
     for (int off = 32; off > 0; off >>= 1) hl += __shfl_xor(hl, off);
-    if ((threadIdx.x & 63) == 0) s_hits[threadIdx.x >> 6] = hl;
+    if (l == 0) s_hits[part] = hl;
     __syncthreads();
-    if (threadIdx.x == 0) b.gpart[nd + (long long)br0 * nbx + blockIdx.x] = s_hits[0] + s_hits[1] + s_hits[2] + s_hits[3];
+    if (threadIdx.x == 0) *gp = s_hits[0] + s_hits[1] + s_hits[2] + s_hits[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -2617,17 +2674,19 @@ hipError_t launch_prepare(const Geom &g, const Phys &ph, const double *mom, Buff
 hipError_t launch_scan(const Geom &g, Buffers &b, int nbands, long long slot_cap, int m_plan, int step,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, g.ntx, nbands, (const BandInfo *)b.bands, b.tiles, b.flags,
-                       slot_cap, step, b.order, (const int *)b.maxreach, m_plan);
+                       slot_cap, step, b.order, b.rlist, b.rcount, (const int *)b.maxreach, m_plan);
     return hipGetLastError();
 }
 
-// variant 0: cells with narrow stencils, 1: refined stencils, 2: wide
+// variant 0: cells with narrow stencils, 1: refined stencils (of band
+// `band`: a grid of at most EPR_REF_GRID workgroups over its list), 2: wide
 template <typename T, int D>
 static void epr_launch(const Geom &g, const Phys &ph, const double *mom, Buffers &b, int step, int variant,
-                       int tile0, int ntiles, hipStream_t s) {
+                       int tile0, int ntiles, int band, hipStream_t s) {
     const dim3 grid((unsigned)ntiles), blk(256);
     if (variant == 1)
-        hipLaunchKernelGGL((k_epr_ref<T, D>), grid, blk, 0, s, g, ph, mom, b, step, tile0);
+        hipLaunchKernelGGL((k_epr_ref<T, D>), dim3((unsigned)std::min(ntiles, EPR_REF_GRID)), blk, 0, s, g, ph, mom, b,
+                           step, tile0, band);
     else if (variant == 2)
         hipLaunchKernelGGL((k_epr<T, D, true>), grid, blk, 0, s, g, ph, mom, b, step, tile0);
     else
@@ -2635,26 +2694,26 @@ static void epr_launch(const Geom &g, const Phys &ph, const double *mom, Buffers
 }
 
 static void epr_dispatch(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step,
-                         int variant, int tile0, int ntiles, hipStream_t s) {
+                         int variant, int tile0, int ntiles, int band, hipStream_t s) {
     if (ntiles <= 0) return;
     if (mixed) {
-        if (g.dim == 1) epr_launch<float, 1>(g, ph, mom, b, step, variant, tile0, ntiles, s);
-        else epr_launch<float, 2>(g, ph, mom, b, step, variant, tile0, ntiles, s);
+        if (g.dim == 1) epr_launch<float, 1>(g, ph, mom, b, step, variant, tile0, ntiles, band, s);
+        else epr_launch<float, 2>(g, ph, mom, b, step, variant, tile0, ntiles, band, s);
     } else {
-        if (g.dim == 1) epr_launch<double, 1>(g, ph, mom, b, step, variant, tile0, ntiles, s);
-        else epr_launch<double, 2>(g, ph, mom, b, step, variant, tile0, ntiles, s);
+        if (g.dim == 1) epr_launch<double, 1>(g, ph, mom, b, step, variant, tile0, ntiles, band, s);
+        else epr_launch<double, 2>(g, ph, mom, b, step, variant, tile0, ntiles, band, s);
     }
 }
 
 hipError_t launch_epr(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step, int tile0,
                       int ntiles, int wide, hipStream_t s) {
-    epr_dispatch(g, ph, mixed, mom, b, step, wide ? 2 : 0, tile0, ntiles, s);
+    epr_dispatch(g, ph, mixed, mom, b, step, wide ? 2 : 0, tile0, ntiles, 0, s);
     return hipGetLastError();
 }
 
 hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step,
-                          int tile0, int ntiles, hipStream_t s) {
-    epr_dispatch(g, ph, mixed, mom, b, step, 1, tile0, ntiles, s);
+                          int tile0, int ntiles, int band, hipStream_t s) {
+    epr_dispatch(g, ph, mixed, mom, b, step, 1, tile0, ntiles, band, s);
     return hipGetLastError();
 }
 
@@ -2679,7 +2738,7 @@ static void gather_launch(const Geom &g, double *mom_out, Buffers &b, int gcap, 
         // 8 KB of LDS per wavefront for its blocker bits and summed-area table
         // (five workgroups per CU)
         const size_t lds_near = 32768;
-        hipLaunchKernelGGL((k_gather_near<T, D>), dim3(nt), dim3(256), lds_near, s, g, mom_out, b,
+        hipLaunchKernelGGL((k_gather_near<T, D>), dim3(4 * nt), dim3(256), lds_near, s, g, mom_out, b,
                            (int)(lds_near / 4), br0);
     }
 }
@@ -2702,8 +2761,9 @@ hipError_t launch_step_totals(const Geom &g, Buffers &b, hipStream_t s) {
     const int nt = 2 * g.ntx * g.nty;
     const int nb = (nt + 255) / 256 < 256 ? (nt + 255) / 256 : 256;
     hipLaunchKernelGGL(k_stats_reduce, dim3(nb), dim3(256), 0, s, (const DevStats *)b.bpart, nt, b.stats);
-    // arrival partials of k_gather, then of k_gather_near (when it runs)
-    const int nd = gather_blocks_x(g) * gather_blocks_y(g) * (b.tdist ? 2 : 1);
+    // arrival partials of k_gather, then of k_gather_near (four per block,
+    // when it runs)
+    const int nd = gather_blocks_x(g) * gather_blocks_y(g) * (b.tdist ? 5 : 1);
     const int nb2 = (nd + 255) / 256 < 256 ? (nd + 255) / 256 : 256;
     hipLaunchKernelGGL(k_sum_partials, dim3(nb2), dim3(256), 0, s, (const unsigned long long *)b.gpart, nd,
                        &b.stats->arrivals);
