@@ -621,12 +621,16 @@ static void build_plan(const Geom &g, Plan &P, int rows, int M) {
     const int bpr = gather_blocks_y(g) / std::max(dty, 1);
     for (int it = 0; it < nb; it++) {
         const int k = order[it];
-        // a slot freed by the gathers that followed the previous band's
-        // reconstruction is not reused yet: reusing it would make this
-        // reconstruction wait for those gathers, which wait for the previous
-        // one, and the bands would not overlap (the oldest free slot first)
+        // a slot freed by the gathers that followed one of the two previous
+        // bands' reconstructions is not reused yet: reusing it would make
+        // this reconstruction wait for those gathers, which wait for that
+        // reconstruction, and the bands would not overlap (the oldest free
+        // slot first).  Two bands back rather than one: the next band's
+        // reconstruction then also fills the tail of the current one
+        // (measured on the 8192 x 4096 Mach-10 channel at a 16 GiB budget:
+        // 50.1 -> 48.7 ms per step in FP64).
         int slot = -1;
-        const int delay = P.overlap ? 2 : 1;
+        const int delay = P.overlap ? 3 : 1;
         for (int sl = 0; sl < nslots; sl++)
             if (!slot_busy[sl] && freed_at[sl] <= it - delay && (slot < 0 || freed_at[sl] < freed_at[slot])) slot = sl;
         if (slot < 0) slot = nslots++;
