@@ -22,55 +22,16 @@
 
 using namespace lelbm;
 
+// What the band plan needs of the domain.
+static PlanGeom plan_geom(const Geom &g) {
+    return PlanGeom{g.nty, g.dty, g.ty, g.wb, g.syn, g.dim == 2 && g.bc[2] == LELBM_BC_PERIODIC, gather_blocks_y(g)};
+}
+
 // pinned host staging memory (see stage_h2d / stage_d2h)
 struct Stage {
     void *p = nullptr;
     size_t cap = 0;
 };
-
-// ---------------------------------------------------------------------------
-// Band plan of the population scratch.
-//
-// The source tiles are reconstructed in bands of whole tile rows; a band
-// writes its records into one of nslots slots of slot_cap elements, and the
-// gather of a destination tile row runs as soon as every band holding a
-// source within reach of it (m_plan cells, the plan's largest reach) has
-// been reconstructed.  A slot is reused once no pending destination row
-// needs its band.  With a periodic y axis the last band is reconstructed
-// first, so that the first destination rows, which reach across the wrap,
-// are gathered early; the first and the last band then stay live to the end.
-// The scratch is nslots x slot_cap elements, kept within the context's
-// budget: more bands of fewer rows when a band's records outgrow their slot.
-// ---------------------------------------------------------------------------
-enum { OP_EPR = 0, OP_GATHER = 1 };
-struct Op {
-    int kind;    // OP_EPR: reconstruct band a; OP_GATHER: gather destination block rows [a, a + n)
-    int a, n;
-    // what must finish first: a reconstruction into a reused slot waits for
-    // the last gather of the slot's former band (op dep, -1: none); a gather
-    // waits for the reconstructions of the bands it needs (ops
-    // Plan::gdeps[dep, dep + ndep))
-    int dep, ndep;
-};
-
-struct Plan {
-    int rows = 0;              // source tile rows per band (0: not built)
-    int m_plan = 0;            // largest reach (cells) the plan allows for
-    int nslots = 1;
-    long long slot_cap = 0;    // elements per slot
-    std::vector<BandInfo> bands;
-    std::vector<int> slot_of;
-    std::vector<Op> ops;
-    std::vector<int> gdeps;    // reconstruction ops the gathers wait for
-    bool uploaded = false;     // the device band table holds this plan
-    bool whole = false;        // one band of the whole domain because bands of one tile row cost more
-    bool overlap = true;       // a spare slot lets consecutive bands' reconstructions overlap
-    // working arrays of build_plan, reserved at creation so that re-planning
-    // allocates nothing
-    std::vector<int> w_order, w_int;
-    std::vector<char> w_flags;
-};
-
 
 struct lelbm_ctx {
     lelbm_params p;
@@ -574,173 +535,12 @@ static int upload_interior(lelbm_ctx *c, const void *src, int src_fp32, hipMemcp
     return LELBM_OK;
 }
 
-// Bands of `rows` source tile rows and the schedule of their reconstruction
-// and gathers for a largest reach of M cells (see Plan).
-static void build_plan(const Geom &g, Plan &P, int rows, int M) {
-    const int nty = g.nty, dty = g.dty;
-    rows = std::max(1, std::min(rows, nty));
-    const int nb = (nty + rows - 1) / rows;
-    P.rows = rows;
-    P.whole = false;
-    P.m_plan = nb == 1 ? INT_MAX / 2 : M;
-    P.bands.resize((size_t)nb);
-    P.slot_of.assign((size_t)nb, -1);
-    P.ops.clear();
-    P.gdeps.clear();
-    for (int k = 0; k < nb; k++) {
-        P.bands[k].row0 = k * rows;
-        P.bands[k].row1 = std::min(nty, (k + 1) * rows);
-        P.bands[k].base = 0;
-    }
-    // the bands that hold sources within reach of destination tile row j:
-    // padded cell rows j ty + wb - M ... (j + 1) ty - 1 + wb + M, wrapped on a
-    // periodic axis (mirror images across slip walls lie within that range)
-    const bool pery = g.dim == 2 && g.bc[2] == LELBM_BC_PERIODIC;
-    auto needs = [&](int j, int k) {
-        if (nb == 1) return true;
-        const int y0 = j * g.ty + g.wb - M, y1 = (j + 1) * g.ty - 1 + g.wb + M;
-        const int c0 = P.bands[k].row0 * g.ty, c1 = P.bands[k].row1 * g.ty - 1;   // the band's cell rows
-        if (!pery) return std::max(y0, c0) <= std::min(y1, std::min(c1, g.syn - 1));
-        if (y1 - y0 + 1 >= g.syn) return true;
-        const int a = ((y0 % g.syn) + g.syn) % g.syn, b = ((y1 % g.syn) + g.syn) % g.syn;
-        if (a <= b) return std::max(a, c0) <= std::min(b, c1);
-        return c1 >= a || c0 <= b;
-    };
-    std::vector<int> &order = P.w_order;
-    order.clear();
-    if (pery && nb > 1) order.push_back(nb - 1);
-    for (int k = 0; k < nb; k++)
-        if (!(pery && nb > 1 && k == nb - 1)) order.push_back(k);
-    P.w_flags.assign((size_t)4 * nb + (size_t)dty, 0);
-    char *done = P.w_flags.data(), *live = done + nb, *slot_busy = live + nb, *gathered = slot_busy + 2 * nb;
-    P.w_int.assign((size_t)4 * nb, -1);
-    int *last_gather = P.w_int.data(), *slot_free_op = last_gather + nb, *epr_of = slot_free_op + nb;   // op indices
-    int *freed_at = epr_of + nb;   // iteration that freed a slot
-    int nslots = 0;
-    // destination tile rows -> gather block rows
-    const int bpr = gather_blocks_y(g) / std::max(dty, 1);
-    for (int it = 0; it < nb; it++) {
-        const int k = order[it];
-        // a slot freed by the gathers that followed one of the two previous
-        // bands' reconstructions is not reused yet: reusing it would make
-        // this reconstruction wait for those gathers, which wait for that
-        // reconstruction, and the bands would not overlap (the oldest free
-        // slot first).  Two bands back rather than one: the next band's
-        // reconstruction then also fills the tail of the current one
-        // (measured on the 8192 x 4096 Mach-10 channel at a 16 GiB budget:
-        // 50.1 -> 48.7 ms per step in FP64).
-        int slot = -1;
-        const int delay = P.overlap ? 3 : 1;
-        for (int sl = 0; sl < nslots; sl++)
-            if (!slot_busy[sl] && freed_at[sl] <= it - delay && (slot < 0 || freed_at[sl] < freed_at[slot])) slot = sl;
-        if (slot < 0) slot = nslots++;
-        slot_busy[slot] = 1;
-        P.slot_of[k] = slot;
-        done[k] = live[k] = 1;
-        epr_of[k] = (int)P.ops.size();
-        P.ops.push_back(Op{OP_EPR, k, 1, slot_free_op[slot], 0});
-        // every destination row whose bands are all reconstructed, in runs
-        int run0 = -1;
-        for (int j = 0; j <= dty; j++) {
-            bool ready = j < dty && !gathered[j];
-            for (int kk = 0; ready && kk < nb; kk++) ready = done[kk] || !needs(j, kk);
-            if (ready) {
-                gathered[j] = 1;
-                if (run0 < 0) run0 = j;
-            } else if (run0 >= 0) {
-                const int gop = (int)P.ops.size();
-                Op op{OP_GATHER, run0 * bpr, (j - run0) * bpr, (int)P.gdeps.size(), 0};
-                for (int kk = 0; kk < nb; kk++) {
-                    bool any = false;
-                    for (int jj = run0; jj < j && !any; jj++) any = needs(jj, kk);
-                    if (!any) continue;
-                    last_gather[kk] = gop;
-                    P.gdeps.push_back(epr_of[kk]);
-                    op.ndep++;
-                }
-                P.ops.push_back(op);
-                run0 = -1;
-            }
-        }
-        // slots of bands no pending destination row needs are free again
-        for (int kk = 0; kk < nb; kk++) {
-            if (!live[kk]) continue;
-            bool used = false;
-            for (int j = 0; j < dty && !used; j++) used = !gathered[j] && needs(j, kk);
-            if (!used) {
-                live[kk] = 0;
-                slot_busy[P.slot_of[kk]] = 0;
-                slot_free_op[P.slot_of[kk]] = last_gather[kk];
-                freed_at[P.slot_of[kk]] = it;
-            }
-        }
-    }
-    P.nslots = std::max(1, nslots);
-    P.uploaded = false;
-}
-
-static void set_bases(Plan &P) {
-    for (size_t k = 0; k < P.bands.size(); k++) P.bands[k].base = (long long)P.slot_of[k] * P.slot_cap;
-    P.uploaded = false;
-}
-
 static int upload_plan(lelbm_ctx *c, Plan &P) {
     if (P.uploaded) return LELBM_OK;
     int r = stage_h2d(c->stage, c->stream, c->b.bands, P.bands.data(), P.bands.size() * sizeof(BandInfo));
     if (r != LELBM_OK) return r;
     c->plan.uploaded = c->fixed_plan.uploaded = false;   // the device table holds one plan at a time
     P.uploaded = true;
-    return LELBM_OK;
-}
-
-// After a step found a band's records larger than its slot (err =
-// ERR_OVERFLOW, need = the largest band's elements, total = all bands') or a
-// reach beyond the plan (ERR_REPLAN): the next plan within `limit` elements
-// of scratch.  When even bands of one tile row do not fit, the smaller of
-// one band of the whole domain and bands of one row (the scratch then
-// exceeds the limit); with a fixed scratch that is ENOMEM unless one band
-// fits it.
-static int plan_adapt(const Geom &g, Plan &P, long long limit, bool fixed, int err, long long need, long long total,
-                      int reach) {
-    const int margin = std::max(4, reach / 4);
-    if (P.whole && err == ERR_OVERFLOW) {
-        // stays one band (bands of one row cost more before): it grows
-        if (fixed && need > limit) return LELBM_ENOMEM;
-        P.slot_cap = fixed ? limit : need + need / 4 + 1024;
-    } else if (err == ERR_REPLAN) {
-        build_plan(g, P, P.rows, reach + margin);
-        P.slot_cap = std::min(P.slot_cap, limit / P.nslots);
-    } else if (need <= limit / P.nslots) {
-        P.slot_cap = std::min(limit / P.nslots, need + need / 4 + 1024);
-    } else if (P.rows > 1) {
-        // thinner bands, scaled by the share of a slot the largest band may
-        // take (a thinner plan may keep more bands live at once)
-        const long long per = limit / P.nslots;
-        const int old_rows = P.rows;
-        int rows = (int)std::max(1.0, 0.8 * old_rows * (double)per / (double)need);
-        rows = std::min(rows, old_rows - 1);
-        build_plan(g, P, rows, std::max(P.m_plan == INT_MAX / 2 ? 0 : P.m_plan, reach + margin));
-        const long long est = (long long)((double)need * rows / old_rows * 1.25) + 1024;
-        P.slot_cap = std::min(limit / P.nslots, est);
-    } else if (P.overlap) {
-        // bands of one row without the spare slot (no overlap of consecutive
-        // bands' reconstructions) before giving up the budget
-        P.overlap = false;
-        build_plan(g, P, 1, std::max(P.m_plan == INT_MAX / 2 ? 0 : P.m_plan, reach + margin));
-        P.slot_cap = limit / P.nslots;
-    } else {
-        const long long whole = total + total / 4 + 1024, rowwise = P.nslots * (need + need / 4 + 1024);
-        if (whole <= rowwise || (fixed && whole <= limit)) {
-            if (fixed && whole > limit) return LELBM_ENOMEM;
-            build_plan(g, P, g.nty, 0);
-            P.whole = true;
-            P.slot_cap = fixed ? limit : whole;
-        } else {
-            if (fixed) return LELBM_ENOMEM;
-            P.slot_cap = need + need / 4 + 1024;
-        }
-    }
-    set_bases(P);
     return LELBM_OK;
 }
 
@@ -753,7 +553,7 @@ static int finish_create(lelbm_ctx *c) {
     HIPCHECK(launch_prepare(c->g, c->ph, c->b.mom[c->cur], c->b, 0, s));
     // one band of all rows with an empty slot: the scan reports the records
     // of the whole domain
-    build_plan(c->g, c->plan, c->g.nty, 0);
+    build_plan(plan_geom(c->g), c->plan, c->g.nty, 0);
     c->plan.slot_cap = 0;
     set_bases(c->plan);
     int rr = upload_plan(c, c->plan);
@@ -763,21 +563,11 @@ static int finish_create(lelbm_ctx *c) {
     rr = stage_d2h(c->stage, s, &f, c->b.flags, sizeof(Flags));
     if (rr != LELBM_OK) return rr;
     if (f.err == ERR_OVERFLOW) {
-        // the first plan: one band if the whole domain's records (with a
-        // quarter to spare) fit the budget, else bands sized for about five
-        // slots (the most a periodic plan keeps live with bands wider than
-        // the reach)
+        // the first plan: one band if the whole domain's records fit the
+        // budget, else bands
         const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
         const long long limit = std::max<long long>(c->budget / (long long)esz, 1);
-        const long long want = f.need + f.need / 4 + 1024;
-        if (want <= limit) {
-            c->plan.slot_cap = want;
-        } else {
-            const int rows = (int)std::max(1.0, (double)c->g.nty * (double)limit / (5.0 * (double)want));
-            build_plan(c->g, c->plan, rows, f.reach + std::max(4, f.reach / 4));
-            c->plan.slot_cap = limit / c->plan.nslots;
-        }
-        set_bases(c->plan);
+        plan_first(plan_geom(c->g), c->plan, limit, f.need, f.reach);
         int r = grow_scratch(c, (long long)c->plan.nslots * c->plan.slot_cap);
         if (r != LELBM_OK) return r;
     } else if (f.err != 0) {
@@ -1027,7 +817,7 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
         if (f.err == ERR_OVERFLOW || f.err == ERR_REPLAN) {
             // re-plan the bands (and grow the context's scratch within its
             // budget), then repeat the step
-            r = plan_adapt(c->g, P, limit, noalloc, f.err, f.need, f.total, f.reach);
+            r = plan_adapt(plan_geom(c->g), P, limit, noalloc, f.err, f.need, f.total, f.reach);
             if (getenv("LELBM_DEBUG"))
                 fprintf(stderr,
                         "lelbm: step %d %s (need %lld, total %lld, reach %d): %zu bands of %d rows, %d slots of "
@@ -1224,7 +1014,7 @@ extern "C" int lelbm_set_scratch_budget(lelbm_ctx *c, long long bytes) {
         c->b.scratch_cap = 0;
     }
     c->plan.overlap = true;
-    build_plan(c->g, c->plan, c->g.nty, 0);
+    build_plan(plan_geom(c->g), c->plan, c->g.nty, 0);
     c->plan.slot_cap = std::min(c->b.scratch_cap, limit);
     set_bases(c->plan);
     return LELBM_OK;

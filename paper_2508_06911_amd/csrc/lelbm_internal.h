@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/lelbm.h"
+#include "lelbm_plan.h"
 
 namespace lelbm {
 
@@ -47,22 +48,6 @@ constexpr int MLP_IN = 16, MLP_H = 64, MLP_OUT = 16;
 constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 1024, MLP_OFF_W2 = 1088, MLP_OFF_B2 = 5184, MLP_OFF_W3 = 5248,
               MLP_OFF_B3 = 6272, MLP_NPARAM = 6288;
 constexpr int MLP_NORM = 64;   // standardisation constants (input/output mean and scale)
-
-// Internal error codes: a band's population records exceed their scratch
-// slot (the host grows the slots or re-plans the bands and repeats the step);
-// a stencil reaches farther than the band plan allows for (the host re-plans
-// and repeats the step).
-constexpr int ERR_OVERFLOW = -100;
-constexpr int ERR_REPLAN = -101;
-
-// The source tiles are reconstructed in bands of whole tile rows, each
-// writing its records into one slot of the population scratch (the slots
-// are reused as the gather consumes them), so the scratch is bounded by a
-// budget instead of growing with the stencils of the whole domain.
-struct BandInfo {
-    int row0, row1;          // source tile rows [row0, row1)
-    long long base;          // first scratch element of the band's slot
-};
 
 struct Geom {
     int dim, nx, ny;
