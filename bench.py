@@ -127,6 +127,8 @@ def parse():
     ap.add_argument("--c4-horizon", type=int, default=0,
                     help="only run the 8192x4096 Mach-10 channel for this many steps on both paths "
                          "(FP64 and FP32 + learned guess) and report the L1 error per field")
+    ap.add_argument("--c4-horizon-seconds", type=float, default=900.0,
+                    help="wall-time limit of the --c4-horizon run (it stops at the last whole chunk)")
     ap.add_argument("--channel-only", action="store_true",
                     help="run only the 4096x2048 channel context (for kernel traces of that workload)")
     ap.add_argument("--c4-only", action="store_true",
@@ -439,6 +441,56 @@ def horizon_run(lb, torch, cfg, prim, steps, runs, mlp, label, fluid=None):
     return out
 
 
+def lockstep_horizon(lb, torch, cfg, prim, steps, runs, mlp, label, fluid, budget, seconds, chunk=250):
+    """Two paths from the same initial state advanced in lockstep, `chunk`
+    steps at a time, with the relative L1 error of each field of the second
+    against the first after every chunk (the error's growth over the
+    horizon).  Stops at `steps`, or once the next chunk would pass `seconds`
+    of wall time; reports the steps reached."""
+    m = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
+    ctxs = []
+    for name, prec, guess in runs:
+        c = lb.Lelbm(cfg, m, precision=prec, guess=guess)
+        if guess == lb.GUESS_MLP:
+            c.set_mlp(mlp)
+        if budget:
+            c.set_scratch_budget(budget)
+        ctxs.append(c)
+    del m
+    t0 = time.perf_counter()
+    done, curve, per = 0, [], {name: 0.0 for name, _, _ in runs}
+    qmax = {name: 0 for name, _, _ in runs}
+    last = None
+    while done < steps:
+        k = min(chunk, steps - done)
+        if done and time.perf_counter() - t0 + last * k / chunk > seconds:
+            break
+        tc = time.perf_counter()
+        for (name, _, _), c in zip(runs, ctxs):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            st = c.step(k)
+            torch.cuda.synchronize()
+            per[name] += time.perf_counter() - ts
+            qmax[name] = max(qmax[name], st["q_max"])
+        done += k
+        moms = [c.read_moments()[:, fluid] for c in ctxs]
+        e = l1_errors(moms[1], moms[0])
+        del moms
+        curve.append({"step": done, "l1": {f: float("%.4g" % v) for f, v in e.items()},
+                      "q_mean": round(st["q_mean"], 1), "q_max": int(st["q_max"])})
+        last = time.perf_counter() - tc
+        log("%s: %d / %d steps, %.0f s, L1 rho %.3g u %.3g T %.3g, q_mean %.0f q_max %d"
+            % (label, done, steps, time.perf_counter() - t0, e["rho"], e["u"], e["T"], st["q_mean"], st["q_max"]))
+    out = {"steps_requested": steps, "steps": done, "l1_curve": curve, "seconds": round(time.perf_counter() - t0, 1)}
+    for (name, _, _), c in zip(runs, ctxs):
+        persistent, scratch = c.memory()
+        out[name] = {"ms_per_step": round(per[name] / max(done, 1) * 1e3, 3), "q_max": qmax[name],
+                     "hbm_bytes": {"persistent": persistent, "scratch": scratch}}
+        c.close()
+    return out
+
+
 def c0_line(lb, li, torch):
     """The 1D two-state configuration: 2000 cells, seed 0, 1000 steps, on both
     paths, beside the oracle on the host cores for the same 1000 steps."""
@@ -524,9 +576,9 @@ def main():
     if a.c4_horizon:
         mlp, _ = harvest_and_train(a, lb, li, torch)
         cfg, prim = li.channel(0, nx=8192, ny=4096, n_obstacles=8, mach=10.0, pad=48)
-        out = horizon_run(lb, torch, cfg, prim, a.c4_horizon,
-                          (("fp64-eq", lb.FP64, lb.GUESS_EQ), ("mixed-mlp", lb.MIXED, lb.GUESS_MLP)), mlp, "C4",
-                          fluid=cfg["solid"].ravel() == 0)
+        out = lockstep_horizon(lb, torch, cfg, prim, a.c4_horizon,
+                               (("fp64-eq", lb.FP64, lb.GUESS_EQ), ("mixed-mlp", lb.MIXED, lb.GUESS_MLP)), mlp,
+                               "C4", cfg["solid"].ravel() == 0, a.scratch_budget, a.c4_horizon_seconds)
         out["workload"] = ("channel 8192x4096, Mach 10 inflow, 8 obstacles (seed 0), started from rest, "
                            "%d steps" % a.c4_horizon)
         mlp.close()

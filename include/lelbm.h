@@ -115,6 +115,15 @@ typedef struct {
                                          NULL; copied at create.  Solid cells hold no gas (their moments
                                          read as 0) and reflect population paths like slip walls
                                          (Sec. III.B); they may not touch an outflow or inflow face. */
+    /* Oscillating point mass source (Sec. IV.C, Eqs. VC1, VC6-VC8): each step
+     * adds mass src_rate * sin(src_omega * t) (Delta t = 1) to interior cell
+     * (src_x, src_y) as a Maxwellian at rest in the cell's frame at its RT,
+     * with t = src_t0 + the number of steps the context has completed.
+     * src_rate = 0: no source.  The cell must be an interior fluid cell
+     * (src_y = 0 in 1D); rho + the added mass must stay positive (otherwise
+     * the reconstruction fails with LELBM_EEPR). */
+    int src_x, src_y;
+    double src_rate, src_omega, src_t0;
 } lelbm_params;
 
 /* Statistics accumulated over the steps of one lelbm_step call.  Newton

@@ -20,8 +20,8 @@ Workloads (lattice units, dx = dt = 1):
   * ``channel``    -- supersonic inflow past seeded elliptical obstacles in a
     channel with slip walls (structure of the paper's blunt-body cases,
     Sec. V.E; no external reference data is used).
-  * ``shear_wave`` / ``acoustic_pulse`` -- the paper's verification problems
-    (Sec. IV.A, IV.D).
+  * ``shear_wave`` / ``acoustic_pulse`` / ``acoustic_source`` -- the paper's
+    verification problems (Sec. IV.A, IV.D, IV.C).
 
 Physical states are mapped to lattice units by acoustic scaling (Sec. V.B):
 RT_lat = s^2 RT_phys and u_lat = s u_phys with s^2 = RT_floor / min RT_phys.
@@ -213,6 +213,23 @@ def acoustic_pulse(n=400, RT=1.0, drho=1e-4, width=4.0, K=K_1D, pad=32):
     x = np.arange(n) + 0.5
     rho = 1.0 + drho * np.exp(-0.5 * ((x - n / 2) / width) ** 2)
     prim = {"rho": rho[None, :], "ux": np.zeros((1, n)), "uy": np.zeros((1, n)), "RT": np.full((1, n), RT)}
+    return cfg, prim
+
+
+def acoustic_source(n=1200, RT=1.0, rate=1e-6, period=64.0, nu_b=0.8, nu=1e-3, K=K_1D):
+    """Quiescent periodic 1D gas with an oscillating point mass source of
+    rate * sin(2 pi t / period) in the centre cell (Sec. IV.C).  Collision
+    frequencies from the targets: shear and heat flux from nu = RT (1/omega -
+    1/2), bulk from nu_b = RT (2/D - 2/(D + K)) (1/omega_b - 1/2) (Eqs.
+    C8a-c with D = 1)."""
+    cfg = _base_cfg(1, n, 1, K)
+    om = 1.0 / (nu / RT + 0.5)
+    om_b = 1.0 / (nu_b / (RT * (2.0 - 2.0 / (1.0 + K))) + 0.5)
+    cfg.update({"omega_f": om, "omega_b": om_b, "omega_h": om, "kn_limiter": 0,
+                "source": {"x": n // 2, "y": 0, "rate": rate, "omega": 2 * np.pi / period, "t0": 0.0},
+                "nu": nu, "nu_b": nu_b})
+    shape = (1, n)
+    prim = {"rho": np.ones(shape), "ux": np.zeros(shape), "uy": np.zeros(shape), "RT": np.full(shape, RT)}
     return cfg, prim
 
 

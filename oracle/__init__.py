@@ -48,6 +48,8 @@ class Params(ctypes.Structure):
         ("bc", ctypes.c_int * 4), ("pad", ctypes.c_int),
         ("in_rho", ctypes.c_double), ("in_u", ctypes.c_double * 2), ("in_RT", ctypes.c_double),
         ("solid", ctypes.c_void_p),
+        ("src_x", ctypes.c_int), ("src_y", ctypes.c_int),
+        ("src_rate", ctypes.c_double), ("src_omega", ctypes.c_double), ("src_t", ctypes.c_double),
     ]
 
 
@@ -84,6 +86,7 @@ def lib():
         L.orc_moments_from_primitives.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_long,
                                                   dp, dp, dp, dp, dp]
         L.orc_collide_flat.argtypes = [ctypes.POINTER(Params), dp, dp]
+        L.orc_collide_src_flat.argtypes = [ctypes.POINTER(Params), dp, ctypes.c_double, dp]
         L.orc_las.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                               ctypes.c_int, dp, dp, ip, dp]
         L.orc_las_radius.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
@@ -140,6 +143,10 @@ def make_params(cfg):
         m = np.ascontiguousarray(solid, dtype=np.uint8).reshape(p.ny, p.nx)
         p._solid_ref = m                     # keep the mask alive with the struct
         p.solid = m.ctypes.data_as(ctypes.c_void_p)
+    src = cfg.get("source")
+    if src is not None:
+        p.src_x, p.src_y = src["x"], src.get("y", 0)
+        p.src_rate, p.src_omega, p.src_t = src["rate"], src["omega"], src.get("t0", 0.0)
     return p
 
 
@@ -160,13 +167,17 @@ _COLLIDE_KEYS = ["rho", "ux", "uy", "RT", "kn", "om_f", "om_b", "om_h", "limited
                  "Pxx", "Pxy", "Pyy", "Qx", "Qy", "g0", "hx", "hy"]
 
 
-def collide(cfg, mom):
+def collide(cfg, mom, src=None):
     """Collision stage of one cell: dict of macroscopic variables, non-equilibrium
-    central moments, effective frequencies and the normalised targets m, n."""
+    central moments, effective frequencies and the normalised targets m, n
+    (with src: a mass source of src in the cell, Eqs. VC6-VC8)."""
     p = make_params(cfg)
     mom = np.ascontiguousarray(mom, dtype=np.float64)
     out = np.zeros(len(_COLLIDE_KEYS) + 16)
-    st = lib().orc_collide_flat(ctypes.byref(p), _dp(mom), _dp(out))
+    if src is None:
+        st = lib().orc_collide_flat(ctypes.byref(p), _dp(mom), _dp(out))
+    else:
+        st = lib().orc_collide_src_flat(ctypes.byref(p), _dp(mom), ctypes.c_double(src), _dp(out))
     d = dict(zip(_COLLIDE_KEYS, out[:len(_COLLIDE_KEYS)]))
     k = len(_COLLIDE_KEYS)
     nf, ng = (4, 3) if cfg["dim"] == 1 else (10, 6)

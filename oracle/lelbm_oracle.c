@@ -27,6 +27,7 @@
  *   - slip walls and solid cells ....... Sec. III.B (specular reflection of
  *                                        the population path at every face
  *                                        it would cross into a blocker)
+ *   - oscillating point mass source .... Sec. IV.C, Eqs. (VC1, VC6-VC8)
  *
  * Readings taken where the paper is ambiguous are listed in the header
  * comment of each function.
@@ -43,6 +44,9 @@
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+/* residual below which a Newton solve that stops decreasing is converged */
+#define ORC_STALL_RES 1e-10
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EEPR = -4, ORC_ENONFINITE = -5, ORC_EREACH = -6 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_INFLOW = 2, ORC_BC_SLIPWALL = 3 };
@@ -62,6 +66,11 @@ typedef struct {
     int pad;                         /* pad width for outflow/inflow faces */
     double in_rho, in_u[2], in_RT;   /* inflow state */
     const unsigned char *solid;      /* nx*ny legoland mask (1 = solid cell) or NULL */
+    /* oscillating point mass source, Sec. IV.C: rate*sin(omega*t) in cell
+     * (src_x, src_y) of the interior; rate = 0: none.  src_t is the time of
+     * the first step's collision (steps of orc_run follow at src_t + k). */
+    int src_x, src_y;
+    double src_rate, src_omega, src_t;
 } orc_params;
 
 typedef struct {
@@ -140,6 +149,7 @@ int orc_moments_from_primitives(int dim, double K, long n, const double *rho, co
 /* ------------------------------------------------------------------------ */
 typedef struct {
     double rho, u[2], RT;
+    double rho_post;                     /* zeroth post-collision moment (rho plus a mass source) */
     double Pneq[2][2], Q[2], g0, h[2];   /* non-equilibrium central moments */
     double kn, om_f, om_b, om_h;
     int limited;
@@ -156,7 +166,15 @@ static double limit_omega(double kn, double om, const orc_params *p)
     return (p->omega_H - om) / (p->kn_hi - p->kn_lo) * (k - p->kn_lo) + om;
 }
 
-int orc_collide(const orc_params *p, const double *mom, orc_cell *c)
+/* src: mass added to the cell in this step, Delta t times the rate of the  */
+/* source (Eq. VC1), 0 elsewhere.  Its central moments (Eqs. VC6-VC7) are   */
+/* those of a Maxwellian at rest in the cell's frame at the cell's RT: mass */
+/* src, no first or third moments, second moments src RT delta, phonon     */
+/* energy src K RT with second moments src K RT RT delta.  Added to the     */
+/* post-collision moments (Eq. VC8), they leave RT and the frame unchanged  */
+/* and raise the zeroth moment to rho + src, which the targets are          */
+/* normalised by (Eq. IIB18) and the moment fractions scaled by.            */
+static int collide_src(const orc_params *p, const double *mom, double src, orc_cell *c)
 {
     int D = p->dim;
     double K = p->K;
@@ -177,6 +195,9 @@ int orc_collide(const orc_params *p, const double *mom, orc_cell *c)
     double RT = ((Mxx + Myy + G0) / rho - uu) / (D + K);
     if (!(RT > 0.0) || !isfinite(RT)) return ORC_EEPR;
     c->rho = rho; c->u[0] = ux; c->u[1] = uy; c->RT = RT;
+    double rp = rho + src;
+    if (!(rp > 0.0)) return ORC_EEPR;
+    c->rho_post = rp;
 
     /* Eq. (IIB9a): P_ab = M_ab - rho (u_a u_b + RT delta_ab) */
     double P[2][2] = {{0, 0}, {0, 0}};
@@ -236,16 +257,17 @@ int orc_collide(const orc_params *p, const double *mom, orc_cell *c)
     for (int a = 0; a < 2; a++)
         for (int g = 0; g < 2; g++) t[a][g] = (1.0 + 2.0 * (a == g)) / (D + 2) * Q[g];
 
-    /* Eqs. (IIB16a-d) normalised by rho (Eq. IIB18) */
+    /* Eqs. (IIB16a-d) normalised by rho (Eq. IIB18), with a mass source by  */
+    /* rho + src: (rho RT delta + neq + src RT delta) / (rho + src)          */
     double mab[2][2];
     for (int a = 0; a < 2; a++)
         for (int b = 0; b < 2; b++)
-            mab[a][b] = RT * (a == b) + ((1.0 - of) * shear[a][b] + (1.0 - ob) * bulk[a][b]) / rho;
-    double rKT = rho * K * RT;
+            mab[a][b] = RT * (a == b) + ((1.0 - of) * shear[a][b] + (1.0 - ob) * bulk[a][b]) / rp;
+    double rKT = rp * K * RT;
     if (D == 1) {
         c->nf = 4; c->ng = 3;
         c->m[0] = 1.0; c->m[1] = 0.0; c->m[2] = mab[0][0];
-        c->m[3] = (1.0 - oh) * t[0][0] / rho;
+        c->m[3] = (1.0 - oh) * t[0][0] / rp;
         /* Eqs. (IIB16e-f, IIB17) normalised by rho K RT */
         c->n[0] = 1.0 + (1.0 - ob) * g0 / rKT;
         c->n[1] = (1.0 - oh) * h[0] / rKT;
@@ -254,10 +276,10 @@ int orc_collide(const orc_params *p, const double *mom, orc_cell *c)
         c->nf = 10; c->ng = 6;
         c->m[0] = 1.0; c->m[1] = 0.0; c->m[2] = 0.0;
         c->m[3] = mab[0][0]; c->m[4] = mab[0][1]; c->m[5] = mab[1][1];
-        c->m[6] = (1.0 - oh) * t[0][0] / rho;   /* xxx = M~_{xx|x} */
-        c->m[7] = (1.0 - oh) * t[0][1] / rho;   /* xxy = M~_{xx|y} */
-        c->m[8] = (1.0 - oh) * t[1][0] / rho;   /* xyy = M~_{yy|x} */
-        c->m[9] = (1.0 - oh) * t[1][1] / rho;   /* yyy = M~_{yy|y} */
+        c->m[6] = (1.0 - oh) * t[0][0] / rp;    /* xxx = M~_{xx|x} */
+        c->m[7] = (1.0 - oh) * t[0][1] / rp;    /* xxy = M~_{xx|y} */
+        c->m[8] = (1.0 - oh) * t[1][0] / rp;    /* xyy = M~_{yy|x} */
+        c->m[9] = (1.0 - oh) * t[1][1] / rp;    /* yyy = M~_{yy|y} */
         c->n[0] = 1.0 + (1.0 - ob) * g0 / rKT;
         c->n[1] = (1.0 - oh) * h[0] / rKT;
         c->n[2] = (1.0 - oh) * h[1] / rKT;
@@ -266,12 +288,28 @@ int orc_collide(const orc_params *p, const double *mom, orc_cell *c)
     return ORC_OK;
 }
 
+int orc_collide(const orc_params *p, const double *mom, orc_cell *c) { return collide_src(p, mom, 0.0, c); }
+
 /* Flat export of orc_collide for the tests: out = [rho, ux, uy, RT, kn,
  * om_f, om_b, om_h, limited, Pxx, Pxy, Pyy, Qx, Qy, g0, hx, hy, m[10], n[6]] */
 int orc_collide_flat(const orc_params *p, const double *mom, double *out)
 {
     orc_cell c;
     int st = orc_collide(p, mom, &c);
+    double v[] = {c.rho, c.u[0], c.u[1], c.RT, c.kn, c.om_f, c.om_b, c.om_h, (double)c.limited,
+                  c.Pneq[0][0], c.Pneq[0][1], c.Pneq[1][1], c.Q[0], c.Q[1], c.g0, c.h[0], c.h[1]};
+    int k = 0;
+    for (unsigned i = 0; i < sizeof(v) / sizeof(v[0]); i++) out[k++] = v[i];
+    for (int i = 0; i < 10; i++) out[k++] = c.m[i];
+    for (int i = 0; i < 6; i++) out[k++] = c.n[i];
+    return st;
+}
+
+/* As orc_collide_flat, with a mass source of src in the cell. */
+int orc_collide_src_flat(const orc_params *p, const double *mom, double src, double *out)
+{
+    orc_cell c;
+    int st = collide_src(p, mom, src, &c);
     double v[] = {c.rho, c.u[0], c.u[1], c.RT, c.kn, c.om_f, c.om_b, c.om_h, (double)c.limited,
                   c.Pneq[0][0], c.Pneq[0][1], c.Pneq[1][1], c.Q[0], c.Q[1], c.g0, c.h[0], c.h[1]};
     int k = 0;
@@ -416,7 +454,10 @@ int orc_las(int dim, const double *u, double RT, double n_conf, int r_min, int c
 /* rounding level), and the populations are evaluated at the polished        */
 /* multipliers.  Safeguard: while the Newton decrement r.dl exceeds 1e-8, a   */
 /* step must lower the convex dual Phi = sum_i f_i + lambda.M' by the Armijo  */
-/* fraction 1e-4, else it is halved (at most 30 times).  Failure (Cholesky    */
+/* fraction 1e-4, else it is halved (at most 30 times).  A residual that is  */
+/* below 1e-10 and did not decrease at the last update has reached the       */
+/* rounding floor of the sums (large, badly conditioned stencils stall just  */
+/* above 1e-12): the solve is taken as converged there.  Failure (Cholesky    */
 /* breakdown, non-finite values, line search or iteration cap exhausted)      */
 /* returns ORC_EEPR.                                                          */
 /* ------------------------------------------------------------------------ */
@@ -516,6 +557,7 @@ int orc_epr(int dim, int nb, int q, const double *c, const double *dC, const dou
     if (!popt) return ORC_ENOMEM;
     int st = epr_eval(dim, nb, q, c, dC, u, lam, target, pop, &phi, r, A);
     int nit = 0;
+    double res_prev = INFINITY;
     if (st != ORC_OK) { free(popt); return ORC_EEPR; }
     for (;;) {
         double res = 0.0;
@@ -524,6 +566,8 @@ int orc_epr(int dim, int nb, int q, const double *c, const double *dC, const dou
             if (v > res) res = v;
         }
         if (res <= tol) break;
+        if (nit > 0 && res <= ORC_STALL_RES && !(res < res_prev)) break;
+        res_prev = res;
         if (nit >= maxit) { free(popt); return ORC_EEPR; }
         if (cholesky_solve(nb, A, r, dl) != ORC_OK) { free(popt); return ORC_EEPR; }
         double dec = 0.0;
@@ -592,11 +636,11 @@ static void source_moments(const orc_params *p, const double *in, int sx, int sy
     for (int k = 0; k < nm; k++) m[k] = in[(long)k * n + (long)iy * nx + ix];
 }
 
-static void process_cell(const orc_params *p, const double *mom, cell_out *co)
+static void process_cell(const orc_params *p, const double *mom, double src, cell_out *co)
 {
     orc_cell cl;
     memset(co, 0, sizeof(*co));
-    int st = orc_collide(p, mom, &cl);
+    int st = collide_src(p, mom, src, &cl);
     if (st != ORC_OK) { co->status = st; return; }
     co->rho = cl.rho; co->RT = cl.RT; co->u[0] = cl.u[0]; co->u[1] = cl.u[1];
     co->kn = cl.kn; co->limited = cl.limited;
@@ -622,9 +666,10 @@ static void process_cell(const orc_params *p, const double *mom, cell_out *co)
         free(c); free(d); free(pf); free(pg);
         return;
     }
-    /* moment fractions, Eq. (IIE3a): rho f' and rho K RT g' */
-    double sg = cl.rho * p->K * cl.RT;
-    for (int i = 0; i < q; i++) { pf[i] *= cl.rho; pg[i] *= sg; }
+    /* moment fractions, Eq. (IIE3a): rho f' and rho K RT g' (rho plus the  */
+    /* source's mass at the source cell)                                     */
+    double sg = cl.rho_post * p->K * cl.RT;
+    for (int i = 0; i < q; i++) { pf[i] *= cl.rho_post; pg[i] *= sg; }
     co->q = q; co->c = c; co->d = d; co->wf = pf; co->wg = pg;
     co->it_f = itf; co->it_g = itg;
     co->status = ORC_OK;
@@ -796,7 +841,10 @@ int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
             }
             double m[11];
             source_moments(p, in, sx, sy, m);
-            process_cell(p, m, &co[k - c0]);
+            /* Eq. (VC1) at the time of this step's collision, Delta t = 1 */
+            double src = 0.0;
+            if (p->src_rate != 0.0 && sx == p->src_x && sy == p->src_y) src = p->src_rate * sin(p->src_omega * p->src_t);
+            process_cell(p, m, src, &co[k - c0]);
         }
         /* serial, source-major deposit */
         for (long k = c0; k < c1; k++) {
@@ -861,9 +909,11 @@ int orc_run(const orc_params *p, const double *in, double *out, int nsteps, orc_
     memset(&acc, 0, sizeof(acc));
     acc.q_min = 1 << 30; acc.rt_min = INFINITY; acc.fail_cell = -1;
     int status = ORC_OK, k;
+    orc_params pk = *p;
     for (k = 0; k < nsteps; k++) {
         orc_stats s;
-        status = orc_step(p, out, tmp, &s);
+        pk.src_t = p->src_t + k;
+        status = orc_step(&pk, out, tmp, &s);
         if (status != ORC_OK) { acc.fail_cell = s.fail_cell; acc.fail_code = s.fail_code; break; }
         memcpy(out, tmp, sizeof(double) * nm * n);
         acc.cells += s.cells; acc.it_sum_f += s.it_sum_f; acc.it_sum_g += s.it_sum_g;

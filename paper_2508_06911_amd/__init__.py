@@ -39,6 +39,8 @@ class Params(ctypes.Structure):
         ("bc", ctypes.c_int * 4), ("pad", ctypes.c_int),
         ("in_rho", ctypes.c_double), ("in_u", ctypes.c_double * 2), ("in_RT", ctypes.c_double),
         ("solid", ctypes.c_void_p),
+        ("src_x", ctypes.c_int), ("src_y", ctypes.c_int),
+        ("src_rate", ctypes.c_double), ("src_omega", ctypes.c_double), ("src_t0", ctypes.c_double),
     ]
 
 
@@ -168,6 +170,10 @@ def make_params(cfg, precision=FP64, guess=GUESS_EQ):
         m = np.ascontiguousarray(solid, dtype=np.uint8).reshape(p.ny, p.nx)
         p._solid_ref = m                     # kept alive with the struct; the library copies it
         p.solid = m.ctypes.data_as(ctypes.c_void_p)
+    src = cfg.get("source")
+    if src is not None:
+        p.src_x, p.src_y = src["x"], src.get("y", 0)
+        p.src_rate, p.src_omega, p.src_t0 = src["rate"], src["omega"], src.get("t0", 0.0)
     return p
 
 

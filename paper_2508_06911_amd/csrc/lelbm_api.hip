@@ -37,6 +37,8 @@ struct lelbm_ctx {
     lelbm_params p;
     Geom g;
     Phys ph;
+    Phys ph_step;            // ph with the current step's source mass (read at each launch)
+    long long steps_done;    // completed steps (the time of a point mass source)
     int mixed;
     int nmom;
     hipStream_t stream;
@@ -198,6 +200,12 @@ static int validate(const lelbm_params *p) {
         if (p->bc[f] == LELBM_BC_OUTFLOW || p->bc[f] == LELBM_BC_INFLOW) needpad = true;
     if (needpad && p->pad < 1) return LELBM_EINVAL;
     if (p->kn_limiter && !(p->kn_hi > p->kn_lo)) return LELBM_EINVAL;
+    if (p->src_rate != 0.0) {
+        if (!std::isfinite(p->src_rate) || !std::isfinite(p->src_omega) || !std::isfinite(p->src_t0))
+            return LELBM_EINVAL;
+        if (p->src_x < 0 || p->src_x >= p->nx || p->src_y < 0 || p->src_y >= p->ny) return LELBM_EINVAL;
+        if (p->solid && p->solid[(long long)p->src_y * p->nx + p->src_x]) return LELBM_EINVAL;
+    }
     return LELBM_OK;
 }
 
@@ -432,6 +440,10 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ph.in_RT = p->in_RT;
     ph.lin_guess = p->guess == LELBM_GUESS_LIN;
     ph.prev_guess = p->guess == LELBM_GUESS_PREV;
+    ph.src_node = p->src_rate != 0.0 ? (long long)(p->src_y + g.wb) * g.sxn + (p->src_x + g.wl) : -1;
+    ph.src_mass = 0.0;
+    c->ph_step = ph;
+    c->steps_done = 0;
 
     Buffers &b = c->b;
     long long ns = g.ns;
@@ -672,19 +684,19 @@ static hipError_t do_scan(lelbm_ctx *c, void *a) {
 static hipError_t do_epr(lelbm_ctx *c, void *a) {
     const StepArg &s = *(StepArg *)a;
     const BandInfo &bd = s.plan->bands[s.a];
-    return launch_epr(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
+    return launch_epr(c->g, c->ph_step, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
                       (bd.row1 - bd.row0) * c->g.ntx, 0, s.es);
 }
 static hipError_t do_epr_wide(lelbm_ctx *c, void *a) {
     const StepArg &s = *(StepArg *)a;
     const BandInfo &bd = s.plan->bands[s.a];
-    return launch_epr(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
+    return launch_epr(c->g, c->ph_step, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
                       (bd.row1 - bd.row0) * c->g.ntx, 1, s.ws);
 }
 static hipError_t do_epr_ref(lelbm_ctx *c, void *a) {
     const StepArg &s = *(StepArg *)a;
     const BandInfo &bd = s.plan->bands[s.a];
-    return launch_epr_ref(c->g, c->ph, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
+    return launch_epr_ref(c->g, c->ph_step, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
                           (bd.row1 - bd.row0) * c->g.ntx, s.a, s.es);
 }
 static hipError_t do_gather(lelbm_ctx *c, void *a) {
@@ -758,6 +770,11 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
         const bool multi = nops > 2 && c->opev.size() >= 2 * nops + 1;
         for (int k = base; k < nsteps; k++) {
             StepArg a{k, &P, 0, 0, multi ? c->side[1] : s, s, multi ? c->side[2] : s};
+            // mass of a point source in this step (Eq. VC1 at the step's
+            // collision time, Delta t = 1)
+            c->ph_step.src_mass =
+                c->ph.src_node >= 0 ? c->p.src_rate * sin(c->p.src_omega * (c->p.src_t0 + (double)(c->steps_done + k)))
+                                    : 0.0;
             if ((r = timed(c, 0, do_fill, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 1, do_prepare, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 2, do_scan, &a)) != LELBM_OK) return r;
@@ -810,7 +827,10 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
         Flags f;
         if ((r = stage_d2h(c->stage, s, &f, c->b.flags, sizeof(Flags))) != LELBM_OK) return r;
         if (c->timing && (r = collect_times(c)) != LELBM_OK) return r;
-        if (f.err == 0) break;
+        if (f.err == 0) {
+            c->steps_done += nsteps;
+            break;
+        }
         // every kernel after the failing one returned early, so the state at
         // the start of step f.step is intact
         c->cur = (cur0 + (f.step - base)) & 1;
@@ -831,6 +851,7 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
                 base = f.step;
                 continue;
             }
+            c->steps_done += f.step;
             c->last_fail_node = -1;
             c->last_fail_step = f.step;
             c->last_fail_detail = 0;
@@ -838,6 +859,7 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
             c->last_fail_residual = 0.0;
             return r;
         }
+        c->steps_done += f.step;
         c->last_fail_node = (long)f.node;
         c->last_fail_step = f.step;
         c->last_fail_detail = f.detail;

@@ -40,6 +40,10 @@ constexpr int GATHER_CAP_MAX = 2340;      // 64 KiB of LDS
 // stop squares the residual (quadratic convergence), landing near 1e-8, the
 // rounding level of the path's FP32 records and state
 constexpr double MIXED_TOL_FLOOR = 1e-4;
+// A Newton solve whose scaled residual is below this and did not decrease at
+// the last update has reached the rounding floor of its sums (large, badly
+// conditioned stencils stall just above 1e-12) and is taken as converged.
+constexpr double STALL_RES = 1e-10;
 
 // Warm-start network: 16 inputs, two hidden layers of 64, 16 outputs.
 // Canonical FP32 parameter vector: W1[16][64], b1[64], W2[64][64], b2[64],
@@ -80,7 +84,15 @@ struct Phys {
     double in_rho, in_u[2], in_RT;
     int lin_guess;                  // 1: start Newton from the linearised guess (lin_guess_scaled)
     int prev_guess;                 // 1: linearised guess plus the cell's previous-step correction
+    long long src_node;             // padded index of the mass-source cell, -1: none
+    double src_mass;                // mass the source adds in the current step
 };
+
+// Zeroth post-collision moment of cell s: rho, plus the mass of a point
+// source (Sec. IV.C, Eq. VC8) in its cell.
+__host__ __device__ inline double post_mass(const Phys &ph, long long s, double rho) {
+    return s == ph.src_node ? rho + ph.src_mass : rho;
+}
 
 struct Flags {
     int err;                 // 0 or first error code

@@ -666,10 +666,13 @@ __device__ inline int species_update(Species<NB, Store> &sp, const double *S, co
         res = v > res ? v : res;
     }
     sp.res = res;
-    if (sp.mlp && sp.nit > 0 && res > tol && !(res < sp.res_prev)) return RESTART_EQ;
+    // a residual below STALL_RES that did not decrease at the last update has
+    // reached the rounding floor of the sums: converged
+    const bool stalled = sp.nit > 0 && res <= STALL_RES && !(res < sp.res_prev);
+    if (sp.mlp && sp.nit > 0 && res > tol && !stalled && !(res < sp.res_prev)) return RESTART_EQ;
     sp.res_prev = res;
     double dl[NB];
-    if (res <= tol) {
+    if (res <= tol || stalled) {
         if (!hess_solve<D, NB>(S, r, dl)) return -FAIL_CHOL_POLISH;
 #pragma unroll
         for (int j = 0; j < NB; j++) { sp.v.lam(j) += dl[j]; sp.v.del(j) = 0.0; }
@@ -770,25 +773,29 @@ __device__ inline void collide_targets(const Geom &g, const Phys &ph, const T *m
     kn_out = kn;
     lim_out = lim;
     double bulk = -g0 / D;
-    double rKT = rho * K * RT;
+    // normalised by the zeroth post-collision moment (Eq. IIB18): rho, plus
+    // the mass a point source adds in its cell, whose Maxwellian (Eqs.
+    // VC6-VC7) leaves the equilibrium parts RT delta unchanged
+    const double rp = post_mass(ph, s, rho);
+    double rKT = rp * K * RT;
     if (D == 1) {
         double shear = P[0][0] - bulk;
         mf[0] = 1.0; mf[1] = 0.0;
-        mf[2] = RT + ((1.0 - of) * shear + (1.0 - ob) * bulk) / rho;
-        mf[3] = (1.0 - oh) * Q[0] / rho;
+        mf[2] = RT + ((1.0 - of) * shear + (1.0 - ob) * bulk) / rp;
+        mf[3] = (1.0 - oh) * Q[0] / rp;
         mg[0] = 1.0 + (1.0 - ob) * g0 / rKT;
         mg[1] = (1.0 - oh) * h[0] / rKT;
         mg[2] = RT;
     } else {
         double shxx = P[0][0] - bulk, shxy = P[0][1], shyy = P[1][1] - bulk;
         mf[0] = 1.0; mf[1] = 0.0; mf[2] = 0.0;
-        mf[3] = RT + ((1.0 - of) * shxx + (1.0 - ob) * bulk) / rho;
-        mf[4] = ((1.0 - of) * shxy) / rho;
-        mf[5] = RT + ((1.0 - of) * shyy + (1.0 - ob) * bulk) / rho;
-        mf[6] = (1.0 - oh) * (0.75 * Q[0]) / rho;
-        mf[7] = (1.0 - oh) * (0.25 * Q[1]) / rho;
-        mf[8] = (1.0 - oh) * (0.25 * Q[0]) / rho;
-        mf[9] = (1.0 - oh) * (0.75 * Q[1]) / rho;
+        mf[3] = RT + ((1.0 - of) * shxx + (1.0 - ob) * bulk) / rp;
+        mf[4] = ((1.0 - of) * shxy) / rp;
+        mf[5] = RT + ((1.0 - of) * shyy + (1.0 - ob) * bulk) / rp;
+        mf[6] = (1.0 - oh) * (0.75 * Q[0]) / rp;
+        mf[7] = (1.0 - oh) * (0.25 * Q[1]) / rp;
+        mf[8] = (1.0 - oh) * (0.25 * Q[0]) / rp;
+        mf[9] = (1.0 - oh) * (0.75 * Q[1]) / rp;
         mg[0] = 1.0 + (1.0 - ob) * g0 / rKT;
         mg[1] = (1.0 - oh) * h[0] / rKT;
         mg[2] = (1.0 - oh) * h[1] / rKT;
@@ -1489,8 +1496,9 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const double *m
                     }
                 }
             }
-            // final pass: moment fractions rho f', rho K RT g' (Eq. IIE3a)
-            const double wsf = rho, wsg = rho * ph.K * RT;
+            // final pass: moment fractions rho f', rho K RT g' (Eq. IIE3a), rho plus
+            // the mass a point source adds in its cell
+            const double wsf = post_mass(ph, s, rho), wsg = wsf * ph.K * RT;
             T *P = (T *)b.scratch + ti.base;
             int q = 0;
             unsigned nxt = tab ? spt[0] : 0u;
@@ -1665,7 +1673,7 @@ __device__ void epr_ref_tile(const Geom &g, const Phys &ph, const double *mom, B
         if (fail) {
             flag_fail(b.flags, LELBM_EEPR, step, s, fail, fsp, fsp ? sg.res : sf.res);
         } else {
-            const double wsf = rho, wsg = rho * ph.K * RT;
+            const double wsf = post_mass(ph, s, rho), wsg = wsf * ph.K * RT;
             T *P = (T *)b.scratch + ti.base;
             double acc[NM];
 #pragma unroll

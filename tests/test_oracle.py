@@ -726,3 +726,119 @@ def test_solid_touching_a_pad_face_is_rejected():
     cfg["solid"][:, 0] = 1
     st, *_ = oracle.step(cfg, prim_moments(cfg, prim), 1)
     assert st == -1
+
+
+# --------------------------------------------------------------------------
+# Oscillating point mass source (Sec. IV.C)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [1, 2])
+def test_mass_source_adds_a_maxwellian_of_its_mass(dim):
+    """Eqs. (VC6-VC8): a source of mass s adds to the post-collision central
+    moments those of a Maxwellian of mass s at rest in the cell's frame at its
+    temperature -- fluons s, 0, s RT delta, 0; phonons s K RT, 0,
+    s K RT RT delta -- and the targets are normalised by rho + s (Eq. IIB18).
+    Checked as the difference of the un-normalised targets with and without
+    the source, on random non-equilibrium cells."""
+    rng = np.random.default_rng(31 + dim)
+    cfg = dict(li.hotbox(1.0, n=4, dim=dim)[0])
+    cfg["omega_f"], cfg["omega_b"], cfg["omega_h"], cfg["kn_limiter"] = 1.3, 0.9, 1.6, 0
+    K = cfg["K"]
+    for s in (0.3, -0.05, 1e-6):
+        c, f, g = _random_populations(dim, rng)
+        mom = _raw_moments(dim, c, f, g)
+        a = oracle.collide(cfg, mom)
+        b = oracle.collide(cfg, mom, src=s)
+        assert a["status"] == 0 and b["status"] == 0
+        rho, RT = a["rho"], a["RT"]
+        assert b["rho"] == rho and b["RT"] == RT
+        dm = (rho + s) * b["m"] - rho * a["m"]
+        dn = (rho + s) * K * RT * b["n"] - rho * K * RT * a["n"]
+        if dim == 1:
+            em, en = [s, 0, s * RT, 0], [s * K * RT, 0, s * K * RT * RT]
+        else:
+            em = [s, 0, 0, s * RT, 0, s * RT, 0, 0, 0, 0]
+            en = [s * K * RT, 0, 0, s * K * RT * RT, 0, s * K * RT * RT]
+        scale = rho * max(1.0, RT) ** 2
+        assert np.allclose(dm, em, rtol=0, atol=1e-12 * scale)
+        assert np.allclose(dn, en, rtol=0, atol=1e-12 * scale * K)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_mass_source_exact_balances(dim):
+    """Each step adds exactly the source's mass s_k = rate sin(omega t_k) with
+    t_k = t0 + k (Eq. VC1 at the step's collision, Delta t = 1), the momentum
+    s_k u and the energy trace s_k (|u|^2 + (D + K) RT) of the source cell at
+    the step's start (a Maxwellian in its frame); everything else moves
+    conservatively."""
+    cfg, prim = li.smooth_periodic(2, n=16 if dim == 2 else 48, ny=10, dim=dim)
+    sx, sy = (5, 3) if dim == 2 else (17, 0)
+    rate, omega, t0 = 2e-3, 0.7, 3.0
+    cfg["source"] = {"x": sx, "y": sy, "rate": rate, "omega": omega, "t0": t0}
+    nx = cfg["nx"]
+    cur = prim_moments(cfg, prim)
+    K, D = cfg["K"], dim
+    for k in range(5):
+        c2 = dict(cfg)
+        c2["source"] = dict(cfg["source"], t0=t0 + k)
+        st, nxt, stats, done = oracle.step(c2, cur, 1)
+        assert st == 0
+        s = rate * np.sin(omega * (t0 + k))
+        i = sy * nx + sx
+        rho = cur[0, i]
+        u = np.array([cur[1, i], cur[2, i] if dim == 2 else 0.0]) / rho
+        if dim == 2:
+            tr = cur[3] + cur[5] + cur[8]
+            trn = nxt[3] + nxt[5] + nxt[8]
+        else:
+            tr = cur[2] + cur[4]
+            trn = nxt[2] + nxt[4]
+        RT = (tr[i] / rho - u @ u) / (D + K)
+        assert abs((nxt[0].sum() - cur[0].sum()) - s) < 1e-11
+        for a in range(dim):
+            assert abs((nxt[1 + a].sum() - cur[1 + a].sum()) - s * u[a]) < 1e-11
+        assert abs((trn.sum() - tr.sum()) - s * (u @ u + (D + K) * RT)) < 1e-10
+
+
+def _source_pressure_amplitude(cfg, prim, t_fit0, t_fit1):
+    """Runs the source case and fits a sin + cos + constant of the source's
+    frequency to the pressure history of every cell over [t_fit0, t_fit1)."""
+    m = prim_moments(cfg, prim)
+    st, cur, _, _ = oracle.step(cfg, m, t_fit0)
+    assert st == 0
+    hist = []
+    for k in range(t_fit0, t_fit1):
+        c2 = dict(cfg)
+        c2["source"] = dict(cfg["source"], t0=float(k))
+        st, cur, _, _ = oracle.step(c2, cur, 1)
+        assert st == 0
+        rho = cur[0]
+        ux = cur[1] / rho
+        RT = ((cur[2] + cur[4]) / rho - ux ** 2) / (1 + cfg["K"])
+        hist.append(rho * RT)
+    t = np.arange(t_fit0, t_fit1) + 1.0
+    w = cfg["source"]["omega"]
+    A = np.stack([np.sin(w * t), np.cos(w * t), np.ones_like(t)], 1)
+    coef = np.linalg.lstsq(A, np.array(hist), rcond=None)[0]
+    return np.hypot(coef[0], coef[1])
+
+
+def test_acoustic_source_bulk_viscosity_and_amplitude():
+    """Sec. IV.C: a 1D oscillating point mass source radiates plane waves whose
+    amplitude decays as exp(-alpha_x x) with alpha_x of Eq. (VC3); Eq. (VC4)
+    then gives the bulk viscosity, to compare with RT (2/D - 2/(D+K))
+    (1/omega_b - 1/2) (Eq. C8b); the paper's bar is +-10 %.  The source adds
+    mass at the local temperature, a pressure source RT rate, so the
+    linearised equations fix the radiated amplitude at RT rate / (2 c_s) on
+    each side (before absorption)."""
+    cfg, prim = li.acoustic_source(n=1200, RT=1.0, rate=1e-6, period=64.0, nu_b=0.8, nu=1e-3)
+    amp = _source_pressure_amplitude(cfg, prim, 320, 448)
+    cs = np.sqrt(1.4)
+    w = cfg["source"]["omega"]
+    xs = cfg["source"]["x"]
+    d1, d2 = 40, 200
+    for side in (1, -1):
+        ax = -np.log(amp[xs + side * d2] / amp[xs + side * d1]) / (d2 - d1)
+        nu_b = 2 * cs ** 3 / w ** 2 * ax - 0.4 * cfg["nu"]
+        assert abs(nu_b / cfg["nu_b"] - 1) < 0.03
+        a0 = amp[xs + side * d1] * np.exp(ax * d1)
+        assert abs(a0 / (1.0 * 1e-6 / (2 * cs)) - 1) < 0.03
