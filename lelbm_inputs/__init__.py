@@ -22,6 +22,9 @@ Workloads (lattice units, dx = dt = 1):
     Sec. V.E; no external reference data is used).
   * ``shear_wave`` / ``acoustic_pulse`` / ``acoustic_source`` -- the paper's
     verification problems (Sec. IV.A, IV.D, IV.C).
+  * ``oblique_shock`` -- uniform supersonic flow turned by a slip wall
+    (Sec. V.F): the flow enters through the left and top faces inclined by
+    theta toward the bottom slip wall, which deflects it along the wall.
 
 Physical states are mapped to lattice units by acoustic scaling (Sec. V.B):
 RT_lat = s^2 RT_phys and u_lat = s u_phys with s^2 = RT_floor / min RT_phys.
@@ -230,6 +233,25 @@ def acoustic_source(n=1200, RT=1.0, rate=1e-6, period=64.0, nu_b=0.8, nu=1e-3, K
                 "nu": nu, "nu_b": nu_b})
     shape = (1, n)
     prim = {"rho": np.ones(shape), "ux": np.zeros(shape), "uy": np.zeros(shape), "RT": np.full(shape, RT)}
+    return cfg, prim
+
+
+def oblique_shock(mach=2.0, theta_deg=5.0, nx=512, ny=320, RT=0.5, pad=8):
+    """Sec. V.F: inflow at Mach `mach` (rho 1, RT) inclined by theta toward
+    the bottom slip wall through the left and top faces, outflow on the right.
+    The wall turns the flow by theta, which makes an oblique shock from the
+    bottom-left corner; the whole domain starts in the inflow state.
+    Inviscid shock settings (reading 11) with the Knudsen limiter."""
+    cfg = _base_cfg(2, nx, ny, K_2D)
+    th = np.deg2rad(theta_deg)
+    u = mach * np.sqrt(GAMMA * RT)
+    uin = (u * np.cos(th), -u * np.sin(th))
+    cfg["bc"] = ["inflow", "outflow", "slipwall", "inflow"]
+    cfg["pad"] = pad
+    cfg.update({"in_rho": 1.0, "in_u": uin, "in_RT": RT, "mach": mach, "theta_deg": theta_deg})
+    shape = (ny, nx)
+    prim = {"rho": np.ones(shape), "ux": np.full(shape, uin[0]), "uy": np.full(shape, uin[1]),
+            "RT": np.full(shape, RT)}
     return cfg, prim
 
 

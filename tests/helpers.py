@@ -46,3 +46,40 @@ def primitives(mom, dim, K):
     ux, uy = mom[1] / rho, mom[2] / rho
     RT = ((mom[3] + mom[5] + mom[8]) / rho - ux * ux - uy * uy) / (2 + K)
     return rho, ux, uy, RT
+
+
+def oblique_shock_measure(mom, cfg, x0f=0.5, x1f=0.9):
+    """Shock angle and post-shock state of an oblique-shock run (Sec. V.F).
+    Per column in [x0f, x1f) of the width, the shock is where the density,
+    scanned down from the top, first reaches the mid value between the
+    inflow and the exact post-shock density; a line fitted through these
+    points gives the shock's angle to the wall, plus theta the angle to the
+    inflow.  Density, temperature and Mach number are averaged between the
+    wall and the shock (3 cells above the wall to 8 below the shock).
+    Returns (beta_deg, rho2/rho1, T2/T1, M2) measured and the exact values."""
+    from oracle import oblique
+    nx, ny, K = cfg["nx"], cfg["ny"], cfg["K"]
+    rho = mom[0].reshape(ny, nx)
+    ux = mom[1].reshape(ny, nx) / rho
+    uy = mom[2].reshape(ny, nx) / rho
+    RT = ((mom[3] + mom[5] + mom[8]).reshape(ny, nx) / rho - ux ** 2 - uy ** 2) / (2 + K)
+    M, th = cfg["mach"], np.deg2rad(cfg["theta_deg"])
+    beta = oblique.weak_beta(M, th)
+    m2, r2, t2, _ = oblique.jumps(M, beta, th)
+    half = 0.5 * (cfg["in_rho"] + r2 * cfg["in_rho"])
+    xs, ys = [], []
+    for x in range(int(x0f * nx), int(x1f * nx)):
+        col = rho[:, x]
+        for y in range(ny - 2, 0, -1):
+            if col[y] < half <= col[y - 1]:
+                ys.append(y - 1 + (col[y - 1] - half) / (col[y - 1] - col[y]) + 0.5)
+                xs.append(x + 0.5)
+                break
+    b, a = np.polyfit(np.array(xs), np.array(ys), 1)
+    beta_m = np.arctan(b) + th
+    cells = [(y, x) for x in range(int(x0f * nx), int(x1f * nx)) for y in range(3, int(a + b * (x + 0.5) - 8))]
+    yy, xx = np.array(cells).T
+    r = rho[yy, xx].mean() / cfg["in_rho"]
+    T = RT[yy, xx].mean()
+    m2m = np.hypot(ux[yy, xx], uy[yy, xx]).mean() / np.sqrt(cfg["gamma"] * T)
+    return (np.rad2deg(beta_m), r, T / cfg["in_RT"], m2m), (np.rad2deg(beta), r2, t2, m2)

@@ -842,3 +842,34 @@ def test_acoustic_source_bulk_viscosity_and_amplitude():
         assert abs(nu_b / cfg["nu_b"] - 1) < 0.03
         a0 = amp[xs + side * d1] * np.exp(ax * d1)
         assert abs(a0 / (1.0 * 1e-6 / (2 * cs)) - 1) < 0.03
+
+
+# --------------------------------------------------------------------------
+# Oblique shock (Sec. V.F)
+# --------------------------------------------------------------------------
+def test_oblique_shock_relations_match_the_printed_table():
+    """The textbook theta-beta-Mach relation and normal-shock jumps
+    (oracle/oblique.py) reproduce the analytical rows of Table II to the
+    printed precision (golden file)."""
+    from oracle import oblique
+    rows = np.loadtxt(os.path.join(GOLDEN, "oblique_shock_table2.txt"))
+    for M, th, beta, m2, r, t in rows:
+        b = oblique.weak_beta(M, np.deg2rad(th))
+        m2c, rc, tc, _ = oblique.jumps(M, b, np.deg2rad(th))
+        assert abs(np.rad2deg(b) - beta) < 6e-4
+        assert abs(m2c - m2) < 6e-4 and abs(rc - r) < 6e-4 and abs(tc - t) < 6e-4
+
+
+def test_oblique_shock_angle_and_jumps():
+    """Sec. V.F: Mach-2 inflow turned by 5 degrees by a slip wall (RT 0.5,
+    gamma 1.4): the shock angle within 0.1 degree of theta-beta-Mach and the
+    post-shock density, temperature and Mach number within 0.3 % of the
+    oblique-shock jumps."""
+    from helpers import oblique_shock_measure
+    cfg, prim = li.oblique_shock(mach=2.0, theta_deg=5.0, nx=160, ny=100)
+    st, out, stats, done = oracle.step(cfg, prim_moments(cfg, prim), 200)
+    assert st == 0
+    meas, exact = oblique_shock_measure(out, cfg)
+    assert abs(meas[0] - exact[0]) < 0.1
+    for k in (1, 2, 3):
+        assert abs(meas[k] / exact[k] - 1) < 3e-3
