@@ -127,6 +127,9 @@ def parse():
     ap.add_argument("--c4-horizon", type=int, default=0,
                     help="only run the 8192x4096 Mach-10 channel for this many steps on both paths "
                          "(FP64 and FP32 + learned guess) and report the L1 error per field")
+    ap.add_argument("--c4-horizon-runs", default="fp64-eq,mixed-mlp",
+                    help="the reference and the compared path of --c4-horizon (fp64-eq, fp64-lin, mixed-mlp, "
+                         "mixed-eq)")
     ap.add_argument("--c4-horizon-seconds", type=float, default=900.0,
                     help="wall-time limit of the --c4-horizon run (it stops at the last whole chunk)")
     ap.add_argument("--channel-only", action="store_true",
@@ -576,8 +579,10 @@ def main():
     if a.c4_horizon:
         mlp, _ = harvest_and_train(a, lb, li, torch)
         cfg, prim = li.channel(0, nx=8192, ny=4096, n_obstacles=8, mach=10.0, pad=48)
-        out = lockstep_horizon(lb, torch, cfg, prim, a.c4_horizon,
-                               (("fp64-eq", lb.FP64, lb.GUESS_EQ), ("mixed-mlp", lb.MIXED, lb.GUESS_MLP)), mlp,
+        kinds = {"fp64-eq": (lb.FP64, lb.GUESS_EQ), "fp64-lin": (lb.FP64, lb.GUESS_LIN),
+                 "mixed-mlp": (lb.MIXED, lb.GUESS_MLP), "mixed-eq": (lb.MIXED, lb.GUESS_EQ)}
+        pair = tuple((n,) + kinds[n] for n in a.c4_horizon_runs.split(","))
+        out = lockstep_horizon(lb, torch, cfg, prim, a.c4_horizon, pair, mlp,
                                "C4", cfg["solid"].ravel() == 0, a.scratch_budget, a.c4_horizon_seconds)
         out["workload"] = ("channel 8192x4096, Mach 10 inflow, 8 obstacles (seed 0), started from rest, "
                            "%d steps" % a.c4_horizon)

@@ -129,3 +129,27 @@ def test_channel_mixed_precision_errors():
     l1 = np.abs(rho_a - rho_b).sum() / np.abs(rho_b).sum()
     print("L1 rho", l1)
     assert l1 < 1e-4
+
+
+def test_reach_beyond_the_walk_cache_parity():
+    """Hot fast gas around a solid block: RT 40 (R = 25) at u = (8, 3) gives a
+    reach of 34 cells, beyond the largest reach whose backward walks are
+    cached (31), so the tiles near the block walk every displacement at every
+    step, and the blocker map of a wavefront's region is too large for its
+    LDS share, so the walks read the mask from global memory."""
+    _case("reach 34 around a solid block, 96x96 periodic, 6 steps")
+    cfg, prim = li.hotbox(40.0, n=96, u=(8.0, 3.0))
+    solid = np.zeros((96, 96), dtype=np.uint8)
+    solid[40:52, 44:52] = 1
+    cfg["solid"] = solid
+    y = (np.arange(96) + 0.5)[:, None]
+    x = (np.arange(96) + 0.5)[None, :]
+    prim["rho"] = 1.0 + 0.02 * np.sin(2 * np.pi * x / 96) * np.cos(2 * np.pi * y / 96)
+    m = oracle_moments(cfg, prim)
+    a, st = run_gpu(cfg, prim, 6, mom=m)
+    b, _ = run_oracle(cfg, prim, 6, mom=m)
+    print("colat_max %.2f" % st["colat_max"])
+    assert st["colat_max"] + 1 > 31
+    err = _fluid_rel_linf(a, b, solid)
+    print("rel_linf", err)
+    assert err < 1e-10
