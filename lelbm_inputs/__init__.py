@@ -22,6 +22,8 @@ Workloads (lattice units, dx = dt = 1):
     Sec. V.E; no external reference data is used).
   * ``shear_wave`` / ``acoustic_pulse`` / ``acoustic_source`` -- the paper's
     verification problems (Sec. IV.A, IV.D, IV.C).
+  * ``couette`` -- gas between no-slip walls on the y faces, the top wall
+    moving along x (Sec. III.B).
   * ``oblique_shock`` -- uniform supersonic flow turned by a slip wall
     (Sec. V.F): the flow enters through the left and top faces inclined by
     theta toward the bottom slip wall, which deflects it along the wall.
@@ -233,6 +235,20 @@ def acoustic_source(n=1200, RT=1.0, rate=1e-6, period=64.0, nu_b=0.8, nu=1e-3, K
                 "nu": nu, "nu_b": nu_b})
     shape = (1, n)
     prim = {"rho": np.ones(shape), "ux": np.zeros(shape), "uy": np.zeros(shape), "RT": np.full(shape, RT)}
+    return cfg, prim
+
+
+def couette(ny=16, nx=4, RT=1.0, U=0.1, nu=0.2, K=K_2D, u0=(0.0, 0.0)):
+    """Gas at rest (or at velocity u0) between no-slip walls on the y faces,
+    periodic in x; the top wall moves at U along x.  Shear and heat-flux
+    frequencies from nu = RT (1/omega - 1/2)."""
+    cfg = _base_cfg(2, nx, ny, K)
+    om = 1.0 / (nu / RT + 0.5)
+    cfg.update({"omega_f": om, "omega_b": 1.0, "omega_h": om, "kn_limiter": 0,
+                "bc": ["periodic", "periodic", "wall", "wall"], "wall_u": (0.0, 0.0, 0.0, U), "nu": nu})
+    shape = (ny, nx)
+    prim = {"rho": np.ones(shape), "ux": np.full(shape, float(u0[0])), "uy": np.full(shape, float(u0[1])),
+            "RT": np.full(shape, RT)}
     return cfg, prim
 
 

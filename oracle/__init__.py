@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lelbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblelbm_oracle.so")
 
-BC_PERIODIC, BC_OUTFLOW, BC_INFLOW, BC_SLIPWALL = 0, 1, 2, 3
+BC_PERIODIC, BC_OUTFLOW, BC_INFLOW, BC_SLIPWALL, BC_WALL = 0, 1, 2, 3, 4
 OK, EINVAL, ENOMEM, EEPR, ENONFINITE, EREACH = 0, -1, -2, -4, -5, -6
 
 
@@ -50,6 +50,7 @@ class Params(ctypes.Structure):
         ("solid", ctypes.c_void_p),
         ("src_x", ctypes.c_int), ("src_y", ctypes.c_int),
         ("src_rate", ctypes.c_double), ("src_omega", ctypes.c_double), ("src_t", ctypes.c_double),
+        ("wall_u", ctypes.c_double * 4),
     ]
 
 
@@ -128,7 +129,8 @@ def make_params(cfg):
     p.newton_max_it = cfg.get("newton_max_it", 50)
     p.kn_limiter = cfg.get("kn_limiter", 1)
     p.kn_lo, p.kn_hi, p.omega_H = cfg.get("kn_lo", -2.0), cfg.get("kn_hi", -1.0), cfg.get("omega_H", 1.0)
-    names = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW, "inflow": BC_INFLOW, "slipwall": BC_SLIPWALL}
+    names = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW, "inflow": BC_INFLOW, "slipwall": BC_SLIPWALL,
+             "wall": BC_WALL}
     for i, b in enumerate(cfg.get("bc", ["periodic"] * 4)):
         p.bc[i] = names[b] if isinstance(b, str) else int(b)
     p.pad = cfg.get("pad", 0)
@@ -147,6 +149,8 @@ def make_params(cfg):
     if src is not None:
         p.src_x, p.src_y = src["x"], src.get("y", 0)
         p.src_rate, p.src_omega, p.src_t = src["rate"], src["omega"], src.get("t0", 0.0)
+    for i, v in enumerate(cfg.get("wall_u", (0.0, 0.0, 0.0, 0.0))):
+        p.wall_u[i] = v
     return p
 
 

@@ -28,6 +28,8 @@
  *                                        the population path at every face
  *                                        it would cross into a blocker)
  *   - oscillating point mass source .... Sec. IV.C, Eqs. (VC1, VC6-VC8)
+ *   - no-slip / moving walls ........... Sec. III.B, Eqs. (IIIB8-IIIB15),
+ *                                        extended bounce-back on the y faces
  *
  * Readings taken where the paper is ambiguous are listed in the header
  * comment of each function.
@@ -49,7 +51,7 @@
 #define ORC_STALL_RES 1e-10
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EEPR = -4, ORC_ENONFINITE = -5, ORC_EREACH = -6 };
-enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_INFLOW = 2, ORC_BC_SLIPWALL = 3 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_INFLOW = 2, ORC_BC_SLIPWALL = 3, ORC_BC_WALL = 4 };
 
 /* Parameters of one run.  Mirrored field by field by the Python wrapper. */
 typedef struct {
@@ -71,6 +73,9 @@ typedef struct {
      * the first step's collision (steps of orc_run follow at src_t + k). */
     int src_x, src_y;
     double src_rate, src_omega, src_t;
+    /* no-slip walls (ORC_BC_WALL, y faces of a 2D domain): velocity of the
+     * wall along x, per face (entries 2 and 3 used) */
+    double wall_u[4];
 } orc_params;
 
 typedef struct {
@@ -606,6 +611,16 @@ typedef struct {
     double rho, RT, u[2], kn;
     double *c, *wf, *wg;
     int *d;
+    /* no-slip walls: per real point, the wall face it crosses (2 low, 3
+     * high) or -1; per face the image populations that leave it (count,
+     * velocities before the reflection, landing displacements, scaled
+     * weights), or fallback[face] = 1: the absorbed points are reflected
+     * specularly instead (no image population crosses the face) */
+    signed char *wall;
+    int qi[2];
+    double *ci[2], *wfi[2], *wgi[2];
+    int *di[2];
+    int fallback[2];
 } cell_out;
 
 static int pad_w(const orc_params *p, int face)
@@ -636,7 +651,88 @@ static void source_moments(const orc_params *p, const double *in, int sx, int sy
     for (int k = 0; k < nm; k++) m[k] = in[(long)k * n + (long)iy * nx + ix];
 }
 
-static void process_cell(const orc_params *p, const double *mom, double src, cell_out *co)
+static int has_walls(const orc_params *p)
+{
+    return p->dim == 2 && (p->bc[2] == ORC_BC_WALL || p->bc[3] == ORC_BC_WALL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Extended bounce-back at the no-slip walls of the y faces, Sec. III.B.      */
+/*                                                                            */
+/* A real population whose straight path crosses a wall face n is absorbed:   */
+/* its moment fractions add to the imbalances Delta m_n (fluons) and          */
+/* Delta g_n (phonons) of its source (Eq. IIIB8) instead of streaming.  For   */
+/* each face with Delta m_n > 0 the source reconstructs image populations     */
+/* with the same normalised post-collision targets (non-equilibrium part of   */
+/* the cell, Eqs. IIIB9-10; RT unchanged: adiabatic) on the acoustic stencil  */
+/* of the image velocity u_n = u - 2 u_w (Eq. IIIB11; u_w along x, no slip    */
+/* direction) (Eq. IIIB13), streams them with -c_i, and keeps those whose     */
+/* path crosses face n (the last wall they touch: one reflection, the channel */
+/* being wider than the reach); their sum is Delta m'_n (Eq. IIIB14).  They   */
+/* land at the mirror image of x - d_i across the face with velocity          */
+/* (-c_x, c_y), scaled by Delta m_n / Delta m'_n (Eq. IIIB15).                */
+/* Readings: phonons are scaled by their own ratio Delta g_n / Delta g'_n, so */
+/* the wall returns the internal energy of the extra degrees of freedom it    */
+/* absorbed as it returns the mass; when no image population crosses the     */
+/* face (flow toward the wall faster than the image stencil reaches back),    */
+/* the absorbed populations are reflected specularly instead.  A stencil that */
+/* crosses both faces, a refined stencil that crosses one, and a population  */
+/* that would land only after a second reflection are reported (ORC_EREACH). */
+/* ------------------------------------------------------------------------ */
+static int wall_images(const orc_params *p, int sx, int sy, const orc_cell *cl, cell_out *co,
+                       const double *dm, const double *dg)
+{
+    for (int f = 0; f < 2; f++) {
+        co->qi[f] = 0; co->ci[f] = NULL; co->wfi[f] = NULL; co->wgi[f] = NULL; co->di[f] = NULL; co->fallback[f] = 0;
+    }
+    for (int f = 0; f < 2; f++) {
+        if (!(dm[f] > 0.0)) continue;
+        double un[2] = {cl->u[0] - 2.0 * p->wall_u[2 + f], cl->u[1]};
+        int cap = 64, q;
+        double *c = NULL, *dC = NULL;
+        int *d = NULL;
+        for (;;) {
+            c = malloc(sizeof(double) * 2 * cap); dC = malloc(sizeof(double) * cap); d = malloc(sizeof(int) * 2 * cap);
+            q = orc_las(2, un, cl->RT, p->n_conf, p->r_min, cap, c, dC, d, NULL);
+            if (q >= 0) break;
+            free(c); free(dC); free(d);
+            cap = -q;
+        }
+        double *pf = malloc(sizeof(double) * q), *pg = malloc(sizeof(double) * q);
+        double lf[10], lg[10];
+        int itf = 0, itg = 0;
+        int s1 = orc_epr(2, cl->nf, q, c, dC, un, cl->RT, cl->m, 0, lf, p->newton_tol, p->newton_max_it, pf, &itf);
+        int s2 = orc_epr(2, cl->ng, q, c, dC, un, cl->RT, cl->n, 0, lg, p->newton_tol, p->newton_max_it, pg, &itg);
+        free(dC);
+        if (s1 != ORC_OK || s2 != ORC_OK) { free(c); free(d); free(pf); free(pg); return ORC_EEPR; }
+        double sg = cl->rho_post * p->K * cl->RT;
+        double dmi = 0.0, dgi = 0.0;
+        int keep = 0;
+        for (int i = 0; i < q; i++) {
+            pf[i] *= cl->rho_post; pg[i] *= sg;
+            int yu = sy - d[2 * i + 1];                       /* unfolded end of the -c_i path */
+            int cross = f == 0 ? yu < 0 : yu > p->ny - 1;
+            if (!cross) continue;
+            int ly = f == 0 ? -1 - yu : 2 * p->ny - 1 - yu;    /* mirror image across the face */
+            if (ly < 0 || ly > p->ny - 1) { free(c); free(d); free(pf); free(pg); return ORC_EREACH; }
+            dmi += pf[i]; dgi += pg[i];
+            c[2 * keep] = c[2 * i]; c[2 * keep + 1] = c[2 * i + 1];
+            d[2 * keep] = d[2 * i]; d[2 * keep + 1] = d[2 * i + 1];
+            pf[keep] = pf[i]; pg[keep] = pg[i];
+            keep++;
+        }
+        if (!(dmi > 0.0) || !(dgi > 0.0)) {
+            co->fallback[f] = 1;
+            free(c); free(d); free(pf); free(pg);
+            continue;
+        }
+        for (int i = 0; i < keep; i++) { pf[i] *= dm[f] / dmi; pg[i] *= dg[f] / dgi; }
+        co->qi[f] = keep; co->ci[f] = c; co->di[f] = d; co->wfi[f] = pf; co->wgi[f] = pg;
+    }
+    return ORC_OK;
+}
+
+static void process_cell(const orc_params *p, const double *mom, double src, int sx, int sy, cell_out *co)
 {
     orc_cell cl;
     memset(co, 0, sizeof(*co));
@@ -673,6 +769,33 @@ static void process_cell(const orc_params *p, const double *mom, double src, cel
     co->q = q; co->c = c; co->d = d; co->wf = pf; co->wg = pg;
     co->it_f = itf; co->it_g = itg;
     co->status = ORC_OK;
+    if (has_walls(p)) {
+        co->wall = malloc((size_t)(q > 0 ? q : 1));
+        double dm[2] = {0.0, 0.0}, dg[2] = {0.0, 0.0};
+        for (int i = 0; i < q; i++) {
+            int yu = sy + d[2 * i + 1];
+            int f = -1;
+            if (p->bc[2] == ORC_BC_WALL && yu < 0) f = 0;
+            else if (p->bc[3] == ORC_BC_WALL && yu > p->ny - 1) f = 1;
+            co->wall[i] = (signed char)f;
+            if (f >= 0) { dm[f] += pf[i]; dg[f] += pg[i]; }
+        }
+        if ((dm[0] > 0.0 && dm[1] > 0.0) || ((dm[0] > 0.0 || dm[1] > 0.0) && orc_las_levels(cl.RT) > 0)) {
+            co->status = ORC_EREACH;
+            return;
+        }
+        int st2 = wall_images(p, sx, sy, &cl, co, dm, dg);
+        if (st2 != ORC_OK) { co->status = st2; return; }
+        /* a face that reflects its absorbed points specularly: each lands   */
+        /* after a single reflection, or the stencil reaches too far         */
+        for (int i = 0; i < q; i++) {
+            int f = co->wall[i];
+            if (f < 0 || !co->fallback[f]) continue;
+            int yu = sy + d[2 * i + 1];
+            int ly = f == 0 ? -1 - yu : 2 * p->ny - 1 - yu;
+            if (ly < 0 || ly > p->ny - 1) { co->status = ORC_EREACH; return; }
+        }
+    }
 }
 
 /* Moment fraction deposit, Eq. (IIE3b), with absolute velocity c. */
@@ -802,6 +925,12 @@ int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
         int a = p->bc[2 * ax], b = p->bc[2 * ax + 1];
         if ((a == ORC_BC_PERIODIC) != (b == ORC_BC_PERIODIC)) return ORC_EINVAL;
     }
+    for (int f = 0; f < 4; f++)
+        if (p->bc[f] == ORC_BC_WALL && (D != 2 || f < 2)) return ORC_EINVAL;   /* walls: y faces, 2D */
+    if (has_walls(p) && p->solid) return ORC_EINVAL;
+    if (has_walls(p))
+        for (int f = 0; f < 4; f++)
+            if (p->bc[f] == ORC_BC_SLIPWALL) return ORC_EINVAL;   /* no-slip walls with slip walls: not supported */
     if (p->solid) {
         /* solids are 2D, and may not touch a pad face (its cells copy the
          * nearest interior cell) */
@@ -844,7 +973,7 @@ int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
             /* Eq. (VC1) at the time of this step's collision, Delta t = 1 */
             double src = 0.0;
             if (p->src_rate != 0.0 && sx == p->src_x && sy == p->src_y) src = p->src_rate * sin(p->src_omega * p->src_t);
-            process_cell(p, m, src, &co[k - c0]);
+            process_cell(p, m, src, sx, sy, &co[k - c0]);
         }
         /* serial, source-major deposit */
         for (long k = c0; k < c1; k++) {
@@ -873,7 +1002,19 @@ int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
                 /* the path of the (base) point, Sec. III.B; refined children
                  * follow their parent's path and flips */
                 int lx, ly, fx, fy;
-                walk_path(p, sx, sy, o->d[2 * i], D == 2 ? o->d[2 * i + 1] : 0, &lx, &ly, &fx, &fy);
+                if (o->wall && o->wall[i] >= 0) {
+                    /* crosses a no-slip wall: absorbed, unless the face falls
+                     * back to a specular reflection for this source */
+                    int f = o->wall[i];
+                    if (!o->fallback[f]) continue;
+                    int yu = sy + o->d[2 * i + 1];
+                    lx = sx + o->d[2 * i];
+                    if (p->bc[0] == ORC_BC_PERIODIC) lx = wrap(lx, nx);
+                    ly = f == 0 ? -1 - yu : 2 * ny - 1 - yu;
+                    fx = 1; fy = -1;
+                } else {
+                    walk_path(p, sx, sy, o->d[2 * i], D == 2 ? o->d[2 * i + 1] : 0, &lx, &ly, &fx, &fy);
+                }
                 double cx = fx * o->c[2 * i], cy = fy * o->c[2 * i + 1];
                 /* arrivals in pads are discarded (Sec. III.A) */
                 if (lx < 0 || lx >= nx || ly < 0 || ly >= ny) continue;
@@ -882,9 +1023,26 @@ int orc_step(const orc_params *p, const double *in, double *out, orc_stats *st)
                 long dst = (long)ly * nx + lx;
                 for (int mm = 0; mm < nm; mm++) acc[(long)mm * n + dst] += a[mm];
             }
+            /* image populations of the no-slip walls: streamed with -c_i and
+             * reflected by their face, velocity (-c_x, c_y) */
+            for (int f = 0; f < 2; f++) {
+                for (int i = 0; o->wall && i < o->qi[f]; i++) {
+                    int yu = sy - o->di[f][2 * i + 1];
+                    int lx = sx - o->di[f][2 * i];
+                    if (p->bc[0] == ORC_BC_PERIODIC) lx = wrap(lx, nx);
+                    int ly = f == 0 ? -1 - yu : 2 * ny - 1 - yu;
+                    if (lx < 0 || lx >= nx) continue;
+                    double a[11] = {0};
+                    deposit(D, a, -o->ci[f][2 * i], o->ci[f][2 * i + 1], o->wfi[f][i], o->wgi[f][i]);
+                    long dst = (long)ly * nx + lx;
+                    for (int mm = 0; mm < nm; mm++) acc[(long)mm * n + dst] += a[mm];
+                }
+            }
         }
         for (long k = c0; k < c1; k++) {
-            free(co[k - c0].c); free(co[k - c0].d); free(co[k - c0].wf); free(co[k - c0].wg);
+            cell_out *o = &co[k - c0];
+            free(o->c); free(o->d); free(o->wf); free(o->wg); free(o->wall);
+            for (int f = 0; f < 2; f++) { free(o->ci[f]); free(o->di[f]); free(o->wfi[f]); free(o->wgi[f]); }
         }
     }
     if (status == ORC_OK) memcpy(out, acc, sizeof(double) * nm * n);
