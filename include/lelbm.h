@@ -58,10 +58,27 @@ enum {
                                range: more than 3 refinement levels
                                (RT < 0.0123), acoustic radius above 128
                                (RT > ~1030) or |u| above 2048 cells per
-                               step */
+                               step, or a stencil reaches a no-slip wall
+                               beyond what LELBM_BC_WALL supports */
 };
 
-enum { LELBM_BC_PERIODIC = 0, LELBM_BC_OUTFLOW = 1, LELBM_BC_INFLOW = 2, LELBM_BC_SLIPWALL = 3 };
+/* LELBM_BC_WALL: a no-slip (optionally moving) adiabatic wall on a y face of
+ * a 2D domain, by the extended bounce-back of Sec. III.B (Eqs. IIIB8-15):
+ * populations whose straight path crosses the wall are absorbed; each source
+ * cell that lost mass Delta m to the wall reconstructs image populations with
+ * its own normalised post-collision targets around u_n = u - 2 u_w
+ * (Eq. IIIB11), streams them with -c_i, and those whose path crosses the
+ * wall enter the domain after a specular reflection, scaled by
+ * Delta m / Delta m' (their own sum; phonons by their own ratio).  When no
+ * image population crosses the wall (flow toward it faster than the image
+ * stencil reaches back) the absorbed populations are reflected specularly
+ * instead.  Requires: both walls' faces on y, x faces periodic, outflow or
+ * inflow, no slip walls and no solid cells; a stencil may cross one wall
+ * only, unrefined (RT >= 4/9), from at most LELBM_WALL_ROWS rows away, and
+ * every image or reflected population must land after one reflection;
+ * otherwise lelbm_step fails with LELBM_EREACH. */
+enum { LELBM_BC_PERIODIC = 0, LELBM_BC_OUTFLOW = 1, LELBM_BC_INFLOW = 2, LELBM_BC_SLIPWALL = 3, LELBM_BC_WALL = 4 };
+#define LELBM_WALL_ROWS 64
 
 /* LELBM_FP64: every stage in FP64.
  * LELBM_MIXED: the reconstruction records (population multipliers and moment
@@ -124,6 +141,9 @@ typedef struct {
      * the reconstruction fails with LELBM_EEPR). */
     int src_x, src_y;
     double src_rate, src_omega, src_t0;
+    /* Tangential (x) velocity u_w of the LELBM_BC_WALL wall on each face
+     * (xlo, xhi, ylo, yhi); entries of other faces must be 0. */
+    double wall_u[4];
 } lelbm_params;
 
 /* Statistics accumulated over the steps of one lelbm_step call.  Newton
@@ -224,9 +244,10 @@ int lelbm_last_failure_detail(const lelbm_ctx *c, int *reason, int *species, dou
  * [3] collision + reconstruction of cells with unrefined stencils (narrow and
  * wide stencils; one launch pair per band of the scratch plan), [4]
  * moment-streaming gather (one launch per run of destination rows), [5] step
- * totals (statistics and arrival counts), [6] unused (the learned guess runs
- * inside the reconstruction kernel [3]), [7] collision + reconstruction of
- * cells with refined stencils.
+ * totals (statistics and arrival counts), [6] no-slip walls: image
+ * reconstruction (one launch per band) and image arrivals (one per step)
+ * (the learned guess runs inside the reconstruction kernel [3]), [7]
+ * collision + reconstruction of cells with refined stencils.
  * n is the capacity of ms and launches (at most LELBM_NTIMERS are filled). */
 #define LELBM_NTIMERS 8
 int lelbm_set_timing(lelbm_ctx *c, int enable);

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblelbm.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EEPR, ENONFINITE, EREACH = 0, -1, -2, -3, -4, -5, -6
-BC = {"periodic": 0, "outflow": 1, "inflow": 2, "slipwall": 3}
+BC = {"periodic": 0, "outflow": 1, "inflow": 2, "slipwall": 3, "wall": 4}
 FP64, MIXED = 0, 1
 GUESS_EQ, GUESS_MLP, GUESS_LIN, GUESS_PREV = 0, 1, 2, 3
 
@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("solid", ctypes.c_void_p),
         ("src_x", ctypes.c_int), ("src_y", ctypes.c_int),
         ("src_rate", ctypes.c_double), ("src_omega", ctypes.c_double), ("src_t0", ctypes.c_double),
+        ("wall_u", ctypes.c_double * 4),
     ]
 
 
@@ -174,6 +175,8 @@ def make_params(cfg, precision=FP64, guess=GUESS_EQ):
     if src is not None:
         p.src_x, p.src_y = src["x"], src.get("y", 0)
         p.src_rate, p.src_omega, p.src_t0 = src["rate"], src["omega"], src.get("t0", 0.0)
+    for i, v in enumerate(cfg.get("wall_u", (0.0, 0.0, 0.0, 0.0))):
+        p.wall_u[i] = v
     return p
 
 
@@ -252,7 +255,7 @@ class Lelbm:
         ms = (ctypes.c_double * 8)()
         ln = (ctypes.c_long * 8)()
         _check(lib().lelbm_kernel_times(self._h, ms, ln, 8))
-        names = ["fill_pads", "prepare", "scan", "epr", "gather", "totals", "unused6", "epr_ref"]
+        names = ["fill_pads", "prepare", "scan", "epr", "gather", "totals", "walls", "epr_ref"]
         return {n: (ms[i], ln[i]) for i, n in enumerate(names)}
 
     def memory(self):

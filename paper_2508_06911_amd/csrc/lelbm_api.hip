@@ -172,7 +172,9 @@ extern "C" const char *lelbm_strerror(int code) {
     case LELBM_EDEVICE: return "HIP device error";
     case LELBM_EEPR: return "entropic reconstruction failed (non-realizable state or Newton failure)";
     case LELBM_ENONFINITE: return "non-finite moments";
-    case LELBM_EREACH: return "pad narrower than a stencil's reach, or stencil out of the supported range";
+    case LELBM_EREACH:
+        return "pad narrower than a stencil's reach, stencil out of the supported range, or a no-slip wall reached "
+               "beyond what its bounce-back supports";
     default: return "unknown error";
     }
 }
@@ -190,7 +192,24 @@ static int validate(const lelbm_params *p) {
     if (p->guess == LELBM_GUESS_MLP && p->dim != 2) return LELBM_EINVAL;
     if (p->solid && p->dim != 2) return LELBM_EINVAL;
     for (int f = 0; f < 4; f++)
-        if (p->bc[f] < LELBM_BC_PERIODIC || p->bc[f] > LELBM_BC_SLIPWALL) return LELBM_EINVAL;
+        if (p->bc[f] < LELBM_BC_PERIODIC || p->bc[f] > LELBM_BC_WALL) return LELBM_EINVAL;
+    // no-slip walls (Sec. III.B): y faces of a 2D domain, without slip walls
+    // or solid cells; the wall velocity is tangential (x)
+    bool noslip = false;
+    for (int f = 0; f < 4; f++) {
+        if (!std::isfinite(p->wall_u[f])) return LELBM_EINVAL;
+        if (p->bc[f] != LELBM_BC_WALL) {
+            if (p->wall_u[f] != 0.0) return LELBM_EINVAL;
+            continue;
+        }
+        if (p->dim != 2 || f < 2) return LELBM_EINVAL;
+        noslip = true;
+    }
+    if (noslip) {
+        if (p->solid) return LELBM_EINVAL;
+        for (int f = 0; f < 4; f++)
+            if (p->bc[f] == LELBM_BC_SLIPWALL) return LELBM_EINVAL;
+    }
     for (int ax = 0; ax < p->dim; ax++) {
         int a = p->bc[2 * ax], b = p->bc[2 * ax + 1];
         if ((a == LELBM_BC_PERIODIC) != (b == LELBM_BC_PERIODIC)) return LELBM_EINVAL;
@@ -215,7 +234,7 @@ static void free_ctx(lelbm_ctx *c) {
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.spans, b.tiles,
                     b.dwin, b.scratch, b.flags, b.stats, b.partial, b.harvest_n,
                     c->mlp_w, c->mlp_p, c->mlp_n, (void *)b.solid, (void *)b.tdist, b.maxreach, (void *)b.cdist, (void *)b.tdist_s, b.wcache, (void *)b.wslot, b.wbuilt, b.lamprev,
-                    b.bpart, b.gpart, b.order, b.rlist, b.rcount, b.bands};
+                    b.bpart, b.gpart, b.order, b.rlist, b.rcount, b.bands, b.wflag, b.wimg, b.wreach};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t e : c->opev) (void)hipEventDestroy(e);
@@ -428,6 +447,8 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     else { g.tx = tile_x<1>(); g.ty = tile_y<1>(); }
     g.ntx = (g.sxn + g.tx - 1) / g.tx; g.nty = (g.syn + g.ty - 1) / g.ty;
     g.dtx = (g.nx + g.tx - 1) / g.tx; g.dty = (g.ny + g.ty - 1) / g.ty;
+    const bool noslip = p->dim == 2 && (g.bc[2] == LELBM_BC_WALL || g.bc[3] == LELBM_BC_WALL);
+    g.wrows = noslip ? std::min(g.ny, LELBM_WALL_ROWS) : 0;
     Phys &ph = c->ph;
     ph.K = p->K; ph.omega_f = p->omega_f; ph.omega_b = p->omega_b; ph.omega_h = p->omega_h;
     ph.n_conf = p->n_conf; ph.r_min = p->r_min; ph.tol = p->newton_tol; ph.maxit = p->newton_max_it;
@@ -442,6 +463,8 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ph.prev_guess = p->guess == LELBM_GUESS_PREV;
     ph.src_node = p->src_rate != 0.0 ? (long long)(p->src_y + g.wb) * g.sxn + (p->src_x + g.wl) : -1;
     ph.src_mass = 0.0;
+    ph.wall_ux[0] = p->dim == 2 ? p->wall_u[2] : 0.0;
+    ph.wall_ux[1] = p->dim == 2 ? p->wall_u[3] : 0.0;
     c->ph_step = ph;
     c->steps_done = 0;
 
@@ -476,6 +499,14 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
         // all-ones bytes are a NaN: no stored correction yet
         ok = ok && hipMemset(b.lamprev, 0xff, (size_t)16 * ns * sizeof(double)) == hipSuccess;
     }
+    if (g.wrows > 0) {
+        // image store of the no-slip walls: both faces, g.wrows rows each
+        const long long we = 2ll * g.wrows * g.sxn;
+        ok = ok && hipMalloc((void **)&b.wflag, (size_t)we * sizeof(int)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&b.wimg, (size_t)we * WALL_REC * sizeof(double)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&b.wreach, sizeof(int)) == hipSuccess;
+        ok = ok && hipMemset(b.wflag, 0, (size_t)we * sizeof(int)) == hipSuccess;
+    }
     if (p->guess == LELBM_GUESS_MLP) {
         ok = ok && hipMalloc((void **)&c->mlp_w, MLP_NPARAM * sizeof(unsigned short)) == hipSuccess;
         ok = ok && hipMalloc((void **)&c->mlp_p, MLP_NPARAM * sizeof(float)) == hipSuccess;
@@ -484,7 +515,8 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     if (!ok) { free_ctx(c); return LELBM_ENOMEM; }
     c->persistent_bytes = (long long)2 * c->nmom * ns * sizeof(double) + ns * (4 * sizeof(double) + sizeof(int)) +
                           nt * sizeof(TileInfo) + nd * sizeof(DWin) +
-                          (b.lamprev ? (long long)16 * ns * sizeof(double) : 0);
+                          (b.lamprev ? (long long)16 * ns * sizeof(double) : 0) +
+                          (long long)2 * g.wrows * g.sxn * (WALL_REC * sizeof(double) + sizeof(int));
     int r = setup_blockers(c, p->solid);
     if (r != LELBM_OK) { free_ctx(c); return r; }
     if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess ||
@@ -699,6 +731,15 @@ static hipError_t do_epr_ref(lelbm_ctx *c, void *a) {
     return launch_epr_ref(c->g, c->ph_step, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
                           (bd.row1 - bd.row0) * c->g.ntx, s.a, s.es);
 }
+static hipError_t do_wall_image(lelbm_ctx *c, void *a) {
+    const StepArg &s = *(StepArg *)a;
+    const BandInfo &bd = s.plan->bands[s.a];
+    return launch_wall_image(c->g, c->ph_step, c->mixed, c->b.mom[c->cur], c->b, s.step, bd.row0 * c->g.ntx,
+                             (bd.row1 - bd.row0) * c->g.ntx, s.es);
+}
+static hipError_t do_wall_gather(lelbm_ctx *c, void *) {
+    return launch_wall_gather(c->g, c->b.mom[c->cur ^ 1], c->b, c->stream);
+}
 static hipError_t do_gather(lelbm_ctx *c, void *a) {
     const StepArg &s = *(StepArg *)a;
     return launch_gather(c->g, c->mixed, c->b.mom[c->cur ^ 1], c->b, c->gcap, s.a, s.n, s.gs);
@@ -797,6 +838,16 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
                     if ((r = timed(c, 3, do_epr, &a, a.es)) != LELBM_OK) return r;
                     if ((r = timed(c, 7, do_epr_ref, &a, a.es)) != LELBM_OK) return r;
                     if ((r = timed(c, 3, do_epr_wide, &a, a.ws)) != LELBM_OK) return r;
+                    if (c->b.wflag) {
+                        // the image populations of the band's sources read its
+                        // records (of both reconstruction streams); the gathers
+                        // that wait for this band see them
+                        if (multi && a.ws != a.es) {
+                            HIPCHECK(hipEventRecord(c->opev[2 * i + 1], a.ws));
+                            HIPCHECK(hipStreamWaitEvent(a.es, c->opev[2 * i + 1], 0));
+                        }
+                        if ((r = timed(c, 6, do_wall_image, &a, a.es)) != LELBM_OK) return r;
+                    }
                     if (multi) {
                         HIPCHECK(hipEventRecord(c->opev[2 * i], a.es));
                         HIPCHECK(hipEventRecord(c->opev[2 * i + 1], a.ws));
@@ -821,6 +872,7 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
                 if (last_odd >= 0) HIPCHECK(hipStreamWaitEvent(s, c->opev[2 * last_odd], 0));
                 if (last_wide >= 0) HIPCHECK(hipStreamWaitEvent(s, c->opev[2 * last_wide + 1], 0));
             }
+            if ((r = timed(c, 6, do_wall_gather, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 5, do_totals, &a)) != LELBM_OK) return r;
             c->cur ^= 1;
         }

@@ -62,6 +62,7 @@ struct Geom {
     int tx, ty;               // tile extent (16,16) or (256,1)
     int ntx, nty;             // source tiles over the padded domain
     int dtx, dty;             // destination tiles over the interior
+    int wrows;                // no-slip walls: rows of each face's image store (0: no such wall)
 };
 
 // Gather workgroups: in 2D one per strip of GATHER_NTB x-neighbour
@@ -86,7 +87,18 @@ struct Phys {
     int prev_guess;                 // 1: linearised guess plus the cell's previous-step correction
     long long src_node;             // padded index of the mass-source cell, -1: none
     double src_mass;                // mass the source adds in the current step
+    double wall_ux[2];              // x velocity of the no-slip walls of the ylo / yhi faces
 };
+
+// Image store of the no-slip walls (Sec. III.B), per wall face f, per row r
+// < Geom::wrows counted from the face, per padded column: entry
+// (f * wrows + r) * sxn + px.  wflag: 0 nothing, 1 image populations
+// (bits 8 and up: their radius R), 2 the absorbed populations are reflected
+// specularly; wimg: WALL_REC doubles per entry, the image species'
+// multipliers (fluon 10, phonon 6), u_n (2) and the factors turning the
+// normalised image populations into moment fractions (fluon, phonon).
+constexpr int WALL_REC = 20;
+constexpr int WALL_FLAG_IMAGE = 1, WALL_FLAG_SPECULAR = 2;
 
 // Zeroth post-collision moment of cell s: rho, plus the mass of a point
 // source (Sec. IV.C, Eq. VC8) in its cell.
@@ -179,6 +191,11 @@ struct Buffers {
     unsigned short *wcache;        // [slots][WCACHE_W^2][TILE_N], NULL = not cached
     const int *wslot;              // [dtx*dty] cache slot of a destination tile, -1 = none
     int *wbuilt;                   // largest reach the cache holds every near tile's walks for, -1 = none
+    // no-slip walls (NULL without them): the image store and the largest
+    // displacement of an image population that enters the domain (this step)
+    int *wflag;
+    double *wimg;
+    int *wreach;
 };
 
 // Kernel launchers (defined in lelbm_kernels.hip).  All enqueue on `s`.
@@ -197,6 +214,12 @@ hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const double
 // gather of the destination block rows [br0, br0 + nbr)
 hipError_t launch_gather(const Geom &g, int mixed, double *mom_out, Buffers &b, int gcap, int br0, int nbr,
                          hipStream_t s);
+// no-slip walls: image populations of the sources of band tiles [tile0,
+// tile0 + ntiles) (after their reconstruction, before the gathers that read
+// them), and their arrivals (after the step's last gather)
+hipError_t launch_wall_image(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step,
+                             int tile0, int ntiles, hipStream_t s);
+hipError_t launch_wall_gather(const Geom &g, double *mom_out, Buffers &b, hipStream_t s);
 // statistics and arrival counts of a step (after its last gather)
 hipError_t launch_step_totals(const Geom &g, Buffers &b, hipStream_t s);
 hipError_t launch_sums(const Geom &g, const double *mom, Buffers &b, hipStream_t s);

@@ -96,6 +96,12 @@ __device__ inline void flag_fail(Flags *fl, int code, int step, long long node, 
     if (fl->err == code) atomicMin((unsigned long long *)&fl->node, (unsigned long long)node);
 }
 
+// Faces whose sources the gather may see mirrored: slip walls, and no-slip
+// walls (sources that reflect their absorbed populations specularly).
+__host__ __device__ inline bool mirror_face(const Geom &g, int f) {
+    return g.bc[f] == LELBM_BC_SLIPWALL || g.bc[f] == LELBM_BC_WALL;
+}
+
 // Reasons of a failed reconstruction (lelbm_last_failure_detail).
 enum { FAIL_NONFINITE = 1, FAIL_LINESEARCH = 2, FAIL_CHOL_POLISH = 3, FAIL_MAXIT = 4, FAIL_CHOL_STEP = 5 };
 // species_update asks for a restart from Eq. (IID13) when a solve started
@@ -335,15 +341,17 @@ __global__ void __launch_bounds__(256) k_prepare(Geom g, Phys ph, const T *mom, 
             int x0 = tx0 - g.wl, x1 = min(tx0 + g.tx, g.sxn) - 1 - g.wl;
             int y0 = ty0 - g.wb, y1 = min(ty0 + g.ty, g.syn) - 1 - g.wb;
             int lx = ti.ox, ly = ti.oy, hx = red[2][0], hy = red[3][0];
-            // mirror images across slip walls: m = 0 none, 1 low face, 2 high face
-            bool slipx = g.bc[0] == LELBM_BC_SLIPWALL || g.bc[1] == LELBM_BC_SLIPWALL;
-            bool slipy = D == 2 && (g.bc[2] == LELBM_BC_SLIPWALL || g.bc[3] == LELBM_BC_SLIPWALL);
+            // mirror images across slip walls (and no-slip walls, whose
+            // absorbed populations may be reflected specularly): m = 0 none,
+            // 1 low face, 2 high face
+            bool slipx = mirror_face(g, 0) || mirror_face(g, 1);
+            bool slipy = D == 2 && (mirror_face(g, 2) || mirror_face(g, 3));
             for (int mx = 0; mx < (slipx ? 3 : 1); mx++) {
-                if (mx == 1 && g.bc[0] != LELBM_BC_SLIPWALL) continue;
-                if (mx == 2 && g.bc[1] != LELBM_BC_SLIPWALL) continue;
+                if (mx == 1 && !mirror_face(g, 0)) continue;
+                if (mx == 2 && !mirror_face(g, 1)) continue;
                 for (int my = 0; my < (slipy ? 3 : 1); my++) {
-                    if (my == 1 && g.bc[2] != LELBM_BC_SLIPWALL) continue;
-                    if (my == 2 && g.bc[3] != LELBM_BC_SLIPWALL) continue;
+                    if (my == 1 && !mirror_face(g, 2)) continue;
+                    if (my == 2 && !mirror_face(g, 3)) continue;
                     int gx0 = x0, gx1 = x1, glx = lx, ghx = hx;
                     if (mx == 1) { gx0 = -1 - x1; gx1 = -1 - x0; glx = -hx; ghx = -lx; }
                     if (mx == 2) { gx0 = 2 * g.nx - 1 - x1; gx1 = 2 * g.nx - 1 - x0; glx = -hx; ghx = -lx; }
@@ -1766,6 +1774,7 @@ struct Resolved {
     long long s;    // padded source index, -1 if none
     int px, py;     // padded source coordinates
     int fx, fy;     // 1 if the path is mirrored in x / y
+    int wf;         // the no-slip wall face (0 ylo, 1 yhi) the path is mirrored across, -1 none
 };
 
 // Source tile and the cell's place in it from padded coordinates (tile
@@ -1780,7 +1789,7 @@ __device__ inline void tile_of(const Geom &g, int px, int py, int &st, int &loc)
 
 template <int D>
 __device__ inline Resolved resolve_source(const Geom &g, int xr, int yr) {
-    Resolved r{-1, 0, 0, 0, 0};
+    Resolved r{-1, 0, 0, 0, 0, -1};
     int sx = xr, sy = yr;
     if (g.bc[0] == LELBM_BC_PERIODIC) { sx %= g.nx; if (sx < 0) sx += g.nx; }
     else if (sx < 0 && g.bc[0] == LELBM_BC_SLIPWALL) { sx = -1 - sx; r.fx = 1; }
@@ -1790,6 +1799,8 @@ __device__ inline Resolved resolve_source(const Geom &g, int xr, int yr) {
         if (g.bc[2] == LELBM_BC_PERIODIC) { sy %= g.ny; if (sy < 0) sy += g.ny; }
         else if (sy < 0 && g.bc[2] == LELBM_BC_SLIPWALL) { sy = -1 - sy; r.fy = 1; }
         else if (sy >= g.ny && g.bc[3] == LELBM_BC_SLIPWALL) { sy = 2 * g.ny - 1 - sy; r.fy = 1; }
+        else if (sy < 0 && g.bc[2] == LELBM_BC_WALL) { sy = -1 - sy; r.fy = 1; r.wf = 0; }
+        else if (sy >= g.ny && g.bc[3] == LELBM_BC_WALL) { sy = 2 * g.ny - 1 - sy; r.fy = 1; r.wf = 1; }
         if (sy < -g.wb || sy >= g.ny + g.wt) return r;
     } else {
         sy = 0;
@@ -1798,6 +1809,17 @@ __device__ inline Resolved resolve_source(const Geom &g, int xr, int yr) {
     r.py = sy + g.wb;
     r.s = (long long)r.py * g.sxn + r.px;
     return r;
+}
+
+// A path mirrored across a no-slip wall is absorbed there (Eq. IIIB8); it
+// arrives only when its source reflects its absorbed populations
+// specularly (no image population of the source crosses that wall).
+__device__ inline bool wall_keeps(const Geom &g, const Buffers &b, const Resolved &r) {
+    if (r.wf < 0) return true;
+    const int sy = r.py - g.wb;
+    const int row = r.wf == 0 ? sy : g.ny - 1 - sy;
+    if (row < 0 || row >= g.wrows) return false;
+    return (b.wflag[((long long)r.wf * g.wrows + row) * g.sxn + r.px] & WALL_FLAG_SPECULAR) != 0;
 }
 
 // Adds the moment fractions of one arriving record; (cx, cy) is the
@@ -2031,6 +2053,7 @@ __global__ void __launch_bounds__(256, 4) k_gather(Geom g, double *mom_out, Buff
             for (int i = threadIdx.x; i < RW * RH; i += 256) {
                 Resolved rs = resolve_source<D>(g, rx0 + i % RW, ry0 + i / RW);
                 int meta = -1;
+                if (WALLS && rs.s >= 0 && !wall_keeps(g, b, rs)) rs.s = -1;
                 if (rs.s >= 0) {
                     int rn = b.desc_rn[rs.s];
                     if (rn >= 0) {
@@ -2170,7 +2193,7 @@ __global__ void __launch_bounds__(256, 4) k_gather(Geom g, double *mom_out, Buff
         for (int dy = w.hiy; dy >= w.loy; dy--) {
             for (int dx = w.hix; dx >= w.lox; dx--) {
                 Resolved rs = resolve_source<D>(g, x - dx, y - dy);
-                if (rs.s < 0) continue;
+                if (rs.s < 0 || !wall_keeps(g, b, rs)) continue;
                 const long long s = rs.s;
                 const int rn = b.desc_rn[s];
                 if (rn < 0) continue;
@@ -2469,13 +2492,263 @@ __global__ void __launch_bounds__(256) k_gather_near(Geom g, double *mom_out, Bu
 // ---------------------------------------------------------------------------
 // resets and conserved totals
 // ---------------------------------------------------------------------------
-__global__ void k_reset_windows(int n, DWin *w, int *maxreach) {
+// ---------------------------------------------------------------------------
+// No-slip walls on the y faces: the extended bounce-back of Sec. III.B.
+//
+// The gather drops every population whose straight path crosses such a wall
+// (its mirror-image source, see wall_keeps): it is absorbed, and its moment
+// fractions add to the mass and phonon imbalances Delta m, Delta g of its
+// source and wall (Eq. IIIB8).  k_wall_image takes them from the source's
+// records, right after the reconstruction of its band, and for each wall with
+// Delta m > 0 reconstructs image populations: the same normalised
+// post-collision targets (the non-equilibrium part of the cell at unchanged
+// RT, Eqs. IIIB9-10) on the stencil around u_n = u - 2 u_w (Eq. IIIB11;
+// u_w along x), solved like any cell (Eq. IIIB13).  They stream with -c_i;
+// those whose path crosses the wall land at the mirror image of x - c_i with
+// velocity (-c_x, c_y), their sum Delta m' (Eq. IIIB14), and enter scaled by
+// Delta m / Delta m' (Eq. IIIB15); phonons by Delta g / Delta g'.  The store
+// keeps the multipliers and factors, and k_wall_gather evaluates the image
+// populations at their destinations after the step's gathers.  When no image
+// population crosses the wall the source's absorbed populations are
+// reflected specularly instead (the gather keeps their mirror-image source).
+// A stencil that crosses both walls, a refined one that crosses a wall, a
+// source farther than the store's rows from a wall it reaches, and a
+// population that would land only after a second reflection fail the step
+// with LELBM_EREACH.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_wall_image(Geom g, Phys ph, const double *mom, Buffers b, int step,
+                                                    int tile0) {
+    using BS = Basis<2>;
+    constexpr int NF = BS::NF, NG = BS::NG, NMF = BS::NMF, NMG = BS::NMG, NM = BS::NMOM;
+    __shared__ int s_err;
+    if (threadIdx.x == 0) s_err = b.flags->err;
+    __syncthreads();
+    if (s_err) return;
+    const int t = tile0 + blockIdx.x;
+    const int l = threadIdx.x;
+    const int px = (t % g.ntx) * g.tx + l % g.tx, py = (t / g.ntx) * g.ty + l / g.tx;
+    if (px >= g.sxn || py >= g.syn) return;
+    const int sy = py - g.wb;
+    const long long s = (long long)py * g.sxn + px;
+    const int WR = g.wrows;
+    // the cell's entries in the stores of the two walls
+    long long e[2] = {-1, -1};
+    if (g.bc[2] == LELBM_BC_WALL && sy < WR) e[0] = (long long)sy * g.sxn + px;
+    if (g.bc[3] == LELBM_BC_WALL && g.ny - 1 - sy < WR) e[1] = ((long long)WR + (g.ny - 1 - sy)) * g.sxn + px;
+    if (e[0] >= 0) b.wflag[e[0]] = 0;
+    if (e[1] >= 0) b.wflag[e[1]] = 0;
+    const int rn = b.desc_rn[s];
+    if (rn < 0) return;
+    const int R = rn & 0xffff, Nr = rn >> 16;
+    const double ux = b.desc_u[s], uy = b.desc_u[g.ns + s];
+    const double rr = R + 0.5;
+    const int ubx = (int)floor(ux + 0.5), uby = (int)floor(uy + 0.5);
+    const int xlo = ubx - R - 1, xhi = ubx + R + 1, ylo = uby - R - 1, yhi = uby + R + 1;
+    const bool lo = g.bc[2] == LELBM_BC_WALL && sy + ylo < 0;
+    const bool hi = g.bc[3] == LELBM_BC_WALL && sy + yhi > g.ny - 1;
+    if (!lo && !hi) return;
+    // Delta m and Delta g per wall: the records of the points whose path crosses it
+    const TileInfo ti = b.tiles[t];
+    const T *P = (const T *)b.scratch + ti.base;
+    const long long recsz = ti.fmt ? NM : 2, og = ti.fmt ? 8 : 1;
+    double dm[2] = {0.0, 0.0}, dg[2] = {0.0, 0.0};
+    for (int cy = ylo; cy <= yhi; cy++) {
+        const int f = sy + cy < 0 ? 0 : (sy + cy > g.ny - 1 ? 1 : -1);
+        if (f < 0 || g.bc[2 + f] != LELBM_BC_WALL) continue;
+        int xa, xb;
+        if (!row_span<2>(cy, ux, uy, rr, xlo, xhi, xa, xb)) continue;
+        if (Nr > 0 || e[f] < 0) {
+            flag_fail(b.flags, LELBM_EREACH, step, s);
+            return;
+        }
+        for (int cx = xa; cx <= xb; cx++) {
+            const long long slot = (long long)(cy - ti.oy) * ti.wx + (cx - ti.ox);
+            dm[f] += (double)P[(slot * TILE_N + l) * recsz];
+            dg[f] += (double)P[(slot * TILE_N + l) * recsz + og];
+        }
+    }
+    if (dm[0] > 0.0 && dm[1] > 0.0) {
+        flag_fail(b.flags, LELBM_EREACH, step, s);
+        return;
+    }
+    const double rho = b.desc_rho[s], RT = b.desc_rt[s];
+    double mf[NF], mg[NG], kn;
+    int lim;
+    collide_targets<double, 2>(g, ph, mom, s, rho, ux, uy, RT, mf, mg, kn, lim);
+    const double wsf = post_mass(ph, s, rho), wsg = wsf * ph.K * RT;
+    const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
+    for (int f = 0; f < 2; f++) {
+        if (!(dm[f] > 0.0)) continue;
+        const double unx = ux - 2.0 * ph.wall_ux[f];
+        Species<NF, RegStore<NF>> sf;
+        Species<NG, RegStore<NG>> sg;
+        species_init<2, NF, NG>(sf, sg, RT);
+        int fail = 0, fsp = -1;
+        while (!fail && (sf.phase < 2 || sg.phase < 2)) {
+            double Sf[NMF], Sg[NMG], lf[NF], lg[NG];
+#pragma unroll
+            for (int k = 0; k < NMF; k++) Sf[k] = 0.0;
+#pragma unroll
+            for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
+#pragma unroll
+            for (int j = 0; j < NG; j++) lg[j] = sg.at(j);
+            for_each_point<2>(
+                unx, uy, R, 0,
+                [&](double cx, double cy, double, int, int) {
+                    double m[NMF];
+                    monomials<2, NMF>(cx - unx, cy - uy, m);
+                    double ef = 0.0, eg = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NF; j++) ef += lf[j] * m[j];
+#pragma unroll
+                    for (int j = 0; j < NG; j++) eg += lg[j] * m[j];
+                    const double fv = exp(-(1.0 + ef)), gv = exp(-(1.0 + eg));
+#pragma unroll
+                    for (int k = 0; k < NMF; k++) Sf[k] += fv * m[k];
+#pragma unroll
+                    for (int k = 0; k < NMG; k++) Sg[k] += gv * m[k];
+                },
+                [&](int, int) {});
+            if (sg.phase < 2) {
+                int r = species_update<2, NG, NMG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
+                if (r < 0) { fail = -r; fsp = 1; }
+            }
+            if (sf.phase < 2 && !fail) {
+                int r = species_update<2, NF, NMF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
+                if (r < 0) { fail = -r; fsp = 0; }
+            }
+        }
+        if (fail) {
+            flag_fail(b.flags, LELBM_EEPR, step, s, fail, fsp, fsp ? sg.res : sf.res);
+            return;
+        }
+        // the image points that cross the wall (streamed with -c_i) and their sums
+        double dmi = 0.0, dgi = 0.0;
+        int reach = 0;
+        bool out = false;
+        for_each_point<2>(
+            unx, uy, R, 0,
+            [&](double cx, double cy, double, int dx, int dy) {
+                const int yu = sy - dy;
+                if (f == 0 ? yu >= 0 : yu <= g.ny - 1) return;
+                const int ly = f == 0 ? -1 - yu : 2 * g.ny - 1 - yu;
+                out = out || ly < 0 || ly > g.ny - 1;
+                double m[NF];
+                monomials<2, NF>(cx - unx, cy - uy, m);
+                double ef = 0.0, eg = 0.0;
+#pragma unroll
+                for (int j = 0; j < NF; j++) ef += sf.v.lam(j) * m[j];
+#pragma unroll
+                for (int j = 0; j < NG; j++) eg += sg.v.lam(j) * m[j];
+                dmi += wsf * exp(-(1.0 + ef));
+                dgi += wsg * exp(-(1.0 + eg));
+                reach = max(reach, max(abs(dx), abs(dy)));
+            },
+            [&](int, int) {});
+        if (out) {
+            flag_fail(b.flags, LELBM_EREACH, step, s);
+            return;
+        }
+        if (dmi > 0.0 && dgi > 0.0) {
+            double *rec = b.wimg + e[f] * WALL_REC;
+#pragma unroll
+            for (int j = 0; j < NF; j++) rec[j] = sf.v.lam(j);
+#pragma unroll
+            for (int j = 0; j < NG; j++) rec[NF + j] = sg.v.lam(j);
+            rec[16] = unx;
+            rec[17] = uy;
+            rec[18] = wsf * (dm[f] / dmi);
+            rec[19] = wsg * (dg[f] / dgi);
+            b.wflag[e[f]] = WALL_FLAG_IMAGE | (R << 8);
+            if (reach > __hip_atomic_load(b.wreach, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(b.wreach, reach);
+        } else {
+            // specular reflection of the absorbed points: each must land after one reflection
+            for (int cy = ylo; cy <= yhi; cy++) {
+                const int yu = sy + cy;
+                if (f == 0 ? yu >= 0 : yu <= g.ny - 1) continue;
+                int xa, xb;
+                if (!row_span<2>(cy, ux, uy, rr, xlo, xhi, xa, xb)) continue;
+                const int ly = f == 0 ? -1 - yu : 2 * g.ny - 1 - yu;
+                if (ly < 0 || ly > g.ny - 1) {
+                    flag_fail(b.flags, LELBM_EREACH, step, s);
+                    return;
+                }
+            }
+            b.wflag[e[f]] = WALL_FLAG_SPECULAR;
+        }
+    }
+}
+
+// Arrivals of the image populations (after the step's gathers): one thread
+// per destination cell of the rows within the store's reach of a no-slip
+// wall; the image source of displacement d is the cell whose image point d,
+// streamed with -d and reflected by the wall, lands here: (x + d_x, d_y - y
+// - 1) for the ylo wall, mirrored for yhi.
+__global__ void __launch_bounds__(256) k_wall_gather(Geom g, double *mom_out, Buffers b) {
+    constexpr int NF = Basis<2>::NF, NG = Basis<2>::NG, NM = Basis<2>::NMOM;
+    __shared__ int s_err;
+    if (threadIdx.x == 0) s_err = b.flags->err;
+    __syncthreads();
+    if (s_err) return;
+    const int WR = g.wrows;
+    const int nr = min(g.ny, 2 * WR);
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)nr * g.nx) return;
+    const int x = (int)(i % g.nx), k = (int)(i / g.nx);
+    const int y = (g.ny <= 2 * WR || k < WR) ? k : g.ny - 2 * WR + k;
+    const int M = *b.wreach;
+    const bool perx = g.bc[0] == LELBM_BC_PERIODIC;
+    double acc[NM];
+#pragma unroll
+    for (int j = 0; j < NM; j++) acc[j] = 0.0;
+    for (int f = 0; f < 2; f++) {
+        if (g.bc[2 + f] != LELBM_BC_WALL) continue;
+        const int yd = f == 0 ? y : g.ny - 1 - y;   // rows between the destination and the wall
+        for (int r = 0; r < WR && yd + 1 + r <= M; r++) {
+            const int dy = f == 0 ? yd + 1 + r : -(yd + 1 + r);
+            const long long row = ((long long)f * WR + r) * g.sxn;
+            for (int dx = -M; dx <= M; dx++) {
+                int sx = x + dx;
+                if (perx) sx = wrap_coord(sx, g.nx);
+                const int pxs = sx + g.wl;
+                if (pxs < 0 || pxs >= g.sxn) continue;
+                const int fl = b.wflag[row + pxs];
+                if ((fl & 3) != WALL_FLAG_IMAGE) continue;
+                const double *rec = b.wimg + (row + pxs) * WALL_REC;
+                const double unx = rec[16], uny = rec[17];
+                if (!in_disk2((double)dx, (double)dy, unx, uny, (double)(fl >> 8) + 0.5)) continue;
+                double m[NF];
+                monomials<2, NF>((double)dx - unx, (double)dy - uny, m);
+                double ef = 0.0, eg = 0.0;
+#pragma unroll
+                for (int j = 0; j < NF; j++) ef += rec[j] * m[j];
+#pragma unroll
+                for (int j = 0; j < NG; j++) eg += rec[NF + j] * m[j];
+                const double wf = rec[18] * exp(-(1.0 + ef)), wg = rec[19] * exp(-(1.0 + eg));
+                const double cx = -(double)dx, cy = (double)dy, cc = cx * cx + cy * cy;
+                acc[0] += wf; acc[1] += cx * wf; acc[2] += cy * wf;
+                acc[3] += cx * cx * wf; acc[4] += cx * cy * wf; acc[5] += cy * cy * wf;
+                acc[6] += cc * cx * wf; acc[7] += cc * cy * wf;
+                acc[8] += wg; acc[9] += cx * wg; acc[10] += cy * wg;
+            }
+        }
+    }
+    const long long o = (long long)(y + g.wb) * g.sxn + (x + g.wl);
+#pragma unroll
+    for (int j = 0; j < NM; j++) mom_out[j * g.ns + o] += acc[j];
+}
+
+__global__ void k_reset_windows(int n, DWin *w, int *maxreach, int *wreach) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         w[i].lox = 1 << 29; w[i].loy = 1 << 29; w[i].hix = -(1 << 29); w[i].hiy = -(1 << 29);
         w[i].uxl = 1 << 29; w[i].uyl = 1 << 29; w[i].uxh = -(1 << 29); w[i].uyh = -(1 << 29); w[i].rmax = -1;
     }
     if (i == 0 && maxreach) *maxreach = 0;
+    if (i == 0 && wreach) *wreach = 0;
 }
 
 // Zeroes the state of solid cells (they hold no gas).
@@ -2631,7 +2904,7 @@ hipError_t launch_fill_pads(const Geom &g, const Phys &ph, double *mom, Flags *f
 
 hipError_t launch_reset_step(const Geom &g, Buffers &b, hipStream_t s) {
     int n = g.dtx * g.dty;
-    hipLaunchKernelGGL(k_reset_windows, dim3((n + 255) / 256), dim3(256), 0, s, n, b.dwin, b.maxreach);
+    hipLaunchKernelGGL(k_reset_windows, dim3((n + 255) / 256), dim3(256), 0, s, n, b.dwin, b.maxreach, b.wreach);
     return hipGetLastError();
 }
 
@@ -2725,6 +2998,23 @@ hipError_t launch_epr_ref(const Geom &g, const Phys &ph, int mixed, const double
     return hipGetLastError();
 }
 
+hipError_t launch_wall_image(const Geom &g, const Phys &ph, int mixed, const double *mom, Buffers &b, int step,
+                             int tile0, int ntiles, hipStream_t s) {
+    if (!b.wflag || ntiles <= 0) return hipSuccess;
+    if (mixed)
+        hipLaunchKernelGGL((k_wall_image<float>), dim3((unsigned)ntiles), dim3(256), 0, s, g, ph, mom, b, step, tile0);
+    else
+        hipLaunchKernelGGL((k_wall_image<double>), dim3((unsigned)ntiles), dim3(256), 0, s, g, ph, mom, b, step, tile0);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_gather(const Geom &g, double *mom_out, Buffers &b, hipStream_t s) {
+    if (!b.wflag) return hipSuccess;
+    const long long n = (long long)std::min(g.ny, 2 * g.wrows) * g.nx;
+    hipLaunchKernelGGL(k_wall_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, mom_out, b);
+    return hipGetLastError();
+}
+
 // After the backward-walk gather: a step that filled the walk cache (at a
 // reach above the one it held) makes that reach available to later steps.
 __global__ void k_mark_built(const Flags *fl, const int *maxreach, int *wbuilt) {
@@ -2737,7 +3027,7 @@ static void gather_launch(const Geom &g, double *mom_out, Buffers &b, int gcap, 
     const unsigned nt = (unsigned)(gather_blocks_x(g) * nbr);
     const size_t lds = (size_t)gcap * G_ENTRY_BYTES;
     bool walls = false;
-    for (int f = 0; f < 2 * D; f++) walls = walls || g.bc[f] == LELBM_BC_SLIPWALL;
+    for (int f = 0; f < 2 * D; f++) walls = walls || mirror_face(g, f);
     if (walls)
         hipLaunchKernelGGL((k_gather<T, D, true>), dim3(nt), dim3(256), lds, s, g, mom_out, b, gcap, br0, nbr);
     else

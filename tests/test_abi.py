@@ -62,6 +62,15 @@ def test_invalid_parameters_are_rejected_before_any_device_call():
     c = dict(cfg); c["K"] = 0.0; bad.append(c)
     c = dict(cfg); c["newton_tol"] = -1.0; bad.append(c)
     c = dict(cfg); c["dim"] = 1; bad.append(c)                                                    # ny must be 1
+    # no-slip walls: y faces of a 2D domain only, not with slip walls or solids,
+    # wall velocity only on wall faces
+    c = dict(cfg); c["bc"] = ["wall", "wall", "periodic", "periodic"]; bad.append(c)
+    c = dict(cfg); c["bc"] = ["slipwall", "slipwall", "wall", "wall"]; bad.append(c)
+    c = dict(cfg); c["bc"] = ["periodic", "periodic", "wall", "wall"]; c["solid"] = np.eye(8, dtype=np.uint8)
+    bad.append(c)
+    c = dict(cfg); c["wall_u"] = (0.0, 0.0, 0.1, 0.0); bad.append(c)
+    c = dict(cfg); c["bc"] = ["periodic", "periodic", "wall", "wall"]; c["wall_u"] = (0.0, 0.0, 0.0, float("nan"))
+    bad.append(c)
     for c in bad:
         mm = m if c["dim"] == 2 else np.ones((6, 64))
         with pytest.raises(lb.LelbmError) as e:
