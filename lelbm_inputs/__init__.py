@@ -24,6 +24,8 @@ Workloads (lattice units, dx = dt = 1):
     verification problems (Sec. IV.A, IV.D, IV.C).
   * ``couette`` -- gas between no-slip walls on the y faces, the top wall
     moving along x (Sec. III.B).
+  * ``smooth_periodic3`` / ``shear_wave3`` -- 3D periodic boxes (smooth
+    random fields; the transverse shear wave of Sec. IV.A in 3D).
   * ``oblique_shock`` -- uniform supersonic flow turned by a slip wall
     (Sec. V.F): the flow enters through the left and top faces inclined by
     theta toward the bottom slip wall, which deflects it along the wall.
@@ -37,6 +39,7 @@ GAMMA = 1.4
 # internal degrees of freedom for gamma = 1.4: gamma = (D + K + 2)/(D + K)
 K_1D = 4.0
 K_2D = 3.0
+K_3D = 2.0
 
 RT_FLOOR = 0.5
 
@@ -293,3 +296,45 @@ def smooth_periodic(seed, n=16, ny=12, dim=2, amp=0.05, RT=0.8):
 
 
 BC_NAMES = ("periodic", "outflow", "inflow", "slipwall")
+
+
+def _base_cfg3(nx, ny, nz, K=K_3D):
+    cfg = _base_cfg(3, nx, ny, K)
+    cfg["nz"] = nz
+    cfg["bc"] = ["periodic"] * 6
+    return cfg
+
+
+def smooth_periodic3(seed, n=12, ny=None, nz=None, amp=0.05, RT=1.0, u=(0.3, -0.2, 0.1)):
+    """3D periodic box with a few smooth random Fourier modes in each of rho,
+    u_x, u_y, u_z and RT (fields [nz][ny][nx])."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    z, y, x = np.meshgrid((np.arange(nz) + 0.5) / nz, (np.arange(ny) + 0.5) / ny, (np.arange(n) + 0.5) / n,
+                          indexing="ij")
+    fields = []
+    for _ in range(5):
+        f = np.zeros((nz, ny, n))
+        for a in range(1, 3):
+            for b in range(0, 2):
+                for c in range(0, 2):
+                    f += g.standard_normal() * np.sin(2 * np.pi * (a * x + b * y + c * z) + g.uniform(0, 2 * np.pi))
+        fields.append(f / max(np.abs(f).max(), 1e-30))
+    cfg = _base_cfg3(n, ny, nz)
+    prim = {"rho": 1.0 + amp * fields[0], "ux": u[0] + 5 * amp * fields[1], "uy": u[1] + 5 * amp * fields[2],
+            "uz": u[2] + 5 * amp * fields[3], "RT": RT * (1.0 + amp * fields[4])}
+    return cfg, prim
+
+
+def shear_wave3(L=16, ny=1, nz=1, RT=1.0, u0=0.5, amp=1e-3, nu=0.05, K=K_3D):
+    """3D transverse shear wave u_y = amp cos(2 pi x / L) on a uniform flow
+    u_x = u0 (Sec. IV.A); uniform along y and z.  Shear frequency from
+    nu = RT (1/omega - 1/2)."""
+    cfg = _base_cfg3(L, ny, nz, K)
+    om = 1.0 / (nu / RT + 0.5)
+    cfg.update({"omega_f": om, "omega_b": 1.0, "omega_h": om, "kn_limiter": 0, "nu": nu})
+    x = (np.arange(L) + 0.5)[None, None, :] * np.ones((nz, ny, 1))
+    prim = {"rho": np.ones((nz, ny, L)), "ux": np.full((nz, ny, L), u0),
+            "uy": amp * np.cos(2 * np.pi * x / L), "uz": np.zeros((nz, ny, L)), "RT": np.full((nz, ny, L), RT)}
+    return cfg, prim

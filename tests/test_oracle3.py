@@ -1,0 +1,306 @@
+"""CPU pins of the 3D oracle (oracle/lelbm_oracle3.c) against what the paper
+and the mathematics fix: the stencil by brute force, the central moments of
+Eq. (IIB9) by their definition over a discrete population set, the 2D
+collision on states that do not depend on z, the reconstruction against an
+independent minimiser of its dual, and the step's invariants (uniform flow,
+conservation, Galilean boost by an integer velocity, axis permutations and
+mirrors) and the shear viscosity of Eq. (C8a)."""
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+import lelbm_inputs as li
+import oracle
+
+
+def mom3(cfg, prim):
+    return oracle.moments_from_primitives3(cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["uz"], prim["RT"])
+
+
+# --------------------------------------------------------------------------
+# stencil
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("u,RT", [((0.0, 0.0, 0.0), 1.0), ((0.3, -0.2, 0.1), 0.5), ((2.49, -3.51, 0.5), 2.3),
+                                  ((-7.25, 4.0, 11.6), 0.47)])
+def test_stencil_is_the_ball_by_brute_force(u, RT):
+    """Eq. (IIC6) with the ball |c - u| <= R + 1/2 (reading 1 of the 2D
+    stencil), listed z-major, then y, then x."""
+    d = oracle.las3(u, RT)
+    R = max(int(np.floor(4.0 * np.sqrt(RT) + 0.5)), 2)
+    rng = np.arange(-R - 6, R + 7)
+    pts = [(x, y, z) for z in rng + int(round(u[2])) for y in rng + int(round(u[1])) for x in rng + int(round(u[0]))
+           if (x - u[0]) ** 2 + (y - u[1]) ** 2 + (z - u[2]) ** 2 <= (R + 0.5) ** 2]
+    assert d.shape[0] == len(pts)
+    assert [tuple(p) for p in d] == pts
+
+
+def test_refined_stencils_are_refused():
+    assert oracle.las3((0.1, 0.2, 0.3), 0.44) == oracle.EREACH
+    assert oracle.las3((0.1, 0.2, 0.3), 0.45).shape[0] > 0
+
+
+# --------------------------------------------------------------------------
+# collision
+# --------------------------------------------------------------------------
+def _random_populations(seed, q=60):
+    g = np.random.Generator(np.random.PCG64(seed))
+    c = g.integers(-3, 4, size=(q, 3)).astype(float)
+    f = g.uniform(0.01, 1.0, q)
+    gp = g.uniform(0.01, 1.0, q)
+    return c, f, gp
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_central_moments_match_their_definition(seed):
+    """Raw moments of a random discrete population set, then Eq. (IIB9) must
+    give the central moments summed directly about u (Eq. IIB8 written out):
+    P_ab = sum f c~_a c~_b - rho RT delta, Q_g = sum f |c~|^2 c~_g, g0 =
+    sum g - rho K RT, h_g = sum g c~_g."""
+    c, f, gp = _random_populations(seed)
+    K = 2.0
+    rho = f.sum()
+    u = (f[:, None] * c).sum(0) / rho
+    M = [rho, *(f[:, None] * c).sum(0)]
+    for a in range(3):
+        for b in range(a, 3):
+            M.append((f * c[:, a] * c[:, b]).sum())
+    cc = (c ** 2).sum(1)
+    M += list((f[:, None] * cc[:, None] * c).sum(0))
+    M += [gp.sum(), *(gp[:, None] * c).sum(0)]
+    M = np.array(M)
+    cfg = li._base_cfg3(1, 1, 1)
+    cfg["K"] = K
+    out = oracle.collide3(cfg, M)
+    assert out["status"] == 0
+    ct = c - u
+    RT = ((f[:, None] * ct ** 2).sum() + gp.sum()) / (rho * (3 + K))
+    assert abs(out["RT"] - RT) < 1e-13 * RT
+    P = np.einsum("i,ia,ib->ab", f, ct, ct) - rho * RT * np.eye(3)
+    Q = np.einsum("i,i,ig->g", f, (ct ** 2).sum(1), ct)
+    h = np.einsum("i,ig->g", gp, ct)
+    scale = rho * RT
+    assert np.abs(out["P"] - P).max() < 1e-12 * scale
+    assert np.abs(out["Q"] - Q).max() < 1e-12 * scale * np.sqrt(RT)
+    assert abs(out["g0"] - (gp.sum() - rho * K * RT)) < 1e-12 * scale
+    assert np.abs(out["h"] - h).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_collision_of_a_z_independent_state_matches_2d(seed):
+    """A 2D state embedded in 3D (no z motion, the z degree of freedom in
+    equilibrium, K_3 = K_2 - 1 so that D + K is unchanged) has the 2D
+    non-equilibrium moments, Knudsen number and, for omega_f = omega_b (the
+    bulk/shear split depends on D), the 2D second-order fluon targets."""
+    c, f, gp = _random_populations(seed)
+    c2 = c[:, :2]
+    K2 = 3.0
+    rho = f.sum()
+    u2 = (f[:, None] * c2).sum(0) / rho
+    M2 = np.array([rho, *(f[:, None] * c2).sum(0), (f * c2[:, 0] ** 2).sum(), (f * c2[:, 0] * c2[:, 1]).sum(),
+                   (f * c2[:, 1] ** 2).sum(), *(f[:, None] * (c2 ** 2).sum(1)[:, None] * c2).sum(0), gp.sum(),
+                   *(gp[:, None] * c2).sum(0)])
+    cfg2 = li._base_cfg(2, 1, 1, K2)
+    cfg2.update({"omega_f": 1.3, "omega_b": 1.3, "omega_h": 0.7})
+    o2 = oracle.collide(cfg2, M2)
+    RT = o2["RT"]
+    # embed: add rho RT to M_zz (and RT to the energy per unit mass via MD),
+    # move rho RT out of the phonon energy
+    M3 = np.array([rho, M2[1], M2[2], 0.0, M2[3], M2[4], 0.0, M2[5], 0.0, rho * RT,
+                   M2[6] + rho * RT * u2[0], M2[7] + rho * RT * u2[1], 0.0,
+                   M2[8] - rho * RT, M2[9] - rho * RT * u2[0], M2[10] - rho * RT * u2[1], 0.0])
+    cfg3 = li._base_cfg3(1, 1, 1, K2 - 1.0)
+    cfg3.update({"omega_f": 1.3, "omega_b": 1.3, "omega_h": 0.7})
+    o3 = oracle.collide3(cfg3, M3)
+    assert abs(o3["RT"] - RT) < 1e-13 * RT
+    s = rho * RT
+    assert np.abs(o3["P"][:2, :2] - np.array([[o2["Pxx"], o2["Pxy"]], [o2["Pxy"], o2["Pyy"]]])).max() < 1e-12 * s
+    assert np.abs(o3["P"][2]).max() < 1e-12 * s
+    assert np.abs(o3["Q"][:2] - [o2["Qx"], o2["Qy"]]).max() < 1e-12 * s
+    assert abs(o3["g0"] - o2["g0"]) < 1e-12 * s
+    assert np.abs(o3["h"][:2] - [o2["hx"], o2["hy"]]).max() < 1e-12 * s
+    assert abs(o3["kn"] - o2["kn"]) < 1e-12 * max(o2["kn"], 1e-30)
+    # second-order fluon targets xx, xy, yy (the phonon targets are normalised
+    # by rho K RT, which moves with the z degree of freedom)
+    assert np.abs(o3["m"][[4, 5, 7]] - o2["m"][[3, 4, 5]]).max() < 1e-12 * RT
+
+
+def test_third_order_split_and_phonon_targets():
+    """Eq. (IIB14) with D = 3: M~_{aa|g} = (1 + 2 delta_ag)/5 Q_g, and the
+    pieces of one g add up to Q_g; Eq. (IIB17): second-order phonon targets
+    RT delta."""
+    cfg, prim = li.smooth_periodic3(5, n=4, amp=0.3)
+    cfg.update({"omega_f": 1.2, "omega_b": 1.0, "omega_h": 0.6, "kn_limiter": 0})
+    m = mom3(cfg, prim)[:, 7].copy()
+    m[10] += 0.02; m[11] -= 0.03; m[12] += 0.01      # heat flux out of equilibrium
+    o = oracle.collide3(cfg, m)
+    t = o["m"][10:].reshape(3, 3)                    # rows a, columns g
+    Q = o["Q"] * (1 - 0.6) / o["rho"]
+    for g in range(3):
+        assert abs(t[:, g].sum() - Q[g]) < 1e-14
+        for a in range(3):
+            assert abs(t[a, g] - (3.0 if a == g else 1.0) / 5.0 * Q[g]) < 1e-15
+    assert np.abs(o["n"][4:] - o["RT"] * np.array([1, 0, 0, 1, 0, 1])).max() == 0.0
+
+
+# --------------------------------------------------------------------------
+# reconstruction
+# --------------------------------------------------------------------------
+def test_equilibrium_reconstruction_converges_fast():
+    """Eq. (IID13) starts next to the equilibrium solution: fewer than 5
+    Newton updates (Sec. II.D) and the populations carry the targets."""
+    for u, RT in [((0.2, -0.4, 0.1), 1.0), ((3.3, 0.5, -1.2), 2.5)]:
+        d = oracle.las3(u, RT)
+        tf = np.zeros(19); tf[0] = 1.0; tf[4] = tf[7] = tf[9] = RT
+        st, lam, pop, it = oracle.epr3(d, u, RT, tf)
+        assert st == 0 and it < 5
+        ct = d - np.array(u)
+        assert abs(pop.sum() - 1) < 1e-12
+        assert np.abs((pop[:, None] * ct).sum(0)).max() < 1e-12
+        assert abs((pop * ct[:, 0] ** 2).sum() - RT) < 1e-11 * RT
+
+
+@pytest.mark.parametrize("nb", [19, 10])
+def test_reconstruction_matches_an_independent_minimiser(nb):
+    """Eqs. (IID7-11): the multipliers minimise the convex dual sum f + l.m;
+    BFGS on the same dual (scipy) lands on the same multipliers."""
+    u, RT = (0.35, -0.15, 0.2), 0.9
+    d = oracle.las3(u, RT)
+    ct = (d - np.array(u)).astype(float)
+    x, y, z = ct.T
+    T = np.stack([np.ones_like(x), x, y, z, x * x, x * y, x * z, y * y, y * z, z * z,
+                  x ** 3, x * x * y, x * x * z, x * y * y, y ** 3, y * y * z, x * z * z, y * z * z, z ** 3], 1)[:, :nb]
+    tgt = np.zeros(nb); tgt[0] = 1.0; tgt[4] = 1.05 * RT; tgt[5] = 0.03; tgt[7] = 0.97 * RT; tgt[9] = 0.98 * RT
+    if nb == 19:
+        tgt[10] = 0.02; tgt[14] = -0.015; tgt[16] = 0.01
+    st, lam, pop, it = oracle.epr3(d, u, RT, tgt)
+    assert st == 0
+    sc = np.array([1, *[np.sqrt(RT)] * 3, *[RT] * 6, *[RT ** 1.5] * 9])[:nb]
+
+    def dual(ls):
+        lmb = ls / sc
+        f = np.exp(-(1 + T @ lmb))
+        return f.sum() + lmb @ tgt, (-(T * f[:, None]).sum(0) + tgt) / sc
+
+    l0 = oracle.epr3_initial(nb, RT) * sc
+    res = minimize(dual, l0, jac=True, method="BFGS", options={"gtol": 1e-13, "maxiter": 5000})
+    assert np.abs(res.x / sc - lam).max() < 1e-6 * np.abs(lam).max()
+    assert np.abs(T.T @ pop - tgt).max() < 1e-12
+
+
+# --------------------------------------------------------------------------
+# whole step
+# --------------------------------------------------------------------------
+def test_uniform_flow_is_invariant():
+    cfg, prim = li.smooth_periodic3(0, n=3, amp=0.0, u=(1.3, -0.7, 0.45), RT=1.4)
+    m = mom3(cfg, prim)
+    st, out, stats, done = oracle.step(cfg, m, 2)
+    assert st == 0
+    assert np.abs(out - m).max() < 1e-12 * np.abs(m).max()
+
+
+def test_conservation():
+    cfg, prim = li.smooth_periodic3(1, n=5, ny=4, nz=3, amp=0.08)
+    m = mom3(cfg, prim)
+    st, out, stats, done = oracle.step(cfg, m, 2)
+    assert st == 0
+    E = lambda a: a[4] + a[7] + a[9] + a[13]
+    for k in range(4):
+        assert abs(out[k].sum() - m[k].sum()) < 1e-13 * m[0].sum()
+    assert abs(E(out).sum() / E(m).sum() - 1) < 1e-13
+    assert stats["it_max_f"] < 8 and stats["q_min"] > 0
+
+
+def _fields(m, shape):
+    return m.reshape(17, *shape)
+
+
+def test_integer_galilean_boost():
+    """Adding an integer velocity U to every cell shifts every stencil by U,
+    so the boosted step equals the original one translated by U cells and
+    boosted (the stencil moves with u, Eq. IIC6)."""
+    cfg, prim = li.smooth_periodic3(2, n=4, ny=3, nz=3, amp=0.05)
+    U = (1, -2, 1)
+    m = mom3(cfg, prim)
+    p2 = dict(prim, ux=prim["ux"] + U[0], uy=prim["uy"] + U[1], uz=prim["uz"] + U[2])
+    # the boosted non-equilibrium state: boost the raw moments of the start state exactly
+    st, a, _, _ = oracle.step(cfg, m, 1)
+    st2, b, _, _ = oracle.step(cfg, mom3(cfg, p2), 1)
+    assert st == 0 and st2 == 0
+    rho, ux, uy, uz, RT = _prims(a)
+    shape = (3, 3, 4)
+    shifted = [np.roll(f.reshape(shape), (U[2], U[1], U[0]), axis=(0, 1, 2)).ravel() for f in
+               (rho, ux + U[0], uy + U[1], uz + U[2], RT)]
+    rb = _prims(b)
+    for x, y in zip(rb, shifted):
+        assert np.abs(x - y).max() < 1e-11
+
+
+def _prims(m):
+    rho = m[0]
+    u = m[1:4] / rho
+    RT = ((m[4] + m[7] + m[9] + m[13]) / rho - (u ** 2).sum(0)) / 5.0
+    return rho, u[0], u[1], u[2], RT
+
+
+@pytest.mark.parametrize("perm", [(1, 0, 2), (2, 1, 0), (0, 2, 1)])
+def test_axis_permutation_symmetry(perm):
+    """Exchanging two axes of the input exchanges them in the result (the
+    ball, the basis and the collision are symmetric in the axes)."""
+    cfg, prim = li.smooth_periodic3(3, n=4, amp=0.06)
+    m = mom3(cfg, prim)
+    st, out, _, _ = oracle.step(cfg, m, 1)
+    assert st == 0
+    ax = {0: "ux", 1: "uy", 2: "uz"}
+    arr_axes = (2 - perm[2], 2 - perm[1], 2 - perm[0])   # field arrays are [z][y][x]
+    p2 = {"rho": prim["rho"].transpose(arr_axes), "RT": prim["RT"].transpose(arr_axes)}
+    for i in range(3):
+        p2[ax[i]] = prim[ax[perm[i]]].transpose(arr_axes)
+    st2, out2, _, _ = oracle.step(cfg, mom3(cfg, p2), 1)
+    assert st2 == 0
+    r1, r2 = _prims(out), _prims(out2)
+    f1 = [x.reshape(4, 4, 4).transpose(arr_axes) for x in r1]
+    vel1 = {0: f1[1], 1: f1[2], 2: f1[3]}
+    assert np.abs(r2[0].reshape(4, 4, 4) - f1[0]).max() < 1e-12
+    assert np.abs(r2[4].reshape(4, 4, 4) - f1[4]).max() < 1e-12
+    for i in range(3):
+        assert np.abs(r2[1 + i].reshape(4, 4, 4) - vel1[perm[i]]).max() < 1e-12
+
+
+def test_mirror_symmetry():
+    """Reflecting the input in z (x_z -> -x_z, u_z -> -u_z) reflects the
+    result: the ball and the basis are symmetric under the reflection."""
+    cfg, prim = li.smooth_periodic3(6, n=4, amp=0.06)
+    st, out, _, _ = oracle.step(cfg, mom3(cfg, prim), 1)
+    p2 = {k: v[::-1].copy() for k, v in prim.items()}
+    p2["uz"] = -p2["uz"]
+    st2, out2, _, _ = oracle.step(cfg, mom3(cfg, p2), 1)
+    assert st == 0 and st2 == 0
+    r1, r2 = _prims(out), _prims(out2)
+    for i, sign in enumerate((1, 1, 1, -1, 1)):
+        assert np.abs(r2[i].reshape(4, 4, 4) - sign * r1[i].reshape(4, 4, 4)[::-1]).max() < 1e-12
+
+
+def _shear_nu(L, RT, nu, u0):
+    cfg, prim = li.shear_wave3(L=L, RT=RT, nu=nu, u0=u0, amp=1e-4)
+    m = mom3(cfg, prim)
+    k = 2 * np.pi / L
+    t = int(round(1.0 / (nu * k * k)))     # Fourier number 1
+    st, out, _, _ = oracle.step(cfg, m, t)
+    assert st == 0
+    uy = out[2] / out[0]
+    x = np.arange(L) + 0.5
+    amp = np.hypot((uy * np.cos(k * x)).sum(), (uy * np.sin(k * x)).sum()) * 2 / L
+    return -np.log(amp / 1e-4) / (k * k * t)
+
+
+def test_shear_viscosity_3d():
+    """Transverse shear wave (Sec. IV.A) in 3D.  At rest the decay converges
+    to nu = RT (1/omega_f - 1/2) (Eq. C8a) under refinement (second order in
+    1/L); on the paper's worst-case mean flow u0 = 1/2 (Sec. IV.A) it stays
+    within the +-10 % band the paper draws around the target."""
+    e16 = _shear_nu(16, 1.0, 0.1, 0.0) / 0.1 - 1
+    e32 = _shear_nu(32, 1.0, 0.1, 0.0) / 0.1 - 1
+    assert abs(e32) < 0.03 and abs(e32) < abs(e16) / 3, (e16, e32)
+    for RT in (1.0, 2.0):
+        e = _shear_nu(32, RT, 0.1, 0.5) / 0.1 - 1
+        assert abs(e) < 0.10, (RT, e)
