@@ -144,6 +144,19 @@ typedef struct {
     /* Tangential (x) velocity u_w of the LELBM_BC_WALL wall on each face
      * (xlo, xhi, ylo, yhi); entries of other faces must be 0. */
     double wall_u[4];
+    /* Cells along z (dim = 3; 0 or 1 otherwise).  Three dimensions: 17 stored
+     * values per cell, SoA [17][nz][ny][nx] in the order M0 Mx My Mz Mxx Mxy
+     * Mxz Myy Myz Mzz MDx MDy MDz G0 Gx Gy Gz (Sec. II.E: 13 + 4 values); 19
+     * fluon constraints (1, the first and second moments and the per-axis
+     * third-order pieces M~_{aa|g} of Eq. IIB14) and 10 phonon constraints.
+     * Supported: periodic boxes (bc all LELBM_BC_PERIODIC, z periodic too),
+     * LELBM_GUESS_EQ, both precisions, unrefined stencils (RT > 4/9; refined
+     * ones and radii above 64 fail the step with LELBM_EREACH).  Not in 3D:
+     * solids, walls, point sources, the learned guess and harvest, and
+     * lelbm_step_noalloc (LELBM_EINVAL); the record scratch holds a step's
+     * records whole (lelbm_set_scratch_budget has no effect).  lelbm_stats
+     * sum[] holds mass, x and y momentum and the energy trace. */
+    int nz;
 } lelbm_params;
 
 /* Statistics accumulated over the steps of one lelbm_step call.  Newton
@@ -177,14 +190,22 @@ typedef struct {
                                          holding points x reconstruction passes */
 } lelbm_stats;
 
-/* Number of stored moments per cell: 6 (1D) or 11 (2D); -1 for other dim. */
+/* Number of stored moments per cell: 6 (1D), 11 (2D) or 17 (3D); -1 for
+ * other dim. */
 int lelbm_num_moments(int dim);
 
 /* Equilibrium raw moments of primitive fields (Eqs. IIB7a-d, App. A Eqs. A3,
  * A7): out[k*n + i] for k < lelbm_num_moments(dim).  uy is ignored in 1D and
- * may be NULL there.  Host pointers; EINVAL on bad dim or n < 0. */
+ * may be NULL there.  Host pointers; EINVAL on dim other than 1 or 2 (see
+ * lelbm_moments_from_primitives3) or n < 0. */
 int lelbm_moments_from_primitives(int dim, double K, long n, const double *rho, const double *ux,
                                   const double *uy, const double *RT, double *out);
+
+/* The same in 3D: out[k*n + i] for the 17 moments of lelbm_params.nz's
+ * layout (App. A with D = 3: M_Dg = rho (|u|^2 + 5 RT) u_g).  Host pointers;
+ * EINVAL on a NULL pointer or n < 0. */
+int lelbm_moments_from_primitives3(double K, long n, const double *rho, const double *ux, const double *uy,
+                                   const double *uz, const double *RT, double *out);
 
 /* Create a context from host moments (SoA, nmom*nx*ny doubles).  hip_stream
  * is a hipStream_t (NULL = default stream).  On success *out owns all device

@@ -42,6 +42,7 @@ class Params(ctypes.Structure):
         ("src_x", ctypes.c_int), ("src_y", ctypes.c_int),
         ("src_rate", ctypes.c_double), ("src_omega", ctypes.c_double), ("src_t0", ctypes.c_double),
         ("wall_u", ctypes.c_double * 4),
+        ("nz", ctypes.c_int),
     ]
 
 
@@ -82,6 +83,7 @@ def lib():
         L.lelbm_num_moments.argtypes = [ctypes.c_int]
         L.lelbm_moments_from_primitives.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_long,
                                                     dp, dp, dp, dp, dp]
+        L.lelbm_moments_from_primitives3.argtypes = [ctypes.c_double, ctypes.c_long, dp, dp, dp, dp, dp, dp]
         L.lelbm_create.argtypes = [ctypes.POINTER(Params), dp, vp, ctypes.POINTER(vp)]
         L.lelbm_create_device.argtypes = [ctypes.POINTER(Params), vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
         L.lelbm_step.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Stats)]
@@ -144,6 +146,14 @@ def moments_from_primitives(dim, K, rho, ux, uy, RT):
     return out
 
 
+def moments_from_primitives3(K, rho, ux, uy, uz, RT):
+    """3D equilibrium raw moments (SoA [17][n]) of primitive fields."""
+    f = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (rho, ux, uy, uz, RT)]
+    out = np.zeros((17, f[0].size))
+    _check(lib().lelbm_moments_from_primitives3(K, f[0].size, *[_dp(a) for a in f], _dp(out)))
+    return out
+
+
 def make_params(cfg, precision=FP64, guess=GUESS_EQ):
     p = Params()
     p.dim, p.nx, p.ny = cfg["dim"], cfg["nx"], cfg.get("ny", 1)
@@ -157,7 +167,7 @@ def make_params(cfg, precision=FP64, guess=GUESS_EQ):
     p.kn_lo, p.kn_hi, p.omega_H = cfg.get("kn_lo", -2.0), cfg.get("kn_hi", -1.0), cfg.get("omega_H", 1.0)
     p.precision = precision
     p.guess = guess
-    for i, b in enumerate(cfg.get("bc", ["periodic"] * 4)):
+    for i, b in enumerate(cfg.get("bc", ["periodic"] * 4)[:4]):
         p.bc[i] = BC[b] if isinstance(b, str) else int(b)
     p.pad = cfg.get("pad", 0)
     p.in_rho = cfg.get("in_rho", 1.0)
@@ -177,6 +187,7 @@ def make_params(cfg, precision=FP64, guess=GUESS_EQ):
         p.src_rate, p.src_omega, p.src_t0 = src["rate"], src["omega"], src.get("t0", 0.0)
     for i, v in enumerate(cfg.get("wall_u", (0.0, 0.0, 0.0, 0.0))):
         p.wall_u[i] = v
+    p.nz = cfg.get("nz", 0)
     return p
 
 
@@ -196,7 +207,7 @@ class Lelbm:
         self.cfg = cfg
         self.params = make_params(cfg, precision, guess)
         self.nmom = num_moments(cfg["dim"])
-        self.shape = (self.nmom, cfg.get("ny", 1) * cfg["nx"])
+        self.shape = (self.nmom, (cfg.get("nz", 1) if cfg["dim"] == 3 else 1) * cfg.get("ny", 1) * cfg["nx"])
         self._h = ctypes.c_void_p()
         self._stream = _stream_handle(stream)
         if hasattr(moments, "data_ptr"):           # torch tensor on the device

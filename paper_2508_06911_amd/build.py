@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblelbm.so")
-SOURCES = ["lelbm_api.hip", "lelbm_kernels.hip", "lelbm_mlp.hip", "lelbm_plan.cpp"]
+SOURCES = ["lelbm_api.hip", "lelbm_kernels.hip", "lelbm_3d.hip", "lelbm_mlp.hip", "lelbm_plan.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

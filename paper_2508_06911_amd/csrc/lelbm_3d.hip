@@ -1,0 +1,937 @@
+// The LELBM time step in three dimensions (D = 3) on periodic boxes: 17
+// stored values per cell (13 fluon moments and 4 phonon moments, Sec. II.E),
+// 19 fluon and 10 phonon constraints in the reconstruction.
+//
+// One step = k3_prepare (macroscopic variables, Eq. IIB6; stencil radius,
+// Eq. IIC6; per-tile boxes of the record scratch) -> k3_scan (record offsets)
+// -> k3_epr (collision, Eqs. IIB9-IIB18 and App. D; Newton-Cholesky
+// reconstruction, Eqs. IID7-IID13; moment fractions of Eq. IIE3a into the
+// records) -> k3_gather (moment streaming, Eq. IIE3b, as a deterministic
+// gather).
+//
+// Cells are taken in tiles of 4 x 4 x 4 (one wavefront, one lane per cell).
+// A tile's records hold, per displacement slot of the union of its cells'
+// stencil boxes, the pair (w_f, w_g) of each of its 64 cells, so the lanes of
+// a wavefront that read one displacement read 64 consecutive pairs.
+//
+// Scope: fully periodic boxes; unrefined stencils (RT > 4/9, N_r = 0 in
+// Eq. IIC9) with radii up to 64; the Newton start of Eq. (IID13).  Other
+// cells fail the step with LELBM_EREACH.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <string.h>
+
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "lelbm_internal.h"
+
+namespace lelbm {
+namespace d3 {
+
+constexpr int NF = 19, NG = 10, NMF = 84, NMG = 35, NM = 17, TN = 64, TE = 4;
+constexpr int MAX_R3 = 64;
+
+// Exponents (a, b, c) of x^a y^b z^c of the fluon basis: 1, x, y, z, xx, xy,
+// xz, yy, yz, zz, then the per-axis third-order pieces M~_{aa|g} (Eq. IIB14)
+// (xx|x), (xx|y), (xx|z), (yy|x), (yy|y), (yy|z), (zz|x), (zz|y), (zz|z);
+// the phonon basis is the first ten.
+__host__ __device__ constexpr int bexp(int j, int k) {
+    constexpr int t[NF][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0}, {1, 1, 0}, {1, 0, 1},
+                              {0, 2, 0}, {0, 1, 1}, {0, 0, 2}, {3, 0, 0}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0},
+                              {0, 3, 0}, {0, 2, 1}, {1, 0, 2}, {0, 1, 2}, {0, 0, 3}};
+    return t[j][k];
+}
+__host__ __device__ constexpr int border(int j) { return bexp(j, 0) + bexp(j, 1) + bexp(j, 2); }
+// Monomials x^a y^b z^c of total degree d are numbered degree-major; inside
+// a degree by b + c, then by c.  Degrees <= 6 (fluon sums) take 84 numbers,
+// degrees <= 4 (phonon sums) the first 35.
+__host__ __device__ constexpr int mono(int a, int b, int c) {
+    return (a + b + c) * (a + b + c + 1) * (a + b + c + 2) / 6 + (b + c) * (b + c + 1) / 2 + c;
+}
+__host__ __device__ constexpr int hidx(int i, int j) {
+    return mono(bexp(i, 0) + bexp(j, 0), bexp(i, 1) + bexp(j, 1), bexp(i, 2) + bexp(j, 2));
+}
+
+struct Desc3 {
+    double *rho, *ux, *uy, *uz, *rt;   // [n]
+    int *r;                            // [n] radius R, -1: no population
+};
+
+struct Tile3 {
+    int ox, oy, oz, wx, wy, wz;   // slot box (first displacement, extents)
+    long long size;               // elements (wx wy wz x 64 cells x 2)
+    long long base;               // first element in the scratch
+};
+
+struct Buf3 {
+    double *mom[2];               // [17][n] FP64 state
+    Desc3 d;
+    Tile3 *tiles;                 // [ntiles]
+    void *scratch;
+    long long scratch_cap;        // elements
+    Flags *flags;
+    DevStats *stats;
+    int *maxreach;                // max over cells of max |round(u_a)| + R + 1
+    long long *total;             // record elements of the step (k3_scan)
+    double *partial;              // block sums of the conserved totals
+};
+
+struct G3 {
+    int nx, ny, nz;
+    long long n;
+    int tnx, tny, tnz, ntiles;
+};
+
+// First failure of a step: its code, step and reason; the smallest failing cell.
+__device__ inline void flag3(Flags *fl, int code, int step, long long node, int detail = 0, int species = -1,
+                             double residual = 0.0) {
+    if (atomicCAS(&fl->err, 0, code) == 0) {
+        fl->step = step;
+        fl->detail = detail;
+        fl->species = species;
+        fl->residual = residual;
+    }
+    if (fl->err == code) atomicMin((unsigned long long *)&fl->node, (unsigned long long)node);
+}
+
+__global__ void k3_reset_flags(Flags *f) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        f->err = 0; f->step = -1; f->node = LLONG_MAX; f->need = 0;
+        f->detail = 0; f->species = -1; f->residual = 0.0; f->reach = 0; f->total = 0;
+    }
+}
+
+__device__ inline int wrapi(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// The decisions that define a stencil are taken without FMA contraction and
+// in the order the CPU oracle uses, so that both select the same points.
+__device__ inline bool in_ball(double cx, double cy, double cz, double ux, double uy, double uz, double rr) {
+#pragma clang fp contract(off)
+    const double ex = cx - ux, ey = cy - uy, ez = cz - uz;
+    return ex * ex + ey * ey + ez * ez <= rr * rr;
+}
+__device__ inline int radius3(double RT, double n_conf, int r_min) {
+#pragma clang fp contract(off)
+    int R = (int)floor(n_conf * sqrt(RT) + 0.5);
+    return R > r_min ? R : r_min;
+}
+__device__ inline int levels3(double RT) {
+#pragma clang fp contract(off)
+    return (int)floor(1.0 / (3.0 * sqrt(RT)) + 0.5);
+}
+
+// Integer cx of row (cy, cz) inside the ball, from the analytic estimate
+// corrected with the exact predicate; false if the row is empty.
+__device__ inline bool span3(int cy, int cz, double ux, double uy, double uz, double rr, int lo, int hi, int &xa,
+                             int &xb) {
+    const double ey = (double)cy - uy, ez = (double)cz - uz;
+    const double rem = rr * rr - ey * ey - ez * ez;
+    const double w = rem > 0.0 ? sqrt(rem) : 0.0;
+    int a = (int)ceil(ux - w), b = (int)floor(ux + w);
+    a = a < lo ? lo : (a > hi ? hi : a);
+    b = b > hi ? hi : (b < lo ? lo : b);
+    auto in = [&](int cx) { return in_ball((double)cx, (double)cy, (double)cz, ux, uy, uz, rr); };
+    while (a > lo && in(a - 1)) a--;
+    while (a <= b && !in(a)) a++;
+    while (b < hi && in(b + 1)) b++;
+    while (b >= a && !in(b)) b--;
+    xa = a;
+    xb = b;
+    return a <= b;
+}
+
+// Macroscopic variables as the oracle forms them (Eq. IIB6 with D = 3).
+__device__ inline void macro3(const double *mom, long long n, long long s, double K, double &rho, double &ux,
+                              double &uy, double &uz, double &RT) {
+#pragma clang fp contract(off)
+    rho = mom[s];
+    ux = mom[n + s] / rho;
+    uy = mom[2 * n + s] / rho;
+    uz = mom[3 * n + s] / rho;
+    double uu = ux * ux;
+    uu = uu + uy * uy;
+    uu = uu + uz * uz;
+    RT = ((mom[4 * n + s] + mom[7 * n + s] + mom[9 * n + s] + mom[13 * n + s]) / rho - uu) / (3.0 + K);
+}
+
+// ---------------------------------------------------------------------------
+// k3_prepare: descriptors, tile boxes, reach
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k3_prepare(G3 g, Phys ph, const double *mom, Buf3 b, int step) {
+    if (b.flags->err) return;
+    const int t = blockIdx.x, l = threadIdx.x;
+    const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
+    const int x = tx * TE + (l & 3), y = ty * TE + ((l >> 2) & 3), z = tz * TE + (l >> 4);
+    const bool valid = x < g.nx && y < g.ny && z < g.nz;
+    int lo[3] = {1 << 29, 1 << 29, 1 << 29}, hi[3] = {-(1 << 29), -(1 << 29), -(1 << 29)};
+    int reach = 0;
+    if (valid) {
+        const long long s = ((long long)z * g.ny + y) * g.nx + x;
+        double rho, ux, uy, uz, RT;
+        macro3(mom, g.n, s, ph.K, rho, ux, uy, uz, RT);
+        const bool ok = rho > 0.0 && isfinite(rho) && RT > 0.0 && isfinite(RT) && isfinite(ux) && isfinite(uy) &&
+                        isfinite(uz);
+        int R = -1;
+        if (!ok) {
+            flag3(b.flags, LELBM_EEPR, step, s);
+        } else {
+            R = radius3(RT, ph.n_conf, ph.r_min);
+            const double um = fmax(fabs(ux), fmax(fabs(uy), fabs(uz)));
+            if (levels3(RT) > 0 || R > MAX_R3 || !(um <= MAX_SPEED)) {
+                flag3(b.flags, LELBM_EREACH, step, s);
+                R = -1;
+            } else {
+                const int ub[3] = {(int)floor(ux + 0.5), (int)floor(uy + 0.5), (int)floor(uz + 0.5)};
+                for (int a = 0; a < 3; a++) {
+                    lo[a] = ub[a] - R - 1;
+                    hi[a] = ub[a] + R + 1;
+                    reach = max(reach, abs(ub[a]) + R + 1);
+                }
+            }
+        }
+        b.d.rho[s] = rho; b.d.ux[s] = ux; b.d.uy[s] = uy; b.d.uz[s] = uz; b.d.rt[s] = RT; b.d.r[s] = R;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        for (int a = 0; a < 3; a++) {
+            lo[a] = min(lo[a], __shfl_xor(lo[a], off));
+            hi[a] = max(hi[a], __shfl_xor(hi[a], off));
+        }
+        reach = max(reach, __shfl_xor(reach, off));
+    }
+    if (l == 0) {
+        Tile3 ti;
+        if (lo[0] > hi[0]) {
+            ti.ox = ti.oy = ti.oz = 0; ti.wx = ti.wy = ti.wz = 0; ti.size = 0;
+        } else {
+            ti.ox = lo[0]; ti.oy = lo[1]; ti.oz = lo[2];
+            ti.wx = hi[0] - lo[0] + 1; ti.wy = hi[1] - lo[1] + 1; ti.wz = hi[2] - lo[2] + 1;
+            ti.size = (long long)ti.wx * ti.wy * ti.wz * TN * 2;
+        }
+        ti.base = 0;
+        b.tiles[t] = ti;
+        if (reach > __hip_atomic_load(b.maxreach, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(b.maxreach, reach);
+    }
+}
+
+// Exclusive scan of the tile sizes (one workgroup) -> record offsets; the
+// total goes to b.total.
+__global__ void __launch_bounds__(1024) k3_scan(int ntiles, Buf3 b) {
+    __shared__ long long part[1024];
+    if (b.flags->err) {
+        if (threadIdx.x == 0) *b.total = 0;
+        return;
+    }
+    const int per = (ntiles + 1023) / 1024;
+    const int t0 = threadIdx.x * per, t1 = min(ntiles, t0 + per);
+    long long s = 0;
+    for (int t = t0; t < t1; t++) s += b.tiles[t].size;
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long acc = 0;
+        for (int i = 0; i < 1024; i++) {
+            const long long v = part[i];
+            part[i] = acc;
+            acc += v;
+        }
+        *b.total = acc;
+    }
+    __syncthreads();
+    long long acc = part[threadIdx.x];
+    for (int t = t0; t < t1; t++) {
+        b.tiles[t].base = acc;
+        acc += b.tiles[t].size;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// collision (Eqs. IIB9-IIB18, App. D) with D = 3
+// ---------------------------------------------------------------------------
+__device__ inline void collide3(const Phys &ph, const double *mom, long long n, long long s, double rho, double ux,
+                                double uy, double uz, double RT, double *mf, double *mg, double &kn, int &lim) {
+    const double K = ph.K;
+    const double u[3] = {ux, uy, uz};
+    const double uu = ux * ux + uy * uy + uz * uz;
+    auto M = [&](int k) { return mom[(long long)k * n + s]; };
+    // Eq. (IIB9a); second-moment slot of (a, b)
+    auto sec = [](int a, int c) { return a == 0 ? 4 + c : (a == 1 ? (c == 0 ? 5 : 6 + c) : (c == 0 ? 6 : 7 + c)); };
+    double P[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) P[a][c] = M(sec(a, c)) - rho * (u[a] * u[c] + (a == c ? RT : 0.0));
+    const double trP = P[0][0] + P[1][1] + P[2][2];
+    double Q[3];
+#pragma unroll
+    for (int g = 0; g < 3; g++) {
+        const double sp = u[0] * P[0][g] + u[1] * P[1][g] + u[2] * P[2][g];
+        Q[g] = M(10 + g) - 2.0 * sp - u[g] * trP - rho * (uu + 5.0 * RT) * u[g];
+    }
+    const double G0 = M(13);
+    const double g0 = G0 - rho * K * RT;
+    double h[3];
+#pragma unroll
+    for (int g = 0; g < 3; g++) h[g] = M(14 + g) - u[g] * G0;
+    // Eq. (D2)
+    double sP = 0.0, sQ = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) sP += fabs(P[a][c]);
+        sQ += fabs(Q[a]) + fabs(h[a]);
+    }
+    const double knA = (sP + fabs(g0)) / (rho * (3.0 + K) * RT);
+    const double knB = sQ / (rho * (5.0 + K) * RT * sqrt(RT));
+    kn = fmax(knA, knB);
+    double of = ph.omega_f, ob = ph.omega_b, oh = ph.omega_h;
+    lim = 0;
+    if (ph.kn_limiter && kn >= ph.kn_lo_lin) {
+        // Eq. (D3) as worded after it: linear in log10 Kn between the thresholds
+        auto lw = [&](double om) {
+            if (kn > ph.kn_hi_lin) return ph.omega_H;
+            return (ph.omega_H - om) / (ph.kn_hi - ph.kn_lo) * (log10(kn) - ph.kn_lo) + om;
+        };
+        of = lw(of); ob = lw(ob); oh = lw(oh);
+        lim = (of != ph.omega_f) || (ob != ph.omega_b) || (oh != ph.omega_h);
+    }
+    // Eqs. (IIB10-11, IIB14, IIB16-18)
+    const double bulk = -g0 / 3.0, irho = 1.0 / rho;
+    mf[0] = 1.0; mf[1] = 0.0; mf[2] = 0.0; mf[3] = 0.0;
+    int k = 4;
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int c = a; c < 3; c++) {
+            const double bl = a == c ? bulk : 0.0;
+            mf[k++] = (a == c ? RT : 0.0) + ((1.0 - of) * (P[a][c] - bl) + (1.0 - ob) * bl) * irho;
+        }
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int g = 0; g < 3; g++) mf[10 + 3 * a + g] = (1.0 - oh) * ((a == g ? 3.0 : 1.0) / 5.0) * Q[g] * irho;
+    const double rKT = rho * K * RT;
+    mg[0] = 1.0 + (1.0 - ob) * g0 / rKT;
+#pragma unroll
+    for (int g = 0; g < 3; g++) mg[1 + g] = (1.0 - oh) * h[g] / rKT;
+    mg[4] = RT; mg[5] = 0.0; mg[6] = 0.0; mg[7] = RT; mg[8] = 0.0; mg[9] = RT;
+}
+
+// ---------------------------------------------------------------------------
+// Newton state of one species (registers), Sec. II.D: damped Newton on the
+// convex dual (Armijo backtracking while the decrement exceeds 1e-8), the
+// scaled residual as stop test, the stalled-residual rule, one polishing
+// update after the stop.
+// ---------------------------------------------------------------------------
+template <int NB> struct Sp3 {
+    double lam[NB], del[NB];
+    double t, dec, phi, res, res_prev;
+    int phase, nit, ls;
+    __device__ double at(int j) const { return lam[j] + t * del[j]; }
+};
+
+template <int NB> __device__ inline void sp3_init(Sp3<NB> &sp, double RT) {
+#pragma unroll
+    for (int j = 0; j < NB; j++) { sp.lam[j] = 0.0; sp.del[j] = 0.0; }
+    sp.lam[0] = -1.0 + 1.5 * log(2.0 * M_PI * RT);     // Eq. (IID13), D = 3
+    sp.lam[4] = sp.lam[7] = sp.lam[9] = 1.0 / (2.0 * RT);
+    sp.t = 0.0; sp.dec = 0.0; sp.phi = 0.0; sp.res = 0.0; sp.res_prev = 0.0;
+    sp.phase = 0; sp.nit = 0; sp.ls = 0;
+}
+
+// Cholesky solve of A x = r with A_ij = S[hidx(i, j)] (Eq. IID11a).
+template <int NB> __device__ inline bool chol3(const double *S, const double *r, double *x) {
+    double L[NB * (NB + 1) / 2], inv[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++)
+#pragma unroll
+        for (int j = 0; j <= i; j++) L[i * (i + 1) / 2 + j] = S[hidx(i, j)];
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+#pragma unroll
+        for (int j = 0; j <= i; j++) {
+            double v = L[i * (i + 1) / 2 + j];
+#pragma unroll
+            for (int k = 0; k < j; k++) v -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+            if (i == j) {
+                if (!(v > 0.0) || !isfinite(v)) return false;
+                const double d = sqrt(v);
+                L[i * (i + 1) / 2 + i] = d;
+                inv[i] = 1.0 / d;
+            } else {
+                L[i * (i + 1) / 2 + j] = v * inv[j];
+            }
+        }
+    }
+    double y[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        double v = r[i];
+#pragma unroll
+        for (int k = 0; k < i; k++) v -= L[i * (i + 1) / 2 + k] * y[k];
+        y[i] = v * inv[i];
+    }
+#pragma unroll
+    for (int i = NB - 1; i >= 0; i--) {
+        double v = y[i];
+#pragma unroll
+        for (int k = i + 1; k < NB; k++) v -= L[k * (k + 1) / 2 + i] * x[k];
+        x[i] = v * inv[i];
+    }
+    return true;
+}
+
+// After a pass evaluated at lam + t del: accept / backtrack / step / polish.
+// 0: continue, 1: polished, negative: failure reason.
+template <int NB> __device__ inline int sp3_update(Sp3<NB> &sp, const double *S, const double *tg, const double *isc,
+                                                   double tol, int maxit) {
+    double r[NB];
+    double phit = S[0];
+    bool fin = isfinite(S[0]);
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        r[j] = S[mono(bexp(j, 0), bexp(j, 1), bexp(j, 2))] - tg[j];
+        phit += sp.at(j) * tg[j];
+        fin = fin && isfinite(r[j]);
+    }
+    fin = fin && isfinite(phit);
+    if (sp.phase == 0) {
+        if (!fin) return -1;
+        sp.phase = 1;
+    } else {
+        if (!(fin && (sp.dec <= 1e-8 || phit <= sp.phi - 1e-4 * sp.t * sp.dec))) {
+            sp.t *= 0.5;
+            if (++sp.ls > 30) return -2;
+            return 0;
+        }
+        sp.nit++;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; j++) sp.lam[j] = sp.at(j);
+    sp.t = 0.0;
+    sp.phi = phit;
+    double res = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; j++) res = fmax(res, fabs(r[j]) * isc[border(j)]);
+    sp.res = res;
+    const bool stalled = sp.nit > 0 && res <= STALL_RES && !(res < sp.res_prev);
+    sp.res_prev = res;
+    double dl[NB];
+    if (res <= tol || stalled) {
+        if (!chol3<NB>(S, r, dl)) return -3;
+#pragma unroll
+        for (int j = 0; j < NB; j++) { sp.lam[j] += dl[j]; sp.del[j] = 0.0; }
+        sp.nit++;
+        sp.phase = 2;
+        return 1;
+    }
+    if (sp.nit >= maxit) return -4;
+    if (!chol3<NB>(S, r, dl)) return -5;
+    double dec = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; j++) { sp.del[j] = dl[j]; dec += r[j] * dl[j]; }
+    sp.dec = dec;
+    sp.t = 1.0;
+    sp.ls = 0;
+    return 0;
+}
+
+// Polynomial coefficients of the exponent along a stencil row (y, z fixed):
+// sum_j l_j T_j = C0 + C1 x + C2 x^2 + C3 x^3 (fluon), D0 + D1 x + D2 x^2
+// (phonon).
+__device__ inline void row_coef(const double *lf, const double *lg, double y, double z, double *C, double *Dg) {
+    const double py[4] = {1.0, y, y * y, y * y * y}, pz[4] = {1.0, z, z * z, z * z * z};
+#pragma unroll
+    for (int a = 0; a < 4; a++) C[a] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) Dg[a] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NF; j++) C[bexp(j, 0)] += lf[j] * (py[bexp(j, 1)] * pz[bexp(j, 2)]);
+#pragma unroll
+    for (int j = 0; j < NG; j++) Dg[bexp(j, 0)] += lg[j] * (py[bexp(j, 1)] * pz[bexp(j, 2)]);
+}
+
+// ---------------------------------------------------------------------------
+// k3_epr: one lane per cell.  A pass walks the stencil row by row (z, then
+// y); along a row the exponents are polynomials in x, the populations are
+// direct exponentials and the row accumulates sum f x^a (a <= 6) and sum g
+// x^a (a <= 4), folded once per row into the monomial sums (degree <= 6 and
+// <= 4) that give the residuals and Hessians.  The final pass writes the
+// moment fractions rho f' and rho K RT g' (Eq. IIE3a).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, Buf3 b, int step) {
+    if (b.flags->err) return;
+    const int t = blockIdx.x, l = threadIdx.x;
+    const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
+    const int x = tx * TE + (l & 3), y = ty * TE + ((l >> 2) & 3), z = tz * TE + (l >> 4);
+    const bool valid = x < g.nx && y < g.ny && z < g.nz;
+    const long long s = valid ? ((long long)z * g.ny + y) * g.nx + x : 0;
+    const int R = valid ? b.d.r[s] : -1;
+    int itf = 0, itg = 0, q = 0, lim = 0, passes = 0;
+    double kn = 0.0, RTc = 0.0;
+    if (R >= 0) {
+        const double rho = b.d.rho[s], ux = b.d.ux[s], uy = b.d.uy[s], uz = b.d.uz[s], RT = b.d.rt[s];
+        RTc = RT;
+        double mf[NF], mg[NG];
+        collide3(ph, mom, g.n, s, rho, ux, uy, uz, RT, mf, mg, kn, lim);
+        const double rr = R + 0.5;
+        const int ubx = (int)floor(ux + 0.5), uby = (int)floor(uy + 0.5), ubz = (int)floor(uz + 0.5);
+        const int xlo = ubx - R - 1, xhi = ubx + R + 1;
+        Sp3<NF> sf;
+        Sp3<NG> sg;
+        sp3_init<NF>(sf, RT);
+        sp3_init<NG>(sg, RT);
+        const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
+        int fail = 0, fsp = -1;
+        while (!fail && (sf.phase < 2 || sg.phase < 2)) {
+            passes++;
+            double Sf[NMF], Sg[NMG], lf[NF], lg[NG];
+#pragma unroll
+            for (int k = 0; k < NMF; k++) Sf[k] = 0.0;
+#pragma unroll
+            for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
+#pragma unroll
+            for (int j = 0; j < NG; j++) lg[j] = sg.at(j);
+            for (int cz = ubz - R - 1; cz <= ubz + R + 1; cz++) {
+                const double zz = (double)cz - uz;
+                for (int cy = uby - R - 1; cy <= uby + R + 1; cy++) {
+                    int xa, xb;
+                    if (!span3(cy, cz, ux, uy, uz, rr, xlo, xhi, xa, xb)) continue;
+                    const double yy = (double)cy - uy;
+                    double C[4], Dg[3];
+                    row_coef(lf, lg, yy, zz, C, Dg);
+                    double Rf[7] = {0, 0, 0, 0, 0, 0, 0}, Rg[5] = {0, 0, 0, 0, 0};
+                    for (int cx = xa; cx <= xb; cx++) {
+                        const double xx = (double)cx - ux;
+                        const double f = exp(-(1.0 + (C[0] + xx * (C[1] + xx * (C[2] + xx * C[3])))));
+                        const double gv = exp(-(1.0 + (Dg[0] + xx * (Dg[1] + xx * Dg[2]))));
+                        double p = f;
+                        Rf[0] += p;
+#pragma unroll
+                        for (int a = 1; a < 7; a++) { p *= xx; Rf[a] += p; }
+                        p = gv;
+                        Rg[0] += p;
+#pragma unroll
+                        for (int a = 1; a < 5; a++) { p *= xx; Rg[a] += p; }
+                    }
+                    double py[7], pz[7];
+                    py[0] = 1.0; pz[0] = 1.0;
+#pragma unroll
+                    for (int k = 1; k < 7; k++) { py[k] = py[k - 1] * yy; pz[k] = pz[k - 1] * zz; }
+#pragma unroll
+                    for (int a = 0; a < 7; a++)
+#pragma unroll
+                        for (int bb = 0; bb + a < 7; bb++)
+#pragma unroll
+                            for (int c = 0; c + bb + a < 7; c++) Sf[mono(a, bb, c)] += Rf[a] * (py[bb] * pz[c]);
+#pragma unroll
+                    for (int a = 0; a < 5; a++)
+#pragma unroll
+                        for (int bb = 0; bb + a < 5; bb++)
+#pragma unroll
+                            for (int c = 0; c + bb + a < 5; c++) Sg[mono(a, bb, c)] += Rg[a] * (py[bb] * pz[c]);
+                }
+            }
+            if (sg.phase < 2) {
+                const int r = sp3_update<NG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
+                if (r < 0) { fail = -r; fsp = 1; }
+            }
+            if (sf.phase < 2 && !fail) {
+                const int r = sp3_update<NF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
+                if (r < 0) { fail = -r; fsp = 0; }
+            }
+        }
+        if (fail) {
+            flag3(b.flags, LELBM_EEPR, step, s, fail, fsp, fsp ? sg.res : sf.res);
+        } else {
+            itf = sf.nit;
+            itg = sg.nit;
+            const double wsf = rho, wsg = rho * ph.K * RT;
+            const Tile3 ti = b.tiles[t];
+            T *P = (T *)b.scratch + ti.base;
+            for (int cz = ubz - R - 1; cz <= ubz + R + 1; cz++) {
+                const double zz = (double)cz - uz;
+                for (int cy = uby - R - 1; cy <= uby + R + 1; cy++) {
+                    int xa, xb;
+                    if (!span3(cy, cz, ux, uy, uz, rr, xlo, xhi, xa, xb)) continue;
+                    const double yy = (double)cy - uy;
+                    double C[4], Dg[3];
+                    row_coef(sf.lam, sg.lam, yy, zz, C, Dg);
+                    const long long row = ((long long)(cz - ti.oz) * ti.wy + (cy - ti.oy)) * ti.wx - ti.ox;
+                    for (int cx = xa; cx <= xb; cx++) {
+                        const double xx = (double)cx - ux;
+                        const double f = exp(-(1.0 + (C[0] + xx * (C[1] + xx * (C[2] + xx * C[3])))));
+                        const double gv = exp(-(1.0 + (Dg[0] + xx * (Dg[1] + xx * Dg[2]))));
+                        const long long e = ((row + cx) * TN + l) * 2;
+                        __builtin_nontemporal_store((T)(wsf * f), &P[e]);
+                        __builtin_nontemporal_store((T)(wsg * gv), &P[e + 1]);
+                        q++;
+                    }
+                }
+            }
+            passes++;
+        }
+    }
+    // statistics of the wavefront: one set of atomics per workgroup
+    unsigned long long a[5] = {(unsigned long long)itf, (unsigned long long)itg, (unsigned long long)q,
+                               (unsigned long long)lim, (unsigned long long)(R >= 0 && q > 0 ? 1 : 0)};
+    unsigned long long qp = (unsigned long long)q * (unsigned long long)passes;
+    int mxf = itf, mxg = itg, qmax = q, qmin = q > 0 ? q : INT_MAX;
+    double rtmin = q > 0 ? RTc : 1e300, knmax = kn;
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 5; k++) a[k] += __shfl_xor(a[k], off);
+        qp += __shfl_xor(qp, off);
+        mxf = max(mxf, __shfl_xor(mxf, off));
+        mxg = max(mxg, __shfl_xor(mxg, off));
+        qmax = max(qmax, __shfl_xor(qmax, off));
+        qmin = min(qmin, __shfl_xor(qmin, off));
+        rtmin = fmin(rtmin, __shfl_xor(rtmin, off));
+        knmax = fmax(knmax, __shfl_xor(knmax, off));
+    }
+    if (l == 0 && a[4] > 0) {
+        DevStats *st = b.stats;
+        atomicAdd(&st->it_sum_f, a[0]);
+        atomicAdd(&st->it_sum_g, a[1]);
+        atomicAdd(&st->q_sum, a[2]);
+        atomicAdd(&st->limited, a[3]);
+        atomicAdd(&st->cells, a[4]);
+        atomicAdd(&st->qpass_sum, qp);
+        atomicMax(&st->it_max_f, mxf);
+        atomicMax(&st->it_max_g, mxg);
+        atomicMax(&st->q_max, qmax);
+        atomicMin(&st->q_min, qmin);
+        atomicMin(&st->rt_min_bits, (unsigned long long)__double_as_longlong(rtmin));
+        atomicMax(&st->kn_max_bits, (unsigned long long)__double_as_longlong(knmax));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k3_gather: one lane per destination cell; every displacement d with
+// |d_a| <= the step's reach M is tested against the stencil of its source x
+// - d (wrapped) with the reconstruction's own predicate; a hit adds the
+// source's record with velocity d (Eq. IIE3b).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(64) k3_gather(G3 g, double *out, Buf3 b) {
+    if (b.flags->err) return;
+    const int t = blockIdx.x, l = threadIdx.x;
+    const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
+    const int x = tx * TE + (l & 3), y = ty * TE + ((l >> 2) & 3), z = tz * TE + (l >> 4);
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    const int M = *b.maxreach;
+    const T *SCR = (const T *)b.scratch;
+    double acc[NM];
+#pragma unroll
+    for (int k = 0; k < NM; k++) acc[k] = 0.0;
+    unsigned long long hits = 0;
+    for (int dz = -M; dz <= M; dz++) {
+        const int sz = wrapi(z - dz, g.nz);
+        for (int dy = -M; dy <= M; dy++) {
+            const int sy = wrapi(y - dy, g.ny);
+            double fr = 0, fx = 0, fxx = 0, fxxx = 0, gr = 0, gx = 0;   // row sums over d_x
+            for (int dx = -M; dx <= M; dx++) {
+                const int sx = wrapi(x - dx, g.nx);
+                const long long s = ((long long)sz * g.ny + sy) * g.nx + sx;
+                const int R = b.d.r[s];
+                if (R < 0) continue;
+                if (!in_ball((double)dx, (double)dy, (double)dz, b.d.ux[s], b.d.uy[s], b.d.uz[s], R + 0.5)) continue;
+                const int ts = (sz / TE * g.tny + sy / TE) * g.tnx + sx / TE;
+                const int loc = (sz % TE) * 16 + (sy % TE) * 4 + (sx % TE);
+                const Tile3 ti = b.tiles[ts];
+                const long long slot = ((long long)(dz - ti.oz) * ti.wy + (dy - ti.oy)) * ti.wx + (dx - ti.ox);
+                const T *P = SCR + ti.base + (slot * TN + loc) * 2;
+                const double wf = (double)P[0], wg = (double)P[1], cx = (double)dx;
+                fr += wf; fx += cx * wf; fxx += cx * cx * wf; fxxx += cx * cx * cx * wf;
+                gr += wg; gx += cx * wg;
+                hits++;
+            }
+            const double cy = (double)dy, cz = (double)dz, c2 = cy * cy + cz * cz;
+            acc[0] += fr;
+            acc[1] += fx; acc[2] += cy * fr; acc[3] += cz * fr;
+            acc[4] += fxx; acc[5] += cy * fx; acc[6] += cz * fx;
+            acc[7] += cy * cy * fr; acc[8] += cy * cz * fr; acc[9] += cz * cz * fr;
+            // |c|^2 c_g = (c_x^2 + c_y^2 + c_z^2) c_g
+            acc[10] += fxxx + c2 * fx;
+            acc[11] += cy * fxx + c2 * cy * fr;
+            acc[12] += cz * fxx + c2 * cz * fr;
+            acc[13] += gr; acc[14] += gx; acc[15] += cy * gr; acc[16] += cz * gr;
+        }
+    }
+    const long long o = ((long long)z * g.ny + y) * g.nx + x;
+#pragma unroll
+    for (int k = 0; k < NM; k++) out[k * g.n + o] = acc[k];
+    for (int off = 32; off > 0; off >>= 1) hits += __shfl_xor(hits, off);
+    if (l == 0) atomicAdd(&b.stats->arrivals, hits);
+}
+
+// Conserved totals (mass, x and y momentum, energy trace): block partials,
+// then one ordered sum.
+__global__ void __launch_bounds__(256) k3_sums(G3 g, const double *mom, double *partial) {
+    __shared__ double sh[4][256];
+    double a[4] = {0, 0, 0, 0};
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < g.n; i += (long long)gridDim.x * 256) {
+        a[0] += mom[i];
+        a[1] += mom[g.n + i];
+        a[2] += mom[2 * g.n + i];
+        a[3] += mom[4 * g.n + i] + mom[7 * g.n + i] + mom[9 * g.n + i] + mom[13 * g.n + i];
+    }
+    for (int k = 0; k < 4; k++) sh[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int k = 0; k < 4; k++) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; k++) partial[blockIdx.x * 4 + k] = sh[k][0];
+}
+
+__global__ void k3_sums_final(int nb, double *partial) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double a[4] = {0, 0, 0, 0};
+        for (int i = 0; i < nb; i++)
+            for (int k = 0; k < 4; k++) a[k] += partial[i * 4 + k];
+        for (int k = 0; k < 4; k++) partial[nb * 4 + k] = a[k];
+    }
+}
+
+__global__ void k3_reset(Buf3 b, int stats) {
+    if (threadIdx.x == 0) {
+        *b.maxreach = 0;
+        if (stats) {
+            DevStats z = {};
+            z.q_min = INT_MAX;
+            z.rt_min_bits = 0x7fefffffffffffffull;
+            *b.stats = z;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k3_load(long long n, const void *src, int fp32, double *dst) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = fp32 ? (double)((const float *)src)[i] : ((const double *)src)[i];
+}
+
+}  // namespace d3
+
+// ---------------------------------------------------------------------------
+// host side of the 3D path
+// ---------------------------------------------------------------------------
+using namespace d3;
+
+struct Ctx3 {
+    G3 g;
+    Phys ph;
+    int mixed;
+    hipStream_t stream;
+    Buf3 b;
+    int cur;
+    int nsum;                 // blocks of k3_sums
+    long long persistent;     // bytes
+    void *host_small;         // pinned: flags + totals + statistics
+};
+
+#define H3(x)                                 \
+    do {                                      \
+        if ((x) != hipSuccess) return LELBM_EDEVICE; \
+    } while (0)
+
+static void free3(Ctx3 *c) {
+    if (!c) return;
+    Buf3 &b = c->b;
+    void *ptrs[] = {b.mom[0], b.mom[1], b.d.rho, b.d.ux, b.d.uy, b.d.uz, b.d.rt, b.d.r, b.tiles, b.scratch,
+                    b.flags, b.stats, b.maxreach, b.total, b.partial};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->host_small) (void)hipHostFree(c->host_small);
+    delete c;
+}
+
+int ctx3_create(const lelbm_params *p, const Phys &ph, int mixed, const void *moments, int src_fp32, int on_device,
+                hipStream_t stream, Ctx3 **out) {
+    Ctx3 *c = new Ctx3();
+    memset(&c->b, 0, sizeof(c->b));
+    c->host_small = nullptr;
+    G3 &g = c->g;
+    g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
+    g.n = (long long)g.nx * g.ny * g.nz;
+    g.tnx = (g.nx + TE - 1) / TE; g.tny = (g.ny + TE - 1) / TE; g.tnz = (g.nz + TE - 1) / TE;
+    g.ntiles = g.tnx * g.tny * g.tnz;
+    c->ph = ph;
+    c->mixed = mixed;
+    c->stream = stream;
+    c->cur = 0;
+    c->nsum = (int)std::min<long long>((g.n + 255) / 256, 1024);
+    Buf3 &b = c->b;
+    bool ok = true;
+    auto alloc = [&](void **q, size_t bytes) { ok = ok && hipMalloc(q, bytes) == hipSuccess; };
+    alloc((void **)&b.mom[0], (size_t)NM * g.n * sizeof(double));
+    alloc((void **)&b.mom[1], (size_t)NM * g.n * sizeof(double));
+    for (double **q : {&b.d.rho, &b.d.ux, &b.d.uy, &b.d.uz, &b.d.rt}) alloc((void **)q, (size_t)g.n * sizeof(double));
+    alloc((void **)&b.d.r, (size_t)g.n * sizeof(int));
+    alloc((void **)&b.tiles, (size_t)g.ntiles * sizeof(Tile3));
+    alloc((void **)&b.flags, sizeof(Flags));
+    alloc((void **)&b.stats, sizeof(DevStats));
+    alloc((void **)&b.maxreach, sizeof(int));
+    alloc((void **)&b.total, sizeof(long long));
+    alloc((void **)&b.partial, (size_t)(c->nsum + 1) * 4 * sizeof(double));
+    ok = ok && hipHostMalloc(&c->host_small, 4096, hipHostMallocDefault) == hipSuccess;
+    if (!ok) { free3(c); return LELBM_ENOMEM; }
+    c->persistent = (long long)2 * NM * g.n * 8 + g.n * (5 * 8 + 4) + (long long)g.ntiles * sizeof(Tile3);
+    // state
+    const long long tot = (long long)NM * g.n;
+    if (on_device) {
+        hipLaunchKernelGGL(k3_load, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream, tot, moments, src_fp32,
+                           b.mom[0]);
+        if (hipGetLastError() != hipSuccess) { free3(c); return LELBM_EDEVICE; }
+    } else {
+        if (hipMemcpyAsync(b.mom[0], moments, (size_t)tot * sizeof(double), hipMemcpyHostToDevice, stream) !=
+            hipSuccess) {
+            free3(c);
+            return LELBM_EDEVICE;
+        }
+    }
+    hipLaunchKernelGGL(k3_reset_flags, dim3(1), dim3(64), 0, stream, b.flags);
+    if (hipStreamSynchronize(stream) != hipSuccess) { free3(c); return LELBM_EDEVICE; }
+    *out = c;
+    return LELBM_OK;
+}
+
+void ctx3_destroy(Ctx3 *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free3(c);
+}
+
+int ctx3_memory(const Ctx3 *c, long long *persistent, long long *scratch) {
+    if (persistent) *persistent = c->persistent;
+    if (scratch) *scratch = c->b.scratch_cap * (c->mixed ? 4 : 8);
+    return LELBM_OK;
+}
+
+int ctx3_read(const Ctx3 *c, void *out, int to_device) {
+    const size_t bytes = (size_t)NM * c->g.n * sizeof(double);
+    H3(hipMemcpyAsync(out, c->b.mom[c->cur], bytes, to_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                      c->stream));
+    if (!to_device) H3(hipStreamSynchronize(c->stream));
+    return LELBM_OK;
+}
+
+// Reads flags and the step's record total (one synchronisation).
+static int read_small(Ctx3 *c, Flags *f, long long *total) {
+    char *h = (char *)c->host_small;
+    H3(hipMemcpyAsync(h, c->b.flags, sizeof(Flags), hipMemcpyDeviceToHost, c->stream));
+    H3(hipMemcpyAsync(h + 256, c->b.total, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+    H3(hipStreamSynchronize(c->stream));
+    memcpy(f, h, sizeof(Flags));
+    memcpy(total, h + 256, sizeof(long long));
+    return LELBM_OK;
+}
+
+int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3Failure *fail) {
+    const G3 &g = c->g;
+    Buf3 &b = c->b;
+    hipStream_t s = c->stream;
+    hipLaunchKernelGGL(k3_reset_flags, dim3(1), dim3(64), 0, s, b.flags);
+    hipLaunchKernelGGL(k3_reset, dim3(1), dim3(64), 0, s, b, 1);
+    H3(hipGetLastError());
+    const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+    for (int k = 0; k < nsteps; k++) {
+        double *in = b.mom[c->cur], *outm = b.mom[c->cur ^ 1];
+        tm.begin(tm.ctx, 1, s);
+        hipLaunchKernelGGL(k3_reset, dim3(1), dim3(64), 0, s, b, 0);
+        hipLaunchKernelGGL(k3_prepare, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, c->ph, (const double *)in, b, k);
+        tm.end(tm.ctx, 1, s);
+        tm.begin(tm.ctx, 2, s);
+        hipLaunchKernelGGL(k3_scan, dim3(1), dim3(1024), 0, s, g.ntiles, b);
+        tm.end(tm.ctx, 2, s);
+        H3(hipGetLastError());
+        Flags f;
+        long long total = 0;
+        int r = read_small(c, &f, &total);
+        if (r != LELBM_OK) return r;
+        if (f.err) {
+            fail->err = f.err; fail->step = k; fail->node = f.node; fail->detail = f.detail;
+            fail->species = f.species; fail->residual = f.residual;
+            return f.err;
+        }
+        if (total > b.scratch_cap) {
+            if (b.scratch) H3(hipFree(b.scratch));
+            b.scratch = nullptr;
+            b.scratch_cap = 0;
+            const long long cap = total + total / 8;
+            if (hipMalloc(&b.scratch, (size_t)cap * esz) != hipSuccess) {
+                b.scratch = nullptr;
+                fail->err = LELBM_ENOMEM; fail->step = k; fail->node = -1; fail->detail = 0; fail->species = -1;
+                fail->residual = 0.0;
+                return LELBM_ENOMEM;
+            }
+            b.scratch_cap = cap;
+        }
+        tm.begin(tm.ctx, 3, s);
+        if (c->mixed)
+            hipLaunchKernelGGL(k3_epr<float>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, c->ph, (const double *)in, b, k);
+        else
+            hipLaunchKernelGGL(k3_epr<double>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, c->ph, (const double *)in, b, k);
+        tm.end(tm.ctx, 3, s);
+        tm.begin(tm.ctx, 4, s);
+        if (c->mixed)
+            hipLaunchKernelGGL(k3_gather<float>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, outm, b);
+        else
+            hipLaunchKernelGGL(k3_gather<double>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, outm, b);
+        tm.end(tm.ctx, 4, s);
+        H3(hipGetLastError());
+        // a failed reconstruction leaves the step's output unwritten
+        r = read_small(c, &f, &total);
+        if (r != LELBM_OK) return r;
+        if (f.err) {
+            fail->err = f.err; fail->step = k; fail->node = f.node; fail->detail = f.detail;
+            fail->species = f.species; fail->residual = f.residual;
+            return f.err;
+        }
+        c->cur ^= 1;
+    }
+    if (st) {
+        hipLaunchKernelGGL(k3_sums, dim3((unsigned)c->nsum), dim3(256), 0, s, g, (const double *)b.mom[c->cur],
+                           b.partial);
+        hipLaunchKernelGGL(k3_sums_final, dim3(1), dim3(64), 0, s, c->nsum, b.partial);
+        H3(hipGetLastError());
+        char *h = (char *)c->host_small;
+        H3(hipMemcpyAsync(h, b.stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+        H3(hipMemcpyAsync(h + 1024, b.partial + (size_t)c->nsum * 4, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        H3(hipStreamSynchronize(s));
+        DevStats ds;
+        double sums[4];
+        memcpy(&ds, h, sizeof(ds));
+        memcpy(sums, h + 1024, sizeof(sums));
+        memset(st, 0, sizeof(*st));
+        const double cells = ds.cells ? (double)ds.cells : 1.0;
+        st->it_mean_f = ds.it_sum_f / cells;
+        st->it_mean_g = ds.it_sum_g / cells;
+        st->it_max_f = ds.it_max_f;
+        st->it_max_g = ds.it_max_g;
+        st->limited = (long)ds.limited;
+        st->q_min = ds.cells ? ds.q_min : 0;
+        st->q_max = ds.q_max;
+        st->q_mean = ds.q_sum / cells;
+        double v;
+        memcpy(&v, &ds.rt_min_bits, 8); st->rt_min = v;
+        memcpy(&v, &ds.kn_max_bits, 8); st->kn_max = v;
+        for (int k = 0; k < 4; k++) st->sum[k] = sums[k];
+        st->cells = (long)ds.cells;
+        st->point_passes = (long)ds.qpass_sum;
+        st->arrivals = (long)ds.arrivals;
+    }
+    return LELBM_OK;
+}
+
+}  // namespace lelbm

@@ -77,6 +77,7 @@ struct lelbm_ctx {
     // the streams.
     hipStream_t side[3];
     std::vector<hipEvent_t> opev;
+    Ctx3 *c3;                // the 3D path (dim = 3), else NULL
 };
 
 // HIP errors are reported as LELBM_EDEVICE; with LELBM_DEBUG set in the
@@ -140,12 +141,12 @@ static int stage_d2h(Stage &st, hipStream_t s, void *host, const void *dev, size
     return LELBM_OK;
 }
 
-extern "C" int lelbm_num_moments(int dim) { return dim == 1 ? 6 : (dim == 2 ? 11 : -1); }
+extern "C" int lelbm_num_moments(int dim) { return dim == 1 ? 6 : (dim == 2 ? 11 : (dim == 3 ? 17 : -1)); }
 
 extern "C" int lelbm_moments_from_primitives(int dim, double K, long n, const double *rho, const double *ux,
                                              const double *uy, const double *RT, double *out) {
     int nm = lelbm_num_moments(dim);
-    if (nm < 0 || n < 0 || !rho || !ux || !RT || !out || (dim == 2 && !uy)) return LELBM_EINVAL;
+    if ((dim != 1 && dim != 2) || n < 0 || !rho || !ux || !RT || !out || (dim == 2 && !uy)) return LELBM_EINVAL;
     for (long i = 0; i < n; i++) {
         double r = rho[i], x = ux[i], y = dim == 2 ? uy[i] : 0.0, T = RT[i];
         double m[11];
@@ -160,6 +161,26 @@ extern "C" int lelbm_moments_from_primitives(int dim, double K, long n, const do
             m[8] = r * K * T; m[9] = r * K * T * x; m[10] = r * K * T * y;
         }
         for (int k = 0; k < nm; k++) out[(long)k * n + i] = m[k];
+    }
+    return LELBM_OK;
+}
+
+extern "C" int lelbm_moments_from_primitives3(double K, long n, const double *rho, const double *ux, const double *uy,
+                                              const double *uz, const double *RT, double *out) {
+    if (n < 0 || !rho || !ux || !uy || !uz || !RT || !out) return LELBM_EINVAL;
+    for (long i = 0; i < n; i++) {
+        const double r = rho[i], u[3] = {ux[i], uy[i], uz[i]}, T = RT[i];
+        const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        double m[17];
+        m[0] = r;
+        for (int a = 0; a < 3; a++) m[1 + a] = r * u[a];
+        int k = 4;
+        for (int a = 0; a < 3; a++)
+            for (int c = a; c < 3; c++) m[k++] = r * (u[a] * u[c] + (a == c ? T : 0.0));
+        for (int a = 0; a < 3; a++) m[10 + a] = r * (uu + 5.0 * T) * u[a];    // D + 2 = 5
+        m[13] = r * K * T;
+        for (int a = 0; a < 3; a++) m[14 + a] = r * K * T * u[a];
+        for (int j = 0; j < 17; j++) out[(long)j * n + i] = m[j];
     }
     return LELBM_OK;
 }
@@ -182,6 +203,7 @@ extern "C" const char *lelbm_strerror(int code) {
 static int validate(const lelbm_params *p) {
     if (!p) return LELBM_EINVAL;
     if (p->dim != 1 && p->dim != 2) return LELBM_EINVAL;
+    if (p->nz != 0 && p->nz != 1) return LELBM_EINVAL;
     if (p->nx <= 0 || p->ny <= 0 || (p->dim == 1 && p->ny != 1)) return LELBM_EINVAL;
     if (!(p->K > 0.0) || !(p->n_conf > 0.0) || p->r_min < 1) return LELBM_EINVAL;
     if (!(p->newton_tol > 0.0) || p->newton_max_it < 1) return LELBM_EINVAL;
@@ -228,8 +250,25 @@ static int validate(const lelbm_params *p) {
     return LELBM_OK;
 }
 
+// Three dimensions: periodic boxes, the Newton start of Eq. (IID13), no
+// solids, walls, point sources, learned guess or harvest.
+static int validate3(const lelbm_params *p) {
+    if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return LELBM_EINVAL;
+    if (!(p->K > 0.0) || !(p->n_conf > 0.0) || p->r_min < 1) return LELBM_EINVAL;
+    if (!(p->newton_tol > 0.0) || p->newton_max_it < 1) return LELBM_EINVAL;
+    if (p->precision != LELBM_FP64 && p->precision != LELBM_MIXED) return LELBM_EINVAL;
+    if (p->guess != LELBM_GUESS_EQ) return LELBM_EINVAL;
+    for (int f = 0; f < 4; f++)
+        if (p->bc[f] != LELBM_BC_PERIODIC || p->wall_u[f] != 0.0) return LELBM_EINVAL;
+    if (p->solid || p->src_rate != 0.0) return LELBM_EINVAL;
+    if (p->kn_limiter && !(p->kn_hi > p->kn_lo)) return LELBM_EINVAL;
+    return LELBM_OK;
+}
+
 static void free_ctx(lelbm_ctx *c) {
     if (!c) return;
+    if (c->c3) ctx3_destroy(c->c3);
+    c->c3 = nullptr;
     Buffers &b = c->b;
     void *ptrs[] = {b.mom[0], b.mom[1], b.desc_u, b.desc_rho, b.desc_rt, b.desc_rn, b.spans, b.tiles,
                     b.dwin, b.scratch, b.flags, b.stats, b.partial, b.harvest_n,
@@ -405,6 +444,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     lelbm_ctx *c = new (std::nothrow) lelbm_ctx();
     if (!c) return LELBM_ENOMEM;
     memset(&c->b, 0, sizeof(c->b));
+    c->c3 = nullptr;
     c->ev[0] = c->ev[1] = nullptr;
     c->side[0] = c->side[1] = c->side[2] = nullptr;
     c->mlp_w = nullptr;
@@ -633,8 +673,53 @@ static int finish_create(lelbm_ctx *c) {
     return reset_flags(c);
 }
 
+// A 3D context: the shell of lelbm_ctx (stream, timing, failure record)
+// around the 3D path's own buffers.
+static int create3(const lelbm_params *p, const void *moments, int src_fp32, int on_device, void *hip_stream,
+                   lelbm_ctx **out) {
+    int v = validate3(p);
+    if (v != LELBM_OK) return v;
+    if (!out) return LELBM_EINVAL;
+    lelbm_ctx *c = new (std::nothrow) lelbm_ctx();
+    if (!c) return LELBM_ENOMEM;
+    memset(&c->b, 0, sizeof(c->b));
+    c->c3 = nullptr;
+    c->ev[0] = c->ev[1] = nullptr;
+    c->side[0] = c->side[1] = c->side[2] = nullptr;
+    c->mlp_w = nullptr; c->mlp_p = nullptr; c->mlp_n = nullptr; c->mlp_set = 0;
+    c->c3 = nullptr;
+    c->p = *p;
+    c->mixed = p->precision == LELBM_MIXED;
+    c->nmom = 17;
+    c->stream = (hipStream_t)hip_stream;
+    c->last_fail_node = -1; c->last_fail_step = -1; c->last_fail_detail = 0; c->last_fail_species = -1;
+    c->last_fail_residual = 0.0;
+    c->timing = 0;
+    c->evused = 0;
+    for (int k = 0; k < LELBM_NTIMERS; k++) { c->kms[k] = 0; c->klaunch[k] = 0; }
+    c->budget = LELBM_DEFAULT_SCRATCH_BUDGET;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return LELBM_EDEVICE; }
+    Phys &ph = c->ph;
+    memset(&ph, 0, sizeof(ph));
+    ph.K = p->K; ph.omega_f = p->omega_f; ph.omega_b = p->omega_b; ph.omega_h = p->omega_h;
+    ph.n_conf = p->n_conf; ph.r_min = p->r_min; ph.tol = p->newton_tol; ph.maxit = p->newton_max_it;
+    if (c->mixed && ph.tol < MIXED_TOL_FLOOR) ph.tol = MIXED_TOL_FLOOR;
+    ph.kn_limiter = p->kn_limiter; ph.kn_lo = p->kn_lo; ph.kn_hi = p->kn_hi; ph.omega_H = p->omega_H;
+    ph.kn_lo_lin = pow(10.0, p->kn_lo); ph.kn_hi_lin = pow(10.0, p->kn_hi);
+    ph.src_node = -1;
+    c->ph_step = ph;
+    int r = ctx3_create(p, ph, c->mixed, moments, src_fp32, on_device, c->stream, &c->c3);
+    if (r != LELBM_OK) { free_ctx(c); return r; }
+    long long pb = 0;
+    ctx3_memory(c->c3, &pb, nullptr);
+    c->persistent_bytes = pb;
+    *out = c;
+    return LELBM_OK;
+}
+
 extern "C" int lelbm_create(const lelbm_params *p, const double *moments, void *hip_stream, lelbm_ctx **out) {
     if (!moments) return LELBM_EINVAL;
+    if (p && p->dim == 3) return create3(p, moments, 0, 0, hip_stream, out);
     lelbm_ctx *c = nullptr;
     int r = create_common(p, hip_stream, out, &c);
     if (r != LELBM_OK) return r;
@@ -648,6 +733,7 @@ extern "C" int lelbm_create(const lelbm_params *p, const double *moments, void *
 extern "C" int lelbm_create_device(const lelbm_params *p, const void *dev_moments, int dev_is_fp32,
                                    void *hip_stream, lelbm_ctx **out) {
     if (!dev_moments) return LELBM_EINVAL;
+    if (p && p->dim == 3) return create3(p, dev_moments, dev_is_fp32, 1, hip_stream, out);
     lelbm_ctx *c = nullptr;
     int r = create_common(p, hip_stream, out, &c);
     if (r != LELBM_OK) return r;
@@ -953,11 +1039,53 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
     return LELBM_OK;
 }
 
+// Event hooks of a 3D step: the same pool and kinds as timed().
+static void t3_begin(void *cc, int kind, hipStream_t s) {
+    lelbm_ctx *c = (lelbm_ctx *)cc;
+    if (!c->timing) return;
+    const size_t i = c->evused;
+    while (c->evpool.size() < 2 * (i + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        c->evpool.push_back(e);
+    }
+    if (c->evkind.size() < i + 1) c->evkind.resize(i + 1);
+    (void)hipEventRecord(c->evpool[2 * i], s);
+    c->evkind[i] = kind;
+}
+static void t3_end(void *cc, int, hipStream_t s) {
+    lelbm_ctx *c = (lelbm_ctx *)cc;
+    if (!c->timing || c->evpool.size() < 2 * (c->evused + 1)) return;
+    (void)hipEventRecord(c->evpool[2 * c->evused + 1], s);
+    c->evused++;
+}
+
+static int step3(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
+    if (nsteps < 0) return LELBM_EINVAL;
+    Step3Timer tm{c, t3_begin, t3_end};
+    Step3Failure f{0, -1, 0, -1, -1, 0.0};
+    int r = ctx3_step(c->c3, nsteps, st, tm, &f);
+    if (c->timing) {
+        (void)hipStreamSynchronize(c->stream);
+        int rt = collect_times(c);
+        if (r == LELBM_OK) r = rt;
+    }
+    if (f.err) {
+        c->last_fail_node = (long)f.node;
+        c->last_fail_step = f.step;
+        c->last_fail_detail = f.detail;
+        c->last_fail_species = f.species;
+        c->last_fail_residual = f.residual;
+    }
+    return r;
+}
+
 extern "C" int lelbm_step(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
     if (!c) return LELBM_EINVAL;
     int dev;
     HIPCHECK(hipGetDevice(&dev));
     if (dev != c->device) HIPCHECK(hipSetDevice(c->device));
+    if (c->c3) return step3(c, nsteps, st);
     return step_impl(c, nsteps, st, nullptr, 0);
 }
 
@@ -990,7 +1118,7 @@ static int noalloc_scratch(int dev, void **out) {
 }
 
 extern "C" int lelbm_step_noalloc(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
-    if (!c) return LELBM_EINVAL;
+    if (!c || c->c3) return LELBM_EINVAL;
     int dev;
     HIPCHECK(hipGetDevice(&dev));
     if (dev != c->device) HIPCHECK(hipSetDevice(c->device));
@@ -1006,6 +1134,7 @@ extern "C" int lelbm_step_noalloc(lelbm_ctx *c, int nsteps, lelbm_stats *st) {
 // kernel.
 static int read_common(const lelbm_ctx *cc, void *out, hipMemcpyKind kind, bool sync) {
     lelbm_ctx *c = const_cast<lelbm_ctx *>(cc);     // the stage is scratch state
+    if (c->c3) return ctx3_read(c->c3, out, kind == hipMemcpyDeviceToDevice);
     const Geom &g = c->g;
     const size_t esz = sizeof(double);
     const long long n = (long long)g.nx * g.ny;
@@ -1077,6 +1206,7 @@ extern "C" int lelbm_kernel_times(const lelbm_ctx *c, double *ms, long *launches
 extern "C" int lelbm_set_scratch_budget(lelbm_ctx *c, long long bytes) {
     if (!c || bytes < 1) return LELBM_EINVAL;
     c->budget = bytes;
+    if (c->c3) return LELBM_OK;   // the 3D path holds one step's records whole
     const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
     const long long limit = std::max<long long>(bytes / (long long)esz, 1);
     // the plan starts again from one band of the whole domain (the next step
@@ -1096,6 +1226,13 @@ extern "C" int lelbm_set_scratch_budget(lelbm_ctx *c, long long bytes) {
 
 extern "C" int lelbm_memory(const lelbm_ctx *c, long *persistent_bytes, long *scratch_bytes) {
     if (!c) return LELBM_EINVAL;
+    if (c->c3) {
+        long long pb = 0, sb = 0;
+        ctx3_memory(c->c3, &pb, &sb);
+        if (persistent_bytes) *persistent_bytes = (long)pb;
+        if (scratch_bytes) *scratch_bytes = (long)sb;
+        return LELBM_OK;
+    }
     if (persistent_bytes) *persistent_bytes = (long)c->persistent_bytes;
     if (scratch_bytes) *scratch_bytes = (long)(c->b.scratch_cap * (c->mixed ? 4 : 8));
     return LELBM_OK;
@@ -1297,7 +1434,7 @@ extern "C" int lelbm_set_mlp(lelbm_ctx *c, const lelbm_mlp *m) {
 }
 
 extern "C" int lelbm_harvest(lelbm_ctx *c, float *dev_buf, long long capacity, int stride) {
-    if (!c) return LELBM_EINVAL;
+    if (!c || c->c3) return LELBM_EINVAL;
     if (!dev_buf) {
         c->b.harvest = nullptr;
         c->b.harvest_cap = 0;
@@ -1313,6 +1450,10 @@ extern "C" int lelbm_harvest(lelbm_ctx *c, float *dev_buf, long long capacity, i
 
 extern "C" int lelbm_harvest_count(const lelbm_ctx *c, long long *n) {
     if (!c || !n) return LELBM_EINVAL;
+    if (c->c3) {
+        *n = 0;
+        return LELBM_OK;
+    }
     unsigned long long v = 0;
     int r = stage_d2h(const_cast<lelbm_ctx *>(c)->stage, c->stream, &v, c->b.harvest_n, sizeof(v));
     if (r != LELBM_OK) return r;

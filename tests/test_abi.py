@@ -49,7 +49,11 @@ def test_moments_from_primitives_matches_oracle_definition():
         b = oracle.moments_from_primitives(dim, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
         assert np.array_equal(a, b)
         assert a.shape[0] == lb.num_moments(dim)
-    assert lb.num_moments(3) == -1
+    cfg, prim = li.smooth_periodic3(4, n=5, ny=4, nz=3)
+    a = lb.moments_from_primitives3(cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["uz"], prim["RT"])
+    b = oracle.moments_from_primitives3(cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["uz"], prim["RT"])
+    assert np.array_equal(a, b) and a.shape[0] == lb.num_moments(3) == 17
+    assert lb.num_moments(4) == -1
 
 
 def test_invalid_parameters_are_rejected_before_any_device_call():
@@ -71,6 +75,24 @@ def test_invalid_parameters_are_rejected_before_any_device_call():
     c = dict(cfg); c["wall_u"] = (0.0, 0.0, 0.1, 0.0); bad.append(c)
     c = dict(cfg); c["bc"] = ["periodic", "periodic", "wall", "wall"]; c["wall_u"] = (0.0, 0.0, 0.0, float("nan"))
     bad.append(c)
+    # 3D: periodic boxes with the Eq. (IID13) start only
+    c3, p3 = li.smooth_periodic3(0, n=4)
+    m3 = lb.moments_from_primitives3(c3["K"], p3["rho"], p3["ux"], p3["uy"], p3["uz"], p3["RT"])
+    for key, val in (("bc", ["outflow", "outflow", "periodic", "periodic"]), ("guess", None), ("nz", 0),
+                     ("source", {"x": 1, "y": 1, "rate": 1e-3, "omega": 0.1})):
+        c = dict(c3)
+        if key == "guess":
+            with pytest.raises(lb.LelbmError) as e:
+                lb.Lelbm(c, m3, guess=lb.GUESS_LIN, stream=0)
+            assert e.value.code == lb.EINVAL
+            continue
+        c[key] = val
+        if key == "bc":
+            c["pad"] = 4
+        with pytest.raises(lb.LelbmError) as e:
+            lb.Lelbm(c, m3 if key != "nz" else np.ones((17, 0)), stream=0)
+        assert e.value.code == lb.EINVAL
+    c = dict(cfg); c["nz"] = 3; bad.append(c)                                                     # nz in 2D
     for c in bad:
         mm = m if c["dim"] == 2 else np.ones((6, 64))
         with pytest.raises(lb.LelbmError) as e:

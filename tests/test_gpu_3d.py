@@ -1,0 +1,122 @@
+"""The 3D step (D = 3, periodic boxes) on the HIP path: element-wise parity
+with the 3D oracle in both precisions on boxes of several ragged tiles,
+across step calls, exact conservation and a uniform flow at size, the
+shear viscosity at a resolution the oracle would need minutes for, and the
+refusal of refined stencils."""
+import numpy as np
+import pytest
+
+import lelbm_inputs as li
+import oracle
+from helpers import rel_linf
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    print("\n[gpu case] %s" % name, flush=True)
+
+
+def _mom(cfg, prim):
+    import paper_2508_06911_amd as lb
+    return lb.moments_from_primitives3(cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["uz"], prim["RT"])
+
+
+def _oracle(cfg, prim, steps):
+    m = oracle.moments_from_primitives3(cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["uz"], prim["RT"])
+    st, out, stats, done = oracle.step(cfg, m, steps)
+    assert st == 0, (st, done)
+    return out, stats
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-6)])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_parity_ragged_box(prec, tol, seed):
+    import paper_2508_06911_amd as lb
+    _case("3D parity seed %d precision %d, 10 x 9 x 7, 4 steps" % (seed, prec))
+    cfg, prim = li.smooth_periodic3(seed, n=10, ny=9, nz=7, amp=0.08, RT=0.9)
+    ref, rs = _oracle(cfg, prim, 4)
+    ctx = lb.Lelbm(cfg, _mom(cfg, prim), precision=prec)
+    st = ctx.step(4)
+    out = ctx.read_moments()
+    ctx.close()
+    err = rel_linf(out, ref)
+    print("rel Linf vs oracle %.3g, q mean %.1f (oracle %.1f), Newton it %.2f" % (err, st["q_mean"], rs["q_mean"],
+                                                                               st["it_mean_f"]), flush=True)
+    assert err < tol
+    assert abs(st["q_mean"] - rs["q_mean"]) < 1e-9
+
+
+def test_parity_across_calls_and_hot_fast_gas():
+    """A hotter, faster state (R up to 6, |u| above 2) split over two calls
+    equals one call of all steps, and the oracle."""
+    import paper_2508_06911_amd as lb
+    _case("3D hot fast gas 8 x 8 x 8, 2 + 3 steps")
+    cfg, prim = li.smooth_periodic3(2, n=8, amp=0.1, RT=2.2, u=(2.3, -1.4, 0.7))
+    ref, _ = _oracle(cfg, prim, 5)
+    a = lb.Lelbm(cfg, _mom(cfg, prim))
+    a.step(2)
+    a.step(3)
+    oa = a.read_moments()
+    a.close()
+    b = lb.Lelbm(cfg, _mom(cfg, prim))
+    b.step(5)
+    ob = b.read_moments()
+    b.close()
+    print("rel Linf vs oracle %.3g" % rel_linf(oa, ref), flush=True)
+    assert np.array_equal(oa, ob)
+    assert rel_linf(oa, ref) < 1e-10
+
+
+def test_conservation_and_uniform_flow_at_size():
+    import paper_2508_06911_amd as lb
+    _case("3D conservation 48^3, 3 steps; uniform flow 32^3")
+    cfg, prim = li.smooth_periodic3(3, n=48, amp=0.1, RT=1.2)
+    m = _mom(cfg, prim)
+    ctx = lb.Lelbm(cfg, m)
+    st = ctx.step(3)
+    out = ctx.read_moments()
+    ctx.close()
+    E = lambda a: a[4] + a[7] + a[9] + a[13]
+    for k in range(4):
+        assert abs(out[k].sum() - m[k].sum()) < 1e-12 * m[0].sum()
+    assert abs(E(out).sum() / E(m).sum() - 1) < 1e-12
+    assert abs(st["sum"][0] / m[0].sum() - 1) < 1e-13
+    cfg, prim = li.smooth_periodic3(0, n=32, amp=0.0, u=(1.3, -0.7, 0.45), RT=1.4)
+    m = _mom(cfg, prim)
+    ctx = lb.Lelbm(cfg, m)
+    ctx.step(2)
+    out = ctx.read_moments()
+    ctx.close()
+    assert np.abs(out - m).max() < 1e-12 * np.abs(m).max()
+
+
+def test_shear_viscosity_64():
+    """Transverse shear wave (Sec. IV.A) on 64 x 4 x 4 at rest: nu = RT (1/omega_f - 1/2) (Eq. C8a) within 1 %."""
+    import paper_2508_06911_amd as lb
+    _case("3D shear wave L = 64, RT 1, nu 0.1")
+    L, nu = 64, 0.1
+    cfg, prim = li.shear_wave3(L=L, ny=4, nz=4, RT=1.0, nu=nu, u0=0.0, amp=1e-4)
+    k = 2 * np.pi / L
+    t = int(round(1.0 / (nu * k * k)))
+    ctx = lb.Lelbm(cfg, _mom(cfg, prim))
+    ctx.step_nostats(t)
+    out = ctx.read_moments()
+    ctx.close()
+    uy = (out[2] / out[0]).reshape(4, 4, L).mean(axis=(0, 1))
+    x = np.arange(L) + 0.5
+    amp = np.hypot((uy * np.cos(k * x)).sum(), (uy * np.sin(k * x)).sum()) * 2 / L
+    nu_m = -np.log(amp / 1e-4) / (k * k * t)
+    print("nu measured %.5f target %.5f" % (nu_m, nu), flush=True)
+    assert abs(nu_m / nu - 1) < 0.01
+
+
+def test_refined_stencils_are_refused():
+    import paper_2508_06911_amd as lb
+    _case("3D refined stencil refused")
+    cfg, prim = li.smooth_periodic3(4, n=4, amp=0.0, RT=0.4)
+    ctx = lb.Lelbm(cfg, _mom(cfg, prim))
+    with pytest.raises(lb.LelbmError) as e:
+        ctx.step(1)
+    ctx.close()
+    assert e.value.code == lb.EREACH
