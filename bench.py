@@ -86,6 +86,30 @@ def epr_flops_per_step(st, steps):
             + FLOPS_EVAL * evals + FLOPS_CELL * st["cells"]) / steps
 
 
+# FP64 work of the 3D reconstruction kernel (k3_epr) as written, per unit:
+#   78 per point and Newton evaluation: the cubic and quadratic exponents
+#      (5 multiply-adds), two exponentials (~22 each), x^1..x^6 and x^1..x^4
+#      (10 multiplies) and 12 row-sum updates
+#   56 per point of the final pass: the exponents, two exponentials, two
+#      weights
+#  500 per stencil row and pass: the exponents' row coefficients (29 terms),
+#      the row's span, y and z powers, and folding the row sums into the
+#      84 + 35 monomial sums (a product and a multiply-add each)
+# 6000 per evaluation: the 19x19 and 10x10 Hessians, their Cholesky
+#      factorisations and solves
+#  300 per cell: collision
+FLOPS3_POINT_EVAL, FLOPS3_POINT_FINAL, FLOPS3_ROW, FLOPS3_EVAL, FLOPS3_CELL = 78, 56, 500, 6000, 300
+
+
+def epr3_flops_per_step(st, steps):
+    """Executed FP64 flops of k3_epr per step from the step statistics."""
+    q = st["q_mean"] * st["cells"]
+    eval_points = max(st["point_passes"] - q, 0.0)
+    evals = max(st["point_passes"] / max(st["q_mean"], 1e-30) - st["cells"], 0.0)
+    return (FLOPS3_POINT_EVAL * eval_points + FLOPS3_POINT_FINAL * q + FLOPS3_ROW * st["row_passes"]
+            + FLOPS3_EVAL * evals + FLOPS3_CELL * st["cells"]) / steps
+
+
 # Algorithmic bytes of the gather: per arriving stencil point the (w_f, w_g)
 # pair, per destination the written moments, per source its descriptor
 # (velocity, density, temperature, radius: 20 bytes).
@@ -137,6 +161,8 @@ def parse():
     ap.add_argument("--c4-only", action="store_true",
                     help="run only the 8192x4096 Mach-10 channel context, FP32 path with the learned guess "
                          "(for kernel traces of that workload)")
+    ap.add_argument("--d3", type=int, default=0,
+                    help="time the 3D step on an N^3 periodic box instead (its own JSON line)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -551,6 +577,79 @@ def c1_line(lb, li, torch, mlp):
     return out
 
 
+def d3_line(a, lb, li, torch):
+    """The 3D step on an N^3 periodic box with smooth random fields (RT ~ 1,
+    mean velocity (0.3, -0.2, 0.1)): FP64 and FP32 records, W warm-up and K
+    timed steps each, HIP events on the library's stream, and the oracle on
+    a 16^3 box of the same kind on the host cores."""
+    import oracle
+    n = a.d3
+    cfg, prim = li.smooth_periodic3(a.seed, n=n, amp=0.1, RT=1.0)
+    m = lb.moments_from_primitives3(cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["uz"], prim["RT"])
+    ncell = n ** 3
+    out, moms = {}, {}
+    for name, prec in (("fp64", lb.FP64), ("mixed", lb.MIXED)):
+        stream = torch.cuda.current_stream()
+        c = lb.Lelbm(cfg, m, precision=prec, stream=stream)
+        c.step_nostats(a.warmup)
+        torch.cuda.synchronize()
+        c.set_timing(True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        st = c.step(a.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / a.steps
+        kt = c.kernel_times()
+        persistent, scratch = c.memory()
+        moms[name] = c.read_moments()
+        c.close()
+        epr_ms = kt["epr"][0] / a.steps
+        gat_ms = kt["gather"][0] / a.steps
+        flops = epr3_flops_per_step(st, a.steps)
+        gbytes = st["arrivals"] / a.steps * GATHER_PAIR_BYTES[name] + ncell * (17 * 8 + 28)
+        out[name] = {"mlups": round(ncell / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4),
+                     "epr_ms": round(epr_ms, 4), "gather_ms": round(gat_ms, 4),
+                     "kernels_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in kt.items() if v[1]},
+                     "epr_tflops_executed": round(flops / (epr_ms * 1e-3) / 1e12, 3),
+                     "epr_frac_fp64_peak": round(flops / (epr_ms * 1e-3) / 1e12 / VALU_PEAK_TFLOPS, 4),
+                     "gather_gbs": round(gbytes / (gat_ms * 1e-3) / 1e9, 1),
+                     "newton_it_f": round(st["it_mean_f"], 3), "q_mean": round(st["q_mean"], 1),
+                     "q_max": st["q_max"], "hbm_bytes": {"persistent": persistent, "scratch": scratch}}
+        log("3D %s: %.2f ms/step, %.1f MLUPS, epr %.3f ms (%.2f TFLOP/s executed), gather %.3f ms"
+            % (name, ms, out[name]["mlups"], epr_ms, out[name]["epr_tflops_executed"], gat_ms))
+    out["l1_mixed_vs_fp64"] = l1_errors3(moms["mixed"], moms["fp64"])
+    c8, p8 = li.smooth_periodic3(a.seed, n=16, amp=0.1, RT=1.0)
+    m8 = oracle.moments_from_primitives3(c8["K"], p8["rho"], p8["ux"], p8["uy"], p8["uz"], p8["RT"])
+    t0 = time.perf_counter()
+    code, _, _, _ = oracle.step(c8, m8, 4)
+    el = time.perf_counter() - t0
+    res = {"metric": "MLUPS of the 3D LELBM step (D = 3, 17 stored values)", "value": out["mixed"]["mlups"],
+           "unit": "MLUPS", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": out["mixed"]["ms_per_step"], "higher_is_better": True, "dtype": "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": "3D periodic box %d^3, smooth random fields (seed %d), RT ~ 1, "
+                                  "FP32 records" % (n, a.seed)},
+           "fp64_mlups": out["fp64"]["mlups"],
+           "roofline": {"bound": "alu", "achieved": out["fp64"]["epr_tflops_executed"], "peak": VALU_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": out["fp64"]["epr_frac_fp64_peak"], "traffic": None,
+                        "kernel": "k3_epr<double> (FP64 path)"},
+           "cpu_baseline": {"value": round(16 ** 3 * 4 / el / 1e6, 5), "unit": "MLUPS", "cores": oracle.num_threads(),
+                            "kind": "oracle", "sample": "16^3 box of the same kind, 4 steps (%.1f s)" % el,
+                            "status": code},
+           "runs": out}
+    return res
+
+
+def l1_errors3(a, b):
+    r = {}
+    for name, f in (("rho", lambda m: m[0]), ("u", lambda m: np.sqrt(((m[1:4] / m[0]) ** 2).sum(0))),
+                    ("T", lambda m: ((m[4] + m[7] + m[9] + m[13]) / m[0] - ((m[1:4] / m[0]) ** 2).sum(0)) / 5.0)):
+        x, y = f(a), f(b)
+        r[name] = float(np.abs(x - y).sum() / np.abs(y).sum())
+    return r
+
+
 def main():
     a = parse()
     if a.copy_probe:
@@ -573,6 +672,9 @@ def main():
     import paper_2508_06911_amd as lb
 
     torch.cuda.set_device(0)
+    if a.d3:
+        print(json.dumps(d3_line(a, lb, li, torch)), flush=True)
+        return
     if a.channel_only:
         print(json.dumps({"channel_context": channel_context(lb, li, torch, a)}), flush=True)
         return

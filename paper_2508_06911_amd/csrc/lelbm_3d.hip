@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
     const bool valid = x < g.nx && y < g.ny && z < g.nz;
     const long long s = valid ? ((long long)z * g.ny + y) * g.nx + x : 0;
     const int R = valid ? b.d.r[s] : -1;
-    int itf = 0, itg = 0, q = 0, lim = 0, passes = 0;
+    int itf = 0, itg = 0, q = 0, lim = 0, passes = 0, rows = 0;
     double kn = 0.0, RTc = 0.0;
     if (R >= 0) {
         const double rho = b.d.rho[s], ux = b.d.ux[s], uy = b.d.uy[s], uz = b.d.uz[s], RT = b.d.rt[s];
@@ -562,6 +562,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
                 for (int cy = uby - R - 1; cy <= uby + R + 1; cy++) {
                     int xa, xb;
                     if (!span3(cy, cz, ux, uy, uz, rr, xlo, xhi, xa, xb)) continue;
+                    rows++;
                     const double yy = (double)cy - uy;
                     double C[4], Dg[3];
                     row_coef(sf.lam, sg.lam, yy, zz, C, Dg);
@@ -584,12 +585,14 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
     unsigned long long a[5] = {(unsigned long long)itf, (unsigned long long)itg, (unsigned long long)q,
                                (unsigned long long)lim, (unsigned long long)(R >= 0 && q > 0 ? 1 : 0)};
     unsigned long long qp = (unsigned long long)q * (unsigned long long)passes;
+    unsigned long long rp = (unsigned long long)rows * (unsigned long long)passes;
     int mxf = itf, mxg = itg, qmax = q, qmin = q > 0 ? q : INT_MAX;
     double rtmin = q > 0 ? RTc : 1e300, knmax = kn;
     for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
         for (int k = 0; k < 5; k++) a[k] += __shfl_xor(a[k], off);
         qp += __shfl_xor(qp, off);
+        rp += __shfl_xor(rp, off);
         mxf = max(mxf, __shfl_xor(mxf, off));
         mxg = max(mxg, __shfl_xor(mxg, off));
         qmax = max(qmax, __shfl_xor(qmax, off));
@@ -605,6 +608,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
         atomicAdd(&st->limited, a[3]);
         atomicAdd(&st->cells, a[4]);
         atomicAdd(&st->qpass_sum, qp);
+        atomicAdd(&st->row_passes, rp);
         atomicMax(&st->it_max_f, mxf);
         atomicMax(&st->it_max_g, mxg);
         atomicMax(&st->q_max, qmax);
@@ -618,10 +622,106 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
 // k3_gather: one lane per destination cell; every displacement d with
 // |d_a| <= the step's reach M is tested against the stencil of its source x
 // - d (wrapped) with the reconstruction's own predicate; a hit adds the
-// source's record with velocity d (Eq. IIE3b).
+// source's record with velocity d (Eq. IIE3b).  A workgroup takes a
+// GX x GY x 1 block of destinations; for each d_z the descriptors of the
+// source plane it needs ((GX + 2M) x (GY + 2M) cells: velocity, radius and the
+// address of the record of displacement 0 in the source tile's slot box) are
+// staged in LDS, so a candidate costs one LDS entry and the exact test.
+// Along a row of d_x the row sums of w_f c_x^k (k <= 3) and w_g c_x^k (k <= 1)
+// are formed, and the 17 moments once per row.
 // ---------------------------------------------------------------------------
+constexpr int GX = 16, GY = 8;
+constexpr int G3_ENTRY_BYTES = 40;
+
+struct RowSums {
+    double fr = 0, fx = 0, fxx = 0, fxxx = 0, gr = 0, gx = 0;
+    __device__ void add(double wf, double wg, double cx) {
+        const double w1 = cx * wf, w2 = cx * w1;
+        fr += wf; fx += w1; fxx += w2; fxxx += cx * w2;
+        gr += wg; gx += cx * wg;
+    }
+    __device__ void fold(double *acc, int dy, int dz) const {
+        const double cy = (double)dy, cz = (double)dz, c2 = cy * cy + cz * cz;
+        acc[0] += fr;
+        acc[1] += fx; acc[2] += cy * fr; acc[3] += cz * fr;
+        acc[4] += fxx; acc[5] += cy * fx; acc[6] += cz * fx;
+        acc[7] += cy * cy * fr; acc[8] += cy * cz * fr; acc[9] += cz * cz * fr;
+        // |c|^2 c_g = (c_x^2 + c_y^2 + c_z^2) c_g
+        acc[10] += fxxx + c2 * fx;
+        acc[11] += cy * fxx + c2 * cy * fr;
+        acc[12] += cz * fxx + c2 * cz * fr;
+        acc[13] += gr; acc[14] += gx; acc[15] += cy * gr; acc[16] += cz * gr;
+    }
+};
+
 template <typename T>
-__global__ void __launch_bounds__(64) k3_gather(G3 g, double *out, Buf3 b) {
+__global__ void __launch_bounds__(GX * GY) k3_gather(G3 g, double *out, Buf3 b, int M) {
+    extern __shared__ double g3_lds[];
+    if (b.flags->err) return;
+    const int W = GX + 2 * M, H = GY + 2 * M, NE = W * H;
+    double *s_ux = g3_lds, *s_uy = s_ux + NE, *s_uz = s_uy + NE;
+    long long *s_a0 = (long long *)(s_uz + NE);
+    int *s_r = (int *)(s_a0 + NE), *s_wxy = s_r + NE;
+    const int bx = (g.nx + GX - 1) / GX, by = (g.ny + GY - 1) / GY;
+    const int blk = blockIdx.x;
+    const int x0 = (blk % bx) * GX, y0 = ((blk / bx) % by) * GY, z = blk / (bx * by);
+    const int lx = threadIdx.x % GX, ly = threadIdx.x / GX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool mine = x < g.nx && y < g.ny;
+    const T *SCR = (const T *)b.scratch;
+    double acc[NM];
+#pragma unroll
+    for (int k = 0; k < NM; k++) acc[k] = 0.0;
+    unsigned long long hits = 0;
+    for (int dz = -M; dz <= M; dz++) {
+        const int sz = wrapi(z - dz, g.nz);
+        __syncthreads();
+        for (int e = threadIdx.x; e < NE; e += GX * GY) {
+            const int sx = wrapi(x0 - M + e % W, g.nx), sy = wrapi(y0 - M + e / W, g.ny);
+            const long long s = ((long long)sz * g.ny + sy) * g.nx + sx;
+            const int R = b.d.r[s];
+            s_r[e] = R;
+            if (R < 0) continue;
+            const Tile3 ti = b.tiles[(sz / TE * g.tny + sy / TE) * g.tnx + sx / TE];
+            const int loc = (sz % TE) * 16 + (sy % TE) * 4 + (sx % TE);
+            s_ux[e] = b.d.ux[s];
+            s_uy[e] = b.d.uy[s];
+            s_uz[e] = b.d.uz[s];
+            s_a0[e] = ti.base + (long long)loc * 2 -
+                      (((long long)ti.oz * ti.wy + ti.oy) * ti.wx + ti.ox) * (TN * 2);
+            s_wxy[e] = ti.wx | (ti.wy << 16);
+        }
+        __syncthreads();
+        if (!mine) continue;
+        for (int dy = -M; dy <= M; dy++) {
+            RowSums rs;
+            const int rowe = (ly - dy + M) * W + lx + M;
+            for (int dx = -M; dx <= M; dx++) {
+                const int e = rowe - dx;
+                const int R = s_r[e];
+                if (R < 0) continue;
+                if (!in_ball((double)dx, (double)dy, (double)dz, s_ux[e], s_uy[e], s_uz[e], R + 0.5)) continue;
+                const int wx = s_wxy[e] & 0xffff, wy = s_wxy[e] >> 16;
+                const T *P = SCR + s_a0[e] + (((long long)dz * wy + dy) * wx + dx) * (TN * 2);
+                rs.add((double)P[0], (double)P[1], (double)dx);
+                hits++;
+            }
+            rs.fold(acc, dy, dz);
+        }
+    }
+    if (mine) {
+        const long long o = ((long long)z * g.ny + y) * g.nx + x;
+#pragma unroll
+        for (int k = 0; k < NM; k++) out[k * g.n + o] = acc[k];
+    }
+    for (int off = 32; off > 0; off >>= 1) hits += __shfl_xor(hits, off);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&b.stats->arrivals, hits);
+}
+
+// The same without staging, for reaches whose source planes do not fit the
+// LDS: descriptors straight from global memory.
+template <typename T>
+__global__ void __launch_bounds__(64) k3_gather_wide(G3 g, double *out, Buf3 b) {
     if (b.flags->err) return;
     const int t = blockIdx.x, l = threadIdx.x;
     const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
@@ -637,33 +737,21 @@ __global__ void __launch_bounds__(64) k3_gather(G3 g, double *out, Buf3 b) {
         const int sz = wrapi(z - dz, g.nz);
         for (int dy = -M; dy <= M; dy++) {
             const int sy = wrapi(y - dy, g.ny);
-            double fr = 0, fx = 0, fxx = 0, fxxx = 0, gr = 0, gx = 0;   // row sums over d_x
+            RowSums rs;
             for (int dx = -M; dx <= M; dx++) {
                 const int sx = wrapi(x - dx, g.nx);
                 const long long s = ((long long)sz * g.ny + sy) * g.nx + sx;
                 const int R = b.d.r[s];
                 if (R < 0) continue;
                 if (!in_ball((double)dx, (double)dy, (double)dz, b.d.ux[s], b.d.uy[s], b.d.uz[s], R + 0.5)) continue;
-                const int ts = (sz / TE * g.tny + sy / TE) * g.tnx + sx / TE;
+                const Tile3 ti = b.tiles[(sz / TE * g.tny + sy / TE) * g.tnx + sx / TE];
                 const int loc = (sz % TE) * 16 + (sy % TE) * 4 + (sx % TE);
-                const Tile3 ti = b.tiles[ts];
                 const long long slot = ((long long)(dz - ti.oz) * ti.wy + (dy - ti.oy)) * ti.wx + (dx - ti.ox);
                 const T *P = SCR + ti.base + (slot * TN + loc) * 2;
-                const double wf = (double)P[0], wg = (double)P[1], cx = (double)dx;
-                fr += wf; fx += cx * wf; fxx += cx * cx * wf; fxxx += cx * cx * cx * wf;
-                gr += wg; gx += cx * wg;
+                rs.add((double)P[0], (double)P[1], (double)dx);
                 hits++;
             }
-            const double cy = (double)dy, cz = (double)dz, c2 = cy * cy + cz * cz;
-            acc[0] += fr;
-            acc[1] += fx; acc[2] += cy * fr; acc[3] += cz * fr;
-            acc[4] += fxx; acc[5] += cy * fx; acc[6] += cz * fx;
-            acc[7] += cy * cy * fr; acc[8] += cy * cz * fr; acc[9] += cz * cz * fr;
-            // |c|^2 c_g = (c_x^2 + c_y^2 + c_z^2) c_g
-            acc[10] += fxxx + c2 * fx;
-            acc[11] += cy * fxx + c2 * cy * fr;
-            acc[12] += cz * fxx + c2 * cz * fr;
-            acc[13] += gr; acc[14] += gx; acc[15] += cy * gr; acc[16] += cz * gr;
+            rs.fold(acc, dy, dz);
         }
     }
     const long long o = ((long long)z * g.ny + y) * g.nx + x;
@@ -826,15 +914,23 @@ int ctx3_read(const Ctx3 *c, void *out, int to_device) {
     return LELBM_OK;
 }
 
-// Reads flags and the step's record total (one synchronisation).
-static int read_small(Ctx3 *c, Flags *f, long long *total) {
+// Reads flags, the step's record total and its reach (one synchronisation).
+static int read_small(Ctx3 *c, Flags *f, long long *total, int *reach) {
     char *h = (char *)c->host_small;
     H3(hipMemcpyAsync(h, c->b.flags, sizeof(Flags), hipMemcpyDeviceToHost, c->stream));
     H3(hipMemcpyAsync(h + 256, c->b.total, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+    H3(hipMemcpyAsync(h + 512, c->b.maxreach, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     H3(hipStreamSynchronize(c->stream));
     memcpy(f, h, sizeof(Flags));
     memcpy(total, h + 256, sizeof(long long));
+    memcpy(reach, h + 512, sizeof(int));
     return LELBM_OK;
+}
+
+// LDS of the staged gather at reach M; 0 if it does not fit.
+static size_t gather3_lds(int M) {
+    const size_t bytes = (size_t)(GX + 2 * M) * (GY + 2 * M) * G3_ENTRY_BYTES;
+    return bytes <= 64 * 1024 ? bytes : 0;
 }
 
 int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3Failure *fail) {
@@ -857,7 +953,8 @@ int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3F
         H3(hipGetLastError());
         Flags f;
         long long total = 0;
-        int r = read_small(c, &f, &total);
+        int M = 0;
+        int r = read_small(c, &f, &total, &M);
         if (r != LELBM_OK) return r;
         if (f.err) {
             fail->err = f.err; fail->step = k; fail->node = f.node; fail->detail = f.detail;
@@ -884,14 +981,20 @@ int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3F
             hipLaunchKernelGGL(k3_epr<double>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, c->ph, (const double *)in, b, k);
         tm.end(tm.ctx, 3, s);
         tm.begin(tm.ctx, 4, s);
-        if (c->mixed)
-            hipLaunchKernelGGL(k3_gather<float>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, outm, b);
+        const size_t lds = gather3_lds(M);
+        const unsigned nblk = (unsigned)(((g.nx + GX - 1) / GX) * ((g.ny + GY - 1) / GY) * g.nz);
+        if (lds && c->mixed)
+            hipLaunchKernelGGL(k3_gather<float>, dim3(nblk), dim3(GX * GY), lds, s, g, outm, b, M);
+        else if (lds)
+            hipLaunchKernelGGL(k3_gather<double>, dim3(nblk), dim3(GX * GY), lds, s, g, outm, b, M);
+        else if (c->mixed)
+            hipLaunchKernelGGL(k3_gather_wide<float>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, outm, b);
         else
-            hipLaunchKernelGGL(k3_gather<double>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, outm, b);
+            hipLaunchKernelGGL(k3_gather_wide<double>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, outm, b);
         tm.end(tm.ctx, 4, s);
         H3(hipGetLastError());
         // a failed reconstruction leaves the step's output unwritten
-        r = read_small(c, &f, &total);
+        r = read_small(c, &f, &total, &M);
         if (r != LELBM_OK) return r;
         if (f.err) {
             fail->err = f.err; fail->step = k; fail->node = f.node; fail->detail = f.detail;
@@ -930,6 +1033,7 @@ int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3F
         st->cells = (long)ds.cells;
         st->point_passes = (long)ds.qpass_sum;
         st->arrivals = (long)ds.arrivals;
+        st->row_passes = (long)ds.row_passes;
     }
     return LELBM_OK;
 }
