@@ -958,7 +958,7 @@ static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scra
                 if (last_odd >= 0) HIPCHECK(hipStreamWaitEvent(s, c->opev[2 * last_odd], 0));
                 if (last_wide >= 0) HIPCHECK(hipStreamWaitEvent(s, c->opev[2 * last_wide + 1], 0));
             }
-            if ((r = timed(c, 6, do_wall_gather, &a)) != LELBM_OK) return r;
+            if (c->b.wflag && (r = timed(c, 6, do_wall_gather, &a)) != LELBM_OK) return r;
             if ((r = timed(c, 5, do_totals, &a)) != LELBM_OK) return r;
             c->cur ^= 1;
         }
