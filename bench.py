@@ -192,13 +192,21 @@ def l1_errors(a, b):
     }
 
 
+def kernel_source_sha():
+    """sha256 over the sources compiled into the 2D kernels, in a fixed order."""
+    h = hashlib.sha256()
+    for name in ("lelbm_kernels.hip", "lelbm_internal.h", "lelbm_mlp_dev.h"):
+        with open(os.path.join(ROOT, "paper_2508_06911_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def stored_traffic():
     """HBM traffic per launch from committed counter summaries: a line
     ``TRAFFIC {json}`` in profiles/*.md whose ``source_sha256`` equals the
-    current kernel source (any change to the kernels voids the figure)."""
-    src = os.path.join(ROOT, "paper_2508_06911_amd", "csrc", "lelbm_kernels.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    hash of the current sources of the 2D kernels (the kernel file and the
+    headers it includes: any change to them voids the figure)."""
+    sha = kernel_source_sha()
     out = {}
     for p in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(p) as f:

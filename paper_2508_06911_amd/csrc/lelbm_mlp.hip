@@ -44,13 +44,16 @@ __device__ inline void weight_grad(const unsigned short *aT, const unsigned shor
         for (int nt = 0; nt < NTO; nt++) {
             f32x4 d = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kt = 0; kt < 4; kt++) {
-                bf16x4 a, b;
-                const unsigned short *pa = aT + (16 * mt + c) * 64 + 16 * kt + r4;
-                const unsigned short *pb = bT + (16 * nt + c) * 64 + 16 * kt + r4;
+            for (int kt = 0; kt < 4; kt += 2) {
+                bf16x4 a[2], b[2];
 #pragma unroll
-                for (int i = 0; i < 4; i++) { a[i] = (short)pa[i]; b[i] = (short)pb[i]; }
-                d = mfma(a, b, d);
+                for (int h = 0; h < 2; h++) {
+                    const unsigned short *pa = aT + (16 * mt + c) * 64 + 16 * (kt + h) + r4;
+                    const unsigned short *pb = bT + (16 * nt + c) * 64 + 16 * (kt + h) + r4;
+#pragma unroll
+                    for (int i = 0; i < 4; i++) { a[h][i] = (short)pa[i]; b[h][i] = (short)pb[i]; }
+                }
+                d = mfma2(a[0], a[1], b[0], b[1], d);
             }
             // d: rows = in 16mt + r4 + i, col = out 16nt + c
 #pragma unroll
@@ -180,10 +183,10 @@ __global__ void __launch_bounds__(64) k_mlp_fwdbwd(const unsigned short *Wb, con
 #pragma unroll
         for (int nt = 0; nt < 4; nt++) d[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 4; kt++) {
-            bf16x4 a = frag_w(W2, MLP_H, mt, kt, lane);
+        for (int kt = 0; kt < 4; kt += 2) {
+            const bf16x4 a0 = frag_w(W2, MLP_H, mt, kt, lane), a1 = frag_w(W2, MLP_H, mt, kt + 1, lane);
 #pragma unroll
-            for (int nt = 0; nt < 4; nt++) d[nt] = mfma(a, dh2[kt][nt], d[nt]);
+            for (int nt = 0; nt < 4; nt++) d[nt] = mfma2(a0, a1, dh2[kt][nt], dh2[kt + 1][nt], d[nt]);
         }
 #pragma unroll
         for (int i = 0; i < 4; i++) db1[mt][i] = 0.f;

@@ -32,6 +32,20 @@ __device__ inline f32x4 mfma(const bf16x4 &a, const bf16x4 &b, const f32x4 &c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// Two K-tiles of 16 in one gfx950 16x16x32 BF16 MFMA: lane group g holds
+// the four k of tile 0 and the four k of tile 1 that it holds in the
+// 16x16x16 form, in both operands, so every product pairs the same k and
+// the sum runs over all 32.
+typedef short bf16x8s __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ inline f32x4 mfma2(const bf16x4 &a0, const bf16x4 &a1, const bf16x4 &b0, const bf16x4 &b1,
+                              const f32x4 &c) {
+    const bf16x8s a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+    const bf16x8s b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
 // A fragment of W^T (tile mt of outputs, kt of inputs) from a row-major
 // [nin][nout] BF16 weight matrix: lane l holds W[16kt+4(l/16)+i][16mt+l%16].
 __device__ inline bf16x4 frag_wT(const unsigned short *W, int nout, int mt, int kt, int lane) {
@@ -88,10 +102,10 @@ __device__ inline void mlp_forward_wave_rows(const unsigned short *Wb, const flo
 #pragma unroll
         for (int nt = 0; nt < 4; nt++) d[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 4; kt++) {
-            bf16x4 a = frag_wT(W2, MLP_H, mt, kt, lane);
+        for (int kt = 0; kt < 4; kt += 2) {
+            const bf16x4 a0 = frag_wT(W2, MLP_H, mt, kt, lane), a1 = frag_wT(W2, MLP_H, mt, kt + 1, lane);
 #pragma unroll
-            for (int nt = 0; nt < 4; nt++) d[nt] = mfma(a, h1[kt][nt], d[nt]);
+            for (int nt = 0; nt < 4; nt++) d[nt] = mfma2(a0, a1, h1[kt][nt], h1[kt + 1][nt], d[nt]);
         }
 #pragma unroll
         for (int nt = 0; nt < 4; nt++) {
@@ -104,10 +118,10 @@ __device__ inline void mlp_forward_wave_rows(const unsigned short *Wb, const flo
 #pragma unroll
     for (int nt = 0; nt < 4; nt++) y[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kt = 0; kt < 4; kt++) {
-        bf16x4 a = frag_wT(W3, MLP_OUT, 0, kt, lane);
+    for (int kt = 0; kt < 4; kt += 2) {
+        const bf16x4 a0 = frag_wT(W3, MLP_OUT, 0, kt, lane), a1 = frag_wT(W3, MLP_OUT, 0, kt + 1, lane);
 #pragma unroll
-        for (int nt = 0; nt < 4; nt++) y[nt] = mfma(a, h2[kt][nt], y[nt]);
+        for (int nt = 0; nt < 4; nt++) y[nt] = mfma2(a0, a1, h2[kt][nt], h2[kt + 1][nt], y[nt]);
     }
 #pragma unroll
     for (int nt = 0; nt < 4; nt++)
