@@ -599,6 +599,8 @@ def d3_line(a, lb, li, torch):
     for name, prec in (("fp64", lb.FP64), ("mixed", lb.MIXED)):
         stream = torch.cuda.current_stream()
         c = lb.Lelbm(cfg, m, precision=prec, stream=stream)
+        if a.scratch_budget:
+            c.set_scratch_budget(int(a.scratch_budget))
         c.step_nostats(a.warmup)
         torch.cuda.synchronize()
         c.set_timing(True)
@@ -637,7 +639,8 @@ def d3_line(a, lb, li, torch):
            "ms_per_step": out["mixed"]["ms_per_step"], "higher_is_better": True, "dtype": "f32+f64",
            "data": "synthetic",
            "config": {"workload": "3D periodic box %d^3, smooth random fields (seed %d), RT ~ 1, "
-                                  "FP32 records" % (n, a.seed)},
+                                  "FP32 records" % (n, a.seed),
+                      "scratch_budget_bytes": int(a.scratch_budget) if a.scratch_budget else 16 << 30},
            "fp64_mlups": out["fp64"]["mlups"],
            "roofline": {"bound": "alu", "achieved": out["fp64"]["epr_tflops_executed"], "peak": VALU_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": out["fp64"]["epr_frac_fp64_peak"], "traffic": None,

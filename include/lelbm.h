@@ -153,8 +153,8 @@ typedef struct {
      * LELBM_GUESS_EQ, both precisions, unrefined stencils (RT > 4/9; refined
      * ones and radii above 64 fail the step with LELBM_EREACH).  Not in 3D:
      * solids, walls, point sources, the learned guess and harvest, and
-     * lelbm_step_noalloc (LELBM_EINVAL); the record scratch holds a step's
-     * records whole (lelbm_set_scratch_budget has no effect).  lelbm_stats
+     * lelbm_step_noalloc (LELBM_EINVAL).  The records are banded over layers
+     * of 4 cells in z within lelbm_set_scratch_budget as in 2D.  lelbm_stats
      * sum[] holds mass, x and y momentum and the energy trace. */
     int nz;
 } lelbm_params;

@@ -219,32 +219,44 @@ __global__ void __launch_bounds__(64) k3_prepare(G3 g, Phys ph, const double *mo
     }
 }
 
-// Exclusive scan of the tile sizes (one workgroup) -> record offsets; the
-// total goes to b.total.
-__global__ void __launch_bounds__(1024) k3_scan(int ntiles, Buf3 b) {
-    __shared__ long long part[1024];
-    if (b.flags->err) {
-        if (threadIdx.x == 0) *b.total = 0;
-        return;
-    }
-    const int per = (ntiles + 1023) / 1024;
-    const int t0 = threadIdx.x * per, t1 = min(ntiles, t0 + per);
+// Record elements of each layer of tiles (one workgroup per layer).
+__global__ void __launch_bounds__(256) k3_layer_sizes(G3 g, Buf3 b, long long *layer) {
+    __shared__ long long part[256];
+    const int per = g.tnx * g.tny, t0 = blockIdx.x * per;
     long long s = 0;
-    for (int t = t0; t < t1; t++) s += b.tiles[t].size;
+    if (!b.flags->err)
+        for (int i = threadIdx.x; i < per; i += 256) s += b.tiles[t0 + i].size;
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) layer[blockIdx.x] = part[0];
+}
+
+// Exclusive scan of the sizes of tiles [t0, t0 + nt) (one workgroup) from
+// `base` on -> their record offsets (the tiles of one band, in its slot).
+__global__ void __launch_bounds__(1024) k3_scan(int t0, int nt, long long base, Buf3 b) {
+    __shared__ long long part[1024];
+    if (b.flags->err) return;
+    const int per = (nt + 1023) / 1024;
+    const int a0 = t0 + threadIdx.x * per, a1 = min(t0 + nt, a0 + per);
+    long long s = 0;
+    for (int t = a0; t < a1; t++) s += b.tiles[t].size;
     part[threadIdx.x] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
-        long long acc = 0;
+        long long acc = base;
         for (int i = 0; i < 1024; i++) {
             const long long v = part[i];
             part[i] = acc;
             acc += v;
         }
-        *b.total = acc;
     }
     __syncthreads();
     long long acc = part[threadIdx.x];
-    for (int t = t0; t < t1; t++) {
+    for (int t = a0; t < a1; t++) {
         b.tiles[t].base = acc;
         acc += b.tiles[t].size;
     }
@@ -465,9 +477,9 @@ __device__ inline void row_coef(const double *lf, const double *lg, double y, do
 // moment fractions rho f' and rho K RT g' (Eq. IIE3a).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, Buf3 b, int step) {
+__global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, Buf3 b, int step, int tile0) {
     if (b.flags->err) return;
-    const int t = blockIdx.x, l = threadIdx.x;
+    const int t = tile0 + blockIdx.x, l = threadIdx.x;
     const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
     const int x = tx * TE + (l & 3), y = ty * TE + ((l >> 2) & 3), z = tz * TE + (l >> 4);
     const bool valid = x < g.nx && y < g.ny && z < g.nz;
@@ -655,7 +667,7 @@ struct RowSums {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(GX * GY) k3_gather(G3 g, double *out, Buf3 b, int M) {
+__global__ void __launch_bounds__(GX * GY) k3_gather(G3 g, double *out, Buf3 b, int M, int zb) {
     extern __shared__ double g3_lds[];
     if (b.flags->err) return;
     const int W = GX + 2 * M, H = GY + 2 * M, NE = W * H;
@@ -664,7 +676,7 @@ __global__ void __launch_bounds__(GX * GY) k3_gather(G3 g, double *out, Buf3 b, 
     int *s_r = (int *)(s_a0 + NE), *s_wxy = s_r + NE;
     const int bx = (g.nx + GX - 1) / GX, by = (g.ny + GY - 1) / GY;
     const int blk = blockIdx.x;
-    const int x0 = (blk % bx) * GX, y0 = ((blk / bx) % by) * GY, z = blk / (bx * by);
+    const int x0 = (blk % bx) * GX, y0 = ((blk / bx) % by) * GY, z = zb + blk / (bx * by);
     const int lx = threadIdx.x % GX, ly = threadIdx.x / GX;
     const int x = x0 + lx, y = y0 + ly;
     const bool mine = x < g.nx && y < g.ny;
@@ -721,9 +733,9 @@ __global__ void __launch_bounds__(GX * GY) k3_gather(G3 g, double *out, Buf3 b, 
 // The same without staging, for reaches whose source planes do not fit the
 // LDS: descriptors straight from global memory.
 template <typename T>
-__global__ void __launch_bounds__(64) k3_gather_wide(G3 g, double *out, Buf3 b) {
+__global__ void __launch_bounds__(64) k3_gather_wide(G3 g, double *out, Buf3 b, int tile0) {
     if (b.flags->err) return;
-    const int t = blockIdx.x, l = threadIdx.x;
+    const int t = tile0 + blockIdx.x, l = threadIdx.x;
     const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
     const int x = tx * TE + (l & 3), y = ty * TE + ((l >> 2) & 3), z = tz * TE + (l >> 4);
     if (x >= g.nx || y >= g.ny || z >= g.nz) return;
@@ -825,7 +837,11 @@ struct Ctx3 {
     int cur;
     int nsum;                 // blocks of k3_sums
     long long persistent;     // bytes
-    void *host_small;         // pinned: flags + totals + statistics
+    void *host_small;         // pinned: flags, reach, statistics, layer sizes
+    long long *layer;         // [tnz] record elements per layer of tiles (device)
+    long long budget;         // record scratch budget (bytes)
+    Plan plan;                // bands of tile layers and their schedule (host)
+    std::vector<long long> hlayers;
 };
 
 #define H3(x)                                 \
@@ -837,7 +853,7 @@ static void free3(Ctx3 *c) {
     if (!c) return;
     Buf3 &b = c->b;
     void *ptrs[] = {b.mom[0], b.mom[1], b.d.rho, b.d.ux, b.d.uy, b.d.uz, b.d.rt, b.d.r, b.tiles, b.scratch,
-                    b.flags, b.stats, b.maxreach, b.total, b.partial};
+                    b.flags, b.stats, b.maxreach, b.total, b.partial, c->layer};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->host_small) (void)hipHostFree(c->host_small);
@@ -849,6 +865,8 @@ int ctx3_create(const lelbm_params *p, const Phys &ph, int mixed, const void *mo
     Ctx3 *c = new Ctx3();
     memset(&c->b, 0, sizeof(c->b));
     c->host_small = nullptr;
+    c->layer = nullptr;
+    c->budget = LELBM_DEFAULT_SCRATCH_BUDGET;
     G3 &g = c->g;
     g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
     g.n = (long long)g.nx * g.ny * g.nz;
@@ -872,7 +890,9 @@ int ctx3_create(const lelbm_params *p, const Phys &ph, int mixed, const void *mo
     alloc((void **)&b.maxreach, sizeof(int));
     alloc((void **)&b.total, sizeof(long long));
     alloc((void **)&b.partial, (size_t)(c->nsum + 1) * 4 * sizeof(double));
-    ok = ok && hipHostMalloc(&c->host_small, 4096, hipHostMallocDefault) == hipSuccess;
+    alloc((void **)&c->layer, (size_t)g.tnz * sizeof(long long));
+    ok = ok && hipHostMalloc(&c->host_small, 4096 + (size_t)g.tnz * sizeof(long long), hipHostMallocDefault) ==
+                   hipSuccess;
     if (!ok) { free3(c); return LELBM_ENOMEM; }
     c->persistent = (long long)2 * NM * g.n * 8 + g.n * (5 * 8 + 4) + (long long)g.ntiles * sizeof(Tile3);
     // state
@@ -914,17 +934,50 @@ int ctx3_read(const Ctx3 *c, void *out, int to_device) {
     return LELBM_OK;
 }
 
-// Reads flags, the step's record total and its reach (one synchronisation).
-static int read_small(Ctx3 *c, Flags *f, long long *total, int *reach) {
+// Reads the flags, the step's reach and, with `layers`, the record elements
+// of each layer of tiles (one synchronisation).
+static int read_small(Ctx3 *c, Flags *f, int *reach, std::vector<long long> *layers) {
     char *h = (char *)c->host_small;
     H3(hipMemcpyAsync(h, c->b.flags, sizeof(Flags), hipMemcpyDeviceToHost, c->stream));
-    H3(hipMemcpyAsync(h + 256, c->b.total, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
     H3(hipMemcpyAsync(h + 512, c->b.maxreach, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (layers)
+        H3(hipMemcpyAsync(h + 4096, c->layer, (size_t)c->g.tnz * sizeof(long long), hipMemcpyDeviceToHost,
+                          c->stream));
     H3(hipStreamSynchronize(c->stream));
     memcpy(f, h, sizeof(Flags));
-    memcpy(total, h + 256, sizeof(long long));
     memcpy(reach, h + 512, sizeof(int));
+    if (layers) {
+        layers->resize((size_t)c->g.tnz);
+        memcpy(layers->data(), h + 4096, (size_t)c->g.tnz * sizeof(long long));
+    }
     return LELBM_OK;
+}
+
+void ctx3_set_budget(Ctx3 *c, long long bytes) { c->budget = bytes; }
+
+// Bands of tile layers (the z axis, periodic) whose records fit the budget:
+// the fewest bands, each band's slot as large as its largest band; one band
+// when everything fits, bands of one layer as the last resort (then over the
+// budget).  The schedule is build_plan's: a destination layer is gathered
+// once every band within the step's reach M of it has been reconstructed,
+// and a slot is reused once no pending layer needs its band.
+static void plan3(Ctx3 *c, const std::vector<long long> &layers, int M, long long limit) {
+    const G3 &g = c->g;
+    const PlanGeom pg{g.tnz, g.tnz, TE, 0, g.nz, 1, g.tnz};
+    Plan &P = c->plan;
+    P.overlap = false;     // one stream: a freed slot is reused at once
+    for (int rows = g.tnz; rows >= 1; rows--) {
+        build_plan(pg, P, rows, M);
+        long long mx = 0;
+        for (const BandInfo &bd : P.bands) {
+            long long sz = 0;
+            for (int r = bd.row0; r < bd.row1; r++) sz += layers[(size_t)r];
+            mx = std::max(mx, sz);
+        }
+        P.slot_cap = std::max<long long>(mx, 1);
+        if ((long long)P.nslots * P.slot_cap <= limit || rows == 1) break;
+    }
+    set_bases(P);
 }
 
 // LDS of the staged gather at reach M; 0 if it does not fit.
@@ -948,53 +1001,76 @@ int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3F
         hipLaunchKernelGGL(k3_prepare, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, c->ph, (const double *)in, b, k);
         tm.end(tm.ctx, 1, s);
         tm.begin(tm.ctx, 2, s);
-        hipLaunchKernelGGL(k3_scan, dim3(1), dim3(1024), 0, s, g.ntiles, b);
+        hipLaunchKernelGGL(k3_layer_sizes, dim3((unsigned)g.tnz), dim3(256), 0, s, g, b, c->layer);
         tm.end(tm.ctx, 2, s);
         H3(hipGetLastError());
         Flags f;
-        long long total = 0;
         int M = 0;
-        int r = read_small(c, &f, &total, &M);
+        std::vector<long long> &layers = c->hlayers;
+        int r = read_small(c, &f, &M, &layers);
         if (r != LELBM_OK) return r;
         if (f.err) {
             fail->err = f.err; fail->step = k; fail->node = f.node; fail->detail = f.detail;
             fail->species = f.species; fail->residual = f.residual;
             return f.err;
         }
-        if (total > b.scratch_cap) {
+        plan3(c, layers, M, std::max<long long>(c->budget / (long long)esz, 1));
+        const Plan &P = c->plan;
+        const long long need = (long long)P.nslots * P.slot_cap;
+        if (need > b.scratch_cap) {
             if (b.scratch) H3(hipFree(b.scratch));
             b.scratch = nullptr;
             b.scratch_cap = 0;
-            const long long cap = total + total / 8;
-            if (hipMalloc(&b.scratch, (size_t)cap * esz) != hipSuccess) {
+            if (hipMalloc(&b.scratch, (size_t)need * esz) != hipSuccess) {
                 b.scratch = nullptr;
                 fail->err = LELBM_ENOMEM; fail->step = k; fail->node = -1; fail->detail = 0; fail->species = -1;
                 fail->residual = 0.0;
                 return LELBM_ENOMEM;
             }
-            b.scratch_cap = cap;
+            b.scratch_cap = need;
         }
-        tm.begin(tm.ctx, 3, s);
-        if (c->mixed)
-            hipLaunchKernelGGL(k3_epr<float>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, c->ph, (const double *)in, b, k);
-        else
-            hipLaunchKernelGGL(k3_epr<double>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, c->ph, (const double *)in, b, k);
-        tm.end(tm.ctx, 3, s);
-        tm.begin(tm.ctx, 4, s);
+        const int per = g.tnx * g.tny;
+        tm.begin(tm.ctx, 2, s);
+        for (const BandInfo &bd : P.bands)
+            hipLaunchKernelGGL(k3_scan, dim3(1), dim3(1024), 0, s, bd.row0 * per, (bd.row1 - bd.row0) * per, bd.base,
+                               b);
+        tm.end(tm.ctx, 2, s);
         const size_t lds = gather3_lds(M);
-        const unsigned nblk = (unsigned)(((g.nx + GX - 1) / GX) * ((g.ny + GY - 1) / GY) * g.nz);
-        if (lds && c->mixed)
-            hipLaunchKernelGGL(k3_gather<float>, dim3(nblk), dim3(GX * GY), lds, s, g, outm, b, M);
-        else if (lds)
-            hipLaunchKernelGGL(k3_gather<double>, dim3(nblk), dim3(GX * GY), lds, s, g, outm, b, M);
-        else if (c->mixed)
-            hipLaunchKernelGGL(k3_gather_wide<float>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, outm, b);
-        else
-            hipLaunchKernelGGL(k3_gather_wide<double>, dim3((unsigned)g.ntiles), dim3(64), 0, s, g, outm, b);
-        tm.end(tm.ctx, 4, s);
+        const int bxy = ((g.nx + GX - 1) / GX) * ((g.ny + GY - 1) / GY);
+        for (const Op &op : P.ops) {
+            if (op.kind == OP_EPR) {
+                const BandInfo &bd = P.bands[(size_t)op.a];
+                const unsigned nt = (unsigned)((bd.row1 - bd.row0) * per);
+                tm.begin(tm.ctx, 3, s);
+                if (c->mixed)
+                    hipLaunchKernelGGL(k3_epr<float>, dim3(nt), dim3(64), 0, s, g, c->ph, (const double *)in, b, k,
+                                       bd.row0 * per);
+                else
+                    hipLaunchKernelGGL(k3_epr<double>, dim3(nt), dim3(64), 0, s, g, c->ph, (const double *)in, b, k,
+                                       bd.row0 * per);
+                tm.end(tm.ctx, 3, s);
+            } else {
+                // destination layers [a, a + n): cell planes [4a, min(nz, 4(a + n)))
+                const int z0 = op.a * TE, z1 = std::min(g.nz, (op.a + op.n) * TE);
+                tm.begin(tm.ctx, 4, s);
+                if (lds && c->mixed)
+                    hipLaunchKernelGGL(k3_gather<float>, dim3((unsigned)(bxy * (z1 - z0))), dim3(GX * GY), lds, s, g,
+                                       outm, b, M, z0);
+                else if (lds)
+                    hipLaunchKernelGGL(k3_gather<double>, dim3((unsigned)(bxy * (z1 - z0))), dim3(GX * GY), lds, s, g,
+                                       outm, b, M, z0);
+                else if (c->mixed)
+                    hipLaunchKernelGGL(k3_gather_wide<float>, dim3((unsigned)(op.n * per)), dim3(64), 0, s, g, outm,
+                                       b, op.a * per);
+                else
+                    hipLaunchKernelGGL(k3_gather_wide<double>, dim3((unsigned)(op.n * per)), dim3(64), 0, s, g, outm,
+                                       b, op.a * per);
+                tm.end(tm.ctx, 4, s);
+            }
+        }
         H3(hipGetLastError());
         // a failed reconstruction leaves the step's output unwritten
-        r = read_small(c, &f, &total, &M);
+        r = read_small(c, &f, &M, nullptr);
         if (r != LELBM_OK) return r;
         if (f.err) {
             fail->err = f.err; fail->step = k; fail->node = f.node; fail->detail = f.detail;

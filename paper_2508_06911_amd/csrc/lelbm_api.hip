@@ -1206,7 +1206,10 @@ extern "C" int lelbm_kernel_times(const lelbm_ctx *c, double *ms, long *launches
 extern "C" int lelbm_set_scratch_budget(lelbm_ctx *c, long long bytes) {
     if (!c || bytes < 1) return LELBM_EINVAL;
     c->budget = bytes;
-    if (c->c3) return LELBM_OK;   // the 3D path holds one step's records whole
+    if (c->c3) {
+        ctx3_set_budget(c->c3, bytes);
+        return LELBM_OK;
+    }
     const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
     const long long limit = std::max<long long>(bytes / (long long)esz, 1);
     // the plan starts again from one band of the whole domain (the next step

@@ -237,6 +237,7 @@ int ctx3_create(const lelbm_params *p, const Phys &ph, int mixed, const void *mo
 int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3Failure *fail);
 int ctx3_read(const Ctx3 *c, void *out, int to_device);
 int ctx3_memory(const Ctx3 *c, long long *persistent, long long *scratch);
+void ctx3_set_budget(Ctx3 *c, long long bytes);   // record scratch budget (bytes): bands of tile layers beyond it
 void ctx3_destroy(Ctx3 *c);
 // statistics and arrival counts of a step (after its last gather)
 hipError_t launch_step_totals(const Geom &g, Buffers &b, hipStream_t s);
