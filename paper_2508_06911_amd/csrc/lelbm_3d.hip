@@ -77,6 +77,7 @@ struct Buf3 {
     int *maxreach;                // max over cells of max |round(u_a)| + R + 1
     long long *total;             // record elements of the step (k3_scan)
     double *partial;              // block sums of the conserved totals
+    const double *ainv;           // inverse scaled Maxwellian Hessians of the linearised start, or NULL
 };
 
 struct G3 {
@@ -344,6 +345,7 @@ template <int NB> struct Sp3 {
     double lam[NB], del[NB];
     double t, dec, phi, res, res_prev;
     int phase, nit, ls;
+    int lin;          // 1 while iterating from the linearised start
     __device__ double at(int j) const { return lam[j] + t * del[j]; }
 };
 
@@ -354,6 +356,43 @@ template <int NB> __device__ inline void sp3_init(Sp3<NB> &sp, double RT) {
     sp.lam[4] = sp.lam[7] = sp.lam[9] = 1.0 / (2.0 * RT);
     sp.t = 0.0; sp.dec = 0.0; sp.phi = 0.0; sp.res = 0.0; sp.res_prev = 0.0;
     sp.phase = 0; sp.nit = 0; sp.ls = 0;
+    sp.lin = 0;
+}
+
+// Linearised start: Eq. (IID13) plus one Newton step taken with the Hessian
+// of the continuous Maxwellian.  In units scaled by RT^(k/2) (k the order of
+// a basis function) that Hessian is the constant matrix of the moments
+// <T_i T_j> of the unit normal distribution; ainv holds its inverse (fluon
+// 19 x 19, then phonon 10 x 10), computed once on the host.  The step is
+// A~ dl~ = (equilibrium moments - targets) / RT^(k/2).
+__device__ inline void sp3_linear(Sp3<NF> &sf, Sp3<NG> &sg, const double *mf, const double *mg, double RT,
+                                  const double *ainv) {
+    const double sq = sqrt(RT);
+    const double sc[4] = {1.0, sq, RT, RT * sq};
+    double rf[NF], rg[NG];
+#pragma unroll
+    for (int j = 0; j < NF; j++) {
+        const bool diag = j == 4 || j == 7 || j == 9;
+        const double eq = j == 0 ? 1.0 : (diag ? RT : 0.0);
+        rf[j] = (eq - mf[j]) / sc[border(j)];
+        if (j < NG) rg[j] = (eq - mg[j]) / sc[border(j)];
+    }
+#pragma unroll
+    for (int i = 0; i < NF; i++) {
+        double d = 0.0;
+#pragma unroll
+        for (int j = 0; j < NF; j++) d += ainv[i * NF + j] * rf[j];
+        sf.lam[i] += d / sc[border(i)];
+    }
+#pragma unroll
+    for (int i = 0; i < NG; i++) {
+        double d = 0.0;
+#pragma unroll
+        for (int j = 0; j < NG; j++) d += ainv[NF * NF + i * NG + j] * rg[j];
+        sg.lam[i] += d / sc[border(i)];
+    }
+    sf.lin = 1;
+    sg.lin = 1;
 }
 
 // Cholesky solve of A x = r with A_ij = S[hidx(i, j)] (Eq. IID11a).
@@ -413,7 +452,7 @@ template <int NB> __device__ inline int sp3_update(Sp3<NB> &sp, const double *S,
     }
     fin = fin && isfinite(phit);
     if (sp.phase == 0) {
-        if (!fin) return -1;
+        if (!fin) return sp.lin ? 2 : -1;
         sp.phase = 1;
     } else {
         if (!(fin && (sp.dec <= 1e-8 || phit <= sp.phi - 1e-4 * sp.t * sp.dec))) {
@@ -432,6 +471,9 @@ template <int NB> __device__ inline int sp3_update(Sp3<NB> &sp, const double *S,
     for (int j = 0; j < NB; j++) res = fmax(res, fabs(r[j]) * isc[border(j)]);
     sp.res = res;
     const bool stalled = sp.nit > 0 && res <= STALL_RES && !(res < sp.res_prev);
+    // from the linearised start, an accepted update that does not lower the
+    // residual sends the solve back to Eq. (IID13)
+    if (sp.lin && sp.nit > 0 && res > tol && !stalled && !(res < sp.res_prev)) return 2;
     sp.res_prev = res;
     double dl[NB];
     if (res <= tol || stalled) {
@@ -485,7 +527,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
     const bool valid = x < g.nx && y < g.ny && z < g.nz;
     const long long s = valid ? ((long long)z * g.ny + y) * g.nx + x : 0;
     const int R = valid ? b.d.r[s] : -1;
-    int itf = 0, itg = 0, q = 0, lim = 0, passes = 0, rows = 0;
+    int itf = 0, itg = 0, q = 0, lim = 0, passes = 0, rows = 0, fb = 0;
     double kn = 0.0, RTc = 0.0;
     if (R >= 0) {
         const double rho = b.d.rho[s], ux = b.d.ux[s], uy = b.d.uy[s], uz = b.d.uz[s], RT = b.d.rt[s];
@@ -499,6 +541,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
         Sp3<NG> sg;
         sp3_init<NF>(sf, RT);
         sp3_init<NG>(sg, RT);
+        if (b.ainv) sp3_linear(sf, sg, mf, mg, RT, b.ainv);
         const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
         int fail = 0, fsp = -1;
         while (!fail && (sf.phase < 2 || sg.phase < 2)) {
@@ -553,12 +596,16 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
                 }
             }
             if (sg.phase < 2) {
-                const int r = sp3_update<NG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
+                int r = sp3_update<NG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
+                if (r < 0 && r != -3 && sg.lin) r = 2;
                 if (r < 0) { fail = -r; fsp = 1; }
+                else if (r == 2) { sp3_init<NG>(sg, RT); fb = 1; }
             }
             if (sf.phase < 2 && !fail) {
-                const int r = sp3_update<NF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
+                int r = sp3_update<NF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
+                if (r < 0 && r != -3 && sf.lin) r = 2;
                 if (r < 0) { fail = -r; fsp = 0; }
+                else if (r == 2) { sp3_init<NF>(sf, RT); fb = 1; }
             }
         }
         if (fail) {
@@ -594,15 +641,16 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
         }
     }
     // statistics of the wavefront: one set of atomics per workgroup
-    unsigned long long a[5] = {(unsigned long long)itf, (unsigned long long)itg, (unsigned long long)q,
-                               (unsigned long long)lim, (unsigned long long)(R >= 0 && q > 0 ? 1 : 0)};
+    unsigned long long a[6] = {(unsigned long long)itf, (unsigned long long)itg, (unsigned long long)q,
+                               (unsigned long long)lim, (unsigned long long)(R >= 0 && q > 0 ? 1 : 0),
+                               (unsigned long long)fb};
     unsigned long long qp = (unsigned long long)q * (unsigned long long)passes;
     unsigned long long rp = (unsigned long long)rows * (unsigned long long)passes;
     int mxf = itf, mxg = itg, qmax = q, qmin = q > 0 ? q : INT_MAX;
     double rtmin = q > 0 ? RTc : 1e300, knmax = kn;
     for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
-        for (int k = 0; k < 5; k++) a[k] += __shfl_xor(a[k], off);
+        for (int k = 0; k < 6; k++) a[k] += __shfl_xor(a[k], off);
         qp += __shfl_xor(qp, off);
         rp += __shfl_xor(rp, off);
         mxf = max(mxf, __shfl_xor(mxf, off));
@@ -619,6 +667,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
         atomicAdd(&st->q_sum, a[2]);
         atomicAdd(&st->limited, a[3]);
         atomicAdd(&st->cells, a[4]);
+        if (a[5]) atomicAdd(&st->fallbacks, a[5]);
         atomicAdd(&st->qpass_sum, qp);
         atomicAdd(&st->row_passes, rp);
         atomicMax(&st->it_max_f, mxf);
@@ -842,7 +891,41 @@ struct Ctx3 {
     long long budget;         // record scratch budget (bytes)
     Plan plan;                // bands of tile layers and their schedule (host)
     std::vector<long long> hlayers;
+    double *ainv_dev;         // the linearised start's matrices (device), or NULL
 };
+
+// Inverses of the scaled Maxwellian Hessians <T_i T_j> (unit normal
+// distribution in 3D: E[x^n] = 0 for odd n, 1, 1, 3, 15 for n = 0, 2, 4, 6)
+// of the fluon (19 x 19) and phonon (10 x 10) bases, by Gauss-Jordan
+// elimination with partial pivoting.
+static void lin_inverse(std::vector<double> &out) {
+    auto gm = [](int n) { return n % 2 ? 0.0 : (n == 0 ? 1.0 : (n == 2 ? 1.0 : (n == 4 ? 3.0 : 15.0))); };
+    out.clear();
+    for (int nb : {NF, NG}) {
+        std::vector<double> A((size_t)nb * 2 * nb, 0.0);
+        for (int i = 0; i < nb; i++) {
+            for (int j = 0; j < nb; j++)
+                A[(size_t)i * 2 * nb + j] =
+                    gm(bexp(i, 0) + bexp(j, 0)) * gm(bexp(i, 1) + bexp(j, 1)) * gm(bexp(i, 2) + bexp(j, 2));
+            A[(size_t)i * 2 * nb + nb + i] = 1.0;
+        }
+        for (int c = 0; c < nb; c++) {
+            int p = c;
+            for (int r = c + 1; r < nb; r++)
+                if (fabs(A[(size_t)r * 2 * nb + c]) > fabs(A[(size_t)p * 2 * nb + c])) p = r;
+            for (int k = 0; k < 2 * nb; k++) std::swap(A[(size_t)c * 2 * nb + k], A[(size_t)p * 2 * nb + k]);
+            const double piv = A[(size_t)c * 2 * nb + c];
+            for (int k = 0; k < 2 * nb; k++) A[(size_t)c * 2 * nb + k] /= piv;
+            for (int r = 0; r < nb; r++) {
+                if (r == c) continue;
+                const double f = A[(size_t)r * 2 * nb + c];
+                for (int k = 0; k < 2 * nb; k++) A[(size_t)r * 2 * nb + k] -= f * A[(size_t)c * 2 * nb + k];
+            }
+        }
+        for (int i = 0; i < nb; i++)
+            for (int j = 0; j < nb; j++) out.push_back(A[(size_t)i * 2 * nb + nb + j]);
+    }
+}
 
 #define H3(x)                                 \
     do {                                      \
@@ -853,7 +936,7 @@ static void free3(Ctx3 *c) {
     if (!c) return;
     Buf3 &b = c->b;
     void *ptrs[] = {b.mom[0], b.mom[1], b.d.rho, b.d.ux, b.d.uy, b.d.uz, b.d.rt, b.d.r, b.tiles, b.scratch,
-                    b.flags, b.stats, b.maxreach, b.total, b.partial, c->layer};
+                    b.flags, b.stats, b.maxreach, b.total, b.partial, c->layer, c->ainv_dev};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->host_small) (void)hipHostFree(c->host_small);
@@ -866,6 +949,7 @@ int ctx3_create(const lelbm_params *p, const Phys &ph, int mixed, const void *mo
     memset(&c->b, 0, sizeof(c->b));
     c->host_small = nullptr;
     c->layer = nullptr;
+    c->ainv_dev = nullptr;
     c->budget = LELBM_DEFAULT_SCRATCH_BUDGET;
     G3 &g = c->g;
     g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
@@ -891,6 +975,13 @@ int ctx3_create(const lelbm_params *p, const Phys &ph, int mixed, const void *mo
     alloc((void **)&b.total, sizeof(long long));
     alloc((void **)&b.partial, (size_t)(c->nsum + 1) * 4 * sizeof(double));
     alloc((void **)&c->layer, (size_t)g.tnz * sizeof(long long));
+    if (ph.lin_guess) {
+        std::vector<double> ai;
+        lin_inverse(ai);
+        alloc((void **)&c->ainv_dev, ai.size() * sizeof(double));
+        if (ok) ok = hipMemcpy(c->ainv_dev, ai.data(), ai.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+        b.ainv = c->ainv_dev;
+    }
     ok = ok && hipHostMalloc(&c->host_small, 4096 + (size_t)g.tnz * sizeof(long long), hipHostMallocDefault) ==
                    hipSuccess;
     if (!ok) { free3(c); return LELBM_ENOMEM; }
@@ -1098,6 +1189,7 @@ int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3F
         st->it_mean_g = ds.it_sum_g / cells;
         st->it_max_f = ds.it_max_f;
         st->it_max_g = ds.it_max_g;
+        st->fallbacks = (long)ds.fallbacks;
         st->limited = (long)ds.limited;
         st->q_min = ds.cells ? ds.q_min : 0;
         st->q_max = ds.q_max;

@@ -147,3 +147,26 @@ def test_banded_records_equal_one_band():
     assert np.array_equal(banded, whole)
     assert s_band <= 0.65 * s_whole
     assert rel_linf(banded, ref) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-6)])
+def test_linearised_start_matches_eq(prec, tol):
+    """The linearised Newton start (Eq. IID13 plus one step with the
+    continuous Maxwellian's Hessian) converges to the same multipliers in
+    fewer updates."""
+    import paper_2508_06911_amd as lb
+    _case("3D linearised start, precision %d, 10 x 9 x 7, 4 steps" % prec)
+    cfg, prim = li.smooth_periodic3(1, n=10, ny=9, nz=7, amp=0.08, RT=0.9)
+    m = _mom(cfg, prim)
+    outs, its = {}, {}
+    for g in (lb.GUESS_EQ, lb.GUESS_LIN):
+        c = lb.Lelbm(cfg, m, precision=prec, guess=g)
+        st = c.step(4)
+        outs[g] = c.read_moments()
+        its[g] = st["it_mean_f"] + st["it_mean_g"]
+        c.close()
+    err = rel_linf(outs[lb.GUESS_LIN], outs[lb.GUESS_EQ])
+    print("LIN vs EQ %.3g; Newton updates per cell (f + g) EQ %.2f LIN %.2f" % (err, its[lb.GUESS_EQ],
+                                                                                its[lb.GUESS_LIN]), flush=True)
+    assert err < tol
+    assert its[lb.GUESS_LIN] < its[lb.GUESS_EQ]
