@@ -138,9 +138,9 @@ def lib():
         L.orc3_collide_flat.argtypes = [P3, dp, dp]
         L.orc3_las_radius.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.orc3_las_levels.argtypes = [ctypes.c_double]
-        L.orc3_las.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, ip]
+        L.orc3_las.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp, ip]
         L.orc3_epr_initial.argtypes = [ctypes.c_int, ctypes.c_double, dp]
-        L.orc3_epr.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, ctypes.c_double, dp, ctypes.c_int, dp,
+        L.orc3_epr.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_double, dp, ctypes.c_int, dp,
                                ctypes.c_double, ctypes.c_int, dp, ip]
         L.orc3_run.argtypes = [P3, dp, dp, ctypes.c_int, ctypes.POINTER(Stats3), ip]
         _lib = L
@@ -323,32 +323,36 @@ def collide3(cfg, mom):
     return d
 
 
-def las3(u, RT, n_conf=4.0, r_min=2):
-    """3D stencil of one cell: integer points d [q, 3] (z-major, then y, x), or the status if refused."""
+def las3(u, RT, n_conf=4.0, r_min=2, full=False):
+    """3D stencil of one cell: the landing displacements d [q, 3] (base points
+    z-major, then y, x; refined children follow their parent), with full=True
+    (c [q, 3] velocities, dC [q] volumes, d), or the status if refused."""
     u = np.ascontiguousarray(u, dtype=np.float64)
     cap = 1024
     while True:
-        d = np.zeros((cap, 3), dtype=np.int32)
-        q = lib().orc3_las(_dp(u), RT, n_conf, r_min, cap, _ip(d))
+        c = np.zeros((cap, 3)); dC = np.zeros(cap); d = np.zeros((cap, 3), dtype=np.int32)
+        q = lib().orc3_las(_dp(u), RT, n_conf, r_min, cap, _dp(c), _dp(dC), _ip(d))
         if q == EREACH:
             return q
         if q >= 0:
-            return d[:q].copy()
+            return (c[:q].copy(), dC[:q].copy(), d[:q].copy()) if full else d[:q].copy()
         cap = -q
 
 
-def epr3(d, u, RT, target, lam0=None, tol=1e-12, maxit=50):
-    """3D entropic reconstruction on integer points d.  Returns (status, lambda, populations, iterations)."""
-    d = np.ascontiguousarray(d, dtype=np.int32)
-    q = d.shape[0]
+def epr3(d, u, RT, target, lam0=None, tol=1e-12, maxit=50, dC=None):
+    """3D entropic reconstruction on the points d (velocities, [q, 3]; volumes
+    dC, default 1).  Returns (status, lambda, populations, iterations)."""
+    c = np.ascontiguousarray(d, dtype=np.float64)
+    q = c.shape[0]
+    dC = np.ones(q) if dC is None else np.ascontiguousarray(dC, dtype=np.float64)
     target = np.ascontiguousarray(target, dtype=np.float64)
     nb = target.size
     u = np.ascontiguousarray(u, dtype=np.float64)
     lam = np.zeros(nb) if lam0 is None else np.ascontiguousarray(lam0, dtype=np.float64).copy()
     pop = np.zeros(q)
     it = np.zeros(1, dtype=np.int32)
-    st = lib().orc3_epr(nb, q, _ip(d), _dp(u), RT, _dp(target), 0 if lam0 is None else 1, _dp(lam), tol, maxit,
-                        _dp(pop), _ip(it))
+    st = lib().orc3_epr(nb, q, _dp(c), _dp(dC), _dp(u), RT, _dp(target), 0 if lam0 is None else 1, _dp(lam), tol,
+                        maxit, _dp(pop), _ip(it))
     return st, lam, pop, int(it[0])
 
 

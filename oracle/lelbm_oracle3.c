@@ -28,9 +28,9 @@
  * (zz|z).  Phonon constraints (10): the first ten; the second-order ones are
  * RT delta_ab (Eq. IIB17).
  *
- * Scope: fully periodic boxes and unrefined stencils.  A cell whose stencil
- * would be refined (Eq. IIC9 gives N_r > 0, i.e. RT <= 4/9) is reported as
- * ORC3_EREACH; so are radii above 64.
+ * Scope: fully periodic boxes.  Stencils are refined as in 2D (Eqs. IIC9-11
+ * with 2^3 children per refined point); more than 3 levels (RT < 0.0123) or
+ * radii above 64 are reported as ORC3_EREACH.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -241,24 +241,87 @@ int orc3_las_radius(double RT, double n_conf, int r_min)
 
 int orc3_las_levels(double RT) { return (int)rhu(1.0 / (3.0 * sqrt(RT))); }
 
-int orc3_las(const double *u, double RT, double n_conf, int r_min, int cap, int *d)
+/* Fills c[3i] (velocity), dC[i] (velocity volume) and d[3i] (landing      */
+/* displacement: the integer ancestor) for i < q and returns q, -q_needed if */
+/* cap is too small, or ORC3_EREACH.  Refinement (Eqs. IIC10-11, the 2D      */
+/* readings with D = 3): for Lvl = 1..N_r every point whose distance to u is  */
+/* at most 3 2^-Lvl is replaced by its 8 children at c + (+-h/4, +-h/4,     */
+/* +-h/4) (h its spacing), each with a volume of 1/8 of the parent's; the  */
+/* children follow the parent in the order (-,-,-), (+,-,-), (-,+,-), ...   */
+/* (x fastest).                                                             */
+int orc3_las(const double *u, double RT, double n_conf, int r_min, int cap, double *c, double *dC, int *d)
 {
-    if (orc3_las_levels(RT) > 0) return ORC3_EREACH;
+    int Nr = orc3_las_levels(RT);
     int R = orc3_las_radius(RT, n_conf, r_min);
-    if (R > 64) return ORC3_EREACH;
+    if (Nr > 3 || R > 64) return ORC3_EREACH;
     double rr = R + 0.5;
     int b[3];
     for (int a = 0; a < 3; a++) b[a] = (int)rhu(u[a]);
-    int q = 0;
+    int nbase = 0;
     for (int cz = b[2] - R - 1; cz <= b[2] + R + 1; cz++)
         for (int cy = b[1] - R - 1; cy <= b[1] + R + 1; cy++)
             for (int cx = b[0] - R - 1; cx <= b[0] + R + 1; cx++) {
                 double ex = cx - u[0], ey = cy - u[1], ez = cz - u[2];
-                if (ex * ex + ey * ey + ez * ez > rr * rr) continue;
-                if (q < cap) { d[3 * q] = cx; d[3 * q + 1] = cy; d[3 * q + 2] = cz; }
-                q++;
+                if (ex * ex + ey * ey + ez * ez <= rr * rr) nbase++;
             }
-    return q <= cap ? q : -q;
+    int nmax = nbase;
+    for (int l = 0; l < Nr; l++) nmax *= 8;
+    double *tc = malloc(sizeof(double) * 3 * nmax), *tdc = malloc(sizeof(double) * nmax);
+    double *th = malloc(sizeof(double) * nmax), *nc = malloc(sizeof(double) * 3 * nmax);
+    double *ndc = malloc(sizeof(double) * nmax), *nh = malloc(sizeof(double) * nmax);
+    int *td = malloc(sizeof(int) * 3 * nmax), *nd = malloc(sizeof(int) * 3 * nmax);
+    int q = 0;
+    if (tc && tdc && th && nc && ndc && nh && td && nd) {
+        for (int cz = b[2] - R - 1; cz <= b[2] + R + 1; cz++)
+            for (int cy = b[1] - R - 1; cy <= b[1] + R + 1; cy++)
+                for (int cx = b[0] - R - 1; cx <= b[0] + R + 1; cx++) {
+                    double ex = cx - u[0], ey = cy - u[1], ez = cz - u[2];
+                    if (ex * ex + ey * ey + ez * ez > rr * rr) continue;
+                    tc[3 * q] = cx; tc[3 * q + 1] = cy; tc[3 * q + 2] = cz;
+                    td[3 * q] = cx; td[3 * q + 1] = cy; td[3 * q + 2] = cz;
+                    tdc[q] = 1.0; th[q] = 1.0;
+                    q++;
+                }
+        for (int lvl = 1; lvl <= Nr; lvl++) {
+            double thr = 3.0 * pow(0.5, lvl);
+            int m = 0;
+            for (int i = 0; i < q; i++) {
+                double ex = tc[3 * i] - u[0], ey = tc[3 * i + 1] - u[1], ez = tc[3 * i + 2] - u[2];
+                if (sqrt(ex * ex + ey * ey + ez * ez) <= thr) {
+                    double h = th[i];
+                    for (int k = 0; k < 8; k++) {
+                        double sg[3] = {(k & 1) ? 1.0 : -1.0, (k & 2) ? 1.0 : -1.0, (k & 4) ? 1.0 : -1.0};
+                        for (int a = 0; a < 3; a++) {
+                            nc[3 * m + a] = tc[3 * i + a] + sg[a] * h / 4.0;
+                            nd[3 * m + a] = td[3 * i + a];
+                        }
+                        ndc[m] = tdc[i] / 8.0;
+                        nh[m] = h / 2.0;
+                        m++;
+                    }
+                } else {
+                    for (int a = 0; a < 3; a++) { nc[3 * m + a] = tc[3 * i + a]; nd[3 * m + a] = td[3 * i + a]; }
+                    ndc[m] = tdc[i]; nh[m] = th[i];
+                    m++;
+                }
+            }
+            double *sw;
+            int *swi;
+            sw = tc; tc = nc; nc = sw;
+            sw = tdc; tdc = ndc; ndc = sw;
+            sw = th; th = nh; nh = sw;
+            swi = td; td = nd; nd = swi;
+            q = m;
+        }
+    }
+    int ret = q <= cap ? q : -q;
+    if (q <= cap)
+        for (int i = 0; i < q; i++) {
+            for (int a = 0; a < 3; a++) { c[3 * i + a] = tc[3 * i + a]; d[3 * i + a] = td[3 * i + a]; }
+            dC[i] = tdc[i];
+        }
+    free(tc); free(tdc); free(th); free(nc); free(ndc); free(nh); free(td); free(nd);
+    return ret;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -278,19 +341,19 @@ static void basis3(int nb, const double *ct, double *T, int *order)
     for (int j = 0; j < nb; j++) { T[j] = v[j]; if (order) order[j] = o[j]; }
 }
 
-static int epr3_eval(int nb, int q, const int *d, const double *u, const double *lam, const double *target,
-                     double *pop, double *phi, double *r, double *A)
+static int epr3_eval(int nb, int q, const double *c, const double *dC, const double *u, const double *lam,
+                     const double *target, double *pop, double *phi, double *r, double *A)
 {
     double s[ORC3_NF] = {0};
     for (int i = 0; i < nb * nb; i++) A[i] = 0.0;
     double sum = 0.0;
     for (int i = 0; i < q; i++) {
-        double ct[3] = {d[3 * i] - u[0], d[3 * i + 1] - u[1], d[3 * i + 2] - u[2]};
+        double ct[3] = {c[3 * i] - u[0], c[3 * i + 1] - u[1], c[3 * i + 2] - u[2]};
         double T[ORC3_NF];
         basis3(nb, ct, T, NULL);
         double e = 0.0;
         for (int j = 0; j < nb; j++) e += lam[j] * T[j];
-        double f = exp(-(1.0 + e));
+        double f = dC[i] * exp(-(1.0 + e));
         pop[i] = f;
         sum += f;
         for (int j = 0; j < nb; j++) s[j] += T[j] * f;
@@ -340,8 +403,8 @@ void orc3_epr_initial(int nb, double RT, double *lam)
     lam[4] = lam[7] = lam[9] = 1.0 / (2.0 * RT);
 }
 
-int orc3_epr(int nb, int q, const int *d, const double *u, double RT, const double *target, int use_init,
-             double *lam, double tol, int maxit, double *pop, int *iters)
+int orc3_epr(int nb, int q, const double *c, const double *dC, const double *u, double RT, const double *target,
+             int use_init, double *lam, double tol, int maxit, double *pop, int *iters)
 {
     double r[ORC3_NF], A[ORC3_NF * ORC3_NF], dl[ORC3_NF], lt[ORC3_NF], rt[ORC3_NF], At[ORC3_NF * ORC3_NF];
     double phi, phit, Tz[ORC3_NF], zero[3] = {0, 0, 0};
@@ -350,7 +413,7 @@ int orc3_epr(int nb, int q, const int *d, const double *u, double RT, const doub
     if (!use_init) orc3_epr_initial(nb, RT, lam);
     double *popt = malloc(sizeof(double) * (q > 0 ? q : 1));
     if (!popt) return ORC3_ENOMEM;
-    if (epr3_eval(nb, q, d, u, lam, target, pop, &phi, r, A) != ORC3_OK) { free(popt); return ORC3_EEPR; }
+    if (epr3_eval(nb, q, c, dC, u, lam, target, pop, &phi, r, A) != ORC3_OK) { free(popt); return ORC3_EEPR; }
     int nit = 0;
     double res_prev = INFINITY;
     for (;;) {
@@ -369,7 +432,7 @@ int orc3_epr(int nb, int q, const int *d, const double *u, double RT, const doub
         int ok = 0;
         for (int ls = 0; ls <= 30; ls++) {
             for (int j = 0; j < nb; j++) lt[j] = lam[j] + t * dl[j];
-            int s2 = epr3_eval(nb, q, d, u, lt, target, popt, &phit, rt, At);
+            int s2 = epr3_eval(nb, q, c, dC, u, lt, target, popt, &phit, rt, At);
             if (s2 == ORC3_OK && (dec <= 1e-8 || phit <= phi - 1e-4 * t * dec)) { ok = 1; break; }
             t *= 0.5;
         }
@@ -382,7 +445,7 @@ int orc3_epr(int nb, int q, const int *d, const double *u, double RT, const doub
     if (chol3(nb, A, r, dl) != ORC3_OK) { free(popt); return ORC3_EEPR; }
     for (int j = 0; j < nb; j++) lam[j] += dl[j];
     nit++;
-    int st = epr3_eval(nb, q, d, u, lam, target, pop, &phi, r, A);
+    int st = epr3_eval(nb, q, c, dC, u, lam, target, pop, &phi, r, A);
     free(popt);
     if (st != ORC3_OK) return ORC3_EEPR;
     *iters = nit;
@@ -398,7 +461,8 @@ int orc3_epr(int nb, int q, const int *d, const double *u, double RT, const doub
 typedef struct {
     int status, q, it_f, it_g, limited;
     double RT, kn;
-    int *d;
+    int *d;              /* landing displacements (integer ancestors) */
+    double *c;           /* exact velocities */
     double *wf, *wg;
 } cell3_out;
 
@@ -411,28 +475,32 @@ static void process_cell3(const orc3_params *p, const double *mom, cell3_out *co
     co->RT = cl.RT; co->kn = cl.kn; co->limited = cl.limited;
     int cap = 512, q;
     int *d = NULL;
+    double *c = NULL, *dC = NULL;
     for (;;) {
         d = malloc(sizeof(int) * 3 * cap);
-        if (!d) { co->status = ORC3_ENOMEM; return; }
-        q = orc3_las(cl.u, cl.RT, p->n_conf, p->r_min, cap, d);
+        c = malloc(sizeof(double) * 3 * cap);
+        dC = malloc(sizeof(double) * cap);
+        if (!d || !c || !dC) { free(d); free(c); free(dC); co->status = ORC3_ENOMEM; return; }
+        q = orc3_las(cl.u, cl.RT, p->n_conf, p->r_min, cap, c, dC, d);
         if (q >= 0 || q == ORC3_EREACH) break;
-        free(d);
+        free(d); free(c); free(dC);
         cap = -q;
     }
-    if (q == ORC3_EREACH) { free(d); co->status = ORC3_EREACH; return; }
+    if (q == ORC3_EREACH) { free(d); free(c); free(dC); co->status = ORC3_EREACH; return; }
     double *pf = malloc(sizeof(double) * q), *pg = malloc(sizeof(double) * q);
     double lf[ORC3_NF], lg[ORC3_NG];
     int itf = 0, itg = 0;
-    int s1 = orc3_epr(ORC3_NF, q, d, cl.u, cl.RT, cl.m, 0, lf, p->newton_tol, p->newton_max_it, pf, &itf);
-    int s2 = orc3_epr(ORC3_NG, q, d, cl.u, cl.RT, cl.n, 0, lg, p->newton_tol, p->newton_max_it, pg, &itg);
+    int s1 = orc3_epr(ORC3_NF, q, c, dC, cl.u, cl.RT, cl.m, 0, lf, p->newton_tol, p->newton_max_it, pf, &itf);
+    int s2 = orc3_epr(ORC3_NG, q, c, dC, cl.u, cl.RT, cl.n, 0, lg, p->newton_tol, p->newton_max_it, pg, &itg);
+    free(dC);
     if (s1 != ORC3_OK || s2 != ORC3_OK) {
-        free(d); free(pf); free(pg);
+        free(d); free(c); free(pf); free(pg);
         co->status = ORC3_EEPR;
         return;
     }
     double sg = cl.rho * p->K * cl.RT;
     for (int i = 0; i < q; i++) { pf[i] *= cl.rho; pg[i] *= sg; }
-    co->q = q; co->d = d; co->wf = pf; co->wg = pg; co->it_f = itf; co->it_g = itg;
+    co->q = q; co->d = d; co->c = c; co->wf = pf; co->wg = pg; co->it_f = itf; co->it_g = itg;
     co->status = ORC3_OK;
 }
 
@@ -478,9 +546,11 @@ int orc3_step(const orc3_params *p, const double *in, double *out, orc3_stats *s
             if (o->kn > s.kn_max) s.kn_max = o->kn;
             s.limited += o->limited;
             for (int i = 0; i < o->q; i++) {
+                /* lands in the cell of its integer ancestor, with its exact velocity */
                 int cx = o->d[3 * i], cy = o->d[3 * i + 1], cz = o->d[3 * i + 2];
                 long dst = ((long)wrap3(sz + cz, nz) * ny + wrap3(sy + cy, ny)) * nx + wrap3(sx + cx, nx);
-                double c[3] = {cx, cy, cz}, cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+                double c[3] = {o->c[3 * i], o->c[3 * i + 1], o->c[3 * i + 2]};
+                double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
                 double wf = o->wf[i], wg = o->wg[i];
                 double a[ORC3_NMOM];
                 a[0] = wf;
@@ -494,7 +564,9 @@ int orc3_step(const orc3_params *p, const double *in, double *out, orc3_stats *s
                 for (int j = 0; j < ORC3_NMOM; j++) acc[(long)j * n + dst] += a[j];
             }
         }
-        for (long k = c0; k < c1; k++) { free(co[k - c0].d); free(co[k - c0].wf); free(co[k - c0].wg); }
+        for (long k = c0; k < c1; k++) {
+            free(co[k - c0].d); free(co[k - c0].c); free(co[k - c0].wf); free(co[k - c0].wg);
+        }
     }
     if (status == ORC3_OK) memcpy(out, acc, sizeof(double) * ORC3_NMOM * n);
     free(acc);

@@ -34,9 +34,55 @@ def test_stencil_is_the_ball_by_brute_force(u, RT):
     assert [tuple(p) for p in d] == pts
 
 
-def test_refined_stencils_are_refused():
-    assert oracle.las3((0.1, 0.2, 0.3), 0.44) == oracle.EREACH
-    assert oracle.las3((0.1, 0.2, 0.3), 0.45).shape[0] > 0
+def _refined_by_definition(u, RT):
+    """Eqs. (IIC9-11) with D = 3, written out independently: for each level,
+    points within 3 2^-Lvl of u split into 8 children at +-h/4 with an eighth
+    of the volume; every descendant keeps its integer ancestor."""
+    R = max(int(np.floor(4.0 * np.sqrt(RT) + 0.5)), 2)
+    Nr = int(np.floor(1.0 / (3.0 * np.sqrt(RT)) + 0.5))
+    u = np.array(u)
+    b = np.floor(u + 0.5).astype(int)
+    pts = []
+    for z in range(b[2] - R - 1, b[2] + R + 2):
+        for y in range(b[1] - R - 1, b[1] + R + 2):
+            for x in range(b[0] - R - 1, b[0] + R + 2):
+                if ((np.array([x, y, z]) - u) ** 2).sum() <= (R + 0.5) ** 2:
+                    pts.append((np.array([x, y, z], float), 1.0, 1.0, (x, y, z)))
+    for lvl in range(1, Nr + 1):
+        new = []
+        for c, dC, h, d in pts:
+            if np.sqrt(((c - u) ** 2).sum()) <= 3.0 * 0.5 ** lvl:
+                for k in range(8):
+                    sg = np.array([1 if k & 1 else -1, 1 if k & 2 else -1, 1 if k & 4 else -1])
+                    new.append((c + sg * h / 4, dC / 8, h / 2, d))
+            else:
+                new.append((c, dC, h, d))
+        pts = new
+    return pts, R, Nr
+
+
+@pytest.mark.parametrize("u,RT", [((0.3, -0.2, 0.1), 0.3), ((1.45, 0.05, -2.2), 0.1), ((0.0, 0.5, 0.25), 0.03)])
+def test_refined_stencil_by_definition(u, RT):
+    """Refined stencils (N_r = 1, 1, 2 levels here) against the definition;
+    the children's volumes add up to the base points' (the stencil covers
+    the same ball) and the children of a point are centred on it."""
+    c, dC, d = oracle.las3(u, RT, full=True)
+    ref, R, Nr = _refined_by_definition(u, RT)
+    assert Nr >= 1
+    assert len(ref) == c.shape[0]
+    for i, (rc, rdC, _, rd) in enumerate(ref):
+        assert np.abs(c[i] - rc).max() == 0.0 and dC[i] == rdC and tuple(d[i]) == rd
+    nbase = len({tuple(x) for x in d})
+    assert abs(dC.sum() - nbase) < 1e-12
+    for key in {tuple(x) for x in d}:
+        sel = np.all(d == key, axis=1)
+        assert np.abs((dC[sel][:, None] * c[sel]).sum(0) / dC[sel].sum() - np.array(key)).max() < 1e-12
+
+
+def test_refinement_beyond_three_levels_is_refused():
+    assert oracle.las3((0.1, 0.2, 0.3), 0.008) == oracle.EREACH
+    c, dC, d = oracle.las3((0.1, 0.2, 0.3), 0.01, full=True)
+    assert dC.min() == 0.5 ** 9
 
 
 # --------------------------------------------------------------------------
@@ -190,12 +236,29 @@ def test_reconstruction_matches_an_independent_minimiser(nb):
 # --------------------------------------------------------------------------
 # whole step
 # --------------------------------------------------------------------------
-def test_uniform_flow_is_invariant():
-    cfg, prim = li.smooth_periodic3(0, n=3, amp=0.0, u=(1.3, -0.7, 0.45), RT=1.4)
+@pytest.mark.parametrize("RT", [1.4, 0.3])
+def test_uniform_flow_is_invariant(RT):
+    """Uniform flow stays uniform, with unrefined (RT 1.4) and refined (RT
+    0.3, one level) stencils."""
+    cfg, prim = li.smooth_periodic3(0, n=3, amp=0.0, u=(1.3, -0.7, 0.45), RT=RT)
     m = mom3(cfg, prim)
     st, out, stats, done = oracle.step(cfg, m, 2)
     assert st == 0
     assert np.abs(out - m).max() < 1e-12 * np.abs(m).max()
+
+
+def test_conservation_with_refined_stencils():
+    """A cold state around RT = 0.4 (cells on both sides of the refinement
+    threshold 4/9): mass, momentum and energy conserved to 1e-13."""
+    cfg, prim = li.smooth_periodic3(7, n=5, ny=4, nz=3, amp=0.15, RT=0.42)
+    m = mom3(cfg, prim)
+    st, out, stats, done = oracle.step(cfg, m, 2)
+    assert st == 0
+    E = lambda a: a[4] + a[7] + a[9] + a[13]
+    for k in range(4):
+        assert abs(out[k].sum() - m[k].sum()) < 1e-13 * m[0].sum()
+    assert abs(E(out).sum() / E(m).sum() - 1) < 1e-13
+    assert stats["q_max"] > stats["q_min"]
 
 
 def test_conservation():
