@@ -150,9 +150,11 @@ typedef struct {
      * fluon constraints (1, the first and second moments and the per-axis
      * third-order pieces M~_{aa|g} of Eq. IIB14) and 10 phonon constraints.
      * Supported: periodic boxes (bc all LELBM_BC_PERIODIC, z periodic too),
-     * LELBM_GUESS_EQ, both precisions, unrefined stencils (RT > 4/9; refined
-     * ones and radii above 64 fail the step with LELBM_EREACH).  Not in 3D:
-     * solids, walls, point sources, the learned guess and harvest, and
+     * LELBM_GUESS_EQ or LELBM_GUESS_LIN, both precisions, up to 3 refinement
+     * levels (8 children per level) and radii up to 64 (beyond: LELBM_EREACH).
+     * Not in 3D:
+     * solids, walls, point sources, the learned and previous-step guesses,
+     * harvest, and
      * lelbm_step_noalloc (LELBM_EINVAL).  The records are banded over layers
      * of 4 cells in z within lelbm_set_scratch_budget as in 2D.  lelbm_stats
      * sum[] holds mass, x and y momentum and the energy trace. */

@@ -14,9 +14,13 @@
 // stencil boxes, the pair (w_f, w_g) of each of its 64 cells, so the lanes of
 // a wavefront that read one displacement read 64 consecutive pairs.
 //
-// Scope: fully periodic boxes; unrefined stencils (RT > 4/9, N_r = 0 in
-// Eq. IIC9) with radii up to 64; the Newton start of Eq. (IID13).  Other
-// cells fail the step with LELBM_EREACH.
+// Cells with refined stencils (N_r > 0 in Eq. IIC9, RT <= 4/9) go to
+// k3_epr_ref, which visits their points one by one (8 children per level)
+// and writes, per base point, the pre-summed moments of its descendants; their
+// tiles hold all 17 moments per slot.
+//
+// Scope: fully periodic boxes; up to 3 refinement levels and radii up to 64
+// (other cells fail the step with LELBM_EREACH).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -32,7 +36,7 @@ namespace lelbm {
 namespace d3 {
 
 constexpr int NF = 19, NG = 10, NMF = 84, NMG = 35, NM = 17, TN = 64, TE = 4;
-constexpr int MAX_R3 = 64;
+constexpr int MAX_R3 = 64, MAX_REFINE3 = 3;
 
 // Exponents (a, b, c) of x^a y^b z^c of the fluon basis: 1, x, y, z, xx, xy,
 // xz, yy, yz, zz, then the per-axis third-order pieces M~_{aa|g} (Eq. IIB14)
@@ -57,11 +61,12 @@ __host__ __device__ constexpr int hidx(int i, int j) {
 
 struct Desc3 {
     double *rho, *ux, *uy, *uz, *rt;   // [n]
-    int *r;                            // [n] radius R, -1: no population
+    int *r;                            // [n] R | N_r << 16 (radius, refinement levels), -1: no population
 };
 
 struct Tile3 {
     int ox, oy, oz, wx, wy, wz;   // slot box (first displacement, extents)
+    int fmt;                      // 0: (w_f, w_g) per slot and cell; 1: the 17 moments (refined cells in the tile)
     long long size;               // elements (wx wy wz x 64 cells x 2)
     long long base;               // first element in the scratch
 };
@@ -171,7 +176,7 @@ __global__ void __launch_bounds__(64) k3_prepare(G3 g, Phys ph, const double *mo
     const int x = tx * TE + (l & 3), y = ty * TE + ((l >> 2) & 3), z = tz * TE + (l >> 4);
     const bool valid = x < g.nx && y < g.ny && z < g.nz;
     int lo[3] = {1 << 29, 1 << 29, 1 << 29}, hi[3] = {-(1 << 29), -(1 << 29), -(1 << 29)};
-    int reach = 0;
+    int reach = 0, refined = 0;
     if (valid) {
         const long long s = ((long long)z * g.ny + y) * g.nx + x;
         double rho, ux, uy, uz, RT;
@@ -183,17 +188,20 @@ __global__ void __launch_bounds__(64) k3_prepare(G3 g, Phys ph, const double *mo
             flag3(b.flags, LELBM_EEPR, step, s);
         } else {
             R = radius3(RT, ph.n_conf, ph.r_min);
+            const int Nr = levels3(RT);
             const double um = fmax(fabs(ux), fmax(fabs(uy), fabs(uz)));
-            if (levels3(RT) > 0 || R > MAX_R3 || !(um <= MAX_SPEED)) {
+            if (Nr > MAX_REFINE3 || R > MAX_R3 || !(um <= MAX_SPEED)) {
                 flag3(b.flags, LELBM_EREACH, step, s);
                 R = -1;
             } else {
+                refined = Nr > 0;
                 const int ub[3] = {(int)floor(ux + 0.5), (int)floor(uy + 0.5), (int)floor(uz + 0.5)};
                 for (int a = 0; a < 3; a++) {
                     lo[a] = ub[a] - R - 1;
                     hi[a] = ub[a] + R + 1;
                     reach = max(reach, abs(ub[a]) + R + 1);
                 }
+                R |= Nr << 16;
             }
         }
         b.d.rho[s] = rho; b.d.ux[s] = ux; b.d.uy[s] = uy; b.d.uz[s] = uz; b.d.rt[s] = RT; b.d.r[s] = R;
@@ -204,15 +212,17 @@ __global__ void __launch_bounds__(64) k3_prepare(G3 g, Phys ph, const double *mo
             hi[a] = max(hi[a], __shfl_xor(hi[a], off));
         }
         reach = max(reach, __shfl_xor(reach, off));
+        refined |= __shfl_xor(refined, off);
     }
     if (l == 0) {
         Tile3 ti;
+        ti.fmt = refined;
         if (lo[0] > hi[0]) {
             ti.ox = ti.oy = ti.oz = 0; ti.wx = ti.wy = ti.wz = 0; ti.size = 0;
         } else {
             ti.ox = lo[0]; ti.oy = lo[1]; ti.oz = lo[2];
             ti.wx = hi[0] - lo[0] + 1; ti.wy = hi[1] - lo[1] + 1; ti.wz = hi[2] - lo[2] + 1;
-            ti.size = (long long)ti.wx * ti.wy * ti.wz * TN * 2;
+            ti.size = (long long)ti.wx * ti.wy * ti.wz * TN * (refined ? NM : 2);
         }
         ti.base = 0;
         b.tiles[t] = ti;
@@ -495,6 +505,114 @@ template <int NB> __device__ inline int sp3_update(Sp3<NB> &sp, const double *S,
     return 0;
 }
 
+// Moments (Eq. IIE3b) of one arrival with velocity c and moment fractions
+// (w_f, w_g), in the stored order.
+__device__ inline void moments17(double cx, double cy, double cz, double wf, double wg, double *mo) {
+    const double c[3] = {cx, cy, cz}, cc = cx * cx + cy * cy + cz * cz;
+    mo[0] = wf;
+    int k = 4;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        mo[1 + a] = c[a] * wf;
+        mo[10 + a] = cc * c[a] * wf;
+        mo[14 + a] = c[a] * wg;
+#pragma unroll
+        for (int bb = a; bb < 3; bb++) mo[k++] = c[a] * c[bb] * wf;
+    }
+    mo[13] = wg;
+}
+
+// Statistics of a wavefront's cells: one set of atomics per wavefront.
+__device__ inline void stats3(DevStats *st, int itf, int itg, int q, int lim, int fb, int passes, int rows, double RT,
+                              double kn, int l) {
+    unsigned long long a[6] = {(unsigned long long)itf, (unsigned long long)itg, (unsigned long long)q,
+                               (unsigned long long)lim, (unsigned long long)(q > 0 ? 1 : 0), (unsigned long long)fb};
+    unsigned long long qp = (unsigned long long)q * (unsigned long long)passes;
+    unsigned long long rp = (unsigned long long)rows * (unsigned long long)passes;
+    int mxf = itf, mxg = itg, qmax = q, qmin = q > 0 ? q : INT_MAX;
+    double rtmin = q > 0 ? RT : 1e300, knmax = kn;
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) a[k] += __shfl_xor(a[k], off);
+        qp += __shfl_xor(qp, off);
+        rp += __shfl_xor(rp, off);
+        mxf = max(mxf, __shfl_xor(mxf, off));
+        mxg = max(mxg, __shfl_xor(mxg, off));
+        qmax = max(qmax, __shfl_xor(qmax, off));
+        qmin = min(qmin, __shfl_xor(qmin, off));
+        rtmin = fmin(rtmin, __shfl_xor(rtmin, off));
+        knmax = fmax(knmax, __shfl_xor(knmax, off));
+    }
+    if (l == 0 && a[4] > 0) {
+        atomicAdd(&st->it_sum_f, a[0]);
+        atomicAdd(&st->it_sum_g, a[1]);
+        atomicAdd(&st->q_sum, a[2]);
+        atomicAdd(&st->limited, a[3]);
+        atomicAdd(&st->cells, a[4]);
+        if (a[5]) atomicAdd(&st->fallbacks, a[5]);
+        atomicAdd(&st->qpass_sum, qp);
+        atomicAdd(&st->row_passes, rp);
+        atomicMax(&st->it_max_f, mxf);
+        atomicMax(&st->it_max_g, mxg);
+        atomicMax(&st->q_max, qmax);
+        atomicMin(&st->q_min, qmin);
+        atomicMin(&st->rt_min_bits, (unsigned long long)__double_as_longlong(rtmin));
+        atomicMax(&st->kn_max_bits, (unsigned long long)__double_as_longlong(knmax));
+    }
+}
+
+__device__ inline double dist3(double cx, double cy, double cz, double ux, double uy, double uz) {
+#pragma clang fp contract(off)
+    const double ex = cx - ux, ey = cy - uy, ez = cz - uz;
+    return sqrt(ex * ex + ey * ey + ez * ez);
+}
+
+// Stencil enumeration with refinement (Eqs. IIC10-11 with D = 3): the base
+// points of the ball row by row; a point within 3 2^-Lvl of u is replaced by
+// its 8 children at +-h/4 (x, then y, then z sign bits), each with an eighth
+// of its volume, for Lvl up to N_r.  leaf(c_x, c_y, c_z, dC) gets the exact
+// velocity and volume; parent_end(d_x, d_y, d_z) follows the last leaf of a
+// base point (all of whose descendants land at its displacement).
+template <typename Leaf, typename End>
+__device__ inline void for_each_point3(double ux, double uy, double uz, int R, int Nr, Leaf &&leaf, End &&parent_end) {
+    const double rr = R + 0.5;
+    const int ubx = (int)floor(ux + 0.5), uby = (int)floor(uy + 0.5), ubz = (int)floor(uz + 0.5);
+    const int xlo = ubx - R - 1, xhi = ubx + R + 1;
+    for (int cz = ubz - R - 1; cz <= ubz + R + 1; cz++) {
+        for (int cy = uby - R - 1; cy <= uby + R + 1; cy++) {
+            int xa, xb;
+            if (!span3(cy, cz, ux, uy, uz, rr, xlo, xhi, xa, xb)) continue;
+            for (int cx = xa; cx <= xb; cx++) {
+                const double fx = cx, fy = cy, fz = cz;
+                if (Nr == 0 || dist3(fx, fy, fz, ux, uy, uz) > 1.5) {
+                    leaf(fx, fy, fz, 1.0);
+                } else {
+                    for (int k1 = 0; k1 < 8; k1++) {
+                        const double ax = fx + ((k1 & 1) ? 0.25 : -0.25), ay = fy + ((k1 & 2) ? 0.25 : -0.25),
+                                     az = fz + ((k1 & 4) ? 0.25 : -0.25);
+                        if (Nr < 2 || dist3(ax, ay, az, ux, uy, uz) > 0.75) {
+                            leaf(ax, ay, az, 0.125);
+                            continue;
+                        }
+                        for (int k2 = 0; k2 < 8; k2++) {
+                            const double bx = ax + ((k2 & 1) ? 0.125 : -0.125), by = ay + ((k2 & 2) ? 0.125 : -0.125),
+                                         bz = az + ((k2 & 4) ? 0.125 : -0.125);
+                            if (Nr < 3 || dist3(bx, by, bz, ux, uy, uz) > 0.375) {
+                                leaf(bx, by, bz, 0.015625);
+                                continue;
+                            }
+                            for (int k3 = 0; k3 < 8; k3++)
+                                leaf(bx + ((k3 & 1) ? 0.0625 : -0.0625), by + ((k3 & 2) ? 0.0625 : -0.0625),
+                                     bz + ((k3 & 4) ? 0.0625 : -0.0625), 0.001953125);
+                        }
+                    }
+                }
+                parent_end(cx, cy, cz);
+            }
+        }
+    }
+}
+
 // Polynomial coefficients of the exponent along a stencil row (y, z fixed):
 // sum_j l_j T_j = C0 + C1 x + C2 x^2 + C3 x^3 (fluon), D0 + D1 x + D2 x^2
 // (phonon).
@@ -526,10 +644,11 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
     const int x = tx * TE + (l & 3), y = ty * TE + ((l >> 2) & 3), z = tz * TE + (l >> 4);
     const bool valid = x < g.nx && y < g.ny && z < g.nz;
     const long long s = valid ? ((long long)z * g.ny + y) * g.nx + x : 0;
-    const int R = valid ? b.d.r[s] : -1;
+    const int rn = valid ? b.d.r[s] : -1;
+    const int R = rn & 0xffff;
     int itf = 0, itg = 0, q = 0, lim = 0, passes = 0, rows = 0, fb = 0;
     double kn = 0.0, RTc = 0.0;
-    if (R >= 0) {
+    if (rn >= 0 && (rn >> 16) == 0) {
         const double rho = b.d.rho[s], ux = b.d.ux[s], uy = b.d.uy[s], uz = b.d.uz[s], RT = b.d.rt[s];
         RTc = RT;
         double mf[NF], mg[NG];
@@ -630,9 +749,18 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
                         const double xx = (double)cx - ux;
                         const double f = exp(-(1.0 + (C[0] + xx * (C[1] + xx * (C[2] + xx * C[3])))));
                         const double gv = exp(-(1.0 + (Dg[0] + xx * (Dg[1] + xx * Dg[2]))));
-                        const long long e = ((row + cx) * TN + l) * 2;
-                        __builtin_nontemporal_store((T)(wsf * f), &P[e]);
-                        __builtin_nontemporal_store((T)(wsg * gv), &P[e + 1]);
+                        const double wf = wsf * f, wg = wsg * gv;
+                        if (ti.fmt == 0) {
+                            const long long e = ((row + cx) * TN + l) * 2;
+                            __builtin_nontemporal_store((T)wf, &P[e]);
+                            __builtin_nontemporal_store((T)wg, &P[e + 1]);
+                        } else {
+                            double mo[NM];
+                            moments17((double)cx, (double)cy, (double)cz, wf, wg, mo);
+                            const long long e = ((row + cx) * TN + l) * NM;
+#pragma unroll
+                            for (int k = 0; k < NM; k++) P[e + k] = (T)mo[k];
+                        }
                         q++;
                     }
                 }
@@ -640,43 +768,137 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
             passes++;
         }
     }
-    // statistics of the wavefront: one set of atomics per workgroup
-    unsigned long long a[6] = {(unsigned long long)itf, (unsigned long long)itg, (unsigned long long)q,
-                               (unsigned long long)lim, (unsigned long long)(R >= 0 && q > 0 ? 1 : 0),
-                               (unsigned long long)fb};
-    unsigned long long qp = (unsigned long long)q * (unsigned long long)passes;
-    unsigned long long rp = (unsigned long long)rows * (unsigned long long)passes;
-    int mxf = itf, mxg = itg, qmax = q, qmin = q > 0 ? q : INT_MAX;
-    double rtmin = q > 0 ? RTc : 1e300, knmax = kn;
-    for (int off = 32; off > 0; off >>= 1) {
+    stats3(b.stats, itf, itg, q, lim, fb, passes, rows, RTc, kn, l);
+}
+
+// ---------------------------------------------------------------------------
+// k3_epr_ref: cells with refined stencils (their tiles only), one lane per
+// cell, every point visited with direct exponentials of the full basis
+// polynomials; the final pass writes, per base point, the 17 moments of its
+// descendants' moment fractions with their exact velocities.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(64) k3_epr_ref(G3 g, Phys ph, const double *mom, Buf3 b, int step, int tile0) {
+    __shared__ int s_skip;
+    const int t = tile0 + blockIdx.x, l = threadIdx.x;
+    if (l == 0) s_skip = b.flags->err || !b.tiles[t].fmt;
+    __syncthreads();
+    if (s_skip) return;
+    const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
+    const int x = tx * TE + (l & 3), y = ty * TE + ((l >> 2) & 3), z = tz * TE + (l >> 4);
+    const bool valid = x < g.nx && y < g.ny && z < g.nz;
+    const long long s = valid ? ((long long)z * g.ny + y) * g.nx + x : 0;
+    const int rn = valid ? b.d.r[s] : -1;
+    const int R = rn & 0xffff, Nr = rn >> 16;
+    int itf = 0, itg = 0, q = 0, lim = 0, passes = 0, fb = 0;
+    double kn = 0.0, RTc = 0.0;
+    if (rn >= 0 && Nr > 0) {
+        const double rho = b.d.rho[s], ux = b.d.ux[s], uy = b.d.uy[s], uz = b.d.uz[s], RT = b.d.rt[s];
+        RTc = RT;
+        double mf[NF], mg[NG];
+        collide3(ph, mom, g.n, s, rho, ux, uy, uz, RT, mf, mg, kn, lim);
+        Sp3<NF> sf;
+        Sp3<NG> sg;
+        sp3_init<NF>(sf, RT);
+        sp3_init<NG>(sg, RT);
+        if (b.ainv) sp3_linear(sf, sg, mf, mg, RT, b.ainv);
+        const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
+        int fail = 0, fsp = -1;
+        while (!fail && (sf.phase < 2 || sg.phase < 2)) {
+            passes++;
+            double Sf[NMF], Sg[NMG], lf[NF], lg[NG];
 #pragma unroll
-        for (int k = 0; k < 6; k++) a[k] += __shfl_xor(a[k], off);
-        qp += __shfl_xor(qp, off);
-        rp += __shfl_xor(rp, off);
-        mxf = max(mxf, __shfl_xor(mxf, off));
-        mxg = max(mxg, __shfl_xor(mxg, off));
-        qmax = max(qmax, __shfl_xor(qmax, off));
-        qmin = min(qmin, __shfl_xor(qmin, off));
-        rtmin = fmin(rtmin, __shfl_xor(rtmin, off));
-        knmax = fmax(knmax, __shfl_xor(knmax, off));
+            for (int k = 0; k < NMF; k++) Sf[k] = 0.0;
+#pragma unroll
+            for (int k = 0; k < NMG; k++) Sg[k] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
+#pragma unroll
+            for (int j = 0; j < NG; j++) lg[j] = sg.at(j);
+            for_each_point3(
+                ux, uy, uz, R, Nr,
+                [&](double cx, double cy, double cz, double dC) {
+                    double px[7], py[7], pz[7];
+                    px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+                    for (int k = 1; k < 7; k++) {
+                        px[k] = px[k - 1] * (cx - ux);
+                        py[k] = py[k - 1] * (cy - uy);
+                        pz[k] = pz[k - 1] * (cz - uz);
+                    }
+                    double ef = 0.0, eg = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NF; j++) ef += lf[j] * (px[bexp(j, 0)] * py[bexp(j, 1)] * pz[bexp(j, 2)]);
+#pragma unroll
+                    for (int j = 0; j < NG; j++) eg += lg[j] * (px[bexp(j, 0)] * py[bexp(j, 1)] * pz[bexp(j, 2)]);
+                    const double f = dC * exp(-(1.0 + ef)), gv = dC * exp(-(1.0 + eg));
+#pragma unroll
+                    for (int a = 0; a < 7; a++)
+#pragma unroll
+                        for (int bb = 0; bb + a < 7; bb++)
+#pragma unroll
+                            for (int c = 0; c + bb + a < 7; c++) {
+                                const double m = px[a] * (py[bb] * pz[c]);
+                                Sf[mono(a, bb, c)] += f * m;
+                                if (a + bb + c <= 4) Sg[mono(a, bb, c)] += gv * m;
+                            }
+                },
+                [](int, int, int) {});
+            if (sg.phase < 2) {
+                int r = sp3_update<NG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
+                if (r < 0 && r != -3 && sg.lin) r = 2;
+                if (r < 0) { fail = -r; fsp = 1; }
+                else if (r == 2) { sp3_init<NG>(sg, RT); fb = 1; }
+            }
+            if (sf.phase < 2 && !fail) {
+                int r = sp3_update<NF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
+                if (r < 0 && r != -3 && sf.lin) r = 2;
+                if (r < 0) { fail = -r; fsp = 0; }
+                else if (r == 2) { sp3_init<NF>(sf, RT); fb = 1; }
+            }
+        }
+        if (fail) {
+            flag3(b.flags, LELBM_EEPR, step, s, fail, fsp, fsp ? sg.res : sf.res);
+        } else {
+            itf = sf.nit;
+            itg = sg.nit;
+            const double wsf = rho, wsg = rho * ph.K * RT;
+            const Tile3 ti = b.tiles[t];
+            T *P = (T *)b.scratch + ti.base;
+            double acc[NM];
+#pragma unroll
+            for (int k = 0; k < NM; k++) acc[k] = 0.0;
+            for_each_point3(
+                ux, uy, uz, R, Nr,
+                [&](double cx, double cy, double cz, double dC) {
+                    const double x1 = cx - ux, y1 = cy - uy, z1 = cz - uz;
+                    const double px[4] = {1.0, x1, x1 * x1, x1 * x1 * x1}, py[4] = {1.0, y1, y1 * y1, y1 * y1 * y1},
+                                 pz[4] = {1.0, z1, z1 * z1, z1 * z1 * z1};
+                    double ef = 0.0, eg = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NF; j++)
+                        ef += sf.lam[j] * (px[bexp(j, 0)] * py[bexp(j, 1)] * pz[bexp(j, 2)]);
+#pragma unroll
+                    for (int j = 0; j < NG; j++)
+                        eg += sg.lam[j] * (px[bexp(j, 0)] * py[bexp(j, 1)] * pz[bexp(j, 2)]);
+                    double mo[NM];
+                    moments17(cx, cy, cz, wsf * (dC * exp(-(1.0 + ef))), wsg * (dC * exp(-(1.0 + eg))), mo);
+#pragma unroll
+                    for (int k = 0; k < NM; k++) acc[k] += mo[k];
+                    q++;
+                },
+                [&](int dx, int dy, int dz) {
+                    const long long slot = ((long long)(dz - ti.oz) * ti.wy + (dy - ti.oy)) * ti.wx + (dx - ti.ox);
+#pragma unroll
+                    for (int k = 0; k < NM; k++) {
+                        P[(slot * TN + l) * NM + k] = (T)acc[k];
+                        acc[k] = 0.0;
+                    }
+                });
+            passes++;
+        }
     }
-    if (l == 0 && a[4] > 0) {
-        DevStats *st = b.stats;
-        atomicAdd(&st->it_sum_f, a[0]);
-        atomicAdd(&st->it_sum_g, a[1]);
-        atomicAdd(&st->q_sum, a[2]);
-        atomicAdd(&st->limited, a[3]);
-        atomicAdd(&st->cells, a[4]);
-        if (a[5]) atomicAdd(&st->fallbacks, a[5]);
-        atomicAdd(&st->qpass_sum, qp);
-        atomicAdd(&st->row_passes, rp);
-        atomicMax(&st->it_max_f, mxf);
-        atomicMax(&st->it_max_g, mxg);
-        atomicMax(&st->q_max, qmax);
-        atomicMin(&st->q_min, qmin);
-        atomicMin(&st->rt_min_bits, (unsigned long long)__double_as_longlong(rtmin));
-        atomicMax(&st->kn_max_bits, (unsigned long long)__double_as_longlong(knmax));
-    }
+    stats3(b.stats, itf, itg, q, lim, fb, passes, 0, RTc, kn, l);
 }
 
 // ---------------------------------------------------------------------------
@@ -740,16 +962,20 @@ __global__ void __launch_bounds__(GX * GY) k3_gather(G3 g, double *out, Buf3 b, 
         for (int e = threadIdx.x; e < NE; e += GX * GY) {
             const int sx = wrapi(x0 - M + e % W, g.nx), sy = wrapi(y0 - M + e / W, g.ny);
             const long long s = ((long long)sz * g.ny + sy) * g.nx + sx;
-            const int R = b.d.r[s];
-            s_r[e] = R;
-            if (R < 0) continue;
+            const int rn = b.d.r[s];
+            if (rn < 0) {
+                s_r[e] = -1;
+                continue;
+            }
             const Tile3 ti = b.tiles[(sz / TE * g.tny + sy / TE) * g.tnx + sx / TE];
             const int loc = (sz % TE) * 16 + (sy % TE) * 4 + (sx % TE);
+            const long long rs = ti.fmt ? NM : 2;
+            s_r[e] = (rn & 0xffff) | (ti.fmt << 20);
             s_ux[e] = b.d.ux[s];
             s_uy[e] = b.d.uy[s];
             s_uz[e] = b.d.uz[s];
-            s_a0[e] = ti.base + (long long)loc * 2 -
-                      (((long long)ti.oz * ti.wy + ti.oy) * ti.wx + ti.ox) * (TN * 2);
+            s_a0[e] = ti.base + (long long)loc * rs -
+                      (((long long)ti.oz * ti.wy + ti.oy) * ti.wx + ti.ox) * (TN * rs);
             s_wxy[e] = ti.wx | (ti.wy << 16);
         }
         __syncthreads();
@@ -759,13 +985,21 @@ __global__ void __launch_bounds__(GX * GY) k3_gather(G3 g, double *out, Buf3 b, 
             const int rowe = (ly - dy + M) * W + lx + M;
             for (int dx = -M; dx <= M; dx++) {
                 const int e = rowe - dx;
-                const int R = s_r[e];
-                if (R < 0) continue;
-                if (!in_ball((double)dx, (double)dy, (double)dz, s_ux[e], s_uy[e], s_uz[e], R + 0.5)) continue;
+                const int m = s_r[e];
+                if (m < 0) continue;
+                if (!in_ball((double)dx, (double)dy, (double)dz, s_ux[e], s_uy[e], s_uz[e], (m & 0xffff) + 0.5))
+                    continue;
                 const int wx = s_wxy[e] & 0xffff, wy = s_wxy[e] >> 16;
+                hits++;
+                if (m >> 20) {
+                    // pre-summed moments of a refined source's base point
+                    const T *P = SCR + s_a0[e] + (((long long)dz * wy + dy) * wx + dx) * (TN * NM);
+#pragma unroll
+                    for (int k = 0; k < NM; k++) acc[k] += (double)P[k];
+                    continue;
+                }
                 const T *P = SCR + s_a0[e] + (((long long)dz * wy + dy) * wx + dx) * (TN * 2);
                 rs.add((double)P[0], (double)P[1], (double)dx);
-                hits++;
             }
             rs.fold(acc, dy, dz);
         }
@@ -802,15 +1036,22 @@ __global__ void __launch_bounds__(64) k3_gather_wide(G3 g, double *out, Buf3 b, 
             for (int dx = -M; dx <= M; dx++) {
                 const int sx = wrapi(x - dx, g.nx);
                 const long long s = ((long long)sz * g.ny + sy) * g.nx + sx;
-                const int R = b.d.r[s];
-                if (R < 0) continue;
-                if (!in_ball((double)dx, (double)dy, (double)dz, b.d.ux[s], b.d.uy[s], b.d.uz[s], R + 0.5)) continue;
+                const int rn = b.d.r[s];
+                if (rn < 0) continue;
+                if (!in_ball((double)dx, (double)dy, (double)dz, b.d.ux[s], b.d.uy[s], b.d.uz[s], (rn & 0xffff) + 0.5))
+                    continue;
                 const Tile3 ti = b.tiles[(sz / TE * g.tny + sy / TE) * g.tnx + sx / TE];
                 const int loc = (sz % TE) * 16 + (sy % TE) * 4 + (sx % TE);
                 const long long slot = ((long long)(dz - ti.oz) * ti.wy + (dy - ti.oy)) * ti.wx + (dx - ti.ox);
+                hits++;
+                if (ti.fmt) {
+                    const T *P = SCR + ti.base + (slot * TN + loc) * NM;
+#pragma unroll
+                    for (int k = 0; k < NM; k++) acc[k] += (double)P[k];
+                    continue;
+                }
                 const T *P = SCR + ti.base + (slot * TN + loc) * 2;
                 rs.add((double)P[0], (double)P[1], (double)dx);
-                hits++;
             }
             rs.fold(acc, dy, dz);
         }
@@ -1140,6 +1381,14 @@ int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3F
                     hipLaunchKernelGGL(k3_epr<double>, dim3(nt), dim3(64), 0, s, g, c->ph, (const double *)in, b, k,
                                        bd.row0 * per);
                 tm.end(tm.ctx, 3, s);
+                tm.begin(tm.ctx, 7, s);
+                if (c->mixed)
+                    hipLaunchKernelGGL(k3_epr_ref<float>, dim3(nt), dim3(64), 0, s, g, c->ph, (const double *)in, b,
+                                       k, bd.row0 * per);
+                else
+                    hipLaunchKernelGGL(k3_epr_ref<double>, dim3(nt), dim3(64), 0, s, g, c->ph, (const double *)in, b,
+                                       k, bd.row0 * per);
+                tm.end(tm.ctx, 7, s);
             } else {
                 // destination layers [a, a + n): cell planes [4a, min(nz, 4(a + n)))
                 const int z0 = op.a * TE, z1 = std::min(g.nz, (op.a + op.n) * TE);

@@ -111,10 +111,10 @@ def test_shear_viscosity_64():
     assert abs(nu_m / nu - 1) < 0.01
 
 
-def test_refined_stencils_are_refused():
+def test_refinement_beyond_three_levels_is_refused():
     import paper_2508_06911_amd as lb
-    _case("3D refined stencil refused")
-    cfg, prim = li.smooth_periodic3(4, n=4, amp=0.0, RT=0.4)
+    _case("3D stencil beyond three refinement levels refused")
+    cfg, prim = li.smooth_periodic3(4, n=4, amp=0.0, RT=0.008)
     ctx = lb.Lelbm(cfg, _mom(cfg, prim))
     with pytest.raises(lb.LelbmError) as e:
         ctx.step(1)
@@ -170,3 +170,24 @@ def test_linearised_start_matches_eq(prec, tol):
                                                                                 its[lb.GUESS_LIN]), flush=True)
     assert err < tol
     assert its[lb.GUESS_LIN] < its[lb.GUESS_EQ]
+
+
+@pytest.mark.parametrize("prec,tol,RT,amp,seed", [(0, 1e-10, 0.42, 0.15, 6), (1, 1e-6, 0.42, 0.15, 6),
+                                                  (0, 1e-10, 0.03, 0.05, 8)])
+def test_refined_stencils_parity(prec, tol, RT, amp, seed):
+    """Cold boxes with refined stencils (Eqs. IIC9-11, 8 children per level):
+    around RT = 0.42 cells on both sides of the threshold 4/9 share tiles (all
+    moments per slot), at RT ~ 0.03 every cell is refined twice."""
+    import paper_2508_06911_amd as lb
+    _case("3D refined stencils RT %.2f precision %d, 8 x 7 x 6, 3 steps" % (RT, prec))
+    cfg, prim = li.smooth_periodic3(seed, n=8, ny=7, nz=6, amp=amp, RT=RT)
+    ref, rs = _oracle(cfg, prim, 3)
+    ctx = lb.Lelbm(cfg, _mom(cfg, prim), precision=prec)
+    st = ctx.step(3)
+    out = ctx.read_moments()
+    ctx.close()
+    err = rel_linf(out, ref)
+    print("rel Linf vs oracle %.3g; q min/mean/max %d / %.1f / %d (oracle %d / %.1f / %d)"
+          % (err, st["q_min"], st["q_mean"], st["q_max"], rs["q_min"], rs["q_mean"], rs["q_max"]), flush=True)
+    assert err < tol
+    assert st["q_max"] == rs["q_max"] and st["q_min"] == rs["q_min"]
