@@ -66,6 +66,7 @@ class Params3(ctypes.Structure):
         ("newton_tol", ctypes.c_double), ("newton_max_it", ctypes.c_int),
         ("kn_limiter", ctypes.c_int),
         ("kn_lo", ctypes.c_double), ("kn_hi", ctypes.c_double), ("omega_H", ctypes.c_double),
+        ("open", ctypes.c_int),
     ]
 
 
@@ -278,7 +279,9 @@ def epr(dim, c, dC, u, RT, target, lam0=None, tol=1e-12, maxit=50):
 
 
 def make_params3(cfg):
-    """3D oracle parameter struct (periodic box) from a configuration dict."""
+    """3D oracle parameter struct from a configuration dict (a periodic box,
+    or with ``open`` true a window with no sources outside it whose outgoing
+    populations are dropped)."""
     p = Params3()
     p.nx, p.ny, p.nz = cfg["nx"], cfg["ny"], cfg["nz"]
     p.K = cfg["K"]
@@ -289,6 +292,7 @@ def make_params3(cfg):
     p.newton_max_it = cfg.get("newton_max_it", 50)
     p.kn_limiter = cfg.get("kn_limiter", 1)
     p.kn_lo, p.kn_hi, p.omega_H = cfg.get("kn_lo", -2.0), cfg.get("kn_hi", -1.0), cfg.get("omega_H", 1.0)
+    p.open = 1 if cfg.get("open") else 0
     return p
 
 

@@ -28,9 +28,12 @@
  * (zz|z).  Phonon constraints (10): the first ten; the second-order ones are
  * RT delta_ab (Eq. IIB17).
  *
- * Scope: fully periodic boxes.  Stencils are refined as in 2D (Eqs. IIC9-11
- * with 2^3 children per refined point); more than 3 levels (RT < 0.0123) or
- * radii above 64 are reported as ORC3_EREACH.
+ * Scope: fully periodic boxes, or an open box (a window cut out of a larger
+ * domain: it has no sources outside, and populations landing outside it are
+ * dropped; only cells farther than the reach from its faces see the step of
+ * the larger domain).  Stencils are refined as in 2D (Eqs. IIC9-11 with 2^3
+ * children per refined point); more than 3 levels (RT < 0.0123) or radii
+ * above 64 are reported as ORC3_EREACH.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -46,7 +49,7 @@
 
 enum { ORC3_OK = 0, ORC3_EINVAL = -1, ORC3_ENOMEM = -2, ORC3_EEPR = -4, ORC3_ENONFINITE = -5, ORC3_EREACH = -6 };
 
-/* Parameters of one 3D run (periodic box).  Mirrored by the Python wrapper. */
+/* Parameters of one 3D run.  Mirrored by the Python wrapper. */
 typedef struct {
     int nx, ny, nz;
     double K;
@@ -57,6 +60,7 @@ typedef struct {
     int newton_max_it;
     int kn_limiter;
     double kn_lo, kn_hi, omega_H;
+    int open;            /* 0: periodic box; 1: open box (window, see above) */
 } orc3_params;
 
 typedef struct {
@@ -453,10 +457,10 @@ int orc3_epr(int nb, int q, const double *c, const double *dC, const double *u, 
 }
 
 /* ------------------------------------------------------------------------ */
-/* One step on a periodic box: every cell collides, reconstructs both species */
-/* on its stencil and deposits the moment fractions rho f' and rho K RT g'    */
-/* (Eq. IIE3a) of each point at x + c (wrapped) with velocity c (Eq. IIE3b).  */
-/* Serial, source-major deposit.                                              */
+/* One step: every cell collides, reconstructs both species on its stencil   */
+/* and deposits the moment fractions rho f' and rho K RT g' (Eq. IIE3a) of   */
+/* each point at x + c (wrapped on a periodic box, dropped outside an open    */
+/* one) with velocity c (Eq. IIE3b).  Serial, source-major deposit.           */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int status, q, it_f, it_g, limited;
@@ -547,8 +551,9 @@ int orc3_step(const orc3_params *p, const double *in, double *out, orc3_stats *s
             s.limited += o->limited;
             for (int i = 0; i < o->q; i++) {
                 /* lands in the cell of its integer ancestor, with its exact velocity */
-                int cx = o->d[3 * i], cy = o->d[3 * i + 1], cz = o->d[3 * i + 2];
-                long dst = ((long)wrap3(sz + cz, nz) * ny + wrap3(sy + cy, ny)) * nx + wrap3(sx + cx, nx);
+                int tx = sx + o->d[3 * i], ty = sy + o->d[3 * i + 1], tz = sz + o->d[3 * i + 2];
+                if (p->open && (tx < 0 || tx >= nx || ty < 0 || ty >= ny || tz < 0 || tz >= nz)) continue;
+                long dst = ((long)wrap3(tz, nz) * ny + wrap3(ty, ny)) * nx + wrap3(tx, nx);
                 double c[3] = {o->c[3 * i], o->c[3 * i + 1], o->c[3 * i + 2]};
                 double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
                 double wf = o->wf[i], wg = o->wg[i];

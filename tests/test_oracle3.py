@@ -273,6 +273,32 @@ def test_conservation():
     assert stats["it_max_f"] < 8 and stats["q_min"] > 0
 
 
+def test_open_window_equals_the_periodic_box_inside():
+    """An open box cut out of a periodic one (no sources outside it, its
+    outgoing populations dropped): after one step every cell farther than the
+    largest landing displacement from the window's faces equals the periodic
+    box's result bit for bit (same sources, summed in the same order); cells
+    nearer the faces have lost arrivals, so the window's mass drops."""
+    n = 20
+    cfg, prim = li.smooth_periodic3(4, n=n, amp=0.08, RT=0.9)
+    m = mom3(cfg, prim)
+    st, ref, _, _ = oracle.step(cfg, m, 1)
+    assert st == 0
+    R = max(int(np.floor(4 * np.sqrt(prim["RT"].max()) + 0.5)), 2)      # Eq. (IIC6) radius, r_min 2
+    reach = int(np.ceil(max(np.abs(prim[k]).max() for k in ("ux", "uy", "uz")) + R + 0.5))
+    lo, W = 2, 16
+    win = m.reshape(17, n, n, n)[:, lo:lo + W, lo:lo + W, lo:lo + W].reshape(17, -1)
+    wc = dict(cfg, nx=W, ny=W, nz=W, open=True)
+    st, out, _, _ = oracle.step(wc, win, 1)
+    assert st == 0
+    inner = slice(reach, W - reach)
+    assert W - 2 * reach >= 2
+    a = out.reshape(17, W, W, W)[:, inner, inner, inner]
+    b = ref.reshape(17, n, n, n)[:, lo:lo + W, lo:lo + W, lo:lo + W][:, inner, inner, inner]
+    assert np.array_equal(a, b)
+    assert out[0].sum() < win[0].sum() * (1 - 1e-3)
+
+
 def _fields(m, shape):
     return m.reshape(17, *shape)
 
