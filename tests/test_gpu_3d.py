@@ -1,8 +1,10 @@
 """The 3D step (D = 3, periodic boxes) on the HIP path: element-wise parity
 with the 3D oracle in both precisions on boxes of several ragged tiles,
 across step calls, exact conservation and a uniform flow at size, the
-shear viscosity at a resolution the oracle would need minutes for, and the
-refusal of refined stencils."""
+shear viscosity at a resolution the oracle would need minutes for, refined
+stencils, banded records, the linearised start, stencils beyond three
+refinement levels refused, and the full 96^3 box in the launch configuration
+of the 3D benchmark compared on sampled windows."""
 import numpy as np
 import pytest
 
@@ -191,3 +193,53 @@ def test_refined_stencils_parity(prec, tol, RT, amp, seed):
           % (err, st["q_min"], st["q_mean"], st["q_max"], rs["q_min"], rs["q_mean"], rs["q_max"]), flush=True)
     assert err < tol
     assert st["q_max"] == rs["q_max"] and st["q_min"] == rs["q_min"]
+
+
+def _reach(m, K):
+    """Largest landing displacement per axis of any cell's stencil: |u_a| + R
+    + 1/2 with R = round(4 sqrt(RT)) (Eq. IIC6, r_min 2), RT the larger of the
+    translational and the phonon temperature, plus one cell of margin."""
+    rho = m[0]
+    u = m[1:4] / rho
+    rt_tr = ((m[4] + m[7] + m[9]) / rho - (u * u).sum(axis=0)) / 3
+    rt = max(rt_tr.max(), (m[13] / (rho * K)).max())
+    R = max(int(np.floor(4 * np.sqrt(rt) + 0.5)), 2)
+    return int(np.ceil(np.abs(u).max() + R + 0.5)) + 1
+
+
+@pytest.mark.parametrize("prec,guess,tol", [(1, "lin", 1e-6), (0, "eq", 1e-10)])
+def test_full_size_box_sampled_windows(prec, guess, tol):
+    """The 96^3 box of the 3D benchmark (seed 10, RT ~ 1, default scratch
+    budget, the benchmark's precision and Newton start): after two GPU steps,
+    a third is compared on sampled windows (one across the periodic corner)
+    with an oracle step of the same window as an open box; cells farther
+    than the reach from the window's faces only receive from inside it."""
+    import paper_2508_06911_amd as lb
+    _case("3D 96^3 sampled windows, precision %d, guess %s" % (prec, guess))
+    n = 96
+    cfg, prim = li.smooth_periodic3(10, n=n, amp=0.1, RT=1.0)
+    g = lb.GUESS_LIN if guess == "lin" else lb.GUESS_EQ
+    c = lb.Lelbm(cfg, _mom(cfg, prim), precision=prec, guess=g)
+    c.step(2)
+    mk = c.read_moments()
+    c.step(1)
+    mk1 = c.read_moments()
+    c.close()
+    reach = _reach(mk, cfg["K"])
+    W = 2 * reach + 6
+    rng = np.random.default_rng(1)
+    corners = [(n - W // 2, n - W // 2, n - W // 2), (n // 2 - W // 2,) * 3]
+    corners += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(3)]
+    mk = mk.reshape(17, n, n, n)
+    mk1 = mk1.reshape(17, n, n, n)
+    inner = slice(reach, W - reach)
+    for x0, y0, z0 in corners:
+        xs, ys, zs = [np.arange(v, v + W) % n for v in (x0, y0, z0)]
+        win = mk[:, zs][:, :, ys][:, :, :, xs].reshape(17, -1)
+        st, out, _, _ = oracle.step(dict(cfg, nx=W, ny=W, nz=W, open=True), win, 1)
+        assert st == 0
+        out = out.reshape(17, W, W, W)[:, inner, inner, inner].reshape(17, -1)
+        ref = mk1[:, zs[inner]][:, :, ys[inner]][:, :, :, xs[inner]].reshape(17, -1)
+        err = rel_linf(ref, out)
+        print("window at (%d, %d, %d), %d^3 compared: rel Linf %.3g" % (x0, y0, z0, W - 2 * reach, err), flush=True)
+        assert err < tol
