@@ -36,6 +36,7 @@ import argparse
 import glob
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -86,19 +87,23 @@ def epr_flops_per_step(st, steps):
             + FLOPS_EVAL * evals + FLOPS_CELL * st["cells"]) / steps
 
 
-# FP64 work of the 3D reconstruction kernel (k3_epr) as written, per unit:
-#   78 per point and Newton evaluation: the cubic and quadratic exponents
-#      (5 multiply-adds), two exponentials (~22 each), x^1..x^6 and x^1..x^4
-#      (10 multiplies) and 12 row-sum updates
-#   56 per point of the final pass: the exponents, two exponentials, two
-#      weights
-#  500 per stencil row and pass: the exponents' row coefficients (29 terms),
-#      the row's span, y and z powers, and folding the row sums into the
-#      84 + 35 monomial sums (a product and a multiply-add each)
-# 6000 per evaluation: the 19x19 and 10x10 Hessians, their Cholesky
-#      factorisations and solves
+# FP64 work of the 3D reconstruction kernel (k3_epr) as written, per unit
+# (a multiply-add counts 2):
+#   28 per point and Newton evaluation: x, the five product recurrences, x^1..x^6
+#      and x^1..x^4 (10 multiplies) and 12 row-sum updates
+#    8 per point of the final pass: x, the recurrences, two weights
+#  370 per stencil row and pass: the exponents' row coefficients (29 terms), the
+#      row's span, y powers, folding the row sums into the 28 + 15 plane sums,
+#      and the recurrences' start values (their polynomials and five
+#      exponentials of ~22)
+#  250 per stencil plane and pass: z powers and folding the plane sums into
+#      the 84 + 35 monomial sums; planes are not counted by the step
+#      statistics and are taken as rows x 2 / (pi (R + 1/2)) (the planes and
+#      rows of a ball), with R + 1/2 from the mean stencil size
+# 6050 per evaluation: the 19x19 and 10x10 Hessians, their Cholesky
+#      factorisations and solves, the two constant recurrence factors
 #  300 per cell: collision
-FLOPS3_POINT_EVAL, FLOPS3_POINT_FINAL, FLOPS3_ROW, FLOPS3_EVAL, FLOPS3_CELL = 78, 56, 500, 6000, 300
+FLOPS3_POINT_EVAL, FLOPS3_POINT_FINAL, FLOPS3_ROW, FLOPS3_PLANE, FLOPS3_EVAL, FLOPS3_CELL = 28, 8, 370, 250, 6050, 300
 
 
 def epr3_flops_per_step(st, steps):
@@ -106,8 +111,10 @@ def epr3_flops_per_step(st, steps):
     q = st["q_mean"] * st["cells"]
     eval_points = max(st["point_passes"] - q, 0.0)
     evals = max(st["point_passes"] / max(st["q_mean"], 1e-30) - st["cells"], 0.0)
+    radius = (3.0 * st["q_mean"] / (4.0 * math.pi)) ** (1.0 / 3.0)
+    planes = st["row_passes"] * 2.0 / (math.pi * max(radius, 1.0))
     return (FLOPS3_POINT_EVAL * eval_points + FLOPS3_POINT_FINAL * q + FLOPS3_ROW * st["row_passes"]
-            + FLOPS3_EVAL * evals + FLOPS3_CELL * st["cells"]) / steps
+            + FLOPS3_PLANE * planes + FLOPS3_EVAL * evals + FLOPS3_CELL * st["cells"]) / steps
 
 
 # Algorithmic bytes of the gather: per arriving stencil point the (w_f, w_g)
@@ -646,9 +653,9 @@ def d3_line(a, lb, li, torch):
                                   "FP32 records, linearised Newton start" % (n, a.seed),
                       "scratch_budget_bytes": int(a.scratch_budget) if a.scratch_budget else 16 << 30},
            "fp64_mlups": out["fp64"]["mlups"],
-           "roofline": {"bound": "alu", "achieved": out["fp64"]["epr_tflops_executed"], "peak": VALU_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": out["fp64"]["epr_frac_fp64_peak"], "traffic": None,
-                        "kernel": "k3_epr<double> (FP64 path)"},
+           "roofline": {"bound": "alu", "achieved": out["mixed-lin"]["epr_tflops_executed"],
+                        "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": out["mixed-lin"]["epr_frac_fp64_peak"],
+                        "traffic": None, "kernel": "k3_epr<float> (FP32 records, linearised start)"},
            "cpu_baseline": {"value": round(16 ** 3 * 4 / el / 1e6, 5), "unit": "MLUPS", "cores": oracle.num_threads(),
                             "kind": "oracle", "sample": "16^3 box of the same kind, 4 steps (%.1f s)" % el,
                             "status": code},

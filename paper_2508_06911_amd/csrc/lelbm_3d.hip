@@ -628,13 +628,39 @@ __device__ inline void row_coef(const double *lf, const double *lg, double y, do
     for (int j = 0; j < NG; j++) Dg[bexp(j, 0)] += lg[j] * (py[bexp(j, 1)] * pz[bexp(j, 2)]);
 }
 
+// Product recurrences along a row.  With E(x) = -(1 + C0 + C1 x + C2 x^2 +
+// C3 x^3) and H(x) = -(1 + D0 + D1 x + D2 x^2), unit steps in x multiply
+// f = exp(E) by r = exp(E(x + 1) - E(x)), r by s2 = exp of the second
+// difference and s2 by exp(-6 C3); g = exp(H) by rg, and rg by exp(-2 D2).
+// row_start3 sets the five values at x0 by direct exponentials.
+constexpr int REC3 = 16;   // points between direct restarts of a row's recurrences
+
+__device__ inline void row_start3(const double *C, const double *Dg, double x0, double &f, double &r, double &s2,
+                                  double &gv, double &rg) {
+    f = exp(-(1.0 + (C[0] + x0 * (C[1] + x0 * (C[2] + x0 * C[3])))));
+    r = exp(-(C[1] + C[2] * (2.0 * x0 + 1.0) + C[3] * (3.0 * x0 * (x0 + 1.0) + 1.0)));
+    s2 = exp(-(2.0 * C[2] + C[3] * (6.0 * x0 + 6.0)));
+    gv = exp(-(1.0 + (Dg[0] + x0 * (Dg[1] + x0 * Dg[2]))));
+    rg = exp(-(Dg[1] + Dg[2] * (2.0 * x0 + 1.0)));
+}
+
+// Start values in the normal range: products of them stay finite over a
+// segment; otherwise the row's points are evaluated directly.
+__device__ inline bool rec3_ok(double f, double r, double s2, double gv, double rg) {
+    const double lo = 1e-280, hi = 1e280;
+    return f > lo && f < hi && r > lo && r < hi && s2 > lo && s2 < hi && gv > lo && gv < hi && rg > lo && rg < hi;
+}
+
 // ---------------------------------------------------------------------------
 // k3_epr: one lane per cell.  A pass walks the stencil row by row (z, then
-// y); along a row the exponents are polynomials in x, the populations are
-// direct exponentials and the row accumulates sum f x^a (a <= 6) and sum g
-// x^a (a <= 4), folded once per row into the monomial sums (degree <= 6 and
-// <= 4) that give the residuals and Hessians.  The final pass writes the
-// moment fractions rho f' and rho K RT g' (Eq. IIE3a).
+// y); along a row the exponents are polynomials in x, the populations follow
+// the product recurrences above (restarted every REC3 points) and the row
+// accumulates sum f x^a (a <= 6) and sum g x^a (a <= 4); these are folded
+// with the powers of y once per row into plane sums (sum f x^a y^b, a + b <=
+// 6 and <= 4), and those with the powers of z once per plane into the
+// monomial sums (degree <= 6 and <= 4) that give the residuals and Hessians.
+// The final pass writes the moment fractions rho f' and rho K RT g' (Eq.
+// IIE3a).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, Buf3 b, int step, int tile0) {
@@ -674,19 +700,37 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
             for (int j = 0; j < NF; j++) lf[j] = sf.at(j);
 #pragma unroll
             for (int j = 0; j < NG; j++) lg[j] = sg.at(j);
+            // third and second differences of the exponents along x (basis
+            // terms xxx and xx): the same on every row
+            const double t3 = exp(-6.0 * lf[10]), sg2 = exp(-2.0 * lg[4]);
             for (int cz = ubz - R - 1; cz <= ubz + R + 1; cz++) {
                 const double zz = (double)cz - uz;
+                double Pf[28], Pg[15];   // plane sums, index (a + b)(a + b + 1)/2 + b
+#pragma unroll
+                for (int k = 0; k < 28; k++) Pf[k] = 0.0;
+#pragma unroll
+                for (int k = 0; k < 15; k++) Pg[k] = 0.0;
+                bool any = false;
                 for (int cy = uby - R - 1; cy <= uby + R + 1; cy++) {
                     int xa, xb;
                     if (!span3(cy, cz, ux, uy, uz, rr, xlo, xhi, xa, xb)) continue;
+                    any = true;
                     const double yy = (double)cy - uy;
                     double C[4], Dg[3];
                     row_coef(lf, lg, yy, zz, C, Dg);
                     double Rf[7] = {0, 0, 0, 0, 0, 0, 0}, Rg[5] = {0, 0, 0, 0, 0};
+                    double f, r, s2, gv, rg;
+                    bool direct = false;
                     for (int cx = xa; cx <= xb; cx++) {
                         const double xx = (double)cx - ux;
-                        const double f = exp(-(1.0 + (C[0] + xx * (C[1] + xx * (C[2] + xx * C[3])))));
-                        const double gv = exp(-(1.0 + (Dg[0] + xx * (Dg[1] + xx * Dg[2]))));
+                        if (((cx - xa) & (REC3 - 1)) == 0) {
+                            row_start3(C, Dg, xx, f, r, s2, gv, rg);
+                            direct = !rec3_ok(f, r, s2, gv, rg);
+                        }
+                        if (direct) {
+                            f = exp(-(1.0 + (C[0] + xx * (C[1] + xx * (C[2] + xx * C[3])))));
+                            gv = exp(-(1.0 + (Dg[0] + xx * (Dg[1] + xx * Dg[2]))));
+                        }
                         double p = f;
                         Rf[0] += p;
 #pragma unroll
@@ -695,24 +739,39 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
                         Rg[0] += p;
 #pragma unroll
                         for (int a = 1; a < 5; a++) { p *= xx; Rg[a] += p; }
+                        f *= r; r *= s2; s2 *= t3;
+                        gv *= rg; rg *= sg2;
                     }
-                    double py[7], pz[7];
-                    py[0] = 1.0; pz[0] = 1.0;
+                    double py[7];
+                    py[0] = 1.0;
 #pragma unroll
-                    for (int k = 1; k < 7; k++) { py[k] = py[k - 1] * yy; pz[k] = pz[k - 1] * zz; }
+                    for (int k = 1; k < 7; k++) py[k] = py[k - 1] * yy;
 #pragma unroll
                     for (int a = 0; a < 7; a++)
 #pragma unroll
-                        for (int bb = 0; bb + a < 7; bb++)
-#pragma unroll
-                            for (int c = 0; c + bb + a < 7; c++) Sf[mono(a, bb, c)] += Rf[a] * (py[bb] * pz[c]);
+                        for (int bb = 0; bb + a < 7; bb++) Pf[(a + bb) * (a + bb + 1) / 2 + bb] += Rf[a] * py[bb];
 #pragma unroll
                     for (int a = 0; a < 5; a++)
 #pragma unroll
-                        for (int bb = 0; bb + a < 5; bb++)
-#pragma unroll
-                            for (int c = 0; c + bb + a < 5; c++) Sg[mono(a, bb, c)] += Rg[a] * (py[bb] * pz[c]);
+                        for (int bb = 0; bb + a < 5; bb++) Pg[(a + bb) * (a + bb + 1) / 2 + bb] += Rg[a] * py[bb];
                 }
+                if (!any) continue;
+                double pz[7];
+                pz[0] = 1.0;
+#pragma unroll
+                for (int k = 1; k < 7; k++) pz[k] = pz[k - 1] * zz;
+#pragma unroll
+                for (int a = 0; a < 7; a++)
+#pragma unroll
+                    for (int bb = 0; bb + a < 7; bb++)
+#pragma unroll
+                        for (int c = 0; c + bb + a < 7; c++) Sf[mono(a, bb, c)] += Pf[(a + bb) * (a + bb + 1) / 2 + bb] * pz[c];
+#pragma unroll
+                for (int a = 0; a < 5; a++)
+#pragma unroll
+                    for (int bb = 0; bb + a < 5; bb++)
+#pragma unroll
+                        for (int c = 0; c + bb + a < 5; c++) Sg[mono(a, bb, c)] += Pg[(a + bb) * (a + bb + 1) / 2 + bb] * pz[c];
             }
             if (sg.phase < 2) {
                 int r = sp3_update<NG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
@@ -735,6 +794,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
             const double wsf = rho, wsg = rho * ph.K * RT;
             const Tile3 ti = b.tiles[t];
             T *P = (T *)b.scratch + ti.base;
+            const double t3 = exp(-6.0 * sf.lam[10]), sg2 = exp(-2.0 * sg.lam[4]);
             for (int cz = ubz - R - 1; cz <= ubz + R + 1; cz++) {
                 const double zz = (double)cz - uz;
                 for (int cy = uby - R - 1; cy <= uby + R + 1; cy++) {
@@ -745,10 +805,18 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
                     double C[4], Dg[3];
                     row_coef(sf.lam, sg.lam, yy, zz, C, Dg);
                     const long long row = ((long long)(cz - ti.oz) * ti.wy + (cy - ti.oy)) * ti.wx - ti.ox;
+                    double f, r, s2, gv, rg;
+                    bool direct = false;
                     for (int cx = xa; cx <= xb; cx++) {
                         const double xx = (double)cx - ux;
-                        const double f = exp(-(1.0 + (C[0] + xx * (C[1] + xx * (C[2] + xx * C[3])))));
-                        const double gv = exp(-(1.0 + (Dg[0] + xx * (Dg[1] + xx * Dg[2]))));
+                        if (((cx - xa) & (REC3 - 1)) == 0) {
+                            row_start3(C, Dg, xx, f, r, s2, gv, rg);
+                            direct = !rec3_ok(f, r, s2, gv, rg);
+                        }
+                        if (direct) {
+                            f = exp(-(1.0 + (C[0] + xx * (C[1] + xx * (C[2] + xx * C[3])))));
+                            gv = exp(-(1.0 + (Dg[0] + xx * (Dg[1] + xx * Dg[2]))));
+                        }
                         const double wf = wsf * f, wg = wsg * gv;
                         if (ti.fmt == 0) {
                             const long long e = ((row + cx) * TN + l) * 2;
@@ -761,6 +829,8 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
 #pragma unroll
                             for (int k = 0; k < NM; k++) P[e + k] = (T)mo[k];
                         }
+                        f *= r; r *= s2; s2 *= t3;
+                        gv *= rg; rg *= sg2;
                         q++;
                     }
                 }
