@@ -977,14 +977,22 @@ __global__ void __launch_bounds__(64) k3_epr_ref(G3 g, Phys ph, const double *mo
 // - d (wrapped) with the reconstruction's own predicate; a hit adds the
 // source's record with velocity d (Eq. IIE3b).  A workgroup takes a
 // GX x GY x 1 block of destinations; for each d_z the descriptors of the
-// source plane it needs ((GX + 2M) x (GY + 2M) cells: velocity, radius and the
-// address of the record of displacement 0 in the source tile's slot box) are
-// staged in LDS, so a candidate costs one LDS entry and the exact test.
-// Along a row of d_x the row sums of w_f c_x^k (k <= 3) and w_g c_x^k (k <= 1)
-// are formed, and the 17 moments once per row.
+// source plane it needs ((GX + 2M) x (GY + 2M) cells: velocity, the test's
+// terms that do not depend on d_x and d_y, and the address of the source's
+// record of displacement (0, 0, d_z)) are staged in LDS, with the bounds of
+// the plane's velocities and radii, which narrow each row of d_x to the
+// displacements some source can reach.  Along a row of d_x the row sums of
+// w_f c_x^k (k <= 3) and w_g c_x^k (k <= 1) are formed, and the 17 moments
+// once per row.
 // ---------------------------------------------------------------------------
-constexpr int GX = 16, GY = 8;
-constexpr int G3_ENTRY_BYTES = 40;
+constexpr int GX = 16, GY = 16;
+constexpr int G3_ENTRY_BYTES = 48;
+constexpr int G3U = 4;   // candidates per batch in the gather
+
+// The (w_f, w_g) pair of a record, read as one load.
+template <typename T> struct Pair3;
+template <> struct Pair3<double> { using type = double2; };
+template <> struct Pair3<float> { using type = float2; };
 
 struct RowSums {
     double fr = 0, fx = 0, fxx = 0, fxxx = 0, gr = 0, gx = 0;
@@ -1008,13 +1016,17 @@ struct RowSums {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(GX * GY) k3_gather(G3 g, double *out, Buf3 b, int M, int zb) {
+__global__ void __launch_bounds__(GX * GY, 4) k3_gather(G3 g, double *out, Buf3 b, int M, int zb) {
     extern __shared__ double g3_lds[];
     if (b.flags->err) return;
     const int W = GX + 2 * M, H = GY + 2 * M, NE = W * H;
-    double *s_ux = g3_lds, *s_uy = s_ux + NE, *s_uz = s_uy + NE;
-    long long *s_a0 = (long long *)(s_uz + NE);
-    int *s_r = (int *)(s_a0 + NE), *s_wxy = s_r + NE;
+    // per staged source of the plane d_z: u_x, u_y, (d_z - u_z)^2, (R + 1/2)^2
+    // (-1: no source, or one with all-moment records), the address of its
+    // record of displacement (0, 0, d_z), the slot box row length w_x, and
+    // R | fmt << 20 (-1: no source) for the sources with all-moment records
+    double *s_ux = g3_lds, *s_uy = s_ux + NE, *s_ez2 = s_uy + NE, *s_rr2 = s_ez2 + NE;
+    long long *s_a0 = (long long *)(s_rr2 + NE);
+    int *s_r = (int *)(s_a0 + NE), *s_wx = s_r + NE;
     const int bx = (g.nx + GX - 1) / GX, by = (g.ny + GY - 1) / GY;
     const int blk = blockIdx.x;
     const int x0 = (blk % bx) * GX, y0 = ((blk / bx) % by) * GY, z = zb + blk / (bx * by);
@@ -1026,50 +1038,123 @@ __global__ void __launch_bounds__(GX * GY) k3_gather(G3 g, double *out, Buf3 b, 
 #pragma unroll
     for (int k = 0; k < NM; k++) acc[k] = 0.0;
     unsigned long long hits = 0;
+    // bounds of the staged sources' velocities (in 1/1024 cells, rounded
+    // outwards) and their largest radius: a row (d_y, d_z) can only hold hits
+    // with |d_x - u_x| <= sqrt(rr^2 - dist(d_y, [u_y])^2 - dist(d_z, [u_z])^2)
+    __shared__ int s_bnd[8];   // [7]: some staged source has all-moment records
     for (int dz = -M; dz <= M; dz++) {
         const int sz = wrapi(z - dz, g.nz);
         __syncthreads();
+        if (threadIdx.x == 0) {
+            s_bnd[0] = s_bnd[2] = s_bnd[4] = INT_MAX;
+            s_bnd[1] = s_bnd[3] = s_bnd[5] = INT_MIN;
+            s_bnd[6] = -1;
+            s_bnd[7] = 0;
+        }
+        __syncthreads();
+        int bl[3] = {INT_MAX, INT_MAX, INT_MAX}, bh[3] = {INT_MIN, INT_MIN, INT_MIN}, brm = -1, anyref = 0;
         for (int e = threadIdx.x; e < NE; e += GX * GY) {
             const int sx = wrapi(x0 - M + e % W, g.nx), sy = wrapi(y0 - M + e / W, g.ny);
             const long long s = ((long long)sz * g.ny + sy) * g.nx + sx;
             const int rn = b.d.r[s];
             if (rn < 0) {
                 s_r[e] = -1;
+                s_ux[e] = 0.0; s_uy[e] = 0.0; s_ez2[e] = 0.0; s_rr2[e] = -1.0;
+                s_a0[e] = 0; s_wx[e] = 0;
                 continue;
             }
+            const double uu[3] = {b.d.ux[s], b.d.uy[s], b.d.uz[s]};
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                bl[k] = min(bl[k], (int)floor(uu[k] * 1024.0));
+                bh[k] = max(bh[k], (int)ceil(uu[k] * 1024.0));
+            }
+            brm = max(brm, rn & 0xffff);
             const Tile3 ti = b.tiles[(sz / TE * g.tny + sy / TE) * g.tnx + sx / TE];
             const int loc = (sz % TE) * 16 + (sy % TE) * 4 + (sx % TE);
             const long long rs = ti.fmt ? NM : 2;
+            const double rr = (double)(rn & 0xffff) + 0.5, ez = (double)dz - uu[2];
             s_r[e] = (rn & 0xffff) | (ti.fmt << 20);
-            s_ux[e] = b.d.ux[s];
-            s_uy[e] = b.d.uy[s];
-            s_uz[e] = b.d.uz[s];
-            s_a0[e] = ti.base + (long long)loc * rs -
-                      (((long long)ti.oz * ti.wy + ti.oy) * ti.wx + ti.ox) * (TN * rs);
-            s_wxy[e] = ti.wx | (ti.wy << 16);
+            anyref |= ti.fmt;
+            s_ux[e] = uu[0];
+            s_uy[e] = uu[1];
+            // the terms of the exact test (in_ball) that do not depend on d_x, d_y
+            s_ez2[e] = ez * ez;
+            s_rr2[e] = ti.fmt ? -1.0 : rr * rr;
+            s_a0[e] = ti.base + (long long)loc * rs +
+                      (((long long)(dz - ti.oz) * ti.wy - ti.oy) * ti.wx - ti.ox) * (TN * rs);
+            s_wx[e] = ti.wx;
         }
+        if (brm >= 0) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) { atomicMin(&s_bnd[2 * k], bl[k]); atomicMax(&s_bnd[2 * k + 1], bh[k]); }
+            atomicMax(&s_bnd[6], brm);
+        }
+        if (anyref) s_bnd[7] = 1;
         __syncthreads();
-        if (!mine) continue;
+        if (!mine || s_bnd[6] < 0) continue;
+        const bool ref = s_bnd[7] != 0;
+        const double q = 1.0 / 1024.0, rrm = s_bnd[6] + 0.5;
+        const double ddz = fmax(0.0, fmax(s_bnd[4] * q - (double)dz, (double)dz - s_bnd[5] * q));
         for (int dy = -M; dy <= M; dy++) {
+            const double ddy = fmax(0.0, fmax(s_bnd[2] * q - (double)dy, (double)dy - s_bnd[3] * q));
+            const double rem = rrm * rrm - ddz * ddz - ddy * ddy;
+            if (rem < 0.0) continue;
+            // the slack of 1e-6 covers the rounding of the exact test
+            const double hw = sqrt(rem);
+            const int dxlo = max(-M, (int)ceil(s_bnd[0] * q - hw - 1e-6));
+            const int dxhi = min(M, (int)floor(s_bnd[1] * q + hw + 1e-6));
             RowSums rs;
             const int rowe = (ly - dy + M) * W + lx + M;
-            for (int dx = -M; dx <= M; dx++) {
-                const int e = rowe - dx;
-                const int m = s_r[e];
-                if (m < 0) continue;
-                if (!in_ball((double)dx, (double)dy, (double)dz, s_ux[e], s_uy[e], s_uz[e], (m & 0xffff) + 0.5))
-                    continue;
-                const int wx = s_wxy[e] & 0xffff, wy = s_wxy[e] >> 16;
-                hits++;
-                if (m >> 20) {
-                    // pre-summed moments of a refined source's base point
-                    const T *P = SCR + s_a0[e] + (((long long)dz * wy + dy) * wx + dx) * (TN * NM);
+            const double cy = (double)dy;
+            // Straight-line candidates: each reads its entry and one record
+            // pair (a miss reads the scratch's first pair and adds zeros), so
+            // no per-lane branches; G3U candidates per batch, their record
+            // loads in flight together (entries past dxhi are masked and read
+            // the row's first entry).
+            for (int dxb = dxlo; dxb <= dxhi; dxb += G3U) {
+                bool in[G3U];
+                typename Pair3<T>::type v[G3U];
+#pragma unroll
+                for (int u = 0; u < G3U; u++) {
+                    const int dx = dxb + u;
+                    const int e = rowe - (dx <= dxhi ? dx : dxlo);
+                    const double ex = (double)dx - s_ux[e], ey = cy - s_uy[e];
+                    bool hit;
+                    {
+                        // in_ball's expression, term for term
+#pragma clang fp contract(off)
+                        hit = ex * ex + ey * ey + s_ez2[e] <= s_rr2[e];
+                    }
+                    in[u] = (dx <= dxhi) & hit;
+                    const long long off = s_a0[e] + (long long)(dy * s_wx[e] + dx) * (TN * 2);
+                    v[u] = *(const typename Pair3<T>::type *)(SCR + (in[u] ? off : 0ll));
+                }
+#pragma unroll
+                for (int u = 0; u < G3U; u++) {
+                    hits += in[u] ? 1 : 0;
+                    rs.add(in[u] ? (double)v[u].x : 0.0, in[u] ? (double)v[u].y : 0.0, (double)(dxb + u));
+                }
+            }
+            if (ref) {
+                // sources with all-moment records: the pre-summed moments of a
+                // base point's descendants
+                for (int dx = dxlo; dx <= dxhi; dx++) {
+                    const int e = rowe - dx;
+                    const int m = s_r[e];
+                    if (m < 0 || !(m >> 20)) continue;
+                    const double ex = (double)dx - s_ux[e], ey = cy - s_uy[e], rr = (double)(m & 0xffff) + 0.5;
+                    bool hit;
+                    {
+#pragma clang fp contract(off)
+                        hit = ex * ex + ey * ey + s_ez2[e] <= rr * rr;
+                    }
+                    if (!hit) continue;
+                    hits++;
+                    const T *P = SCR + s_a0[e] + (long long)(dy * s_wx[e] + dx) * (TN * NM);
 #pragma unroll
                     for (int k = 0; k < NM; k++) acc[k] += (double)P[k];
-                    continue;
                 }
-                const T *P = SCR + s_a0[e] + (((long long)dz * wy + dy) * wx + dx) * (TN * 2);
-                rs.add((double)P[0], (double)P[1], (double)dx);
             }
             rs.fold(acc, dy, dz);
         }
