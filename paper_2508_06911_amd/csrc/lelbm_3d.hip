@@ -976,7 +976,8 @@ __global__ void __launch_bounds__(64) k3_epr_ref(G3 g, Phys ph, const double *mo
 // |d_a| <= the step's reach M is tested against the stencil of its source x
 // - d (wrapped) with the reconstruction's own predicate; a hit adds the
 // source's record with velocity d (Eq. IIE3b).  A workgroup takes a
-// GX x GY x 1 block of destinations; for each d_z the descriptors of the
+// GX x GY x 1 block of destinations (GY = 16, or 8 where the staged plane
+// of 16 rows does not fit the LDS); for each d_z the descriptors of the
 // source plane it needs ((GX + 2M) x (GY + 2M) cells: velocity, the test's
 // terms that do not depend on d_x and d_y, and the address of the source's
 // record of displacement (0, 0, d_z)) are staged in LDS, with the bounds of
@@ -985,7 +986,7 @@ __global__ void __launch_bounds__(64) k3_epr_ref(G3 g, Phys ph, const double *mo
 // w_f c_x^k (k <= 3) and w_g c_x^k (k <= 1) are formed, and the 17 moments
 // once per row.
 // ---------------------------------------------------------------------------
-constexpr int GX = 16, GY = 16;
+constexpr int GX = 16;
 constexpr int G3_ENTRY_BYTES = 48;
 constexpr int G3U = 4;   // candidates per batch in the gather
 
@@ -1015,7 +1016,7 @@ struct RowSums {
     }
 };
 
-template <typename T>
+template <typename T, int GY>
 __global__ void __launch_bounds__(GX * GY, 4) k3_gather(G3 g, double *out, Buf3 b, int M, int zb) {
     extern __shared__ double g3_lds[];
     if (b.flags->err) return;
@@ -1467,8 +1468,9 @@ static void plan3(Ctx3 *c, const std::vector<long long> &layers, int M, long lon
     set_bases(P);
 }
 
-// LDS of the staged gather at reach M; 0 if it does not fit.
-static size_t gather3_lds(int M) {
+// LDS of the staged gather at reach M with GY destination rows per
+// workgroup; 0 if it does not fit.
+static size_t gather3_lds(int M, int GY) {
     const size_t bytes = (size_t)(GX + 2 * M) * (GY + 2 * M) * G3_ENTRY_BYTES;
     return bytes <= 64 * 1024 ? bytes : 0;
 }
@@ -1522,7 +1524,9 @@ int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3F
             hipLaunchKernelGGL(k3_scan, dim3(1), dim3(1024), 0, s, bd.row0 * per, (bd.row1 - bd.row0) * per, bd.base,
                                b);
         tm.end(tm.ctx, 2, s);
-        const size_t lds = gather3_lds(M);
+        // 16-row blocks where their staged plane fits the LDS, else 8 rows
+        const int GY = gather3_lds(M, 16) ? 16 : 8;
+        const size_t lds = gather3_lds(M, GY);
         const int bxy = ((g.nx + GX - 1) / GX) * ((g.ny + GY - 1) / GY);
         for (const Op &op : P.ops) {
             if (op.kind == OP_EPR) {
@@ -1548,12 +1552,15 @@ int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3F
                 // destination layers [a, a + n): cell planes [4a, min(nz, 4(a + n)))
                 const int z0 = op.a * TE, z1 = std::min(g.nz, (op.a + op.n) * TE);
                 tm.begin(tm.ctx, 4, s);
-                if (lds && c->mixed)
-                    hipLaunchKernelGGL(k3_gather<float>, dim3((unsigned)(bxy * (z1 - z0))), dim3(GX * GY), lds, s, g,
-                                       outm, b, M, z0);
+                const dim3 grid((unsigned)(bxy * (z1 - z0))), blk((unsigned)(GX * GY));
+                if (lds && GY == 16 && c->mixed)
+                    hipLaunchKernelGGL((k3_gather<float, 16>), grid, blk, lds, s, g, outm, b, M, z0);
+                else if (lds && GY == 16)
+                    hipLaunchKernelGGL((k3_gather<double, 16>), grid, blk, lds, s, g, outm, b, M, z0);
+                else if (lds && c->mixed)
+                    hipLaunchKernelGGL((k3_gather<float, 8>), grid, blk, lds, s, g, outm, b, M, z0);
                 else if (lds)
-                    hipLaunchKernelGGL(k3_gather<double>, dim3((unsigned)(bxy * (z1 - z0))), dim3(GX * GY), lds, s, g,
-                                       outm, b, M, z0);
+                    hipLaunchKernelGGL((k3_gather<double, 8>), grid, blk, lds, s, g, outm, b, M, z0);
                 else if (c->mixed)
                     hipLaunchKernelGGL(k3_gather_wide<float>, dim3((unsigned)(op.n * per)), dim3(64), 0, s, g, outm,
                                        b, op.a * per);

@@ -70,6 +70,25 @@ def test_parity_across_calls_and_hot_fast_gas():
     assert rel_linf(oa, ref) < 1e-10
 
 
+@pytest.mark.parametrize("RT,ux,what", [(2.6, 4.5, "reach ~11: 8-row gather blocks"),
+                                        (5.0, 4.5, "reach ~14: unstaged gather")])
+def test_parity_large_reach(RT, ux, what):
+    """Fast hot gases whose reach leaves the 16-row staged gather (its source
+    planes exceed the LDS): the 8-row blocks and the unstaged gather agree
+    with the oracle too."""
+    import paper_2508_06911_amd as lb
+    _case("3D %s, RT %.1f, u_x %.1f, 8 x 7 x 6, 2 steps" % (what, RT, ux))
+    cfg, prim = li.smooth_periodic3(3, n=8, ny=7, nz=6, amp=0.05, RT=RT, u=(ux, -0.8, 0.3))
+    ref, _ = _oracle(cfg, prim, 2)
+    ctx = lb.Lelbm(cfg, _mom(cfg, prim))
+    st = ctx.step(2)
+    out = ctx.read_moments()
+    ctx.close()
+    err = rel_linf(out, ref)
+    print("rel Linf vs oracle %.3g, q max %d" % (err, st["q_max"]), flush=True)
+    assert err < 1e-10
+
+
 def test_conservation_and_uniform_flow_at_size():
     import paper_2508_06911_amd as lb
     _case("3D conservation 48^3, 3 steps; uniform flow 32^3")
