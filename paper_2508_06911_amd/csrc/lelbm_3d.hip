@@ -30,7 +30,7 @@
 #include <climits>
 #include <vector>
 
-#include "lelbm_internal.h"
+#include "lelbm_3d.h"
 
 namespace lelbm {
 namespace d3 {

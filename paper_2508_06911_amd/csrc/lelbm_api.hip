@@ -18,7 +18,7 @@
 #include <mutex>
 #include <vector>
 
-#include "lelbm_internal.h"
+#include "lelbm_3d.h"
 
 using namespace lelbm;
 
