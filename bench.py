@@ -122,7 +122,8 @@ def epr3_flops_per_step(st, steps):
 # (velocity, density, temperature, radius: 20 bytes).
 GATHER_PAIR_BYTES = {"fp64": 16, "mixed": 8}
 GATHER_DESC_BYTES = 20
-RUNS = ("fp64-eq", "mixed-mlp", "mixed-eq", "fp64-mlp", "mixed-lin", "fp64-lin", "mixed-prev", "fp64-prev")
+RUNS = ("fp64-eq", "mixed-mlp", "mixed-eq", "fp64-mlp", "mixed-lin", "fp64-lin", "mixed-prev", "fp64-prev",
+        "mixed-mlpprev", "fp64-mlpprev")
 # The paper's own timings (hot-box advection, 4096^2, RTX 4070), as context.
 PAPER_HOTBOX_S_PER_STEP = {0.5: 10.9, 2.0: 33.8}
 
@@ -248,7 +249,11 @@ def cpu_baseline(cfg, prim, window, steps):
                       % (window, window, steps, el)}
 
 
-def harvest_and_train(a, lb, li, torch):
+def harvest_and_train(a, lb, li, torch, prev=False):
+    """Harvest (features, correction) pairs from FP64 runs of the four-quadrant
+    input at the harvest size and train the network on them.  With prev the
+    harvest runs use the previous-step guess, so the targets are what the
+    network should add to it (for the learned + previous-step guess)."""
     seeds = [int(s) for s in a.harvest_seeds.split(",") if s]
     cells = a.harvest_n * a.harvest_n
     stride = max(1, (cells * a.harvest_steps * len(seeds)) // a.harvest_pairs)
@@ -261,14 +266,14 @@ def harvest_and_train(a, lb, li, torch):
             break
         cfg, prim = li.quadrants(s, n=a.harvest_n)
         m = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
-        c = lb.Lelbm(cfg, m)
+        c = lb.Lelbm(cfg, m, guess=lb.GUESS_PREV if prev else lb.GUESS_EQ)
         c.harvest(buf[n:], stride=stride)        # each context counts from 0
         c.step_nostats(a.harvest_steps)
         n = min(cap, n + c.harvest_count())
         c.close()
     torch.cuda.synchronize()
     t_h = time.perf_counter() - t0
-    log("harvested %d pairs (stride %d) in %.1f s" % (n, stride, t_h))
+    log("harvested %d pairs (stride %d%s) in %.1f s" % (n, stride, ", previous-step guess" if prev else "", t_h))
     g = torch.Generator(device="cpu").manual_seed(1234)
     perm = torch.randperm(n, generator=g).to("cuda")
     nval = min(200_000, n // 20)
@@ -291,20 +296,25 @@ def harvest_and_train(a, lb, li, torch):
             "harvest_steps": a.harvest_steps, "stride": stride, "harvest_s": round(t_h, 2),
             "train_steps": a.train_steps, "batch": a.batch, "train_s": round(t_t, 2),
             "train_mse": round(loss, 5), "heldout_mse": round(vmse, 5),
-            "mse_unit": "per-output standardised (1.0 = predicting the mean)"}
+            "mse_unit": "per-output standardised (1.0 = predicting the mean)",
+            "targets": "correction beyond LIN + the stored previous-step correction" if prev else
+                       "correction beyond LIN"}
     del train, val
     return mlp, info
 
 
-def timed_run(name, a, lb, torch, cfg, mom0, mlp):
+def timed_run(name, a, lb, torch, cfg, mom0, mlp, mlp_prev=None):
     prec = lb.FP64 if name.startswith("fp64") else lb.MIXED
-    guess = {"eq": lb.GUESS_EQ, "mlp": lb.GUESS_MLP, "lin": lb.GUESS_LIN, "prev": lb.GUESS_PREV}[name.split("-")[1]]
+    guess = {"eq": lb.GUESS_EQ, "mlp": lb.GUESS_MLP, "lin": lb.GUESS_LIN, "prev": lb.GUESS_PREV,
+             "mlpprev": lb.GUESS_MLP_PREV}[name.split("-")[1]]
     stream = torch.cuda.current_stream()
     ctx = lb.Lelbm(cfg, mom0, precision=prec, guess=guess, stream=stream)
     if a.scratch_budget:
         ctx.set_scratch_budget(a.scratch_budget)
     if guess == lb.GUESS_MLP:
         ctx.set_mlp(mlp)
+    if guess == lb.GUESS_MLP_PREV:
+        ctx.set_mlp(mlp_prev)
     if a.warmup:
         ctx.step(a.warmup)
     torch.cuda.synchronize()
@@ -726,12 +736,15 @@ def main():
     mlp, train_info = (None, None)
     if any(r.endswith("mlp") for r in runs):
         mlp, train_info = harvest_and_train(a, lb, li, torch)
+    mlp_prev, train_info_prev = (None, None)
+    if any(r.endswith("mlpprev") for r in runs):
+        mlp_prev, train_info_prev = harvest_and_train(a, lb, li, torch, prev=True)
 
     cfg, prim = li.quadrants(a.seed, n=a.n)
     mom0 = lb.moments_from_primitives(2, cfg["K"], prim["rho"], prim["ux"], prim["uy"], prim["RT"])
     res_runs, moms = {}, {}
     for r in runs:
-        res_runs[r], moms[r] = timed_run(r, a, lb, torch, cfg, mom0, mlp)
+        res_runs[r], moms[r] = timed_run(r, a, lb, torch, cfg, mom0, mlp, mlp_prev)
     ref = "fp64-eq" if "fp64-eq" in moms else None
     for r in runs:
         if ref is not None and r != ref:
@@ -784,6 +797,8 @@ def main():
     }
     if train_info is not None:
         res["mlp"] = train_info
+    if train_info_prev is not None:
+        res["mlp_prev"] = train_info_prev
     if not a.no_context:
         res["c0"] = c0_line(lb, li, torch)
         if mlp is not None:
@@ -808,6 +823,8 @@ def main():
             res["c4_context"] = c4_context(lb, li, torch, a, mlp)
     if mlp is not None:
         mlp.close()
+    if mlp_prev is not None:
+        mlp_prev.close()
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline(cfg, prim, a.cpu_window, a.cpu_steps)
     print(json.dumps(res), flush=True)

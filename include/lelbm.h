@@ -105,12 +105,15 @@ enum { LELBM_FP64 = 0, LELBM_MIXED = 1 };
  * targets flips sign every step, and LIN, not the stored correction, follows
  * that flip.  The context keeps 16 doubles per cell for it; the first step,
  * and cells whose previous step used refined stencils, start from LIN.
- * With LIN, MLP and PREV a cell whose first Newton update does not lower
+ * With MLP_PREV (2D): PREV plus the learned network's correction of it, in
+ * the cells that have a stored correction (the others start from LIN); the
+ * network is then one trained on pairs harvested in PREV mode (lelbm_harvest).
+ * With LIN, MLP, PREV and MLP_PREV a cell whose first Newton update does not lower
  * the residual, or whose solve fails (non-finite values, Cholesky
  * breakdown, line search exhausted, iteration cap), restarts from
  * Eq. (IID13); the converged result is the same in all modes (the
  * multipliers are unique). */
-enum { LELBM_GUESS_EQ = 0, LELBM_GUESS_MLP = 1, LELBM_GUESS_LIN = 2, LELBM_GUESS_PREV = 3 };
+enum { LELBM_GUESS_EQ = 0, LELBM_GUESS_MLP = 1, LELBM_GUESS_LIN = 2, LELBM_GUESS_PREV = 3, LELBM_GUESS_MLP_PREV = 4 };
 
 typedef struct {
     int dim, nx, ny;                  /* dim = 1 requires ny = 1 */
@@ -124,7 +127,7 @@ typedef struct {
     int kn_limiter;                   /* 1: Knudsen limiter of App. D, Eqs. (D2-D3) */
     double kn_lo, kn_hi, omega_H;     /* log10 Kn thresholds and target frequency (paper: -2, -1, 1) */
     int precision;                    /* LELBM_FP64 | LELBM_MIXED */
-    int guess;                        /* LELBM_GUESS_EQ | _MLP | _LIN | _PREV */
+    int guess;                        /* LELBM_GUESS_EQ | _MLP | _LIN | _PREV | _MLP_PREV */
     int bc[4];                        /* faces xlo, xhi, ylo, yhi: LELBM_BC_*; periodic faces pair up */
     int pad;                          /* pad width W of outflow/inflow faces (Sec. III, Fig. 5) */
     double in_rho, in_u[2], in_RT;    /* inflow (Dirichlet) state of LELBM_BC_INFLOW faces */
@@ -349,12 +352,16 @@ int lelbm_mlp_set_norm(lelbm_mlp *m, const float *host_norm);
 void lelbm_mlp_destroy(lelbm_mlp *m);
 
 /* Copies the network into a context created with guess = LELBM_GUESS_MLP
- * (required before its first step). */
+ * or LELBM_GUESS_MLP_PREV (required before its first step). */
 int lelbm_set_mlp(lelbm_ctx *c, const lelbm_mlp *m);
 /* Harvest (features, converged multipliers) pairs during lelbm_step into a
  * caller-owned device buffer of capacity x 32 floats: cell s at step k is
  * recorded when (s + 7919 k) is divisible by stride (unrefined 2D cells).
- * dev_buf = NULL stops harvesting.  The order of the pairs is not fixed. */
+ * The target is the scaled correction of the converged multipliers beyond
+ * the context's own non-learned start: LIN, or in PREV and MLP_PREV modes
+ * LIN plus the stored correction (there only cells that have one are
+ * recorded).  dev_buf = NULL stops harvesting.  The order of the pairs is
+ * not fixed. */
 int lelbm_harvest(lelbm_ctx *c, float *dev_buf, long long capacity, int stride);
 int lelbm_harvest_count(const lelbm_ctx *c, long long *n);
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblelbm.so")
 OK, EINVAL, ENOMEM, EDEVICE, EEPR, ENONFINITE, EREACH = 0, -1, -2, -3, -4, -5, -6
 BC = {"periodic": 0, "outflow": 1, "inflow": 2, "slipwall": 3, "wall": 4}
 FP64, MIXED = 0, 1
-GUESS_EQ, GUESS_MLP, GUESS_LIN, GUESS_PREV = 0, 1, 2, 3
+GUESS_EQ, GUESS_MLP, GUESS_LIN, GUESS_PREV, GUESS_MLP_PREV = 0, 1, 2, 3, 4
 
 
 class LelbmError(RuntimeError):

@@ -209,9 +209,9 @@ static int validate(const lelbm_params *p) {
     if (!(p->newton_tol > 0.0) || p->newton_max_it < 1) return LELBM_EINVAL;
     if (p->precision != LELBM_FP64 && p->precision != LELBM_MIXED) return LELBM_EINVAL;
     if (p->guess != LELBM_GUESS_EQ && p->guess != LELBM_GUESS_MLP && p->guess != LELBM_GUESS_LIN &&
-        p->guess != LELBM_GUESS_PREV)
+        p->guess != LELBM_GUESS_PREV && p->guess != LELBM_GUESS_MLP_PREV)
         return LELBM_EINVAL;
-    if (p->guess == LELBM_GUESS_MLP && p->dim != 2) return LELBM_EINVAL;
+    if ((p->guess == LELBM_GUESS_MLP || p->guess == LELBM_GUESS_MLP_PREV) && p->dim != 2) return LELBM_EINVAL;
     if (p->solid && p->dim != 2) return LELBM_EINVAL;
     for (int f = 0; f < 4; f++)
         if (p->bc[f] < LELBM_BC_PERIODIC || p->bc[f] > LELBM_BC_WALL) return LELBM_EINVAL;
@@ -500,7 +500,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     ph.in_rho = p->in_rho; ph.in_u[0] = p->in_u[0]; ph.in_u[1] = p->dim == 2 ? p->in_u[1] : 0.0;
     ph.in_RT = p->in_RT;
     ph.lin_guess = p->guess == LELBM_GUESS_LIN;
-    ph.prev_guess = p->guess == LELBM_GUESS_PREV;
+    ph.prev_guess = p->guess == LELBM_GUESS_PREV || p->guess == LELBM_GUESS_MLP_PREV;
     ph.src_node = p->src_rate != 0.0 ? (long long)(p->src_y + g.wb) * g.sxn + (p->src_x + g.wl) : -1;
     ph.src_mass = 0.0;
     ph.wall_ux[0] = p->dim == 2 ? p->wall_u[2] : 0.0;
@@ -534,7 +534,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
     // arrival partials of the straight gather and of the backward-walk gather
     ok = ok && hipMalloc((void **)&b.gpart, (size_t)5 * gather_blocks_x(g) * gather_blocks_y(g) *
                                                 sizeof(unsigned long long)) == hipSuccess;
-    if (p->guess == LELBM_GUESS_PREV) {
+    if (p->guess == LELBM_GUESS_PREV || p->guess == LELBM_GUESS_MLP_PREV) {
         ok = ok && hipMalloc((void **)&b.lamprev, (size_t)16 * ns * sizeof(double)) == hipSuccess;
         // all-ones bytes are a NaN: no stored correction yet
         ok = ok && hipMemset(b.lamprev, 0xff, (size_t)16 * ns * sizeof(double)) == hipSuccess;
@@ -547,7 +547,7 @@ static int create_common(const lelbm_params *p, void *stream, lelbm_ctx **out, l
         ok = ok && hipMalloc((void **)&b.wreach, sizeof(int)) == hipSuccess;
         ok = ok && hipMemset(b.wflag, 0, (size_t)we * sizeof(int)) == hipSuccess;
     }
-    if (p->guess == LELBM_GUESS_MLP) {
+    if (p->guess == LELBM_GUESS_MLP || p->guess == LELBM_GUESS_MLP_PREV) {
         ok = ok && hipMalloc((void **)&c->mlp_w, MLP_NPARAM * sizeof(unsigned short)) == hipSuccess;
         ok = ok && hipMalloc((void **)&c->mlp_p, MLP_NPARAM * sizeof(float)) == hipSuccess;
         ok = ok && hipMalloc((void **)&c->mlp_n, MLP_NORM * sizeof(float)) == hipSuccess;
@@ -840,7 +840,7 @@ static hipError_t do_totals(lelbm_ctx *c, void *) { return launch_step_totals(c-
 // and no timing events are recorded.
 static int step_impl(lelbm_ctx *c, int nsteps, lelbm_stats *st, void *fixed_scratch, long long fixed_cap) {
     if (!c || nsteps < 0) return LELBM_EINVAL;
-    if (c->p.guess == LELBM_GUESS_MLP && !c->mlp_set) return LELBM_EINVAL;
+    if ((c->p.guess == LELBM_GUESS_MLP || c->p.guess == LELBM_GUESS_MLP_PREV) && !c->mlp_set) return LELBM_EINVAL;
     const bool noalloc = fixed_scratch != nullptr;
     if (noalloc && c->stage.cap < sizeof(DevStats) + sizeof(Flags)) return LELBM_EINVAL;
     hipStream_t s = c->stream;
@@ -1424,7 +1424,7 @@ extern "C" void lelbm_mlp_destroy(lelbm_mlp *m) {
 }
 
 extern "C" int lelbm_set_mlp(lelbm_ctx *c, const lelbm_mlp *m) {
-    if (!c || !m || c->p.guess != LELBM_GUESS_MLP) return LELBM_EINVAL;
+    if (!c || !m || (c->p.guess != LELBM_GUESS_MLP && c->p.guess != LELBM_GUESS_MLP_PREV)) return LELBM_EINVAL;
     HIPCHECK(hipStreamSynchronize(m->stream));
     HIPCHECK(hipMemcpyAsync(c->mlp_p, m->params, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
     HIPCHECK(hipMemcpyAsync(c->mlp_n, m->norm, MLP_NORM * sizeof(float), hipMemcpyDeviceToDevice, c->stream));

@@ -1354,10 +1354,13 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const double *m
         species_init<D, NF, NG>(sf, sg, RT);
         if (ph.lin_guess) species_linear<D>(sf, sg, mf, mg, RT);
         if (ph.prev_guess) species_prev<D>(sf, sg, mf, mg, RT, b.lamprev, g.ns, s);
-        if (D == 2 && b.mlp_w) {
-            // learned guess: the linearised guess plus the network's scaled correction
-            // (mlp_guess_cells)
-            species_linear<D>(sf, sg, mf, mg, RT);
+        // learned guess: the linearised guess plus the network's scaled correction
+        // (mlp_guess_cells); on top of the previous step's correction, where one
+        // is stored, when the previous-step guess is on too (species_prev has then
+        // applied the linearised guess and that correction)
+        const bool prev_ok = ph.prev_guess && b.lamprev[s] == b.lamprev[s];
+        if (D == 2 && b.mlp_w && (!ph.prev_guess || prev_ok)) {
+            if (!ph.prev_guess) species_linear<D>(sf, sg, mf, mg, RT);
             const double sq = sqrt(RT);
 #pragma unroll
             for (int j = 0; j < NF + NG; j++) {
@@ -1481,8 +1484,11 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const double *m
         if (fail) {
             flag_fail(b.flags, LELBM_EEPR, step, s, fail, fsp, fsp ? sg.res : sf.res);
         } else {
-            if (ph.prev_guess) store_prev<D>(sf, sg, mf, mg, RT, b.lamprev, g.ns, s);
-            if (D == 2 && b.harvest && ((s + (long long)step * 7919) % b.harvest_stride) == 0) {
+            // harvest: what the network should add to the context's own start --
+            // the linearised guess, plus the stored correction with the
+            // previous-step guess (cells without one are not harvested then)
+            if (D == 2 && b.harvest && (!ph.prev_guess || prev_ok) &&
+                ((s + (long long)step * 7919) % b.harvest_stride) == 0) {
                 unsigned long long slot = atomicAdd(b.harvest_n, 1ull);
                 if (slot < (unsigned long long)b.harvest_cap) {
                     float x[16];
@@ -1499,11 +1505,12 @@ __global__ void __launch_bounds__(256, 2) k_epr(Geom g, Phys ph, const double *m
                         const double lam = j < NF ? sf.v.lam(jj) : sg.v.lam(jj);
                         const int k = basis_order2(jj);
                         const double scl = k == 0 ? 1.0 : (k == 1 ? sq : (k == 2 ? RT : RT * sq));
-                        // target: what the network adds to the linearised guess
-                        hp[16 + j] = (float)(lam * scl - iid13_scaled(jj, RT) - dl[j]);
+                        const double e = prev_ok ? b.lamprev[(long long)j * g.ns + s] : 0.0;
+                        hp[16 + j] = (float)(lam * scl - iid13_scaled(jj, RT) - dl[j] - e);
                     }
                 }
             }
+            if (ph.prev_guess) store_prev<D>(sf, sg, mf, mg, RT, b.lamprev, g.ns, s);
             // final pass: moment fractions rho f', rho K RT g' (Eq. IIE3a), rho plus
             // the mass a point source adds in its cell
             const double wsf = post_mass(ph, s, rho), wsg = wsf * ph.K * RT;
