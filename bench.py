@@ -614,7 +614,8 @@ def d3_line(a, lb, li, torch):
     ncell = n ** 3
     out, moms = {}, {}
     for name, prec, guess in (("fp64", lb.FP64, lb.GUESS_EQ), ("mixed", lb.MIXED, lb.GUESS_EQ),
-                              ("fp64-lin", lb.FP64, lb.GUESS_LIN), ("mixed-lin", lb.MIXED, lb.GUESS_LIN)):
+                              ("fp64-lin", lb.FP64, lb.GUESS_LIN), ("mixed-lin", lb.MIXED, lb.GUESS_LIN),
+                              ("fp64-prev", lb.FP64, lb.GUESS_PREV), ("mixed-prev", lb.MIXED, lb.GUESS_PREV)):
         stream = torch.cuda.current_stream()
         c = lb.Lelbm(cfg, m, precision=prec, guess=guess, stream=stream)
         if a.scratch_budget:
@@ -650,6 +651,8 @@ def d3_line(a, lb, li, torch):
     out["l1_mixed_vs_fp64"] = l1_errors3(moms["mixed"], moms["fp64"])
     out["l1_mixed_lin_vs_fp64"] = l1_errors3(moms["mixed-lin"], moms["fp64"])
     out["l1_fp64_lin_vs_fp64"] = l1_errors3(moms["fp64-lin"], moms["fp64"])
+    out["l1_mixed_prev_vs_fp64"] = l1_errors3(moms["mixed-prev"], moms["fp64"])
+    out["l1_fp64_prev_vs_fp64"] = l1_errors3(moms["fp64-prev"], moms["fp64"])
     c8, p8 = li.smooth_periodic3(a.seed, n=16, amp=0.1, RT=1.0)
     m8 = oracle.moments_from_primitives3(c8["K"], p8["rho"], p8["ux"], p8["uy"], p8["uz"], p8["RT"])
     t0 = time.perf_counter()

@@ -153,11 +153,11 @@ typedef struct {
      * fluon constraints (1, the first and second moments and the per-axis
      * third-order pieces M~_{aa|g} of Eq. IIB14) and 10 phonon constraints.
      * Supported: periodic boxes (bc all LELBM_BC_PERIODIC, z periodic too),
-     * LELBM_GUESS_EQ or LELBM_GUESS_LIN, both precisions, up to 3 refinement
-     * levels (8 children per level) and radii up to 64 (beyond: LELBM_EREACH).
-     * Not in 3D:
-     * solids, walls, point sources, the learned and previous-step guesses,
-     * harvest, and
+     * LELBM_GUESS_EQ, _LIN or _PREV (the stored correction is 19 + 10
+     * doubles per cell; cells with refined stencils keep none), both
+     * precisions, up to 3 refinement levels (8 children per level) and radii
+     * up to 64 (beyond: LELBM_EREACH).  Not in 3D: solids, walls, point
+     * sources, the learned guesses, harvest, and
      * lelbm_step_noalloc (LELBM_EINVAL).  The records are banded over layers
      * of 4 cells in z within lelbm_set_scratch_budget as in 2D.  lelbm_stats
      * sum[] holds mass, x and y momentum and the energy trace. */

@@ -83,6 +83,8 @@ struct Buf3 {
     long long *total;             // record elements of the step (k3_scan)
     double *partial;              // block sums of the conserved totals
     const double *ainv;           // inverse scaled Maxwellian Hessians of the linearised start, or NULL
+    double *prev;                 // [19 + 10][n] previous-step guess: each cell's converged correction
+                                  // beyond the linearised start, scaled by RT^(k/2); NaN: none; or NULL
 };
 
 struct G3 {
@@ -375,8 +377,8 @@ template <int NB> __device__ inline void sp3_init(Sp3<NB> &sp, double RT) {
 // <T_i T_j> of the unit normal distribution; ainv holds its inverse (fluon
 // 19 x 19, then phonon 10 x 10), computed once on the host.  The step is
 // A~ dl~ = (equilibrium moments - targets) / RT^(k/2).
-__device__ inline void sp3_linear(Sp3<NF> &sf, Sp3<NG> &sg, const double *mf, const double *mg, double RT,
-                                  const double *ainv) {
+// The step's scaled corrections: d[0..18] fluon, d[19..28] phonon.
+__device__ inline void lin3_scaled(const double *mf, const double *mg, double RT, const double *ainv, double *d) {
     const double sq = sqrt(RT);
     const double sc[4] = {1.0, sq, RT, RT * sq};
     double rf[NF], rg[NG];
@@ -389,20 +391,66 @@ __device__ inline void sp3_linear(Sp3<NF> &sf, Sp3<NG> &sg, const double *mf, co
     }
 #pragma unroll
     for (int i = 0; i < NF; i++) {
-        double d = 0.0;
+        double v = 0.0;
 #pragma unroll
-        for (int j = 0; j < NF; j++) d += ainv[i * NF + j] * rf[j];
-        sf.lam[i] += d / sc[border(i)];
+        for (int j = 0; j < NF; j++) v += ainv[i * NF + j] * rf[j];
+        d[i] = v;
     }
 #pragma unroll
     for (int i = 0; i < NG; i++) {
-        double d = 0.0;
+        double v = 0.0;
 #pragma unroll
-        for (int j = 0; j < NG; j++) d += ainv[NF * NF + i * NG + j] * rg[j];
-        sg.lam[i] += d / sc[border(i)];
+        for (int j = 0; j < NG; j++) v += ainv[NF * NF + i * NG + j] * rg[j];
+        d[NF + i] = v;
     }
+}
+
+__device__ inline void sp3_linear(Sp3<NF> &sf, Sp3<NG> &sg, const double *mf, const double *mg, double RT,
+                                  const double *ainv) {
+    const double sq = sqrt(RT);
+    const double sc[4] = {1.0, sq, RT, RT * sq};
+    double d[NF + NG];
+    lin3_scaled(mf, mg, RT, ainv, d);
+#pragma unroll
+    for (int i = 0; i < NF; i++) sf.lam[i] += d[i] / sc[border(i)];
+#pragma unroll
+    for (int i = 0; i < NG; i++) sg.lam[i] += d[NF + i] / sc[border(i)];
     sf.lin = 1;
     sg.lin = 1;
+}
+
+// Previous-step guess (Sec. II.D suggests reusing stored multipliers): the
+// linearised start plus the cell's stored correction beyond it, where one is
+// stored.  The correction is kept in scaled units, so it carries over when
+// the temperature changes, and beyond the linearised start, which follows
+// the sign flip of the non-equilibrium targets at omega = 2.
+__device__ inline void sp3_prev(Sp3<NF> &sf, Sp3<NG> &sg, double RT, const double *prev, long long n,
+                                long long s) {
+    if (!(prev[s] == prev[s])) return;
+    const double sq = sqrt(RT);
+    const double sc[4] = {1.0, sq, RT, RT * sq};
+#pragma unroll
+    for (int i = 0; i < NF; i++) sf.lam[i] += prev[(long long)i * n + s] / sc[border(i)];
+#pragma unroll
+    for (int i = 0; i < NG; i++) sg.lam[i] += prev[(long long)(NF + i) * n + s] / sc[border(i)];
+}
+
+// Stores the converged multipliers' correction beyond Eq. (IID13) plus the
+// linearised step, in scaled units, for the next step's guess.
+__device__ inline void sp3_store_prev(const Sp3<NF> &sf, const Sp3<NG> &sg, const double *mf, const double *mg,
+                                      double RT, const double *ainv, double *prev, long long n, long long s) {
+    const double sq = sqrt(RT);
+    const double sc[4] = {1.0, sq, RT, RT * sq};
+    const double l0 = -1.0 + 1.5 * log(2.0 * M_PI * RT);   // Eq. (IID13): lam_0; 1/(2 RT) on xx, yy, zz
+    double d[NF + NG];
+    lin3_scaled(mf, mg, RT, ainv, d);
+#pragma unroll
+    for (int i = 0; i < NF + NG; i++) {
+        const int j = i < NF ? i : i - NF;
+        const double lam = i < NF ? sf.lam[j] : sg.lam[j];
+        const double eq = j == 0 ? l0 : ((j == 4 || j == 7 || j == 9) ? 0.5 : 0.0);   // scaled Eq. (IID13)
+        prev[(long long)i * n + s] = lam * sc[border(j)] - eq - d[i];
+    }
 }
 
 // Cholesky solve of A x = r with A_ij = S[hidx(i, j)] (Eq. IID11a).
@@ -687,6 +735,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
         sp3_init<NF>(sf, RT);
         sp3_init<NG>(sg, RT);
         if (b.ainv) sp3_linear(sf, sg, mf, mg, RT, b.ainv);
+        if (b.prev) sp3_prev(sf, sg, RT, b.prev, g.n, s);
         const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
         int fail = 0, fsp = -1;
         while (!fail && (sf.phase < 2 || sg.phase < 2)) {
@@ -791,6 +840,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
         } else {
             itf = sf.nit;
             itg = sg.nit;
+            if (b.prev) sp3_store_prev(sf, sg, mf, mg, RT, b.ainv, b.prev, g.n, s);
             const double wsf = rho, wsg = rho * ph.K * RT;
             const Tile3 ti = b.tiles[t];
             T *P = (T *)b.scratch + ti.base;
@@ -932,6 +982,10 @@ __global__ void __launch_bounds__(64) k3_epr_ref(G3 g, Phys ph, const double *mo
         } else {
             itf = sf.nit;
             itg = sg.nit;
+            // refined cells keep no correction: their next step starts from the
+            // linearised guess
+            if (b.prev)
+                for (int i = 0; i < NF + NG; i++) b.prev[(long long)i * g.n + s] = __longlong_as_double(-1ll);
             const double wsf = rho, wsg = rho * ph.K * RT;
             const Tile3 ti = b.tiles[t];
             T *P = (T *)b.scratch + ti.base;
@@ -1333,7 +1387,7 @@ static void free3(Ctx3 *c) {
     if (!c) return;
     Buf3 &b = c->b;
     void *ptrs[] = {b.mom[0], b.mom[1], b.d.rho, b.d.ux, b.d.uy, b.d.uz, b.d.rt, b.d.r, b.tiles, b.scratch,
-                    b.flags, b.stats, b.maxreach, b.total, b.partial, c->layer, c->ainv_dev};
+                    b.flags, b.stats, b.maxreach, b.total, b.partial, c->layer, c->ainv_dev, b.prev};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->host_small) (void)hipHostFree(c->host_small);
@@ -1372,7 +1426,12 @@ int ctx3_create(const lelbm_params *p, const Phys &ph, int mixed, const void *mo
     alloc((void **)&b.total, sizeof(long long));
     alloc((void **)&b.partial, (size_t)(c->nsum + 1) * 4 * sizeof(double));
     alloc((void **)&c->layer, (size_t)g.tnz * sizeof(long long));
-    if (ph.lin_guess) {
+    if (ph.prev_guess) {
+        alloc((void **)&b.prev, (size_t)(NF + NG) * g.n * sizeof(double));
+        // all-ones bytes are a NaN: no stored correction yet
+        if (ok) ok = hipMemset(b.prev, 0xff, (size_t)(NF + NG) * g.n * sizeof(double)) == hipSuccess;
+    }
+    if (ph.lin_guess || ph.prev_guess) {
         std::vector<double> ai;
         lin_inverse(ai);
         alloc((void **)&c->ainv_dev, ai.size() * sizeof(double));
@@ -1382,7 +1441,8 @@ int ctx3_create(const lelbm_params *p, const Phys &ph, int mixed, const void *mo
     ok = ok && hipHostMalloc(&c->host_small, 4096 + (size_t)g.tnz * sizeof(long long), hipHostMallocDefault) ==
                    hipSuccess;
     if (!ok) { free3(c); return LELBM_ENOMEM; }
-    c->persistent = (long long)2 * NM * g.n * 8 + g.n * (5 * 8 + 4) + (long long)g.ntiles * sizeof(Tile3);
+    c->persistent = (long long)2 * NM * g.n * 8 + g.n * (5 * 8 + 4) + (long long)g.ntiles * sizeof(Tile3) +
+                    (b.prev ? (long long)(NF + NG) * g.n * 8 : 0);
     // state
     const long long tot = (long long)NM * g.n;
     if (on_device) {

@@ -250,14 +250,16 @@ static int validate(const lelbm_params *p) {
     return LELBM_OK;
 }
 
-// Three dimensions: periodic boxes, the Newton start of Eq. (IID13) or its
-// linearisation; no solids, walls, point sources, learned guess or harvest.
+// Three dimensions: periodic boxes, the Newton start of Eq. (IID13), its
+// linearisation or the previous-step guess; no solids, walls, point sources,
+// learned guess or harvest.
 static int validate3(const lelbm_params *p) {
     if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return LELBM_EINVAL;
     if (!(p->K > 0.0) || !(p->n_conf > 0.0) || p->r_min < 1) return LELBM_EINVAL;
     if (!(p->newton_tol > 0.0) || p->newton_max_it < 1) return LELBM_EINVAL;
     if (p->precision != LELBM_FP64 && p->precision != LELBM_MIXED) return LELBM_EINVAL;
-    if (p->guess != LELBM_GUESS_EQ && p->guess != LELBM_GUESS_LIN) return LELBM_EINVAL;
+    if (p->guess != LELBM_GUESS_EQ && p->guess != LELBM_GUESS_LIN && p->guess != LELBM_GUESS_PREV)
+        return LELBM_EINVAL;
     for (int f = 0; f < 4; f++)
         if (p->bc[f] != LELBM_BC_PERIODIC || p->wall_u[f] != 0.0) return LELBM_EINVAL;
     if (p->solid || p->src_rate != 0.0) return LELBM_EINVAL;
@@ -708,6 +710,7 @@ static int create3(const lelbm_params *p, const void *moments, int src_fp32, int
     ph.kn_lo_lin = pow(10.0, p->kn_lo); ph.kn_hi_lin = pow(10.0, p->kn_hi);
     ph.src_node = -1;
     ph.lin_guess = p->guess == LELBM_GUESS_LIN;
+    ph.prev_guess = p->guess == LELBM_GUESS_PREV;
     c->ph_step = ph;
     int r = ctx3_create(p, ph, c->mixed, moments, src_fp32, on_device, c->stream, &c->c3);
     if (r != LELBM_OK) { free_ctx(c); return r; }

@@ -83,7 +83,7 @@ def test_invalid_parameters_are_rejected_before_any_device_call():
         c = dict(c3)
         if key == "guess":
             with pytest.raises(lb.LelbmError) as e:
-                lb.Lelbm(c, m3, guess=lb.GUESS_PREV, stream=0)
+                lb.Lelbm(c, m3, guess=lb.GUESS_MLP, stream=0)
             assert e.value.code == lb.EINVAL
             continue
         c[key] = val

@@ -193,6 +193,37 @@ def test_linearised_start_matches_eq(prec, tol):
     assert its[lb.GUESS_LIN] < its[lb.GUESS_EQ]
 
 
+@pytest.mark.parametrize("prec,tol,n,RT,amp,seed", [(0, 1e-10, 48, 0.9, 0.1, 1), (1, 1e-6, 48, 0.9, 0.1, 1),
+                                                    (0, 1e-10, 10, 0.42, 0.15, 6)])
+def test_previous_step_guess(prec, tol, n, RT, amp, seed):
+    """The linearised start plus each cell's stored correction from the
+    previous step (Sec. II.D's stored multipliers) converges to the fields of
+    Eq. (IID13)'s start; its first step is the linearised path itself; on the
+    smooth 48^3 box the FP64 solves need fewer Newton updates than from the
+    linearised start; around RT = 0.42 refined cells keep no correction and
+    start from the linearised guess."""
+    import paper_2508_06911_amd as lb
+    _case("3D previous-step guess, precision %d, %d^3, RT %.2f, 7 steps" % (prec, n, RT))
+    cfg, prim = li.smooth_periodic3(seed, n=n, amp=amp, RT=RT)
+    m = _mom(cfg, prim)
+    outs, its = {}, {}
+    for g in (lb.GUESS_EQ, lb.GUESS_LIN, lb.GUESS_PREV):
+        c = lb.Lelbm(cfg, m, precision=prec, guess=g)
+        c.step(1)
+        outs[(g, 1)] = c.read_moments()
+        st = c.step(6)
+        outs[g] = c.read_moments()
+        its[g] = st["it_mean_f"] + st["it_mean_g"]
+        c.close()
+    err = rel_linf(outs[lb.GUESS_PREV], outs[lb.GUESS_EQ])
+    print("PREV vs EQ %.3g; Newton updates per cell (f + g) in steps 2-7: EQ %.2f LIN %.2f PREV %.2f"
+          % (err, its[lb.GUESS_EQ], its[lb.GUESS_LIN], its[lb.GUESS_PREV]), flush=True)
+    assert err < tol
+    if prec == 0 and RT > 4.0 / 9.0:
+        assert its[lb.GUESS_PREV] < its[lb.GUESS_LIN]
+    assert np.array_equal(outs[(lb.GUESS_PREV, 1)], outs[(lb.GUESS_LIN, 1)])
+
+
 @pytest.mark.parametrize("prec,tol,RT,amp,seed", [(0, 1e-10, 0.42, 0.15, 6), (1, 1e-6, 0.42, 0.15, 6),
                                                   (0, 1e-10, 0.03, 0.05, 8)])
 def test_refined_stencils_parity(prec, tol, RT, amp, seed):
