@@ -1428,8 +1428,9 @@ int ctx3_create(const lelbm_params *p, const Phys &ph, int mixed, const void *mo
     alloc((void **)&c->layer, (size_t)g.tnz * sizeof(long long));
     if (ph.prev_guess) {
         alloc((void **)&b.prev, (size_t)(NF + NG) * g.n * sizeof(double));
-        // all-ones bytes are a NaN: no stored correction yet
-        if (ok) ok = hipMemset(b.prev, 0xff, (size_t)(NF + NG) * g.n * sizeof(double)) == hipSuccess;
+        // all-ones bytes are a NaN: no stored correction yet (on the context's
+        // stream, ahead of its first step)
+        if (ok) ok = hipMemsetAsync(b.prev, 0xff, (size_t)(NF + NG) * g.n * sizeof(double), stream) == hipSuccess;
     }
     if (ph.lin_guess || ph.prev_guess) {
         std::vector<double> ai;
