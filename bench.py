@@ -92,10 +92,12 @@ def epr_flops_per_step(st, steps):
 #   28 per point and Newton evaluation: x, the five product recurrences, x^1..x^6
 #      and x^1..x^4 (10 multiplies) and 12 row-sum updates
 #    8 per point of the final pass: x, the recurrences, two weights
-#  370 per stencil row and pass: the exponents' row coefficients (29 terms), the
-#      row's span, y powers, folding the row sums into the 28 + 15 plane sums,
-#      and the recurrences' start values (their polynomials and five
-#      exponentials of ~22)
+#  330 per stencil row and pass: the exponents' row coefficients (29 terms), y
+#      powers, folding the row sums into the 28 + 15 plane sums, and the
+#      recurrences' start values (their polynomials and five exponentials of ~22)
+#   50 per stencil row, once per cell: the row spans (the exact ball test at the
+#      span ends), tabulated in LDS for all passes (the table covers the
+#      (2R + 3)^2 rows of the box, about twice the rows that hold points)
 #  250 per stencil plane and pass: z powers and folding the plane sums into
 #      the 84 + 35 monomial sums; planes are not counted by the step
 #      statistics and are taken as rows x 2 / (pi (R + 1/2)) (the planes and
@@ -103,7 +105,8 @@ def epr_flops_per_step(st, steps):
 # 6050 per evaluation: the 19x19 and 10x10 Hessians, their Cholesky
 #      factorisations and solves, the two constant recurrence factors
 #  300 per cell: collision
-FLOPS3_POINT_EVAL, FLOPS3_POINT_FINAL, FLOPS3_ROW, FLOPS3_PLANE, FLOPS3_EVAL, FLOPS3_CELL = 28, 8, 370, 250, 6050, 300
+FLOPS3_POINT_EVAL, FLOPS3_POINT_FINAL, FLOPS3_ROW, FLOPS3_PLANE, FLOPS3_EVAL, FLOPS3_CELL = 28, 8, 330, 250, 6050, 300
+FLOPS3_SPAN = 50
 
 
 def epr3_flops_per_step(st, steps):
@@ -113,8 +116,10 @@ def epr3_flops_per_step(st, steps):
     evals = max(st["point_passes"] / max(st["q_mean"], 1e-30) - st["cells"], 0.0)
     radius = (3.0 * st["q_mean"] / (4.0 * math.pi)) ** (1.0 / 3.0)
     planes = st["row_passes"] * 2.0 / (math.pi * max(radius, 1.0))
+    rows_once = st["row_passes"] / (evals / max(st["cells"], 1) + 1.0)    # passes = evaluations + the final pass
     return (FLOPS3_POINT_EVAL * eval_points + FLOPS3_POINT_FINAL * q + FLOPS3_ROW * st["row_passes"]
-            + FLOPS3_PLANE * planes + FLOPS3_EVAL * evals + FLOPS3_CELL * st["cells"]) / steps
+            + FLOPS3_PLANE * planes + FLOPS3_SPAN * rows_once + FLOPS3_EVAL * evals
+            + FLOPS3_CELL * st["cells"]) / steps
 
 
 # Algorithmic bytes of the gather: per arriving stencil point the (w_f, w_g)

@@ -682,6 +682,7 @@ __device__ inline void row_coef(const double *lf, const double *lg, double y, do
 // difference and s2 by exp(-6 C3); g = exp(H) by rg, and rg by exp(-2 D2).
 // row_start3 sets the five values at x0 by direct exponentials.
 constexpr int REC3 = 16;   // points between direct restarts of a row's recurrences
+constexpr int SPAN3_W = 13;   // k3_epr keeps the row spans of stencils with 2R + 3 <= SPAN3_W in LDS
 
 __device__ inline void row_start3(const double *C, const double *Dg, double x0, double &f, double &r, double &s2,
                                   double &gv, double &rg) {
@@ -712,6 +713,7 @@ __device__ inline bool rec3_ok(double f, double r, double s2, double gv, double 
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, Buf3 b, int step, int tile0) {
+    __shared__ unsigned short s_span[SPAN3_W * SPAN3_W * TN];
     if (b.flags->err) return;
     const int t = tile0 + blockIdx.x, l = threadIdx.x;
     const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
@@ -729,7 +731,31 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
         collide3(ph, mom, g.n, s, rho, ux, uy, uz, RT, mf, mg, kn, lim);
         const double rr = R + 0.5;
         const int ubx = (int)floor(ux + 0.5), uby = (int)floor(uy + 0.5), ubz = (int)floor(uz + 0.5);
-        const int xlo = ubx - R - 1, xhi = ubx + R + 1;
+        const int xlo = ubx - R - 1, xhi = ubx + R + 1, ylo = uby - R - 1, zlo = ubz - R - 1;
+        // The row spans of the stencil are computed once and kept in LDS (each
+        // lane its own column) for all passes, when they fit; wider stencils
+        // compute them in every pass.
+        const int W3 = 2 * R + 3;
+        const bool tab = W3 <= SPAN3_W;
+        if (tab) {
+            for (int kz = 0; kz < W3; kz++)
+                for (int ky = 0; ky < W3; ky++) {
+                    int xa, xb;
+                    unsigned short v = 0x00ff;
+                    if (span3(ylo + ky, zlo + kz, ux, uy, uz, rr, xlo, xhi, xa, xb))
+                        v = (unsigned short)((xa - xlo) | ((xb - xlo) << 8));
+                    s_span[(kz * W3 + ky) * TN + l] = v;
+                }
+        }
+        auto span = [&](int cy, int cz, int &xa, int &xb) -> bool {
+            if (tab) {
+                const unsigned v = s_span[((cz - zlo) * W3 + (cy - ylo)) * TN + l];
+                xa = xlo + (int)(v & 0xffu);
+                xb = xlo + (int)(v >> 8);
+                return xa <= xb;
+            }
+            return span3(cy, cz, ux, uy, uz, rr, xlo, xhi, xa, xb);
+        };
         Sp3<NF> sf;
         Sp3<NG> sg;
         sp3_init<NF>(sf, RT);
@@ -762,7 +788,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
                 bool any = false;
                 for (int cy = uby - R - 1; cy <= uby + R + 1; cy++) {
                     int xa, xb;
-                    if (!span3(cy, cz, ux, uy, uz, rr, xlo, xhi, xa, xb)) continue;
+                    if (!span(cy, cz, xa, xb)) continue;
                     any = true;
                     const double yy = (double)cy - uy;
                     double C[4], Dg[3];
@@ -849,7 +875,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
                 const double zz = (double)cz - uz;
                 for (int cy = uby - R - 1; cy <= uby + R + 1; cy++) {
                     int xa, xb;
-                    if (!span3(cy, cz, ux, uy, uz, rr, xlo, xhi, xa, xb)) continue;
+                    if (!span(cy, cz, xa, xb)) continue;
                     rows++;
                     const double yy = (double)cy - uy;
                     double C[4], Dg[3];
