@@ -143,20 +143,23 @@ def test_refinement_beyond_three_levels_is_refused():
     assert e.value.code == lb.EREACH
 
 
-def test_banded_records_equal_one_band():
+@pytest.mark.parametrize("guess", ["eq", "prev"])
+def test_banded_records_equal_one_band(guess):
     """Records in bands of tile layers within a small scratch budget: the
     fields equal the one-band run bit for bit (and the oracle), with a
-    smaller scratch."""
+    smaller scratch; also with the previous-step guess, whose stored
+    corrections are written band by band."""
     import paper_2508_06911_amd as lb
-    _case("3D banded records, 8 x 8 x 64, 3 steps")
+    _case("3D banded records, 8 x 8 x 64, 3 steps, guess %s" % guess)
+    g = lb.GUESS_PREV if guess == "prev" else lb.GUESS_EQ
     cfg, prim = li.smooth_periodic3(5, n=8, ny=8, nz=64, amp=0.08, RT=0.9)
     m = _mom(cfg, prim)
-    a = lb.Lelbm(cfg, m)
+    a = lb.Lelbm(cfg, m, guess=g)
     a.step(3)
     whole = a.read_moments()
     _, s_whole = a.memory()
     a.close()
-    b = lb.Lelbm(cfg, m)
+    b = lb.Lelbm(cfg, m, guess=g)
     b.set_scratch_budget(int(0.65 * s_whole))
     b.step(3)
     banded = b.read_moments()
