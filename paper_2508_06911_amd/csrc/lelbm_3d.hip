@@ -1592,7 +1592,8 @@ int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3F
         }
         plan3(c, layers, M, std::max<long long>(c->budget / (long long)esz, 1));
         const Plan &P = c->plan;
-        const long long need = (long long)P.nslots * P.slot_cap;
+        // at least one record pair: the gather's misses read the first one
+        const long long need = std::max<long long>((long long)P.nslots * P.slot_cap, 2);
         if (need > b.scratch_cap) {
             if (b.scratch) H3(hipFree(b.scratch));
             b.scratch = nullptr;
