@@ -572,13 +572,13 @@ __device__ inline void moments17(double cx, double cy, double cz, double wf, dou
 
 // Statistics of a wavefront's cells: one set of atomics per wavefront.
 __device__ inline void stats3(DevStats *st, int itf, int itg, int q, int lim, int fb, int passes, int rows, double RT,
-                              double kn, int l) {
+                              double kn, double colat, int l) {
     unsigned long long a[6] = {(unsigned long long)itf, (unsigned long long)itg, (unsigned long long)q,
                                (unsigned long long)lim, (unsigned long long)(q > 0 ? 1 : 0), (unsigned long long)fb};
     unsigned long long qp = (unsigned long long)q * (unsigned long long)passes;
     unsigned long long rp = (unsigned long long)rows * (unsigned long long)passes;
     int mxf = itf, mxg = itg, qmax = q, qmin = q > 0 ? q : INT_MAX;
-    double rtmin = q > 0 ? RT : 1e300, knmax = kn;
+    double rtmin = q > 0 ? RT : 1e300, knmax = kn, cmax = colat;
     for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
         for (int k = 0; k < 6; k++) a[k] += __shfl_xor(a[k], off);
@@ -590,6 +590,7 @@ __device__ inline void stats3(DevStats *st, int itf, int itg, int q, int lim, in
         qmin = min(qmin, __shfl_xor(qmin, off));
         rtmin = fmin(rtmin, __shfl_xor(rtmin, off));
         knmax = fmax(knmax, __shfl_xor(knmax, off));
+        cmax = fmax(cmax, __shfl_xor(cmax, off));
     }
     if (l == 0 && a[4] > 0) {
         atomicAdd(&st->it_sum_f, a[0]);
@@ -606,6 +607,7 @@ __device__ inline void stats3(DevStats *st, int itf, int itg, int q, int lim, in
         atomicMin(&st->q_min, qmin);
         atomicMin(&st->rt_min_bits, (unsigned long long)__double_as_longlong(rtmin));
         atomicMax(&st->kn_max_bits, (unsigned long long)__double_as_longlong(knmax));
+        atomicMax(&st->colat_max_bits, (unsigned long long)__double_as_longlong(cmax));
     }
 }
 
@@ -723,10 +725,11 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
     const int rn = valid ? b.d.r[s] : -1;
     const int R = rn & 0xffff;
     int itf = 0, itg = 0, q = 0, lim = 0, passes = 0, rows = 0, fb = 0;
-    double kn = 0.0, RTc = 0.0;
+    double kn = 0.0, RTc = 0.0, colat = 0.0;   // colat: |u| + R (Eq. IIC7)
     if (rn >= 0 && (rn >> 16) == 0) {
         const double rho = b.d.rho[s], ux = b.d.ux[s], uy = b.d.uy[s], uz = b.d.uz[s], RT = b.d.rt[s];
         RTc = RT;
+        colat = sqrt(ux * ux + uy * uy + uz * uz) + R;
         double mf[NF], mg[NG];
         collide3(ph, mom, g.n, s, rho, ux, uy, uz, RT, mf, mg, kn, lim);
         const double rr = R + 0.5;
@@ -914,7 +917,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
             passes++;
         }
     }
-    stats3(b.stats, itf, itg, q, lim, fb, passes, rows, RTc, kn, l);
+    stats3(b.stats, itf, itg, q, lim, fb, passes, rows, RTc, kn, colat, l);
 }
 
 // ---------------------------------------------------------------------------
@@ -937,10 +940,11 @@ __global__ void __launch_bounds__(64) k3_epr_ref(G3 g, Phys ph, const double *mo
     const int rn = valid ? b.d.r[s] : -1;
     const int R = rn & 0xffff, Nr = rn >> 16;
     int itf = 0, itg = 0, q = 0, lim = 0, passes = 0, fb = 0;
-    double kn = 0.0, RTc = 0.0;
+    double kn = 0.0, RTc = 0.0, colat = 0.0;   // colat: |u| + R (Eq. IIC7)
     if (rn >= 0 && Nr > 0) {
         const double rho = b.d.rho[s], ux = b.d.ux[s], uy = b.d.uy[s], uz = b.d.uz[s], RT = b.d.rt[s];
         RTc = RT;
+        colat = sqrt(ux * ux + uy * uy + uz * uz) + R;
         double mf[NF], mg[NG];
         collide3(ph, mom, g.n, s, rho, ux, uy, uz, RT, mf, mg, kn, lim);
         Sp3<NF> sf;
@@ -1048,7 +1052,7 @@ __global__ void __launch_bounds__(64) k3_epr_ref(G3 g, Phys ph, const double *mo
             passes++;
         }
     }
-    stats3(b.stats, itf, itg, q, lim, fb, passes, 0, RTc, kn, l);
+    stats3(b.stats, itf, itg, q, lim, fb, passes, 0, RTc, kn, colat, l);
 }
 
 // ---------------------------------------------------------------------------
@@ -1696,6 +1700,7 @@ int ctx3_step(Ctx3 *c, int nsteps, lelbm_stats *st, const Step3Timer &tm, Step3F
         double v;
         memcpy(&v, &ds.rt_min_bits, 8); st->rt_min = v;
         memcpy(&v, &ds.kn_max_bits, 8); st->kn_max = v;
+        memcpy(&v, &ds.colat_max_bits, 8); st->colat_max = v;
         for (int k = 0; k < 4; k++) st->sum[k] = sums[k];
         st->cells = (long)ds.cells;
         st->point_passes = (long)ds.qpass_sum;

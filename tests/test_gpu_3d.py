@@ -49,6 +49,20 @@ def test_parity_ragged_box(prec, tol, seed):
     assert abs(st["q_mean"] - rs["q_mean"]) < 1e-9
 
 
+def test_reach_statistic():
+    """The step's colat_max is the largest |u| + R over the cells (Eq. IIC7)."""
+    import paper_2508_06911_amd as lb
+    _case("3D reach statistic, 10 x 9 x 7, 1 step")
+    cfg, prim = li.smooth_periodic3(0, n=10, ny=9, nz=7, amp=0.08, RT=0.9)
+    ctx = lb.Lelbm(cfg, _mom(cfg, prim))
+    st = ctx.step(1)
+    ctx.close()
+    R = np.maximum(np.floor(4.0 * np.sqrt(prim["RT"]) + 0.5), 2)
+    want = (np.sqrt(prim["ux"] ** 2 + prim["uy"] ** 2 + prim["uz"] ** 2) + R).max()
+    print("colat_max %.15g, expected %.15g" % (st["colat_max"], want), flush=True)
+    assert abs(st["colat_max"] - want) < 1e-12 * want
+
+
 def test_parity_across_calls_and_hot_fast_gas():
     """A hotter, faster state (R up to 6, |u| above 2) split over two calls
     equals one call of all steps, and the oracle."""
