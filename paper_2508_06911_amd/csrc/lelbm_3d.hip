@@ -1071,7 +1071,7 @@ __global__ void __launch_bounds__(64) k3_epr_ref(G3 g, Phys ph, const double *mo
 // once per row.
 // ---------------------------------------------------------------------------
 constexpr int GX = 16;
-constexpr int G3_ENTRY_BYTES = 48;
+constexpr int G3_ENTRY_BYTES = 44;
 constexpr int G3U = 4;   // candidates per batch in the gather
 
 // The (w_f, w_g) pair of a record, read as one load.
@@ -1109,9 +1109,10 @@ __global__ void __launch_bounds__(GX * GY, 4) k3_gather(G3 g, double *out, Buf3 
     // (-1: no source, or one with all-moment records), the address of its
     // record of displacement (0, 0, d_z), the slot box row length w_x, and
     // R | fmt << 20 (-1: no source) for the sources with all-moment records
-    double *s_ux = g3_lds, *s_uy = s_ux + NE, *s_ez2 = s_uy + NE, *s_rr2 = s_ez2 + NE;
-    long long *s_a0 = (long long *)(s_rr2 + NE);
-    int *s_r = (int *)(s_a0 + NE), *s_wx = s_r + NE;
+    // three 16-byte vectors per entry, so that a candidate takes three LDS reads
+    double2 *s_u = (double2 *)g3_lds, *s_t = s_u + NE;   // (u_x, u_y), ((d_z - u_z)^2, (R + 1/2)^2)
+    long long *s_aw = (long long *)(s_t + NE);          // record address << 16 | w_x
+    int *s_r = (int *)(s_aw + NE);
     const int bx = (g.nx + GX - 1) / GX, by = (g.ny + GY - 1) / GY;
     const int blk = blockIdx.x;
     const int x0 = (blk % bx) * GX, y0 = ((blk / bx) % by) * GY, z = zb + blk / (bx * by);
@@ -1144,8 +1145,9 @@ __global__ void __launch_bounds__(GX * GY, 4) k3_gather(G3 g, double *out, Buf3 
             const int rn = b.d.r[s];
             if (rn < 0) {
                 s_r[e] = -1;
-                s_ux[e] = 0.0; s_uy[e] = 0.0; s_ez2[e] = 0.0; s_rr2[e] = -1.0;
-                s_a0[e] = 0; s_wx[e] = 0;
+                s_u[e] = make_double2(0.0, 0.0);
+                s_t[e] = make_double2(0.0, -1.0);
+                s_aw[e] = 0;
                 continue;
             }
             const double uu[3] = {b.d.ux[s], b.d.uy[s], b.d.uz[s]};
@@ -1161,14 +1163,12 @@ __global__ void __launch_bounds__(GX * GY, 4) k3_gather(G3 g, double *out, Buf3 
             const double rr = (double)(rn & 0xffff) + 0.5, ez = (double)dz - uu[2];
             s_r[e] = (rn & 0xffff) | (ti.fmt << 20);
             anyref |= ti.fmt;
-            s_ux[e] = uu[0];
-            s_uy[e] = uu[1];
+            s_u[e] = make_double2(uu[0], uu[1]);
             // the terms of the exact test (in_ball) that do not depend on d_x, d_y
-            s_ez2[e] = ez * ez;
-            s_rr2[e] = ti.fmt ? -1.0 : rr * rr;
-            s_a0[e] = ti.base + (long long)loc * rs +
-                      (((long long)(dz - ti.oz) * ti.wy - ti.oy) * ti.wx - ti.ox) * (TN * rs);
-            s_wx[e] = ti.wx;
+            s_t[e] = make_double2(ez * ez, ti.fmt ? -1.0 : rr * rr);
+            const long long a0 = ti.base + (long long)loc * rs +
+                                 (((long long)(dz - ti.oz) * ti.wy - ti.oy) * ti.wx - ti.ox) * (TN * rs);
+            s_aw[e] = (long long)((unsigned long long)a0 << 16) | (long long)ti.wx;
         }
         if (brm >= 0) {
 #pragma unroll
@@ -1204,15 +1204,18 @@ __global__ void __launch_bounds__(GX * GY, 4) k3_gather(G3 g, double *out, Buf3 
                 for (int u = 0; u < G3U; u++) {
                     const int dx = dxb + u;
                     const int e = rowe - (dx <= dxhi ? dx : dxlo);
-                    const double ex = (double)dx - s_ux[e], ey = cy - s_uy[e];
+                    const double2 su = s_u[e], st = s_t[e];
+                    const long long aw = s_aw[e], a0 = aw >> 16;
+                    const int wx = (int)(aw & 0xffff);
+                    const double ex = (double)dx - su.x, ey = cy - su.y;
                     bool hit;
                     {
                         // in_ball's expression, term for term
 #pragma clang fp contract(off)
-                        hit = ex * ex + ey * ey + s_ez2[e] <= s_rr2[e];
+                        hit = ex * ex + ey * ey + st.x <= st.y;
                     }
                     in[u] = (dx <= dxhi) & hit;
-                    const long long off = s_a0[e] + (long long)(dy * s_wx[e] + dx) * (TN * 2);
+                    const long long off = a0 + (long long)(dy * wx + dx) * (TN * 2);
                     v[u] = *(const typename Pair3<T>::type *)(SCR + (in[u] ? off : 0ll));
                 }
 #pragma unroll
@@ -1228,15 +1231,17 @@ __global__ void __launch_bounds__(GX * GY, 4) k3_gather(G3 g, double *out, Buf3 
                     const int e = rowe - dx;
                     const int m = s_r[e];
                     if (m < 0 || !(m >> 20)) continue;
-                    const double ex = (double)dx - s_ux[e], ey = cy - s_uy[e], rr = (double)(m & 0xffff) + 0.5;
+                    const double2 su = s_u[e];
+                    const double ex = (double)dx - su.x, ey = cy - su.y, rr = (double)(m & 0xffff) + 0.5;
                     bool hit;
                     {
 #pragma clang fp contract(off)
-                        hit = ex * ex + ey * ey + s_ez2[e] <= rr * rr;
+                        hit = ex * ex + ey * ey + s_t[e].x <= rr * rr;
                     }
                     if (!hit) continue;
                     hits++;
-                    const T *P = SCR + s_a0[e] + (long long)(dy * s_wx[e] + dx) * (TN * NM);
+                    const long long aw = s_aw[e];
+                    const T *P = SCR + (aw >> 16) + (long long)(dy * (int)(aw & 0xffff) + dx) * (TN * NM);
 #pragma unroll
                     for (int k = 0; k < NM; k++) acc[k] += (double)P[k];
                 }
