@@ -205,21 +205,25 @@ def l1_errors(a, b):
     }
 
 
-def kernel_source_sha():
-    """sha256 over the sources compiled into the 2D kernels, in a fixed order."""
+KERNEL_SOURCES = {"2d": ("lelbm_kernels.hip", "lelbm_internal.h", "lelbm_mlp_dev.h"),
+                  "3d": ("lelbm_3d.hip", "lelbm_3d.h", "lelbm_internal.h")}
+
+
+def kernel_source_sha(dim="2d"):
+    """sha256 over the sources compiled into the 2D (or 3D) kernels, in a fixed order."""
     h = hashlib.sha256()
-    for name in ("lelbm_kernels.hip", "lelbm_internal.h", "lelbm_mlp_dev.h"):
+    for name in KERNEL_SOURCES[dim]:
         with open(os.path.join(ROOT, "paper_2508_06911_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def stored_traffic():
+def stored_traffic(dim="2d"):
     """HBM traffic per launch from committed counter summaries: a line
     ``TRAFFIC {json}`` in profiles/*.md whose ``source_sha256`` equals the
-    hash of the current sources of the 2D kernels (the kernel file and the
-    headers it includes: any change to them voids the figure)."""
-    sha = kernel_source_sha()
+    hash of the current sources of the 2D (or 3D) kernels (the kernel file
+    and the headers it includes: any change to them voids the figure)."""
+    sha = kernel_source_sha(dim)
     out = {}
     for p in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(p) as f:
@@ -673,7 +677,8 @@ def d3_line(a, lb, li, torch):
            "fp64_mlups": out["fp64"]["mlups"],
            "roofline": {"bound": "alu", "achieved": out["mixed-lin"]["epr_tflops_executed"],
                         "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": out["mixed-lin"]["epr_frac_fp64_peak"],
-                        "traffic": None, "kernel": "k3_epr<float> (FP32 records, linearised start)"},
+                        "traffic": stored_traffic("3d").get(("k3_epr", "box%d-mixed-lin" % n)),
+                        "kernel": "k3_epr<float> (FP32 records, linearised start)"},
            "cpu_baseline": {"value": round(16 ** 3 * 4 / el / 1e6, 5), "unit": "MLUPS", "cores": oracle.num_threads(),
                             "kind": "oracle", "sample": "16^3 box of the same kind, 4 steps (%.1f s)" % el,
                             "status": code},
