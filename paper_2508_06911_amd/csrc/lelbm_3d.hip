@@ -353,19 +353,39 @@ __device__ inline void collide3(const Phys &ph, const double *mom, long long n, 
 // scaled residual as stop test, the stalled-residual rule, one polishing
 // update after the stop.
 // ---------------------------------------------------------------------------
-template <int NB> struct Sp3 {
-    double lam[NB], del[NB];
+// Multipliers lam and search direction del of one species: in registers, or
+// in the lane's LDS column (entry j at j * TN), which keeps them out of the
+// registers the stencil passes need.
+template <int NB> struct RegStore3 {
+    double l[NB], d[NB];
+    __device__ double &lam(int j) { return l[j]; }
+    __device__ double &del(int j) { return d[j]; }
+    __device__ double lam(int j) const { return l[j]; }
+    __device__ double del(int j) const { return d[j]; }
+};
+template <int NB> struct LdsStore3 {
+    double *l, *d;
+    __device__ double &lam(int j) const { return l[j * TN]; }
+    __device__ double &del(int j) const { return d[j * TN]; }
+};
+template <int NB, class St = RegStore3<NB>> struct Sp3 {
+    static constexpr int N = NB;
+    St v;
     double t, dec, phi, res, res_prev;
     int phase, nit, ls;
     int lin;          // 1 while iterating from the linearised start
-    __device__ double at(int j) const { return lam[j] + t * del[j]; }
+    __device__ double &lam(int j) { return v.lam(j); }
+    __device__ double &del(int j) { return v.del(j); }
+    __device__ double lam(int j) const { return v.lam(j); }
+    __device__ double at(int j) const { return v.lam(j) + t * v.del(j); }
 };
 
-template <int NB> __device__ inline void sp3_init(Sp3<NB> &sp, double RT) {
+template <class SP> __device__ inline void sp3_init(SP &sp, double RT) {
+    constexpr int NB = SP::N;
 #pragma unroll
-    for (int j = 0; j < NB; j++) { sp.lam[j] = 0.0; sp.del[j] = 0.0; }
-    sp.lam[0] = -1.0 + 1.5 * log(2.0 * M_PI * RT);     // Eq. (IID13), D = 3
-    sp.lam[4] = sp.lam[7] = sp.lam[9] = 1.0 / (2.0 * RT);
+    for (int j = 0; j < NB; j++) { sp.lam(j) = 0.0; sp.del(j) = 0.0; }
+    sp.lam(0) = -1.0 + 1.5 * log(2.0 * M_PI * RT);     // Eq. (IID13), D = 3
+    sp.lam(4) = sp.lam(7) = sp.lam(9) = 1.0 / (2.0 * RT);
     sp.t = 0.0; sp.dec = 0.0; sp.phi = 0.0; sp.res = 0.0; sp.res_prev = 0.0;
     sp.phase = 0; sp.nit = 0; sp.ls = 0;
     sp.lin = 0;
@@ -405,16 +425,17 @@ __device__ inline void lin3_scaled(const double *mf, const double *mg, double RT
     }
 }
 
-__device__ inline void sp3_linear(Sp3<NF> &sf, Sp3<NG> &sg, const double *mf, const double *mg, double RT,
+template <class SF, class SG>
+__device__ inline void sp3_linear(SF &sf, SG &sg, const double *mf, const double *mg, double RT,
                                   const double *ainv) {
     const double sq = sqrt(RT);
     const double sc[4] = {1.0, sq, RT, RT * sq};
     double d[NF + NG];
     lin3_scaled(mf, mg, RT, ainv, d);
 #pragma unroll
-    for (int i = 0; i < NF; i++) sf.lam[i] += d[i] / sc[border(i)];
+    for (int i = 0; i < NF; i++) sf.lam(i) += d[i] / sc[border(i)];
 #pragma unroll
-    for (int i = 0; i < NG; i++) sg.lam[i] += d[NF + i] / sc[border(i)];
+    for (int i = 0; i < NG; i++) sg.lam(i) += d[NF + i] / sc[border(i)];
     sf.lin = 1;
     sg.lin = 1;
 }
@@ -424,20 +445,22 @@ __device__ inline void sp3_linear(Sp3<NF> &sf, Sp3<NG> &sg, const double *mf, co
 // stored.  The correction is kept in scaled units, so it carries over when
 // the temperature changes, and beyond the linearised start, which follows
 // the sign flip of the non-equilibrium targets at omega = 2.
-__device__ inline void sp3_prev(Sp3<NF> &sf, Sp3<NG> &sg, double RT, const double *prev, long long n,
+template <class SF, class SG>
+__device__ inline void sp3_prev(SF &sf, SG &sg, double RT, const double *prev, long long n,
                                 long long s) {
     if (!(prev[s] == prev[s])) return;
     const double sq = sqrt(RT);
     const double sc[4] = {1.0, sq, RT, RT * sq};
 #pragma unroll
-    for (int i = 0; i < NF; i++) sf.lam[i] += prev[(long long)i * n + s] / sc[border(i)];
+    for (int i = 0; i < NF; i++) sf.lam(i) += prev[(long long)i * n + s] / sc[border(i)];
 #pragma unroll
-    for (int i = 0; i < NG; i++) sg.lam[i] += prev[(long long)(NF + i) * n + s] / sc[border(i)];
+    for (int i = 0; i < NG; i++) sg.lam(i) += prev[(long long)(NF + i) * n + s] / sc[border(i)];
 }
 
 // Stores the converged multipliers' correction beyond Eq. (IID13) plus the
 // linearised step, in scaled units, for the next step's guess.
-__device__ inline void sp3_store_prev(const Sp3<NF> &sf, const Sp3<NG> &sg, const double *mf, const double *mg,
+template <class SF, class SG>
+__device__ inline void sp3_store_prev(const SF &sf, const SG &sg, const double *mf, const double *mg,
                                       double RT, const double *ainv, double *prev, long long n, long long s) {
     const double sq = sqrt(RT);
     const double sc[4] = {1.0, sq, RT, RT * sq};
@@ -447,7 +470,7 @@ __device__ inline void sp3_store_prev(const Sp3<NF> &sf, const Sp3<NG> &sg, cons
 #pragma unroll
     for (int i = 0; i < NF + NG; i++) {
         const int j = i < NF ? i : i - NF;
-        const double lam = i < NF ? sf.lam[j] : sg.lam[j];
+        const double lam = i < NF ? sf.lam(j) : sg.lam(j);
         const double eq = j == 0 ? l0 : ((j == 4 || j == 7 || j == 9) ? 0.5 : 0.0);   // scaled Eq. (IID13)
         prev[(long long)i * n + s] = lam * sc[border(j)] - eq - d[i];
     }
@@ -497,8 +520,9 @@ template <int NB> __device__ inline bool chol3(const double *S, const double *r,
 
 // After a pass evaluated at lam + t del: accept / backtrack / step / polish.
 // 0: continue, 1: polished, negative: failure reason.
-template <int NB> __device__ inline int sp3_update(Sp3<NB> &sp, const double *S, const double *tg, const double *isc,
-                                                   double tol, int maxit) {
+template <class SP> __device__ inline int sp3_update(SP &sp, const double *S, const double *tg, const double *isc,
+                                                     double tol, int maxit) {
+    constexpr int NB = SP::N;
     double r[NB];
     double phit = S[0];
     bool fin = isfinite(S[0]);
@@ -521,7 +545,7 @@ template <int NB> __device__ inline int sp3_update(Sp3<NB> &sp, const double *S,
         sp.nit++;
     }
 #pragma unroll
-    for (int j = 0; j < NB; j++) sp.lam[j] = sp.at(j);
+    for (int j = 0; j < NB; j++) sp.lam(j) = sp.at(j);
     sp.t = 0.0;
     sp.phi = phit;
     double res = 0.0;
@@ -537,7 +561,7 @@ template <int NB> __device__ inline int sp3_update(Sp3<NB> &sp, const double *S,
     if (res <= tol || stalled) {
         if (!chol3<NB>(S, r, dl)) return -3;
 #pragma unroll
-        for (int j = 0; j < NB; j++) { sp.lam[j] += dl[j]; sp.del[j] = 0.0; }
+        for (int j = 0; j < NB; j++) { sp.lam(j) += dl[j]; sp.del(j) = 0.0; }
         sp.nit++;
         sp.phase = 2;
         return 1;
@@ -546,7 +570,7 @@ template <int NB> __device__ inline int sp3_update(Sp3<NB> &sp, const double *S,
     if (!chol3<NB>(S, r, dl)) return -5;
     double dec = 0.0;
 #pragma unroll
-    for (int j = 0; j < NB; j++) { sp.del[j] = dl[j]; dec += r[j] * dl[j]; }
+    for (int j = 0; j < NB; j++) { sp.del(j) = dl[j]; dec += r[j] * dl[j]; }
     sp.dec = dec;
     sp.t = 1.0;
     sp.ls = 0;
@@ -684,7 +708,7 @@ __device__ inline void row_coef(const double *lf, const double *lg, double y, do
 // difference and s2 by exp(-6 C3); g = exp(H) by rg, and rg by exp(-2 D2).
 // row_start3 sets the five values at x0 by direct exponentials.
 constexpr int REC3 = 16;   // points between direct restarts of a row's recurrences
-constexpr int SPAN3_W = 13;   // k3_epr keeps the row spans of stencils with 2R + 3 <= SPAN3_W in LDS
+constexpr int SPAN3_W = 13;   // k3_epr keeps the row spans of stencils with 2R + 3 <= SPAN3_W in LDS (4-bit offsets)
 
 __device__ inline void row_start3(const double *C, const double *Dg, double x0, double &f, double &r, double &s2,
                                   double &gv, double &rg) {
@@ -715,7 +739,11 @@ __device__ inline bool rec3_ok(double f, double r, double s2, double gv, double 
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, Buf3 b, int step, int tile0) {
-    __shared__ unsigned short s_span[SPAN3_W * SPAN3_W * TN];
+    // LDS per workgroup (one wavefront): the row-span table (one byte per row
+    // and lane) and the Newton state (multipliers and directions of both
+    // species), 40,512 bytes, so that four workgroups share a CU
+    __shared__ unsigned char s_span[SPAN3_W * SPAN3_W * TN];
+    __shared__ double s_nw[2 * (NF + NG) * TN];
     if (b.flags->err) return;
     const int t = tile0 + blockIdx.x, l = threadIdx.x;
     const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
@@ -744,25 +772,27 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
             for (int kz = 0; kz < W3; kz++)
                 for (int ky = 0; ky < W3; ky++) {
                     int xa, xb;
-                    unsigned short v = 0x00ff;
+                    unsigned char v = 0x0f;   // empty row: first offset 15, last 0
                     if (span3(ylo + ky, zlo + kz, ux, uy, uz, rr, xlo, xhi, xa, xb))
-                        v = (unsigned short)((xa - xlo) | ((xb - xlo) << 8));
+                        v = (unsigned char)((xa - xlo) | ((xb - xlo) << 4));
                     s_span[(kz * W3 + ky) * TN + l] = v;
                 }
         }
         auto span = [&](int cy, int cz, int &xa, int &xb) -> bool {
             if (tab) {
                 const unsigned v = s_span[((cz - zlo) * W3 + (cy - ylo)) * TN + l];
-                xa = xlo + (int)(v & 0xffu);
-                xb = xlo + (int)(v >> 8);
+                xa = xlo + (int)(v & 0xfu);
+                xb = xlo + (int)(v >> 4);
                 return xa <= xb;
             }
             return span3(cy, cz, ux, uy, uz, rr, xlo, xhi, xa, xb);
         };
-        Sp3<NF> sf;
-        Sp3<NG> sg;
-        sp3_init<NF>(sf, RT);
-        sp3_init<NG>(sg, RT);
+        Sp3<NF, LdsStore3<NF>> sf;
+        Sp3<NG, LdsStore3<NG>> sg;
+        sf.v.l = s_nw + l; sf.v.d = s_nw + NF * TN + l;
+        sg.v.l = s_nw + 2 * NF * TN + l; sg.v.d = s_nw + (2 * NF + NG) * TN + l;
+        sp3_init(sf, RT);
+        sp3_init(sg, RT);
         if (b.ainv) sp3_linear(sf, sg, mf, mg, RT, b.ainv);
         if (b.prev) sp3_prev(sf, sg, RT, b.prev, g.n, s);
         const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
@@ -852,16 +882,16 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
                         for (int c = 0; c + bb + a < 5; c++) Sg[mono(a, bb, c)] += Pg[(a + bb) * (a + bb + 1) / 2 + bb] * pz[c];
             }
             if (sg.phase < 2) {
-                int r = sp3_update<NG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
+                int r = sp3_update(sg, Sg, mg, isc, ph.tol, ph.maxit);
                 if (r < 0 && r != -3 && sg.lin) r = 2;
                 if (r < 0) { fail = -r; fsp = 1; }
-                else if (r == 2) { sp3_init<NG>(sg, RT); fb = 1; }
+                else if (r == 2) { sp3_init(sg, RT); fb = 1; }
             }
             if (sf.phase < 2 && !fail) {
-                int r = sp3_update<NF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
+                int r = sp3_update(sf, Sf, mf, isc, ph.tol, ph.maxit);
                 if (r < 0 && r != -3 && sf.lin) r = 2;
                 if (r < 0) { fail = -r; fsp = 0; }
-                else if (r == 2) { sp3_init<NF>(sf, RT); fb = 1; }
+                else if (r == 2) { sp3_init(sf, RT); fb = 1; }
             }
         }
         if (fail) {
@@ -873,7 +903,12 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
             const double wsf = rho, wsg = rho * ph.K * RT;
             const Tile3 ti = b.tiles[t];
             T *P = (T *)b.scratch + ti.base;
-            const double t3 = exp(-6.0 * sf.lam[10]), sg2 = exp(-2.0 * sg.lam[4]);
+            double lf[NF], lg[NG];
+#pragma unroll
+            for (int j = 0; j < NF; j++) lf[j] = sf.lam(j);
+#pragma unroll
+            for (int j = 0; j < NG; j++) lg[j] = sg.lam(j);
+            const double t3 = exp(-6.0 * lf[10]), sg2 = exp(-2.0 * lg[4]);
             for (int cz = ubz - R - 1; cz <= ubz + R + 1; cz++) {
                 const double zz = (double)cz - uz;
                 for (int cy = uby - R - 1; cy <= uby + R + 1; cy++) {
@@ -882,7 +917,7 @@ __global__ void __launch_bounds__(64) k3_epr(G3 g, Phys ph, const double *mom, B
                     rows++;
                     const double yy = (double)cy - uy;
                     double C[4], Dg[3];
-                    row_coef(sf.lam, sg.lam, yy, zz, C, Dg);
+                    row_coef(lf, lg, yy, zz, C, Dg);
                     const long long row = ((long long)(cz - ti.oz) * ti.wy + (cy - ti.oy)) * ti.wx - ti.ox;
                     double f, r, s2, gv, rg;
                     bool direct = false;
@@ -949,8 +984,8 @@ __global__ void __launch_bounds__(64) k3_epr_ref(G3 g, Phys ph, const double *mo
         collide3(ph, mom, g.n, s, rho, ux, uy, uz, RT, mf, mg, kn, lim);
         Sp3<NF> sf;
         Sp3<NG> sg;
-        sp3_init<NF>(sf, RT);
-        sp3_init<NG>(sg, RT);
+        sp3_init(sf, RT);
+        sp3_init(sg, RT);
         if (b.ainv) sp3_linear(sf, sg, mf, mg, RT, b.ainv);
         const double isc[4] = {1.0, 1.0 / sqrt(RT), 1.0 / RT, 1.0 / (RT * sqrt(RT))};
         int fail = 0, fsp = -1;
@@ -995,16 +1030,16 @@ __global__ void __launch_bounds__(64) k3_epr_ref(G3 g, Phys ph, const double *mo
                 },
                 [](int, int, int) {});
             if (sg.phase < 2) {
-                int r = sp3_update<NG>(sg, Sg, mg, isc, ph.tol, ph.maxit);
+                int r = sp3_update(sg, Sg, mg, isc, ph.tol, ph.maxit);
                 if (r < 0 && r != -3 && sg.lin) r = 2;
                 if (r < 0) { fail = -r; fsp = 1; }
-                else if (r == 2) { sp3_init<NG>(sg, RT); fb = 1; }
+                else if (r == 2) { sp3_init(sg, RT); fb = 1; }
             }
             if (sf.phase < 2 && !fail) {
-                int r = sp3_update<NF>(sf, Sf, mf, isc, ph.tol, ph.maxit);
+                int r = sp3_update(sf, Sf, mf, isc, ph.tol, ph.maxit);
                 if (r < 0 && r != -3 && sf.lin) r = 2;
                 if (r < 0) { fail = -r; fsp = 0; }
-                else if (r == 2) { sp3_init<NF>(sf, RT); fb = 1; }
+                else if (r == 2) { sp3_init(sf, RT); fb = 1; }
             }
         }
         if (fail) {
@@ -1031,10 +1066,10 @@ __global__ void __launch_bounds__(64) k3_epr_ref(G3 g, Phys ph, const double *mo
                     double ef = 0.0, eg = 0.0;
 #pragma unroll
                     for (int j = 0; j < NF; j++)
-                        ef += sf.lam[j] * (px[bexp(j, 0)] * py[bexp(j, 1)] * pz[bexp(j, 2)]);
+                        ef += sf.lam(j) * (px[bexp(j, 0)] * py[bexp(j, 1)] * pz[bexp(j, 2)]);
 #pragma unroll
                     for (int j = 0; j < NG; j++)
-                        eg += sg.lam[j] * (px[bexp(j, 0)] * py[bexp(j, 1)] * pz[bexp(j, 2)]);
+                        eg += sg.lam(j) * (px[bexp(j, 0)] * py[bexp(j, 1)] * pz[bexp(j, 2)]);
                     double mo[NM];
                     moments17(cx, cy, cz, wsf * (dC * exp(-(1.0 + ef))), wsg * (dC * exp(-(1.0 + eg))), mo);
 #pragma unroll
