@@ -1149,7 +1149,11 @@ __global__ void __launch_bounds__(GX * GY, 4) k3_gather(G3 g, double *out, Buf3 
     long long *s_aw = (long long *)(s_t + NE);          // record address << 16 | w_x
     int *s_r = (int *)(s_aw + NE);
     const int bx = (g.nx + GX - 1) / GX, by = (g.ny + GY - 1) / GY;
-    const int blk = blockIdx.x;
+    // workgroups go to the eight XCDs in turn; each XCD is dealt one contiguous
+    // run of the (x, y, z)-ordered blocks (a bijection onto [0, gridDim.x)), so
+    // that neighbouring blocks, which read the same record lines, share an L2
+    const int xq = gridDim.x / 8, xr = gridDim.x % 8, xcd = blockIdx.x % 8;
+    const int blk = xcd * xq + min(xcd, xr) + blockIdx.x / 8;
     const int x0 = (blk % bx) * GX, y0 = ((blk / bx) % by) * GY, z = zb + blk / (bx * by);
     const int lx = threadIdx.x % GX, ly = threadIdx.x / GX;
     const int x = x0 + lx, y = y0 + ly;
