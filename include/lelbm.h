@@ -109,10 +109,12 @@ enum { LELBM_FP64 = 0, LELBM_MIXED = 1 };
  * the cells that have a stored correction (the others start from LIN); the
  * network is then one trained on pairs harvested in PREV mode (lelbm_harvest).
  * With LIN, MLP, PREV and MLP_PREV a cell whose first Newton update does not lower
- * the residual, or whose solve fails (non-finite values, Cholesky
- * breakdown, line search exhausted, iteration cap), restarts from
- * Eq. (IID13); the converged result is the same in all modes (the
- * multipliers are unique). */
+ * the residual, or whose first evaluation is not finite, restarts from
+ * Eq. (IID13); in 2D so does one whose solve fails (Cholesky breakdown, line
+ * search exhausted, iteration cap), while in 3D such a failure fails the
+ * step with LELBM_EEPR (state unchanged; run it again with LELBM_GUESS_EQ).
+ * The converged result is the same in all modes (the multipliers are
+ * unique). */
 enum { LELBM_GUESS_EQ = 0, LELBM_GUESS_MLP = 1, LELBM_GUESS_LIN = 2, LELBM_GUESS_PREV = 3, LELBM_GUESS_MLP_PREV = 4 };
 
 typedef struct {
